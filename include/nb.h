@@ -1,0 +1,239 @@
+/*
+ * nb.h -- C ABI of the cluster-pair short-range nonbonded library for AMD MI355X (gfx950).
+ *
+ * The library computes, for one or several periodic rectangular boxes of atoms, the
+ * Lennard-Jones plus reaction-field or Ewald real-space forces, energies and virial of
+ * all non-excluded atom pairs inside a cut-off, with the cluster-pair algorithm of
+ * Pall et al., "Heterogeneous parallelization and acceleration of molecular dynamics
+ * simulations in GROMACS" (J. Chem. Phys. 2020):
+ *
+ *   - atoms are binned on a grid that is regular in x and y and cut along z into cells
+ *     of a fixed atom count; cells are split into clusters of 8 atoms, grouped 2x2x2 into
+ *     super-clusters of 8 clusters (Sec. V.A, Fig. 4);
+ *   - a joint list of j-clusters is built per super-cluster from cluster bounding boxes,
+ *     with an 8-bit mask of the i-clusters each j-cluster interacts with, then pruned on
+ *     atom distances (Sec. V.A, V.D);
+ *   - the list is dual: the outer list (radius rlist) is built every nstlist steps, the
+ *     inner list (radius rinner) is re-derived from it by pruning one part per step in a
+ *     rolling fashion (Sec. V.E);
+ *   - the force kernel evaluates every i-cluster x j-cluster pair of 8 x 8 atoms with the
+ *     interaction mask, exclusion bit masks and the cut-off, each atom pair once with
+ *     Newton's third law (Sec. V.A).
+ *
+ * Conventions
+ *   - Units: nm, kJ/mol, elementary charge.  Rectangular boxes only.
+ *   - "dev" pointers are HIP device pointers (e.g. a torch tensor's data_ptr() on the
+ *     context's device); "host" pointers are ordinary host memory.  The caller owns every
+ *     array it passes; device arrays must stay valid until the enqueued work completes.
+ *   - Every call enqueues work on the context's HIP stream and returns without waiting,
+ *     except those marked [sync], which wait for the stream.
+ *   - No call throws; every call returns an nb_status.  Host-side validation happens
+ *     before anything is enqueued; a failed call leaves the context as it was, except
+ *     NB_ERR_HIP, after which the context should be destroyed.
+ *   - A context is not thread-safe; use one context per stream.
+ */
+#ifndef NB_H
+#define NB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nb_ctx nb_ctx;
+
+typedef enum {
+    NB_OK = 0,
+    NB_ERR_ARG = 1,        /* null pointer, size or parameter out of range               */
+    NB_ERR_BOX = 2,        /* box edge not finite, not positive, or not above 2 * rlist  */
+    NB_ERR_NOMEM = 3,      /* device or host allocation failed                           */
+    NB_ERR_CAPACITY = 4,   /* a list would exceed list_capacity_hint (fixed capacity)    */
+    NB_ERR_STATE = 5,      /* call out of order (no topology / grid / list yet, expired) */
+    NB_ERR_HIP = 6,        /* HIP runtime error; nb_last_error() has the message         */
+    NB_ERR_NONFINITE = 7   /* non-finite coordinate met while building the grid          */
+} nb_status;
+
+enum { NB_COUL_RF = 0, NB_COUL_EWALD = 1 };
+enum { NB_MOD_NONE = 0, NB_MOD_POTSHIFT = 1 };
+
+/* nb_forces / nb_forces_backward flags */
+enum {
+    NB_F_ENERGY = 1u,      /* also compute energies [LJ, Coulomb] per system (FP64)      */
+    NB_F_VIRIAL = 2u,      /* also compute the virial -1/2 sum d (x) f per system (FP64) */
+    NB_F_ACCUMULATE = 4u   /* add into the output arrays instead of overwriting them     */
+};
+
+/*
+ * Interaction and list parameters.  The paper names the interactions (Lennard-Jones,
+ * reaction field, real-space Ewald; Sec. II, V.A) without formulas; the library uses:
+ *   V_LJ = c12 r^-12 - c6 r^-6, minus its value at rc under NB_MOD_POTSHIFT;
+ *   V_RF = epsfac qa qb / eps_r (1/r + k_rf r^2 - c_rf),
+ *          k_rf = (eps_rf - eps_r) / ((2 eps_rf + eps_r) rc^3) (1/(2 rc^3) for eps_rf = inf),
+ *          c_rf = 1/rc + k_rf rc^2;
+ *   V_EW = epsfac qa qb / eps_r erfc(beta r)/r, minus its value at rc under
+ *          NB_MOD_POTSHIFT;
+ * for pairs with r < rc that are neither self pairs nor listed as excluded.
+ */
+typedef struct {
+    int32_t n_types;          /* LJ types T (1..32); lj tables are [T][T][2]              */
+    int32_t coulomb;          /* NB_COUL_RF or NB_COUL_EWALD                               */
+    int32_t modifier;         /* NB_MOD_NONE or NB_MOD_POTSHIFT                            */
+    float rc;                 /* interaction cut-off, nm, > 0                              */
+    float rinner;             /* inner-list radius, rc <= rinner <= rlist                  */
+    float rlist;              /* outer-list radius (buffered cut-off)                      */
+    float eps_r;              /* relative dielectric constant, > 0                         */
+    float eps_rf;             /* reaction-field dielectric, > 0; +INFINITY allowed         */
+    float ewald_beta;         /* Ewald splitting parameter, 1/nm (>= 0)                    */
+    float epsfac;             /* Coulomb constant, kJ mol^-1 nm e^-2 (138.935458)          */
+    int32_t nstlist;          /* steps an outer list stays valid (>= 1)                    */
+    int32_t nstprune;         /* rolling-prune parts: one part pruned per step (>= 1)      */
+    int64_t list_capacity_hint; /* 0: grow lists as needed; > 0: fixed entries per
+                                   super-cluster, exceeding it is NB_ERR_CAPACITY          */
+} nb_params;
+
+/* Counters of the current list and the last force call (see nb_get_stats). */
+typedef struct {
+    int64_t n_atoms, n_slots, n_superclusters, n_clusters;
+    int64_t n_entries;        /* outer-list j-entries (super-cluster, j-cluster, shift)     */
+    int64_t n_work_items;     /* chunks of j-lists processed by one wavefront each         */
+    int64_t outer_pairs;      /* sum over entries of popcount(outer mask), cluster pairs    */
+    int64_t inner_pairs;      /* same for the inner masks as last pruned                   */
+    int64_t bb_pairs;         /* cluster pairs that passed the bounding-box test           */
+    int64_t n_excl_rows;      /* entries carrying an exclusion mask row                    */
+    int64_t effective_pairs;  /* atom pairs inside rc in the last NB_F_ENERGY force call    */
+    int64_t computed_pairs;   /* pair slots evaluated (64 per cluster pair with any pair
+                                 inside rc) in the last NB_F_ENERGY force call              */
+    int64_t grid_columns;     /* total x-y columns over all systems                        */
+    int64_t capacity_per_sc;  /* current list capacity per super-cluster                   */
+    int64_t regrows;          /* list capacity regrowths so far                            */
+} nb_stats;
+
+/*
+ * Create a context for n_systems independent boxes whose atoms are the index ranges
+ * [atom_offsets[s], atom_offsets[s+1]) of every per-atom array (host int64[n_systems+1],
+ * atom_offsets[0] = 0, non-decreasing; empty systems allowed).  hip_stream is a
+ * hipStream_t (NULL = the null stream).  Allocates device memory lazily.
+ * Errors: NB_ERR_ARG for inconsistent parameters (rc <= 0, rinner < rc, rlist < rinner,
+ * n_types out of range, eps_r <= 0, ...).
+ */
+nb_status nb_create(const nb_params* params, int32_t n_systems, const int64_t* atom_offsets,
+                    void* hip_stream, nb_ctx** out);
+
+void nb_destroy(nb_ctx* ctx);
+
+/*
+ * Per-atom LJ types (host int32[N], 0 <= type < n_types) and the force-field exclusions
+ * as a symmetric CSR list (host int64[N+1] row pointers, host int32[] partner atom
+ * indices in the same system); Sec. V.A: excluded pairs never interact and are masked
+ * with bit masks stored with the j-clusters.  Self pairs need not be listed.  Copied once;
+ * fixed for the lifetime of the context.  At most 32 partners per atom.
+ */
+nb_status nb_set_topology(nb_ctx* ctx, const int32_t* type, const int64_t* excl_ptr,
+                          const int32_t* excl_idx);
+
+/*
+ * Grid build (Sec. V.A): wrap the coordinates x (dev float[N][3], continuous, not
+ * re-wrapped by the caller between builds) into the boxes (host float[n_systems][3]) in
+ * single precision, store each atom's image offset, bin atoms into x-y columns, sort each
+ * column on z, cut it into super-cells of 64 atoms and split those 2x2x2 into clusters of
+ * 8; compute cluster bounding boxes.  Requires nb_set_topology.  Errors: NB_ERR_BOX if an
+ * edge is not finite or not above 2 * rlist.  NB_ERR_NONFINITE (reported by the next
+ * nb_pairlist_build) if a coordinate is not finite.
+ */
+nb_status nb_grid_build(nb_ctx* ctx, const float* x, const float* box);
+
+/*
+ * [sync] Outer-list build (Sec. V.A, V.D): per super-cluster, the j-clusters whose
+ * bounding box lies within rlist of one of its i-clusters (27 periodic shifts), each
+ * cluster pair listed once (the canonical owner is the super-cluster of the lower
+ * cluster index); then an atom-distance prune keeps only cluster pairs with an atom pair
+ * closer than rlist (outer list) and marks those closer than rinner (inner list, all parts
+ * pruned at the build positions).  Builds exclusion masks and work items.  Grows its
+ * buffers and retries on overflow unless list_capacity_hint fixes the capacity.
+ * Requires nb_grid_build.
+ */
+nb_status nb_pairlist_build(nb_ctx* ctx);
+
+/*
+ * Rolling prune (Sec. V.E): re-derive the inner masks of part
+ * (steps_since_build mod nstprune) of the outer list from the current coordinates x
+ * (dev float[N][3]) against rinner.  steps_since_build = 0 is a no-op (the build pruned
+ * every part).  Errors: NB_ERR_STATE without a list or when
+ * steps_since_build >= nstlist (the list has expired).
+ */
+nb_status nb_prune_rolling(nb_ctx* ctx, const float* x, int64_t steps_since_build);
+
+/*
+ * Forces (Sec. V.A) over the current inner list: x (dev float[N][3]), q (dev float[N]),
+ * lj (dev float[T][T][2] = (c6, c12) per type pair, symmetric), output f (dev float[N][3]),
+ * and with NB_F_ENERGY energy (dev double[n_systems][2] = LJ, Coulomb), with NB_F_VIRIAL
+ * virial (dev double[n_systems][9], row-major, -1/2 sum over pairs of d (x) f).  Pair
+ * arithmetic is single precision; per-atom force sums are compensated; energies and
+ * virial are reduced in double precision.  Outputs are overwritten unless
+ * NB_F_ACCUMULATE.  energy / virial may be NULL when their flag is not set.
+ * Errors: NB_ERR_STATE without a list.
+ */
+nb_status nb_forces(nb_ctx* ctx, const float* x, const float* q, const float* lj, float* f,
+                    double* energy, double* virial, uint32_t flags);
+
+/*
+ * Backward pass of nb_forces over the frozen inner list: given grad_f = dL/dF (dev
+ * float[N][3]) and optionally grad_energy = dL/dE (dev double[n_systems][2], or NULL),
+ * writes grad_x = dL/dx (dev float[N][3]; the Hessian-vector product of the energy with
+ * grad_f, minus grad_energy times the forces), grad_q = dL/dq (dev float[N]) and
+ * grad_lj = dL/d(c6, c12) (dev double[T][T][2]).  The table must be symmetric
+ * (lj[a][b] = lj[b][a]); the derivative with respect to an off-diagonal value is split
+ * evenly between its two entries, so chaining through any symmetric parameterisation of
+ * the table is exact.  Any of the three outputs may be NULL to skip it.
+ * NB_F_ACCUMULATE adds into the outputs.  Errors: NB_ERR_STATE without a list.
+ */
+nb_status nb_forces_backward(nb_ctx* ctx, const float* x, const float* q, const float* lj,
+                             const float* grad_f, const double* grad_energy, float* grad_x,
+                             float* grad_q, double* grad_lj, uint32_t flags);
+
+/* ---- introspection for tests and tools; all [sync] ---------------------------------- */
+
+/* Slot -> atom map of the current grid (host int32[cap], -1 = empty slot) and its size. */
+nb_status nb_get_grid(nb_ctx* ctx, int32_t* slot_atom, int64_t cap, int64_t* n_slots);
+
+/* Columns per axis of each system's grid (host int32[n_systems][2] = nx, ny). */
+nb_status nb_get_grid_dims(nb_ctx* ctx, int32_t* dims);
+
+/*
+ * Cluster pairs of the outer (which = 1) or inner (which = 2) list as triples
+ * (i-cluster, j-cluster, shift code) in host int32[cap][3]; shift code
+ * (sx+1)*9 + (sy+1)*3 + (sz+1) for the j-cluster image x_j + s L.  *count receives the
+ * number of triples (even when above cap, in which case nothing is written).
+ */
+nb_status nb_get_pairs(nb_ctx* ctx, int32_t which, int32_t* triples, int64_t cap,
+                       int64_t* count);
+
+nb_status nb_get_stats(nb_ctx* ctx, nb_stats* out);
+
+/* Kernel timing with HIP events recorded on the context's stream around each kernel
+ * group (opt-in; for benchmarks and profiling).  Kinds: */
+enum {
+    NB_T_FORCES = 0,          /* the pair force/energy kernel of nb_forces                 */
+    NB_T_FORCE_REDUCE = 1,    /* gather + per-atom force reduction + energy reduction      */
+    NB_T_PRUNE = 2,           /* gather + rolling-prune kernel of nb_prune_rolling         */
+    NB_T_BACKWARD = 3,        /* the pair kernel of nb_forces_backward                     */
+    NB_T_BACKWARD_REDUCE = 4, /* gathers and reductions of nb_forces_backward              */
+    NB_T_COUNT = 5
+};
+
+/* Enable (1) or disable (0) event recording; enabling clears the accumulated totals. */
+nb_status nb_set_timing(nb_ctx* ctx, int32_t enable);
+
+/* [sync] Accumulated milliseconds and launch counts per kind since the last call or since
+ * timing was enabled (host double[NB_T_COUNT], int64[NB_T_COUNT]); then clears them. */
+nb_status nb_get_timing(nb_ctx* ctx, double* ms, int64_t* calls);
+
+const char* nb_strerror(nb_status status);
+const char* nb_last_error(const nb_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NB_H */

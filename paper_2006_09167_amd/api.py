@@ -1,0 +1,235 @@
+"""Python binding of the cluster-pair nonbonded library (torch supplies device memory and
+the stream; every step of the path runs in the HIP kernels of libnbmi.so).
+
+    ctx = Context(n_types=2, coulomb="ewald", rc=1.0, rinner=1.04, rlist=1.1, beta=3.12,
+                  nstlist=100, nstprune=4, atom_offsets=[0, N])
+    ctx.set_topology(types, excl_ptr, excl_idx)
+    ctx.grid_build(x, box); ctx.pairlist_build()
+    f, e, vir = ctx.forces(x, q, lj, energy=True)
+    ctx.prune_rolling(x, steps_since_build)
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import NB_F_ACCUMULATE, NB_F_ENERGY, NB_F_VIRIAL
+
+
+class NBError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (_lib.load().nb_strerror(status).decode(), message))
+        self.status = status
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Context:
+    """One library context (one or several boxes) on one device and stream."""
+
+    def __init__(self, n_types: int, coulomb: str = "rf", rc: float = 1.0,
+                 rinner: Optional[float] = None, rlist: Optional[float] = None,
+                 eps_r: float = 1.0, eps_rf: float = math.inf, beta: float = 0.0,
+                 epsfac: float = 138.935458, modifier: str = "potshift", nstlist: int = 1,
+                 nstprune: int = 1, capacity_hint: int = 0,
+                 atom_offsets: Sequence[int] = (0,), device=None, stream=None):
+        self.lib = _lib.load()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        rinner = rc if rinner is None else rinner
+        rlist = rinner if rlist is None else rlist
+        p = _lib.NbParams(n_types=n_types,
+                          coulomb={"rf": _lib.NB_COUL_RF, "ewald": _lib.NB_COUL_EWALD}[coulomb],
+                          modifier={"none": _lib.NB_MOD_NONE,
+                                    "potshift": _lib.NB_MOD_POTSHIFT}[modifier],
+                          rc=rc, rinner=rinner, rlist=rlist, eps_r=eps_r, eps_rf=eps_rf,
+                          ewald_beta=beta, epsfac=epsfac, nstlist=nstlist, nstprune=nstprune,
+                          list_capacity_hint=capacity_hint)
+        self.params = p
+        self.offsets = np.ascontiguousarray(atom_offsets, dtype=np.int64)
+        self.n_sys = self.offsets.size - 1
+        self.n_atoms = int(self.offsets[-1])
+        self.n_types = n_types
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            h = ctypes.c_void_p()
+            st = self.lib.nb_create(ctypes.byref(p), self.n_sys, _np_ptr(self.offsets),
+                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != 0:
+            raise NBError(st, "nb_create")
+        self.h = h
+
+    # ---- helpers ------------------------------------------------------------------------
+    def _check(self, st: int, what: str):
+        if st != 0:
+            msg = self.lib.nb_last_error(self.h)
+            raise NBError(st, "%s: %s" % (what, msg.decode() if msg else ""))
+
+    def _dev(self, t: torch.Tensor, shape, dtype, name) -> torch.Tensor:
+        if not isinstance(t, torch.Tensor) or t.device != self.device:
+            raise ValueError("%s must be a tensor on %s" % (name, self.device))
+        if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous %s tensor of shape %s (got %s %s)"
+                             % (name, dtype, tuple(shape), t.dtype, tuple(t.shape)))
+        return t
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.nb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- ABI calls -----------------------------------------------------------------------
+    def set_topology(self, types, excl_ptr, excl_idx):
+        t = np.ascontiguousarray(types, dtype=np.int32)
+        ep = np.ascontiguousarray(excl_ptr, dtype=np.int64)
+        ei = np.ascontiguousarray(excl_idx, dtype=np.int32)
+        if t.shape != (self.n_atoms,) or ep.shape != (self.n_atoms + 1,):
+            raise ValueError("topology arrays do not match the atom count")
+        self._check(self.lib.nb_set_topology(self.h, _np_ptr(t), _np_ptr(ep), _np_ptr(ei)),
+                    "nb_set_topology")
+
+    def grid_build(self, x: torch.Tensor, box):
+        x = self._dev(x, (self.n_atoms, 3), torch.float32, "x")
+        b = np.ascontiguousarray(np.asarray(box, dtype=np.float32).reshape(self.n_sys, 3))
+        self._box = b
+        self._check(self.lib.nb_grid_build(self.h, _ptr(x), _np_ptr(b)), "nb_grid_build")
+
+    def pairlist_build(self):
+        self._check(self.lib.nb_pairlist_build(self.h), "nb_pairlist_build")
+
+    def prune_rolling(self, x: torch.Tensor, steps_since_build: int):
+        x = self._dev(x, (self.n_atoms, 3), torch.float32, "x")
+        self._check(self.lib.nb_prune_rolling(self.h, _ptr(x), int(steps_since_build)),
+                    "nb_prune_rolling")
+
+    def forces(self, x, q, lj, energy: bool = True, virial: bool = False, f=None, e=None,
+               vir=None, accumulate: bool = False):
+        """Returns (f [N,3] float32, energy [S,2] float64 or None, virial [S,3,3] or None)."""
+        x = self._dev(x, (self.n_atoms, 3), torch.float32, "x")
+        q = self._dev(q, (self.n_atoms,), torch.float32, "q")
+        lj = self._dev(lj, (self.n_types, self.n_types, 2), torch.float32, "lj")
+        if f is None:
+            f = torch.empty((self.n_atoms, 3), dtype=torch.float32, device=self.device)
+        flags = 0
+        if energy:
+            flags |= NB_F_ENERGY
+            if e is None:
+                e = torch.empty((self.n_sys, 2), dtype=torch.float64, device=self.device)
+        if virial:
+            flags |= NB_F_VIRIAL
+            if vir is None:
+                vir = torch.empty((self.n_sys, 3, 3), dtype=torch.float64, device=self.device)
+        if accumulate:
+            flags |= NB_F_ACCUMULATE
+        self._check(self.lib.nb_forces(self.h, _ptr(x), _ptr(q), _ptr(lj), _ptr(f),
+                                       _ptr(e) if energy else None,
+                                       _ptr(vir) if virial else None, flags), "nb_forces")
+        return f, (e if energy else None), (vir if virial else None)
+
+    def backward(self, x, q, lj, grad_f, grad_energy=None, need_x=True, need_q=True,
+                 need_lj=True, accumulate: bool = False):
+        """Returns (grad_x [N,3] f32, grad_q [N] f32, grad_lj [T,T,2] f64), None if skipped."""
+        x = self._dev(x, (self.n_atoms, 3), torch.float32, "x")
+        q = self._dev(q, (self.n_atoms,), torch.float32, "q")
+        lj = self._dev(lj, (self.n_types, self.n_types, 2), torch.float32, "lj")
+        grad_f = self._dev(grad_f, (self.n_atoms, 3), torch.float32, "grad_f")
+        if grad_energy is not None:
+            grad_energy = self._dev(grad_energy, (self.n_sys, 2), torch.float64, "grad_energy")
+        gx = torch.empty((self.n_atoms, 3), dtype=torch.float32, device=self.device) if need_x else None
+        gq = torch.empty((self.n_atoms,), dtype=torch.float32, device=self.device) if need_q else None
+        gl = torch.empty((self.n_types, self.n_types, 2), dtype=torch.float64,
+                         device=self.device) if need_lj else None
+        flags = NB_F_ACCUMULATE if accumulate else 0
+        self._check(self.lib.nb_forces_backward(self.h, _ptr(x), _ptr(q), _ptr(lj), _ptr(grad_f),
+                                                _ptr(grad_energy), _ptr(gx), _ptr(gq), _ptr(gl),
+                                                flags), "nb_forces_backward")
+        return gx, gq, gl
+
+    # ---- introspection ------------------------------------------------------------------
+    def get_grid(self) -> np.ndarray:
+        n = ctypes.c_int64()
+        self._check(self.lib.nb_get_grid(self.h, None, 0, ctypes.byref(n)), "nb_get_grid")
+        out = np.empty(n.value, dtype=np.int32)
+        self._check(self.lib.nb_get_grid(self.h, _np_ptr(out), n.value, ctypes.byref(n)),
+                    "nb_get_grid")
+        return out
+
+    def get_grid_dims(self) -> np.ndarray:
+        out = np.empty((self.n_sys, 2), dtype=np.int32)
+        self._check(self.lib.nb_get_grid_dims(self.h, _np_ptr(out)), "nb_get_grid_dims")
+        return out
+
+    def get_pairs(self, which: str = "outer") -> np.ndarray:
+        w = {"outer": 1, "inner": 2}[which]
+        n = ctypes.c_int64()
+        self._check(self.lib.nb_get_pairs(self.h, w, None, 0, ctypes.byref(n)), "nb_get_pairs")
+        out = np.empty((n.value, 3), dtype=np.int32)
+        self._check(self.lib.nb_get_pairs(self.h, w, _np_ptr(out), n.value, ctypes.byref(n)),
+                    "nb_get_pairs")
+        return out
+
+    def set_timing(self, enable: bool = True):
+        self._check(self.lib.nb_set_timing(self.h, 1 if enable else 0), "nb_set_timing")
+
+    def get_timing(self) -> dict:
+        """{kind: (milliseconds, launches)} accumulated since the last call (syncs)."""
+        ms = np.zeros(_lib.NB_T_COUNT, dtype=np.float64)
+        calls = np.zeros(_lib.NB_T_COUNT, dtype=np.int64)
+        self._check(self.lib.nb_get_timing(self.h, _np_ptr(ms), _np_ptr(calls)), "nb_get_timing")
+        return {k: (float(ms[i]), int(calls[i])) for i, k in enumerate(_lib.TIMING_KINDS)}
+
+    def stats(self) -> dict:
+        s = _lib.NbStats()
+        self._check(self.lib.nb_get_stats(self.h, ctypes.byref(s)), "nb_get_stats")
+        return {k: int(getattr(s, k)) for k, _ in _lib.NbStats._fields_}
+
+
+def lj_table(sigma: torch.Tensor, eps: torch.Tensor) -> torch.Tensor:
+    """(c6, c12) table [T,T,2] from per-type sigma, epsilon with the Lorentz-Berthelot rule
+    (differentiable; the table itself is what the library consumes)."""
+    s = 0.5 * (sigma[:, None] + sigma[None, :])
+    e = torch.sqrt(eps[:, None] * eps[None, :])
+    return torch.stack([4.0 * e * s ** 6, 4.0 * e * s ** 12], dim=-1).to(torch.float32)
+
+
+class NBForces(torch.autograd.Function):
+    """(x, q, lj) -> (forces [N,3], energies [S,2]) with the HIP backward pass over the
+    frozen inner list: gradients with respect to positions, charges and the LJ table."""
+
+    @staticmethod
+    def forward(fctx, x, q, lj, nb: Context):
+        f, e, _ = nb.forces(x.detach().contiguous(), q.detach().contiguous(),
+                            lj.detach().contiguous(), energy=True)
+        fctx.nb = nb
+        fctx.save_for_backward(x, q, lj)
+        return f, e
+
+    @staticmethod
+    def backward(fctx, gf, ge):
+        x, q, lj = fctx.saved_tensors
+        nb = fctx.nb
+        gf = torch.zeros_like(x) if gf is None else gf.contiguous().to(torch.float32)
+        ge = None if ge is None else ge.contiguous().to(torch.float64)
+        gx, gq, gl = nb.backward(x.detach().contiguous(), q.detach().contiguous(),
+                                 lj.detach().contiguous(), gf, ge,
+                                 need_x=fctx.needs_input_grad[0],
+                                 need_q=fctx.needs_input_grad[1],
+                                 need_lj=fctx.needs_input_grad[2])
+        return gx, gq, (gl.to(lj.dtype) if gl is not None else None), None

@@ -1,0 +1,422 @@
+// Cluster-pair force / energy kernel (Sec. V.A) and the reductions around it.
+//
+// One wavefront processes one work item: a chunk of one super-cluster's joint j-list.
+// Lane l holds the pair (i-atom ii = l & 7, j-atom jj = l >> 3) of the current 8x8
+// cluster pair.  The eight i-clusters' coordinates, charges, types and force
+// accumulators stay in registers for the whole item; per j-entry the loop over the
+// set bits of the interaction mask is uniform (scalar branches, no divergence), the
+// interaction, exclusion and cut-off masks are 64-bit scalar masks applied with one
+// select, and the j-forces are reduced over the eight i-lanes with DPP adds and stored
+// once per entry into the entry's own partial slot (Newton's third law: each pair once).
+// Energies are summed per entry in single precision and accumulated in double.
+//
+// No atomics: every partial has one writer.  A second pass adds, per atom, the
+// j-partials of the entries that reference its cluster (consecutive by construction)
+// and the i-partials of its super-cluster's items with compensated (Neumaier)
+// single-precision sums, and writes the force in the caller's atom order.
+#include "nb_erfc_coeffs.h"
+#include "nb_internal.h"
+
+namespace {
+
+constexpr int kFwdWaves = 4;
+constexpr int kFwdThreads = kFwdWaves * kWave;
+
+__device__ inline float dpp_sum8(float v) {
+    // sum over the 8 consecutive lanes ii = 0..7 of a row half
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                               0xB1, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                               0x4E, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                               0x141, 0xF, 0xF, false));
+    return v;
+}
+
+__device__ inline int shift_x(int code) { return code / 9 - 1; }
+__device__ inline int shift_y(int code) { return (code / 3) % 3 - 1; }
+__device__ inline int shift_z(int code) { return code % 3 - 1; }
+
+__device__ inline uint64_t valid_mask(int ni, int nj, bool diag) {
+    const uint64_t ibyte = (ni >= 8) ? 0xffull : ((1ull << ni) - 1ull);
+    const uint64_t jmask = (nj >= 8) ? ~0ull : ((1ull << (8 * nj)) - 1ull);
+    return ibyte * 0x0101010101010101ull & jmask & (diag ? 0x7f3f1f0f07030100ull : ~0ull);
+}
+
+// erfc(t) exp(t^2) = u P(u), u = 1/(1 + p t) (coefficients fitted by fit_erfc.py).
+__device__ inline float erfcx_poly(float t) {
+    const float u = __builtin_amdgcn_rcpf(fmaf(NB_ERFC_P, t, 1.0f));
+    float p = NB_ERFC_C8;
+    p = fmaf(p, u, NB_ERFC_C7);
+    p = fmaf(p, u, NB_ERFC_C6);
+    p = fmaf(p, u, NB_ERFC_C5);
+    p = fmaf(p, u, NB_ERFC_C4);
+    p = fmaf(p, u, NB_ERFC_C3);
+    p = fmaf(p, u, NB_ERFC_C2);
+    p = fmaf(p, u, NB_ERFC_C1);
+    p = fmaf(p, u, NB_ERFC_C0);
+    return u * p;
+}
+
+struct IData {
+    float x[8], y[8], z[8], q[8];
+    int t[8];
+};
+
+template <int COUL, bool ENERGY, bool VIRIAL, bool SHIFTED>
+__device__ __forceinline__ void entry_pairs(
+    const IData& I, float (&fx)[8], float (&fy)[8], float (&fz)[8], uint32_t mask,
+    const uint64_t (&ivalid)[8], uint64_t jvalid, const uint64_t* __restrict__ xrow,
+    int cj, int ci0, int code, float4 xj, int tj, const float4* __restrict__ s_lj,
+    const NbKParams& kp, float sxi, float syi, float szi, float& fjx, float& fjy, float& fjz,
+    float& elj, float& ec, float (&vir)[6], int& npair, int& nblock) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if (!((mask >> c) & 1u)) continue;
+        uint64_t m = ivalid[c] & jvalid;
+        if (xrow) m &= xrow[c];
+        if (cj == ci0 + c && code == kShiftZero) m &= 0x7f3f1f0f07030100ull;
+        float dx, dy, dz;
+        if (SHIFTED) {
+            dx = (I.x[c] - sxi) - xj.x;
+            dy = (I.y[c] - syi) - xj.y;
+            dz = (I.z[c] - szi) - xj.z;
+        } else {
+            dx = I.x[c] - xj.x;
+            dy = I.y[c] - xj.y;
+            dz = I.z[c] - xj.z;
+        }
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        const uint64_t act = __builtin_amdgcn_ballot_w64(r2 < kp.rc2) & m;
+        if (!act) continue;
+        const bool on = __builtin_amdgcn_inverse_ballot_w64(act);
+        const float rinv = __builtin_amdgcn_rsqf(r2);
+        const float rinv2 = rinv * rinv;
+        const float4 p = s_lj[I.t[c] + tj];              // (6 c6, 12 c12, shift, c6)
+        const float rinv6 = rinv2 * rinv2 * rinv2;
+        const float a = p.y * rinv6;
+        const float flj = rinv6 * (a - p.x);               // F_LJ * r
+        const float qq = I.q[c] * xj.w;                    // epsfac/eps_r folded into q_i
+        float fscal, vc = 0.f;
+        if (COUL == NB_COUL_RF) {
+            fscal = fmaf(flj, rinv2, qq * (rinv * rinv2 - 2.0f * kp.krf));
+            if (ENERGY) vc = qq * (fmaf(kp.krf, r2, rinv) - kp.crf);
+        } else {
+            const float r = r2 * rinv;
+            const float e = __builtin_amdgcn_exp2f(r2 * kp.beta2_log2e);   // exp(-beta^2 r^2)
+            const float erfcv = e * erfcx_poly(kp.beta * r);
+            const float g = fmaf(erfcv, rinv, kp.two_beta_sqrtpi * e);
+            fscal = fmaf(qq, g, flj) * rinv2;
+            if (ENERGY) vc = qq * fmaf(erfcv, rinv, -kp.ewald_shift);
+        }
+        fscal = on ? fscal : 0.f;
+        const float tx = fscal * dx, ty = fscal * dy, tz = fscal * dz;
+        fx[c] += tx;
+        fy[c] += ty;
+        fz[c] += tz;
+        fjx -= tx;
+        fjy -= ty;
+        fjz -= tz;
+        if (ENERGY) {
+            const float vlj = fmaf(rinv6, fmaf(a, 1.0f / 12.0f, -p.w), -p.z);
+            elj += on ? vlj : 0.f;
+            ec += on ? vc : 0.f;
+            npair += __builtin_popcountll(act);
+            nblock += 1;
+        }
+        if (VIRIAL) {
+            vir[0] = fmaf(tx, dx, vir[0]);
+            vir[1] = fmaf(ty, dy, vir[1]);
+            vir[2] = fmaf(tz, dz, vir[2]);
+            vir[3] = fmaf(tx, dy, vir[3]);
+            vir[4] = fmaf(tx, dz, vir[4]);
+            vir[5] = fmaf(ty, dz, vir[5]);
+        }
+    }
+}
+
+template <int COUL, bool ENERGY, bool VIRIAL>
+__global__ __launch_bounds__(kFwdThreads) void k_nb_fwd(NbDev d, NbKParams kp,
+                                                         const float* __restrict__ lj,
+                                                         int n_items) {
+    extern __shared__ float4 s_lj[];
+    const int T = kp.n_types;
+    for (int i = threadIdx.x; i < T * T; i += blockDim.x) {
+        const float c6 = lj[2 * i], c12 = lj[2 * i + 1];
+        s_lj[i] = make_float4(6.0f * c6, 12.0f * c12, c12 * kp.rc_m12 - c6 * kp.rc_m6, c6);
+    }
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int item = blockIdx.x * kFwdWaves + wave;
+    if (item >= n_items) return;
+    const NbItem it = d.items[item];
+    const int ii = lane & 7, jj = lane >> 3;
+    const int sc = it.sc, ci0 = kClustersPerSc * sc;
+    const NbSys S = d.sys[it.sys];
+
+    IData I;
+    uint64_t ivalid[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const float4 v = d.xq[kScAtoms * sc + kClusterSize * c + ii];
+        I.x[c] = v.x;
+        I.y[c] = v.y;
+        I.z[c] = v.z;
+        I.q[c] = v.w * kp.epsfac_r;
+        I.t[c] = d.type_slot[kScAtoms * sc + kClusterSize * c + ii] * T;
+        const int ni = (int)d.cl_bb[2 * (ci0 + c)].w;
+        ivalid[c] = ((ni >= 8) ? 0xffull : ((1ull << ni) - 1ull)) * 0x0101010101010101ull;
+    }
+    float fx[8], fy[8], fz[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) fx[c] = fy[c] = fz[c] = 0.f;
+    double elj_acc = 0.0, ec_acc = 0.0;
+    double vir_acc[6] = {0, 0, 0, 0, 0, 0};
+    int npair = 0, nblock = 0;
+
+    for (int e = it.e0; e < it.e0 + it.ne; ++e) {
+        const NbEntry ent = d.entries[e];
+        const uint32_t mask = (ent.meta >> 16) & 0xffu;
+        float4* jp = d.jpart + (size_t)ent.jpos * kClusterSize;
+        if (!mask) {
+            if (ii == 0) jp[jj] = make_float4(0.f, 0.f, 0.f, 0.f);
+            continue;
+        }
+        const int code = ent.meta & 31u;
+        const int nj = (int)(ent.meta >> 24);
+        const uint64_t jvalid = (nj >= 8) ? ~0ull : ((1ull << (8 * nj)) - 1ull);
+        const uint64_t* xrow =
+            (ent.excl >= 0) ? d.excl_rows + (size_t)ent.excl * kClustersPerSc : nullptr;
+        float4 xj = d.xq[kClusterSize * ent.cj + jj];
+        const int tj = d.type_slot[kClusterSize * ent.cj + jj];
+        float fjx = 0.f, fjy = 0.f, fjz = 0.f, elj = 0.f, ec = 0.f;
+        float vir[6] = {0, 0, 0, 0, 0, 0};
+        if (code == kShiftZero) {
+            entry_pairs<COUL, ENERGY, VIRIAL, false>(I, fx, fy, fz, mask, ivalid, jvalid, xrow,
+                                                     ent.cj, ci0, code, xj, tj, s_lj, kp, 0.f,
+                                                     0.f, 0.f, fjx, fjy, fjz, elj, ec, vir,
+                                                     npair, nblock);
+        } else {
+            // Exact periodic shift: subtract L on the side whose coordinate is near L.
+            const int sx = shift_x(code), sy = shift_y(code), sz = shift_z(code);
+            if (sx < 0) xj.x -= S.L[0];
+            if (sy < 0) xj.y -= S.L[1];
+            if (sz < 0) xj.z -= S.L[2];
+            entry_pairs<COUL, ENERGY, VIRIAL, true>(
+                I, fx, fy, fz, mask, ivalid, jvalid, xrow, ent.cj, ci0, code, xj, tj, s_lj, kp,
+                sx > 0 ? S.L[0] : 0.f, sy > 0 ? S.L[1] : 0.f, sz > 0 ? S.L[2] : 0.f, fjx, fjy,
+                fjz, elj, ec, vir, npair, nblock);
+        }
+        fjx = dpp_sum8(fjx);
+        fjy = dpp_sum8(fjy);
+        fjz = dpp_sum8(fjz);
+        if (ii == 0) jp[jj] = make_float4(fjx, fjy, fjz, 0.f);
+        if (ENERGY) {
+            elj_acc += (double)elj;
+            ec_acc += (double)ec;
+        }
+        if (VIRIAL) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) vir_acc[k] += (double)vir[k];
+        }
+    }
+    // i-forces: reduce over the eight j-lanes jj (stride 8) and store the item's partials.
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+#pragma unroll
+        for (int off = 8; off < kWave; off <<= 1) {
+            fx[c] += __shfl_xor(fx[c], off);
+            fy[c] += __shfl_xor(fy[c], off);
+            fz[c] += __shfl_xor(fz[c], off);
+        }
+    }
+    if (jj == 0) {
+        float4* ip = d.ipart + (size_t)item * kScAtoms;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) ip[kClusterSize * c + ii] = make_float4(fx[c], fy[c], fz[c], 0.f);
+    }
+    if (ENERGY || VIRIAL) {
+        double v[8] = {elj_acc, ec_acc, vir_acc[0], vir_acc[1], vir_acc[2], vir_acc[3],
+                       vir_acc[4], vir_acc[5]};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) v[k] += __shfl_xor(v[k], off);
+        }
+        if (lane == 0) {
+            double* ep = d.epart + (size_t)item * kEpartStride;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) ep[k] = v[k];
+            ep[8] = (double)npair;
+            ep[9] = 64.0 * (double)nblock;
+        }
+    }
+}
+
+// Per-slot gather of user-order coordinates (and charges) into slot order, wrapped with
+// the image offsets of the last grid build in the same sequence as the build.
+__global__ void k_gather(NbDev d, const float* __restrict__ x, const float* __restrict__ q,
+                         float4* __restrict__ out, int n_slots) {
+#pragma clang fp contract(off)
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= n_slots) return;
+    const int a = d.slot_atom[slot];
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (a >= 0) {
+        const int4 k = d.img[a];
+        const NbSys S = d.sys[d.atom_sys[a]];
+        const float kx = (float)k.x * S.L[0], ky = (float)k.y * S.L[1], kz = (float)k.z * S.L[2];
+        v.x = x[3 * a] - kx;
+        v.y = x[3 * a + 1] - ky;
+        v.z = x[3 * a + 2] - kz;
+        v.w = q ? q[a] : 0.f;
+    }
+    out[slot] = v;
+}
+
+__device__ inline void neumaier(float& s, float& c, float v) {
+    const float t = s + v;
+    c += (fabsf(s) >= fabsf(v)) ? ((s - t) + v) : ((v - t) + s);
+    s = t;
+}
+
+// Per slot: compensated sum of its j-partials and its super-cluster's i-partials.
+__global__ void k_reduce_f(NbDev d, float* __restrict__ f, int accumulate, int n_slots) {
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= n_slots) return;
+    const int a = d.slot_atom[slot];
+    if (a < 0) return;
+    const int cj = slot / kClusterSize, jj = slot % kClusterSize;
+    const int sc = slot / kScAtoms, loc = slot % kScAtoms;
+    float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+    for (int k = d.jseg_start[cj]; k < d.jseg_start[cj + 1]; ++k) {
+        const float4 v = d.jpart[(size_t)k * kClusterSize + jj];
+        neumaier(sx, cx, v.x);
+        neumaier(sy, cy, v.y);
+        neumaier(sz, cz, v.z);
+    }
+    const int i0 = d.sc_istart[sc], i1 = i0 + d.sc_icount[sc];
+    for (int i = i0; i < i1; ++i) {
+        const float4 v = d.ipart[(size_t)i * kScAtoms + loc];
+        neumaier(sx, cx, v.x);
+        neumaier(sy, cy, v.y);
+        neumaier(sz, cz, v.z);
+    }
+    float rx = sx + cx, ry = sy + cy, rz = sz + cz;
+    if (accumulate) {
+        rx += f[3 * a];
+        ry += f[3 * a + 1];
+        rz += f[3 * a + 2];
+    }
+    f[3 * a] = rx;
+    f[3 * a + 1] = ry;
+    f[3 * a + 2] = rz;
+}
+
+// Zero forces of atoms that no slot covers (only possible for an empty grid) is not
+// needed: every atom has a slot after a grid build.
+
+constexpr int kRedThreads = 256;
+
+// One block per system: FP64 sums of the per-item energies, virial and pair counts in a
+// fixed order (deterministic).
+__global__ __launch_bounds__(kRedThreads) void k_reduce_e(NbDev d, double* __restrict__ energy,
+                                                          double* __restrict__ virial,
+                                                          uint32_t flags,
+                                                          double* __restrict__ pairs_out) {
+    __shared__ double s_v[kRedThreads];
+    const int sys = blockIdx.x;
+    const int sc0 = d.sys_sc_start[sys], sc1 = d.sys_sc_start[sys + 1];
+    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int sc = sc0 + threadIdx.x; sc < sc1; sc += blockDim.x) {
+        const int i0 = d.sc_istart[sc], i1 = i0 + d.sc_icount[sc];
+        for (int i = i0; i < i1; ++i) {
+            const double* ep = d.epart + (size_t)i * kEpartStride;
+            for (int k = 0; k < 10; ++k) acc[k] += ep[k];
+        }
+    }
+    double out[10];
+    for (int k = 0; k < 10; ++k) {
+        s_v[threadIdx.x] = acc[k];
+        __syncthreads();
+        for (int off = kRedThreads / 2; off > 0; off >>= 1) {
+            if (threadIdx.x < off) s_v[threadIdx.x] += s_v[threadIdx.x + off];
+            __syncthreads();
+        }
+        out[k] = s_v[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const bool accum = flags & NB_F_ACCUMULATE;
+        if ((flags & NB_F_ENERGY) && energy) {
+            energy[2 * sys] = (accum ? energy[2 * sys] : 0.0) + out[0];
+            energy[2 * sys + 1] = (accum ? energy[2 * sys + 1] : 0.0) + out[1];
+        }
+        if ((flags & NB_F_VIRIAL) && virial) {
+            // Xi = -1/2 sum d (x) f, symmetric: xx yy zz xy xz yz
+            const double v[9] = {out[2], out[5], out[6], out[5], out[3], out[7],
+                                 out[6], out[7], out[4]};
+            for (int k = 0; k < 9; ++k)
+                virial[9 * sys + k] = (accum ? virial[9 * sys + k] : 0.0) - 0.5 * v[k];
+        }
+        if (pairs_out) {
+            atomicAdd(pairs_out, out[8]);
+            atomicAdd(pairs_out + 1, out[9]);
+        }
+    }
+}
+
+inline int blocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
+
+template <int COUL, bool E, bool V>
+void launch_fwd_t(const NbDev& d, const NbKParams& kp, const float* lj, int n_items,
+                  hipStream_t s) {
+    const size_t lds = sizeof(float4) * (size_t)kp.n_types * kp.n_types;
+    hipLaunchKernelGGL((k_nb_fwd<COUL, E, V>), dim3(blocks(n_items, kFwdWaves)),
+                       dim3(kFwdThreads), lds, s, d, kp, lj, n_items);
+}
+
+}  // namespace
+
+hipError_t launch_gather(const NbDev& d, const float* x, const float* q, float4* out,
+                         int n_slots, hipStream_t s) {
+    if (n_slots > 0)
+        hipLaunchKernelGGL(k_gather, dim3(blocks(n_slots, 256)), dim3(256), 0, s, d, x, q, out,
+                           n_slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_forces(const NbDev& d, const NbKParams& kp, int coulomb, uint32_t flags,
+                         const float* lj, int n_items, hipStream_t s) {
+    if (n_items <= 0) return hipGetLastError();
+    const bool E = (flags & NB_F_ENERGY) != 0, V = (flags & NB_F_VIRIAL) != 0;
+    if (coulomb == NB_COUL_RF) {
+        if (E && V) launch_fwd_t<NB_COUL_RF, true, true>(d, kp, lj, n_items, s);
+        else if (E) launch_fwd_t<NB_COUL_RF, true, false>(d, kp, lj, n_items, s);
+        else if (V) launch_fwd_t<NB_COUL_RF, false, true>(d, kp, lj, n_items, s);
+        else launch_fwd_t<NB_COUL_RF, false, false>(d, kp, lj, n_items, s);
+    } else {
+        if (E && V) launch_fwd_t<NB_COUL_EWALD, true, true>(d, kp, lj, n_items, s);
+        else if (E) launch_fwd_t<NB_COUL_EWALD, true, false>(d, kp, lj, n_items, s);
+        else if (V) launch_fwd_t<NB_COUL_EWALD, false, true>(d, kp, lj, n_items, s);
+        else launch_fwd_t<NB_COUL_EWALD, false, false>(d, kp, lj, n_items, s);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_forces(const NbDev& d, float* f, bool accumulate, int n_slots,
+                                hipStream_t s) {
+    if (n_slots > 0)
+        hipLaunchKernelGGL(k_reduce_f, dim3(blocks(n_slots, 256)), dim3(256), 0, s, d, f,
+                           accumulate ? 1 : 0, n_slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_energies(const NbDev& d, double* energy, double* virial,
+                                  uint32_t flags, int n_sys, hipStream_t s) {
+    if (n_sys > 0)
+        hipLaunchKernelGGL(k_reduce_e, dim3(n_sys), dim3(kRedThreads), 0, s, d, energy, virial,
+                           flags, d.dstat);
+    return hipGetLastError();
+}

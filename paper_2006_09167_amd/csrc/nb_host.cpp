@@ -1,0 +1,666 @@
+// Host layer of the C ABI (include/nb.h): argument validation, device buffers, and the
+// order of kernel launches for the grid build, the dual pair list and the force passes.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "nb_internal.h"
+
+struct nb_ctx {
+    nb_params p{};
+    int32_t n_sys = 0;
+    std::vector<int64_t> offs;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    NbDev d;
+    std::vector<NbSys> hsys;
+    bool has_topology = false, has_grid = false, has_list = false;
+    int32_t n_sc = 0, n_cl = 0, n_slots = 0;
+    int64_t n_entries = 0;
+    int32_t n_items = 0;
+    int32_t cap = 0;          // entries per super-cluster in the search scratch
+    int32_t item_w = 0;       // entries per work item
+    std::vector<int32_t> part_start;
+    nb_stats stats{};
+    std::string err;
+    // allocated element counts
+    size_t a_atoms = 0, a_cols = 0, a_sc = 0, a_scratch = 0, a_entries = 0, a_items = 0;
+    size_t a_excl_nnz = 0;
+    // opt-in kernel timing: event pairs per kind, recorded on the stream
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[NB_T_COUNT];
+    std::vector<hipEvent_t> ev_free;
+    double t_ms[NB_T_COUNT] = {0, 0, 0, 0, 0};
+    int64_t t_calls[NB_T_COUNT] = {0, 0, 0, 0, 0};
+};
+
+namespace {
+
+template <typename T>
+hipError_t dev_alloc(T*& p, size_t n) {
+    if (p) {
+        hipError_t e = hipFree(p);
+        p = nullptr;
+        if (e != hipSuccess) return e;
+    }
+    if (n == 0) n = 1;
+    return hipMalloc((void**)&p, n * sizeof(T));
+}
+
+nb_status fail(nb_ctx* c, nb_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+nb_status hip_fail(nb_ctx* c, hipError_t e, const char* where) {
+    return fail(c, NB_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define NB_HIP(ctx, call)                                          \
+    do {                                                           \
+        hipError_t e_ = (call);                                    \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #call);   \
+    } while (0)
+
+bool finite_pos(float v) { return isfinite(v) && v > 0.f; }
+
+NbKParams kernel_params(const nb_params& p) {
+    NbKParams k{};
+    const double rc = p.rc;
+    k.rc2 = (float)(rc * rc);
+    double krf;
+    if (isinf(p.eps_rf)) krf = 1.0 / (2.0 * rc * rc * rc);
+    else krf = ((double)p.eps_rf - p.eps_r) / ((2.0 * p.eps_rf + p.eps_r) * rc * rc * rc);
+    k.krf = (float)krf;
+    k.crf = (float)(1.0 / rc + krf * rc * rc);
+    const double b = p.ewald_beta;
+    k.beta = (float)b;
+    k.beta2_log2e = (float)(-b * b / log(2.0));
+    k.two_beta_sqrtpi = (float)(2.0 * b / sqrt(M_PI));
+    const bool shift = p.modifier == NB_MOD_POTSHIFT;
+    k.ewald_shift = shift ? (float)(erfc(b * rc) / rc) : 0.f;
+    k.epsfac_r = (float)((double)p.epsfac / p.eps_r);
+    k.rc_m6 = shift ? (float)pow(rc, -6.0) : 0.f;
+    k.rc_m12 = shift ? (float)pow(rc, -12.0) : 0.f;
+    k.n_types = p.n_types;
+    return k;
+}
+
+float radius_sq(float r) { return (float)((double)r * (double)r); }
+
+nb_status sync(nb_ctx* c) {
+    NB_HIP(c, hipStreamSynchronize(c->stream));
+    return NB_OK;
+}
+
+template <typename T>
+nb_status to_host(nb_ctx* c, T* host, const T* dev, size_t n) {
+    if (n == 0) return NB_OK;
+    NB_HIP(c, hipMemcpyAsync(host, dev, n * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+    return sync(c);
+}
+
+// Device resources of a context are allocated at its first device call, after the
+// arguments of that call have been validated (creation itself touches no device).
+nb_status ensure_device(nb_ctx* c) {
+    if (c->device < 0) NB_HIP(c, hipGetDevice(&c->device));
+    NB_HIP(c, hipSetDevice(c->device));
+    if (c->d.flags) return NB_OK;
+    NbDev& d = c->d;
+    NB_HIP(c, dev_alloc(d.flags, kFlagCount));
+    NB_HIP(c, dev_alloc(d.totals, 8));
+    NB_HIP(c, dev_alloc(d.dstat, 4));
+    NB_HIP(c, dev_alloc(d.sys, c->n_sys));
+    NB_HIP(c, dev_alloc(d.sys_sc_start, c->n_sys + 1));
+    NB_HIP(c, dev_alloc(d.part_start, c->p.nstprune + 1));
+    return NB_OK;
+}
+
+hipEvent_t take_event(nb_ctx* c) {
+    if (!c->ev_free.empty()) {
+        hipEvent_t e = c->ev_free.back();
+        c->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Start / stop an event pair of the given kind around the launches in between.
+struct TimedSection {
+    nb_ctx* c;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedSection(nb_ctx* c_, int k) : c(c_), kind(k) {
+        if (!c->timing) return;
+        a = take_event(c);
+        b = take_event(c);
+        if (a) hipEventRecord(a, c->stream);
+    }
+    ~TimedSection() {
+        if (!c->timing || !a || !b) return;
+        hipEventRecord(b, c->stream);
+        c->ev[kind].emplace_back(a, b);
+    }
+};
+
+nb_status collect_timing(nb_ctx* c) {
+    NB_HIP(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < NB_T_COUNT; ++k) {
+        for (auto& pr : c->ev[k]) {
+            float ms = 0.f;
+            NB_HIP(c, hipEventElapsedTime(&ms, pr.first, pr.second));
+            c->t_ms[k] += ms;
+            c->t_calls[k] += 1;
+            c->ev_free.push_back(pr.first);
+            c->ev_free.push_back(pr.second);
+        }
+        c->ev[k].clear();
+    }
+    return NB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nb_strerror(nb_status s) {
+    switch (s) {
+        case NB_OK: return "ok";
+        case NB_ERR_ARG: return "invalid argument";
+        case NB_ERR_BOX: return "invalid box (edges must be finite and above 2 * rlist)";
+        case NB_ERR_NOMEM: return "out of memory";
+        case NB_ERR_CAPACITY: return "list capacity exceeded";
+        case NB_ERR_STATE: return "call out of order";
+        case NB_ERR_HIP: return "HIP runtime error";
+        case NB_ERR_NONFINITE: return "non-finite coordinates";
+    }
+    return "unknown status";
+}
+
+const char* nb_last_error(const nb_ctx* c) { return c ? c->err.c_str() : ""; }
+
+nb_status nb_create(const nb_params* params, int32_t n_systems, const int64_t* atom_offsets,
+                    void* hip_stream, nb_ctx** out) {
+    if (!out) return NB_ERR_ARG;
+    *out = nullptr;
+    if (!params || !atom_offsets || n_systems < 1) return NB_ERR_ARG;
+    const nb_params& p = *params;
+    if (p.n_types < 1 || p.n_types > kMaxTypes) return NB_ERR_ARG;
+    if (p.coulomb != NB_COUL_RF && p.coulomb != NB_COUL_EWALD) return NB_ERR_ARG;
+    if (p.modifier != NB_MOD_NONE && p.modifier != NB_MOD_POTSHIFT) return NB_ERR_ARG;
+    if (!finite_pos(p.rc) || !isfinite(p.rinner) || !isfinite(p.rlist)) return NB_ERR_ARG;
+    if (p.rinner < p.rc || p.rlist < p.rinner) return NB_ERR_ARG;
+    if (!finite_pos(p.eps_r) || !(p.eps_rf > 0.f) || isnan(p.eps_rf)) return NB_ERR_ARG;
+    if (!isfinite(p.epsfac) || !isfinite(p.ewald_beta) || p.ewald_beta < 0.f) return NB_ERR_ARG;
+    if (p.coulomb == NB_COUL_EWALD && !(p.ewald_beta > 0.f)) return NB_ERR_ARG;
+    if (p.nstlist < 1 || p.nstprune < 1 || p.nstprune > 64) return NB_ERR_ARG;
+    if (p.list_capacity_hint < 0 || p.list_capacity_hint > (1 << 20)) return NB_ERR_ARG;
+    if (atom_offsets[0] != 0) return NB_ERR_ARG;
+    for (int s = 0; s < n_systems; ++s)
+        if (atom_offsets[s + 1] < atom_offsets[s]) return NB_ERR_ARG;
+    if (atom_offsets[n_systems] > (int64_t)1 << 30) return NB_ERR_ARG;
+    nb_ctx* c = new (std::nothrow) nb_ctx();
+    if (!c) return NB_ERR_NOMEM;
+    c->p = p;
+    c->n_sys = n_systems;
+    c->offs.assign(atom_offsets, atom_offsets + n_systems + 1);
+    c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;   // resolved at first use
+    c->d.n_atoms = (int32_t)c->offs[n_systems];
+    c->d.n_sys = n_systems;
+    c->d.n_types = p.n_types;
+    c->cap = p.list_capacity_hint > 0 ? (int32_t)p.list_capacity_hint : 256;
+    c->stats.n_atoms = c->d.n_atoms;
+    c->hsys.resize(n_systems);
+    *out = c;
+    return NB_OK;
+}
+
+void nb_destroy(nb_ctx* c) {
+    if (!c) return;
+    if (c->d.flags) {
+        hipSetDevice(c->device);
+        hipStreamSynchronize(c->stream);
+    }
+    NbDev& d = c->d;
+    void* ptrs[] = {d.type, d.atom_sys, d.excl_ptr, d.excl_idx, d.sys, d.sys_sc_start, d.img,
+                    d.wpos, d.col_count, d.col_start, d.col_sc_start, d.col_cursor, d.col_atoms,
+                    d.col_sorted, d.sc_info, d.slot_atom, d.atom_slot, d.type_slot, d.excl_slot,
+                    d.cl_bb, d.sc_bb, d.xw, d.xq, d.xp, d.gslot, d.sc_ecount, d.sc_estart,
+                    d.sc_istart, d.sc_icount, d.scratch, d.entries, d.entry_sc, d.items,
+                    d.part_start, d.excl_rows, d.jseg_count, d.jseg_start, d.jseg_fill,
+                    d.jseg_entries, d.totals, d.flags, d.jpart, d.ipart, d.epart, d.glj_part,
+                    d.dstat};
+    for (void* q : ptrs)
+        if (q) hipFree(q);
+    for (int k = 0; k < NB_T_COUNT; ++k)
+        for (auto& pr : c->ev[k]) {
+            hipEventDestroy(pr.first);
+            hipEventDestroy(pr.second);
+        }
+    for (hipEvent_t e : c->ev_free) hipEventDestroy(e);
+    delete c;
+}
+
+nb_status nb_set_topology(nb_ctx* c, const int32_t* type, const int64_t* excl_ptr,
+                          const int32_t* excl_idx) {
+    if (!c) return NB_ERR_ARG;
+    const int64_t n = c->d.n_atoms;
+    if ((n > 0 && (!type || !excl_ptr)) || (excl_ptr && excl_ptr[0] != 0))
+        return fail(c, NB_ERR_ARG, "topology arrays missing or excl_ptr[0] != 0");
+    std::vector<int32_t> hsys(n), hptr(n + 1), hidx;
+    int max_excl = 0;
+    for (int s = 0; s < c->n_sys; ++s)
+        for (int64_t a = c->offs[s]; a < c->offs[s + 1]; ++a) hsys[a] = s;
+    for (int64_t a = 0; a < n; ++a) {
+        if (type[a] < 0 || type[a] >= c->p.n_types)
+            return fail(c, NB_ERR_ARG, "atom type out of range at atom " + std::to_string(a));
+        if (excl_ptr[a + 1] < excl_ptr[a])
+            return fail(c, NB_ERR_ARG, "exclusion row pointers decrease");
+        const int64_t len = excl_ptr[a + 1] - excl_ptr[a];
+        if (len > kMaxExcl) return fail(c, NB_ERR_ARG, "more than 32 exclusions for one atom");
+        max_excl = std::max<int>(max_excl, (int)len);
+        for (int64_t k = excl_ptr[a]; k < excl_ptr[a + 1]; ++k) {
+            const int32_t b = excl_idx ? excl_idx[k] : -1;
+            if (b < 0 || b >= n || hsys[b] != hsys[a])
+                return fail(c, NB_ERR_ARG, "exclusion partner out of range or in another system");
+        }
+    }
+    const int64_t nnz = n > 0 ? excl_ptr[n] : 0;
+    if (nnz > INT32_MAX) return fail(c, NB_ERR_ARG, "too many exclusions");
+    for (int64_t a = 0; a <= n; ++a) hptr[a] = n > 0 ? (int32_t)excl_ptr[a] : 0;
+    NbDev& d = c->d;
+    nb_status st = ensure_device(c);
+    if (st != NB_OK) return st;
+    NB_HIP(c, dev_alloc(d.type, n));
+    NB_HIP(c, dev_alloc(d.atom_sys, n));
+    NB_HIP(c, dev_alloc(d.excl_ptr, n + 1));
+    NB_HIP(c, dev_alloc(d.excl_idx, nnz));
+    if (n > 0) {
+        NB_HIP(c, hipMemcpy(d.type, type, n * sizeof(int32_t), hipMemcpyHostToDevice));
+        NB_HIP(c, hipMemcpy(d.atom_sys, hsys.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
+        NB_HIP(c, hipMemcpy(d.excl_ptr, hptr.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+        if (nnz > 0)
+            NB_HIP(c, hipMemcpy(d.excl_idx, excl_idx, nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    d.max_excl = max_excl;
+    c->has_topology = true;
+    c->has_grid = c->has_list = false;
+    return NB_OK;
+}
+
+nb_status nb_grid_build(nb_ctx* c, const float* x, const float* box) {
+    if (!c) return NB_ERR_ARG;
+    if (!c->has_topology) return fail(c, NB_ERR_STATE, "nb_set_topology has not been called");
+    if (!box || (c->d.n_atoms > 0 && !x)) return fail(c, NB_ERR_ARG, "null coordinates or box");
+    const float rlist = c->p.rlist;
+    int n_cols = 0;
+    int64_t n_sc_max = 0;
+    for (int s = 0; s < c->n_sys; ++s) {
+        NbSys S{};
+        for (int k = 0; k < 3; ++k) {
+            const float L = box[3 * s + k];
+            if (!isfinite(L) || !(L > 2.0f * rlist))
+                return fail(c, NB_ERR_BOX, "box edge " + std::to_string(k) + " of system " +
+                                               std::to_string(s) + " not above 2 * rlist");
+            S.L[k] = L;
+            S.invL[k] = (float)(1.0 / (double)L);
+        }
+        const int64_t na = c->offs[s + 1] - c->offs[s];
+        int nx = 1, ny = 1;
+        if (na > 0) {
+            const double V = (double)S.L[0] * (double)S.L[1] * (double)S.L[2];
+            const double size = cbrt(64.0 * V / (double)na);
+            nx = std::max(1, (int)floor((double)S.L[0] / size + 0.5));
+            ny = std::max(1, (int)floor((double)S.L[1] / size + 0.5));
+        }
+        if ((int64_t)nx * ny > (1 << 22)) return fail(c, NB_ERR_BOX, "grid too large");
+        S.nx = nx;
+        S.ny = ny;
+        S.cinv[0] = (float)((double)nx / (double)S.L[0]);
+        S.cinv[1] = (float)((double)ny / (double)S.L[1]);
+        S.colw[0] = (float)((double)S.L[0] / nx);
+        S.colw[1] = (float)((double)S.L[1] / ny);
+        S.col_base = n_cols;
+        S.atom0 = (int32_t)c->offs[s];
+        S.atom1 = (int32_t)c->offs[s + 1];
+        n_cols += nx * ny;
+        n_sc_max += (na + kScAtoms - 1) / kScAtoms + (int64_t)nx * ny;
+        c->hsys[s] = S;
+    }
+    if (n_sc_max * kScAtoms > INT32_MAX / 2) return fail(c, NB_ERR_ARG, "too many atoms");
+    NbDev& d = c->d;
+    NB_HIP(c, hipSetDevice(c->device));
+    const size_t N = (size_t)d.n_atoms;
+    if (N > c->a_atoms) {
+        NB_HIP(c, dev_alloc(d.img, N));
+        NB_HIP(c, dev_alloc(d.wpos, N));
+        NB_HIP(c, dev_alloc(d.col_atoms, N));
+        NB_HIP(c, dev_alloc(d.col_sorted, N));
+        NB_HIP(c, dev_alloc(d.atom_slot, N));
+        c->a_atoms = N;
+    }
+    if ((size_t)n_cols > c->a_cols || !d.col_count) {
+        NB_HIP(c, dev_alloc(d.col_count, n_cols));
+        NB_HIP(c, dev_alloc(d.col_start, n_cols + 1));
+        NB_HIP(c, dev_alloc(d.col_sc_start, n_cols + 1));
+        NB_HIP(c, dev_alloc(d.col_cursor, n_cols));
+        c->a_cols = n_cols;
+    }
+    if ((size_t)n_sc_max > c->a_sc || !d.sc_info) {
+        const size_t ns = (size_t)n_sc_max, slots = ns * kScAtoms, cl = ns * kClustersPerSc;
+        NB_HIP(c, dev_alloc(d.sc_info, ns));
+        NB_HIP(c, dev_alloc(d.slot_atom, slots));
+        NB_HIP(c, dev_alloc(d.type_slot, slots));
+        NB_HIP(c, dev_alloc(d.cl_bb, 2 * cl));
+        NB_HIP(c, dev_alloc(d.sc_bb, 2 * ns));
+        NB_HIP(c, dev_alloc(d.xw, slots));
+        NB_HIP(c, dev_alloc(d.xq, slots));
+        NB_HIP(c, dev_alloc(d.xp, slots));
+        NB_HIP(c, dev_alloc(d.gslot, slots));
+        NB_HIP(c, dev_alloc(d.sc_ecount, ns));
+        NB_HIP(c, dev_alloc(d.sc_estart, ns + 1));
+        NB_HIP(c, dev_alloc(d.sc_istart, ns + 1));
+        NB_HIP(c, dev_alloc(d.sc_icount, ns));
+        NB_HIP(c, dev_alloc(d.jseg_count, cl + 8));
+        NB_HIP(c, dev_alloc(d.jseg_start, cl + 9));
+        NB_HIP(c, dev_alloc(d.jseg_fill, cl + 8));
+        c->a_sc = ns;
+        c->a_excl_nnz = 0;
+    }
+    if (c->a_excl_nnz < (size_t)n_sc_max * kScAtoms * std::max(1, d.max_excl) || !d.excl_slot) {
+        const size_t ne = (size_t)n_sc_max * kScAtoms * std::max(1, d.max_excl);
+        NB_HIP(c, dev_alloc(d.excl_slot, ne));
+        c->a_excl_nnz = ne;
+    }
+    d.n_cols = n_cols;
+    d.n_sc_max = (int32_t)n_sc_max;
+    NB_HIP(c, hipMemcpyAsync(d.sys, c->hsys.data(), sizeof(NbSys) * c->n_sys,
+                             hipMemcpyHostToDevice, c->stream));
+    NB_HIP(c, launch_fill(d.flags, kFlagCount, 0, c->stream));
+    NB_HIP(c, launch_grid_build(d, x, c->stream));
+    c->has_grid = true;
+    c->has_list = false;
+    c->stats.grid_columns = n_cols;
+    return NB_OK;
+}
+
+nb_status nb_pairlist_build(nb_ctx* c) {
+    if (!c) return NB_ERR_ARG;
+    if (!c->has_grid) return fail(c, NB_ERR_STATE, "nb_grid_build has not been called");
+    NB_HIP(c, hipSetDevice(c->device));
+    NbDev& d = c->d;
+    int32_t flags[kFlagCount];
+    nb_status st = to_host(c, flags, d.flags, kFlagCount);
+    if (st != NB_OK) return st;
+    if (flags[kFlagNonFinite]) {
+        c->has_grid = false;
+        return fail(c, NB_ERR_NONFINITE, "non-finite or out-of-range coordinates at grid build");
+    }
+    const int n_sc = flags[kFlagNumSc];
+    c->n_sc = n_sc;
+    c->n_cl = n_sc * kClustersPerSc;
+    c->n_slots = n_sc * kScAtoms;
+    const float r2o = radius_sq(c->p.rlist), r2i = radius_sq(c->p.rinner);
+    const double rbb = (double)c->p.rlist * (1.0 + 1e-5) + 1e-6;
+    const float r2bb = (float)(rbb * rbb);
+    // Search with the current per-super-cluster capacity; grow and repeat on overflow.
+    for (int attempt = 0;; ++attempt) {
+        const size_t need = (size_t)std::max(n_sc, 1) * c->cap;
+        if (need > c->a_scratch) {
+            NB_HIP(c, dev_alloc(d.scratch, need));
+            c->a_scratch = need;
+        }
+        NB_HIP(c, launch_fill(d.flags + kFlagScOverflow, kFlagCount - kFlagScOverflow, 0,
+                              c->stream));
+        // keep the super-cluster count (it lives in the same array)
+        NB_HIP(c, launch_fill(d.flags + kFlagNumSc, 1, n_sc, c->stream));
+        NB_HIP(c, launch_search(d, n_sc, c->cap, r2o, r2i, r2bb, c->p.rlist, c->stream));
+        st = to_host(c, flags, d.flags, kFlagCount);
+        if (st != NB_OK) return st;
+        if (!flags[kFlagScOverflow]) break;
+        if (c->p.list_capacity_hint > 0)
+            return fail(c, NB_ERR_CAPACITY, "a super-cluster has " +
+                                                std::to_string(flags[kFlagScNeeded]) +
+                                                " entries, above list_capacity_hint");
+        c->cap = flags[kFlagScNeeded] + flags[kFlagScNeeded] / 8 + 16;
+        c->stats.regrows++;
+        if (attempt > 4) return fail(c, NB_ERR_CAPACITY, "list capacity did not converge");
+    }
+    c->stats.bb_pairs = (uint32_t)flags[kFlagBbPairs];
+    NB_HIP(c, launch_scan_entries(d, n_sc, c->stream));
+    int32_t totals[8];
+    st = to_host(c, totals, d.totals, 8);
+    if (st != NB_OK) return st;
+    const int64_t E = totals[0];
+    // Work items of at most W entries: enough items to fill the device, long lists split
+    // (Sec. V.F), W between 8 and 64.
+    const int64_t target_items = 8192;
+    int W = (int)std::min<int64_t>(64, std::max<int64_t>(8, (E + target_items - 1) / target_items));
+    c->item_w = W;
+    const size_t item_cap = (size_t)n_sc + (size_t)(E / W) + 1;
+    if ((size_t)E > c->a_entries || !d.entries) {
+        const size_t ne = (size_t)E + E / 8 + 64;
+        NB_HIP(c, dev_alloc(d.entries, ne));
+        NB_HIP(c, dev_alloc(d.entry_sc, ne));
+        NB_HIP(c, dev_alloc(d.excl_rows, ne * kClustersPerSc));
+        NB_HIP(c, dev_alloc(d.jseg_entries, ne));
+        NB_HIP(c, dev_alloc(d.jpart, ne * kClusterSize));
+        c->a_entries = ne;
+    }
+    if (item_cap > c->a_items || !d.items) {
+        const size_t ni = item_cap + item_cap / 8 + 64;
+        NB_HIP(c, dev_alloc(d.items, ni));
+        NB_HIP(c, dev_alloc(d.ipart, ni * kScAtoms));
+        NB_HIP(c, dev_alloc(d.epart, ni * kEpartStride));
+        NB_HIP(c, dev_alloc(d.glj_part, ni * (size_t)c->p.n_types * c->p.n_types * 2));
+        c->a_items = ni;
+    }
+    NB_HIP(c, launch_make_items(d, n_sc, c->cap, W, c->p.nstprune, c->stream));
+    NB_HIP(c, launch_fill(d.totals + 2, 2, 0, c->stream));
+    NB_HIP(c, launch_fill(d.flags + kFlagNumRows, 1, 0, c->stream));
+    NB_HIP(c, launch_list_finish(d, n_sc, E, c->n_cl, c->stream));
+    st = to_host(c, totals, d.totals, 8);
+    if (st != NB_OK) return st;
+    c->n_entries = E;
+    c->n_items = totals[1];
+    c->part_start.resize(c->p.nstprune + 1);
+    st = to_host(c, c->part_start.data(), d.part_start, c->p.nstprune + 1);
+    if (st != NB_OK) return st;
+    st = to_host(c, flags, d.flags, kFlagCount);
+    if (st != NB_OK) return st;
+    c->stats.n_slots = c->n_slots;
+    c->stats.n_superclusters = n_sc;
+    c->stats.n_clusters = c->n_cl;
+    c->stats.n_entries = E;
+    c->stats.n_work_items = c->n_items;
+    c->stats.outer_pairs = totals[2];
+    c->stats.inner_pairs = totals[3];
+    c->stats.n_excl_rows = flags[kFlagNumRows];
+    c->stats.capacity_per_sc = c->cap;
+    c->has_list = true;
+    return NB_OK;
+}
+
+nb_status nb_prune_rolling(nb_ctx* c, const float* x, int64_t steps_since_build) {
+    if (!c) return NB_ERR_ARG;
+    if (!c->has_list) return fail(c, NB_ERR_STATE, "no pair list");
+    if (steps_since_build < 0) return fail(c, NB_ERR_ARG, "negative step");
+    if (steps_since_build >= c->p.nstlist)
+        return fail(c, NB_ERR_STATE, "the outer list has expired (steps_since_build >= nstlist)");
+    if (steps_since_build == 0) return NB_OK;
+    if (!x && c->d.n_atoms > 0) return fail(c, NB_ERR_ARG, "null coordinates");
+    NB_HIP(c, hipSetDevice(c->device));
+    const int part = (int)(steps_since_build % c->p.nstprune);
+    const int i0 = c->part_start[part], i1 = c->part_start[part + 1];
+    TimedSection ts(c, NB_T_PRUNE);
+    NB_HIP(c, launch_gather(c->d, x, nullptr, c->d.xp, c->n_slots, c->stream));
+    NB_HIP(c, launch_prune(c->d, i0, i1 - i0, radius_sq(c->p.rinner), c->stream));
+    return NB_OK;
+}
+
+nb_status nb_forces(nb_ctx* c, const float* x, const float* q, const float* lj, float* f,
+                    double* energy, double* virial, uint32_t flags) {
+    if (!c) return NB_ERR_ARG;
+    if (!c->has_list) return fail(c, NB_ERR_STATE, "no pair list");
+    if (flags & ~(uint32_t)(NB_F_ENERGY | NB_F_VIRIAL | NB_F_ACCUMULATE))
+        return fail(c, NB_ERR_ARG, "unknown flag");
+    if (c->d.n_atoms > 0 && (!x || !q || !lj || !f)) return fail(c, NB_ERR_ARG, "null array");
+    if ((flags & NB_F_ENERGY) && !energy) return fail(c, NB_ERR_ARG, "energy output missing");
+    if ((flags & NB_F_VIRIAL) && !virial) return fail(c, NB_ERR_ARG, "virial output missing");
+    NB_HIP(c, hipSetDevice(c->device));
+    NbDev& d = c->d;
+    const NbKParams kp = kernel_params(c->p);
+    {
+        TimedSection ts(c, NB_T_FORCE_REDUCE);
+        NB_HIP(c, launch_gather(d, x, q, d.xq, c->n_slots, c->stream));
+        NB_HIP(c, launch_fill_d(d.dstat, 4, 0.0, c->stream));
+    }
+    {
+        TimedSection ts(c, NB_T_FORCES);
+        NB_HIP(c, launch_forces(d, kp, c->p.coulomb, flags, lj, c->n_items, c->stream));
+    }
+    TimedSection ts(c, NB_T_FORCE_REDUCE);
+    NB_HIP(c, launch_reduce_forces(d, f, (flags & NB_F_ACCUMULATE) != 0, c->n_slots, c->stream));
+    if (flags & (NB_F_ENERGY | NB_F_VIRIAL))
+        NB_HIP(c, launch_reduce_energies(d, energy, virial, flags, c->n_sys, c->stream));
+    return NB_OK;
+}
+
+nb_status nb_forces_backward(nb_ctx* c, const float* x, const float* q, const float* lj,
+                             const float* grad_f, const double* grad_energy, float* grad_x,
+                             float* grad_q, double* grad_lj, uint32_t flags) {
+    if (!c) return NB_ERR_ARG;
+    if (!c->has_list) return fail(c, NB_ERR_STATE, "no pair list");
+    if (flags & ~(uint32_t)NB_F_ACCUMULATE) return fail(c, NB_ERR_ARG, "unknown flag");
+    if (c->d.n_atoms > 0 && (!x || !q || !lj || !grad_f))
+        return fail(c, NB_ERR_ARG, "null array");
+    NB_HIP(c, hipSetDevice(c->device));
+    NbDev& d = c->d;
+    const NbKParams kp = kernel_params(c->p);
+    const bool acc = (flags & NB_F_ACCUMULATE) != 0;
+    {
+        TimedSection ts(c, NB_T_BACKWARD_REDUCE);
+        NB_HIP(c, launch_gather(d, x, q, d.xq, c->n_slots, c->stream));
+    }
+    {
+        TimedSection ts(c, NB_T_BACKWARD);
+        NB_HIP(c, launch_backward(d, kp, c->p.coulomb, lj, grad_f, grad_energy, grad_lj != nullptr,
+                                  c->n_slots, c->n_items, c->stream));
+    }
+    TimedSection ts(c, NB_T_BACKWARD_REDUCE);
+    NB_HIP(c, launch_reduce_backward(d, grad_x, grad_q, grad_lj, acc, c->n_slots, c->p.n_types,
+                                     c->n_items, c->stream));
+    return NB_OK;
+}
+
+nb_status nb_get_grid(nb_ctx* c, int32_t* slot_atom, int64_t cap, int64_t* n_slots) {
+    if (!c || !n_slots) return NB_ERR_ARG;
+    if (!c->has_grid) return fail(c, NB_ERR_STATE, "no grid");
+    NB_HIP(c, hipSetDevice(c->device));
+    int32_t ns = 0;
+    nb_status st = to_host(c, &ns, c->d.flags + kFlagNumSc, 1);
+    if (st != NB_OK) return st;
+    *n_slots = (int64_t)ns * kScAtoms;
+    if (!slot_atom || cap < *n_slots) return NB_OK;
+    return to_host(c, slot_atom, c->d.slot_atom, (size_t)*n_slots);
+}
+
+nb_status nb_get_grid_dims(nb_ctx* c, int32_t* dims) {
+    if (!c || !dims) return NB_ERR_ARG;
+    if (!c->has_grid) return fail(c, NB_ERR_STATE, "no grid");
+    for (int s = 0; s < c->n_sys; ++s) {
+        dims[2 * s] = c->hsys[s].nx;
+        dims[2 * s + 1] = c->hsys[s].ny;
+    }
+    return NB_OK;
+}
+
+nb_status nb_get_pairs(nb_ctx* c, int32_t which, int32_t* triples, int64_t cap, int64_t* count) {
+    if (!c || !count || (which != 1 && which != 2)) return NB_ERR_ARG;
+    if (!c->has_list) return fail(c, NB_ERR_STATE, "no pair list");
+    NB_HIP(c, hipSetDevice(c->device));
+    const size_t E = (size_t)c->n_entries;
+    std::vector<NbEntry> ent(E);
+    std::vector<int32_t> esc(E);
+    nb_status st = to_host(c, ent.data(), c->d.entries, E);
+    if (st != NB_OK) return st;
+    st = to_host(c, esc.data(), c->d.entry_sc, E);
+    if (st != NB_OK) return st;
+    const int sh = which == 1 ? 8 : 16;
+    int64_t n = 0;
+    for (size_t e = 0; e < E; ++e) n += __builtin_popcount((ent[e].meta >> sh) & 0xffu);
+    *count = n;
+    if (!triples || cap < n) return NB_OK;
+    int64_t k = 0;
+    for (size_t e = 0; e < E; ++e) {
+        const uint32_t m = (ent[e].meta >> sh) & 0xffu;
+        for (int b = 0; b < 8; ++b)
+            if ((m >> b) & 1u) {
+                triples[3 * k] = esc[e] * kClustersPerSc + b;
+                triples[3 * k + 1] = ent[e].cj;
+                triples[3 * k + 2] = (int32_t)(ent[e].meta & 31u);
+                ++k;
+            }
+    }
+    return NB_OK;
+}
+
+nb_status nb_set_timing(nb_ctx* c, int32_t enable) {
+    if (!c) return NB_ERR_ARG;
+    if (c->d.flags) {
+        nb_status st = collect_timing(c);
+        if (st != NB_OK) return st;
+    }
+    for (int k = 0; k < NB_T_COUNT; ++k) {
+        c->t_ms[k] = 0;
+        c->t_calls[k] = 0;
+    }
+    c->timing = enable != 0;
+    return NB_OK;
+}
+
+nb_status nb_get_timing(nb_ctx* c, double* ms, int64_t* calls) {
+    if (!c || !ms || !calls) return NB_ERR_ARG;
+    if (c->d.flags) {
+        NB_HIP(c, hipSetDevice(c->device));
+        nb_status st = collect_timing(c);
+        if (st != NB_OK) return st;
+    }
+    for (int k = 0; k < NB_T_COUNT; ++k) {
+        ms[k] = c->t_ms[k];
+        calls[k] = c->t_calls[k];
+        c->t_ms[k] = 0;
+        c->t_calls[k] = 0;
+    }
+    return NB_OK;
+}
+
+nb_status nb_get_stats(nb_ctx* c, nb_stats* out) {
+    if (!c || !out) return NB_ERR_ARG;
+    if (c->has_list) {
+        NB_HIP(c, hipSetDevice(c->device));
+        double ds[4];
+        nb_status st = to_host(c, ds, c->d.dstat, 4);
+        if (st != NB_OK) return st;
+        c->stats.effective_pairs = (int64_t)ds[0];
+        c->stats.computed_pairs = (int64_t)ds[1];
+        // inner masks change with every rolling prune: recount them
+        std::vector<NbEntry> ent((size_t)c->n_entries);
+        st = to_host(c, ent.data(), c->d.entries, ent.size());
+        if (st != NB_OK) return st;
+        int64_t inner = 0;
+        for (const NbEntry& e : ent) inner += __builtin_popcount((e.meta >> 16) & 0xffu);
+        c->stats.inner_pairs = inner;
+    }
+    *out = c->stats;
+    return NB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,175 @@
+// Internal declarations shared by the host layer and the HIP kernels of the
+// cluster-pair nonbonded library.  Not part of the public ABI (see include/nb.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "nb.h"
+
+// ---- fixed geometry of the cluster setup (Sec. V.A: 8x8 on 64-wide AMD GPUs, 8-way
+// super-clustering from a 2x2x2 grouping) ------------------------------------------------
+constexpr int kClusterSize = 8;                 // atoms per cluster (i and j side)
+constexpr int kClustersPerSc = 8;               // clusters per super-cluster
+constexpr int kScAtoms = 64;                    // atom slots per super-cluster
+constexpr int kWave = 64;                       // wavefront width on gfx950
+constexpr int kMaxTypes = 32;                   // LJ types supported by the kernels
+constexpr int kMaxExcl = 32;                    // exclusion partners per atom
+constexpr int kShiftZero = 13;                  // shift code of s = (0,0,0)
+
+// One j-entry of a super-cluster's joint list (16 bytes, loaded with one scalar load).
+//   meta bits  0..4   shift code (sx+1)*9 + (sy+1)*3 + (sz+1), image x_j + s L
+//              8..15  outer interaction mask (bit c: i-cluster c of the super-cluster)
+//             16..23  inner interaction mask (rolling-pruned copy of the outer mask)
+//             24..27  atoms in the j-cluster (1..8)
+//   excl      exclusion row (8 x 64-bit masks, one per i-cluster), -1 = no exclusions
+//   jpos      slot of this entry's j-force partials in the transposed partial buffer
+struct __attribute__((aligned(16))) NbEntry {
+    int32_t cj;
+    uint32_t meta;
+    int32_t excl;
+    int32_t jpos;
+};
+
+// One work item: a chunk of one super-cluster's j-list, processed by one wavefront.
+struct __attribute__((aligned(16))) NbItem {
+    int32_t sc;
+    int32_t e0;
+    int32_t ne;
+    int32_t sys;
+};
+
+// Per-system grid geometry (device copy).
+struct NbSys {
+    float L[3];          // box edges
+    float invL[3];       // float32(1 / L)
+    float cinv[2];       // float32(nx / Lx), float32(ny / Ly)
+    float colw[2];       // column widths Lx / nx, Ly / ny (search ranges only)
+    int32_t nx, ny;      // columns per axis
+    int32_t col_base;    // first global column id
+    int32_t atom0, atom1;
+    int32_t pad;
+};
+
+// Per-super-cluster info written by the grid build.
+struct NbScInfo {
+    int32_t col;         // global column id
+    int32_t sys;         // system index
+    int32_t cx, cy;      // column coordinates inside the system's grid
+};
+
+// Scalar pair-interaction constants passed by value to the kernels.
+struct NbKParams {
+    float rc2;           // cut-off squared (single precision)
+    float krf, crf;      // reaction-field constants
+    float beta;          // Ewald splitting parameter
+    float beta2_log2e;   // -beta^2 / ln 2 (exp(-beta^2 r^2) = exp2(r^2 * this))
+    float two_beta_sqrtpi;  // 2 beta / sqrt(pi)
+    float ewald_shift;   // erfc(beta rc)/rc under the potential-shift modifier, else 0
+    float epsfac_r;      // epsfac / eps_r
+    float rc_m6, rc_m12; // rc^-6, rc^-12 under the potential-shift modifier, else 0
+    int32_t n_types;
+};
+
+// Device flags written by kernels and read at the next synchronising call.
+enum NbFlag {
+    kFlagNonFinite = 0,   // a coordinate was not finite
+    kFlagScOverflow = 1,  // a super-cluster had more entries than the per-sc capacity
+    kFlagScNeeded = 2,    // largest per-sc entry count seen
+    kFlagNumSc = 3,       // number of super-clusters of the current grid
+    kFlagNumRows = 4,     // exclusion rows allocated
+    kFlagBbPairs = 5,     // cluster pairs passing the bounding-box test (low 32 bits)
+    kFlagCount = 8
+};
+
+// ---- kernel launchers (nb_grid.hip, nb_list.hip, nb_forces.hip, nb_backward.hip) -------
+struct NbDev;   // device buffer set, defined below
+
+hipError_t launch_grid_build(const NbDev& d, const float* x, hipStream_t s);
+hipError_t launch_search(const NbDev& d, int n_sc, int cap, float r2_outer, float r2_inner,
+                         float r2_bb, float rlist, hipStream_t s);
+hipError_t launch_scan_entries(const NbDev& d, int n_sc, hipStream_t s);
+hipError_t launch_make_items(const NbDev& d, int n_sc, int cap, int w, int nstprune,
+                             hipStream_t s);
+hipError_t launch_list_finish(const NbDev& d, int n_sc, int64_t n_entries, int n_cl,
+                              hipStream_t s);
+hipError_t launch_fill(int32_t* p, int n, int32_t v, hipStream_t s);
+hipError_t launch_fill_d(double* p, int n, double v, hipStream_t s);
+hipError_t launch_gather(const NbDev& d, const float* x, const float* q, float4* out,
+                         int n_slots, hipStream_t s);
+hipError_t launch_prune(const NbDev& d, int item0, int n_items, float r2_inner,
+                        hipStream_t s);
+hipError_t launch_forces(const NbDev& d, const NbKParams& kp, int coulomb, uint32_t flags,
+                         const float* lj, int n_items, hipStream_t s);
+hipError_t launch_reduce_forces(const NbDev& d, float* f, bool accumulate, int n_slots,
+                                hipStream_t s);
+hipError_t launch_reduce_energies(const NbDev& d, double* energy, double* virial,
+                                  uint32_t flags, int n_sys, hipStream_t s);
+hipError_t launch_backward(const NbDev& d, const NbKParams& kp, int coulomb, const float* lj,
+                           const float* grad_f, const double* grad_energy, bool ljgrad,
+                           int n_slots, int n_items, hipStream_t s);
+hipError_t launch_reduce_backward(const NbDev& d, float* grad_x, float* grad_q,
+                                  double* grad_lj, bool accumulate, int n_slots,
+                                  int n_types, int n_items, hipStream_t s);
+
+// All device arrays of a context (plain pointers; sizes in the comments).
+struct NbDev {
+    int32_t n_atoms = 0, n_sys = 0, n_cols = 0, n_types = 0, max_excl = 0;
+    int32_t n_sc_max = 0;              // upper bound of super-clusters for the grid
+    // topology
+    int32_t* type = nullptr;           // [N]
+    int32_t* atom_sys = nullptr;       // [N]
+    int32_t* excl_ptr = nullptr;       // [N+1]
+    int32_t* excl_idx = nullptr;       // [nnz]
+    NbSys* sys = nullptr;              // [n_sys]
+    int32_t* sys_sc_start = nullptr;   // [n_sys+1] super-cluster range per system
+    // grid
+    int4* img = nullptr;               // [N] (kx, ky, kz, column)
+    float4* wpos = nullptr;            // [N] wrapped build coordinates
+    int32_t* col_count = nullptr;      // [n_cols]
+    int32_t* col_start = nullptr;      // [n_cols+1]
+    int32_t* col_sc_start = nullptr;   // [n_cols+1]
+    int32_t* col_cursor = nullptr;     // [n_cols]
+    int32_t* col_atoms = nullptr;      // [N] bucketed by column
+    int32_t* col_sorted = nullptr;     // [N] sorted by (column, z, index)
+    NbScInfo* sc_info = nullptr;       // [n_sc_max]
+    int32_t* slot_atom = nullptr;      // [64 n_sc_max]
+    int32_t* atom_slot = nullptr;      // [N]
+    int32_t* type_slot = nullptr;      // [64 n_sc_max]
+    int32_t* excl_slot = nullptr;      // [64 n_sc_max][max_excl]
+    float4* cl_bb = nullptr;           // [8 n_sc_max][2] lo (w = atom count), hi
+    float4* sc_bb = nullptr;           // [n_sc_max][2]
+    float4* xw = nullptr;              // [64 n_sc_max] build coordinates by slot
+    // per-call gathered data
+    float4* xq = nullptr;              // [64 n_sc_max] (x, y, z, q) by slot
+    float4* xp = nullptr;              // [64 n_sc_max] prune coordinates by slot
+    float4* gslot = nullptr;           // [64 n_sc_max] adjoint dL/dF by slot
+    // lists
+    int32_t* sc_ecount = nullptr;      // [n_sc_max]
+    int32_t* sc_estart = nullptr;      // [n_sc_max+1]
+    int32_t* sc_istart = nullptr;      // [n_sc_max+1] items of a super-cluster (contiguous)
+    int32_t* sc_icount = nullptr;      // [n_sc_max]
+    NbEntry* scratch = nullptr;        // [n_sc_max * cap]
+    NbEntry* entries = nullptr;        // [entry_cap]
+    int32_t* entry_sc = nullptr;       // [entry_cap]
+    NbItem* items = nullptr;           // [item_cap]
+    int32_t* part_start = nullptr;     // [nstprune+1] item ranges per rolling part
+    uint64_t* excl_rows = nullptr;     // [entry_cap][8]
+    int32_t* jseg_count = nullptr;     // [8 n_sc_max]
+    int32_t* jseg_start = nullptr;     // [8 n_sc_max + 1]
+    int32_t* jseg_fill = nullptr;      // [8 n_sc_max]
+    int32_t* jseg_entries = nullptr;   // [entry_cap]
+    int32_t* totals = nullptr;         // [8]: entries, items, ...
+    int32_t* flags = nullptr;          // [kFlagCount]
+    // force partials
+    float4* jpart = nullptr;           // [entry_cap * 8]
+    float4* ipart = nullptr;           // [item_cap * 64]
+    double* epart = nullptr;           // [item_cap * kEpartStride]
+    float* glj_part = nullptr;         // [item_cap * T * T * 2]
+    double* dstat = nullptr;           // [4]: effective pair count of the last force call
+};
+
+constexpr int kEpartStride = 10;       // E_LJ, E_C, virial xx yy zz xy xz yz, pairs, pad

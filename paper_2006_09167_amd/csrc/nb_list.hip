@@ -1,0 +1,401 @@
+// Pair-list build and pruning (Sec. V.A, V.D, V.E).
+//
+// * k_search: one wavefront per i-super-cluster walks the neighbouring grid columns
+//   (with periodic shifts), tests super-cluster then cluster bounding boxes against
+//   rlist, and prunes each candidate (j-cluster, i-cluster) pair on atom distances with
+//   a 64-lane ballot ("warp collectives"); the outer mask keeps pairs with an atom pair
+//   closer than rlist, the inner mask those closer than rinner.
+// * k_compact / items: entries are copied to one array in super-cluster order and cut
+//   into work items of at most W entries (list splitting, Sec. V.F), grouped by
+//   rolling-prune part.
+// * exclusion rows: 64-bit masks per (entry, i-cluster) for force-field exclusions.
+// * j-partial slots: entries referencing the same j-cluster get consecutive slots of the
+//   partial-force buffer, ordered by entry index (deterministic force sums).
+// * k_prune: rolling prune of one part of the outer list against rinner (Sec. V.E).
+//
+// Atom distances for list decisions use a fixed single-precision sequence without fused
+// operations: per axis a = (s > 0) ? x_i - L : x_i, b = (s < 0) ? x_j - L : x_j,
+// d = a - b; r2 = (dx*dx + dy*dy) + dz*dz; inside iff r2 < R2.
+#include "nb_internal.h"
+
+namespace {
+
+constexpr int kScanThreads = 1024;
+
+__device__ inline int shift_x(int code) { return code / 9 - 1; }
+__device__ inline int shift_y(int code) { return (code / 3) % 3 - 1; }
+__device__ inline int shift_z(int code) { return code % 3 - 1; }
+
+__device__ inline int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
+
+// Squared distance of atom i and the image s of atom j in the specified sequence.
+__device__ inline float list_r2(float4 xi, float4 xj, int sx, int sy, int sz, const NbSys& S) {
+#pragma clang fp contract(off)
+    const float ax = (sx > 0) ? xi.x - S.L[0] : xi.x;
+    const float ay = (sy > 0) ? xi.y - S.L[1] : xi.y;
+    const float az = (sz > 0) ? xi.z - S.L[2] : xi.z;
+    const float bx = (sx < 0) ? xj.x - S.L[0] : xj.x;
+    const float by = (sy < 0) ? xj.y - S.L[1] : xj.y;
+    const float bz = (sz < 0) ? xj.z - S.L[2] : xj.z;
+    const float dx = ax - bx, dy = ay - by, dz = az - bz;
+    const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+    const float t = xx + yy;
+    return t + zz;
+}
+
+// Squared gap between two boxes, the j box shifted by s L (conservative: compared with a
+// slightly enlarged radius).
+__device__ inline float bb_d2(float4 ilo, float4 ihi, float4 jlo, float4 jhi, float ox, float oy,
+                              float oz) {
+    const float gx = fmaxf(0.f, fmaxf(jlo.x + ox - ihi.x, ilo.x - (jhi.x + ox)));
+    const float gy = fmaxf(0.f, fmaxf(jlo.y + oy - ihi.y, ilo.y - (jhi.y + oy)));
+    const float gz = fmaxf(0.f, fmaxf(jlo.z + oz - ihi.z, ilo.z - (jhi.z + oz)));
+    return gx * gx + gy * gy + gz * gz;
+}
+
+// Valid-lane mask of an 8x8 cluster pair (lane = ii + 8 jj): real i-atoms (ii < ni), real
+// j-atoms (jj < nj) and, for a cluster with itself at s = 0, only ii < jj.
+__device__ inline uint64_t pair_valid_mask(int ni, int nj, bool diag) {
+    const uint64_t ibyte = (ni >= 8) ? 0xffull : ((1ull << ni) - 1ull);
+    const uint64_t imask = ibyte * 0x0101010101010101ull;
+    const uint64_t jmask = (nj >= 8) ? ~0ull : ((1ull << (8 * nj)) - 1ull);
+    const uint64_t tri = 0x7f3f1f0f07030100ull;      // bit ii + 8 jj set iff ii < jj
+    return imask & jmask & (diag ? tri : ~0ull);
+}
+
+__global__ __launch_bounds__(kWave) void k_search(NbDev d, int cap, float r2_outer,
+                                                   float r2_inner, float r2_bb, float rlist) {
+    const int sc = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int ii = lane & 7, jj = lane >> 3;
+    __shared__ float4 s_ilo[kClustersPerSc], s_ihi[kClustersPerSc];
+    __shared__ float4 s_ix[kScAtoms];
+    const NbScInfo info = d.sc_info[sc];
+    const NbSys S = d.sys[info.sys];
+    if (lane < kClustersPerSc) {
+        s_ilo[lane] = d.cl_bb[2 * (kClustersPerSc * sc + lane)];
+        s_ihi[lane] = d.cl_bb[2 * (kClustersPerSc * sc + lane) + 1];
+    }
+    s_ix[lane] = d.xw[kScAtoms * sc + lane];
+    __syncthreads();
+    const float4 slo = d.sc_bb[2 * sc], shi = d.sc_bb[2 * sc + 1];
+    const float margin = 0.01f;   // in column widths; column ranges only need to be supersets
+    const int jx0 = (int)floorf((slo.x - rlist) / S.colw[0] - margin);
+    const int jx1 = (int)floorf((shi.x + rlist) / S.colw[0] + margin);
+    const int jy0 = (int)floorf((slo.y - rlist) / S.colw[1] - margin);
+    const int jy1 = (int)floorf((shi.y + rlist) / S.colw[1] + margin);
+    const int ci0 = kClustersPerSc * sc;
+    int n_out = 0;
+    int bb_pairs = 0;
+    for (int jx = jx0; jx <= jx1; ++jx) {
+        const int sx = floordiv(jx, S.nx);
+        if (sx < -1 || sx > 1) continue;
+        const int colx = jx - sx * S.nx;
+        for (int jy = jy0; jy <= jy1; ++jy) {
+            const int sy = floordiv(jy, S.ny);
+            if (sy < -1 || sy > 1) continue;
+            const int coly = jy - sy * S.ny;
+            const int jcol = S.col_base + colx * S.ny + coly;
+            const int J0 = max(d.col_sc_start[jcol], sc);
+            const int J1 = d.col_sc_start[jcol + 1];
+            const int n_cand = (J1 > J0) ? (J1 - J0) * 3 : 0;
+            for (int base = 0; base < n_cand; base += kWave) {
+                const int k = base + lane;
+                bool pass = false;
+                if (k < n_cand) {
+                    const int J = J0 + k / 3;
+                    const int sz = k % 3 - 1;
+                    const float4 jlo = d.sc_bb[2 * J], jhi = d.sc_bb[2 * J + 1];
+                    pass = bb_d2(slo, shi, jlo, jhi, sx * S.L[0], sy * S.L[1], sz * S.L[2]) < r2_bb;
+                }
+                uint64_t cand = __builtin_amdgcn_ballot_w64(pass);
+                while (cand) {
+                    const int t = __builtin_ctzll(cand);
+                    cand &= cand - 1;
+                    const int J = J0 + (base + t) / 3;
+                    const int sz = (base + t) % 3 - 1;
+                    const int code = (sx + 1) * 9 + (sy + 1) * 3 + (sz + 1);
+                    const float ox = sx * S.L[0], oy = sy * S.L[1], oz = sz * S.L[2];
+                    // 64 cluster-pair box tests: lane -> (j-cluster jj, i-cluster ii)
+                    const int cjl = kClustersPerSc * J + jj;
+                    const int cil = ci0 + ii;
+                    const float4 jlo = d.cl_bb[2 * cjl], jhi = d.cl_bb[2 * cjl + 1];
+                    const bool canon = (cjl > cil) || (cjl == cil && code >= kShiftZero);
+                    const bool ok = canon && jlo.w > 0.f && s_ilo[ii].w > 0.f &&
+                                    bb_d2(s_ilo[ii], s_ihi[ii], jlo, jhi, ox, oy, oz) < r2_bb;
+                    const uint64_t M = __builtin_amdgcn_ballot_w64(ok);
+                    for (int jc = 0; jc < kClustersPerSc; ++jc) {
+                        const uint32_t bbmask = (uint32_t)(M >> (8 * jc)) & 0xffu;
+                        if (!bbmask) continue;
+                        bb_pairs += __builtin_popcount(bbmask);
+                        const int cj = kClustersPerSc * J + jc;
+                        const int nj = (int)d.cl_bb[2 * cj].w;
+                        const float4 xj = d.xw[kClusterSize * cj + jj];
+                        uint32_t omask = 0, imask = 0;
+                        for (uint32_t bits = bbmask; bits; bits &= bits - 1) {
+                            const int c = __builtin_ctz(bits);
+                            const float4 xi = s_ix[kClusterSize * c + ii];
+                            const float r2 = list_r2(xi, xj, sx, sy, sz, S);
+                            const int ni = (int)s_ilo[c].w;
+                            const uint64_t valid =
+                                pair_valid_mask(ni, nj, cj == ci0 + c && code == kShiftZero);
+                            const uint64_t in_o = __builtin_amdgcn_ballot_w64(r2 < r2_outer) & valid;
+                            const uint64_t in_i = __builtin_amdgcn_ballot_w64(r2 < r2_inner) & valid;
+                            omask |= (in_o ? 1u : 0u) << c;
+                            imask |= (in_i ? 1u : 0u) << c;
+                        }
+                        if (omask) {
+                            if (n_out < cap && lane == 0) {
+                                NbEntry e;
+                                e.cj = cj;
+                                e.meta = (uint32_t)code | (omask << 8) | (imask << 16) |
+                                         ((uint32_t)nj << 24);
+                                e.excl = -1;
+                                e.jpos = -1;
+                                d.scratch[(size_t)sc * cap + n_out] = e;
+                            }
+                            ++n_out;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (lane == 0) {
+        d.sc_ecount[sc] = min(n_out, cap);
+        if (n_out > cap) atomicOr(&d.flags[kFlagScOverflow], 1);
+        atomicMax(&d.flags[kFlagScNeeded], n_out);
+        atomicAdd(&d.flags[kFlagBbPairs], bb_pairs);
+    }
+}
+
+// Exclusive scan of a per-super-cluster count (single block).
+template <typename F>
+__device__ int block_scan(int n, F f, int32_t* __restrict__ out) {
+    __shared__ int s_part[kScanThreads];
+    const int t = threadIdx.x;
+    const int seg = (n + kScanThreads - 1) / kScanThreads;
+    const int b = min(n, t * seg), e = min(n, b + seg);
+    int sum = 0;
+    for (int i = b; i < e; ++i) sum += f(i);
+    s_part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        const int v = (t >= off) ? s_part[t - off] : 0;
+        __syncthreads();
+        s_part[t] += v;
+        __syncthreads();
+    }
+    int run = s_part[t] - sum;
+    for (int i = b; i < e; ++i) {
+        out[i] = run;
+        run += f(i);
+    }
+    const int total = s_part[kScanThreads - 1];
+    __syncthreads();
+    if (t == 0) out[n] = total;
+    return total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_entries(NbDev d, int n_sc) {
+    const int total = block_scan(n_sc, [&](int i) { return d.sc_ecount[i]; }, d.sc_estart);
+    if (threadIdx.x == 0) d.totals[0] = total;
+}
+
+// Items per super-cluster: ceil(entries / w), scanned in rolling-part-major order so that
+// each part's items are contiguous (part of super-cluster sc is sc mod nstprune).
+__global__ __launch_bounds__(kScanThreads) void k_scan_items(NbDev d, int n_sc, int w,
+                                                             int nparts, int32_t* tmp) {
+    // permuted position k -> super-cluster: parts p hold sc = p, p + nparts, ...
+    auto sc_of = [&](int k) {
+        int p = 0, before = 0;
+        while (p < nparts) {
+            const int cnt = (n_sc > p) ? (n_sc - p + nparts - 1) / nparts : 0;
+            if (k < before + cnt) break;
+            before += cnt;
+            ++p;
+        }
+        return p + nparts * (k - before);
+    };
+    auto n_items = [&](int k) {
+        const int n = d.sc_ecount[sc_of(k)];
+        return (n + w - 1) / w;
+    };
+    const int total = block_scan(n_sc, n_items, tmp);
+    __syncthreads();
+    for (int k = threadIdx.x; k < n_sc; k += blockDim.x) {
+        const int sc = sc_of(k);
+        d.sc_istart[sc] = tmp[k];
+        d.sc_icount[sc] = n_items(k);
+    }
+    if (threadIdx.x == 0) {
+        int before = 0;
+        for (int p = 0; p < nparts; ++p) {
+            d.part_start[p] = (before < n_sc) ? tmp[before] : total;
+            const int cnt = (n_sc > p) ? (n_sc - p + nparts - 1) / nparts : 0;
+            before += cnt;
+        }
+        d.part_start[nparts] = total;
+        d.totals[1] = total;
+    }
+}
+
+__global__ __launch_bounds__(kWave) void k_compact(NbDev d, int cap, int w) {
+    const int sc = blockIdx.x;
+    const int n = d.sc_ecount[sc];
+    const int e0 = d.sc_estart[sc];
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        d.entries[e0 + k] = d.scratch[(size_t)sc * cap + k];
+        d.entry_sc[e0 + k] = sc;
+    }
+    const int i0 = d.sc_istart[sc], ni = d.sc_icount[sc];
+    const int sys = d.sc_info[sc].sys;
+    for (int k = threadIdx.x; k < ni; k += blockDim.x) {
+        NbItem it;
+        it.sc = sc;
+        it.e0 = e0 + k * w;
+        it.ne = min(w, n - k * w);
+        it.sys = sys;
+        d.items[i0 + k] = it;
+    }
+}
+
+// One thread per entry: exclusion masks (bit ii + 8 jj cleared for excluded atom pairs),
+// a row only for entries with an exclusion; j-segment counts; list statistics.
+__global__ void k_entry_finish(NbDev d, int n_entries) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_entries) return;
+    const NbEntry ent = d.entries[e];
+    const int sc = d.entry_sc[e];
+    const uint32_t omask = (ent.meta >> 8) & 0xffu;
+    uint64_t m[kClustersPerSc];
+    bool any = false;
+    for (int c = 0; c < kClustersPerSc; ++c) {
+        m[c] = ~0ull;
+        if (!((omask >> c) & 1u)) continue;
+        const int ci = kClustersPerSc * sc + c;
+        for (int ii = 0; ii < kClusterSize; ++ii) {
+            const int slot = kClusterSize * ci + ii;
+            for (int k = 0; k < d.max_excl; ++k) {
+                const int ps = d.excl_slot[(size_t)slot * d.max_excl + k];
+                if (ps >= 0 && ps / kClusterSize == ent.cj)
+                    m[c] &= ~(1ull << (ii + 8 * (ps % kClusterSize)));
+            }
+        }
+        any |= (m[c] != ~0ull);
+    }
+    if (any) {
+        const int row = atomicAdd(&d.flags[kFlagNumRows], 1);
+        for (int c = 0; c < kClustersPerSc; ++c) d.excl_rows[(size_t)row * kClustersPerSc + c] = m[c];
+        d.entries[e].excl = row;
+    }
+    atomicAdd(&d.jseg_count[ent.cj], 1);
+    atomicAdd(&d.totals[2], __builtin_popcount(omask));
+    atomicAdd(&d.totals[3], __builtin_popcount((ent.meta >> 16) & 0xffu));
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_jseg(NbDev d, int n_cl) {
+    block_scan(n_cl, [&](int i) { return d.jseg_count[i]; }, d.jseg_start);
+    for (int i = threadIdx.x; i < n_cl; i += blockDim.x) d.jseg_fill[i] = 0;
+}
+
+__global__ void k_jseg_fill(NbDev d, int n_entries) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_entries) return;
+    const int cj = d.entries[e].cj;
+    const int pos = atomicAdd(&d.jseg_fill[cj], 1);
+    d.jseg_entries[d.jseg_start[cj] + pos] = e;
+}
+
+// One wavefront per j-cluster: slot of each referencing entry = rank by entry index.
+__global__ __launch_bounds__(kWave) void k_jseg_rank(NbDev d) {
+    const int cj = blockIdx.x;
+    const int s0 = d.jseg_start[cj], s1 = d.jseg_start[cj + 1];
+    for (int i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
+        const int e = d.jseg_entries[i];
+        int r = 0;
+        for (int j = s0; j < s1; ++j) r += (d.jseg_entries[j] < e) ? 1 : 0;
+        d.entries[e].jpos = s0 + r;
+    }
+}
+
+// Rolling prune (Sec. V.E): one wavefront per work item of the part; re-derive the inner
+// mask of every entry from its outer mask and the current coordinates.
+__global__ __launch_bounds__(kWave) void k_prune(NbDev d, int item0, float r2_inner) {
+    const NbItem it = d.items[item0 + blockIdx.x];
+    const int lane = threadIdx.x;
+    const int ii = lane & 7, jj = lane >> 3;
+    __shared__ float4 s_ix[kScAtoms];
+    __shared__ int s_ni[kClustersPerSc];
+    s_ix[lane] = d.xp[kScAtoms * it.sc + lane];
+    if (lane < kClustersPerSc) s_ni[lane] = (int)d.cl_bb[2 * (kClustersPerSc * it.sc + lane)].w;
+    __syncthreads();
+    const NbSys S = d.sys[it.sys];
+    const int ci0 = kClustersPerSc * it.sc;
+    for (int e = it.e0; e < it.e0 + it.ne; ++e) {
+        const NbEntry ent = d.entries[e];
+        const int code = ent.meta & 31u;
+        const int sx = shift_x(code), sy = shift_y(code), sz = shift_z(code);
+        const int nj = (int)(ent.meta >> 24);
+        const uint32_t omask = (ent.meta >> 8) & 0xffu;
+        const float4 xj = d.xp[kClusterSize * ent.cj + jj];
+        uint32_t imask = 0;
+        for (uint32_t bits = omask; bits; bits &= bits - 1) {
+            const int c = __builtin_ctz(bits);
+            const float r2 = list_r2(s_ix[kClusterSize * c + ii], xj, sx, sy, sz, S);
+            const uint64_t valid =
+                pair_valid_mask(s_ni[c], nj, ent.cj == ci0 + c && code == kShiftZero);
+            const uint64_t in_i = __builtin_amdgcn_ballot_w64(r2 < r2_inner) & valid;
+            imask |= (in_i ? 1u : 0u) << c;
+        }
+        if (lane == 0) d.entries[e].meta = (ent.meta & ~(0xffu << 16)) | (imask << 16);
+    }
+}
+
+inline int blocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_search(const NbDev& d, int n_sc, int cap, float r2_outer, float r2_inner,
+                         float r2_bb, float rlist, hipStream_t s) {
+    if (n_sc > 0)
+        hipLaunchKernelGGL(k_search, dim3(n_sc), dim3(kWave), 0, s, d, cap, r2_outer, r2_inner,
+                           r2_bb, rlist);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_entries(const NbDev& d, int n_sc, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_entries, dim3(1), dim3(kScanThreads), 0, s, d, n_sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_make_items(const NbDev& d, int n_sc, int cap, int w, int nstprune,
+                             hipStream_t s) {
+    // jseg_fill doubles as the scratch of the permuted scan (n_sc + 1 <= 8 n_sc_max).
+    hipLaunchKernelGGL(k_scan_items, dim3(1), dim3(kScanThreads), 0, s, d, n_sc, w, nstprune,
+                       d.jseg_fill);
+    if (n_sc > 0) hipLaunchKernelGGL(k_compact, dim3(n_sc), dim3(kWave), 0, s, d, cap, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_finish(const NbDev& d, int n_sc, int64_t n_entries, int n_cl,
+                              hipStream_t s) {
+    hipError_t err = launch_fill(d.jseg_count, n_cl, 0, s);
+    if (err != hipSuccess) return err;
+    if (n_entries > 0)
+        hipLaunchKernelGGL(k_entry_finish, dim3(blocks(n_entries, 256)), dim3(256), 0, s, d,
+                           (int)n_entries);
+    hipLaunchKernelGGL(k_scan_jseg, dim3(1), dim3(kScanThreads), 0, s, d, n_cl);
+    if (n_entries > 0)
+        hipLaunchKernelGGL(k_jseg_fill, dim3(blocks(n_entries, 256)), dim3(256), 0, s, d,
+                           (int)n_entries);
+    if (n_cl > 0) hipLaunchKernelGGL(k_jseg_rank, dim3(n_cl), dim3(kWave), 0, s, d);
+    (void)n_sc;
+    return hipGetLastError();
+}
+
+hipError_t launch_prune(const NbDev& d, int item0, int n_items, float r2_inner, hipStream_t s) {
+    if (n_items > 0)
+        hipLaunchKernelGGL(k_prune, dim3(n_items), dim3(kWave), 0, s, d, item0, r2_inner);
+    return hipGetLastError();
+}

@@ -1,0 +1,98 @@
+"""Helpers shared by the GPU tests: build a library context for a system and compare
+its outputs with the oracle's."""
+import math
+
+import numpy as np
+import torch
+
+import oracle
+from paper_2006_09167_amd import systems
+
+
+def dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def concat(systems_list):
+    if isinstance(systems_list, systems.System):
+        s = systems_list
+        return dict(x=s.x, q=s.q, type=s.type, excl_ptr=s.excl_ptr, excl_idx=s.excl_idx,
+                    boxes=s.box[None], offsets=np.array([0, s.n], np.int64), lj=s.lj,
+                    parts=[s])
+    c = systems.concat_systems(systems_list)
+    c["lj"] = systems_list[0].lj
+    c["parts"] = systems_list
+    return c
+
+
+def make_ctx(c, coulomb="rf", rc=1.0, rinner=None, rlist=None, beta=0.0, nstlist=1,
+             nstprune=1, modifier="potshift", eps_rf=math.inf, capacity_hint=0):
+    from paper_2006_09167_amd.api import Context
+    T = c["lj"].shape[0]
+    ctx = Context(n_types=T, coulomb=coulomb, rc=rc, rinner=rinner, rlist=rlist, beta=beta,
+                  eps_rf=eps_rf, modifier=modifier, nstlist=nstlist, nstprune=nstprune,
+                  capacity_hint=capacity_hint, atom_offsets=c["offsets"])
+    ctx.set_topology(c["type"], c["excl_ptr"], c["excl_idx"])
+    return ctx
+
+
+def oracle_params(coulomb, rc, beta=0.0, modifier="potshift", eps_rf=math.inf):
+    return oracle.params(coulomb, rc=rc, beta=beta, modifier=modifier, eps_rf=eps_rf)
+
+
+def oracle_forces_multi(c, x, p):
+    """FP64 oracle energies [S,2], forces [N,3], virial [S,3,3] for concatenated systems."""
+    offs = c["offsets"]
+    S = offs.size - 1
+    E = np.zeros((S, 2))
+    F = np.zeros((x.shape[0], 3))
+    V = np.zeros((S, 3, 3))
+    for s in range(S):
+        a0, a1 = int(offs[s]), int(offs[s + 1])
+        if a1 == a0:
+            continue
+        ep = c["excl_ptr"][a0:a1 + 1] - c["excl_ptr"][a0]
+        ei = c["excl_idx"][c["excl_ptr"][a0]:c["excl_ptr"][a1]] - a0
+        e, f, v = oracle.forces(x[a0:a1], c["q"][a0:a1], c["type"][a0:a1], c["lj"], ep, ei,
+                                c["boxes"][s], p)
+        E[s], F[a0:a1], V[s] = e, f, v
+    return E, F, V
+
+
+def keys_of(triples, n_cl):
+    t = np.asarray(triples, dtype=np.int64).reshape(-1, 3)
+    return (t[:, 0] * n_cl + t[:, 1]) * 27 + t[:, 2]
+
+
+def oracle_pair_keys(c, grid, R, w=None, ci_range=None):
+    """Oracle cluster-pair keys for all systems (global cluster numbering)."""
+    slot_atom = grid["slot_atom"]
+    n_cl = slot_atom.size // 8
+    w = grid["w"] if w is None else w
+    sc_col = grid["sc_col"]
+    out = []
+    offs = c["offsets"]
+    for s in range(offs.size - 1):
+        cb = grid["col_base"][s]
+        nx, ny = grid["dims"][s]
+        sel = np.flatnonzero((sc_col >= cb) & (sc_col < cb + nx * ny))
+        if sel.size == 0:
+            continue
+        sc0, sc1 = int(sel[0]), int(sel[-1]) + 1
+        sub = slot_atom[64 * sc0:64 * sc1]
+        lo, hi = 0, 8 * (sc1 - sc0)
+        if ci_range is not None:
+            lo = max(lo, ci_range[0] - 8 * sc0)
+            hi = min(hi, ci_range[1] - 8 * sc0)
+            if hi <= lo:
+                continue
+        keys = oracle.cluster_pairs(sub, w, c["boxes"][s], R, lo, hi)
+        ci, cj, code = oracle.split_key(keys, 8 * (sc1 - sc0))
+        out.append(((ci + 8 * sc0) * n_cl + (cj + 8 * sc0)) * 27 + code)
+    return np.unique(np.concatenate(out)) if out else np.zeros(0, np.int64)
+
+
+def rel_rms(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
