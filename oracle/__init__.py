@@ -69,7 +69,7 @@ def _load():
         P = ctypes.c_void_p
         i64 = ctypes.c_int64
         lib.oracle_forces.argtypes = [i64, P, P, P, ctypes.c_int32, P, P, P, P,
-                                      ctypes.POINTER(Params), P, P, P]
+                                      ctypes.POINTER(Params), P, P, P, P]
         lib.oracle_forces_on.argtypes = [i64, P, P, P, ctypes.c_int32, P, P, P, P,
                                          ctypes.POINTER(Params), i64, P, P]
         lib.oracle_backward.argtypes = [i64, P, P, P, ctypes.c_int32, P, P, P, P,
@@ -93,8 +93,9 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def forces(x, q, type_, lj, excl_ptr, excl_idx, box, p: Params):
-    """FP64 all-pairs minimum-image energies [E_LJ, E_C], forces [N,3] and virial [3,3]."""
+def forces(x, q, type_, lj, excl_ptr, excl_idx, box, p: Params, energy_abs: bool = False):
+    """FP64 all-pairs minimum-image energies [E_LJ, E_C], forces [N,3] and virial [3,3];
+    with energy_abs also the sums of |pair energy| [LJ, Coulomb]."""
     x, q, t = _c(x, np.float32), _c(q, np.float32), _c(type_, np.int32)
     lj = _c(lj, np.float32)
     ep, ei, box = _c(excl_ptr, np.int64), _c(excl_idx, np.int32), _c(box, np.float32)
@@ -102,10 +103,14 @@ def forces(x, q, type_, lj, excl_ptr, excl_idx, box, p: Params):
     f = np.zeros((n, 3), dtype=np.float64)
     e = np.zeros(2, dtype=np.float64)
     v = np.zeros(9, dtype=np.float64)
+    ea = np.zeros(2, dtype=np.float64)
     rc = _load().oracle_forces(n, _ptr(x), _ptr(q), _ptr(t), lj.shape[0], _ptr(lj), _ptr(ep),
-                               _ptr(ei), _ptr(box), ctypes.byref(p), _ptr(f), _ptr(e), _ptr(v))
+                               _ptr(ei), _ptr(box), ctypes.byref(p), _ptr(f), _ptr(e), _ptr(v),
+                               _ptr(ea))
     if rc != 0:
         raise MemoryError("oracle_forces failed")
+    if energy_abs:
+        return e, f, v.reshape(3, 3), ea
     return e, f, v.reshape(3, 3)
 
 

@@ -136,13 +136,15 @@ static void pair_eval(const oracle_params* p, double r2, double c6, double c12, 
 /*
  * Energies [LJ, Coulomb], forces f[n][3] and virial Xi = -1/2 sum_pairs d (x) (phi d),
  * all in FP64, over every pair a < b with (a, b) not excluded and |d_ab| < rc.
+ * energy_abs (may be NULL) receives the sums of |pair energy| [LJ, Coulomb], the scale
+ * against which the rounding of single-precision pair energies is judged.
  * Inputs are the single-precision values the HIP path receives.
  * Atoms outside [0, L) are fine: the minimum image takes care of them.
  */
 int oracle_forces(int64_t n, const float* x, const float* q, const int32_t* type,
                   int32_t ntypes, const float* lj, const int64_t* excl_ptr,
                   const int32_t* excl_idx, const float* box, const oracle_params* p,
-                  double* f, double* energy, double* virial) {
+                  double* f, double* energy, double* virial, double* energy_abs) {
     double L[3] = {box[0], box[1], box[2]};
     double krf = 0, crf = 0;
     rf_constants(p, &krf, &crf);
@@ -150,7 +152,7 @@ int oracle_forces(int64_t n, const float* x, const float* q, const int32_t* type
     const double kq0 = p->epsfac / p->eps_r;
     int nt = oracle_num_threads();
     double* fbuf = (double*)calloc((size_t)nt * (size_t)n * 3, sizeof(double));
-    double* ebuf = (double*)calloc((size_t)nt * 11, sizeof(double));
+    double* ebuf = (double*)calloc((size_t)nt * 13, sizeof(double));
     if (!fbuf || !ebuf) { free(fbuf); free(ebuf); return -1; }
 
 #pragma omp parallel num_threads(nt)
@@ -160,7 +162,7 @@ int oracle_forces(int64_t n, const float* x, const float* q, const int32_t* type
         tid = omp_get_thread_num();
 #endif
         double* fl = fbuf + (size_t)tid * (size_t)n * 3;
-        double* el = ebuf + (size_t)tid * 11;
+        double* el = ebuf + (size_t)tid * 13;
 #pragma omp for schedule(dynamic, 64)
         for (int64_t a = 0; a < n; ++a) {
             for (int64_t b = a + 1; b < n; ++b) {
@@ -182,15 +184,19 @@ int oracle_forces(int64_t n, const float* x, const float* q, const int32_t* type
                 el[1] += t.vc;
                 for (int i = 0; i < 3; ++i)
                     for (int j = 0; j < 3; ++j) el[2 + 3 * i + j] += -0.5 * d[i] * phi * d[j];
+                el[11] += fabs(t.vlj);
+                el[12] += fabs(t.vc);
             }
         }
     }
     /* Fixed-order reduction over threads. */
     memset(f, 0, sizeof(double) * 3 * (size_t)n);
-    for (int k = 0; k < 11; ++k) {
+    for (int k = 0; k < 13; ++k) {
         double s = 0;
-        for (int t = 0; t < nt; ++t) s += ebuf[11 * t + k];
-        if (k < 2) energy[k] = s; else virial[k - 2] = s;
+        for (int t = 0; t < nt; ++t) s += ebuf[13 * t + k];
+        if (k < 2) energy[k] = s;
+        else if (k < 11) virial[k - 2] = s;
+        else if (energy_abs) energy_abs[k - 11] = s;
     }
     for (int t = 0; t < nt; ++t) {
         const double* fl = fbuf + (size_t)t * (size_t)n * 3;
