@@ -51,115 +51,105 @@ __device__ inline float erfcx_poly(float t) {
     return u * p;
 }
 
-struct BData {
-    float x[8], y[8], z[8], q[8];
-    float gx[8], gy[8], gz[8];     // adjoint G of the i-atoms
-    int t[8];
-};
-
-struct BAcc {
-    float x[8], y[8], z[8], q[8];  // dL/dx_i and dL/dq_i / K accumulators
-};
-
 struct BScal {
     float gel, gec;                // dL/dE_LJ, dL/dE_C of the item's system
     float rc_m6, rc_m12;
 };
 
+// One 8x8 block of pairs: i-atom data and accumulators as scalars (lane = ii + 8 jj).
 template <int COUL, bool LJGRAD, bool PRIV, bool SHIFTED>
-__device__ __forceinline__ void entry_bwd(
-    const BData& I, BAcc& A, uint32_t mask, const uint64_t (&ivalid)[8], uint64_t jvalid,
-    const uint64_t* __restrict__ xrow, int cj, int ci0, int code, float4 xj, float4 gj, int tj,
+__device__ __forceinline__ void bwd_block(
+    float xi, float yi, float zi, float qi, float gxi, float gyi, float gzi, int ti, uint64_t m,
+    float& ax, float& ay, float& az, float& aq, const float4& xj, const float4& gj, int tj,
     const float4* __restrict__ s_lj, float* __restrict__ s_hist, int lane, const NbKParams& kp,
     const BScal& bs, float sxi, float syi, float szi, float& ajx, float& ajy, float& ajz,
     float& ajq) {
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        if (!((mask >> c) & 1u)) continue;
-        uint64_t m = ivalid[c] & jvalid;
-        if (xrow) m &= xrow[c];
-        if (cj == ci0 + c && code == kShiftZero) m &= 0x7f3f1f0f07030100ull;
-        float dx, dy, dz;
-        if (SHIFTED) {
-            dx = (I.x[c] - sxi) - xj.x;
-            dy = (I.y[c] - syi) - xj.y;
-            dz = (I.z[c] - szi) - xj.z;
+    float dx, dy, dz;
+    if (SHIFTED) {
+        dx = (xi - sxi) - xj.x;
+        dy = (yi - syi) - xj.y;
+        dz = (zi - szi) - xj.z;
+    } else {
+        dx = xi - xj.x;
+        dy = yi - xj.y;
+        dz = zi - xj.z;
+    }
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const uint64_t act = __builtin_amdgcn_ballot_w64(r2 < kp.rc2) & m;
+    if (!act) return;
+    const bool on = __builtin_amdgcn_inverse_ballot_w64(act);
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float rinv2 = rinv * rinv;
+    const float4 p = s_lj[ti + tj];                    // (6 c6, 12 c12, shift, c6)
+    const float rinv6 = rinv2 * rinv2 * rinv2;
+    const float a = p.y * rinv6;                       // 12 c12 r^-6
+    const float phi_lj = rinv6 * (a - p.x) * rinv2;
+    const float dphi_lj = rinv6 * rinv2 * rinv2 * fmaf(-14.0f, a, 8.0f * p.x);
+    const float qq = qi * xj.w;
+    float psi, dpsi, v;
+    if (COUL == NB_COUL_RF) {
+        psi = rinv * rinv2 - 2.0f * kp.krf;
+        dpsi = -3.0f * rinv2 * rinv2 * rinv;
+        v = fmaf(kp.krf, r2, rinv) - kp.crf;
+    } else {
+        const float r = r2 * rinv;
+        const float e = __builtin_amdgcn_exp2f(r2 * kp.beta2_log2e);
+        const float erfcv = e * erfcx_poly(kp.beta * r);
+        const float te = kp.two_beta_sqrtpi * e;
+        const float g = fmaf(erfcv, rinv, te);
+        psi = g * rinv2;
+        dpsi = fmaf(-3.0f * g, rinv2 * rinv2, -2.0f * kp.beta * kp.beta * te * rinv2);
+        v = fmaf(erfcv, rinv, -kp.ewald_shift);
+    }
+    const float phi_c = qq * psi;
+    const float gdx = gxi - gj.x, gdy = gyi - gj.y, gdz = gzi - gj.z;
+    const float u = fmaf(gdx, dx, fmaf(gdy, dy, gdz * dz));
+    const float phi = phi_lj + phi_c;
+    const float coef = fmaf(dphi_lj + qq * dpsi, u, -fmaf(bs.gel, phi_lj, bs.gec * phi_c));
+    float hx = fmaf(coef, dx, phi * gdx);
+    float hy = fmaf(coef, dy, phi * gdy);
+    float hz = fmaf(coef, dz, phi * gdz);
+    float w = fmaf(psi, u, bs.gec * v);
+    hx = on ? hx : 0.f;
+    hy = on ? hy : 0.f;
+    hz = on ? hz : 0.f;
+    w = on ? w : 0.f;
+    ax += hx;
+    ay += hy;
+    az += hz;
+    aq = fmaf(xj.w, w, aq);                  // times K after the item
+    ajx -= hx;
+    ajy -= hy;
+    ajz -= hz;
+    ajq = fmaf(qi, w, ajq);                  // qi already holds K q_i
+    if (LJGRAD) {
+        const float rinv12 = rinv6 * rinv6;
+        float g12 = fmaf(u * 12.0f * rinv2, rinv12, bs.gel * (rinv12 - bs.rc_m12));
+        float g6 = fmaf(u * -6.0f * rinv2, rinv6, bs.gel * (bs.rc_m6 - rinv6));
+        g12 = on ? g12 : 0.f;
+        g6 = on ? g6 : 0.f;
+        const int key = ti + tj;
+        if (PRIV) {
+            atomicAdd(&s_hist[(2 * key) * kWave + lane], g6);
+            atomicAdd(&s_hist[(2 * key + 1) * kWave + lane], g12);
         } else {
-            dx = I.x[c] - xj.x;
-            dy = I.y[c] - xj.y;
-            dz = I.z[c] - xj.z;
-        }
-        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        const uint64_t act = __builtin_amdgcn_ballot_w64(r2 < kp.rc2) & m;
-        if (!act) continue;
-        const bool on = __builtin_amdgcn_inverse_ballot_w64(act);
-        const float rinv = __builtin_amdgcn_rsqf(r2);
-        const float rinv2 = rinv * rinv;
-        const float4 p = s_lj[I.t[c] + tj];              // (6 c6, 12 c12, shift, c6)
-        const float rinv6 = rinv2 * rinv2 * rinv2;
-        const float a = p.y * rinv6;                       // 12 c12 r^-6
-        const float phi_lj = rinv6 * (a - p.x) * rinv2;
-        const float dphi_lj = rinv6 * rinv2 * rinv2 * fmaf(-14.0f, a, 8.0f * p.x);
-        const float qq = I.q[c] * xj.w;
-        float psi, dpsi, v;
-        if (COUL == NB_COUL_RF) {
-            psi = rinv * rinv2 - 2.0f * kp.krf;
-            dpsi = -3.0f * rinv2 * rinv2 * rinv;
-            v = fmaf(kp.krf, r2, rinv) - kp.crf;
-        } else {
-            const float r = r2 * rinv;
-            const float e = __builtin_amdgcn_exp2f(r2 * kp.beta2_log2e);
-            const float erfcv = e * erfcx_poly(kp.beta * r);
-            const float te = kp.two_beta_sqrtpi * e;
-            const float g = fmaf(erfcv, rinv, te);
-            psi = g * rinv2;
-            dpsi = fmaf(-3.0f * g, rinv2 * rinv2, -2.0f * kp.beta * kp.beta * te * rinv2);
-            v = fmaf(erfcv, rinv, -kp.ewald_shift);
-        }
-        const float phi_c = qq * psi;
-        const float gdx = I.gx[c] - gj.x, gdy = I.gy[c] - gj.y, gdz = I.gz[c] - gj.z;
-        const float u = fmaf(gdx, dx, fmaf(gdy, dy, gdz * dz));
-        const float phi = phi_lj + phi_c;
-        const float coef = fmaf(dphi_lj + qq * dpsi, u, -fmaf(bs.gel, phi_lj, bs.gec * phi_c));
-        float hx = fmaf(coef, dx, phi * gdx);
-        float hy = fmaf(coef, dy, phi * gdy);
-        float hz = fmaf(coef, dz, phi * gdz);
-        float w = fmaf(psi, u, bs.gec * v);
-        hx = on ? hx : 0.f;
-        hy = on ? hy : 0.f;
-        hz = on ? hz : 0.f;
-        w = on ? w : 0.f;
-        A.x[c] += hx;
-        A.y[c] += hy;
-        A.z[c] += hz;
-        A.q[c] = fmaf(xj.w, w, A.q[c]);          // times K after the item
-        ajx -= hx;
-        ajy -= hy;
-        ajz -= hz;
-        ajq = fmaf(I.q[c], w, ajq);              // I.q already holds K q_i
-        if (LJGRAD) {
-            const float rinv12 = rinv6 * rinv6;
-            float g12 = fmaf(u * 12.0f * rinv2, rinv12, bs.gel * (rinv12 - bs.rc_m12));
-            float g6 = fmaf(u * -6.0f * rinv2, rinv6, bs.gel * (bs.rc_m6 - rinv6));
-            g12 = on ? g12 : 0.f;
-            g6 = on ? g6 : 0.f;
-            const int key = I.t[c] + tj;
-            if (PRIV) {
-                atomicAdd(&s_hist[(2 * key) * kWave + lane], g6);
-                atomicAdd(&s_hist[(2 * key + 1) * kWave + lane], g12);
-            } else {
-                atomicAdd(&s_hist[2 * key], g6);
-                atomicAdd(&s_hist[2 * key + 1], g12);
-            }
+            atomicAdd(&s_hist[2 * key], g6);
+            atomicAdd(&s_hist[2 * key + 1], g12);
         }
     }
 }
 
+#define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
+
 template <int COUL, bool LJGRAD, bool PRIV>
-__global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(NbDev d, NbKParams kp,
-                                                         const float* __restrict__ lj,
-                                                         const double* __restrict__ grad_e,
-                                                         int n_items) {
+__global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
+    const NbItem* __restrict__ items, const NbEntry* __restrict__ entries,
+    const uint64_t* __restrict__ excl_rows, const float4* __restrict__ xq,
+    const float4* __restrict__ gslot, const int32_t* __restrict__ type_slot,
+    const float4* __restrict__ cl_bb, const NbScInfo* __restrict__ sc_info,
+    const NbSys* __restrict__ sys, const float* __restrict__ lj,
+    const double* __restrict__ grad_e, float4* __restrict__ jpart, float4* __restrict__ ipart,
+    float* __restrict__ glj_part, NbKParams kp, int n_items) {
     extern __shared__ float4 s_dyn[];
     const int T = kp.n_types;
     const int TT = T * T;
@@ -178,41 +168,58 @@ __global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(NbDev d, NbKParams kp,
     const int item = blockIdx.x * kBwdWaves + wave;
     if (item >= n_items) return;
     float* s_hist = s_hist_all + wave * hist_per_wave;
-    const NbItem it = d.items[item];
+    const NbItem it = items[item];
     const int ii = lane & 7, jj = lane >> 3;
     const int sc = it.sc, ci0 = kClustersPerSc * sc;
-    const NbSys S = d.sys[it.sys];
+    const int sysi = sc_info[sc].sys;
+    const NbSys S = sys[sysi];
     BScal bs;
-    bs.gel = grad_e ? (float)grad_e[2 * it.sys] : 0.f;
-    bs.gec = grad_e ? (float)grad_e[2 * it.sys + 1] : 0.f;
+    bs.gel = grad_e ? (float)grad_e[2 * sysi] : 0.f;
+    bs.gec = grad_e ? (float)grad_e[2 * sysi + 1] : 0.f;
     bs.rc_m6 = kp.rc_m6;
     bs.rc_m12 = kp.rc_m12;
+    const int ibase = kScAtoms * sc + ii;
 
-    BData I;
-    BAcc A;
-    uint64_t ivalid[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int slot = kScAtoms * sc + kClusterSize * c + ii;
-        const float4 v = d.xq[slot];
-        const float4 g = d.gslot[slot];
-        I.x[c] = v.x;
-        I.y[c] = v.y;
-        I.z[c] = v.z;
-        I.q[c] = v.w * kp.epsfac_r;
-        I.gx[c] = g.x;
-        I.gy[c] = g.y;
-        I.gz[c] = g.z;
-        I.t[c] = d.type_slot[slot] * T;
-        const int ni = (int)d.cl_bb[2 * (ci0 + c)].w;
-        ivalid[c] = ((ni >= 8) ? 0xffull : ((1ull << ni) - 1ull)) * 0x0101010101010101ull;
-        A.x[c] = A.y[c] = A.z[c] = A.q[c] = 0.f;
+#define NB_ILOAD(c)                                                                    \
+    float xi##c, yi##c, zi##c, qi##c, gxi##c, gyi##c, gzi##c;                          \
+    int ti##c;                                                                         \
+    uint64_t iv##c;                                                                    \
+    float ax##c = 0.f, ay##c = 0.f, az##c = 0.f, aq##c = 0.f;                          \
+    {                                                                                  \
+        const float4 v = xq[ibase + kClusterSize * c];                                 \
+        const float4 g = gslot[ibase + kClusterSize * c];                              \
+        xi##c = v.x;                                                                   \
+        yi##c = v.y;                                                                   \
+        zi##c = v.z;                                                                   \
+        qi##c = v.w * kp.epsfac_r;                                                     \
+        gxi##c = g.x;                                                                  \
+        gyi##c = g.y;                                                                  \
+        gzi##c = g.z;                                                                  \
+        ti##c = type_slot[ibase + kClusterSize * c] * T;                               \
+        const int ni = (int)cl_bb[2 * (ci0 + c)].w;                                    \
+        iv##c = ((ni >= 8) ? 0xffull : ((1ull << ni) - 1ull)) * 0x0101010101010101ull; \
     }
+    NB_FOR8(NB_ILOAD)
+#undef NB_ILOAD
 
-    for (int e = it.e0; e < it.e0 + it.ne; ++e) {
-        const NbEntry ent = d.entries[e];
+    const int e_end = it.e0 + it.ne;
+    NbEntry nxt = entries[it.e0];
+    float4 xj_n = xq[kClusterSize * nxt.cj + jj];
+    float4 gj_n = gslot[kClusterSize * nxt.cj + jj];
+    int tj_n = type_slot[kClusterSize * nxt.cj + jj];
+    for (int e = it.e0; e < e_end; ++e) {
+        const NbEntry ent = nxt;
+        float4 xj = xj_n;
+        const float4 gj = gj_n;
+        const int tj = tj_n;
+        if (e + 1 < e_end) {
+            nxt = entries[e + 1];
+            xj_n = xq[kClusterSize * nxt.cj + jj];
+            gj_n = gslot[kClusterSize * nxt.cj + jj];
+            tj_n = type_slot[kClusterSize * nxt.cj + jj];
+        }
         const uint32_t mask = (ent.meta >> 16) & 0xffu;
-        float4* jp = d.jpart + (size_t)ent.jpos * kClusterSize;
+        float4* jp = jpart + (size_t)ent.jpos * kClusterSize;
         if (!mask) {
             if (ii == 0) jp[jj] = make_float4(0.f, 0.f, 0.f, 0.f);
             continue;
@@ -221,51 +228,60 @@ __global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(NbDev d, NbKParams kp,
         const int nj = (int)(ent.meta >> 24);
         const uint64_t jvalid = (nj >= 8) ? ~0ull : ((1ull << (8 * nj)) - 1ull);
         const uint64_t* xrow =
-            (ent.excl >= 0) ? d.excl_rows + (size_t)ent.excl * kClustersPerSc : nullptr;
-        const int jslot = kClusterSize * ent.cj + jj;
-        float4 xj = d.xq[jslot];
-        const float4 gj = d.gslot[jslot];
-        const int tj = d.type_slot[jslot];
+            (ent.excl >= 0) ? excl_rows + (size_t)ent.excl * kClustersPerSc : nullptr;
+        const bool self = (ent.cj >> 3) == sc && code == kShiftZero;
+        const int dc = ent.cj - ci0;
         float ajx = 0.f, ajy = 0.f, ajz = 0.f, ajq = 0.f;
+#define NB_MASK(c)                                                                     \
+    (iv##c & jvalid & (xrow ? xrow[c] : ~0ull) &                                       \
+     ((self && dc == c) ? 0x7f3f1f0f07030100ull : ~0ull))
         if (code == kShiftZero) {
-            entry_bwd<COUL, LJGRAD, PRIV, false>(I, A, mask, ivalid, jvalid, xrow, ent.cj, ci0,
-                                                  code, xj, gj, tj, s_lj, s_hist, lane, kp, bs,
-                                                  0.f, 0.f, 0.f, ajx, ajy, ajz, ajq);
+#define NB_BLOCK0(c)                                                                   \
+    if ((mask >> c) & 1u)                                                              \
+        bwd_block<COUL, LJGRAD, PRIV, false>(xi##c, yi##c, zi##c, qi##c, gxi##c, gyi##c,  \
+                                             gzi##c, ti##c, NB_MASK(c), ax##c, ay##c,     \
+                                             az##c, aq##c, xj, gj, tj, s_lj, s_hist, lane,\
+                                             kp, bs, 0.f, 0.f, 0.f, ajx, ajy, ajz, ajq);
+            NB_FOR8(NB_BLOCK0)
+#undef NB_BLOCK0
         } else {
             const int sx = shift_x(code), sy = shift_y(code), sz = shift_z(code);
             if (sx < 0) xj.x -= S.L[0];
             if (sy < 0) xj.y -= S.L[1];
             if (sz < 0) xj.z -= S.L[2];
-            entry_bwd<COUL, LJGRAD, PRIV, true>(I, A, mask, ivalid, jvalid, xrow, ent.cj, ci0,
-                                                 code, xj, gj, tj, s_lj, s_hist, lane, kp, bs,
-                                                 sx > 0 ? S.L[0] : 0.f, sy > 0 ? S.L[1] : 0.f,
-                                                 sz > 0 ? S.L[2] : 0.f, ajx, ajy, ajz, ajq);
+            const float sxi = sx > 0 ? S.L[0] : 0.f, syi = sy > 0 ? S.L[1] : 0.f,
+                        szi = sz > 0 ? S.L[2] : 0.f;
+#define NB_BLOCK1(c)                                                                   \
+    if ((mask >> c) & 1u)                                                              \
+        bwd_block<COUL, LJGRAD, PRIV, true>(xi##c, yi##c, zi##c, qi##c, gxi##c, gyi##c,   \
+                                            gzi##c, ti##c, NB_MASK(c), ax##c, ay##c,      \
+                                            az##c, aq##c, xj, gj, tj, s_lj, s_hist, lane, \
+                                            kp, bs, sxi, syi, szi, ajx, ajy, ajz, ajq);
+            NB_FOR8(NB_BLOCK1)
+#undef NB_BLOCK1
         }
+#undef NB_MASK
         ajx = dpp_sum8(ajx);
         ajy = dpp_sum8(ajy);
         ajz = dpp_sum8(ajz);
         ajq = dpp_sum8(ajq);
         if (ii == 0) jp[jj] = make_float4(ajx, ajy, ajz, ajq);
     }
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-#pragma unroll
-        for (int off = 8; off < kWave; off <<= 1) {
-            A.x[c] += __shfl_xor(A.x[c], off);
-            A.y[c] += __shfl_xor(A.y[c], off);
-            A.z[c] += __shfl_xor(A.z[c], off);
-            A.q[c] += __shfl_xor(A.q[c], off);
-        }
-    }
-    if (jj == 0) {
-        float4* ip = d.ipart + (size_t)item * kScAtoms;
-#pragma unroll
-        for (int c = 0; c < 8; ++c)
-            ip[kClusterSize * c + ii] = make_float4(A.x[c], A.y[c], A.z[c], A.q[c] * kp.epsfac_r);
-    }
+    float4* ip = ipart + (size_t)item * kScAtoms;
+#define NB_IRED(c)                                                                     \
+    for (int off = 8; off < kWave; off <<= 1) {                                        \
+        ax##c += __shfl_xor(ax##c, off);                                               \
+        ay##c += __shfl_xor(ay##c, off);                                               \
+        az##c += __shfl_xor(az##c, off);                                               \
+        aq##c += __shfl_xor(aq##c, off);                                               \
+    }                                                                                  \
+    if (jj == 0)                                                                       \
+        ip[kClusterSize * c + ii] = make_float4(ax##c, ay##c, az##c, aq##c * kp.epsfac_r);
+    NB_FOR8(NB_IRED)
+#undef NB_IRED
     if (LJGRAD) {
         __builtin_amdgcn_wave_barrier();
-        float* out = d.glj_part + (size_t)item * 2 * TT;
+        float* out = glj_part + (size_t)item * 2 * TT;
         for (int k = lane; k < 2 * TT; k += kWave) {
             float v = 0.f;
             if (PRIV) {
@@ -329,24 +345,35 @@ __global__ void k_reduce_bwd(NbDev d, float* __restrict__ gx, float* __restrict_
     }
 }
 
-// Table gradient: FP64 sum over items, one thread per (type pair, c6/c12), fixed order.
-// The table is symmetric, so the derivative with respect to the shared value of
+// Table gradient: one block per (type pair, c6/c12) sums the items in a fixed order in
+// FP64.  The table is symmetric, so the derivative with respect to the shared value of
 // [t1][t2] and [t2][t1] is split evenly between the two entries (independent of which
 // atom of a pair the kernel treats as i).
-__global__ void k_reduce_glj(NbDev d, double* __restrict__ out, int n_types, int n_items,
-                             int accumulate) {
+constexpr int kGljThreads = 256;
+__global__ __launch_bounds__(kGljThreads) void k_reduce_glj(NbDev d, double* __restrict__ out,
+                                                            int n_types, int n_items,
+                                                            int accumulate) {
+    __shared__ double s_v[kGljThreads];
     const int n_keys = 2 * n_types * n_types;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_keys) return;
+    const int k = blockIdx.x;
     const int c = k & 1, t1 = (k >> 1) / n_types, t2 = (k >> 1) % n_types;
     const int kt = 2 * (t2 * n_types + t1) + c;
     double s = 0.0;
-    for (int i = 0; i < n_items; ++i) {
+    for (int i = threadIdx.x; i < n_items; i += blockDim.x) {
         s += (double)d.glj_part[(size_t)i * n_keys + k];
         if (kt != k) s += (double)d.glj_part[(size_t)i * n_keys + kt];
     }
-    if (kt != k) s *= 0.5;
-    out[k] = accumulate ? out[k] + s : s;
+    s_v[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = kGljThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) s_v[threadIdx.x] += s_v[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double r = s_v[0];
+        if (kt != k) r *= 0.5;
+        out[k] = accumulate ? out[k] + r : r;
+    }
 }
 
 inline int blocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
@@ -358,7 +385,9 @@ void launch_bwd_t(const NbDev& d, const NbKParams& kp, const float* lj, const do
     const size_t hist = LJG ? (size_t)(PRIV ? 2 * TT * kWave : 2 * TT) * kBwdWaves : 0;
     const size_t lds = sizeof(float4) * TT + sizeof(float) * hist;
     hipLaunchKernelGGL((k_nb_bwd<COUL, LJG, PRIV>), dim3(blocks(n_items, kBwdWaves)),
-                       dim3(kBwdThreads), lds, s, d, kp, lj, ge, n_items);
+                       dim3(kBwdThreads), lds, s, d.items, d.entries, d.excl_rows, d.xq, d.gslot,
+                       d.type_slot, d.cl_bb, d.sc_info, d.sys, lj, ge, d.jpart, d.ipart,
+                       d.glj_part, kp, n_items);
 }
 
 template <int COUL>
@@ -392,7 +421,7 @@ hipError_t launch_reduce_backward(const NbDev& d, float* grad_x, float* grad_q, 
                            grad_q, accumulate ? 1 : 0, n_slots);
     if (grad_lj) {
         const int nk = 2 * n_types * n_types;
-        hipLaunchKernelGGL(k_reduce_glj, dim3(blocks(nk, 64)), dim3(64), 0, s, d, grad_lj,
+        hipLaunchKernelGGL(k_reduce_glj, dim3(nk), dim3(kGljThreads), 0, s, d, grad_lj,
                            n_types, n_items, accumulate ? 1 : 0);
     }
     return hipGetLastError();

@@ -58,87 +58,85 @@ __device__ inline float erfcx_poly(float t) {
     return u * p;
 }
 
-struct IData {
-    float x[8], y[8], z[8], q[8];
-    int t[8];
-};
-
+// One 8x8 block of pairs (i-cluster c of the item, the current j-cluster): m is the
+// scalar 64-bit mask of valid, non-excluded lanes (lane = ii + 8 jj).
 template <int COUL, bool ENERGY, bool VIRIAL, bool SHIFTED>
-__device__ __forceinline__ void entry_pairs(
-    const IData& I, float (&fx)[8], float (&fy)[8], float (&fz)[8], uint32_t mask,
-    const uint64_t (&ivalid)[8], uint64_t jvalid, const uint64_t* __restrict__ xrow,
-    int cj, int ci0, int code, float4 xj, int tj, const float4* __restrict__ s_lj,
-    const NbKParams& kp, float sxi, float syi, float szi, float& fjx, float& fjy, float& fjz,
-    float& elj, float& ec, float (&vir)[6], int& npair, int& nblock) {
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        if (!((mask >> c) & 1u)) continue;
-        uint64_t m = ivalid[c] & jvalid;
-        if (xrow) m &= xrow[c];
-        if (cj == ci0 + c && code == kShiftZero) m &= 0x7f3f1f0f07030100ull;
-        float dx, dy, dz;
-        if (SHIFTED) {
-            dx = (I.x[c] - sxi) - xj.x;
-            dy = (I.y[c] - syi) - xj.y;
-            dz = (I.z[c] - szi) - xj.z;
-        } else {
-            dx = I.x[c] - xj.x;
-            dy = I.y[c] - xj.y;
-            dz = I.z[c] - xj.z;
-        }
-        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        const uint64_t act = __builtin_amdgcn_ballot_w64(r2 < kp.rc2) & m;
-        if (!act) continue;
-        const bool on = __builtin_amdgcn_inverse_ballot_w64(act);
-        const float rinv = __builtin_amdgcn_rsqf(r2);
-        const float rinv2 = rinv * rinv;
-        const float4 p = s_lj[I.t[c] + tj];              // (6 c6, 12 c12, shift, c6)
-        const float rinv6 = rinv2 * rinv2 * rinv2;
-        const float a = p.y * rinv6;
-        const float flj = rinv6 * (a - p.x);               // F_LJ * r
-        const float qq = I.q[c] * xj.w;                    // epsfac/eps_r folded into q_i
-        float fscal, vc = 0.f;
-        if (COUL == NB_COUL_RF) {
-            fscal = fmaf(flj, rinv2, qq * (rinv * rinv2 - 2.0f * kp.krf));
-            if (ENERGY) vc = qq * (fmaf(kp.krf, r2, rinv) - kp.crf);
-        } else {
-            const float r = r2 * rinv;
-            const float e = __builtin_amdgcn_exp2f(r2 * kp.beta2_log2e);   // exp(-beta^2 r^2)
-            const float erfcv = e * erfcx_poly(kp.beta * r);
-            const float g = fmaf(erfcv, rinv, kp.two_beta_sqrtpi * e);
-            fscal = fmaf(qq, g, flj) * rinv2;
-            if (ENERGY) vc = qq * fmaf(erfcv, rinv, -kp.ewald_shift);
-        }
-        fscal = on ? fscal : 0.f;
-        const float tx = fscal * dx, ty = fscal * dy, tz = fscal * dz;
-        fx[c] += tx;
-        fy[c] += ty;
-        fz[c] += tz;
-        fjx -= tx;
-        fjy -= ty;
-        fjz -= tz;
-        if (ENERGY) {
-            const float vlj = fmaf(rinv6, fmaf(a, 1.0f / 12.0f, -p.w), -p.z);
-            elj += on ? vlj : 0.f;
-            ec += on ? vc : 0.f;
-            npair += __builtin_popcountll(act);
-            nblock += 1;
-        }
-        if (VIRIAL) {
-            vir[0] = fmaf(tx, dx, vir[0]);
-            vir[1] = fmaf(ty, dy, vir[1]);
-            vir[2] = fmaf(tz, dz, vir[2]);
-            vir[3] = fmaf(tx, dy, vir[3]);
-            vir[4] = fmaf(tx, dz, vir[4]);
-            vir[5] = fmaf(ty, dz, vir[5]);
-        }
+__device__ __forceinline__ void pair_block(float xi, float yi, float zi, float qi, int ti,
+                                           uint64_t m, float& fx, float& fy, float& fz,
+                                           const float4& xj, int tj,
+                                           const float4* __restrict__ s_lj, const NbKParams& kp,
+                                           float sxi, float syi, float szi, float& fjx,
+                                           float& fjy, float& fjz, float& elj, float& ec,
+                                           float (&vir)[6], int& npair, int& nblock) {
+    float dx, dy, dz;
+    if (SHIFTED) {
+        dx = (xi - sxi) - xj.x;
+        dy = (yi - syi) - xj.y;
+        dz = (zi - szi) - xj.z;
+    } else {
+        dx = xi - xj.x;
+        dy = yi - xj.y;
+        dz = zi - xj.z;
+    }
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const uint64_t act = __builtin_amdgcn_ballot_w64(r2 < kp.rc2) & m;
+    if (!act) return;
+    const bool on = __builtin_amdgcn_inverse_ballot_w64(act);
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float rinv2 = rinv * rinv;
+    const float4 p = s_lj[ti + tj];                    // (6 c6, 12 c12, shift, c6)
+    const float rinv6 = rinv2 * rinv2 * rinv2;
+    const float a = p.y * rinv6;
+    const float flj = rinv6 * (a - p.x);               // F_LJ * r
+    const float qq = qi * xj.w;                        // epsfac/eps_r folded into q_i
+    float fscal, vc = 0.f;
+    if (COUL == NB_COUL_RF) {
+        fscal = fmaf(flj, rinv2, qq * (rinv * rinv2 - 2.0f * kp.krf));
+        if (ENERGY) vc = qq * (fmaf(kp.krf, r2, rinv) - kp.crf);
+    } else {
+        const float r = r2 * rinv;
+        const float e = __builtin_amdgcn_exp2f(r2 * kp.beta2_log2e);   // exp(-beta^2 r^2)
+        const float erfcv = e * erfcx_poly(kp.beta * r);
+        const float g = fmaf(erfcv, rinv, kp.two_beta_sqrtpi * e);
+        fscal = fmaf(qq, g, flj) * rinv2;
+        if (ENERGY) vc = qq * fmaf(erfcv, rinv, -kp.ewald_shift);
+    }
+    fscal = on ? fscal : 0.f;
+    const float tx = fscal * dx, ty = fscal * dy, tz = fscal * dz;
+    fx += tx;
+    fy += ty;
+    fz += tz;
+    fjx -= tx;
+    fjy -= ty;
+    fjz -= tz;
+    if (ENERGY) {
+        const float vlj = fmaf(rinv6, fmaf(a, 1.0f / 12.0f, -p.w), -p.z);
+        elj += on ? vlj : 0.f;
+        ec += on ? vc : 0.f;
+        npair += __builtin_popcountll(act);
+        nblock += 1;
+    }
+    if (VIRIAL) {
+        vir[0] = fmaf(tx, dx, vir[0]);
+        vir[1] = fmaf(ty, dy, vir[1]);
+        vir[2] = fmaf(tz, dz, vir[2]);
+        vir[3] = fmaf(tx, dy, vir[3]);
+        vir[4] = fmaf(tx, dz, vir[4]);
+        vir[5] = fmaf(ty, dz, vir[5]);
     }
 }
 
+// Per-cluster scalars of the item's eight i-clusters (kept in registers).
+#define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
+
 template <int COUL, bool ENERGY, bool VIRIAL>
-__global__ __launch_bounds__(kFwdThreads) void k_nb_fwd(NbDev d, NbKParams kp,
-                                                         const float* __restrict__ lj,
-                                                         int n_items) {
+__global__ __launch_bounds__(kFwdThreads) void k_nb_fwd(
+    const NbItem* __restrict__ items, const NbEntry* __restrict__ entries,
+    const uint64_t* __restrict__ excl_rows, const float4* __restrict__ xq,
+    const int32_t* __restrict__ type_slot, const float4* __restrict__ cl_bb,
+    const NbScInfo* __restrict__ sc_info, const NbSys* __restrict__ sys,
+    const float* __restrict__ lj, float4* __restrict__ jpart, float4* __restrict__ ipart,
+    double* __restrict__ epart, int epart_stride, NbKParams kp, int n_items) {
     extern __shared__ float4 s_lj[];
     const int T = kp.n_types;
     for (int i = threadIdx.x; i < T * T; i += blockDim.x) {
@@ -150,35 +148,49 @@ __global__ __launch_bounds__(kFwdThreads) void k_nb_fwd(NbDev d, NbKParams kp,
     const int lane = threadIdx.x & (kWave - 1);
     const int item = blockIdx.x * kFwdWaves + wave;
     if (item >= n_items) return;
-    const NbItem it = d.items[item];
+    const NbItem it = items[item];
     const int ii = lane & 7, jj = lane >> 3;
     const int sc = it.sc, ci0 = kClustersPerSc * sc;
-    const NbSys S = d.sys[it.sys];
+    const NbSys S = sys[sc_info[sc].sys];
+    const int ibase = kScAtoms * sc + ii;
 
-    IData I;
-    uint64_t ivalid[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const float4 v = d.xq[kScAtoms * sc + kClusterSize * c + ii];
-        I.x[c] = v.x;
-        I.y[c] = v.y;
-        I.z[c] = v.z;
-        I.q[c] = v.w * kp.epsfac_r;
-        I.t[c] = d.type_slot[kScAtoms * sc + kClusterSize * c + ii] * T;
-        const int ni = (int)d.cl_bb[2 * (ci0 + c)].w;
-        ivalid[c] = ((ni >= 8) ? 0xffull : ((1ull << ni) - 1ull)) * 0x0101010101010101ull;
+#define NB_ILOAD(c)                                                                    \
+    float xi##c, yi##c, zi##c, qi##c;                                                  \
+    int ti##c;                                                                         \
+    uint64_t iv##c;                                                                    \
+    float fx##c = 0.f, fy##c = 0.f, fz##c = 0.f;                                       \
+    {                                                                                  \
+        const float4 v = xq[ibase + kClusterSize * c];                                 \
+        xi##c = v.x;                                                                   \
+        yi##c = v.y;                                                                   \
+        zi##c = v.z;                                                                   \
+        qi##c = v.w * kp.epsfac_r;                                                     \
+        ti##c = type_slot[ibase + kClusterSize * c] * T;                               \
+        const int ni = (int)cl_bb[2 * (ci0 + c)].w;                                    \
+        iv##c = ((ni >= 8) ? 0xffull : ((1ull << ni) - 1ull)) * 0x0101010101010101ull; \
     }
-    float fx[8], fy[8], fz[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) fx[c] = fy[c] = fz[c] = 0.f;
+    NB_FOR8(NB_ILOAD)
+#undef NB_ILOAD
+
     double elj_acc = 0.0, ec_acc = 0.0;
     double vir_acc[6] = {0, 0, 0, 0, 0, 0};
     int npair = 0, nblock = 0;
 
-    for (int e = it.e0; e < it.e0 + it.ne; ++e) {
-        const NbEntry ent = d.entries[e];
+    const int e_end = it.e0 + it.ne;
+    NbEntry nxt = entries[it.e0];
+    float4 xj_n = xq[kClusterSize * nxt.cj + jj];
+    int tj_n = type_slot[kClusterSize * nxt.cj + jj];
+    for (int e = it.e0; e < e_end; ++e) {
+        const NbEntry ent = nxt;
+        float4 xj = xj_n;
+        const int tj = tj_n;
+        if (e + 1 < e_end) {               // prefetch the next j-cluster
+            nxt = entries[e + 1];
+            xj_n = xq[kClusterSize * nxt.cj + jj];
+            tj_n = type_slot[kClusterSize * nxt.cj + jj];
+        }
         const uint32_t mask = (ent.meta >> 16) & 0xffu;
-        float4* jp = d.jpart + (size_t)ent.jpos * kClusterSize;
+        float4* jp = jpart + (size_t)ent.jpos * kClusterSize;
         if (!mask) {
             if (ii == 0) jp[jj] = make_float4(0.f, 0.f, 0.f, 0.f);
             continue;
@@ -187,27 +199,42 @@ __global__ __launch_bounds__(kFwdThreads) void k_nb_fwd(NbDev d, NbKParams kp,
         const int nj = (int)(ent.meta >> 24);
         const uint64_t jvalid = (nj >= 8) ? ~0ull : ((1ull << (8 * nj)) - 1ull);
         const uint64_t* xrow =
-            (ent.excl >= 0) ? d.excl_rows + (size_t)ent.excl * kClustersPerSc : nullptr;
-        float4 xj = d.xq[kClusterSize * ent.cj + jj];
-        const int tj = d.type_slot[kClusterSize * ent.cj + jj];
+            (ent.excl >= 0) ? excl_rows + (size_t)ent.excl * kClustersPerSc : nullptr;
+        const bool self = (ent.cj >> 3) == sc && code == kShiftZero;
         float fjx = 0.f, fjy = 0.f, fjz = 0.f, elj = 0.f, ec = 0.f;
         float vir[6] = {0, 0, 0, 0, 0, 0};
+        const int dc = ent.cj - ci0;        // the i-cluster equal to the j-cluster, if any
+
+#define NB_MASK(c)                                                                     \
+    (iv##c & jvalid & (xrow ? xrow[c] : ~0ull) &                                       \
+     ((self && dc == c) ? 0x7f3f1f0f07030100ull : ~0ull))
         if (code == kShiftZero) {
-            entry_pairs<COUL, ENERGY, VIRIAL, false>(I, fx, fy, fz, mask, ivalid, jvalid, xrow,
-                                                     ent.cj, ci0, code, xj, tj, s_lj, kp, 0.f,
-                                                     0.f, 0.f, fjx, fjy, fjz, elj, ec, vir,
-                                                     npair, nblock);
+#define NB_BLOCK0(c)                                                                   \
+    if ((mask >> c) & 1u)                                                              \
+        pair_block<COUL, ENERGY, VIRIAL, false>(xi##c, yi##c, zi##c, qi##c, ti##c,     \
+                                                NB_MASK(c), fx##c, fy##c, fz##c, xj, tj, \
+                                                s_lj, kp, 0.f, 0.f, 0.f, fjx, fjy, fjz,  \
+                                                elj, ec, vir, npair, nblock);
+            NB_FOR8(NB_BLOCK0)
+#undef NB_BLOCK0
         } else {
             // Exact periodic shift: subtract L on the side whose coordinate is near L.
             const int sx = shift_x(code), sy = shift_y(code), sz = shift_z(code);
             if (sx < 0) xj.x -= S.L[0];
             if (sy < 0) xj.y -= S.L[1];
             if (sz < 0) xj.z -= S.L[2];
-            entry_pairs<COUL, ENERGY, VIRIAL, true>(
-                I, fx, fy, fz, mask, ivalid, jvalid, xrow, ent.cj, ci0, code, xj, tj, s_lj, kp,
-                sx > 0 ? S.L[0] : 0.f, sy > 0 ? S.L[1] : 0.f, sz > 0 ? S.L[2] : 0.f, fjx, fjy,
-                fjz, elj, ec, vir, npair, nblock);
+            const float sxi = sx > 0 ? S.L[0] : 0.f, syi = sy > 0 ? S.L[1] : 0.f,
+                        szi = sz > 0 ? S.L[2] : 0.f;
+#define NB_BLOCK1(c)                                                                   \
+    if ((mask >> c) & 1u)                                                              \
+        pair_block<COUL, ENERGY, VIRIAL, true>(xi##c, yi##c, zi##c, qi##c, ti##c,      \
+                                               NB_MASK(c), fx##c, fy##c, fz##c, xj, tj,  \
+                                               s_lj, kp, sxi, syi, szi, fjx, fjy, fjz,   \
+                                               elj, ec, vir, npair, nblock);
+            NB_FOR8(NB_BLOCK1)
+#undef NB_BLOCK1
         }
+#undef NB_MASK
         fjx = dpp_sum8(fjx);
         fjy = dpp_sum8(fjy);
         fjz = dpp_sum8(fjz);
@@ -222,20 +249,16 @@ __global__ __launch_bounds__(kFwdThreads) void k_nb_fwd(NbDev d, NbKParams kp,
         }
     }
     // i-forces: reduce over the eight j-lanes jj (stride 8) and store the item's partials.
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-#pragma unroll
-        for (int off = 8; off < kWave; off <<= 1) {
-            fx[c] += __shfl_xor(fx[c], off);
-            fy[c] += __shfl_xor(fy[c], off);
-            fz[c] += __shfl_xor(fz[c], off);
-        }
-    }
-    if (jj == 0) {
-        float4* ip = d.ipart + (size_t)item * kScAtoms;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) ip[kClusterSize * c + ii] = make_float4(fx[c], fy[c], fz[c], 0.f);
-    }
+    float4* ip = ipart + (size_t)item * kScAtoms;
+#define NB_IRED(c)                                                                     \
+    for (int off = 8; off < kWave; off <<= 1) {                                        \
+        fx##c += __shfl_xor(fx##c, off);                                               \
+        fy##c += __shfl_xor(fy##c, off);                                               \
+        fz##c += __shfl_xor(fz##c, off);                                               \
+    }                                                                                  \
+    if (jj == 0) ip[kClusterSize * c + ii] = make_float4(fx##c, fy##c, fz##c, 0.f);
+    NB_FOR8(NB_IRED)
+#undef NB_IRED
     if (ENERGY || VIRIAL) {
         double v[8] = {elj_acc, ec_acc, vir_acc[0], vir_acc[1], vir_acc[2], vir_acc[3],
                        vir_acc[4], vir_acc[5]};
@@ -245,11 +268,11 @@ __global__ __launch_bounds__(kFwdThreads) void k_nb_fwd(NbDev d, NbKParams kp,
             for (int off = 1; off < kWave; off <<= 1) v[k] += __shfl_xor(v[k], off);
         }
         if (lane == 0) {
-            double* ep = d.epart + (size_t)item * kEpartStride;
+            // structure of arrays by the item's position in super-cluster order
 #pragma unroll
-            for (int k = 0; k < 8; ++k) ep[k] = v[k];
-            ep[8] = (double)npair;
-            ep[9] = 64.0 * (double)nblock;
+            for (int k = 0; k < 8; ++k) epart[(size_t)k * epart_stride + it.pos] = v[k];
+            epart[(size_t)8 * epart_stride + it.pos] = (double)npair;
+            epart[(size_t)9 * epart_stride + it.pos] = 64.0 * (double)nblock;
         }
     }
 }
@@ -319,25 +342,23 @@ __global__ void k_reduce_f(NbDev d, float* __restrict__ f, int accumulate, int n
 
 constexpr int kRedThreads = 256;
 
-// One block per system: FP64 sums of the per-item energies, virial and pair counts in a
-// fixed order (deterministic).
+// One block per system: FP64 sums of the per-item energies, virial and pair counts, the
+// items of the system being contiguous in super-cluster order; fixed order (deterministic).
 __global__ __launch_bounds__(kRedThreads) void k_reduce_e(NbDev d, double* __restrict__ energy,
                                                           double* __restrict__ virial,
-                                                          uint32_t flags,
-                                                          double* __restrict__ pairs_out) {
+                                                          uint32_t flags) {
     __shared__ double s_v[kRedThreads];
     const int sys = blockIdx.x;
-    const int sc0 = d.sys_sc_start[sys], sc1 = d.sys_sc_start[sys + 1];
-    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int sc = sc0 + threadIdx.x; sc < sc1; sc += blockDim.x) {
-        const int i0 = d.sc_istart[sc], i1 = i0 + d.sc_icount[sc];
-        for (int i = i0; i < i1; ++i) {
-            const double* ep = d.epart + (size_t)i * kEpartStride;
-            for (int k = 0; k < 10; ++k) acc[k] += ep[k];
-        }
+    const int p0 = d.sc_ipos[d.sys_sc_start[sys]], p1 = d.sc_ipos[d.sys_sc_start[sys + 1]];
+    double acc[kEpartStride];
+#pragma unroll
+    for (int k = 0; k < kEpartStride; ++k) acc[k] = 0.0;
+    for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < kEpartStride; ++k) acc[k] += d.epart[(size_t)k * d.epart_stride + i];
     }
-    double out[10];
-    for (int k = 0; k < 10; ++k) {
+    double out[kEpartStride];
+    for (int k = 0; k < kEpartStride; ++k) {
         s_v[threadIdx.x] = acc[k];
         __syncthreads();
         for (int off = kRedThreads / 2; off > 0; off >>= 1) {
@@ -360,10 +381,8 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_e(NbDev d, double* __res
             for (int k = 0; k < 9; ++k)
                 virial[9 * sys + k] = (accum ? virial[9 * sys + k] : 0.0) - 0.5 * v[k];
         }
-        if (pairs_out) {
-            atomicAdd(pairs_out, out[8]);
-            atomicAdd(pairs_out + 1, out[9]);
-        }
+        d.dstat[2 * sys] = out[8];
+        d.dstat[2 * sys + 1] = out[9];
     }
 }
 
@@ -374,7 +393,9 @@ void launch_fwd_t(const NbDev& d, const NbKParams& kp, const float* lj, int n_it
                   hipStream_t s) {
     const size_t lds = sizeof(float4) * (size_t)kp.n_types * kp.n_types;
     hipLaunchKernelGGL((k_nb_fwd<COUL, E, V>), dim3(blocks(n_items, kFwdWaves)),
-                       dim3(kFwdThreads), lds, s, d, kp, lj, n_items);
+                       dim3(kFwdThreads), lds, s, d.items, d.entries, d.excl_rows, d.xq,
+                       d.type_slot, d.cl_bb, d.sc_info, d.sys, lj, d.jpart, d.ipart, d.epart,
+                       d.epart_stride, kp, n_items);
 }
 
 }  // namespace
@@ -417,6 +438,6 @@ hipError_t launch_reduce_energies(const NbDev& d, double* energy, double* virial
                                   uint32_t flags, int n_sys, hipStream_t s) {
     if (n_sys > 0)
         hipLaunchKernelGGL(k_reduce_e, dim3(n_sys), dim3(kRedThreads), 0, s, d, energy, virial,
-                           flags, d.dstat);
+                           flags);
     return hipGetLastError();
 }

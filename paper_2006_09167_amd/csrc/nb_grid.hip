@@ -29,7 +29,8 @@ __global__ void k_fill_d(double* __restrict__ p, int n, double v) {
 __global__ void k_wrap_bin(int n, const float* __restrict__ x,
                            const int32_t* __restrict__ atom_sys, const NbSys* __restrict__ sys,
                            int4* __restrict__ img, float4* __restrict__ wpos,
-                           int32_t* __restrict__ col_count, int32_t* __restrict__ flags) {
+                           int32_t* __restrict__ col_count, int32_t* __restrict__ flags,
+                           int direct_count) {
 #pragma clang fp contract(off)
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= n) return;
@@ -58,7 +59,50 @@ __global__ void k_wrap_bin(int n, const float* __restrict__ x,
     const int col = S.col_base + cx * S.ny + cy;
     img[a] = make_int4(k[0], k[1], k[2], col);
     wpos[a] = make_float4(w[0], w[1], w[2], 0.0f);
-    atomicAdd(&col_count[col], 1);
+    if (direct_count) atomicAdd(&col_count[col], 1);
+}
+
+// Column counts and bucketing with block-local LDS histograms: one global atomic per
+// (block, column) instead of one per atom (columns are few and hot).
+constexpr int kBinThreads = 256;
+constexpr int kBinAtoms = 2048;        // atoms per block
+constexpr int kBinMaxCols = 8192;      // LDS histogram limit (32 KB)
+
+__global__ __launch_bounds__(kBinThreads) void k_count_cols(int n, int n_cols,
+                                                             const int4* __restrict__ img,
+                                                             int32_t* __restrict__ col_count) {
+    extern __shared__ int s_h[];
+    for (int c = threadIdx.x; c < n_cols; c += blockDim.x) s_h[c] = 0;
+    __syncthreads();
+    const int a0 = blockIdx.x * kBinAtoms, a1 = min(n, a0 + kBinAtoms);
+    for (int a = a0 + threadIdx.x; a < a1; a += blockDim.x) atomicAdd(&s_h[img[a].w], 1);
+    __syncthreads();
+    for (int c = threadIdx.x; c < n_cols; c += blockDim.x)
+        if (s_h[c]) atomicAdd(&col_count[c], s_h[c]);
+}
+
+__global__ __launch_bounds__(kBinThreads) void k_col_scatter_lds(
+    int n, int n_cols, const int4* __restrict__ img, const int32_t* __restrict__ col_start,
+    int32_t* __restrict__ col_cursor, int32_t* __restrict__ col_atoms) {
+    extern __shared__ int s_h[];
+    for (int c = threadIdx.x; c < n_cols; c += blockDim.x) s_h[c] = 0;
+    __syncthreads();
+    const int a0 = blockIdx.x * kBinAtoms, a1 = min(n, a0 + kBinAtoms);
+    constexpr int kPer = kBinAtoms / kBinThreads;
+    int rank[kPer], col[kPer];
+    for (int k = 0; k < kPer; ++k) {
+        const int a = a0 + threadIdx.x + k * kBinThreads;
+        col[k] = (a < a1) ? img[a].w : -1;
+        rank[k] = (a < a1) ? atomicAdd(&s_h[col[k]], 1) : 0;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < n_cols; c += blockDim.x)
+        if (s_h[c]) s_h[c] = atomicAdd(&col_cursor[c], s_h[c]);
+    __syncthreads();
+    for (int k = 0; k < kPer; ++k) {
+        const int a = a0 + threadIdx.x + k * kBinThreads;
+        if (a < a1) col_atoms[col_start[col[k]] + s_h[col[k]] + rank[k]] = a;
+    }
 }
 
 // Exclusive scan by one block of kScanThreads threads: each thread scans a contiguous
@@ -268,13 +312,24 @@ hipError_t launch_grid_build(const NbDev& d, const float* x, hipStream_t s) {
     if (d.n_cols > 0)
         hipLaunchKernelGGL(k_fill, dim3(blocks(d.n_cols, 256)), dim3(256), 0, s, d.col_count,
                            d.n_cols, 0);
-    if (n > 0)
+    const bool lds_bins = d.n_cols <= kBinMaxCols;
+    const size_t lds = sizeof(int) * (size_t)d.n_cols;
+    if (n > 0) {
         hipLaunchKernelGGL(k_wrap_bin, dim3(blocks(n, 256)), dim3(256), 0, s, n, x, d.atom_sys,
-                           d.sys, d.img, d.wpos, d.col_count, d.flags);
+                           d.sys, d.img, d.wpos, d.col_count, d.flags, lds_bins ? 0 : 1);
+        if (lds_bins)
+            hipLaunchKernelGGL(k_count_cols, dim3(blocks(n, kBinAtoms)), dim3(kBinThreads), lds, s,
+                               n, d.n_cols, d.img, d.col_count);
+    }
     hipLaunchKernelGGL(k_scan_cols, dim3(1), dim3(kScanThreads), 0, s, d);
     if (n > 0) {
-        hipLaunchKernelGGL(k_col_scatter, dim3(blocks(n, 256)), dim3(256), 0, s, n, d.img,
-                           d.col_start, d.col_cursor, d.col_atoms);
+        if (lds_bins)
+            hipLaunchKernelGGL(k_col_scatter_lds, dim3(blocks(n, kBinAtoms)), dim3(kBinThreads),
+                               lds, s, n, d.n_cols, d.img, d.col_start, d.col_cursor,
+                               d.col_atoms);
+        else
+            hipLaunchKernelGGL(k_col_scatter, dim3(blocks(n, 256)), dim3(256), 0, s, n, d.img,
+                               d.col_start, d.col_cursor, d.col_atoms);
         hipLaunchKernelGGL(k_col_sort, dim3(d.n_cols), dim3(kSortThreads), 0, s, d.col_start,
                            d.col_count, d.col_atoms, d.wpos, d.col_sorted);
     }

@@ -113,7 +113,7 @@ nb_status ensure_device(nb_ctx* c) {
     NbDev& d = c->d;
     NB_HIP(c, dev_alloc(d.flags, kFlagCount));
     NB_HIP(c, dev_alloc(d.totals, 8));
-    NB_HIP(c, dev_alloc(d.dstat, 4));
+    NB_HIP(c, dev_alloc(d.dstat, 2 * c->n_sys));
     NB_HIP(c, dev_alloc(d.sys, c->n_sys));
     NB_HIP(c, dev_alloc(d.sys_sc_start, c->n_sys + 1));
     NB_HIP(c, dev_alloc(d.part_start, c->p.nstprune + 1));
@@ -229,7 +229,7 @@ void nb_destroy(nb_ctx* c) {
         hipStreamSynchronize(c->stream);
     }
     NbDev& d = c->d;
-    void* ptrs[] = {d.type, d.atom_sys, d.excl_ptr, d.excl_idx, d.sys, d.sys_sc_start, d.img,
+    void* ptrs[] = {d.sc_ipos, d.type, d.atom_sys, d.excl_ptr, d.excl_idx, d.sys, d.sys_sc_start, d.img,
                     d.wpos, d.col_count, d.col_start, d.col_sc_start, d.col_cursor, d.col_atoms,
                     d.col_sorted, d.sc_info, d.slot_atom, d.atom_slot, d.type_slot, d.excl_slot,
                     d.cl_bb, d.sc_bb, d.xw, d.xq, d.xp, d.gslot, d.sc_ecount, d.sc_estart,
@@ -368,6 +368,7 @@ nb_status nb_grid_build(nb_ctx* c, const float* x, const float* box) {
         NB_HIP(c, dev_alloc(d.sc_estart, ns + 1));
         NB_HIP(c, dev_alloc(d.sc_istart, ns + 1));
         NB_HIP(c, dev_alloc(d.sc_icount, ns));
+        NB_HIP(c, dev_alloc(d.sc_ipos, ns + 1));
         NB_HIP(c, dev_alloc(d.jseg_count, cl + 8));
         NB_HIP(c, dev_alloc(d.jseg_start, cl + 9));
         NB_HIP(c, dev_alloc(d.jseg_fill, cl + 8));
@@ -459,6 +460,7 @@ nb_status nb_pairlist_build(nb_ctx* c) {
         NB_HIP(c, dev_alloc(d.items, ni));
         NB_HIP(c, dev_alloc(d.ipart, ni * kScAtoms));
         NB_HIP(c, dev_alloc(d.epart, ni * kEpartStride));
+        d.epart_stride = (int32_t)ni;
         NB_HIP(c, dev_alloc(d.glj_part, ni * (size_t)c->p.n_types * c->p.n_types * 2));
         c->a_items = ni;
     }
@@ -520,7 +522,6 @@ nb_status nb_forces(nb_ctx* c, const float* x, const float* q, const float* lj, 
     {
         TimedSection ts(c, NB_T_FORCE_REDUCE);
         NB_HIP(c, launch_gather(d, x, q, d.xq, c->n_slots, c->stream));
-        NB_HIP(c, launch_fill_d(d.dstat, 4, 0.0, c->stream));
     }
     {
         TimedSection ts(c, NB_T_FORCES);
@@ -646,11 +647,16 @@ nb_status nb_get_stats(nb_ctx* c, nb_stats* out) {
     if (!c || !out) return NB_ERR_ARG;
     if (c->has_list) {
         NB_HIP(c, hipSetDevice(c->device));
-        double ds[4];
-        nb_status st = to_host(c, ds, c->d.dstat, 4);
+        std::vector<double> ds(2 * (size_t)c->n_sys);
+        nb_status st = to_host(c, ds.data(), c->d.dstat, ds.size());
         if (st != NB_OK) return st;
-        c->stats.effective_pairs = (int64_t)ds[0];
-        c->stats.computed_pairs = (int64_t)ds[1];
+        double eff = 0, comp = 0;
+        for (int s = 0; s < c->n_sys; ++s) {
+            eff += ds[2 * s];
+            comp += ds[2 * s + 1];
+        }
+        c->stats.effective_pairs = (int64_t)eff;
+        c->stats.computed_pairs = (int64_t)comp;
         // inner masks change with every rolling prune: recount them
         std::vector<NbEntry> ent((size_t)c->n_entries);
         st = to_host(c, ent.data(), c->d.entries, ent.size());

@@ -35,11 +35,13 @@ struct __attribute__((aligned(16))) NbEntry {
 };
 
 // One work item: a chunk of one super-cluster's j-list, processed by one wavefront.
+// pos is the item's rank in super-cluster order (items themselves are grouped by
+// rolling-prune part), so that per-system partial sums are contiguous.
 struct __attribute__((aligned(16))) NbItem {
     int32_t sc;
     int32_t e0;
     int32_t ne;
-    int32_t sys;
+    int32_t pos;
 };
 
 // Per-system grid geometry (device copy).
@@ -152,6 +154,7 @@ struct NbDev {
     int32_t* sc_estart = nullptr;      // [n_sc_max+1]
     int32_t* sc_istart = nullptr;      // [n_sc_max+1] items of a super-cluster (contiguous)
     int32_t* sc_icount = nullptr;      // [n_sc_max]
+    int32_t* sc_ipos = nullptr;        // [n_sc_max+1] item ranks in super-cluster order
     NbEntry* scratch = nullptr;        // [n_sc_max * cap]
     NbEntry* entries = nullptr;        // [entry_cap]
     int32_t* entry_sc = nullptr;       // [entry_cap]
@@ -167,9 +170,10 @@ struct NbDev {
     // force partials
     float4* jpart = nullptr;           // [entry_cap * 8]
     float4* ipart = nullptr;           // [item_cap * 64]
-    double* epart = nullptr;           // [item_cap * kEpartStride]
+    double* epart = nullptr;           // [kEpartStride][epart_stride] by item rank
+    int32_t epart_stride = 0;
     float* glj_part = nullptr;         // [item_cap * T * T * 2]
-    double* dstat = nullptr;           // [4]: effective pair count of the last force call
+    double* dstat = nullptr;           // [n_sys][2]: effective / computed pairs, last call
 };
 
 constexpr int kEpartStride = 10;       // E_LJ, E_C, virial xx yy zz xy xz yz, pairs, pad

@@ -221,6 +221,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_items(NbDev d, int n_sc, 
         const int n = d.sc_ecount[sc_of(k)];
         return (n + w - 1) / w;
     };
+    block_scan(n_sc, [&](int sc) { return (d.sc_ecount[sc] + w - 1) / w; }, d.sc_ipos);
+    __syncthreads();
     const int total = block_scan(n_sc, n_items, tmp);
     __syncthreads();
     for (int k = threadIdx.x; k < n_sc; k += blockDim.x) {
@@ -249,13 +251,13 @@ __global__ __launch_bounds__(kWave) void k_compact(NbDev d, int cap, int w) {
         d.entry_sc[e0 + k] = sc;
     }
     const int i0 = d.sc_istart[sc], ni = d.sc_icount[sc];
-    const int sys = d.sc_info[sc].sys;
+    const int p0 = d.sc_ipos[sc];
     for (int k = threadIdx.x; k < ni; k += blockDim.x) {
         NbItem it;
         it.sc = sc;
         it.e0 = e0 + k * w;
         it.ne = min(w, n - k * w);
-        it.sys = sys;
+        it.pos = p0 + k;
         d.items[i0 + k] = it;
     }
 }
@@ -319,26 +321,35 @@ __global__ __launch_bounds__(kWave) void k_jseg_rank(NbDev d) {
     }
 }
 
-// Rolling prune (Sec. V.E): one wavefront per work item of the part; re-derive the inner
-// mask of every entry from its outer mask and the current coordinates.
-__global__ __launch_bounds__(kWave) void k_prune(NbDev d, int item0, float r2_inner) {
-    const NbItem it = d.items[item0 + blockIdx.x];
-    const int lane = threadIdx.x;
-    const int ii = lane & 7, jj = lane >> 3;
+// Rolling prune (Sec. V.E): one block of four wavefronts per work item of the part; the
+// waves take every fourth entry and re-derive its inner mask from its outer mask and the
+// current coordinates.
+constexpr int kPruneWaves = 4;
+
+__global__ __launch_bounds__(kPruneWaves * kWave) void k_prune(
+    const NbItem* __restrict__ items, NbEntry* __restrict__ entries,
+    const float4* __restrict__ xp, const float4* __restrict__ cl_bb,
+    const NbScInfo* __restrict__ sc_info, const NbSys* __restrict__ sys, int item0,
+    float r2_inner) {
+    const NbItem it = items[item0 + blockIdx.x];
     __shared__ float4 s_ix[kScAtoms];
     __shared__ int s_ni[kClustersPerSc];
-    s_ix[lane] = d.xp[kScAtoms * it.sc + lane];
-    if (lane < kClustersPerSc) s_ni[lane] = (int)d.cl_bb[2 * (kClustersPerSc * it.sc + lane)].w;
+    if (threadIdx.x < kScAtoms) s_ix[threadIdx.x] = xp[kScAtoms * it.sc + threadIdx.x];
+    if (threadIdx.x < kClustersPerSc)
+        s_ni[threadIdx.x] = (int)cl_bb[2 * (kClustersPerSc * it.sc + threadIdx.x)].w;
     __syncthreads();
-    const NbSys S = d.sys[it.sys];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int ii = lane & 7, jj = lane >> 3;
+    const NbSys S = sys[sc_info[it.sc].sys];
     const int ci0 = kClustersPerSc * it.sc;
-    for (int e = it.e0; e < it.e0 + it.ne; ++e) {
-        const NbEntry ent = d.entries[e];
+    for (int e = it.e0 + wave; e < it.e0 + it.ne; e += kPruneWaves) {
+        const NbEntry ent = entries[e];
         const int code = ent.meta & 31u;
         const int sx = shift_x(code), sy = shift_y(code), sz = shift_z(code);
         const int nj = (int)(ent.meta >> 24);
         const uint32_t omask = (ent.meta >> 8) & 0xffu;
-        const float4 xj = d.xp[kClusterSize * ent.cj + jj];
+        const float4 xj = xp[kClusterSize * ent.cj + jj];
         uint32_t imask = 0;
         for (uint32_t bits = omask; bits; bits &= bits - 1) {
             const int c = __builtin_ctz(bits);
@@ -348,7 +359,7 @@ __global__ __launch_bounds__(kWave) void k_prune(NbDev d, int item0, float r2_in
             const uint64_t in_i = __builtin_amdgcn_ballot_w64(r2 < r2_inner) & valid;
             imask |= (in_i ? 1u : 0u) << c;
         }
-        if (lane == 0) d.entries[e].meta = (ent.meta & ~(0xffu << 16)) | (imask << 16);
+        if (lane == 0) entries[e].meta = (ent.meta & ~(0xffu << 16)) | (imask << 16);
     }
 }
 
@@ -396,6 +407,7 @@ hipError_t launch_list_finish(const NbDev& d, int n_sc, int64_t n_entries, int n
 
 hipError_t launch_prune(const NbDev& d, int item0, int n_items, float r2_inner, hipStream_t s) {
     if (n_items > 0)
-        hipLaunchKernelGGL(k_prune, dim3(n_items), dim3(kWave), 0, s, d, item0, r2_inner);
+        hipLaunchKernelGGL(k_prune, dim3(n_items), dim3(kPruneWaves * kWave), 0, s, d.items,
+                           d.entries, d.xp, d.cl_bb, d.sc_info, d.sys, item0, r2_inner);
     return hipGetLastError();
 }
