@@ -72,6 +72,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)",
@@ -107,6 +109,13 @@ def main():
     q = torch.from_numpy(s.q).to(dev)
     lj = torch.from_numpy(s.lj).to(dev)
     box = s.box
+    if args.copy_probe_mb:
+        # a plain copy kernel of known size: reads and writes copy_probe_mb MiB once
+        src = torch.ones(args.copy_probe_mb * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     ctx = Context(n_types=s.n_types, coulomb="ewald", rc=cfg["rc"], rinner=cfg["rinner"],
                   rlist=cfg["rlist"], beta=cfg["beta"], nstlist=nstlist,

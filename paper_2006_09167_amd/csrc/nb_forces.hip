@@ -304,28 +304,50 @@ __device__ inline void neumaier(float& s, float& c, float v) {
     s = t;
 }
 
-// Per slot: compensated sum of its j-partials and its super-cluster's i-partials.
-__global__ void k_reduce_f(NbDev d, float* __restrict__ f, int accumulate, int n_slots) {
-    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= n_slots) return;
-    const int a = d.slot_atom[slot];
-    if (a < 0) return;
-    const int cj = slot / kClusterSize, jj = slot % kClusterSize;
-    const int sc = slot / kScAtoms, loc = slot % kScAtoms;
+// One wavefront per cluster: lane (k0 = l >> 3, jj = l & 7) sums, with compensation, the
+// j-partials k0, k0 + 8, ... of the entries referencing the cluster (contiguous, 1 KB per
+// step), the eight k0-lanes are combined in a fixed butterfly order, and lanes 0..7 add
+// the super-cluster's i-partials and write the atom's force in the caller's order.
+constexpr int kRedWaves = 4;
+__global__ __launch_bounds__(kRedWaves * kWave) void k_reduce_f(
+    const int32_t* __restrict__ slot_atom, const int32_t* __restrict__ jseg_start,
+    const float4* __restrict__ jpart, const int32_t* __restrict__ sc_istart,
+    const int32_t* __restrict__ sc_icount, const float4* __restrict__ ipart,
+    float* __restrict__ f, int accumulate, int n_cl) {
+    const int cj = blockIdx.x * kRedWaves + (int)(threadIdx.x / kWave);
+    if (cj >= n_cl) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int jj = lane & 7, k0 = lane >> 3;
     float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
-    for (int k = d.jseg_start[cj]; k < d.jseg_start[cj + 1]; ++k) {
-        const float4 v = d.jpart[(size_t)k * kClusterSize + jj];
+    const int s0 = jseg_start[cj], s1 = jseg_start[cj + 1];
+    for (int k = s0 + k0; k < s1; k += 8) {
+        const float4 v = jpart[(size_t)k * kClusterSize + jj];
         neumaier(sx, cx, v.x);
         neumaier(sy, cy, v.y);
         neumaier(sz, cz, v.z);
     }
-    const int i0 = d.sc_istart[sc], i1 = i0 + d.sc_icount[sc];
+    for (int off = 8; off < kWave; off <<= 1) {   // combine (sum, compensation) pairs
+        const float px = __shfl_xor(sx, off), py = __shfl_xor(sy, off), pz = __shfl_xor(sz, off);
+        const float qx = __shfl_xor(cx, off), qy = __shfl_xor(cy, off), qz = __shfl_xor(cz, off);
+        neumaier(sx, cx, px);
+        neumaier(sy, cy, py);
+        neumaier(sz, cz, pz);
+        cx += qx;
+        cy += qy;
+        cz += qz;
+    }
+    if (k0 != 0) return;
+    const int slot = cj * kClusterSize + jj;
+    const int a = slot_atom[slot];
+    const int sc = cj >> 3, loc = slot & (kScAtoms - 1);
+    const int i0 = sc_istart[sc], i1 = i0 + sc_icount[sc];
     for (int i = i0; i < i1; ++i) {
-        const float4 v = d.ipart[(size_t)i * kScAtoms + loc];
+        const float4 v = ipart[(size_t)i * kScAtoms + loc];
         neumaier(sx, cx, v.x);
         neumaier(sy, cy, v.y);
         neumaier(sz, cz, v.z);
     }
+    if (a < 0) return;
     float rx = sx + cx, ry = sy + cy, rz = sz + cz;
     if (accumulate) {
         rx += f[3 * a];
@@ -347,7 +369,6 @@ constexpr int kRedThreads = 256;
 __global__ __launch_bounds__(kRedThreads) void k_reduce_e(NbDev d, double* __restrict__ energy,
                                                           double* __restrict__ virial,
                                                           uint32_t flags) {
-    __shared__ double s_v[kRedThreads];
     const int sys = blockIdx.x;
     const int p0 = d.sc_ipos[d.sys_sc_start[sys]], p1 = d.sc_ipos[d.sys_sc_start[sys + 1]];
     double acc[kEpartStride];
@@ -357,16 +378,21 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_e(NbDev d, double* __res
 #pragma unroll
         for (int k = 0; k < kEpartStride; ++k) acc[k] += d.epart[(size_t)k * d.epart_stride + i];
     }
+    // fixed-order butterfly inside each wavefront, then the wavefronts in order
+    __shared__ double s_w[kRedThreads / kWave][kEpartStride];
+#pragma unroll
+    for (int k = 0; k < kEpartStride; ++k) {
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) acc[k] += __shfl_xor(acc[k], off);
+    }
+    const int wv = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0)
+        for (int k = 0; k < kEpartStride; ++k) s_w[wv][k] = acc[k];
+    __syncthreads();
     double out[kEpartStride];
     for (int k = 0; k < kEpartStride; ++k) {
-        s_v[threadIdx.x] = acc[k];
-        __syncthreads();
-        for (int off = kRedThreads / 2; off > 0; off >>= 1) {
-            if (threadIdx.x < off) s_v[threadIdx.x] += s_v[threadIdx.x + off];
-            __syncthreads();
-        }
-        out[k] = s_v[0];
-        __syncthreads();
+        out[k] = 0.0;
+        for (int w = 0; w < kRedThreads / kWave; ++w) out[k] += s_w[w][k];
     }
     if (threadIdx.x == 0) {
         const bool accum = flags & NB_F_ACCUMULATE;
@@ -428,9 +454,11 @@ hipError_t launch_forces(const NbDev& d, const NbKParams& kp, int coulomb, uint3
 
 hipError_t launch_reduce_forces(const NbDev& d, float* f, bool accumulate, int n_slots,
                                 hipStream_t s) {
-    if (n_slots > 0)
-        hipLaunchKernelGGL(k_reduce_f, dim3(blocks(n_slots, 256)), dim3(256), 0, s, d, f,
-                           accumulate ? 1 : 0, n_slots);
+    const int n_cl = n_slots / kClusterSize;
+    if (n_cl > 0)
+        hipLaunchKernelGGL(k_reduce_f, dim3(blocks(n_cl, kRedWaves)), dim3(kRedWaves * kWave), 0,
+                           s, d.slot_atom, d.jseg_start, d.jpart, d.sc_istart, d.sc_icount,
+                           d.ipart, f, accumulate ? 1 : 0, n_cl);
     return hipGetLastError();
 }
 

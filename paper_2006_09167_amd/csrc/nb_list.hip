@@ -343,13 +343,21 @@ __global__ __launch_bounds__(kPruneWaves * kWave) void k_prune(
     const int ii = lane & 7, jj = lane >> 3;
     const NbSys S = sys[sc_info[it.sc].sys];
     const int ci0 = kClustersPerSc * it.sc;
-    for (int e = it.e0 + wave; e < it.e0 + it.ne; e += kPruneWaves) {
-        const NbEntry ent = entries[e];
+    const int e_end = it.e0 + it.ne;
+    int e = it.e0 + wave;
+    NbEntry nxt = entries[min(e, e_end - 1)];
+    float4 xj_n = xp[kClusterSize * nxt.cj + jj];
+    for (; e < e_end; e += kPruneWaves) {
+        const NbEntry ent = nxt;
+        const float4 xj = xj_n;
+        if (e + kPruneWaves < e_end) {       // prefetch this wave's next entry
+            nxt = entries[e + kPruneWaves];
+            xj_n = xp[kClusterSize * nxt.cj + jj];
+        }
         const int code = ent.meta & 31u;
         const int sx = shift_x(code), sy = shift_y(code), sz = shift_z(code);
         const int nj = (int)(ent.meta >> 24);
         const uint32_t omask = (ent.meta >> 8) & 0xffu;
-        const float4 xj = xp[kClusterSize * ent.cj + jj];
         uint32_t imask = 0;
         for (uint32_t bits = omask; bits; bits &= bits - 1) {
             const int c = __builtin_ctz(bits);
