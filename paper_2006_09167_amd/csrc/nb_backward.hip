@@ -130,8 +130,12 @@ __device__ __forceinline__ void bwd_block(
         g6 = on ? g6 : 0.f;
         const int key = ti + tj;
         if (PRIV) {
-            atomicAdd(&s_hist[(2 * key) * kWave + lane], g6);
-            atomicAdd(&s_hist[(2 * key + 1) * kWave + lane], g12);
+            // lane-private slots: plain read-modify-write (no LDS atomics needed)
+            float2* h = reinterpret_cast<float2*>(s_hist) + key * kWave + lane;
+            float2 hv = *h;
+            hv.x += g6;
+            hv.y += g12;
+            *h = hv;
         } else {
             atomicAdd(&s_hist[2 * key], g6);
             atomicAdd(&s_hist[2 * key + 1], g12);
@@ -285,7 +289,9 @@ __global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
         for (int k = lane; k < 2 * TT; k += kWave) {
             float v = 0.f;
             if (PRIV) {
-                for (int l = 0; l < kWave; ++l) v += s_hist[k * kWave + l];
+                // slot (key, lane) holds (g6, g12) at float offset 2 (key * 64 + lane) + c
+                const int key = k >> 1, c = k & 1;
+                for (int l = 0; l < kWave; ++l) v += s_hist[2 * (key * kWave + l) + c];
             } else {
                 v = s_hist[k];
             }
@@ -309,30 +315,50 @@ __device__ inline void neumaier(float& s, float& c, float v) {
     s = t;
 }
 
-__global__ void k_reduce_bwd(NbDev d, float* __restrict__ gx, float* __restrict__ gq,
-                             int accumulate, int n_slots) {
-    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= n_slots) return;
-    const int a = d.slot_atom[slot];
-    if (a < 0) return;
-    const int cj = slot / kClusterSize, jj = slot % kClusterSize;
-    const int sc = slot / kScAtoms, loc = slot % kScAtoms;
+// One wavefront per cluster, as the force reduction: lanes (k0, jj) sum the j-partials
+// k0, k0 + 8, ... with compensation, a fixed butterfly combines the k0-lanes, and lanes
+// 0..7 add the i-partials and write dL/dx and dL/dq in the caller's atom order.
+constexpr int kRedWaves = 4;
+__global__ __launch_bounds__(kRedWaves * kWave) void k_reduce_bwd(
+    const int32_t* __restrict__ slot_atom, const int32_t* __restrict__ jseg_start,
+    const float4* __restrict__ jpart, const int32_t* __restrict__ sc_istart,
+    const int32_t* __restrict__ sc_icount, const float4* __restrict__ ipart,
+    float* __restrict__ gx, float* __restrict__ gq, int accumulate, int n_cl) {
+    const int cj = blockIdx.x * kRedWaves + (int)(threadIdx.x / kWave);
+    if (cj >= n_cl) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int jj = lane & 7, k0 = lane >> 3;
     float s[4] = {0, 0, 0, 0}, cmp[4] = {0, 0, 0, 0};
-    for (int k = d.jseg_start[cj]; k < d.jseg_start[cj + 1]; ++k) {
-        const float4 v = d.jpart[(size_t)k * kClusterSize + jj];
+    const int s0 = jseg_start[cj], s1 = jseg_start[cj + 1];
+#pragma unroll 4
+    for (int k = s0 + k0; k < s1; k += 8) {
+        const float4 v = jpart[(size_t)k * kClusterSize + jj];
         neumaier(s[0], cmp[0], v.x);
         neumaier(s[1], cmp[1], v.y);
         neumaier(s[2], cmp[2], v.z);
         neumaier(s[3], cmp[3], v.w);
     }
-    const int i0 = d.sc_istart[sc], i1 = i0 + d.sc_icount[sc];
+    for (int off = 8; off < kWave; off <<= 1) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float ps = __shfl_xor(s[q], off), pc = __shfl_xor(cmp[q], off);
+            neumaier(s[q], cmp[q], ps);
+            cmp[q] += pc;
+        }
+    }
+    if (k0 != 0) return;
+    const int slot = cj * kClusterSize + jj;
+    const int a = slot_atom[slot];
+    const int sc = cj >> 3, loc = slot & (kScAtoms - 1);
+    const int i0 = sc_istart[sc], i1 = i0 + sc_icount[sc];
     for (int i = i0; i < i1; ++i) {
-        const float4 v = d.ipart[(size_t)i * kScAtoms + loc];
+        const float4 v = ipart[(size_t)i * kScAtoms + loc];
         neumaier(s[0], cmp[0], v.x);
         neumaier(s[1], cmp[1], v.y);
         neumaier(s[2], cmp[2], v.z);
         neumaier(s[3], cmp[3], v.w);
     }
+    if (a < 0) return;
     if (gx) {
         for (int k = 0; k < 3; ++k) {
             const float r = s[k] + cmp[k];
@@ -416,9 +442,11 @@ hipError_t launch_backward(const NbDev& d, const NbKParams& kp, int coulomb, con
 hipError_t launch_reduce_backward(const NbDev& d, float* grad_x, float* grad_q, double* grad_lj,
                                   bool accumulate, int n_slots, int n_types, int n_items,
                                   hipStream_t s) {
-    if (n_slots > 0 && (grad_x || grad_q))
-        hipLaunchKernelGGL(k_reduce_bwd, dim3(blocks(n_slots, 256)), dim3(256), 0, s, d, grad_x,
-                           grad_q, accumulate ? 1 : 0, n_slots);
+    const int n_cl = n_slots / kClusterSize;
+    if (n_cl > 0 && (grad_x || grad_q))
+        hipLaunchKernelGGL(k_reduce_bwd, dim3(blocks(n_cl, kRedWaves)), dim3(kRedWaves * kWave),
+                           0, s, d.slot_atom, d.jseg_start, d.jpart, d.sc_istart, d.sc_icount,
+                           d.ipart, grad_x, grad_q, accumulate ? 1 : 0, n_cl);
     if (grad_lj) {
         const int nk = 2 * n_types * n_types;
         hipLaunchKernelGGL(k_reduce_glj, dim3(nk), dim3(kGljThreads), 0, s, d, grad_lj,

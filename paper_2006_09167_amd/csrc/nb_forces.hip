@@ -130,7 +130,7 @@ __device__ __forceinline__ void pair_block(float xi, float yi, float zi, float q
 #define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
 template <int COUL, bool ENERGY, bool VIRIAL>
-__global__ __launch_bounds__(kFwdThreads) void k_nb_fwd(
+__global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIRIAL ? 3 : 4))) void k_nb_fwd(
     const NbItem* __restrict__ items, const NbEntry* __restrict__ entries,
     const uint64_t* __restrict__ excl_rows, const float4* __restrict__ xq,
     const int32_t* __restrict__ type_slot, const float4* __restrict__ cl_bb,
@@ -320,6 +320,7 @@ __global__ __launch_bounds__(kRedWaves * kWave) void k_reduce_f(
     const int jj = lane & 7, k0 = lane >> 3;
     float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
     const int s0 = jseg_start[cj], s1 = jseg_start[cj + 1];
+#pragma unroll 4
     for (int k = s0 + k0; k < s1; k += 8) {
         const float4 v = jpart[(size_t)k * kClusterSize + jj];
         neumaier(sx, cx, v.x);
@@ -362,7 +363,7 @@ __global__ __launch_bounds__(kRedWaves * kWave) void k_reduce_f(
 // Zero forces of atoms that no slot covers (only possible for an empty grid) is not
 // needed: every atom has a slot after a grid build.
 
-constexpr int kRedThreads = 256;
+constexpr int kRedThreads = 1024;
 
 // One block per system: FP64 sums of the per-item energies, virial and pair counts, the
 // items of the system being contiguous in super-cluster order; fixed order (deterministic).
@@ -374,6 +375,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_e(NbDev d, double* __res
     double acc[kEpartStride];
 #pragma unroll
     for (int k = 0; k < kEpartStride; ++k) acc[k] = 0.0;
+#pragma unroll 4
     for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
 #pragma unroll
         for (int k = 0; k < kEpartStride; ++k) acc[k] += d.epart[(size_t)k * d.epart_stride + i];

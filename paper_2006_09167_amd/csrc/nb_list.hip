@@ -326,23 +326,27 @@ __global__ __launch_bounds__(kWave) void k_jseg_rank(NbDev d) {
 // current coordinates.
 constexpr int kPruneWaves = 4;
 
+#define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
+
 __global__ __launch_bounds__(kPruneWaves * kWave) void k_prune(
     const NbItem* __restrict__ items, NbEntry* __restrict__ entries,
     const float4* __restrict__ xp, const float4* __restrict__ cl_bb,
     const NbScInfo* __restrict__ sc_info, const NbSys* __restrict__ sys, int item0,
     float r2_inner) {
     const NbItem it = items[item0 + blockIdx.x];
-    __shared__ float4 s_ix[kScAtoms];
-    __shared__ int s_ni[kClustersPerSc];
-    if (threadIdx.x < kScAtoms) s_ix[threadIdx.x] = xp[kScAtoms * it.sc + threadIdx.x];
-    if (threadIdx.x < kClustersPerSc)
-        s_ni[threadIdx.x] = (int)cl_bb[2 * (kClustersPerSc * it.sc + threadIdx.x)].w;
-    __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x & (kWave - 1);
     const int ii = lane & 7, jj = lane >> 3;
     const NbSys S = sys[sc_info[it.sc].sys];
     const int ci0 = kClustersPerSc * it.sc;
+    // the eight i-clusters' coordinates and valid-lane masks, in registers
+#define NB_PI(c)                                                                       \
+    const float4 xi##c = xp[kScAtoms * it.sc + kClusterSize * c + ii];                 \
+    const int ni##c = (int)cl_bb[2 * (ci0 + c)].w;                                     \
+    const uint64_t iv##c =                                                             \
+        ((ni##c >= 8) ? 0xffull : ((1ull << ni##c) - 1ull)) * 0x0101010101010101ull;
+    NB_FOR8(NB_PI)
+#undef NB_PI
     const int e_end = it.e0 + it.ne;
     int e = it.e0 + wave;
     NbEntry nxt = entries[min(e, e_end - 1)];
@@ -358,15 +362,17 @@ __global__ __launch_bounds__(kPruneWaves * kWave) void k_prune(
         const int sx = shift_x(code), sy = shift_y(code), sz = shift_z(code);
         const int nj = (int)(ent.meta >> 24);
         const uint32_t omask = (ent.meta >> 8) & 0xffu;
+        const uint64_t jv = (nj >= 8) ? ~0ull : ((1ull << (8 * nj)) - 1ull);
+        const int dc = (code == kShiftZero) ? ent.cj - ci0 : -1;
         uint32_t imask = 0;
-        for (uint32_t bits = omask; bits; bits &= bits - 1) {
-            const int c = __builtin_ctz(bits);
-            const float r2 = list_r2(s_ix[kClusterSize * c + ii], xj, sx, sy, sz, S);
-            const uint64_t valid =
-                pair_valid_mask(s_ni[c], nj, ent.cj == ci0 + c && code == kShiftZero);
-            const uint64_t in_i = __builtin_amdgcn_ballot_w64(r2 < r2_inner) & valid;
-            imask |= (in_i ? 1u : 0u) << c;
+#define NB_PB(c)                                                                       \
+        if ((omask >> c) & 1u) {                                                       \
+            const float r2 = list_r2(xi##c, xj, sx, sy, sz, S);                        \
+            const uint64_t m = iv##c & jv & (dc == c ? 0x7f3f1f0f07030100ull : ~0ull); \
+            if (__builtin_amdgcn_ballot_w64(r2 < r2_inner) & m) imask |= 1u << c;      \
         }
+        NB_FOR8(NB_PB)
+#undef NB_PB
         if (lane == 0) entries[e].meta = (ent.meta & ~(0xffu << 16)) | (imask << 16);
     }
 }
