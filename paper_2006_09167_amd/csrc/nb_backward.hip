@@ -17,6 +17,8 @@
 #include "nb_erfc_coeffs.h"
 #include "nb_internal.h"
 
+hipError_t launch_glj_chunks(const NbDev& d, int n_keys, int n_items, hipStream_t s);
+
 namespace {
 
 constexpr int kBwdWaves = 2;
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
     const float4* __restrict__ cl_bb, const NbScInfo* __restrict__ sc_info,
     const NbSys* __restrict__ sys, const float* __restrict__ lj,
     const double* __restrict__ grad_e, float4* __restrict__ jpart, float4* __restrict__ ipart,
-    float* __restrict__ glj_part, NbKParams kp, int n_items) {
+    float* __restrict__ glj_part, int glj_stride, NbKParams kp, int n_items) {
     extern __shared__ float4 s_dyn[];
     const int T = kp.n_types;
     const int TT = T * T;
@@ -285,7 +287,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
 #undef NB_IRED
     if (LJGRAD) {
         __builtin_amdgcn_wave_barrier();
-        float* out = glj_part + (size_t)item * 2 * TT;
+        // column it.pos of the [key][rank] table partials
         for (int k = lane; k < 2 * TT; k += kWave) {
             float v = 0.f;
             if (PRIV) {
@@ -295,7 +297,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
             } else {
                 v = s_hist[k];
             }
-            out[k] = v;
+            glj_part[(size_t)k * glj_stride + it.pos] = v;
         }
     }
 }
@@ -371,35 +373,24 @@ __global__ __launch_bounds__(kRedWaves * kWave) void k_reduce_bwd(
     }
 }
 
-// Table gradient: one block per (type pair, c6/c12) sums the items in a fixed order in
-// FP64.  The table is symmetric, so the derivative with respect to the shared value of
+// Table gradient, stage 2: one thread per (type pair, c6/c12) adds the chunk partials in
+// order.  The table is symmetric, so the derivative with respect to the shared value of
 // [t1][t2] and [t2][t1] is split evenly between the two entries (independent of which
 // atom of a pair the kernel treats as i).
-constexpr int kGljThreads = 256;
-__global__ __launch_bounds__(kGljThreads) void k_reduce_glj(NbDev d, double* __restrict__ out,
-                                                            int n_types, int n_items,
-                                                            int accumulate) {
-    __shared__ double s_v[kGljThreads];
+__global__ void k_glj_final(NbDev d, double* __restrict__ out, int n_types, int n_chunks,
+                            int accumulate) {
     const int n_keys = 2 * n_types * n_types;
-    const int k = blockIdx.x;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_keys) return;
     const int c = k & 1, t1 = (k >> 1) / n_types, t2 = (k >> 1) % n_types;
     const int kt = 2 * (t2 * n_types + t1) + c;
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n_items; i += blockDim.x) {
-        s += (double)d.glj_part[(size_t)i * n_keys + k];
-        if (kt != k) s += (double)d.glj_part[(size_t)i * n_keys + kt];
+    double sk = 0.0, st = 0.0;
+    for (int q = 0; q < n_chunks; ++q) {
+        sk += d.cpart[(size_t)q * kChunkVals + k];
+        st += d.cpart[(size_t)q * kChunkVals + kt];
     }
-    s_v[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = kGljThreads / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) s_v[threadIdx.x] += s_v[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        double r = s_v[0];
-        if (kt != k) r *= 0.5;
-        out[k] = accumulate ? out[k] + r : r;
-    }
+    const double r = (kt != k) ? 0.5 * (sk + st) : sk;
+    out[k] = accumulate ? out[k] + r : r;
 }
 
 inline int blocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
@@ -413,7 +404,7 @@ void launch_bwd_t(const NbDev& d, const NbKParams& kp, const float* lj, const do
     hipLaunchKernelGGL((k_nb_bwd<COUL, LJG, PRIV>), dim3(blocks(n_items, kBwdWaves)),
                        dim3(kBwdThreads), lds, s, d.items, d.entries, d.excl_rows, d.xq, d.gslot,
                        d.type_slot, d.cl_bb, d.sc_info, d.sys, lj, ge, d.jpart, d.ipart,
-                       d.glj_part, kp, n_items);
+                       d.glj_part, d.epart_stride, kp, n_items);
 }
 
 template <int COUL>
@@ -449,8 +440,10 @@ hipError_t launch_reduce_backward(const NbDev& d, float* grad_x, float* grad_q, 
                            d.ipart, grad_x, grad_q, accumulate ? 1 : 0, n_cl);
     if (grad_lj) {
         const int nk = 2 * n_types * n_types;
-        hipLaunchKernelGGL(k_reduce_glj, dim3(nk), dim3(kGljThreads), 0, s, d, grad_lj,
-                           n_types, n_items, accumulate ? 1 : 0);
+        hipError_t e = launch_glj_chunks(d, nk, n_items, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_glj_final, dim3(blocks(nk, 64)), dim3(64), 0, s, d, grad_lj,
+                           n_types, blocks(n_items, kChunkItems), accumulate ? 1 : 0);
     }
     return hipGetLastError();
 }

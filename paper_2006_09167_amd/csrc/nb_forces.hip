@@ -320,7 +320,7 @@ __global__ __launch_bounds__(kRedWaves * kWave) void k_reduce_f(
     const int jj = lane & 7, k0 = lane >> 3;
     float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
     const int s0 = jseg_start[cj], s1 = jseg_start[cj + 1];
-#pragma unroll 4
+#pragma unroll 8
     for (int k = s0 + k0; k < s1; k += 8) {
         const float4 v = jpart[(size_t)k * kClusterSize + jj];
         neumaier(sx, cx, v.x);
@@ -363,40 +363,54 @@ __global__ __launch_bounds__(kRedWaves * kWave) void k_reduce_f(
 // Zero forces of atoms that no slot covers (only possible for an empty grid) is not
 // needed: every atom has a slot after a grid build.
 
-constexpr int kRedThreads = 1024;
+constexpr int kRedThreads = 256;
 
-// One block per system: FP64 sums of the per-item energies, virial and pair counts, the
-// items of the system being contiguous in super-cluster order; fixed order (deterministic).
-__global__ __launch_bounds__(kRedThreads) void k_reduce_e(NbDev d, double* __restrict__ energy,
-                                                          double* __restrict__ virial,
-                                                          uint32_t flags) {
+// Deterministic two-stage reductions of per-item partial sums (structure of arrays, K
+// values, one column per item rank).  Stage 1: one block per chunk of up to kChunkItems
+// consecutive ranks of one segment sums each value (fixed butterfly and wave order) into
+// the chunk partial.  Stage 2: one block per segment adds its chunks in order.
+template <typename T>
+__device__ void chunk_sums(const T* __restrict__ vals, int stride, int K, int p0, int p1,
+                           double* __restrict__ out) {
+    __shared__ double s_w[kRedThreads / kWave];
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    for (int k = 0; k < K; ++k) {
+        double acc = 0.0;
+        for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x)
+            acc += (double)vals[(size_t)k * stride + i];
+        for (int off = 1; off < kWave; off <<= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) s_w[wv] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < kRedThreads / kWave; ++w) t += s_w[w];
+            out[k] = t;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_energy_chunks(NbDev d) {
+    const int4 ch = d.chunks[blockIdx.x];
+    chunk_sums(d.epart, d.epart_stride, kEpartStride, ch.y, ch.z,
+               d.cpart + (size_t)blockIdx.x * kChunkVals);
+}
+
+// One block per system: chunk partials in order, then energies, virial and pair counts.
+__global__ void k_energy_final(NbDev d, double* __restrict__ energy, double* __restrict__ virial,
+                               uint32_t flags) {
     const int sys = blockIdx.x;
-    const int p0 = d.sc_ipos[d.sys_sc_start[sys]], p1 = d.sc_ipos[d.sys_sc_start[sys + 1]];
-    double acc[kEpartStride];
-#pragma unroll
-    for (int k = 0; k < kEpartStride; ++k) acc[k] = 0.0;
-#pragma unroll 4
-    for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
-#pragma unroll
-        for (int k = 0; k < kEpartStride; ++k) acc[k] += d.epart[(size_t)k * d.epart_stride + i];
+    const int c0 = d.sys_chunk_start[sys], c1 = d.sys_chunk_start[sys + 1];
+    __shared__ double s_out[kEpartStride];
+    const int k = threadIdx.x;
+    if (k < kEpartStride) {
+        double t = 0.0;
+        for (int c = c0; c < c1; ++c) t += d.cpart[(size_t)c * kChunkVals + k];
+        s_out[k] = t;
     }
-    // fixed-order butterfly inside each wavefront, then the wavefronts in order
-    __shared__ double s_w[kRedThreads / kWave][kEpartStride];
-#pragma unroll
-    for (int k = 0; k < kEpartStride; ++k) {
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) acc[k] += __shfl_xor(acc[k], off);
-    }
-    const int wv = threadIdx.x / kWave;
-    if ((threadIdx.x & (kWave - 1)) == 0)
-        for (int k = 0; k < kEpartStride; ++k) s_w[wv][k] = acc[k];
     __syncthreads();
-    double out[kEpartStride];
-    for (int k = 0; k < kEpartStride; ++k) {
-        out[k] = 0.0;
-        for (int w = 0; w < kRedThreads / kWave; ++w) out[k] += s_w[w][k];
-    }
     if (threadIdx.x == 0) {
+        const double* out = s_out;
         const bool accum = flags & NB_F_ACCUMULATE;
         if ((flags & NB_F_ENERGY) && energy) {
             energy[2 * sys] = (accum ? energy[2 * sys] : 0.0) + out[0];
@@ -406,8 +420,8 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_e(NbDev d, double* __res
             // Xi = -1/2 sum d (x) f, symmetric: xx yy zz xy xz yz
             const double v[9] = {out[2], out[5], out[6], out[5], out[3], out[7],
                                  out[6], out[7], out[4]};
-            for (int k = 0; k < 9; ++k)
-                virial[9 * sys + k] = (accum ? virial[9 * sys + k] : 0.0) - 0.5 * v[k];
+            for (int q = 0; q < 9; ++q)
+                virial[9 * sys + q] = (accum ? virial[9 * sys + q] : 0.0) - 0.5 * v[q];
         }
         d.dstat[2 * sys] = out[8];
         d.dstat[2 * sys + 1] = out[9];
@@ -466,8 +480,27 @@ hipError_t launch_reduce_forces(const NbDev& d, float* f, bool accumulate, int n
 
 hipError_t launch_reduce_energies(const NbDev& d, double* energy, double* virial,
                                   uint32_t flags, int n_sys, hipStream_t s) {
+    if (d.n_chunks > 0)
+        hipLaunchKernelGGL(k_energy_chunks, dim3(d.n_chunks), dim3(kRedThreads), 0, s, d);
     if (n_sys > 0)
-        hipLaunchKernelGGL(k_reduce_e, dim3(n_sys), dim3(kRedThreads), 0, s, d, energy, virial,
+        hipLaunchKernelGGL(k_energy_final, dim3(n_sys), dim3(kWave), 0, s, d, energy, virial,
                            flags);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_value_chunks(const T* __restrict__ vals,
+                                                              int stride, int K, int n,
+                                                              double* __restrict__ cpart) {
+    const int p0 = blockIdx.x * kChunkItems, p1 = min(n, p0 + kChunkItems);
+    chunk_sums(vals, stride, K, p0, p1, cpart + (size_t)blockIdx.x * kChunkVals);
+}
+
+// Stage 1 for the table gradient partials (float, one segment of n item ranks).
+hipError_t launch_glj_chunks(const NbDev& d, int n_keys, int n_items, hipStream_t s) {
+    const int nc = blocks(n_items, kChunkItems);
+    if (nc > 0)
+        hipLaunchKernelGGL((k_value_chunks<float>), dim3(nc), dim3(kRedThreads), 0, s,
+                           d.glj_part, d.epart_stride, n_keys, n_items, d.cpart);
     return hipGetLastError();
 }

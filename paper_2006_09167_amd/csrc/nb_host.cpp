@@ -229,7 +229,7 @@ void nb_destroy(nb_ctx* c) {
         hipStreamSynchronize(c->stream);
     }
     NbDev& d = c->d;
-    void* ptrs[] = {d.sc_ipos, d.type, d.atom_sys, d.excl_ptr, d.excl_idx, d.sys, d.sys_sc_start, d.img,
+    void* ptrs[] = {d.chunks, d.sys_chunk_start, d.cpart, d.sc_ipos, d.type, d.atom_sys, d.excl_ptr, d.excl_idx, d.sys, d.sys_sc_start, d.img,
                     d.wpos, d.col_count, d.col_start, d.col_sc_start, d.col_cursor, d.col_atoms,
                     d.col_sorted, d.sc_info, d.slot_atom, d.atom_slot, d.type_slot, d.excl_slot,
                     d.cl_bb, d.sc_bb, d.xw, d.xq, d.xp, d.gslot, d.sc_ecount, d.sc_estart,
@@ -461,7 +461,7 @@ nb_status nb_pairlist_build(nb_ctx* c) {
         NB_HIP(c, dev_alloc(d.ipart, ni * kScAtoms));
         NB_HIP(c, dev_alloc(d.epart, ni * kEpartStride));
         d.epart_stride = (int32_t)ni;
-        NB_HIP(c, dev_alloc(d.glj_part, ni * (size_t)c->p.n_types * c->p.n_types * 2));
+        NB_HIP(c, dev_alloc(d.glj_part, ni * (size_t)c->p.n_types * c->p.n_types * 2));  // [key][rank]
         c->a_items = ni;
     }
     NB_HIP(c, launch_make_items(d, n_sc, c->cap, W, c->p.nstprune, c->stream));
@@ -477,6 +477,34 @@ nb_status nb_pairlist_build(nb_ctx* c) {
     if (st != NB_OK) return st;
     st = to_host(c, flags, d.flags, kFlagCount);
     if (st != NB_OK) return st;
+    // Chunks of the two-stage per-system reductions: item ranks of system s are the range
+    // [sc_ipos[sys_sc_start[s]], sc_ipos[sys_sc_start[s+1]]).
+    {
+        std::vector<int32_t> sss(c->n_sys + 1), ipos((size_t)n_sc + 1);
+        st = to_host(c, sss.data(), d.sys_sc_start, sss.size());
+        if (st != NB_OK) return st;
+        st = to_host(c, ipos.data(), d.sc_ipos, ipos.size());
+        if (st != NB_OK) return st;
+        std::vector<int4> ch;
+        std::vector<int32_t> start(c->n_sys + 1, 0);
+        for (int s = 0; s < c->n_sys; ++s) {
+            start[s] = (int32_t)ch.size();
+            const int p0 = ipos[sss[s]], p1 = ipos[sss[s + 1]];
+            for (int p = p0; p < p1; p += kChunkItems)
+                ch.push_back(make_int4(s, p, std::min(p1, p + kChunkItems), 0));
+        }
+        start[c->n_sys] = (int32_t)ch.size();
+        const size_t nglj = (size_t)(c->n_items + kChunkItems - 1) / kChunkItems;
+        const size_t ncap = std::max(ch.size(), nglj) + 1;
+        NB_HIP(c, dev_alloc(d.chunks, ch.size() + 1));
+        NB_HIP(c, dev_alloc(d.sys_chunk_start, c->n_sys + 1));
+        NB_HIP(c, dev_alloc(d.cpart, ncap * kChunkVals));
+        if (!ch.empty())
+            NB_HIP(c, hipMemcpy(d.chunks, ch.data(), ch.size() * sizeof(int4), hipMemcpyHostToDevice));
+        NB_HIP(c, hipMemcpy(d.sys_chunk_start, start.data(), start.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice));
+        d.n_chunks = (int32_t)ch.size();
+    }
     c->stats.n_slots = c->n_slots;
     c->stats.n_superclusters = n_sc;
     c->stats.n_clusters = c->n_cl;

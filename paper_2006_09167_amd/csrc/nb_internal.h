@@ -172,8 +172,14 @@ struct NbDev {
     float4* ipart = nullptr;           // [item_cap * 64]
     double* epart = nullptr;           // [kEpartStride][epart_stride] by item rank
     int32_t epart_stride = 0;
-    float* glj_part = nullptr;         // [item_cap * T * T * 2]
+    float* glj_part = nullptr;         // [T * T * 2][epart_stride] by item rank
+    int4* chunks = nullptr;            // [n_chunks] (system, first rank, end rank, 0)
+    int32_t* sys_chunk_start = nullptr;// [n_sys+1]
+    double* cpart = nullptr;           // [n_chunks][kChunkVals] chunk partial sums
+    int32_t n_chunks = 0;
     double* dstat = nullptr;           // [n_sys][2]: effective / computed pairs, last call
 };
 
-constexpr int kEpartStride = 10;       // E_LJ, E_C, virial xx yy zz xy xz yz, pairs, pad
+constexpr int kEpartStride = 10;       // E_LJ, E_C, virial xx yy zz xy xz yz, pairs, slots
+constexpr int kChunkItems = 1024;      // items per chunk of the two-stage reductions
+constexpr int kChunkVals = 2 * kMaxTypes * kMaxTypes;  // values per chunk partial (max)

@@ -321,10 +321,10 @@ __global__ __launch_bounds__(kWave) void k_jseg_rank(NbDev d) {
     }
 }
 
-// Rolling prune (Sec. V.E): one block of four wavefronts per work item of the part; the
-// waves take every fourth entry and re-derive its inner mask from its outer mask and the
+// Rolling prune (Sec. V.E): one block of eight wavefronts per work item of the part; the
+// waves take every eighth entry and re-derive its inner mask from its outer mask and the
 // current coordinates.
-constexpr int kPruneWaves = 4;
+constexpr int kPruneWaves = 8;
 
 #define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
