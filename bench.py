@@ -140,15 +140,20 @@ def main():
             have_bwd = False
         torch.cuda.synchronize()
 
-    def step(t, bwd=False):
+    def step(t, bwd=False, fused=True):
+        # list build every nstlist steps; otherwise the rolling prune of one part, fused
+        # into the force pass (nb_step) or as a separate call before nb_forces
         k = t % nstlist
         xt = traj[t]
         if k == 0:
             ctx.grid_build(xt, box)
             ctx.pairlist_build()
+        if fused:
+            ctx.step(xt, q, lj, k, energy=True, f=f, e=e)
         else:
-            ctx.prune_rolling(xt, k)
-        ctx.forces(xt, q, lj, energy=True, f=f, e=e)
+            if k:
+                ctx.prune_rolling(xt, k)
+            ctx.forces(xt, q, lj, energy=True, f=f, e=e)
         if bwd:
             ctx.backward(xt, q, lj, G)
 
@@ -167,14 +172,14 @@ def main():
             first_stats = st
     eff_timed, comp_timed = eff[W:].sum(), comp[W:].sum()
 
-    def timed(bwd):
+    def timed(bwd, fused=True):
         for t in range(W):
-            step(t, bwd)
+            step(t, bwd, fused)
         torch.cuda.synchronize()
         ctx.set_timing(True)
         t0 = time.perf_counter()
         for t in range(W, T):
-            step(t, bwd)
+            step(t, bwd, fused)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         tm = ctx.get_timing()
@@ -185,6 +190,8 @@ def main():
     wall, tm = timed(False)
     fwd_ms, fwd_calls = tm["forces"]
     log("forward: %.3f ms/step, force kernel %.1f us/launch" % (1e3 * wall / K, 1e3 * fwd_ms / max(fwd_calls, 1)))
+    wall_sep, tm_sep = timed(False, fused=False)
+    log("separate prune + forces calls: %.3f ms/step" % (1e3 * wall_sep / K))
     wall_fb = None
     tm_fb = None
     if have_bwd:
@@ -215,6 +222,7 @@ def main():
         "effective_pairs_per_step": float(eff[W:].mean()),
         "raw_pairs_per_s": comp_timed / wall,
         "ns_per_day_equiv": 0.1728 / (wall / K),
+        "ms_per_step_separate_prune_call": 1e3 * wall_sep / K,
         "fwd_bwd_pairs_per_s": (eff_timed / wall_fb) if wall_fb else None,
         "fwd_bwd_ms_per_step": (1e3 * wall_fb / K) if wall_fb else None,
         "bwd_over_fwd_kernel": (tm_fb["backward"][0] / max(tm_fb["forces"][0], 1e-9))

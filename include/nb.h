@@ -178,6 +178,16 @@ nb_status nb_forces(nb_ctx* ctx, const float* x, const float* q, const float* lj
                     double* energy, double* virial, uint32_t flags);
 
 /*
+ * One MD step of the pair path in a single pass: exactly nb_prune_rolling(x,
+ * steps_since_build) followed by nb_forces(x, q, lj, ...), with the rolling prune of the
+ * part done inside the pair kernel (Sec. V.D: a special version of the force kernel
+ * prunes the list it processes).  Same inner list, same forces, one gather and one
+ * kernel fewer.  steps_since_build = 0 evaluates forces only.  Errors as both calls.
+ */
+nb_status nb_step(nb_ctx* ctx, const float* x, const float* q, const float* lj, float* f,
+                  double* energy, double* virial, uint32_t flags, int64_t steps_since_build);
+
+/*
  * Backward pass of nb_forces over the frozen inner list: given grad_f = dL/dF (dev
  * float[N][3]) and optionally grad_energy = dL/dE (dev double[n_systems][2], or NULL),
  * writes grad_x = dL/dx (dev float[N][3]; the Hessian-vector product of the energy with

@@ -13,7 +13,7 @@ NB_MOD_NONE, NB_MOD_POTSHIFT = 0, 1
 NB_F_ENERGY, NB_F_VIRIAL, NB_F_ACCUMULATE = 1, 2, 4
 
 EXPORTS = ["nb_create", "nb_destroy", "nb_set_topology", "nb_grid_build", "nb_pairlist_build",
-           "nb_prune_rolling", "nb_forces", "nb_forces_backward", "nb_get_grid",
+           "nb_prune_rolling", "nb_forces", "nb_step", "nb_forces_backward", "nb_get_grid",
            "nb_get_grid_dims", "nb_get_pairs", "nb_get_stats", "nb_set_timing", "nb_get_timing",
            "nb_strerror", "nb_last_error"]
 NB_T_FORCES, NB_T_FORCE_REDUCE, NB_T_PRUNE, NB_T_BACKWARD, NB_T_BACKWARD_REDUCE, NB_T_COUNT = range(6)
@@ -59,6 +59,7 @@ def load():
         "nb_pairlist_build": ([P], st),
         "nb_prune_rolling": ([P, P, i64], st),
         "nb_forces": ([P, P, P, P, P, P, P, u32], st),
+        "nb_step": ([P, P, P, P, P, P, P, u32, i64], st),
         "nb_forces_backward": ([P, P, P, P, P, P, P, P, P, u32], st),
         "nb_get_grid": ([P, P, i64, ctypes.POINTER(i64)], st),
         "nb_get_grid_dims": ([P, P], st),

@@ -143,6 +143,31 @@ class Context:
                                        _ptr(vir) if virial else None, flags), "nb_forces")
         return f, (e if energy else None), (vir if virial else None)
 
+    def step(self, x, q, lj, steps_since_build: int, energy: bool = True, virial: bool = False,
+             f=None, e=None, vir=None, accumulate: bool = False):
+        """Rolling prune of part (steps_since_build mod nstprune) fused into the force pass;
+        the same result as prune_rolling(x, steps_since_build) followed by forces(...)."""
+        x = self._dev(x, (self.n_atoms, 3), torch.float32, "x")
+        q = self._dev(q, (self.n_atoms,), torch.float32, "q")
+        lj = self._dev(lj, (self.n_types, self.n_types, 2), torch.float32, "lj")
+        if f is None:
+            f = torch.empty((self.n_atoms, 3), dtype=torch.float32, device=self.device)
+        flags = 0
+        if energy:
+            flags |= NB_F_ENERGY
+            if e is None:
+                e = torch.empty((self.n_sys, 2), dtype=torch.float64, device=self.device)
+        if virial:
+            flags |= NB_F_VIRIAL
+            if vir is None:
+                vir = torch.empty((self.n_sys, 3, 3), dtype=torch.float64, device=self.device)
+        if accumulate:
+            flags |= NB_F_ACCUMULATE
+        self._check(self.lib.nb_step(self.h, _ptr(x), _ptr(q), _ptr(lj), _ptr(f),
+                                     _ptr(e) if energy else None, _ptr(vir) if virial else None,
+                                     flags, int(steps_since_build)), "nb_step")
+        return f, (e if energy else None), (vir if virial else None)
+
     def backward(self, x, q, lj, grad_f, grad_energy=None, need_x=True, need_q=True,
                  need_lj=True, accumulate: bool = False):
         """Returns (grad_x [N,3] f32, grad_q [N] f32, grad_lj [T,T,2] f64), None if skipped."""

@@ -60,14 +60,26 @@ __device__ inline float erfcx_poly(float t) {
 
 // One 8x8 block of pairs (i-cluster c of the item, the current j-cluster): m is the
 // scalar 64-bit mask of valid, non-excluded lanes (lane = ii + 8 jj).
-template <int COUL, bool ENERGY, bool VIRIAL, bool SHIFTED>
+// Squared distance in the list-decision sequence (each product and sum rounded).
+__device__ inline float list_r2_exact(float dx, float dy, float dz) {
+#pragma clang fp contract(off)
+    const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+    const float t = xx + yy;
+    return t + zz;
+}
+
+template <int COUL, bool ENERGY, bool VIRIAL, bool SHIFTED, bool PRUNE>
 __device__ __forceinline__ void pair_block(float xi, float yi, float zi, float qi, int ti,
-                                           uint64_t m, float& fx, float& fy, float& fz,
-                                           const float4& xj, int tj,
+                                           uint64_t m_list, uint64_t m, float& fx, float& fy,
+                                           float& fz, const float4& xj, int tj,
                                            const float4* __restrict__ s_lj, const NbKParams& kp,
                                            float sxi, float syi, float szi, float& fjx,
                                            float& fjy, float& fjz, float& elj, float& ec,
-                                           float (&vir)[6], int& npair, int& nblock) {
+                                           float (&vir)[6], int& npair, int& nblock,
+                                           bool do_prune, float r2_inner, uint32_t& new_inner,
+                                           int c) {
+    // The same separation as the list build: x_i - L for s > 0 on the i side, the j side
+    // already shifted by -L for s < 0.
     float dx, dy, dz;
     if (SHIFTED) {
         dx = (xi - sxi) - xj.x;
@@ -77,6 +89,13 @@ __device__ __forceinline__ void pair_block(float xi, float yi, float zi, float q
         dx = xi - xj.x;
         dy = yi - xj.y;
         dz = zi - xj.z;
+    }
+    if (PRUNE && do_prune) {
+        // rolling prune of this cluster pair (Sec. V.E): inner iff an atom pair is inside
+        // rinner; exclusions do not remove cluster pairs
+        const float r2l = list_r2_exact(dx, dy, dz);
+        if (!(__builtin_amdgcn_ballot_w64(r2l < r2_inner) & m_list)) return;
+        new_inner |= 1u << c;
     }
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     const uint64_t act = __builtin_amdgcn_ballot_w64(r2 < kp.rc2) & m;
@@ -129,14 +148,15 @@ __device__ __forceinline__ void pair_block(float xi, float yi, float zi, float q
 // Per-cluster scalars of the item's eight i-clusters (kept in registers).
 #define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
-template <int COUL, bool ENERGY, bool VIRIAL>
+template <int COUL, bool ENERGY, bool VIRIAL, bool PRUNE>
 __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIRIAL ? 3 : 4))) void k_nb_fwd(
-    const NbItem* __restrict__ items, const NbEntry* __restrict__ entries,
+    const NbItem* __restrict__ items, NbEntry* __restrict__ entries,
     const uint64_t* __restrict__ excl_rows, const float4* __restrict__ xq,
     const int32_t* __restrict__ type_slot, const float4* __restrict__ cl_bb,
     const NbScInfo* __restrict__ sc_info, const NbSys* __restrict__ sys,
     const float* __restrict__ lj, float4* __restrict__ jpart, float4* __restrict__ ipart,
-    double* __restrict__ epart, int epart_stride, NbKParams kp, int n_items) {
+    double* __restrict__ epart, int epart_stride, NbKParams kp, int n_items, int prune_i0,
+    int prune_i1, float r2_inner) {
     extern __shared__ float4 s_lj[];
     const int T = kp.n_types;
     for (int i = threadIdx.x; i < T * T; i += blockDim.x) {
@@ -176,6 +196,8 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
     double vir_acc[6] = {0, 0, 0, 0, 0, 0};
     int npair = 0, nblock = 0;
 
+    // items of the part pruned in this pass walk their outer masks and rewrite the inner ones
+    const bool do_prune = PRUNE && item >= prune_i0 && item < prune_i1;
     const int e_end = it.e0 + it.ne;
     NbEntry nxt = entries[it.e0];
     float4 xj_n = xq[kClusterSize * nxt.cj + jj];
@@ -189,12 +211,13 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
             xj_n = xq[kClusterSize * nxt.cj + jj];
             tj_n = type_slot[kClusterSize * nxt.cj + jj];
         }
-        const uint32_t mask = (ent.meta >> 16) & 0xffu;
+        const uint32_t mask = (ent.meta >> (do_prune ? 8 : 16)) & 0xffu;
         float4* jp = jpart + (size_t)ent.jpos * kClusterSize;
         if (!mask) {
             if (ii == 0) jp[jj] = make_float4(0.f, 0.f, 0.f, 0.f);
             continue;
         }
+        uint32_t new_inner = 0;
         const int code = ent.meta & 31u;
         const int nj = (int)(ent.meta >> 24);
         const uint64_t jvalid = (nj >= 8) ? ~0ull : ((1ull << (8 * nj)) - 1ull);
@@ -205,16 +228,15 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
         float vir[6] = {0, 0, 0, 0, 0, 0};
         const int dc = ent.cj - ci0;        // the i-cluster equal to the j-cluster, if any
 
-#define NB_MASK(c)                                                                     \
-    (iv##c & jvalid & (xrow ? xrow[c] : ~0ull) &                                       \
-     ((self && dc == c) ? 0x7f3f1f0f07030100ull : ~0ull))
+#define NB_LMASK(c) (iv##c & jvalid & ((self && dc == c) ? 0x7f3f1f0f07030100ull : ~0ull))
+#define NB_MASK(c) (NB_LMASK(c) & (xrow ? xrow[c] : ~0ull))
         if (code == kShiftZero) {
 #define NB_BLOCK0(c)                                                                   \
     if ((mask >> c) & 1u)                                                              \
-        pair_block<COUL, ENERGY, VIRIAL, false>(xi##c, yi##c, zi##c, qi##c, ti##c,     \
-                                                NB_MASK(c), fx##c, fy##c, fz##c, xj, tj, \
-                                                s_lj, kp, 0.f, 0.f, 0.f, fjx, fjy, fjz,  \
-                                                elj, ec, vir, npair, nblock);
+        pair_block<COUL, ENERGY, VIRIAL, false, PRUNE>(                                \
+            xi##c, yi##c, zi##c, qi##c, ti##c, NB_LMASK(c), NB_MASK(c), fx##c, fy##c,    \
+            fz##c, xj, tj, s_lj, kp, 0.f, 0.f, 0.f, fjx, fjy, fjz, elj, ec, vir, npair,  \
+            nblock, do_prune, r2_inner, new_inner, c);
             NB_FOR8(NB_BLOCK0)
 #undef NB_BLOCK0
         } else {
@@ -227,14 +249,16 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
                         szi = sz > 0 ? S.L[2] : 0.f;
 #define NB_BLOCK1(c)                                                                   \
     if ((mask >> c) & 1u)                                                              \
-        pair_block<COUL, ENERGY, VIRIAL, true>(xi##c, yi##c, zi##c, qi##c, ti##c,      \
-                                               NB_MASK(c), fx##c, fy##c, fz##c, xj, tj,  \
-                                               s_lj, kp, sxi, syi, szi, fjx, fjy, fjz,   \
-                                               elj, ec, vir, npair, nblock);
+        pair_block<COUL, ENERGY, VIRIAL, true, PRUNE>(                                 \
+            xi##c, yi##c, zi##c, qi##c, ti##c, NB_LMASK(c), NB_MASK(c), fx##c, fy##c,    \
+            fz##c, xj, tj, s_lj, kp, sxi, syi, szi, fjx, fjy, fjz, elj, ec, vir, npair,  \
+            nblock, do_prune, r2_inner, new_inner, c);
             NB_FOR8(NB_BLOCK1)
 #undef NB_BLOCK1
         }
 #undef NB_MASK
+#undef NB_LMASK
+        if (do_prune && lane == 0) entries[e].meta = (ent.meta & ~(0xffu << 16)) | (new_inner << 16);
         fjx = dpp_sum8(fjx);
         fjy = dpp_sum8(fjy);
         fjz = dpp_sum8(fjz);
@@ -372,19 +396,29 @@ constexpr int kRedThreads = 256;
 template <typename T>
 __device__ void chunk_sums(const T* __restrict__ vals, int stride, int K, int p0, int p1,
                            double* __restrict__ out) {
-    __shared__ double s_w[kRedThreads / kWave];
+    constexpr int kG = 16;                 // values summed per pass (loads issued together)
+    __shared__ double s_w[kRedThreads / kWave][kG];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-    for (int k = 0; k < K; ++k) {
-        double acc = 0.0;
-        for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x)
-            acc += (double)vals[(size_t)k * stride + i];
-        for (int off = 1; off < kWave; off <<= 1) acc += __shfl_xor(acc, off);
-        if (lane == 0) s_w[wv] = acc;
+    for (int k0 = 0; k0 < K; k0 += kG) {
+        const int g = min(kG, K - k0);
+        double acc[kG];
+#pragma unroll
+        for (int q = 0; q < kG; ++q) acc[q] = 0.0;
+        for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
+#pragma unroll
+            for (int q = 0; q < kG; ++q)
+                if (q < g) acc[q] += (double)vals[(size_t)(k0 + q) * stride + i];
+        }
+#pragma unroll
+        for (int q = 0; q < kG; ++q) {
+            for (int off = 1; off < kWave; off <<= 1) acc[q] += __shfl_xor(acc[q], off);
+            if (lane == 0) s_w[wv][q] = acc[q];
+        }
         __syncthreads();
-        if (threadIdx.x == 0) {
+        if (threadIdx.x < g) {
             double t = 0.0;
-            for (int w = 0; w < kRedThreads / kWave; ++w) t += s_w[w];
-            out[k] = t;
+            for (int w = 0; w < kRedThreads / kWave; ++w) t += s_w[w][threadIdx.x];
+            out[k0 + threadIdx.x] = t;
         }
         __syncthreads();
     }
@@ -430,14 +464,24 @@ __global__ void k_energy_final(NbDev d, double* __restrict__ energy, double* __r
 
 inline int blocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
-template <int COUL, bool E, bool V>
+template <int COUL, bool E, bool V, bool P>
 void launch_fwd_t(const NbDev& d, const NbKParams& kp, const float* lj, int n_items,
-                  hipStream_t s) {
+                  int pi0, int pi1, float r2_inner, hipStream_t s) {
     const size_t lds = sizeof(float4) * (size_t)kp.n_types * kp.n_types;
-    hipLaunchKernelGGL((k_nb_fwd<COUL, E, V>), dim3(blocks(n_items, kFwdWaves)),
+    hipLaunchKernelGGL((k_nb_fwd<COUL, E, V, P>), dim3(blocks(n_items, kFwdWaves)),
                        dim3(kFwdThreads), lds, s, d.items, d.entries, d.excl_rows, d.xq,
                        d.type_slot, d.cl_bb, d.sc_info, d.sys, lj, d.jpart, d.ipart, d.epart,
-                       d.epart_stride, kp, n_items);
+                       d.epart_stride, kp, n_items, pi0, pi1, r2_inner);
+}
+
+template <int COUL, bool P>
+void launch_fwd_c(const NbDev& d, const NbKParams& kp, uint32_t flags, const float* lj,
+                  int n_items, int pi0, int pi1, float r2_inner, hipStream_t s) {
+    const bool E = (flags & NB_F_ENERGY) != 0, V = (flags & NB_F_VIRIAL) != 0;
+    if (E && V) launch_fwd_t<COUL, true, true, P>(d, kp, lj, n_items, pi0, pi1, r2_inner, s);
+    else if (E) launch_fwd_t<COUL, true, false, P>(d, kp, lj, n_items, pi0, pi1, r2_inner, s);
+    else if (V) launch_fwd_t<COUL, false, true, P>(d, kp, lj, n_items, pi0, pi1, r2_inner, s);
+    else launch_fwd_t<COUL, false, false, P>(d, kp, lj, n_items, pi0, pi1, r2_inner, s);
 }
 
 }  // namespace
@@ -451,19 +495,16 @@ hipError_t launch_gather(const NbDev& d, const float* x, const float* q, float4*
 }
 
 hipError_t launch_forces(const NbDev& d, const NbKParams& kp, int coulomb, uint32_t flags,
-                         const float* lj, int n_items, hipStream_t s) {
+                         const float* lj, int n_items, int prune_i0, int prune_i1,
+                         float r2_inner, hipStream_t s) {
     if (n_items <= 0) return hipGetLastError();
-    const bool E = (flags & NB_F_ENERGY) != 0, V = (flags & NB_F_VIRIAL) != 0;
+    const bool P = prune_i1 > prune_i0;
     if (coulomb == NB_COUL_RF) {
-        if (E && V) launch_fwd_t<NB_COUL_RF, true, true>(d, kp, lj, n_items, s);
-        else if (E) launch_fwd_t<NB_COUL_RF, true, false>(d, kp, lj, n_items, s);
-        else if (V) launch_fwd_t<NB_COUL_RF, false, true>(d, kp, lj, n_items, s);
-        else launch_fwd_t<NB_COUL_RF, false, false>(d, kp, lj, n_items, s);
+        if (P) launch_fwd_c<NB_COUL_RF, true>(d, kp, flags, lj, n_items, prune_i0, prune_i1, r2_inner, s);
+        else launch_fwd_c<NB_COUL_RF, false>(d, kp, flags, lj, n_items, 0, 0, 0.f, s);
     } else {
-        if (E && V) launch_fwd_t<NB_COUL_EWALD, true, true>(d, kp, lj, n_items, s);
-        else if (E) launch_fwd_t<NB_COUL_EWALD, true, false>(d, kp, lj, n_items, s);
-        else if (V) launch_fwd_t<NB_COUL_EWALD, false, true>(d, kp, lj, n_items, s);
-        else launch_fwd_t<NB_COUL_EWALD, false, false>(d, kp, lj, n_items, s);
+        if (P) launch_fwd_c<NB_COUL_EWALD, true>(d, kp, flags, lj, n_items, prune_i0, prune_i1, r2_inner, s);
+        else launch_fwd_c<NB_COUL_EWALD, false>(d, kp, flags, lj, n_items, 0, 0, 0.f, s);
     }
     return hipGetLastError();
 }

@@ -535,10 +535,9 @@ nb_status nb_prune_rolling(nb_ctx* c, const float* x, int64_t steps_since_build)
     return NB_OK;
 }
 
-nb_status nb_forces(nb_ctx* c, const float* x, const float* q, const float* lj, float* f,
-                    double* energy, double* virial, uint32_t flags) {
-    if (!c) return NB_ERR_ARG;
-    if (!c->has_list) return fail(c, NB_ERR_STATE, "no pair list");
+namespace {
+nb_status forces_impl(nb_ctx* c, const float* x, const float* q, const float* lj, float* f,
+                      double* energy, double* virial, uint32_t flags, int prune_part) {
     if (flags & ~(uint32_t)(NB_F_ENERGY | NB_F_VIRIAL | NB_F_ACCUMULATE))
         return fail(c, NB_ERR_ARG, "unknown flag");
     if (c->d.n_atoms > 0 && (!x || !q || !lj || !f)) return fail(c, NB_ERR_ARG, "null array");
@@ -547,19 +546,41 @@ nb_status nb_forces(nb_ctx* c, const float* x, const float* q, const float* lj, 
     NB_HIP(c, hipSetDevice(c->device));
     NbDev& d = c->d;
     const NbKParams kp = kernel_params(c->p);
+    const int pi0 = prune_part >= 0 ? c->part_start[prune_part] : 0;
+    const int pi1 = prune_part >= 0 ? c->part_start[prune_part + 1] : 0;
     {
         TimedSection ts(c, NB_T_FORCE_REDUCE);
         NB_HIP(c, launch_gather(d, x, q, d.xq, c->n_slots, c->stream));
     }
     {
         TimedSection ts(c, NB_T_FORCES);
-        NB_HIP(c, launch_forces(d, kp, c->p.coulomb, flags, lj, c->n_items, c->stream));
+        NB_HIP(c, launch_forces(d, kp, c->p.coulomb, flags, lj, c->n_items, pi0, pi1,
+                                radius_sq(c->p.rinner), c->stream));
     }
     TimedSection ts(c, NB_T_FORCE_REDUCE);
     NB_HIP(c, launch_reduce_forces(d, f, (flags & NB_F_ACCUMULATE) != 0, c->n_slots, c->stream));
     if (flags & (NB_F_ENERGY | NB_F_VIRIAL))
         NB_HIP(c, launch_reduce_energies(d, energy, virial, flags, c->n_sys, c->stream));
     return NB_OK;
+}
+}  // namespace
+
+nb_status nb_forces(nb_ctx* c, const float* x, const float* q, const float* lj, float* f,
+                    double* energy, double* virial, uint32_t flags) {
+    if (!c) return NB_ERR_ARG;
+    if (!c->has_list) return fail(c, NB_ERR_STATE, "no pair list");
+    return forces_impl(c, x, q, lj, f, energy, virial, flags, -1);
+}
+
+nb_status nb_step(nb_ctx* c, const float* x, const float* q, const float* lj, float* f,
+                  double* energy, double* virial, uint32_t flags, int64_t steps_since_build) {
+    if (!c) return NB_ERR_ARG;
+    if (!c->has_list) return fail(c, NB_ERR_STATE, "no pair list");
+    if (steps_since_build < 0) return fail(c, NB_ERR_ARG, "negative step");
+    if (steps_since_build >= c->p.nstlist)
+        return fail(c, NB_ERR_STATE, "the outer list has expired (steps_since_build >= nstlist)");
+    const int part = steps_since_build == 0 ? -1 : (int)(steps_since_build % c->p.nstprune);
+    return forces_impl(c, x, q, lj, f, energy, virial, flags, part);
 }
 
 nb_status nb_forces_backward(nb_ctx* c, const float* x, const float* q, const float* lj,

@@ -105,7 +105,8 @@ hipError_t launch_gather(const NbDev& d, const float* x, const float* q, float4*
 hipError_t launch_prune(const NbDev& d, int item0, int n_items, float r2_inner,
                         hipStream_t s);
 hipError_t launch_forces(const NbDev& d, const NbKParams& kp, int coulomb, uint32_t flags,
-                         const float* lj, int n_items, hipStream_t s);
+                         const float* lj, int n_items, int prune_i0, int prune_i1,
+                         float r2_inner, hipStream_t s);
 hipError_t launch_reduce_forces(const NbDev& d, float* f, bool accumulate, int n_slots,
                                 hipStream_t s);
 hipError_t launch_reduce_energies(const NbDev& d, double* energy, double* virial,

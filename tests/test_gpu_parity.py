@@ -199,3 +199,31 @@ def test_bad_box_rejected(sys3k):
     with pytest.raises(NBError) as ei:
         ctx.grid_build(dev(c["x"]), c["boxes"])       # 3.104 < 2 * 1.6
     assert ei.value.status == 2
+
+
+def test_fused_step_equals_prune_then_forces(sys3k):
+    """nb_step (rolling prune inside the pair kernel) gives the same inner list and bitwise
+    the same forces and energies as nb_prune_rolling followed by nb_forces."""
+    c = concat(sys3k)
+    kw = dict(coulomb="ewald", rc=1.0, rinner=1.04, rlist=1.1, beta=3.12, nstlist=20,
+              nstprune=4)
+    ctx_a, _ = build(c, **kw)
+    ctx_b, _ = build(c, **kw)
+    g = oracle.grid_spec.build_grid(c["x"], c["boxes"], c["offsets"])
+    n_cl = g["slot_atom"].size // 8
+    q, lj = dev(c["q"]), dev(c["lj"])
+    rng = np.random.default_rng(11)
+    x = c["x"].copy()
+    for t in range(1, 9):
+        x = (x + rng.normal(0, 0.01, x.shape)).astype(np.float32)
+        xt = dev(x)
+        ctx_a.prune_rolling(xt, t)
+        fa, ea, va = ctx_a.forces(xt, q, lj, energy=True, virial=True)
+        fb, eb, vb = ctx_b.step(xt, q, lj, t, energy=True, virial=True)
+        ia = np.sort(keys_of(ctx_a.get_pairs("inner"), n_cl))
+        ib = np.sort(keys_of(ctx_b.get_pairs("inner"), n_cl))
+        assert np.array_equal(ia, ib), t
+        assert torch.equal(fa, fb) and torch.equal(ea, eb) and torch.equal(va, vb), t
+    fb, eb, _ = ctx_b.step(xt, q, lj, 0)
+    fa, ea, _ = ctx_a.forces(xt, q, lj)
+    assert torch.equal(fa, fb)
