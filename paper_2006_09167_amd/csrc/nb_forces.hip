@@ -69,7 +69,7 @@ __device__ inline float list_r2_exact(float dx, float dy, float dz) {
 }
 
 template <int COUL, bool ENERGY, bool VIRIAL, bool SHIFTED, bool PRUNE>
-__device__ __forceinline__ void pair_block(float xi, float yi, float zi, float qi, int ti,
+__device__ __forceinline__ void pair_block(float xi, float yi, float zi, const float2* s_qt,
                                            uint64_t m_list, uint64_t m, float& fx, float& fy,
                                            float& fz, const float4& xj, int tj,
                                            const float4* __restrict__ s_lj, const NbKParams& kp,
@@ -101,6 +101,9 @@ __device__ __forceinline__ void pair_block(float xi, float yi, float zi, float q
     const uint64_t act = __builtin_amdgcn_ballot_w64(r2 < kp.rc2) & m;
     if (!act) return;
     const bool on = __builtin_amdgcn_inverse_ballot_w64(act);
+    const float2 qt = *s_qt;                           // (K q_i, type_i * T) of this lane's i-atom
+    const float qi = qt.x;
+    const int ti = __builtin_bit_cast(int, qt.y);
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float rinv2 = rinv * rinv;
     const float4 p = s_lj[ti + tj];                    // (6 c6, 12 c12, shift, c6)
@@ -158,6 +161,7 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
     double* __restrict__ epart, int epart_stride, NbKParams kp, int n_items, int prune_i0,
     int prune_i1, float r2_inner) {
     extern __shared__ float4 s_lj[];
+    __shared__ float2 s_qt_all[kFwdWaves][kScAtoms];   // per wave: (K q_i, type_i * T)
     const int T = kp.n_types;
     for (int i = threadIdx.x; i < T * T; i += blockDim.x) {
         const float c6 = lj[2 * i], c12 = lj[2 * i + 1];
@@ -173,10 +177,17 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
     const int sc = it.sc, ci0 = kClustersPerSc * sc;
     const NbSys S = sys[sc_info[sc].sys];
     const int ibase = kScAtoms * sc + ii;
+    float2* s_qt = s_qt_all[wave];
+    {
+        // lane l holds slot l of the super-cluster: (8 c + ii) for c = l >> 3
+        const float4 v = xq[kScAtoms * sc + lane];
+        s_qt[lane] = make_float2(v.w * kp.epsfac_r,
+                                 __builtin_bit_cast(float, type_slot[kScAtoms * sc + lane] * T));
+    }
+    __builtin_amdgcn_wave_barrier();
 
 #define NB_ILOAD(c)                                                                    \
-    float xi##c, yi##c, zi##c, qi##c;                                                  \
-    int ti##c;                                                                         \
+    float xi##c, yi##c, zi##c;                                                         \
     uint64_t iv##c;                                                                    \
     float fx##c = 0.f, fy##c = 0.f, fz##c = 0.f;                                       \
     {                                                                                  \
@@ -184,8 +195,6 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
         xi##c = v.x;                                                                   \
         yi##c = v.y;                                                                   \
         zi##c = v.z;                                                                   \
-        qi##c = v.w * kp.epsfac_r;                                                     \
-        ti##c = type_slot[ibase + kClusterSize * c] * T;                               \
         const int ni = (int)cl_bb[2 * (ci0 + c)].w;                                    \
         iv##c = ((ni >= 8) ? 0xffull : ((1ull << ni) - 1ull)) * 0x0101010101010101ull; \
     }
@@ -234,7 +243,8 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
 #define NB_BLOCK0(c)                                                                   \
     if ((mask >> c) & 1u)                                                              \
         pair_block<COUL, ENERGY, VIRIAL, false, PRUNE>(                                \
-            xi##c, yi##c, zi##c, qi##c, ti##c, NB_LMASK(c), NB_MASK(c), fx##c, fy##c,    \
+            xi##c, yi##c, zi##c, s_qt + kClusterSize * c + ii, NB_LMASK(c), NB_MASK(c),  \
+            fx##c, fy##c,                                                                \
             fz##c, xj, tj, s_lj, kp, 0.f, 0.f, 0.f, fjx, fjy, fjz, elj, ec, vir, npair,  \
             nblock, do_prune, r2_inner, new_inner, c);
             NB_FOR8(NB_BLOCK0)
@@ -250,7 +260,8 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
 #define NB_BLOCK1(c)                                                                   \
     if ((mask >> c) & 1u)                                                              \
         pair_block<COUL, ENERGY, VIRIAL, true, PRUNE>(                                 \
-            xi##c, yi##c, zi##c, qi##c, ti##c, NB_LMASK(c), NB_MASK(c), fx##c, fy##c,    \
+            xi##c, yi##c, zi##c, s_qt + kClusterSize * c + ii, NB_LMASK(c), NB_MASK(c),  \
+            fx##c, fy##c,                                                                \
             fz##c, xj, tj, s_lj, kp, sxi, syi, szi, fjx, fjy, fjz, elj, ec, vir, npair,  \
             nblock, do_prune, r2_inner, new_inner, c);
             NB_FOR8(NB_BLOCK1)
@@ -404,10 +415,15 @@ __device__ void chunk_sums(const T* __restrict__ vals, int stride, int K, int p0
         double acc[kG];
 #pragma unroll
         for (int q = 0; q < kG; ++q) acc[q] = 0.0;
+        // Rows past the last value re-read row g-1 (in bounds, never written out), so
+        // every load of a pass is unconditional and all of them are in flight together.
+#pragma unroll 2
         for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
+            T v[kG];
 #pragma unroll
-            for (int q = 0; q < kG; ++q)
-                if (q < g) acc[q] += (double)vals[(size_t)(k0 + q) * stride + i];
+            for (int q = 0; q < kG; ++q) v[q] = vals[(size_t)(k0 + min(q, g - 1)) * stride + i];
+#pragma unroll
+            for (int q = 0; q < kG; ++q) acc[q] += (double)v[q];
         }
 #pragma unroll
         for (int q = 0; q < kG; ++q) {

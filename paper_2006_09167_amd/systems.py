@@ -124,29 +124,46 @@ def _orient(rng: np.random.Generator, n: int) -> np.ndarray:
     return OH_DIST * np.stack([u1, u2], axis=1)
 
 
-def _close_molecules(x: np.ndarray, box: float, mol: np.ndarray, dmin: float) -> np.ndarray:
-    """Molecules with an atom closer than dmin to an atom of another molecule
-    (periodic); the higher-numbered molecule of each close pair is returned."""
+def _wrapped_tree(x: np.ndarray, box: float):
     from scipy.spatial import cKDTree
     xw = np.mod(x.astype(np.float64), box)
     xw[xw >= box] = 0.0
-    tree = cKDTree(xw, boxsize=box)
-    pairs = tree.query_pairs(dmin, output_type="ndarray")
-    if pairs.size == 0:
-        return np.zeros(0, dtype=np.int64)
-    ma, mb = mol[pairs[:, 0]], mol[pairs[:, 1]]
+    return cKDTree(xw, boxsize=box), xw
+
+
+def _close_molecules(tree, xw: np.ndarray, mol: np.ndarray, dmin: float,
+                     changed: Optional[np.ndarray] = None) -> np.ndarray:
+    """Molecules with an atom closer than dmin to an atom of another molecule
+    (periodic); the higher-numbered molecule of each close pair is returned.
+
+    With ``changed`` (molecules moved since the last call, which returned exactly
+    them), only pairs with an atom of a changed molecule are examined: every other
+    pair kept its distance and was not close at that call, or the higher molecule
+    of the pair would have been returned and changed."""
+    if changed is None:
+        pairs = tree.query_pairs(dmin, output_type="ndarray")
+        if pairs.size == 0:
+            return np.zeros(0, dtype=np.int64)
+        a, b = pairs[:, 0], pairs[:, 1]
+    else:
+        atoms = (3 * changed[:, None] + np.arange(3)[None, :]).reshape(-1)
+        hits = tree.query_ball_point(xw[atoms], dmin)
+        cnt = np.fromiter((len(h) for h in hits), dtype=np.int64, count=len(hits))
+        if cnt.sum() == 0:
+            return np.zeros(0, dtype=np.int64)
+        a = np.repeat(atoms, cnt)
+        b = np.concatenate([np.asarray(h, dtype=np.int64) for h in hits if len(h)])
+    ma, mb = mol[a], mol[b]
     inter = ma != mb
     return np.unique(np.maximum(ma[inter], mb[inter]))
 
 
-def _best_orientation(rng: np.random.Generator, x: np.ndarray, o: np.ndarray, mol: np.ndarray,
-                      bad: np.ndarray, box: float, n_try: int = 16) -> np.ndarray:
+def _best_orientation(rng: np.random.Generator, tree, x: np.ndarray, o: np.ndarray,
+                      mol: np.ndarray, bad: np.ndarray, box: float,
+                      n_try: int = 16) -> np.ndarray:
     """For each listed molecule, the H offsets (out of n_try seeded draws) whose H
-    atoms keep the largest distance to the atoms of all other molecules."""
-    from scipy.spatial import cKDTree
-    xw = np.mod(x.astype(np.float64), box)
-    xw[xw >= box] = 0.0
-    tree = cKDTree(xw, boxsize=box)
+    atoms keep the largest distance to the atoms of all other molecules (tree: the
+    periodic KD-tree of the current wrapped coordinates x)."""
     nb = bad.size
     cand = np.stack([_orient(rng, nb) for _ in range(n_try)], axis=1)      # [nb, n_try, 2, 3]
     hpos = o[bad][:, None, None, :] + cand                                   # [nb, n_try, 2, 3]
@@ -194,12 +211,14 @@ def water_box(n_mol: int, k: int, box: float, seed: int, min_contact: float = 0.
 
     x = assemble(o, h)
     redraws = 0
+    bad = None
     for _ in range(100):
-        bad = _close_molecules(x, box, mol, min_contact)
+        tree, xw = _wrapped_tree(x, box)
+        bad = _close_molecules(tree, xw, mol, min_contact, bad)
         if bad.size == 0:
             break
         redraws += int(bad.size)
-        h[bad] = _best_orientation(r_ori, x, o, mol, bad, box)
+        h[bad] = _best_orientation(r_ori, tree, x, o, mol, bad, box)
         x = assemble(o, h)
 
     n = 3 * n_mol
