@@ -1,19 +1,22 @@
 #!/usr/bin/env python
 """Benchmark of the cluster-pair nonbonded path on one MI355X.
 
-Workload: the 96,000-atom water-like box (32,000 three-site molecules, 9.86 nm cube,
-seeded jittered lattice), Ewald real space (beta = 3.12/nm, rc = 1.0 nm, potential
+Default workload: the 96,000-atom water-like box (32,000 three-site molecules, 9.86 nm
+cube, seeded jittered lattice), Ewald real space (beta = 3.12/nm, rc = 1.0 nm, potential
 shift), outer list rlist = 1.1 nm rebuilt every 100 steps, inner list rinner = 1.04 nm
 rolling-pruned in 4 parts, positions given seeded Gaussian displacements of 0.002 nm per
-step.  The whole displacement trajectory is generated on the GPU before timing, so inputs
-are resident in HBM when the timed region starts.
+step.  --workload selects the 1.5M-atom box or the ensemble of 256 uneven replicas
+instead (one JSON line each).  The whole displacement trajectory is generated on the
+GPU before timing, so inputs are resident in HBM when the timed region starts.
 
-One step = list build (grid + outer list + initial prune) when t mod 100 == 0, otherwise
-one rolling prune; then the force + energy evaluation (and, for the fwd+bwd leg, the
-backward pass of a force-matching loss).  The JSON line reports effective pair
-interactions/s (pairs inside the cut-off) of the forward step, the fwd+bwd rate, the raw
-rate, ns/day-equivalent at 2 fs, the force kernel's FP32 roofline fraction from HIP-event
-kernel times, and the FP64 oracle timed on the host cores.
+One step = list build (grid + outer list + initial prune) when t mod nstlist == 0,
+otherwise the rolling prune of one part fused into the force + energy pass (nb_step),
+replayed from a HIP graph with positions updated in place (the copy of the step's
+positions into the fixed buffer is inside the timed region).  The execution shape of
+the pair kernel is chosen by the autotuner at the first list build (untimed).  The JSON
+line reports effective pair interactions/s of that step, the eager and separate-call
+variants, forward + backward, ns/day-equivalent at 2 fs, the force kernel's FP32
+roofline fraction from HIP-event kernel times, and the FP64 oracle timed on the host.
 """
 import argparse
 import json
@@ -26,50 +29,117 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "pair interactions/s & % FP32 VALU peak, fwd vs fwd+bwd, 96k-atom box"
-CONFIG = "water96k_ewald"
 PEAK_FP32 = 157.3e12          # MI355X FP32 vector peak (FLOP/s), counting packed FP32
 PEAK_FP32_NONPACKED = 78.6e12 # without packed FP32 (one FMA per lane per cycle)
-# Algorithmic FLOP per evaluated pair slot of the Ewald force+energy kernel (FMA = 2,
+# Algorithmic FLOP per evaluated pair slot of the force+energy kernels (FMA = 2,
 # add/mul = 1, rsqrt/rcp/exp2 = 1, compare/select = 0):
-#   separation 3, r^2 5, rsqrt 1, r^-2 1, LJ force 5, q_i q_j 1,
-#   Ewald: r 1, beta r 1, u = 1/(1 + p t) 3, P(u) 16, u P 1, exp argument 1, exp2 1,
-#          erfc 1, g 3 (= 29), F/r 3, force accumulation 9, energies 9     => 66
-FLOP_PER_PAIR_EWALD_E = 66
-# Backward pass per evaluated pair slot (same counting), documented in the design doc.
-FLOP_PER_PAIR_EWALD_BWD = 148
+#   common: separation 3, r^2 5, rsqrt 1, r^-2 1, LJ force 5, q_i q_j 1,
+#           force accumulation 9                                            (= 25)
+#   Ewald:  r 1, beta r 1, u = 1/(1 + p t) 3, P(u) 16, u P 1, exp argument 1, exp2 1,
+#           erfc 1, g 3 (= 28), F/r 3, energies 9 (V_C 3, V_LJ 4, 2 sums)   => 66
+#   RF:     force 5, energies 10 (V_C 4, V_LJ 4, 2 sums)                    => 40
+FLOP_PER_PAIR = {"ewald": 66, "rf": 40}
+
+WORKLOADS = {
+    "water96k_ewald": "96,000-atom water-like box (32,000 molecules, 9.86 nm cube), Ewald "
+                      "real space beta=3.12/nm rc=1.0 nm, rlist=1.1 nm every 100 steps, "
+                      "rinner=1.04 nm rolling prune in 4 parts, Gaussian steps 0.002 nm",
+    "water1500k_ewald": "1,500,000-atom water-like box (500,000 molecules, 24.7 nm cube), "
+                        "Ewald real space beta=2.60/nm rc=1.2 nm, rlist=1.3 nm every 80 "
+                        "steps, rinner=1.24 nm rolling prune in 4 parts, Gaussian steps "
+                        "0.002 nm",
+    "ensemble256_rf": "256 independent water-like replicas of 3k-24k atoms (log-uniform, "
+                      "2.63M atoms in all, density 100/nm^3) in one context, reaction field "
+                      "rc=0.9 nm, rlist=1.0 nm every 100 steps, rinner=0.94 nm rolling prune "
+                      "in 4 parts, Gaussian steps 0.002 nm",
+}
 
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(s, xs, cfg, budget_s=8.0):
-    """Time the FP64 oracle (full brute-force evaluations of the box at consecutive steps'
-    positions, until about budget_s seconds have passed) on the host cores.  Returns the
-    seconds per evaluation, the first evaluation's energies and forces, the thread count
-    and the number of evaluations."""
+def load_workload(name):
+    """Host arrays and parameters of a workload (seeded synthetic inputs)."""
+    import numpy as np
+    from paper_2006_09167_amd import systems
+    if name == "ensemble256_rf":
+        cfg = dict(systems.ENSEMBLE)
+        reps = systems.ensemble_systems()
+        c = systems.concat_systems(reps)
+        c["lj"] = reps[0].lj
+        c["parts"] = reps
+        c["n_types"] = reps[0].n_types
+    else:
+        cfg = dict(systems.CONFIGS[name])
+        s = systems.config_system(name)
+        c = dict(x=s.x, q=s.q, type=s.type, excl_ptr=s.excl_ptr, excl_idx=s.excl_idx,
+                 boxes=s.box[None], offsets=np.array([0, s.n], np.int64), lj=s.lj, parts=[s],
+                 n_types=s.n_types)
+    cfg.setdefault("beta", 0.0)
+    return c, cfg
+
+
+def cpu_baseline(c, cfg, x_np, budget_s=8.0):
+    """Time the FP64 oracle on the host cores on a bounded sample of the workload at one
+    step's positions.  Returns (seconds, fraction of the step's pair interactions the
+    sample covers, description, oracle results for the parity check)."""
+    import numpy as np
     import oracle
     oracle.build(force=False)
-    p = oracle.params("ewald", rc=cfg["rc"], beta=cfg["beta"])
+    p = oracle.params(cfg["coulomb"], rc=cfg["rc"], beta=cfg["beta"])
+    offs = c["offsets"]
+    N = int(offs[-1])
+    if len(c["parts"]) > 1:
+        # whole replicas in order until the budget is spent
+        t0 = time.perf_counter()
+        done, atoms, res = 0, 0, []
+        for r, s in enumerate(c["parts"]):
+            a0, a1 = int(offs[r]), int(offs[r + 1])
+            E, F, _ = oracle.forces(x_np[a0:a1], s.q, s.type, s.lj, s.excl_ptr, s.excl_idx,
+                                    s.box, p)
+            res.append((r, E, F))
+            done += 1
+            atoms += a1 - a0
+            if time.perf_counter() - t0 >= budget_s:
+                break
+        dt = time.perf_counter() - t0
+        return dt, atoms / N, ("FP64 brute-force force+energy evaluations of the first %d "
+                               "replicas (%d atoms); pairs credited in proportion to atoms"
+                               % (done, atoms)), res
+    s = c["parts"][0]
+    if N <= 200000:
+        t0 = time.perf_counter()
+        n, first = 0, None
+        while True:
+            E, F, _ = oracle.forces(x_np, s.q, s.type, s.lj, s.excl_ptr, s.excl_idx, s.box, p)
+            if first is None:
+                first = (E, F)
+            n += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+        dt = (time.perf_counter() - t0) / n
+        return dt, 1.0, ("%d FP64 brute-force force+energy evaluations of the box (all "
+                         "N(N-1)/2 minimum-image pairs)" % n), [(0, first[0], first[1])]
+    # large box: forces on a seeded sample of atoms (all partners of each)
+    rng = np.random.default_rng(7)
+    sel = np.sort(rng.choice(N, size=1024, replace=False))
     t0 = time.perf_counter()
-    first = None
-    n = 0
-    for x_np in xs:
-        E, F, _ = oracle.forces(x_np, s.q, s.type, s.lj, s.excl_ptr, s.excl_idx, s.box, p)
-        if first is None:
-            first = (E, F)
-        n += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = (time.perf_counter() - t0) / n
-    return dt, first[0], first[1], oracle.num_threads(), n
+    F = oracle.forces_on(sel, x_np, s.q, s.type, s.lj, s.excl_ptr, s.excl_idx, s.box, p)
+    dt = time.perf_counter() - t0
+    # the pairs of 1024 sampled atoms: 2 * 1024 / N of all pair interactions
+    return dt, 2.0 * sel.size / N, ("FP64 brute-force forces on 1024 seeded atoms of the "
+                                    "box (all partners of each)"), [(sel, None, F)]
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: workload's)")
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="water96k_ewald", choices=sorted(WORKLOADS))
+    ap.add_argument("--exec", default="auto", choices=["auto", "static", "xcd", "queue"],
+                    help="pair kernel execution shape (auto = autotuner at the first build)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -83,32 +153,35 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2006_09167_amd import _lib, systems
+    from paper_2006_09167_amd import _lib
     if not os.path.exists(_lib.LIB_PATH):
         import __graft_entry__
         __graft_entry__.build()
     from paper_2006_09167_amd.api import Context, NBError
 
-    cfg = systems.CONFIGS[CONFIG]
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    log("generating %s" % CONFIG)
-    s = systems.config_system(CONFIG)
-    N = s.n
-    K, W = args.steps, args.warmup
+    log("generating %s" % args.workload)
+    c, cfg = load_workload(args.workload)
+    N = int(c["offsets"][-1])
+    S = len(c["parts"])
+    K = args.steps if args.steps is not None else cfg["steps"]
+    W = args.warmup
     T = W + K
     nstlist = cfg["nstlist"]
+    coul = cfg["coulomb"]
 
     # Seeded displacement trajectory, resident on the GPU before timing.
+    log("trajectory: %d steps of %d atoms" % (T, N))
     gen = torch.Generator(device=dev)
     gen.manual_seed(cfg["seed"])
     traj = torch.empty((T, N, 3), dtype=torch.float32, device=dev)
-    traj[0] = torch.from_numpy(s.x).to(dev)
+    traj[0] = torch.from_numpy(c["x"]).to(dev)
     for t in range(1, T):
         traj[t] = traj[t - 1] + cfg["sigma_step"] * torch.randn((N, 3), generator=gen, device=dev)
-    q = torch.from_numpy(s.q).to(dev)
-    lj = torch.from_numpy(s.lj).to(dev)
-    box = s.box
+    q = torch.from_numpy(c["q"]).to(dev)
+    lj = torch.from_numpy(c["lj"]).to(dev)
+    boxes = c["boxes"]
     if args.copy_probe_mb:
         # a plain copy kernel of known size: reads and writes copy_probe_mb MiB once
         src = torch.ones(args.copy_probe_mb * (1 << 20) // 4, dtype=torch.float32, device=dev)
@@ -117,22 +190,33 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    ctx = Context(n_types=s.n_types, coulomb="ewald", rc=cfg["rc"], rinner=cfg["rinner"],
+    ctx = Context(n_types=c["n_types"], coulomb=coul, rc=cfg["rc"], rinner=cfg["rinner"],
                   rlist=cfg["rlist"], beta=cfg["beta"], nstlist=nstlist,
-                  nstprune=cfg["nstprune"], atom_offsets=[0, N], device=dev)
-    ctx.set_topology(s.type, s.excl_ptr, s.excl_idx)
+                  nstprune=cfg["nstprune"], atom_offsets=c["offsets"], device=dev)
+    ctx.set_topology(c["type"], c["excl_ptr"], c["excl_idx"])
     f = torch.empty((N, 3), dtype=torch.float32, device=dev)
-    e = torch.empty((1, 2), dtype=torch.float64, device=dev)
+    e = torch.empty((S, 2), dtype=torch.float64, device=dev)
+    xbuf = traj[0].clone()                  # positions at a fixed address (graph replays)
+
+    ctx.grid_build(traj[0], boxes)
+    ctx.pairlist_build()
+    tune = None
+    if args.exec == "auto":
+        best, trials = ctx.autotune(traj[0], q, lj, energy=True, repeats=5)
+        tune = {"best": best, "trials": trials}
+        log("autotune: item width %d, mode %s, %.1f us per force call"
+            % (best["item_width"], best["mode"], best["us_per_call"]))
+    else:
+        ctx.set_exec(0, args.exec)
 
     have_bwd = not args.no_backward
     G = None
     if have_bwd:
         # adjoint of a force-matching loss: G = 2 (F - F_ref), F_ref from parameters x1.05
-        ctx.grid_build(traj[0], box)
-        ctx.pairlist_build()
         f_ref, _, _ = ctx.forces(traj[0], q * 1.05, lj * 1.05, energy=True)
         f0, _, _ = ctx.forces(traj[0], q, lj, energy=True)
         G = (2.0 * (f0 - f_ref)).contiguous()
+        del f_ref, f0
         try:
             ctx.backward(traj[0], q, lj, G)
         except NBError as err:
@@ -140,20 +224,24 @@ def main():
             have_bwd = False
         torch.cuda.synchronize()
 
-    def step(t, bwd=False, fused=True):
+    def step(t, path="graph", bwd=False):
         # list build every nstlist steps; otherwise the rolling prune of one part, fused
-        # into the force pass (nb_step) or as a separate call before nb_forces
+        # into the force pass (nb_step, eager or graph-replayed) or a separate call
         k = t % nstlist
-        xt = traj[t]
-        if k == 0:
-            ctx.grid_build(xt, box)
-            ctx.pairlist_build()
-        if fused:
-            ctx.step(xt, q, lj, k, energy=True, f=f, e=e)
+        if path == "graph":
+            xbuf.copy_(traj[t])
+            xt = xbuf
         else:
+            xt = traj[t]
+        if k == 0:
+            ctx.grid_build(xt, boxes)
+            ctx.pairlist_build()
+        if path == "separate":
             if k:
                 ctx.prune_rolling(xt, k)
             ctx.forces(xt, q, lj, energy=True, f=f, e=e)
+        else:
+            ctx.step(xt, q, lj, k, energy=True, f=f, e=e, graph=(path == "graph"))
         if bwd:
             ctx.backward(xt, q, lj, G)
 
@@ -162,47 +250,49 @@ def main():
     eff = np.zeros(T)
     comp = np.zeros(T)
     inner = np.zeros(T)
-    n_entries = n_items = 0
+    first_stats = None
     for t in range(T):
-        step(t)
+        step(t, "eager")
         st = ctx.stats()
         eff[t], comp[t], inner[t] = st["effective_pairs"], st["computed_pairs"], st["inner_pairs"]
         if t == 0:
-            n_entries, n_items = st["n_entries"], st["n_work_items"]
             first_stats = st
     eff_timed, comp_timed = eff[W:].sum(), comp[W:].sum()
 
-    def timed(bwd, fused=True):
+    def timed(path, bwd=False, timing=False):
         for t in range(W):
-            step(t, bwd, fused)
+            step(t, path, bwd)
         torch.cuda.synchronize()
-        ctx.set_timing(True)
+        if timing:
+            ctx.set_timing(True)
         t0 = time.perf_counter()
         for t in range(W, T):
-            step(t, bwd, fused)
+            step(t, path, bwd)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        tm = ctx.get_timing()
-        ctx.set_timing(False)
+        tm = ctx.get_timing() if timing else None
+        if timing:
+            ctx.set_timing(False)
         return wall, tm
 
-    log("timed forward pass: %d warmup + %d steps" % (W, K))
-    wall, tm = timed(False)
-    fwd_ms, fwd_calls = tm["forces"]
-    log("forward: %.3f ms/step, force kernel %.1f us/launch" % (1e3 * wall / K, 1e3 * fwd_ms / max(fwd_calls, 1)))
-    wall_sep, tm_sep = timed(False, fused=False)
+    log("timed graph-replayed step: %d warmup + %d steps" % (W, K))
+    wall, _ = timed("graph")
+    log("graph: %.3f ms/step" % (1e3 * wall / K))
+    wall_eager, tm_eager = timed("eager", timing=True)
+    log("eager fused step: %.3f ms/step" % (1e3 * wall_eager / K))
+    wall_sep, tm_sep = timed("separate", timing=True)
     log("separate prune + forces calls: %.3f ms/step" % (1e3 * wall_sep / K))
-    wall_fb = None
-    tm_fb = None
+    wall_fb = tm_fb = None
     if have_bwd:
         log("timed fwd+bwd pass")
-        wall_fb, tm_fb = timed(True)
+        wall_fb, tm_fb = timed("eager", bwd=True, timing=True)
 
     # Roofline of the plain force kernel: the separate-call pass launches only that flavor
     # (the fused pass adds the list-distance test of the pruned part to some launches).
     plain_ms, plain_calls = tm_sep["forces"]
-    achieved = comp_timed * FLOP_PER_PAIR_EWALD_E / (plain_ms * 1e-3)
-    # force + energy at one step for the CPU comparison
+    flop = FLOP_PER_PAIR[coul]
+    achieved = comp_timed * flop / (plain_ms * 1e-3)
+    fused_ms, fused_calls = tm_eager["forces"]
     result = {
         "metric": METRIC,
         "value": eff_timed / wall,
@@ -216,57 +306,76 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "water96k_ewald: 96,000-atom water-like box (32,000 molecules, "
-                               "9.86 nm cube), Ewald real space beta=3.12/nm rc=1.0 nm, "
-                               "rlist=1.1 nm every 100 steps, rinner=1.04 nm rolling prune "
-                               "in 4 parts, Gaussian steps 0.002 nm",
-                   "atoms": N, "nstlist": nstlist, "nstprune": cfg["nstprune"],
-                   "list_entries": int(n_entries), "work_items": int(n_items)},
+        "config": {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]),
+                   "atoms": N, "systems": S, "nstlist": nstlist, "nstprune": cfg["nstprune"],
+                   "list_entries": int(first_stats["n_entries"]),
+                   "work_items": int(first_stats["n_work_items"]),
+                   "exec": ctx.get_exec()},
+        "step_path": "nb_step_graph (prune fused, HIP graph replay, positions copied in place)",
         "effective_pairs_per_step": float(eff[W:].mean()),
         "raw_pairs_per_s": comp_timed / wall,
         "ns_per_day_equiv": 0.1728 / (wall / K),
+        "ms_per_step_eager_fused": 1e3 * wall_eager / K,
         "ms_per_step_separate_prune_call": 1e3 * wall_sep / K,
         "fwd_bwd_pairs_per_s": (eff_timed / wall_fb) if wall_fb else None,
         "fwd_bwd_ms_per_step": (1e3 * wall_fb / K) if wall_fb else None,
         "bwd_over_fwd_kernel": (tm_fb["backward"][0] / max(tm_fb["forces"][0], 1e-9))
         if tm_fb else None,
         "kernel_us": {k: (1e3 * v[0] / v[1] if v[1] else None)
-                      for k, v in (tm_fb or tm).items()},
+                      for k, v in (tm_fb or tm_eager).items()},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
-                     "kernel": "k_nb_fwd<Ewald, energy>",
-                     "flop_per_pair": FLOP_PER_PAIR_EWALD_E,
+                     "kernel": "k_nb_fwd<%s, energy>" % ("Ewald" if coul == "ewald" else "RF"),
+                     "flop_per_pair": flop,
                      "avg_launch_us": 1e3 * plain_ms / max(plain_calls, 1),
-                     "fused_prune_launch_us": 1e3 * fwd_ms / max(fwd_calls, 1),
+                     "fused_prune_launch_us": 1e3 * fused_ms / max(fused_calls, 1),
                      "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED},
         "work_efficiency": float(eff[W:].sum() / max(comp[W:].sum(), 1)),
         "list": {"outer_cluster_pairs": int(first_stats["outer_pairs"]),
                  "bb_cluster_pairs": int(first_stats["bb_pairs"]),
                  "mean_inner_cluster_pairs": float(inner[W:].mean())},
     }
+    if tune:
+        result["autotune"] = tune
 
     if not args.no_cpu_baseline:
-        log("cpu baseline: FP64 oracle, one full evaluation of the box")
-        tb = W  # a timed-range step
-        # recompute the GPU result at step tb for the comparison (list state of that step)
+        tb = W  # a timed-range step: recompute the GPU result with that step's list state
+        log("cpu baseline: FP64 oracle on a bounded sample at step %d" % tb)
         for t in range(tb + 1):
-            step(t)
+            step(t, "eager")
         torch.cuda.synchronize()
-        xs = (traj[t].cpu().numpy() for t in range(tb, T))
+        x_np = traj[tb].cpu().numpy()
         fe = f.cpu().numpy()
-        ee = e.cpu().numpy()[0]
-        dt, E, F, cores, n_eval = cpu_baseline(s, xs, cfg)
-        err_f = float(np.linalg.norm(fe - F) / np.linalg.norm(F))
-        err_e = [float(abs(ee[k] - E[k]) / abs(E[k])) for k in range(2)]
-        result["cpu_baseline"] = {"value": float(eff[tb:tb + n_eval].mean()) / dt,
+        ee = e.cpu().numpy()
+        dt, frac, sample, res = cpu_baseline(c, cfg, x_np)
+        par = {"step": tb}
+        if S > 1:
+            offs = c["offsets"]
+            num = den = 0.0
+            worst = 0.0
+            for r, E, F in res:
+                a0, a1 = int(offs[r]), int(offs[r + 1])
+                num += float(np.sum((fe[a0:a1] - F) ** 2))
+                den += float(np.sum(F ** 2))
+                worst = max(worst, float(np.max(np.abs(ee[r] - E) / np.abs(E))))
+            par.update(force_rel_rms=math.sqrt(num / den), energy_rel_max=worst,
+                       replicas=len(res))
+        elif res[0][1] is None:
+            sel, _, F = res[0]
+            par.update(force_rel_rms=float(np.linalg.norm(fe[sel] - F) / np.linalg.norm(F)),
+                       sampled_atoms=int(sel.size))
+        else:
+            _, E, F = res[0]
+            par.update(force_rel_rms=float(np.linalg.norm(fe - F) / np.linalg.norm(F)),
+                       energy_rel=[float(abs(ee[0, k] - E[k]) / abs(E[k])) for k in range(2)])
+        import oracle
+        result["cpu_baseline"] = {"value": float(eff[tb]) * frac / dt,
                                   "unit": "pair interactions/s",
-                                  "cores": cores, "kind": "oracle",
-                                  "sample": "%d FP64 brute-force force+energy evaluations of the "
-                                            "96k box (all N(N-1)/2 minimum-image pairs) at steps "
-                                            "%d.." % (n_eval, tb),
-                                  "seconds_per_eval": dt}
-        result["parity_at_step"] = {"step": tb, "force_rel_rms": err_f, "energy_rel": err_e}
-        log("oracle %.2f s; GPU force rel RMS %.2e energy rel %s" % (dt, err_f, err_e))
+                                  "cores": oracle.num_threads(), "kind": "oracle",
+                                  "sample": sample + " at step %d" % tb,
+                                  "seconds": dt}
+        result["parity_at_step"] = par
+        log("oracle %.2f s; parity %s" % (dt, par))
     print(json.dumps(result), flush=True)
 
 

@@ -188,6 +188,58 @@ nb_status nb_step(nb_ctx* ctx, const float* x, const float* q, const float* lj, 
                   double* energy, double* virial, uint32_t flags, int64_t steps_since_build);
 
 /*
+ * nb_step replayed from a HIP graph.  The first call for a given rolling part, flag set
+ * and set of array pointers after a list change captures the step's kernels (gather,
+ * pair kernel, reductions) on a private stream and instantiates a graph; later calls
+ * with the same key launch that graph on the context's stream as one submission.  This
+ * removes the gaps of a sequence of short dependent kernels (Sec. V.F) and the host
+ * cost of issuing them.  Same results as nb_step, bit for bit.  Graphs are dropped at
+ * every nb_pairlist_build, nb_set_exec and nb_autotune; at most nstprune + 4 are kept.
+ * The arrays must stay at the same addresses for a graph to be reused (update positions
+ * in place).  Errors as nb_step; NB_ERR_HIP if capture or instantiation fails.
+ */
+nb_status nb_step_graph(nb_ctx* ctx, const float* x, const float* q, const float* lj,
+                        float* f, double* energy, double* virial, uint32_t flags,
+                        int64_t steps_since_build);
+
+/*
+ * Execution shape of the pair kernel.  Work items hold at most item_width entries of
+ * one super-cluster's list (long lists are split for parallelism, Sec. V.F);
+ * exec_mode selects how wavefronts take items:
+ *   NB_EXEC_STATIC  one wavefront per item in item order;
+ *   NB_EXEC_XCD     the same, blocks renumbered so that each of the 8 XCDs (each with its
+ *                   own L2) processes one contiguous range of neighbouring items;
+ *   NB_EXEC_QUEUE   persistent: one resident grid takes items from an atomic queue,
+ *                   most pair work first (long lists not scheduled late, Sec. V.F).
+ * Results do not depend on exec_mode (each item writes its own partial sums); they
+ * depend on item_width only through the order of the final per-atom sums (a few ulp).
+ */
+enum { NB_EXEC_STATIC = 0, NB_EXEC_XCD = 1, NB_EXEC_QUEUE = 2 };
+typedef struct {
+    int32_t item_width;   /* entries per work item, 1..64 */
+    int32_t exec_mode;    /* NB_EXEC_* */
+    double us_per_call;   /* nb_autotune: median time of one nb_forces call, microseconds */
+} nb_exec_config;
+
+/* Fix the item width (0 = the built-in rule, about 8192 items, width 8..64) and mode;
+ * applies to the current list at once and to every later build.  Errors: NB_ERR_ARG. */
+nb_status nb_set_exec(nb_ctx* ctx, int32_t item_width, int32_t exec_mode);
+nb_status nb_get_exec(nb_ctx* ctx, nb_exec_config* out);
+
+/*
+ * [sync] Autotuner (the paper calls for dynamic auto-tuning of code flavors, Sec. VII):
+ * times nb_forces(x, q, lj, flags) on the current list for item widths 8, 16, 24, 32,
+ * 48, 64 and the three execution modes (repeats timed calls after one warm-up each,
+ * HIP events, median), writes up to cap trials to host trials[] and their number to
+ * *n_trials, and keeps the fastest (also returned in *best) for this and later builds.
+ * flags: NB_F_ENERGY and/or NB_F_VIRIAL.  Allocates and frees its own output buffers.
+ * Errors: NB_ERR_STATE without a list, NB_ERR_ARG.
+ */
+nb_status nb_autotune(nb_ctx* ctx, const float* x, const float* q, const float* lj,
+                      uint32_t flags, int32_t repeats, nb_exec_config* trials, int32_t cap,
+                      int32_t* n_trials, nb_exec_config* best);
+
+/*
  * Backward pass of nb_forces over the frozen inner list: given grad_f = dL/dF (dev
  * float[N][3]) and optionally grad_energy = dL/dE (dev double[n_systems][2], or NULL),
  * writes grad_x = dL/dx (dev float[N][3]; the Hessian-vector product of the energy with

@@ -15,7 +15,10 @@ NB_F_ENERGY, NB_F_VIRIAL, NB_F_ACCUMULATE = 1, 2, 4
 EXPORTS = ["nb_create", "nb_destroy", "nb_set_topology", "nb_grid_build", "nb_pairlist_build",
            "nb_prune_rolling", "nb_forces", "nb_step", "nb_forces_backward", "nb_get_grid",
            "nb_get_grid_dims", "nb_get_pairs", "nb_get_stats", "nb_set_timing", "nb_get_timing",
-           "nb_strerror", "nb_last_error"]
+           "nb_strerror", "nb_last_error", "nb_step_graph", "nb_set_exec", "nb_get_exec",
+           "nb_autotune"]
+NB_EXEC_STATIC, NB_EXEC_XCD, NB_EXEC_QUEUE = 0, 1, 2
+EXEC_MODES = {"static": NB_EXEC_STATIC, "xcd": NB_EXEC_XCD, "queue": NB_EXEC_QUEUE}
 NB_T_FORCES, NB_T_FORCE_REDUCE, NB_T_PRUNE, NB_T_BACKWARD, NB_T_BACKWARD_REDUCE, NB_T_COUNT = range(6)
 TIMING_KINDS = ["forces", "force_reduce", "prune", "backward", "backward_reduce"]
 
@@ -35,6 +38,11 @@ class NbStats(ctypes.Structure):
         "n_atoms", "n_slots", "n_superclusters", "n_clusters", "n_entries", "n_work_items",
         "outer_pairs", "inner_pairs", "bb_pairs", "n_excl_rows", "effective_pairs",
         "computed_pairs", "grid_columns", "capacity_per_sc", "regrows")]
+
+
+class NbExecConfig(ctypes.Structure):
+    _fields_ = [("item_width", ctypes.c_int32), ("exec_mode", ctypes.c_int32),
+                ("us_per_call", ctypes.c_double)]
 
 
 _lib = None
@@ -60,6 +68,11 @@ def load():
         "nb_prune_rolling": ([P, P, i64], st),
         "nb_forces": ([P, P, P, P, P, P, P, u32], st),
         "nb_step": ([P, P, P, P, P, P, P, u32, i64], st),
+        "nb_step_graph": ([P, P, P, P, P, P, P, u32, i64], st),
+        "nb_set_exec": ([P, i32, i32], st),
+        "nb_get_exec": ([P, ctypes.POINTER(NbExecConfig)], st),
+        "nb_autotune": ([P, P, P, P, u32, i32, P, i32, ctypes.POINTER(i32),
+                         ctypes.POINTER(NbExecConfig)], st),
         "nb_forces_backward": ([P, P, P, P, P, P, P, P, P, u32], st),
         "nb_get_grid": ([P, P, i64, ctypes.POINTER(i64)], st),
         "nb_get_grid_dims": ([P, P], st),

@@ -18,7 +18,9 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import NB_F_ACCUMULATE, NB_F_ENERGY, NB_F_VIRIAL
+from ._lib import EXEC_MODES, NB_F_ACCUMULATE, NB_F_ENERGY, NB_F_VIRIAL, NbExecConfig
+
+_MODE_NAMES = {v: k for k, v in EXEC_MODES.items()}
 
 
 class NBError(RuntimeError):
@@ -144,9 +146,11 @@ class Context:
         return f, (e if energy else None), (vir if virial else None)
 
     def step(self, x, q, lj, steps_since_build: int, energy: bool = True, virial: bool = False,
-             f=None, e=None, vir=None, accumulate: bool = False):
+             f=None, e=None, vir=None, accumulate: bool = False, graph: bool = False):
         """Rolling prune of part (steps_since_build mod nstprune) fused into the force pass;
-        the same result as prune_rolling(x, steps_since_build) followed by forces(...)."""
+        the same result as prune_rolling(x, steps_since_build) followed by forces(...).
+        graph=True replays the step from a captured HIP graph (nb_step_graph): keep x, q,
+        lj and the outputs at fixed addresses (update them in place) so it is reused."""
         x = self._dev(x, (self.n_atoms, 3), torch.float32, "x")
         q = self._dev(q, (self.n_atoms,), torch.float32, "q")
         lj = self._dev(lj, (self.n_types, self.n_types, 2), torch.float32, "lj")
@@ -163,10 +167,41 @@ class Context:
                 vir = torch.empty((self.n_sys, 3, 3), dtype=torch.float64, device=self.device)
         if accumulate:
             flags |= NB_F_ACCUMULATE
-        self._check(self.lib.nb_step(self.h, _ptr(x), _ptr(q), _ptr(lj), _ptr(f),
-                                     _ptr(e) if energy else None, _ptr(vir) if virial else None,
-                                     flags, int(steps_since_build)), "nb_step")
+        fn = self.lib.nb_step_graph if graph else self.lib.nb_step
+        self._check(fn(self.h, _ptr(x), _ptr(q), _ptr(lj), _ptr(f),
+                       _ptr(e) if energy else None, _ptr(vir) if virial else None,
+                       flags, int(steps_since_build)), "nb_step_graph" if graph else "nb_step")
         return f, (e if energy else None), (vir if virial else None)
+
+    def set_exec(self, item_width: int = 0, mode: str = "static"):
+        """Item width (0 = built-in rule) and execution mode ('static', 'xcd', 'queue')."""
+        self._check(self.lib.nb_set_exec(self.h, int(item_width), EXEC_MODES[mode]),
+                    "nb_set_exec")
+
+    def get_exec(self) -> dict:
+        out = NbExecConfig()
+        self._check(self.lib.nb_get_exec(self.h, ctypes.byref(out)), "nb_get_exec")
+        return {"item_width": out.item_width, "mode": _MODE_NAMES[out.exec_mode]}
+
+    def autotune(self, x, q, lj, energy: bool = True, virial: bool = False, repeats: int = 5):
+        """Time nb_forces over item widths and execution modes on the current list, keep the
+        fastest; returns (best, trials) as dicts with item_width, mode, us_per_call."""
+        x = self._dev(x, (self.n_atoms, 3), torch.float32, "x")
+        q = self._dev(q, (self.n_atoms,), torch.float32, "q")
+        lj = self._dev(lj, (self.n_types, self.n_types, 2), torch.float32, "lj")
+        flags = (NB_F_ENERGY if energy else 0) | (NB_F_VIRIAL if virial else 0)
+        cap = 64
+        trials = (NbExecConfig * cap)()
+        n = ctypes.c_int32(0)
+        best = NbExecConfig()
+        self._check(self.lib.nb_autotune(self.h, _ptr(x), _ptr(q), _ptr(lj), flags, int(repeats),
+                                         ctypes.cast(trials, ctypes.c_void_p), cap,
+                                         ctypes.byref(n), ctypes.byref(best)), "nb_autotune")
+
+        def d(t):
+            return {"item_width": t.item_width, "mode": _MODE_NAMES[t.exec_mode],
+                    "us_per_call": t.us_per_call}
+        return d(best), [d(trials[i]) for i in range(min(n.value, cap))]
 
     def backward(self, x, q, lj, grad_f, grad_energy=None, need_x=True, need_q=True,
                  need_lj=True, accumulate: bool = False):

@@ -14,6 +14,8 @@
 // j-partials of the entries that reference its cluster (consecutive by construction)
 // and the i-partials of its super-cluster's items with compensated (Neumaier)
 // single-precision sums, and writes the force in the caller's atom order.
+#include <algorithm>
+
 #include "nb_erfc_coeffs.h"
 #include "nb_internal.h"
 
@@ -151,33 +153,24 @@ __device__ __forceinline__ void pair_block(float xi, float yi, float zi, const f
 // Per-cluster scalars of the item's eight i-clusters (kept in registers).
 #define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
+// The work of one item (one wavefront): s_qt is the wavefront's 64-entry LDS table of
+// i-charges and types, s_lj the block's LJ table.
 template <int COUL, bool ENERGY, bool VIRIAL, bool PRUNE>
-__global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIRIAL ? 3 : 4))) void k_nb_fwd(
+__device__ __forceinline__ void fwd_item(
+    const int item, const int lane, float2* s_qt, const float4* __restrict__ s_lj,
     const NbItem* __restrict__ items, NbEntry* __restrict__ entries,
     const uint64_t* __restrict__ excl_rows, const float4* __restrict__ xq,
     const int32_t* __restrict__ type_slot, const float4* __restrict__ cl_bb,
     const NbScInfo* __restrict__ sc_info, const NbSys* __restrict__ sys,
-    const float* __restrict__ lj, float4* __restrict__ jpart, float4* __restrict__ ipart,
-    double* __restrict__ epart, int epart_stride, NbKParams kp, int n_items, int prune_i0,
-    int prune_i1, float r2_inner) {
-    extern __shared__ float4 s_lj[];
-    __shared__ float2 s_qt_all[kFwdWaves][kScAtoms];   // per wave: (K q_i, type_i * T)
+    float4* __restrict__ jpart, float4* __restrict__ ipart, double* __restrict__ epart,
+    const int epart_stride, const NbKParams& kp, const int prune_i0, const int prune_i1,
+    const float r2_inner) {
     const int T = kp.n_types;
-    for (int i = threadIdx.x; i < T * T; i += blockDim.x) {
-        const float c6 = lj[2 * i], c12 = lj[2 * i + 1];
-        s_lj[i] = make_float4(6.0f * c6, 12.0f * c12, c12 * kp.rc_m12 - c6 * kp.rc_m6, c6);
-    }
-    __syncthreads();
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int lane = threadIdx.x & (kWave - 1);
-    const int item = blockIdx.x * kFwdWaves + wave;
-    if (item >= n_items) return;
     const NbItem it = items[item];
     const int ii = lane & 7, jj = lane >> 3;
     const int sc = it.sc, ci0 = kClustersPerSc * sc;
     const NbSys S = sys[sc_info[sc].sys];
     const int ibase = kScAtoms * sc + ii;
-    float2* s_qt = s_qt_all[wave];
     {
         // lane l holds slot l of the super-cluster: (8 c + ii) for c = l >> 3
         const float4 v = xq[kScAtoms * sc + lane];
@@ -310,6 +303,70 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
             epart[(size_t)9 * epart_stride + it.pos] = 64.0 * (double)nblock;
         }
     }
+}
+
+// Block b of a grid of g blocks is dispatched to XCD b mod 8 (round robin).  Renumber
+// the blocks so that each XCD takes one contiguous range of items: neighbouring
+// super-clusters share j-clusters, so their coordinates stay in that XCD's L2.
+__device__ inline int xcd_block(int b, int g) {
+    const int x = b & (kXcds - 1), k = b / kXcds;
+    const int q = g / kXcds, r = g % kXcds;
+    return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+// Execution modes (chosen per context, by hand or by the autotuner):
+//   kExecStatic  one wavefront per item, item = 4 block + wave;
+//   kExecXcd     the same with the XCD-contiguous block numbering above;
+//   kExecQueue   persistent: a grid that fills the device once; wavefronts take items
+//                from an atomic counter in the order given by `order` (most pair work
+//                first), until the counter passes n_items.  queue[0] is the counter,
+//                queue[1] counts finished wavefronts; the last one resets both to zero,
+//                so the next launch needs no clearing pass (and a captured graph none).
+template <int COUL, bool ENERGY, bool VIRIAL, bool PRUNE>
+__global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIRIAL ? 3 : 4))) void k_nb_fwd(
+    const NbItem* __restrict__ items, NbEntry* __restrict__ entries,
+    const uint64_t* __restrict__ excl_rows, const float4* __restrict__ xq,
+    const int32_t* __restrict__ type_slot, const float4* __restrict__ cl_bb,
+    const NbScInfo* __restrict__ sc_info, const NbSys* __restrict__ sys,
+    const float* __restrict__ lj, float4* __restrict__ jpart, float4* __restrict__ ipart,
+    double* __restrict__ epart, int epart_stride, NbKParams kp, int n_items, int prune_i0,
+    int prune_i1, float r2_inner, int mode, const int32_t* __restrict__ order,
+    int32_t* __restrict__ queue) {
+    extern __shared__ float4 s_lj[];
+    __shared__ float2 s_qt_all[kFwdWaves][kScAtoms];   // per wave: (K q_i, type_i * T)
+    const int T = kp.n_types;
+    for (int i = threadIdx.x; i < T * T; i += blockDim.x) {
+        const float c6 = lj[2 * i], c12 = lj[2 * i + 1];
+        s_lj[i] = make_float4(6.0f * c6, 12.0f * c12, c12 * kp.rc_m12 - c6 * kp.rc_m6, c6);
+    }
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x & (kWave - 1);
+    float2* s_qt = s_qt_all[wave];
+#define NB_ITEM_ARGS                                                                    \
+    lane, s_qt, s_lj, items, entries, excl_rows, xq, type_slot, cl_bb, sc_info, sys, jpart, \
+        ipart, epart, epart_stride, kp, prune_i0, prune_i1, r2_inner
+    if (mode == kExecQueue) {
+        for (;;) {
+            int slot = 0;
+            if (lane == 0) slot = atomicAdd(queue, 1);
+            slot = __builtin_amdgcn_readfirstlane(slot);
+            if (slot >= n_items) break;
+            fwd_item<COUL, ENERGY, VIRIAL, PRUNE>(order[slot], NB_ITEM_ARGS);
+        }
+        if (lane == 0) {
+            const int waves = (int)gridDim.x * kFwdWaves;
+            if (atomicAdd(queue + 1, 1) == waves - 1) {
+                atomicExch(queue, 0);
+                atomicExch(queue + 1, 0);
+            }
+        }
+        return;
+    }
+    const int b = (mode == kExecXcd) ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int item = b * kFwdWaves + wave;
+    if (item < n_items) fwd_item<COUL, ENERGY, VIRIAL, PRUNE>(item, NB_ITEM_ARGS);
+#undef NB_ITEM_ARGS
 }
 
 // Per-slot gather of user-order coordinates (and charges) into slot order, wrapped with
@@ -480,27 +537,66 @@ __global__ void k_energy_final(NbDev d, double* __restrict__ energy, double* __r
 
 inline int blocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
+// Resident blocks per CU of one flavor (queried once; the LJ table's LDS is small next
+// to the per-wave tables, so the first query holds for every table size).
+template <int COUL, bool E, bool V, bool P>
+int fwd_blocks_per_cu(size_t lds) {
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_nb_fwd<COUL, E, V, P>,
+                                                         kFwdThreads, lds) != hipSuccess)
+            nb = 0;
+        per_cu = nb > 0 ? nb : 1;
+    }
+    return per_cu;
+}
+
+template <int COUL, bool P>
+void prepare_fwd_c(uint32_t flags, size_t lds) {
+    const bool E = (flags & NB_F_ENERGY) != 0, V = (flags & NB_F_VIRIAL) != 0;
+    if (E && V) fwd_blocks_per_cu<COUL, true, true, P>(lds);
+    else if (E) fwd_blocks_per_cu<COUL, true, false, P>(lds);
+    else if (V) fwd_blocks_per_cu<COUL, false, true, P>(lds);
+    else fwd_blocks_per_cu<COUL, false, false, P>(lds);
+}
+
 template <int COUL, bool E, bool V, bool P>
 void launch_fwd_t(const NbDev& d, const NbKParams& kp, const float* lj, int n_items,
-                  int pi0, int pi1, float r2_inner, hipStream_t s) {
+                  int pi0, int pi1, float r2_inner, int mode, hipStream_t s) {
     const size_t lds = sizeof(float4) * (size_t)kp.n_types * kp.n_types;
-    hipLaunchKernelGGL((k_nb_fwd<COUL, E, V, P>), dim3(blocks(n_items, kFwdWaves)),
-                       dim3(kFwdThreads), lds, s, d.items, d.entries, d.excl_rows, d.xq,
-                       d.type_slot, d.cl_bb, d.sc_info, d.sys, lj, d.jpart, d.ipart, d.epart,
-                       d.epart_stride, kp, n_items, pi0, pi1, r2_inner);
+    int grid = blocks(n_items, kFwdWaves);
+    if (mode == kExecQueue)    // one resident wave of blocks over the whole device
+        grid = std::min(grid, fwd_blocks_per_cu<COUL, E, V, P>(lds) * std::max(d.n_cu, 1));
+    hipLaunchKernelGGL((k_nb_fwd<COUL, E, V, P>), dim3(grid), dim3(kFwdThreads), lds, s,
+                       d.items, d.entries, d.excl_rows, d.xq, d.type_slot, d.cl_bb, d.sc_info,
+                       d.sys, lj, d.jpart, d.ipart, d.epart, d.epart_stride, kp, n_items, pi0,
+                       pi1, r2_inner, mode, d.item_order, d.queue);
 }
 
 template <int COUL, bool P>
 void launch_fwd_c(const NbDev& d, const NbKParams& kp, uint32_t flags, const float* lj,
-                  int n_items, int pi0, int pi1, float r2_inner, hipStream_t s) {
+                  int n_items, int pi0, int pi1, float r2_inner, int mode, hipStream_t s) {
     const bool E = (flags & NB_F_ENERGY) != 0, V = (flags & NB_F_VIRIAL) != 0;
-    if (E && V) launch_fwd_t<COUL, true, true, P>(d, kp, lj, n_items, pi0, pi1, r2_inner, s);
-    else if (E) launch_fwd_t<COUL, true, false, P>(d, kp, lj, n_items, pi0, pi1, r2_inner, s);
-    else if (V) launch_fwd_t<COUL, false, true, P>(d, kp, lj, n_items, pi0, pi1, r2_inner, s);
-    else launch_fwd_t<COUL, false, false, P>(d, kp, lj, n_items, pi0, pi1, r2_inner, s);
+    if (E && V) launch_fwd_t<COUL, true, true, P>(d, kp, lj, n_items, pi0, pi1, r2_inner, mode, s);
+    else if (E) launch_fwd_t<COUL, true, false, P>(d, kp, lj, n_items, pi0, pi1, r2_inner, mode, s);
+    else if (V) launch_fwd_t<COUL, false, true, P>(d, kp, lj, n_items, pi0, pi1, r2_inner, mode, s);
+    else launch_fwd_t<COUL, false, false, P>(d, kp, lj, n_items, pi0, pi1, r2_inner, mode, s);
 }
 
 }  // namespace
+
+hipError_t prepare_forces(int coulomb, uint32_t flags, bool prune, int n_types) {
+    const size_t lds = sizeof(float4) * (size_t)n_types * n_types;
+    if (coulomb == NB_COUL_RF) {
+        if (prune) prepare_fwd_c<NB_COUL_RF, true>(flags, lds);
+        else prepare_fwd_c<NB_COUL_RF, false>(flags, lds);
+    } else {
+        if (prune) prepare_fwd_c<NB_COUL_EWALD, true>(flags, lds);
+        else prepare_fwd_c<NB_COUL_EWALD, false>(flags, lds);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_gather(const NbDev& d, const float* x, const float* q, float4* out,
                          int n_slots, hipStream_t s) {
@@ -512,15 +608,17 @@ hipError_t launch_gather(const NbDev& d, const float* x, const float* q, float4*
 
 hipError_t launch_forces(const NbDev& d, const NbKParams& kp, int coulomb, uint32_t flags,
                          const float* lj, int n_items, int prune_i0, int prune_i1,
-                         float r2_inner, hipStream_t s) {
+                         float r2_inner, int mode, hipStream_t s) {
     if (n_items <= 0) return hipGetLastError();
     const bool P = prune_i1 > prune_i0;
+    const int i0 = P ? prune_i0 : 0, i1 = P ? prune_i1 : 0;
+    const float r2 = P ? r2_inner : 0.f;
     if (coulomb == NB_COUL_RF) {
-        if (P) launch_fwd_c<NB_COUL_RF, true>(d, kp, flags, lj, n_items, prune_i0, prune_i1, r2_inner, s);
-        else launch_fwd_c<NB_COUL_RF, false>(d, kp, flags, lj, n_items, 0, 0, 0.f, s);
+        if (P) launch_fwd_c<NB_COUL_RF, true>(d, kp, flags, lj, n_items, i0, i1, r2, mode, s);
+        else launch_fwd_c<NB_COUL_RF, false>(d, kp, flags, lj, n_items, i0, i1, r2, mode, s);
     } else {
-        if (P) launch_fwd_c<NB_COUL_EWALD, true>(d, kp, flags, lj, n_items, prune_i0, prune_i1, r2_inner, s);
-        else launch_fwd_c<NB_COUL_EWALD, false>(d, kp, flags, lj, n_items, 0, 0, 0.f, s);
+        if (P) launch_fwd_c<NB_COUL_EWALD, true>(d, kp, flags, lj, n_items, i0, i1, r2, mode, s);
+        else launch_fwd_c<NB_COUL_EWALD, false>(d, kp, flags, lj, n_items, i0, i1, r2, mode, s);
     }
     return hipGetLastError();
 }

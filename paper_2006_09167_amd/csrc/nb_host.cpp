@@ -23,8 +23,22 @@ struct nb_ctx {
     int64_t n_entries = 0;
     int32_t n_items = 0;
     int32_t cap = 0;          // entries per super-cluster in the search scratch
-    int32_t item_w = 0;       // entries per work item
+    int32_t item_w = 0;       // entries per work item of the current list
+    int32_t fixed_w = 0;      // item width chosen by nb_set_exec / nb_autotune (0 = rule)
+    int32_t exec_mode = kExecStatic;
+    uint64_t list_gen = 0;    // bumped whenever items or launch shapes change
+    // graphs of nb_step_graph: key = (part, flags, pointers, list_gen)
+    struct GraphEntry {
+        int part;
+        uint32_t flags;
+        const void* ptr[7];
+        uint64_t gen;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+    hipStream_t cap_stream = nullptr;
     std::vector<int32_t> part_start;
+    int32_t h_totals[8] = {};  // host copy of the device totals after the last list change
     nb_stats stats{};
     std::string err;
     // allocated element counts
@@ -117,7 +131,17 @@ nb_status ensure_device(nb_ctx* c) {
     NB_HIP(c, dev_alloc(d.sys, c->n_sys));
     NB_HIP(c, dev_alloc(d.sys_sc_start, c->n_sys + 1));
     NB_HIP(c, dev_alloc(d.part_start, c->p.nstprune + 1));
+    NB_HIP(c, dev_alloc(d.queue, 2));
+    NB_HIP(c, launch_fill(d.queue, 2, 0, c->stream));
+    int n_cu = 0;
+    NB_HIP(c, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
+    d.n_cu = n_cu;
     return NB_OK;
+}
+
+void drop_graphs(nb_ctx* c) {
+    for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
 }
 
 hipEvent_t take_event(nb_ctx* c) {
@@ -236,7 +260,9 @@ void nb_destroy(nb_ctx* c) {
                     d.sc_istart, d.sc_icount, d.scratch, d.entries, d.entry_sc, d.items,
                     d.part_start, d.excl_rows, d.jseg_count, d.jseg_start, d.jseg_fill,
                     d.jseg_entries, d.totals, d.flags, d.jpart, d.ipart, d.epart, d.glj_part,
-                    d.dstat};
+                    d.dstat, d.item_cost, d.item_order, d.queue};
+    drop_graphs(c);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     for (void* q : ptrs)
         if (q) hipFree(q);
     for (int k = 0; k < NB_T_COUNT; ++k)
@@ -392,6 +418,86 @@ nb_status nb_grid_build(nb_ctx* c, const float* x, const float* box) {
     return NB_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Entries per work item: the width fixed by nb_set_exec / nb_autotune, else enough items
+// to fill the device (about 8192), long lists split (Sec. V.F), between 8 and 64.
+int item_width(const nb_ctx* c) {
+    if (c->fixed_w > 0) return c->fixed_w;
+    const int64_t target_items = 8192;
+    return (int)std::min<int64_t>(64, std::max<int64_t>(8, (c->n_entries + target_items - 1) /
+                                                               target_items));
+}
+
+// Split every super-cluster's entries into items of at most W entries (rolling-part
+// major order); at a build also copy the entries out of the search scratch.
+nb_status make_items(nb_ctx* c, int W, bool copy_entries) {
+    NbDev& d = c->d;
+    const size_t item_cap = (size_t)c->n_sc + (size_t)(c->n_entries / W) + 1;
+    if (item_cap > c->a_items || !d.items) {
+        const size_t ni = item_cap + item_cap / 8 + 64;
+        NB_HIP(c, dev_alloc(d.items, ni));
+        NB_HIP(c, dev_alloc(d.item_cost, ni));
+        NB_HIP(c, dev_alloc(d.item_order, ni));
+        NB_HIP(c, dev_alloc(d.ipart, ni * kScAtoms));
+        NB_HIP(c, dev_alloc(d.epart, ni * kEpartStride));
+        d.epart_stride = (int32_t)ni;
+        NB_HIP(c, dev_alloc(d.glj_part, ni * (size_t)c->p.n_types * c->p.n_types * 2));
+        c->a_items = ni;
+    }
+    NB_HIP(c, launch_make_items(d, c->n_sc, c->cap, W, c->p.nstprune, copy_entries, c->stream));
+    c->item_w = W;
+    return NB_OK;
+}
+
+// After make_items: item count, rolling-part ranges, the chunk tables of the two-stage
+// per-system reductions and the queue order of the items.
+nb_status finish_items(nb_ctx* c) {
+    NbDev& d = c->d;
+    nb_status st = to_host(c, c->h_totals, d.totals, 8);
+    if (st != NB_OK) return st;
+    c->n_items = c->h_totals[1];
+    c->part_start.resize(c->p.nstprune + 1);
+    st = to_host(c, c->part_start.data(), d.part_start, c->p.nstprune + 1);
+    if (st != NB_OK) return st;
+    // item ranks of system s are [sc_ipos[sys_sc_start[s]], sc_ipos[sys_sc_start[s+1]])
+    std::vector<int32_t> sss(c->n_sys + 1), ipos((size_t)c->n_sc + 1);
+    st = to_host(c, sss.data(), d.sys_sc_start, sss.size());
+    if (st != NB_OK) return st;
+    st = to_host(c, ipos.data(), d.sc_ipos, ipos.size());
+    if (st != NB_OK) return st;
+    std::vector<int4> ch;
+    std::vector<int32_t> start(c->n_sys + 1, 0);
+    for (int s = 0; s < c->n_sys; ++s) {
+        start[s] = (int32_t)ch.size();
+        const int p0 = ipos[sss[s]], p1 = ipos[sss[s + 1]];
+        for (int p = p0; p < p1; p += kChunkItems)
+            ch.push_back(make_int4(s, p, std::min(p1, p + kChunkItems), 0));
+    }
+    start[c->n_sys] = (int32_t)ch.size();
+    const size_t nglj = (size_t)(c->n_items + kChunkItems - 1) / kChunkItems;
+    const size_t ncap = std::max(ch.size(), nglj) + 1;
+    NB_HIP(c, dev_alloc(d.chunks, ch.size() + 1));
+    NB_HIP(c, dev_alloc(d.sys_chunk_start, c->n_sys + 1));
+    NB_HIP(c, dev_alloc(d.cpart, ncap * kChunkVals));
+    if (!ch.empty())
+        NB_HIP(c, hipMemcpy(d.chunks, ch.data(), ch.size() * sizeof(int4), hipMemcpyHostToDevice));
+    NB_HIP(c, hipMemcpy(d.sys_chunk_start, start.data(), start.size() * sizeof(int32_t),
+                        hipMemcpyHostToDevice));
+    d.n_chunks = (int32_t)ch.size();
+    NB_HIP(c, launch_item_order(d, c->n_items, c->stream));
+    c->stats.n_work_items = c->n_items;
+    c->list_gen++;
+    drop_graphs(c);
+    return NB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 nb_status nb_pairlist_build(nb_ctx* c) {
     if (!c) return NB_ERR_ARG;
     if (!c->has_grid) return fail(c, NB_ERR_STATE, "nb_grid_build has not been called");
@@ -440,12 +546,7 @@ nb_status nb_pairlist_build(nb_ctx* c) {
     st = to_host(c, totals, d.totals, 8);
     if (st != NB_OK) return st;
     const int64_t E = totals[0];
-    // Work items of at most W entries: enough items to fill the device, long lists split
-    // (Sec. V.F), W between 8 and 64.
-    const int64_t target_items = 8192;
-    int W = (int)std::min<int64_t>(64, std::max<int64_t>(8, (E + target_items - 1) / target_items));
-    c->item_w = W;
-    const size_t item_cap = (size_t)n_sc + (size_t)(E / W) + 1;
+    c->n_entries = E;
     if ((size_t)E > c->a_entries || !d.entries) {
         const size_t ne = (size_t)E + E / 8 + 64;
         NB_HIP(c, dev_alloc(d.entries, ne));
@@ -455,63 +556,21 @@ nb_status nb_pairlist_build(nb_ctx* c) {
         NB_HIP(c, dev_alloc(d.jpart, ne * kClusterSize));
         c->a_entries = ne;
     }
-    if (item_cap > c->a_items || !d.items) {
-        const size_t ni = item_cap + item_cap / 8 + 64;
-        NB_HIP(c, dev_alloc(d.items, ni));
-        NB_HIP(c, dev_alloc(d.ipart, ni * kScAtoms));
-        NB_HIP(c, dev_alloc(d.epart, ni * kEpartStride));
-        d.epart_stride = (int32_t)ni;
-        NB_HIP(c, dev_alloc(d.glj_part, ni * (size_t)c->p.n_types * c->p.n_types * 2));  // [key][rank]
-        c->a_items = ni;
-    }
-    NB_HIP(c, launch_make_items(d, n_sc, c->cap, W, c->p.nstprune, c->stream));
+    st = make_items(c, item_width(c), true);
+    if (st != NB_OK) return st;
     NB_HIP(c, launch_fill(d.totals + 2, 2, 0, c->stream));
     NB_HIP(c, launch_fill(d.flags + kFlagNumRows, 1, 0, c->stream));
     NB_HIP(c, launch_list_finish(d, n_sc, E, c->n_cl, c->stream));
-    st = to_host(c, totals, d.totals, 8);
-    if (st != NB_OK) return st;
-    c->n_entries = E;
-    c->n_items = totals[1];
-    c->part_start.resize(c->p.nstprune + 1);
-    st = to_host(c, c->part_start.data(), d.part_start, c->p.nstprune + 1);
-    if (st != NB_OK) return st;
     st = to_host(c, flags, d.flags, kFlagCount);
     if (st != NB_OK) return st;
-    // Chunks of the two-stage per-system reductions: item ranks of system s are the range
-    // [sc_ipos[sys_sc_start[s]], sc_ipos[sys_sc_start[s+1]]).
-    {
-        std::vector<int32_t> sss(c->n_sys + 1), ipos((size_t)n_sc + 1);
-        st = to_host(c, sss.data(), d.sys_sc_start, sss.size());
-        if (st != NB_OK) return st;
-        st = to_host(c, ipos.data(), d.sc_ipos, ipos.size());
-        if (st != NB_OK) return st;
-        std::vector<int4> ch;
-        std::vector<int32_t> start(c->n_sys + 1, 0);
-        for (int s = 0; s < c->n_sys; ++s) {
-            start[s] = (int32_t)ch.size();
-            const int p0 = ipos[sss[s]], p1 = ipos[sss[s + 1]];
-            for (int p = p0; p < p1; p += kChunkItems)
-                ch.push_back(make_int4(s, p, std::min(p1, p + kChunkItems), 0));
-        }
-        start[c->n_sys] = (int32_t)ch.size();
-        const size_t nglj = (size_t)(c->n_items + kChunkItems - 1) / kChunkItems;
-        const size_t ncap = std::max(ch.size(), nglj) + 1;
-        NB_HIP(c, dev_alloc(d.chunks, ch.size() + 1));
-        NB_HIP(c, dev_alloc(d.sys_chunk_start, c->n_sys + 1));
-        NB_HIP(c, dev_alloc(d.cpart, ncap * kChunkVals));
-        if (!ch.empty())
-            NB_HIP(c, hipMemcpy(d.chunks, ch.data(), ch.size() * sizeof(int4), hipMemcpyHostToDevice));
-        NB_HIP(c, hipMemcpy(d.sys_chunk_start, start.data(), start.size() * sizeof(int32_t),
-                            hipMemcpyHostToDevice));
-        d.n_chunks = (int32_t)ch.size();
-    }
+    st = finish_items(c);
+    if (st != NB_OK) return st;
+    c->stats.outer_pairs = c->h_totals[2];
+    c->stats.inner_pairs = c->h_totals[3];
     c->stats.n_slots = c->n_slots;
     c->stats.n_superclusters = n_sc;
     c->stats.n_clusters = c->n_cl;
     c->stats.n_entries = E;
-    c->stats.n_work_items = c->n_items;
-    c->stats.outer_pairs = totals[2];
-    c->stats.inner_pairs = totals[3];
     c->stats.n_excl_rows = flags[kFlagNumRows];
     c->stats.capacity_per_sc = c->cap;
     c->has_list = true;
@@ -555,7 +614,7 @@ nb_status forces_impl(nb_ctx* c, const float* x, const float* q, const float* lj
     {
         TimedSection ts(c, NB_T_FORCES);
         NB_HIP(c, launch_forces(d, kp, c->p.coulomb, flags, lj, c->n_items, pi0, pi1,
-                                radius_sq(c->p.rinner), c->stream));
+                                radius_sq(c->p.rinner), c->exec_mode, c->stream));
     }
     TimedSection ts(c, NB_T_FORCE_REDUCE);
     NB_HIP(c, launch_reduce_forces(d, f, (flags & NB_F_ACCUMULATE) != 0, c->n_slots, c->stream));
@@ -572,15 +631,183 @@ nb_status nb_forces(nb_ctx* c, const float* x, const float* q, const float* lj, 
     return forces_impl(c, x, q, lj, f, energy, virial, flags, -1);
 }
 
-nb_status nb_step(nb_ctx* c, const float* x, const float* q, const float* lj, float* f,
-                  double* energy, double* virial, uint32_t flags, int64_t steps_since_build) {
-    if (!c) return NB_ERR_ARG;
+namespace {
+// Rolling part pruned by nb_step at steps_since_build (-1: none), or a status < 0.
+nb_status step_part(nb_ctx* c, int64_t steps_since_build, int* part) {
     if (!c->has_list) return fail(c, NB_ERR_STATE, "no pair list");
     if (steps_since_build < 0) return fail(c, NB_ERR_ARG, "negative step");
     if (steps_since_build >= c->p.nstlist)
         return fail(c, NB_ERR_STATE, "the outer list has expired (steps_since_build >= nstlist)");
-    const int part = steps_since_build == 0 ? -1 : (int)(steps_since_build % c->p.nstprune);
+    *part = steps_since_build == 0 ? -1 : (int)(steps_since_build % c->p.nstprune);
+    return NB_OK;
+}
+}  // namespace
+
+nb_status nb_step(nb_ctx* c, const float* x, const float* q, const float* lj, float* f,
+                  double* energy, double* virial, uint32_t flags, int64_t steps_since_build) {
+    if (!c) return NB_ERR_ARG;
+    int part = -1;
+    nb_status st = step_part(c, steps_since_build, &part);
+    if (st != NB_OK) return st;
     return forces_impl(c, x, q, lj, f, energy, virial, flags, part);
+}
+
+nb_status nb_step_graph(nb_ctx* c, const float* x, const float* q, const float* lj, float* f,
+                        double* energy, double* virial, uint32_t flags,
+                        int64_t steps_since_build) {
+    if (!c) return NB_ERR_ARG;
+    int part = -1;
+    nb_status st = step_part(c, steps_since_build, &part);
+    if (st != NB_OK) return st;
+    if (flags & ~(uint32_t)(NB_F_ENERGY | NB_F_VIRIAL | NB_F_ACCUMULATE))
+        return fail(c, NB_ERR_ARG, "unknown flag");
+    NB_HIP(c, hipSetDevice(c->device));
+    const void* key[7] = {x, q, lj, f, energy, virial, nullptr};
+    for (auto& g : c->graphs)
+        if (g.part == part && g.flags == flags && g.gen == c->list_gen &&
+            std::equal(key, key + 7, g.ptr)) {
+            NB_HIP(c, hipGraphLaunch(g.exec, c->stream));
+            return NB_OK;
+        }
+    // Capture the step's launches on a private stream (nothing runs during capture),
+    // without timing events, then replay the instantiated graph on the context's stream.
+    if (!c->cap_stream) NB_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    NB_HIP(c, prepare_forces(c->p.coulomb, flags, part >= 0, c->p.n_types));
+    const hipStream_t user = c->stream;
+    const bool timing = c->timing;
+    c->stream = c->cap_stream;
+    c->timing = false;
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) st = forces_impl(c, x, q, lj, f, energy, virial, flags, part);
+    hipGraph_t graph = nullptr;
+    const hipError_t e_end = (e == hipSuccess) ? hipStreamEndCapture(c->cap_stream, &graph) : e;
+    c->stream = user;
+    c->timing = timing;
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
+    if (st != NB_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return st;
+    }
+    if (e_end != hipSuccess) return hip_fail(c, e_end, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+    // one graph per rolling part and flag set is the steady state; bound the cache
+    const size_t max_graphs = (size_t)c->p.nstprune + 4;
+    if (c->graphs.size() >= max_graphs) {
+        hipGraphExecDestroy(c->graphs.front().exec);
+        c->graphs.erase(c->graphs.begin());
+    }
+    nb_ctx::GraphEntry g{};
+    g.part = part;
+    g.flags = flags;
+    std::copy(key, key + 7, g.ptr);
+    g.gen = c->list_gen;
+    g.exec = exec;
+    c->graphs.push_back(g);
+    NB_HIP(c, hipGraphLaunch(exec, c->stream));
+    return NB_OK;
+}
+
+nb_status nb_set_exec(nb_ctx* c, int32_t width, int32_t exec_mode) {
+    if (!c) return NB_ERR_ARG;
+    if (width < 0 || width > 64) return fail(c, NB_ERR_ARG, "item width must be 0 (rule) or 1..64");
+    if (exec_mode != kExecStatic && exec_mode != kExecXcd && exec_mode != kExecQueue)
+        return fail(c, NB_ERR_ARG, "unknown execution mode");
+    c->fixed_w = width;
+    c->exec_mode = exec_mode;
+    c->list_gen++;
+    if (c->d.flags) {
+        NB_HIP(c, hipSetDevice(c->device));
+        drop_graphs(c);
+    }
+    if (c->has_list && item_width(c) != c->item_w) {
+        nb_status st = make_items(c, item_width(c), false);
+        if (st != NB_OK) return st;
+        return finish_items(c);
+    }
+    return NB_OK;
+}
+
+nb_status nb_get_exec(nb_ctx* c, nb_exec_config* out) {
+    if (!c || !out) return NB_ERR_ARG;
+    out->item_width = c->has_list ? c->item_w : c->fixed_w;
+    out->exec_mode = c->exec_mode;
+    out->us_per_call = 0.0;
+    return NB_OK;
+}
+
+nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj,
+                      uint32_t flags, int32_t repeats, nb_exec_config* trials, int32_t cap,
+                      int32_t* n_trials, nb_exec_config* best) {
+    if (!c) return NB_ERR_ARG;
+    if (!c->has_list) return fail(c, NB_ERR_STATE, "no pair list");
+    if (flags & ~(uint32_t)(NB_F_ENERGY | NB_F_VIRIAL))
+        return fail(c, NB_ERR_ARG, "autotune flags: NB_F_ENERGY and NB_F_VIRIAL only");
+    if (repeats < 1 || repeats > 1000) return fail(c, NB_ERR_ARG, "repeats out of range");
+    if (cap < 0 || (cap > 0 && !trials)) return fail(c, NB_ERR_ARG, "trial buffer");
+    if (c->d.n_atoms > 0 && (!x || !q || !lj)) return fail(c, NB_ERR_ARG, "null array");
+    NB_HIP(c, hipSetDevice(c->device));
+    // outputs of the timed calls live in buffers of this call
+    float* f = nullptr;
+    double* ev = nullptr;
+    NB_HIP(c, dev_alloc(f, (size_t)c->d.n_atoms * 3));
+    hipError_t e = dev_alloc(ev, (size_t)c->n_sys * 11);
+    if (e != hipSuccess) {
+        hipFree(f);
+        return hip_fail(c, e, "autotune buffers");
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    const bool timing = c->timing;
+    c->timing = false;
+    const int widths[] = {8, 16, 24, 32, 48, 64};
+    const int modes[] = {kExecStatic, kExecXcd, kExecQueue};
+    nb_exec_config win{0, 0, 1e300};
+    int n = 0;
+    nb_status st = NB_OK;
+    for (int W : widths) {
+        if (st != NB_OK) break;
+        st = make_items(c, W, false);
+        if (st == NB_OK) st = finish_items(c);
+        for (int m : modes) {
+            if (st != NB_OK) break;
+            c->exec_mode = m;
+            std::vector<float> ms;
+            for (int r = 0; r <= repeats && st == NB_OK; ++r) {   // the first call warms up
+                hipEventRecord(e0, c->stream);
+                st = forces_impl(c, x, q, lj, f, ev, ev + 2 * c->n_sys, flags, -1);
+                hipEventRecord(e1, c->stream);
+                if (st == NB_OK && hipEventSynchronize(e1) != hipSuccess)
+                    st = fail(c, NB_ERR_HIP, "autotune event");
+                float t = 0.f;
+                if (st == NB_OK && r > 0 && hipEventElapsedTime(&t, e0, e1) == hipSuccess)
+                    ms.push_back(t);
+            }
+            if (st != NB_OK || ms.empty()) break;
+            std::sort(ms.begin(), ms.end());
+            const nb_exec_config t{W, m, 1e3 * ms[ms.size() / 2]};
+            if (n < cap) trials[n] = t;
+            ++n;
+            if (t.us_per_call < win.us_per_call) win = t;
+        }
+    }
+    c->timing = timing;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(f);
+    hipFree(ev);
+    if (st != NB_OK) return st;
+    if (n_trials) *n_trials = n;
+    c->fixed_w = win.item_width;
+    c->exec_mode = win.exec_mode;
+    st = make_items(c, win.item_width, false);
+    if (st == NB_OK) st = finish_items(c);
+    if (st != NB_OK) return st;
+    if (best) *best = win;
+    return NB_OK;
 }
 
 nb_status nb_forces_backward(nb_ctx* c, const float* x, const float* q, const float* lj,

@@ -19,6 +19,13 @@ constexpr int kWave = 64;                       // wavefront width on gfx950
 constexpr int kMaxTypes = 32;                   // LJ types supported by the kernels
 constexpr int kMaxExcl = 32;                    // exclusion partners per atom
 constexpr int kShiftZero = 13;                  // shift code of s = (0,0,0)
+constexpr int kXcds = 8;                        // accelerator complex dies of an MI355X
+
+// Execution modes of the pair kernel (values of NB_EXEC_* in nb.h).
+constexpr int kExecStatic = 0;                  // one wavefront per item, in item order
+constexpr int kExecXcd = 1;                     // blocks renumbered XCD-contiguously
+constexpr int kExecQueue = 2;                   // persistent grid, atomic item queue
+constexpr int kMaxItemCost = 64 * 8;            // set outer-mask bits of one item, at most
 
 // One j-entry of a super-cluster's joint list (16 bytes, loaded with one scalar load).
 //   meta bits  0..4   shift code (sx+1)*9 + (sy+1)*3 + (sz+1), image x_j + s L
@@ -95,7 +102,8 @@ hipError_t launch_search(const NbDev& d, int n_sc, int cap, float r2_outer, floa
                          float r2_bb, float rlist, hipStream_t s);
 hipError_t launch_scan_entries(const NbDev& d, int n_sc, hipStream_t s);
 hipError_t launch_make_items(const NbDev& d, int n_sc, int cap, int w, int nstprune,
-                             hipStream_t s);
+                             bool copy_entries, hipStream_t s);
+hipError_t launch_item_order(const NbDev& d, int n_items, hipStream_t s);
 hipError_t launch_list_finish(const NbDev& d, int n_sc, int64_t n_entries, int n_cl,
                               hipStream_t s);
 hipError_t launch_fill(int32_t* p, int n, int32_t v, hipStream_t s);
@@ -106,7 +114,10 @@ hipError_t launch_prune(const NbDev& d, int item0, int n_items, float r2_inner,
                         hipStream_t s);
 hipError_t launch_forces(const NbDev& d, const NbKParams& kp, int coulomb, uint32_t flags,
                          const float* lj, int n_items, int prune_i0, int prune_i1,
-                         float r2_inner, hipStream_t s);
+                         float r2_inner, int mode, hipStream_t s);
+// Resolve once, outside any stream capture, the launch shape of the pair kernel flavor
+// for these flags (its occupancy, used by the persistent mode).
+hipError_t prepare_forces(int coulomb, uint32_t flags, bool prune, int n_types);
 hipError_t launch_reduce_forces(const NbDev& d, float* f, bool accumulate, int n_slots,
                                 hipStream_t s);
 hipError_t launch_reduce_energies(const NbDev& d, double* energy, double* virial,
@@ -122,6 +133,7 @@ hipError_t launch_reduce_backward(const NbDev& d, float* grad_x, float* grad_q,
 struct NbDev {
     int32_t n_atoms = 0, n_sys = 0, n_cols = 0, n_types = 0, max_excl = 0;
     int32_t n_sc_max = 0;              // upper bound of super-clusters for the grid
+    int32_t n_cu = 0;                  // compute units of the device
     // topology
     int32_t* type = nullptr;           // [N]
     int32_t* atom_sys = nullptr;       // [N]
@@ -160,6 +172,10 @@ struct NbDev {
     NbEntry* entries = nullptr;        // [entry_cap]
     int32_t* entry_sc = nullptr;       // [entry_cap]
     NbItem* items = nullptr;           // [item_cap]
+    int32_t* item_cost = nullptr;      // [item_cap] set outer-mask bits per item
+    int32_t* item_order = nullptr;     // [item_cap] items by decreasing cost (queue order)
+    int32_t* queue = nullptr;          // [2] item counter, finished wavefronts (kept zero
+                                       //     between launches by the kernel itself)
     int32_t* part_start = nullptr;     // [nstprune+1] item ranges per rolling part
     uint64_t* excl_rows = nullptr;     // [entry_cap][8]
     int32_t* jseg_count = nullptr;     // [8 n_sc_max]

@@ -242,14 +242,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_items(NbDev d, int n_sc, 
     }
 }
 
-__global__ __launch_bounds__(kWave) void k_compact(NbDev d, int cap, int w) {
+// Per super-cluster: copy its entries from the search scratch (at a build only; later
+// re-splits into items of another width keep the entries, whose masks the rolling prune
+// has changed since), and write its work items.
+__global__ __launch_bounds__(kWave) void k_compact(NbDev d, int cap, int w, int copy_entries) {
     const int sc = blockIdx.x;
     const int n = d.sc_ecount[sc];
     const int e0 = d.sc_estart[sc];
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
-        d.entries[e0 + k] = d.scratch[(size_t)sc * cap + k];
-        d.entry_sc[e0 + k] = sc;
-    }
+    if (copy_entries)
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            d.entries[e0 + k] = d.scratch[(size_t)sc * cap + k];
+            d.entry_sc[e0 + k] = sc;
+        }
     const int i0 = d.sc_istart[sc], ni = d.sc_icount[sc];
     const int p0 = d.sc_ipos[sc];
     for (int k = threadIdx.x; k < ni; k += blockDim.x) {
@@ -377,9 +381,52 @@ __global__ __launch_bounds__(kPruneWaves * kWave) void k_prune(
     }
 }
 
+// Pair work of each item (one wavefront per item): set bits of its entries' outer masks.
+__global__ __launch_bounds__(4 * kWave) void k_item_cost(NbDev d, int n_items) {
+    const int item = blockIdx.x * 4 + (int)(threadIdx.x / kWave);
+    const int lane = threadIdx.x & (kWave - 1);
+    if (item >= n_items) return;
+    const NbItem it = d.items[item];
+    int c = 0;
+    for (int k = lane; k < it.ne; k += kWave)
+        c += __builtin_popcount((d.entries[it.e0 + k].meta >> 8) & 0xffu);
+    for (int off = 1; off < kWave; off <<= 1) c += __shfl_xor(c, off);
+    if (lane == 0) d.item_cost[item] = c;
+}
+
+// Items by decreasing cost (counting sort in one block), the order in which the
+// persistent pair kernel hands them out: the longest items start first.  The order
+// among items of equal cost is arbitrary; it changes no result.
+__global__ __launch_bounds__(1024) void k_item_order(NbDev d, int n_items) {
+    __shared__ int cnt[kMaxItemCost + 1];
+    for (int c = threadIdx.x; c <= kMaxItemCost; c += blockDim.x) cnt[c] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_items; i += blockDim.x)
+        atomicAdd(&cnt[min(d.item_cost[i], kMaxItemCost)], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;                        // first position of each cost, largest first
+        for (int c = kMaxItemCost; c >= 0; --c) {
+            const int k = cnt[c];
+            cnt[c] = run;
+            run += k;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_items; i += blockDim.x)
+        d.item_order[atomicAdd(&cnt[min(d.item_cost[i], kMaxItemCost)], 1)] = i;
+}
+
 inline int blocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
+
+hipError_t launch_item_order(const NbDev& d, int n_items, hipStream_t s) {
+    if (n_items <= 0) return hipGetLastError();
+    hipLaunchKernelGGL(k_item_cost, dim3(blocks(n_items, 4)), dim3(4 * kWave), 0, s, d, n_items);
+    hipLaunchKernelGGL(k_item_order, dim3(1), dim3(1024), 0, s, d, n_items);
+    return hipGetLastError();
+}
 
 hipError_t launch_search(const NbDev& d, int n_sc, int cap, float r2_outer, float r2_inner,
                          float r2_bb, float rlist, hipStream_t s) {
@@ -395,11 +442,13 @@ hipError_t launch_scan_entries(const NbDev& d, int n_sc, hipStream_t s) {
 }
 
 hipError_t launch_make_items(const NbDev& d, int n_sc, int cap, int w, int nstprune,
-                             hipStream_t s) {
+                             bool copy_entries, hipStream_t s) {
     // jseg_fill doubles as the scratch of the permuted scan (n_sc + 1 <= 8 n_sc_max).
     hipLaunchKernelGGL(k_scan_items, dim3(1), dim3(kScanThreads), 0, s, d, n_sc, w, nstprune,
                        d.jseg_fill);
-    if (n_sc > 0) hipLaunchKernelGGL(k_compact, dim3(n_sc), dim3(kWave), 0, s, d, cap, w);
+    if (n_sc > 0)
+        hipLaunchKernelGGL(k_compact, dim3(n_sc), dim3(kWave), 0, s, d, cap, w,
+                           copy_entries ? 1 : 0);
     return hipGetLastError();
 }
 

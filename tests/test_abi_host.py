@@ -122,3 +122,27 @@ def test_cross_system_exclusion_rejected():
         assert lib.nb_set_topology(h, vp(t), vp(ptr), vp(idx)) == _lib.NB_ERR_ARG
     finally:
         lib.nb_destroy(h)
+
+
+def test_exec_shape_validation_without_device():
+    lib = _lib.load()
+    st, h = create(good_params(), offsets=(0, 4))
+    assert st == _lib.NB_OK
+    try:
+        assert ctypes.sizeof(_lib.NbExecConfig) == 16
+        assert lib.nb_set_exec(h, -1, _lib.NB_EXEC_STATIC) == _lib.NB_ERR_ARG
+        assert lib.nb_set_exec(h, 65, _lib.NB_EXEC_STATIC) == _lib.NB_ERR_ARG
+        assert lib.nb_set_exec(h, 16, 3) == _lib.NB_ERR_ARG
+        assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_QUEUE) == _lib.NB_OK
+        cfg = _lib.NbExecConfig()
+        assert lib.nb_get_exec(h, ctypes.byref(cfg)) == _lib.NB_OK
+        assert (cfg.item_width, cfg.exec_mode) == (16, _lib.NB_EXEC_QUEUE)
+        n = ctypes.c_int32(0)
+        best = _lib.NbExecConfig()
+        assert lib.nb_autotune(h, None, None, None, 1, 3, None, 0, ctypes.byref(n),
+                               ctypes.byref(best)) == _lib.NB_ERR_STATE
+        assert lib.nb_step_graph(h, None, None, None, None, None, None, 0, 1) \
+            == _lib.NB_ERR_STATE
+        assert lib.nb_get_exec(h, None) == _lib.NB_ERR_ARG
+    finally:
+        lib.nb_destroy(h)

@@ -1,0 +1,174 @@
+"""Execution shapes of the pair kernel (static, XCD-contiguous, persistent queue), item
+widths, the autotuner, the graph-replayed step and an ensemble of uneven replicas in one
+context, through the C ABI on an MI355X, against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_common import (concat, dev, energy_tolerance, make_ctx, oracle_forces_multi,
+                        oracle_params, rel_rms)
+from paper_2006_09167_amd import systems
+
+pytestmark = pytest.mark.gpu
+
+EWALD = dict(coulomb="ewald", rc=1.0, rinner=1.04, rlist=1.1, beta=3.12)
+
+
+def built(c, **kw):
+    ctx = make_ctx(c, **kw)
+    x = dev(c["x"])
+    ctx.grid_build(x, c["boxes"])
+    ctx.pairlist_build()
+    return ctx, x
+
+
+def check_oracle(c, x_np, f, e, coul, rc, beta=0.0, strict=True):
+    E, F, _, A = oracle_forces_multi(c, x_np, oracle_params(coul, rc, beta))
+    tol = energy_tolerance(E, A, strict)
+    assert rel_rms(f.cpu().numpy(), F) <= 1e-5
+    e = e.cpu().numpy()
+    for s in range(E.shape[0]):
+        for k in range(2):
+            assert abs(e[s, k] - E[s, k]) <= max(tol[s, k], 1e-9), (s, k, e[s, k], E[s, k])
+
+
+@pytest.mark.parametrize("width", [8, 32, 64])
+def test_modes_bitwise_equal_and_queue_relaunches(sys3k, width):
+    """For one item width every mode gives bitwise the same forces, energies and virial
+    (each item writes its own partials); the persistent queue resets itself between
+    launches, so consecutive launches repeat the result."""
+    c = concat(sys3k)
+    ctx, x = built(c, nstlist=10, nstprune=4, **EWALD)
+    q, lj = dev(c["q"]), dev(c["lj"])
+    ref = None
+    for mode in ("static", "xcd", "queue", "queue", "queue", "static"):
+        ctx.set_exec(width, mode)
+        assert ctx.get_exec() == {"item_width": width, "mode": mode}
+        out = ctx.forces(x, q, lj, energy=True, virial=True)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = [t.clone() for t in out]
+            check_oracle(c, c["x"], out[0], out[1], "ewald", 1.0, 3.12)
+        else:
+            for a, b in zip(ref, out):
+                assert torch.equal(a, b), mode
+
+
+def test_fused_step_in_queue_mode_matches_static(sys3k):
+    """nb_step (prune fused into the pair kernel) under the persistent queue: same inner
+    lists and bitwise the same outputs as the static mode over a rolling cycle."""
+    c = concat(sys3k)
+    kw = dict(nstlist=20, nstprune=4, **EWALD)
+    ctx_a, _ = built(c, **kw)
+    ctx_b, _ = built(c, **kw)
+    ctx_b.set_exec(0, "queue")
+    q, lj = dev(c["q"]), dev(c["lj"])
+    rng = np.random.default_rng(3)
+    x = c["x"].copy()
+    for t in range(1, 9):
+        x = (x + rng.normal(0, 0.01, x.shape)).astype(np.float32)
+        xt = dev(x)
+        fa, ea, va = ctx_a.step(xt, q, lj, t, energy=True, virial=True)
+        fb, eb, vb = ctx_b.step(xt, q, lj, t, energy=True, virial=True)
+        assert torch.equal(fa, fb) and torch.equal(ea, eb) and torch.equal(va, vb), t
+    assert np.array_equal(ctx_a.get_pairs("inner"), ctx_b.get_pairs("inner"))
+
+
+def test_item_width_changes_only_rounding(sys3k):
+    """Another item width re-splits the lists: outputs agree with the default to FP32
+    summation-order rounding and stay within the oracle bars."""
+    c = concat(sys3k)
+    ctx, x = built(c, **EWALD)
+    q, lj = dev(c["q"]), dev(c["lj"])
+    f0, e0, _ = ctx.forces(x, q, lj)
+    f0, e0 = f0.clone(), e0.clone()
+    for w in (1, 5, 16, 64):
+        ctx.set_exec(w, "xcd")
+        f, e, _ = ctx.forces(x, q, lj)
+        torch.cuda.synchronize()
+        assert rel_rms(f.cpu().numpy(), f0.cpu().numpy()) <= 1e-6, w
+        assert torch.allclose(e, e0, rtol=1e-9, atol=0), w
+        check_oracle(c, c["x"], f, e, "ewald", 1.0, 3.12)
+    st = ctx.stats()
+    assert st["n_work_items"] >= st["n_superclusters"]
+
+
+def test_autotune_keeps_fastest_and_stays_exact(sys3k):
+    c = concat(sys3k)
+    ctx, x = built(c, nstlist=10, nstprune=2, **EWALD)
+    q, lj = dev(c["q"]), dev(c["lj"])
+    best, trials = ctx.autotune(x, q, lj, energy=True, repeats=3)
+    assert len(trials) == 18
+    assert all(t["us_per_call"] > 0 for t in trials)
+    assert best["us_per_call"] == min(t["us_per_call"] for t in trials)
+    assert ctx.get_exec() == {"item_width": best["item_width"], "mode": best["mode"]}
+    f, e, _ = ctx.forces(x, q, lj)
+    torch.cuda.synchronize()
+    check_oracle(c, c["x"], f, e, "ewald", 1.0, 3.12)
+    # the choice survives the next build
+    ctx.grid_build(x, c["boxes"])
+    ctx.pairlist_build()
+    assert ctx.get_exec()["item_width"] == best["item_width"]
+
+
+@pytest.mark.parametrize("mode", ["static", "queue"])
+def test_graph_step_replays_match_eager(sys3k, mode):
+    """nb_step_graph over two list lifetimes with positions updated in place: every replay
+    (with eager work and synchronisation in between) equals the eager nb_step bitwise."""
+    c = concat(sys3k)
+    kw = dict(nstlist=8, nstprune=4, **EWALD)
+    ctx_g, _ = built(c, **kw)
+    ctx_e, _ = built(c, **kw)
+    ctx_g.set_exec(0, mode)
+    ctx_e.set_exec(0, mode)
+    q, lj = dev(c["q"]), dev(c["lj"])
+    xg = dev(c["x"])                                   # fixed addresses for the graph
+    fg = torch.empty_like(xg)
+    eg = torch.empty((1, 2), dtype=torch.float64, device="cuda")
+    vg = torch.empty((1, 3, 3), dtype=torch.float64, device="cuda")
+    rng = np.random.default_rng(5)
+    x = c["x"].copy()
+    for t in range(16):
+        k = t % 8
+        if t > 0:
+            x = (x + rng.normal(0, 0.004, x.shape)).astype(np.float32)
+            xg.copy_(dev(x))
+        if k == 0:
+            for ctx in (ctx_g, ctx_e):
+                ctx.grid_build(xg, c["boxes"])
+                ctx.pairlist_build()
+        ctx_g.step(xg, q, lj, k, energy=True, virial=True, f=fg, e=eg, vir=vg, graph=True)
+        torch.cuda.synchronize()
+        scratch = torch.randn(1000, device="cuda").sum()        # eager work in between
+        fe, ee, ve = ctx_e.step(dev(x), q, lj, k, energy=True, virial=True)
+        torch.cuda.synchronize()
+        assert torch.isfinite(scratch)
+        assert torch.equal(fg, fe) and torch.equal(eg, ee) and torch.equal(vg, ve), t
+    check_oracle(c, x, fg, eg, "ewald", 1.0, 3.12)
+
+
+def test_ensemble_uneven_replicas_all_modes():
+    """Sixteen water-like replicas of 3k-24k atoms (log-uniform sizes) in one context and
+    one launch per kernel: per-replica energies and all forces against the oracle, in
+    every execution mode."""
+    reps = systems.ensemble_systems(n_replicas=16)
+    c = concat(reps)
+    e_cfg = systems.ENSEMBLE
+    ctx, x = built(c, coulomb="rf", rc=e_cfg["rc"], rinner=e_cfg["rinner"],
+                   rlist=e_cfg["rlist"], nstlist=e_cfg["nstlist"], nstprune=e_cfg["nstprune"])
+    q, lj = dev(c["q"]), dev(c["lj"])
+    E, F, _, A = oracle_forces_multi(c, c["x"], oracle_params("rf", e_cfg["rc"]))
+    tol = energy_tolerance(E, A, True)
+    ref = None
+    for mode in ("static", "xcd", "queue"):
+        ctx.set_exec(0, mode)
+        f, e, _ = ctx.forces(x, q, lj)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = (f.clone(), e.clone())
+            assert rel_rms(f.cpu().numpy(), F) <= 1e-5
+            en = e.cpu().numpy()
+            assert np.all(np.abs(en - E) <= tol), np.max(np.abs(en - E) / np.abs(E))
+        else:
+            assert torch.equal(f, ref[0]) and torch.equal(e, ref[1]), mode
