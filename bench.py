@@ -140,6 +140,8 @@ def main():
     ap.add_argument("--workload", default="water96k_ewald", choices=sorted(WORKLOADS))
     ap.add_argument("--exec", default="auto", choices=["auto", "static", "xcd", "queue"],
                     help="pair kernel execution shape (auto = autotuner at the first build)")
+    ap.add_argument("--item-width", type=int, default=0,
+                    help="entries per work item with a fixed --exec mode (0 = built-in rule)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -207,7 +209,7 @@ def main():
         log("autotune: item width %d, mode %s, %.1f us per force call"
             % (best["item_width"], best["mode"], best["us_per_call"]))
     else:
-        ctx.set_exec(0, args.exec)
+        ctx.set_exec(args.item_width, args.exec)
 
     have_bwd = not args.no_backward
     G = None

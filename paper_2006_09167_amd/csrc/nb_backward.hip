@@ -25,6 +25,9 @@ constexpr int kBwdWaves = 2;
 constexpr int kBwdThreads = kBwdWaves * kWave;
 constexpr int kPrivateHistTypes = 4;   // per-lane histograms up to this many types
 
+// Sum over the 8 consecutive lanes ii = 0..7 of a j-atom (row half), complete in every
+// lane of it: swap neighbours, swap pairs, then add the mirrored half row.
+constexpr int kJSumLane = 0;
 __device__ inline float dpp_sum8(float v) {
     v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
                                                                0xB1, 0xF, 0xF, false));
@@ -61,7 +64,7 @@ struct BScal {
 // One 8x8 block of pairs: i-atom data and accumulators as scalars (lane = ii + 8 jj).
 template <int COUL, bool LJGRAD, bool PRIV, bool SHIFTED>
 __device__ __forceinline__ void bwd_block(
-    float xi, float yi, float zi, float qi, float gxi, float gyi, float gzi, int ti, uint64_t m,
+    float xi, float yi, float zi, const float4* s_gq, const int* s_ti, uint64_t m,
     float& ax, float& ay, float& az, float& aq, const float4& xj, const float4& gj, int tj,
     const float4* __restrict__ s_lj, float* __restrict__ s_hist, int lane, const NbKParams& kp,
     const BScal& bs, float sxi, float syi, float szi, float& ajx, float& ajy, float& ajz,
@@ -80,6 +83,9 @@ __device__ __forceinline__ void bwd_block(
     const uint64_t act = __builtin_amdgcn_ballot_w64(r2 < kp.rc2) & m;
     if (!act) return;
     const bool on = __builtin_amdgcn_inverse_ballot_w64(act);
+    const float4 gq = *s_gq;                           // (G_i, K q_i) of this lane's i-atom
+    const float gxi = gq.x, gyi = gq.y, gzi = gq.z, qi = gq.w;
+    const int ti = *s_ti;                              // type_i * T
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float rinv2 = rinv * rinv;
     const float4 p = s_lj[ti + tj];                    // (6 c6, 12 c12, shift, c6)
@@ -152,11 +158,13 @@ __global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
     const NbItem* __restrict__ items, const NbEntry* __restrict__ entries,
     const uint64_t* __restrict__ excl_rows, const float4* __restrict__ xq,
     const float4* __restrict__ gslot, const int32_t* __restrict__ type_slot,
-    const float4* __restrict__ cl_bb, const NbScInfo* __restrict__ sc_info,
+    const NbScInfo* __restrict__ sc_info,
     const NbSys* __restrict__ sys, const float* __restrict__ lj,
     const double* __restrict__ grad_e, float4* __restrict__ jpart, float4* __restrict__ ipart,
     float* __restrict__ glj_part, int glj_stride, NbKParams kp, int n_items) {
     extern __shared__ float4 s_dyn[];
+    __shared__ float4 s_gq_all[kBwdWaves][kScAtoms];   // per wave: (G_i, K q_i)
+    __shared__ int s_ti_all[kBwdWaves][kScAtoms];      // per wave: type_i * T
     const int T = kp.n_types;
     const int TT = T * T;
     float4* s_lj = s_dyn;
@@ -185,25 +193,25 @@ __global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
     bs.rc_m6 = kp.rc_m6;
     bs.rc_m12 = kp.rc_m12;
     const int ibase = kScAtoms * sc + ii;
+    float4* s_gq = s_gq_all[wave];
+    int* s_ti = s_ti_all[wave];
+    {
+        // lane l holds slot l of the super-cluster: (8 c + ii) for c = l >> 3
+        const float4 v = xq[kScAtoms * sc + lane];
+        const float4 g = gslot[kScAtoms * sc + lane];
+        s_gq[lane] = make_float4(g.x, g.y, g.z, v.w * kp.epsfac_r);
+        s_ti[lane] = type_slot[kScAtoms * sc + lane] * T;
+    }
+    __builtin_amdgcn_wave_barrier();
 
 #define NB_ILOAD(c)                                                                    \
-    float xi##c, yi##c, zi##c, qi##c, gxi##c, gyi##c, gzi##c;                          \
-    int ti##c;                                                                         \
-    uint64_t iv##c;                                                                    \
+    float xi##c, yi##c, zi##c;                                                         \
     float ax##c = 0.f, ay##c = 0.f, az##c = 0.f, aq##c = 0.f;                          \
     {                                                                                  \
         const float4 v = xq[ibase + kClusterSize * c];                                 \
-        const float4 g = gslot[ibase + kClusterSize * c];                              \
         xi##c = v.x;                                                                   \
         yi##c = v.y;                                                                   \
         zi##c = v.z;                                                                   \
-        qi##c = v.w * kp.epsfac_r;                                                     \
-        gxi##c = g.x;                                                                  \
-        gyi##c = g.y;                                                                  \
-        gzi##c = g.z;                                                                  \
-        ti##c = type_slot[ibase + kClusterSize * c] * T;                               \
-        const int ni = (int)cl_bb[2 * (ci0 + c)].w;                                    \
-        iv##c = ((ni >= 8) ? 0xffull : ((1ull << ni) - 1ull)) * 0x0101010101010101ull; \
     }
     NB_FOR8(NB_ILOAD)
 #undef NB_ILOAD
@@ -231,23 +239,22 @@ __global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
             continue;
         }
         const int code = ent.meta & 31u;
-        const int nj = (int)(ent.meta >> 24);
-        const uint64_t jvalid = (nj >= 8) ? ~0ull : ((1ull << (8 * nj)) - 1ull);
         const uint64_t* xrow =
             (ent.excl >= 0) ? excl_rows + (size_t)ent.excl * kClustersPerSc : nullptr;
         const bool self = (ent.cj >> 3) == sc && code == kShiftZero;
         const int dc = ent.cj - ci0;
         float ajx = 0.f, ajy = 0.f, ajz = 0.f, ajq = 0.f;
+        // empty slots sit far outside the box (no distance test passes): only exclusions
+        // and, for a cluster with itself, ii < jj are masked
 #define NB_MASK(c)                                                                     \
-    (iv##c & jvalid & (xrow ? xrow[c] : ~0ull) &                                       \
-     ((self && dc == c) ? 0x7f3f1f0f07030100ull : ~0ull))
+    ((xrow ? xrow[c] : ~0ull) & ((self && dc == c) ? 0x7f3f1f0f07030100ull : ~0ull))
         if (code == kShiftZero) {
 #define NB_BLOCK0(c)                                                                   \
     if ((mask >> c) & 1u)                                                              \
-        bwd_block<COUL, LJGRAD, PRIV, false>(xi##c, yi##c, zi##c, qi##c, gxi##c, gyi##c,  \
-                                             gzi##c, ti##c, NB_MASK(c), ax##c, ay##c,     \
-                                             az##c, aq##c, xj, gj, tj, s_lj, s_hist, lane,\
-                                             kp, bs, 0.f, 0.f, 0.f, ajx, ajy, ajz, ajq);
+        bwd_block<COUL, LJGRAD, PRIV, false>(                                          \
+            xi##c, yi##c, zi##c, s_gq + kClusterSize * c + ii, s_ti + kClusterSize * c + ii, \
+            NB_MASK(c), ax##c, ay##c, az##c, aq##c, xj, gj, tj, s_lj, s_hist, lane, kp, bs, \
+            0.f, 0.f, 0.f, ajx, ajy, ajz, ajq);
             NB_FOR8(NB_BLOCK0)
 #undef NB_BLOCK0
         } else {
@@ -259,10 +266,10 @@ __global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
                         szi = sz > 0 ? S.L[2] : 0.f;
 #define NB_BLOCK1(c)                                                                   \
     if ((mask >> c) & 1u)                                                              \
-        bwd_block<COUL, LJGRAD, PRIV, true>(xi##c, yi##c, zi##c, qi##c, gxi##c, gyi##c,   \
-                                            gzi##c, ti##c, NB_MASK(c), ax##c, ay##c,      \
-                                            az##c, aq##c, xj, gj, tj, s_lj, s_hist, lane, \
-                                            kp, bs, sxi, syi, szi, ajx, ajy, ajz, ajq);
+        bwd_block<COUL, LJGRAD, PRIV, true>(                                           \
+            xi##c, yi##c, zi##c, s_gq + kClusterSize * c + ii, s_ti + kClusterSize * c + ii, \
+            NB_MASK(c), ax##c, ay##c, az##c, aq##c, xj, gj, tj, s_lj, s_hist, lane, kp, bs, \
+            sxi, syi, szi, ajx, ajy, ajz, ajq);
             NB_FOR8(NB_BLOCK1)
 #undef NB_BLOCK1
         }
@@ -271,7 +278,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
         ajy = dpp_sum8(ajy);
         ajz = dpp_sum8(ajz);
         ajq = dpp_sum8(ajq);
-        if (ii == 0) jp[jj] = make_float4(ajx, ajy, ajz, ajq);
+        if (ii == kJSumLane) jp[jj] = make_float4(ajx, ajy, ajz, ajq);
     }
     float4* ip = ipart + (size_t)item * kScAtoms;
 #define NB_IRED(c)                                                                     \
@@ -403,7 +410,7 @@ void launch_bwd_t(const NbDev& d, const NbKParams& kp, const float* lj, const do
     const size_t lds = sizeof(float4) * TT + sizeof(float) * hist;
     hipLaunchKernelGGL((k_nb_bwd<COUL, LJG, PRIV>), dim3(blocks(n_items, kBwdWaves)),
                        dim3(kBwdThreads), lds, s, d.items, d.entries, d.excl_rows, d.xq, d.gslot,
-                       d.type_slot, d.cl_bb, d.sc_info, d.sys, lj, ge, d.jpart, d.ipart,
+                       d.type_slot, d.sc_info, d.sys, lj, ge, d.jpart, d.ipart,
                        d.glj_part, d.epart_stride, kp, n_items);
 }
 

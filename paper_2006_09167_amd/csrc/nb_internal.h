@@ -20,6 +20,7 @@ constexpr int kMaxTypes = 32;                   // LJ types supported by the ker
 constexpr int kMaxExcl = 32;                    // exclusion partners per atom
 constexpr int kShiftZero = 13;                  // shift code of s = (0,0,0)
 constexpr int kXcds = 8;                        // accelerator complex dies of an MI355X
+constexpr float kFillerSpacing = 1.0e6f;        // nm between the far points of empty slots
 
 // Execution modes of the pair kernel (values of NB_EXEC_* in nb.h).
 constexpr int kExecStatic = 0;                  // one wavefront per item, in item order
