@@ -37,8 +37,16 @@ PEAK_FP32_NONPACKED = 78.6e12 # without packed FP32 (one FMA per lane per cycle)
 #           force accumulation 9                                            (= 25)
 #   Ewald:  r 1, beta r 1, u = 1/(1 + p t) 3, P(u) 16, u P 1, exp argument 1, exp2 1,
 #           erfc 1, g 3 (= 28), F/r 3, energies 9 (V_C 3, V_LJ 4, 2 sums)   => 66
-#   RF:     force 5, energies 10 (V_C 4, V_LJ 4, 2 sums)                    => 40
-FLOP_PER_PAIR = {"ewald": 66, "rf": 40}
+#   RF:     force 5, energies 13 (V_C 7 with hi + lo constants, V_LJ 4, 2 sums) => 43
+FLOP_PER_PAIR = {"ewald": 66, "rf": 43}
+# Backward pass per evaluated pair slot (same counting, with the table gradient):
+#   separation 3, r^2 5, rsqrt 1, r^-2 1, r^-6 and 12 c12 r^-6 3, phi_LJ 3, phi'_LJ/r 6,
+#   q_i q_j 1, phi_C 1, G_i - G_j 3, u 5, phi 1, coefficient of d 7, h 9, w 3,
+#   i- and j-accumulation 10, table gradient 15                                (= 77)
+#   Ewald psi, psi', v: beta r 2, u = 1/(1 + p t) 3, P(u) 16, u P 1, exp 2, erfc 1,
+#           2 beta/sqrt(pi) e 1, g 2, psi 1, psi' 6, v 2                      (= 37) => 114
+#   RF psi, psi', v 8                                                                => 85
+FLOP_PER_PAIR_BWD = {"ewald": 114, "rf": 85}
 
 WORKLOADS = {
     "water96k_ewald": "96,000-atom water-like box (32,000 molecules, 9.86 nm cube), Ewald "
@@ -332,6 +340,15 @@ def main():
                      "avg_launch_us": 1e3 * plain_ms / max(plain_calls, 1),
                      "fused_prune_launch_us": 1e3 * fused_ms / max(fused_calls, 1),
                      "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED},
+        "roofline_backward": ({"bound": "alu", "kernel": "k_nb_bwd (with table gradient)",
+                               "flop_per_pair": FLOP_PER_PAIR_BWD[coul],
+                               "achieved": comp_timed * FLOP_PER_PAIR_BWD[coul]
+                               / (tm_fb["backward"][0] * 1e-3) / 1e12,
+                               "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                               "frac": comp_timed * FLOP_PER_PAIR_BWD[coul]
+                               / (tm_fb["backward"][0] * 1e-3) / PEAK_FP32,
+                               "avg_launch_us": 1e3 * tm_fb["backward"][0]
+                               / max(tm_fb["backward"][1], 1)} if tm_fb else None),
         "work_efficiency": float(eff[W:].sum() / max(comp[W:].sum(), 1)),
         "list": {"outer_cluster_pairs": int(first_stats["outer_pairs"]),
                  "bb_cluster_pairs": int(first_stats["bb_pairs"]),

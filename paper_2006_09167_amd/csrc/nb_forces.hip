@@ -118,7 +118,8 @@ __device__ __forceinline__ void pair_block(float xi, float yi, float zi, const f
     float fscal, vc = 0.f;
     if (COUL == NB_COUL_RF) {
         fscal = fmaf(flj, rinv2, qq * (rinv * rinv2 - 2.0f * kp.krf));
-        if (ENERGY) vc = qq * (fmaf(kp.krf, r2, rinv) - kp.crf);
+        if (ENERGY)   // constants as hi + lo pairs: no systematic rounding bias in E_C
+            vc = qq * ((fmaf(kp.krf_lo, r2, fmaf(kp.krf, r2, rinv)) - kp.crf) - kp.crf_lo);
     } else {
         const float r = r2 * rinv;
         const float e = __builtin_amdgcn_exp2f(r2 * kp.beta2_log2e);   // exp(-beta^2 r^2)
@@ -343,19 +344,21 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
     lane, s_qt, s_lj, items, entries, excl_rows, xq, type_slot, sc_info, sys, jpart, ipart, \
         epart, epart_stride, kp, prune_i0, prune_i1, r2_inner
     if (mode == kExecQueue) {
+        // Tickets are taken in converged code: every lane issues the atomic, lane 0 adding
+        // one and the others zero, and lane 0's result is broadcast.  (A fetch inside a
+        // lane-0-only branch makes the loop exit divergent: the other lanes would never
+        // see the end of the queue.)  The exit test below is a uniform scalar branch.
+        const int one = (lane == 0) ? 1 : 0;
         for (;;) {
-            int slot = 0;
-            if (lane == 0) slot = atomicAdd(queue, 1);
-            slot = __builtin_amdgcn_readfirstlane(slot);
+            const int slot = __builtin_amdgcn_readfirstlane(atomicAdd(queue, one));
             if (slot >= n_items) break;
             fwd_item<COUL, ENERGY, VIRIAL, PRUNE>(order[slot], NB_ITEM_ARGS);
         }
-        if (lane == 0) {
-            const int waves = (int)gridDim.x * kFwdWaves;
-            if (atomicAdd(queue + 1, 1) == waves - 1) {
-                atomicExch(queue, 0);
-                atomicExch(queue + 1, 0);
-            }
+        const int waves = (int)gridDim.x * kFwdWaves;
+        const int done = __builtin_amdgcn_readfirstlane(atomicAdd(queue + 1, one));
+        if (done == waves - 1 && lane == 0) {
+            atomicExch(queue, 0);
+            atomicExch(queue + 1, 0);
         }
         return;
     }

@@ -89,8 +89,11 @@ NbKParams kernel_params(const nb_params& p) {
     double krf;
     if (isinf(p.eps_rf)) krf = 1.0 / (2.0 * rc * rc * rc);
     else krf = ((double)p.eps_rf - p.eps_r) / ((2.0 * p.eps_rf + p.eps_r) * rc * rc * rc);
+    const double crf = 1.0 / rc + krf * rc * rc;
     k.krf = (float)krf;
-    k.crf = (float)(1.0 / rc + krf * rc * rc);
+    k.crf = (float)crf;
+    k.krf_lo = (float)(krf - (double)k.krf);
+    k.crf_lo = (float)(crf - (double)k.crf);
     const double b = p.ewald_beta;
     k.beta = (float)b;
     k.beta2_log2e = (float)(-b * b / log(2.0));

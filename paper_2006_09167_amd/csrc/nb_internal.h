@@ -74,7 +74,10 @@ struct NbScInfo {
 // Scalar pair-interaction constants passed by value to the kernels.
 struct NbKParams {
     float rc2;           // cut-off squared (single precision)
-    float krf, crf;      // reaction-field constants
+    float krf, crf;      // reaction-field constants (nearest single-precision values)
+    float krf_lo, crf_lo;// their rounding residuals (k_rf - krf, c_rf - crf), used by the
+                         // energy: c_rf times the sum of q_i q_j over ~1e4 pairs would
+                         // otherwise carry a 1e-6 relative bias into E_C
     float beta;          // Ewald splitting parameter
     float beta2_log2e;   // -beta^2 / ln 2 (exp(-beta^2 r^2) = exp2(r^2 * this))
     float two_beta_sqrtpi;  // 2 beta / sqrt(pi)
