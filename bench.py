@@ -37,8 +37,9 @@ PEAK_FP32_NONPACKED = 78.6e12 # without packed FP32 (one FMA per lane per cycle)
 #           force accumulation 9                                            (= 25)
 #   Ewald:  r 1, beta r 1, u = 1/(1 + p t) 3, P(u) 16, u P 1, exp argument 1, exp2 1,
 #           erfc 1, g 3 (= 28), F/r 3, energies 9 (V_C 3, V_LJ 4, 2 sums)   => 66
-#   RF:     force 5, energies 13 (V_C 7 with hi + lo constants, V_LJ 4, 2 sums) => 43
-FLOP_PER_PAIR = {"ewald": 66, "rf": 43}
+#   RF:     force 5, energies 14 (V_C 4, its constants' residual term 3, V_LJ 4,
+#           3 sums)                                                         => 44
+FLOP_PER_PAIR = {"ewald": 66, "rf": 44}
 # Backward pass per evaluated pair slot (same counting, with the table gradient):
 #   separation 3, r^2 5, rsqrt 1, r^-2 1, r^-6 and 12 c12 r^-6 3, phi_LJ 3, phi'_LJ/r 6,
 #   q_i q_j 1, phi_C 1, G_i - G_j 3, u 5, phi 1, coefficient of d 7, h 9, w 3,

@@ -138,7 +138,7 @@ nb_status nb_set_topology(nb_ctx* ctx, const int32_t* type, const int64_t* excl_
  * single precision, store each atom's image offset, bin atoms into x-y columns, sort each
  * column on z, cut it into super-cells of 64 atoms and split those 2x2x2 into clusters of
  * 8; compute cluster bounding boxes.  Requires nb_set_topology.  Errors: NB_ERR_BOX if an
- * edge is not finite or not above 2 * rlist.  NB_ERR_NONFINITE (reported by the next
+ * edge is not finite, not above 2 * rlist or above 1000 nm.  NB_ERR_NONFINITE (reported by the next
  * nb_pairlist_build) if a coordinate is not finite.
  */
 nb_status nb_grid_build(nb_ctx* ctx, const float* x, const float* box);

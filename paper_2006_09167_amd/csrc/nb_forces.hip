@@ -79,7 +79,7 @@ __device__ __forceinline__ void pair_block(float xi, float yi, float zi, const f
                                            const float4* __restrict__ s_lj, const NbKParams& kp,
                                            float sxi, float syi, float szi, float& fjx,
                                            float& fjy, float& fjz, float& elj, float& ec,
-                                           float (&vir)[6], int& npair, int& nblock,
+                                           float& eclo, float (&vir)[6], int& npair, int& nblock,
                                            bool do_prune, float r2_inner, uint32_t& new_inner,
                                            int c) {
     // The same separation as the list build: x_i - L for s > 0 on the i side, the j side
@@ -115,11 +115,16 @@ __device__ __forceinline__ void pair_block(float xi, float yi, float zi, const f
     const float a = p.y * rinv6;
     const float flj = rinv6 * (a - p.x);               // F_LJ * r
     const float qq = qi * xj.w;                        // epsfac/eps_r folded into q_i
-    float fscal, vc = 0.f;
+    float fscal, vc = 0.f, vlo = 0.f;
     if (COUL == NB_COUL_RF) {
         fscal = fmaf(flj, rinv2, qq * (rinv * rinv2 - 2.0f * kp.krf));
-        if (ENERGY)   // constants as hi + lo pairs: no systematic rounding bias in E_C
-            vc = qq * ((fmaf(kp.krf_lo, r2, fmaf(kp.krf, r2, rinv)) - kp.crf) - kp.crf_lo);
+        if (ENERGY) {
+            vc = qq * (fmaf(kp.krf, r2, rinv) - kp.crf);
+            // The residuals of the single-precision k_rf, c_rf are far below half an ulp of
+            // vc near the cut-off, where most pairs are; summed with vc they would vanish
+            // and leave a systematic 1e-6 bias in E_C.  They get their own accumulator.
+            vlo = qq * fmaf(kp.krf_lo, r2, -kp.crf_lo);
+        }
     } else {
         const float r = r2 * rinv;
         const float e = __builtin_amdgcn_exp2f(r2 * kp.beta2_log2e);   // exp(-beta^2 r^2)
@@ -140,6 +145,7 @@ __device__ __forceinline__ void pair_block(float xi, float yi, float zi, const f
         const float vlj = fmaf(rinv6, fmaf(a, 1.0f / 12.0f, -p.w), -p.z);
         elj += on ? vlj : 0.f;
         ec += on ? vc : 0.f;
+        if (COUL == NB_COUL_RF) eclo += on ? vlo : 0.f;
         npair += __builtin_popcountll(act);
         nblock += 1;
     }
@@ -223,7 +229,7 @@ __device__ __forceinline__ void fwd_item(
         const uint64_t* xrow =
             (ent.excl >= 0) ? excl_rows + (size_t)ent.excl * kClustersPerSc : nullptr;
         const bool self = (ent.cj >> 3) == sc && code == kShiftZero;
-        float fjx = 0.f, fjy = 0.f, fjz = 0.f, elj = 0.f, ec = 0.f;
+        float fjx = 0.f, fjy = 0.f, fjz = 0.f, elj = 0.f, ec = 0.f, eclo = 0.f;
         float vir[6] = {0, 0, 0, 0, 0, 0};
         const int dc = ent.cj - ci0;        // the i-cluster equal to the j-cluster, if any
 
@@ -236,7 +242,7 @@ __device__ __forceinline__ void fwd_item(
         pair_block<COUL, ENERGY, VIRIAL, false, PRUNE>(                                \
             xi##c, yi##c, zi##c, s_qt + kClusterSize * c + ii, NB_LMASK(c), NB_MASK(c),  \
             fx##c, fy##c,                                                                \
-            fz##c, xj, tj, s_lj, kp, 0.f, 0.f, 0.f, fjx, fjy, fjz, elj, ec, vir, npair,  \
+            fz##c, xj, tj, s_lj, kp, 0.f, 0.f, 0.f, fjx, fjy, fjz, elj, ec, eclo, vir, npair,  \
             nblock, do_prune, r2_inner, new_inner, c);
             NB_FOR8(NB_BLOCK0)
 #undef NB_BLOCK0
@@ -253,7 +259,7 @@ __device__ __forceinline__ void fwd_item(
         pair_block<COUL, ENERGY, VIRIAL, true, PRUNE>(                                 \
             xi##c, yi##c, zi##c, s_qt + kClusterSize * c + ii, NB_LMASK(c), NB_MASK(c),  \
             fx##c, fy##c,                                                                \
-            fz##c, xj, tj, s_lj, kp, sxi, syi, szi, fjx, fjy, fjz, elj, ec, vir, npair,  \
+            fz##c, xj, tj, s_lj, kp, sxi, syi, szi, fjx, fjy, fjz, elj, ec, eclo, vir, npair,  \
             nblock, do_prune, r2_inner, new_inner, c);
             NB_FOR8(NB_BLOCK1)
 #undef NB_BLOCK1
@@ -267,7 +273,7 @@ __device__ __forceinline__ void fwd_item(
         if (ii == kJSumLane) jp[jj] = make_float4(fjx, fjy, fjz, 0.f);
         if (ENERGY) {
             elj_acc += (double)elj;
-            ec_acc += (double)ec;
+            ec_acc += (double)ec + (double)eclo;
         }
         if (VIRIAL) {
 #pragma unroll
@@ -376,10 +382,16 @@ __global__ void k_gather(NbDev d, const float* __restrict__ x, const float* __re
     const int slot = blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= n_slots) return;
     const int a = d.slot_atom[slot];
-    // Empty slots sit at distinct points far outside every box (x = 1e6 (slot + 1) nm,
-    // charge 0): no distance test with them passes, so the pair kernel needs no
-    // valid-atom masks.  Products stay finite (|d|^2 < 1e26).
-    float4 v = make_float4(kFillerSpacing * (float)(slot + 1), 0.f, 0.f, 0.f);
+    // Empty slots (charge 0) sit on the lattice -D (1 + i, 1 + j, 1 + k) with spacing
+    // D = max box edge + 2 rlist + 1 nm and (i, j, k) the slot's base-1024 digits.  Any
+    // pair with an empty slot is then at least 2 rlist + 1 nm apart on some axis under
+    // every periodic shift s L (|s| <= 1), and an empty slot and its own image |s L| apart:
+    // with box edges up to 1000 nm the coordinates stay below 1025 D < 1.1e6 nm, where one
+    // ulp is at most 0.125 nm.  No distance test with an empty slot passes, so the pair
+    // kernels need no valid-atom masks.
+    const float D = d.filler_d;
+    float4 v = make_float4(-D * (float)(1 + (slot & 1023)), -D * (float)(1 + ((slot >> 10) & 1023)),
+                           -D * (float)(1 + (slot >> 20)), 0.f);
     if (a >= 0) {
         const int4 k = d.img[a];
         const NbSys S = d.sys[d.atom_sys[a]];

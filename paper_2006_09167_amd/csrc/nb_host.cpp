@@ -331,6 +331,7 @@ nb_status nb_grid_build(nb_ctx* c, const float* x, const float* box) {
     const float rlist = c->p.rlist;
     int n_cols = 0;
     int64_t n_sc_max = 0;
+    double max_edge = 0.0;
     for (int s = 0; s < c->n_sys; ++s) {
         NbSys S{};
         for (int k = 0; k < 3; ++k) {
@@ -338,6 +339,8 @@ nb_status nb_grid_build(nb_ctx* c, const float* x, const float* box) {
             if (!isfinite(L) || !(L > 2.0f * rlist))
                 return fail(c, NB_ERR_BOX, "box edge " + std::to_string(k) + " of system " +
                                                std::to_string(s) + " not above 2 * rlist");
+            if (L > 1000.0f) return fail(c, NB_ERR_BOX, "box edge above 1000 nm");
+            max_edge = std::max(max_edge, (double)L);
             S.L[k] = L;
             S.invL[k] = (float)(1.0 / (double)L);
         }
@@ -411,6 +414,9 @@ nb_status nb_grid_build(nb_ctx* c, const float* x, const float* box) {
     }
     d.n_cols = n_cols;
     d.n_sc_max = (int32_t)n_sc_max;
+    // Empty slots sit on a lattice below every box with this spacing: any two of them, or
+    // one and a real atom, stay more than 2 rlist apart under every periodic shift.
+    d.filler_d = (float)ceil(max_edge + 2.0 * rlist + 1.0);
     NB_HIP(c, hipMemcpyAsync(d.sys, c->hsys.data(), sizeof(NbSys) * c->n_sys,
                              hipMemcpyHostToDevice, c->stream));
     NB_HIP(c, launch_fill(d.flags, kFlagCount, 0, c->stream));

@@ -20,7 +20,6 @@ constexpr int kMaxTypes = 32;                   // LJ types supported by the ker
 constexpr int kMaxExcl = 32;                    // exclusion partners per atom
 constexpr int kShiftZero = 13;                  // shift code of s = (0,0,0)
 constexpr int kXcds = 8;                        // accelerator complex dies of an MI355X
-constexpr float kFillerSpacing = 1.0e6f;        // nm between the far points of empty slots
 
 // Execution modes of the pair kernel (values of NB_EXEC_* in nb.h).
 constexpr int kExecStatic = 0;                  // one wavefront per item, in item order
@@ -75,9 +74,9 @@ struct NbScInfo {
 struct NbKParams {
     float rc2;           // cut-off squared (single precision)
     float krf, crf;      // reaction-field constants (nearest single-precision values)
-    float krf_lo, crf_lo;// their rounding residuals (k_rf - krf, c_rf - crf), used by the
-                         // energy: c_rf times the sum of q_i q_j over ~1e4 pairs would
-                         // otherwise carry a 1e-6 relative bias into E_C
+    float krf_lo, crf_lo;// their rounding residuals (k_rf - krf, c_rf - crf): the energy
+                         // sums q_i q_j (krf_lo r^2 - crf_lo) apart, else c_rf's rounding
+                         // times the sum of q_i q_j leaves a 1e-6 relative bias in E_C
     float beta;          // Ewald splitting parameter
     float beta2_log2e;   // -beta^2 / ln 2 (exp(-beta^2 r^2) = exp2(r^2 * this))
     float two_beta_sqrtpi;  // 2 beta / sqrt(pi)
@@ -138,6 +137,7 @@ struct NbDev {
     int32_t n_atoms = 0, n_sys = 0, n_cols = 0, n_types = 0, max_excl = 0;
     int32_t n_sc_max = 0;              // upper bound of super-clusters for the grid
     int32_t n_cu = 0;                  // compute units of the device
+    float filler_d = 0.f;              // lattice spacing of the empty slots' positions (nm)
     // topology
     int32_t* type = nullptr;           // [N]
     int32_t* atom_sys = nullptr;       // [N]
