@@ -68,6 +68,30 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic(workload, exec_cfg):
+    """HBM bytes per launch of the plain pair kernel from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, copy-calibrated), or None when the summary is for another
+    workload or execution shape, or the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_nb_fwd_%s_counters.txt" % workload)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    src = b"".join(open(os.path.join(ROOT, "paper_2006_09167_amd", "csrc", f), "rb").read()
+                   for f in ("nb_forces.hip", "nb_internal.h", "nb_erfc_coeffs.h"))
+    if hashlib.sha256(src).hexdigest()[:16] not in text:
+        return None
+    shape = "%d entries per item, %s" % (exec_cfg["item_width"],
+                                          {"xcd": "XCD-contiguous", "static": "static",
+                                           "queue": "persistent queue"}[exec_cfg["mode"]])
+    if shape not in text.replace("\n", " "):
+        return None
+    for line in text.splitlines():
+        if line.strip().startswith("HBM traffic"):
+            return float(line.split()[-2]) * 1e6
+    return None
+
+
 def load_workload(name):
     """Host arrays and parameters of a workload (seeded synthetic inputs)."""
     import numpy as np
@@ -335,7 +359,8 @@ def main():
         "kernel_us": {k: (1e3 * v[0] / v[1] if v[1] else None)
                       for k, v in (tm_fb or tm_eager).items()},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
+                     "traffic": measured_traffic(args.workload, ctx.get_exec()),
                      "kernel": "k_nb_fwd<%s, energy>" % ("Ewald" if coul == "ewald" else "RF"),
                      "flop_per_pair": flop,
                      "avg_launch_us": 1e3 * plain_ms / max(plain_calls, 1),
