@@ -218,20 +218,26 @@ enum { NB_EXEC_STATIC = 0, NB_EXEC_XCD = 1, NB_EXEC_QUEUE = 2 };
 typedef struct {
     int32_t item_width;   /* entries per work item, 1..64 */
     int32_t exec_mode;    /* NB_EXEC_* */
-    double us_per_call;   /* nb_autotune: median time of one nb_forces call, microseconds */
+    int32_t prune_fused;  /* nb_step: 1 = rolling prune inside the pair kernel (Sec. V.D),
+                             0 = the prune as its own kernels before the pair kernel */
+    int32_t reserved;
+    double us_per_call;   /* nb_autotune: median time of the timed call, microseconds */
 } nb_exec_config;
 
-/* Fix the item width (0 = the built-in rule, about 8192 items, width 8..64) and mode;
+/* Fix the item width (0 = the built-in rule, about 8192 items, width 8..64), the mode and
+ * where nb_step prunes (prune_fused 0 or 1; same inner list and results either way);
  * applies to the current list at once and to every later build.  Errors: NB_ERR_ARG. */
-nb_status nb_set_exec(nb_ctx* ctx, int32_t item_width, int32_t exec_mode);
+nb_status nb_set_exec(nb_ctx* ctx, int32_t item_width, int32_t exec_mode, int32_t prune_fused);
 nb_status nb_get_exec(nb_ctx* ctx, nb_exec_config* out);
 
 /*
  * [sync] Autotuner (the paper calls for dynamic auto-tuning of code flavors, Sec. VII):
  * times nb_forces(x, q, lj, flags) on the current list for item widths 8, 16, 24, 32,
  * 48, 64 and the three execution modes (repeats timed calls after one warm-up each,
- * HIP events, median), writes up to cap trials to host trials[] and their number to
- * *n_trials, and keeps the fastest (also returned in *best) for this and later builds.
+ * HIP events, median), then, in the fastest shape, a rolling step (nb_step of part 1,
+ * which re-prunes that part with x) with the prune fused and separate; writes up to cap
+ * trials to host trials[] and their number (20) to *n_trials, and keeps the fastest
+ * choices (also returned in *best) for this and later builds.
  * flags: NB_F_ENERGY and/or NB_F_VIRIAL.  Allocates and frees its own output buffers.
  * Errors: NB_ERR_STATE without a list, NB_ERR_ARG.
  */

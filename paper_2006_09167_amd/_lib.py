@@ -42,6 +42,7 @@ class NbStats(ctypes.Structure):
 
 class NbExecConfig(ctypes.Structure):
     _fields_ = [("item_width", ctypes.c_int32), ("exec_mode", ctypes.c_int32),
+                ("prune_fused", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("us_per_call", ctypes.c_double)]
 
 
@@ -69,7 +70,7 @@ def load():
         "nb_forces": ([P, P, P, P, P, P, P, u32], st),
         "nb_step": ([P, P, P, P, P, P, P, u32, i64], st),
         "nb_step_graph": ([P, P, P, P, P, P, P, u32, i64], st),
-        "nb_set_exec": ([P, i32, i32], st),
+        "nb_set_exec": ([P, i32, i32, i32], st),
         "nb_get_exec": ([P, ctypes.POINTER(NbExecConfig)], st),
         "nb_autotune": ([P, P, P, P, u32, i32, P, i32, ctypes.POINTER(i32),
                          ctypes.POINTER(NbExecConfig)], st),

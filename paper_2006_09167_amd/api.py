@@ -173,15 +173,17 @@ class Context:
                        flags, int(steps_since_build)), "nb_step_graph" if graph else "nb_step")
         return f, (e if energy else None), (vir if virial else None)
 
-    def set_exec(self, item_width: int = 0, mode: str = "static"):
-        """Item width (0 = built-in rule) and execution mode ('static', 'xcd', 'queue')."""
-        self._check(self.lib.nb_set_exec(self.h, int(item_width), EXEC_MODES[mode]),
-                    "nb_set_exec")
+    def set_exec(self, item_width: int = 0, mode: str = "static", prune_fused: bool = True):
+        """Item width (0 = built-in rule), execution mode ('static', 'xcd', 'queue') and
+        whether step() prunes inside the pair kernel or with separate kernels."""
+        self._check(self.lib.nb_set_exec(self.h, int(item_width), EXEC_MODES[mode],
+                                         1 if prune_fused else 0), "nb_set_exec")
 
     def get_exec(self) -> dict:
         out = NbExecConfig()
         self._check(self.lib.nb_get_exec(self.h, ctypes.byref(out)), "nb_get_exec")
-        return {"item_width": out.item_width, "mode": _MODE_NAMES[out.exec_mode]}
+        return {"item_width": out.item_width, "mode": _MODE_NAMES[out.exec_mode],
+                "prune_fused": bool(out.prune_fused)}
 
     def autotune(self, x, q, lj, energy: bool = True, virial: bool = False, repeats: int = 5):
         """Time nb_forces over item widths and execution modes on the current list, keep the
@@ -200,7 +202,7 @@ class Context:
 
         def d(t):
             return {"item_width": t.item_width, "mode": _MODE_NAMES[t.exec_mode],
-                    "us_per_call": t.us_per_call}
+                    "prune_fused": bool(t.prune_fused), "us_per_call": t.us_per_call}
         return d(best), [d(trials[i]) for i in range(min(n.value, cap))]
 
     def backward(self, x, q, lj, grad_f, grad_energy=None, need_x=True, need_q=True,

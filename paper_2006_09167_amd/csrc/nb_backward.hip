@@ -234,10 +234,9 @@ __global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
         }
         const uint32_t mask = (ent.meta >> 16) & 0xffu;
         float4* jp = jpart + (size_t)ent.jpos * kClusterSize;
-        if (!mask) {
-            if (ii == 0) jp[jj] = make_float4(0.f, 0.f, 0.f, 0.f);
-            continue;
-        }
+        // An entry with an empty mask runs no block and stores zero j-partials below (no
+        // early exit: a second path to the loop latch makes the compiler copy all
+        // loop-carried accumulators at every entry).
         const int code = ent.meta & 31u;
         const uint64_t* xrow =
             (ent.excl >= 0) ? excl_rows + (size_t)ent.excl * kClustersPerSc : nullptr;
@@ -248,30 +247,22 @@ __global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
         // and, for a cluster with itself, ii < jj are masked
 #define NB_MASK(c)                                                                     \
     ((xrow ? xrow[c] : ~0ull) & ((self && dc == c) ? 0x7f3f1f0f07030100ull : ~0ull))
-        if (code == kShiftZero) {
-#define NB_BLOCK0(c)                                                                   \
-    if ((mask >> c) & 1u)                                                              \
-        bwd_block<COUL, LJGRAD, PRIV, false>(                                          \
-            xi##c, yi##c, zi##c, s_gq + kClusterSize * c + ii, s_ti + kClusterSize * c + ii, \
-            NB_MASK(c), ax##c, ay##c, az##c, aq##c, xj, gj, tj, s_lj, s_hist, lane, kp, bs, \
-            0.f, 0.f, 0.f, ajx, ajy, ajz, ajq);
-            NB_FOR8(NB_BLOCK0)
-#undef NB_BLOCK0
-        } else {
+        // Exact periodic shift, one code path for every entry (x - 0 is exact).
+        {
             const int sx = shift_x(code), sy = shift_y(code), sz = shift_z(code);
-            if (sx < 0) xj.x -= S.L[0];
-            if (sy < 0) xj.y -= S.L[1];
-            if (sz < 0) xj.z -= S.L[2];
+            xj.x -= (sx < 0) ? S.L[0] : 0.f;
+            xj.y -= (sy < 0) ? S.L[1] : 0.f;
+            xj.z -= (sz < 0) ? S.L[2] : 0.f;
             const float sxi = sx > 0 ? S.L[0] : 0.f, syi = sy > 0 ? S.L[1] : 0.f,
                         szi = sz > 0 ? S.L[2] : 0.f;
-#define NB_BLOCK1(c)                                                                   \
+#define NB_BLOCK(c)                                                                    \
     if ((mask >> c) & 1u)                                                              \
         bwd_block<COUL, LJGRAD, PRIV, true>(                                           \
             xi##c, yi##c, zi##c, s_gq + kClusterSize * c + ii, s_ti + kClusterSize * c + ii, \
             NB_MASK(c), ax##c, ay##c, az##c, aq##c, xj, gj, tj, s_lj, s_hist, lane, kp, bs, \
             sxi, syi, szi, ajx, ajy, ajz, ajq);
-            NB_FOR8(NB_BLOCK1)
-#undef NB_BLOCK1
+            NB_FOR8(NB_BLOCK)
+#undef NB_BLOCK
         }
 #undef NB_MASK
         ajx = dpp_sum8(ajx);

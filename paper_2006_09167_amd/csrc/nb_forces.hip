@@ -63,25 +63,16 @@ __device__ inline float erfcx_poly(float t) {
 }
 
 // One 8x8 block of pairs (i-cluster c of the item, the current j-cluster): m is the
-// scalar 64-bit mask of valid, non-excluded lanes (lane = ii + 8 jj).
-// Squared distance in the list-decision sequence (each product and sum rounded).
-__device__ inline float list_r2_exact(float dx, float dy, float dz) {
-#pragma clang fp contract(off)
-    const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-    const float t = xx + yy;
-    return t + zz;
-}
-
-template <int COUL, bool ENERGY, bool VIRIAL, bool SHIFTED, bool PRUNE>
+// scalar 64-bit mask of non-excluded lanes (lane = ii + 8 jj).
+template <int COUL, bool ENERGY, bool VIRIAL, bool SHIFTED>
 __device__ __forceinline__ void pair_block(float xi, float yi, float zi, const float2* s_qt,
-                                           uint64_t m_list, uint64_t m, float& fx, float& fy,
+                                           uint64_t m, float& fx, float& fy,
                                            float& fz, const float4& xj, int tj,
                                            const float4* __restrict__ s_lj, const NbKParams& kp,
                                            float sxi, float syi, float szi, float& fjx,
                                            float& fjy, float& fjz, float& elj, float& ec,
-                                           float& eclo, float (&vir)[6], int& npair, int& nblock,
-                                           bool do_prune, float r2_inner, uint32_t& new_inner,
-                                           int c) {
+                                           float& eclo, float (&vir)[6], int& npair,
+                                           int& nblock) {
     // The same separation as the list build: x_i - L for s > 0 on the i side, the j side
     // already shifted by -L for s < 0.
     float dx, dy, dz;
@@ -93,13 +84,6 @@ __device__ __forceinline__ void pair_block(float xi, float yi, float zi, const f
         dx = xi - xj.x;
         dy = yi - xj.y;
         dz = zi - xj.z;
-    }
-    if (PRUNE && do_prune) {
-        // rolling prune of this cluster pair (Sec. V.E): inner iff an atom pair is inside
-        // rinner; exclusions do not remove cluster pairs
-        const float r2l = list_r2_exact(dx, dy, dz);
-        if (!(__builtin_amdgcn_ballot_w64(r2l < r2_inner) & m_list)) return;
-        new_inner |= 1u << c;
     }
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     const uint64_t act = __builtin_amdgcn_ballot_w64(r2 < kp.rc2) & m;
@@ -203,9 +187,50 @@ __device__ __forceinline__ void fwd_item(
     double vir_acc[6] = {0, 0, 0, 0, 0, 0};
     int npair = 0, nblock = 0;
 
-    // items of the part pruned in this pass walk their outer masks and rewrite the inner ones
-    const bool do_prune = PRUNE && item >= prune_i0 && item < prune_i1;
     const int e_end = it.e0 + it.ne;
+    // Items of the rolling part pruned in this pass (Sec. V.E) first re-derive the inner
+    // masks of all their entries from the outer masks and the current coordinates, in the
+    // list arithmetic: lane (e - e0) keeps entry e's new mask (items hold at most 64
+    // entries) for the force loop below, lane 0 writes it back for later passes.
+    const bool do_prune = PRUNE && item >= prune_i0 && item < prune_i1;
+    uint32_t pmask = 0;
+    if (do_prune) {
+#pragma clang fp contract(off)
+        NbEntry p1 = entries[it.e0];
+        float4 y1 = xq[kClusterSize * p1.cj + jj];
+        for (int e = it.e0; e < e_end; ++e) {
+            const NbEntry ent = p1;
+            float4 xj = y1;
+            if (e + 1 < e_end) {
+                p1 = entries[e + 1];
+                y1 = xq[kClusterSize * p1.cj + jj];
+            }
+            const int code = ent.meta & 31u;
+            const int sx = shift_x(code), sy = shift_y(code), sz = shift_z(code);
+            xj.x -= (sx < 0) ? S.L[0] : 0.f;
+            xj.y -= (sy < 0) ? S.L[1] : 0.f;
+            xj.z -= (sz < 0) ? S.L[2] : 0.f;
+            const float ox = (sx > 0) ? S.L[0] : 0.f, oy = (sy > 0) ? S.L[1] : 0.f,
+                        oz = (sz > 0) ? S.L[2] : 0.f;
+            const uint32_t omask = (ent.meta >> 8) & 0xffu;
+            const bool selfp = (ent.cj >> 3) == sc && code == kShiftZero;
+            const int dcp = ent.cj - ci0;
+            uint32_t imask = 0;
+#define NB_PB(c)                                                                       \
+            if ((omask >> c) & 1u) {                                                   \
+                const float dx = (xi##c - ox) - xj.x;                                  \
+                const float dy = (yi##c - oy) - xj.y;                                  \
+                const float dz = (zi##c - oz) - xj.z;                                  \
+                const float r2 = (dx * dx + dy * dy) + dz * dz;                        \
+                const uint64_t m = (selfp && dcp == c) ? 0x7f3f1f0f07030100ull : ~0ull;  \
+                if (__builtin_amdgcn_ballot_w64(r2 < r2_inner) & m) imask |= 1u << c;  \
+            }
+            NB_FOR8(NB_PB)
+#undef NB_PB
+            if (lane == e - it.e0) pmask = imask;
+            if (lane == 0) entries[e].meta = (ent.meta & ~(0xffu << 16)) | (imask << 16);
+        }
+    }
     NbEntry nxt = entries[it.e0];
     float4 xj_n = xq[kClusterSize * nxt.cj + jj];
     int tj_n = type_slot[kClusterSize * nxt.cj + jj];
@@ -218,13 +243,11 @@ __device__ __forceinline__ void fwd_item(
             xj_n = xq[kClusterSize * nxt.cj + jj];
             tj_n = type_slot[kClusterSize * nxt.cj + jj];
         }
-        const uint32_t mask = (ent.meta >> (do_prune ? 8 : 16)) & 0xffu;
+        const uint32_t mask =
+            do_prune ? (uint32_t)__builtin_amdgcn_readlane((int)pmask, e - it.e0)
+                     : (ent.meta >> 16) & 0xffu;
         float4* jp = jpart + (size_t)ent.jpos * kClusterSize;
-        if (!mask) {
-            if (ii == 0) jp[jj] = make_float4(0.f, 0.f, 0.f, 0.f);
-            continue;
-        }
-        uint32_t new_inner = 0;
+        // an entry with an empty mask runs no block and stores zero j-partials below
         const int code = ent.meta & 31u;
         const uint64_t* xrow =
             (ent.excl >= 0) ? excl_rows + (size_t)ent.excl * kClustersPerSc : nullptr;
@@ -233,40 +256,28 @@ __device__ __forceinline__ void fwd_item(
         float vir[6] = {0, 0, 0, 0, 0, 0};
         const int dc = ent.cj - ci0;        // the i-cluster equal to the j-cluster, if any
 
-        // list mask: self cluster pairs keep ii < jj only (empty slots fail every test)
-#define NB_LMASK(c) ((self && dc == c) ? 0x7f3f1f0f07030100ull : ~0ull)
-#define NB_MASK(c) (NB_LMASK(c) & (xrow ? xrow[c] : ~0ull))
-        if (code == kShiftZero) {
-#define NB_BLOCK0(c)                                                                   \
-    if ((mask >> c) & 1u)                                                              \
-        pair_block<COUL, ENERGY, VIRIAL, false, PRUNE>(                                \
-            xi##c, yi##c, zi##c, s_qt + kClusterSize * c + ii, NB_LMASK(c), NB_MASK(c),  \
-            fx##c, fy##c,                                                                \
-            fz##c, xj, tj, s_lj, kp, 0.f, 0.f, 0.f, fjx, fjy, fjz, elj, ec, eclo, vir, npair,  \
-            nblock, do_prune, r2_inner, new_inner, c);
-            NB_FOR8(NB_BLOCK0)
-#undef NB_BLOCK0
-        } else {
-            // Exact periodic shift: subtract L on the side whose coordinate is near L.
+        // self cluster pairs keep ii < jj only (empty slots fail every distance test)
+#define NB_MASK(c) (((self && dc == c) ? 0x7f3f1f0f07030100ull : ~0ull) & (xrow ? xrow[c] : ~0ull))
+        // Exact periodic shift, one code path for every entry: subtract L on the side whose
+        // coordinate is near L (nothing for s = 0, and x - 0 is exact, so unshifted pairs
+        // see the same arithmetic as without any shift).
+        {
             const int sx = shift_x(code), sy = shift_y(code), sz = shift_z(code);
-            if (sx < 0) xj.x -= S.L[0];
-            if (sy < 0) xj.y -= S.L[1];
-            if (sz < 0) xj.z -= S.L[2];
+            xj.x -= (sx < 0) ? S.L[0] : 0.f;
+            xj.y -= (sy < 0) ? S.L[1] : 0.f;
+            xj.z -= (sz < 0) ? S.L[2] : 0.f;
             const float sxi = sx > 0 ? S.L[0] : 0.f, syi = sy > 0 ? S.L[1] : 0.f,
                         szi = sz > 0 ? S.L[2] : 0.f;
-#define NB_BLOCK1(c)                                                                   \
+#define NB_BLOCK(c)                                                                    \
     if ((mask >> c) & 1u)                                                              \
-        pair_block<COUL, ENERGY, VIRIAL, true, PRUNE>(                                 \
-            xi##c, yi##c, zi##c, s_qt + kClusterSize * c + ii, NB_LMASK(c), NB_MASK(c),  \
-            fx##c, fy##c,                                                                \
-            fz##c, xj, tj, s_lj, kp, sxi, syi, szi, fjx, fjy, fjz, elj, ec, eclo, vir, npair,  \
-            nblock, do_prune, r2_inner, new_inner, c);
-            NB_FOR8(NB_BLOCK1)
-#undef NB_BLOCK1
+        pair_block<COUL, ENERGY, VIRIAL, true>(                                        \
+            xi##c, yi##c, zi##c, s_qt + kClusterSize * c + ii, NB_MASK(c), fx##c, fy##c,  \
+            fz##c, xj, tj, s_lj, kp, sxi, syi, szi, fjx, fjy, fjz, elj, ec, eclo, vir,    \
+            npair, nblock);
+            NB_FOR8(NB_BLOCK)
+#undef NB_BLOCK
         }
 #undef NB_MASK
-#undef NB_LMASK
-        if (do_prune && lane == 0) entries[e].meta = (ent.meta & ~(0xffu << 16)) | (new_inner << 16);
         fjx = dpp_sum8(fjx);
         fjy = dpp_sum8(fjy);
         fjz = dpp_sum8(fjz);
@@ -319,7 +330,8 @@ __device__ inline int xcd_block(int b, int g) {
 }
 
 // Execution modes (chosen per context, by hand or by the autotuner):
-//   kExecStatic  one wavefront per item, item = 4 block + wave;
+//   kExecStatic  one wavefront per item, item = 4 block + wave (rolling-part major: the
+//                items processed together are four super-clusters apart);
 //   kExecXcd     the same with the XCD-contiguous block numbering above;
 //   kExecQueue   persistent: a grid that fills the device once; wavefronts take items
 //                from an atomic counter in the order given by `order` (most pair work

@@ -26,6 +26,7 @@ struct nb_ctx {
     int32_t item_w = 0;       // entries per work item of the current list
     int32_t fixed_w = 0;      // item width chosen by nb_set_exec / nb_autotune (0 = rule)
     int32_t exec_mode = kExecStatic;
+    bool prune_fused = true;  // nb_step: rolling prune inside the pair kernel, else separate
     uint64_t list_gen = 0;    // bumped whenever items or launch shapes change
     // graphs of nb_step_graph: key = (part, flags, pointers, list_gen)
     struct GraphEntry {
@@ -599,7 +600,7 @@ nb_status nb_prune_rolling(nb_ctx* c, const float* x, int64_t steps_since_build)
     const int i0 = c->part_start[part], i1 = c->part_start[part + 1];
     TimedSection ts(c, NB_T_PRUNE);
     NB_HIP(c, launch_gather(c->d, x, nullptr, c->d.xp, c->n_slots, c->stream));
-    NB_HIP(c, launch_prune(c->d, i0, i1 - i0, radius_sq(c->p.rinner), c->stream));
+    NB_HIP(c, launch_prune(c->d, c->d.xp, i0, i1 - i0, radius_sq(c->p.rinner), c->stream));
     return NB_OK;
 }
 
@@ -614,11 +615,19 @@ nb_status forces_impl(nb_ctx* c, const float* x, const float* q, const float* lj
     NB_HIP(c, hipSetDevice(c->device));
     NbDev& d = c->d;
     const NbKParams kp = kernel_params(c->p);
-    const int pi0 = prune_part >= 0 ? c->part_start[prune_part] : 0;
-    const int pi1 = prune_part >= 0 ? c->part_start[prune_part + 1] : 0;
+    const bool fused = prune_part >= 0 && c->prune_fused;
+    const int pi0 = fused ? c->part_start[prune_part] : 0;
+    const int pi1 = fused ? c->part_start[prune_part + 1] : 0;
     {
         TimedSection ts(c, NB_T_FORCE_REDUCE);
         NB_HIP(c, launch_gather(d, x, q, d.xq, c->n_slots, c->stream));
+    }
+    if (prune_part >= 0 && !fused) {
+        // the rolling prune of the part as its own kernel on the gathered coordinates,
+        // then the plain pair kernel
+        const int i0 = c->part_start[prune_part], i1 = c->part_start[prune_part + 1];
+        TimedSection ts(c, NB_T_PRUNE);
+        NB_HIP(c, launch_prune(d, d.xq, i0, i1 - i0, radius_sq(c->p.rinner), c->stream));
     }
     {
         TimedSection ts(c, NB_T_FORCES);
@@ -719,13 +728,15 @@ nb_status nb_step_graph(nb_ctx* c, const float* x, const float* q, const float* 
     return NB_OK;
 }
 
-nb_status nb_set_exec(nb_ctx* c, int32_t width, int32_t exec_mode) {
+nb_status nb_set_exec(nb_ctx* c, int32_t width, int32_t exec_mode, int32_t prune_fused) {
     if (!c) return NB_ERR_ARG;
     if (width < 0 || width > 64) return fail(c, NB_ERR_ARG, "item width must be 0 (rule) or 1..64");
     if (exec_mode != kExecStatic && exec_mode != kExecXcd && exec_mode != kExecQueue)
         return fail(c, NB_ERR_ARG, "unknown execution mode");
+    if (prune_fused != 0 && prune_fused != 1) return fail(c, NB_ERR_ARG, "prune_fused is 0 or 1");
     c->fixed_w = width;
     c->exec_mode = exec_mode;
+    c->prune_fused = prune_fused != 0;
     c->list_gen++;
     if (c->d.flags) {
         NB_HIP(c, hipSetDevice(c->device));
@@ -743,6 +754,8 @@ nb_status nb_get_exec(nb_ctx* c, nb_exec_config* out) {
     if (!c || !out) return NB_ERR_ARG;
     out->item_width = c->has_list ? c->item_w : c->fixed_w;
     out->exec_mode = c->exec_mode;
+    out->prune_fused = c->prune_fused ? 1 : 0;
+    out->reserved = 0;
     out->us_per_call = 0.0;
     return NB_OK;
 }
@@ -774,9 +787,29 @@ nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj
     c->timing = false;
     const int widths[] = {8, 16, 24, 32, 48, 64};
     const int modes[] = {kExecStatic, kExecXcd, kExecQueue};
-    nb_exec_config win{0, 0, 1e300};
+    nb_exec_config win{0, 0, 1, 0, 1e300};
     int n = 0;
     nb_status st = NB_OK;
+    // median time of `repeats` calls after a warm-up; part < 0: forces only, else a step
+    // that also re-prunes that rolling part (valid with any current positions)
+    auto time_calls = [&](int part, double* us) {
+        std::vector<float> ms;
+        for (int r = 0; r <= repeats && st == NB_OK; ++r) {
+            hipEventRecord(e0, c->stream);
+            st = forces_impl(c, x, q, lj, f, ev, ev + 2 * c->n_sys, flags, part);
+            hipEventRecord(e1, c->stream);
+            if (st == NB_OK && hipEventSynchronize(e1) != hipSuccess)
+                st = fail(c, NB_ERR_HIP, "autotune event");
+            float t = 0.f;
+            if (st == NB_OK && r > 0 && hipEventElapsedTime(&t, e0, e1) == hipSuccess)
+                ms.push_back(t);
+        }
+        if (st != NB_OK || ms.empty()) return false;
+        std::sort(ms.begin(), ms.end());
+        *us = 1e3 * ms[ms.size() / 2];
+        return true;
+    };
+    const bool fused0 = c->prune_fused;
     for (int W : widths) {
         if (st != NB_OK) break;
         st = make_items(c, W, false);
@@ -784,23 +817,32 @@ nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj
         for (int m : modes) {
             if (st != NB_OK) break;
             c->exec_mode = m;
-            std::vector<float> ms;
-            for (int r = 0; r <= repeats && st == NB_OK; ++r) {   // the first call warms up
-                hipEventRecord(e0, c->stream);
-                st = forces_impl(c, x, q, lj, f, ev, ev + 2 * c->n_sys, flags, -1);
-                hipEventRecord(e1, c->stream);
-                if (st == NB_OK && hipEventSynchronize(e1) != hipSuccess)
-                    st = fail(c, NB_ERR_HIP, "autotune event");
-                float t = 0.f;
-                if (st == NB_OK && r > 0 && hipEventElapsedTime(&t, e0, e1) == hipSuccess)
-                    ms.push_back(t);
-            }
-            if (st != NB_OK || ms.empty()) break;
-            std::sort(ms.begin(), ms.end());
-            const nb_exec_config t{W, m, 1e3 * ms[ms.size() / 2]};
+            double us = 0.0;
+            if (!time_calls(-1, &us)) break;
+            const nb_exec_config t{W, m, fused0 ? 1 : 0, 0, us};
             if (n < cap) trials[n] = t;
             ++n;
             if (t.us_per_call < win.us_per_call) win = t;
+        }
+    }
+    // Then, for the chosen shape, a rolling step with the prune fused into the pair kernel
+    // against the prune as its own kernels; the step time decides.
+    if (st == NB_OK) {
+        st = make_items(c, win.item_width, false);
+        if (st == NB_OK) st = finish_items(c);
+        c->exec_mode = win.exec_mode;
+        double best_step = 1e300;
+        for (int pf = 1; pf >= 0 && st == NB_OK; --pf) {
+            c->prune_fused = pf != 0;
+            double us = 0.0;
+            if (!time_calls(c->p.nstprune > 1 ? 1 : 0, &us)) break;
+            const nb_exec_config t{win.item_width, win.exec_mode, pf, 0, us};
+            if (n < cap) trials[n] = t;
+            ++n;
+            if (us < best_step) {
+                best_step = us;
+                win.prune_fused = pf;
+            }
         }
     }
     c->timing = timing;
@@ -812,8 +854,8 @@ nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj
     if (n_trials) *n_trials = n;
     c->fixed_w = win.item_width;
     c->exec_mode = win.exec_mode;
-    st = make_items(c, win.item_width, false);
-    if (st == NB_OK) st = finish_items(c);
+    c->prune_fused = win.prune_fused != 0;
+    st = finish_items(c);          // fresh item order and no graphs of the timing calls
     if (st != NB_OK) return st;
     if (best) *best = win;
     return NB_OK;

@@ -113,8 +113,8 @@ hipError_t launch_fill(int32_t* p, int n, int32_t v, hipStream_t s);
 hipError_t launch_fill_d(double* p, int n, double v, hipStream_t s);
 hipError_t launch_gather(const NbDev& d, const float* x, const float* q, float4* out,
                          int n_slots, hipStream_t s);
-hipError_t launch_prune(const NbDev& d, int item0, int n_items, float r2_inner,
-                        hipStream_t s);
+hipError_t launch_prune(const NbDev& d, const float4* coords, int item0, int n_items,
+                        float r2_inner, hipStream_t s);
 hipError_t launch_forces(const NbDev& d, const NbKParams& kp, int coulomb, uint32_t flags,
                          const float* lj, int n_items, int prune_i0, int prune_i1,
                          float r2_inner, int mode, hipStream_t s);

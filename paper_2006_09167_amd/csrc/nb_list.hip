@@ -325,54 +325,68 @@ __global__ __launch_bounds__(kWave) void k_jseg_rank(NbDev d) {
     }
 }
 
-// Rolling prune (Sec. V.E): one block of eight wavefronts per work item of the part; the
-// waves take every eighth entry and re-derive its inner mask from its outer mask and the
-// current coordinates.
-constexpr int kPruneWaves = 8;
-
+constexpr int kPruneWaves = 4;
 #define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
+// Rolling prune (Sec. V.E) of a range of work items: one wavefront per item, the item's
+// eight i-clusters loaded once, entries processed in order with the next two entries'
+// j-clusters in flight.  For every i-cluster of the outer mask the inner bit is set iff
+// some atom pair is closer than r_inner in the list arithmetic (shift split between the
+// two sides, no contraction).  Empty slots sit far outside the box, so no valid-atom masks
+// are needed; a cluster with itself keeps ii < jj.
 __global__ __launch_bounds__(kPruneWaves * kWave) void k_prune(
     const NbItem* __restrict__ items, NbEntry* __restrict__ entries,
-    const float4* __restrict__ xp, const float4* __restrict__ cl_bb,
-    const NbScInfo* __restrict__ sc_info, const NbSys* __restrict__ sys, int item0,
-    float r2_inner) {
-    const NbItem it = items[item0 + blockIdx.x];
+    const float4* __restrict__ xp, const NbScInfo* __restrict__ sc_info,
+    const NbSys* __restrict__ sys, int item0, int n_items, float r2_inner) {
+#pragma clang fp contract(off)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x & (kWave - 1);
+    const int k = blockIdx.x * kPruneWaves + wave;
+    if (k >= n_items) return;
+    const NbItem it = items[item0 + k];
     const int ii = lane & 7, jj = lane >> 3;
     const NbSys S = sys[sc_info[it.sc].sys];
     const int ci0 = kClustersPerSc * it.sc;
-    // the eight i-clusters' coordinates and valid-lane masks, in registers
-#define NB_PI(c)                                                                       \
-    const float4 xi##c = xp[kScAtoms * it.sc + kClusterSize * c + ii];                 \
-    const int ni##c = (int)cl_bb[2 * (ci0 + c)].w;                                     \
-    const uint64_t iv##c =                                                             \
-        ((ni##c >= 8) ? 0xffull : ((1ull << ni##c) - 1ull)) * 0x0101010101010101ull;
+#define NB_PI(c) const float4 xi##c = xp[kScAtoms * it.sc + kClusterSize * c + ii];
     NB_FOR8(NB_PI)
 #undef NB_PI
     const int e_end = it.e0 + it.ne;
-    int e = it.e0 + wave;
-    NbEntry nxt = entries[min(e, e_end - 1)];
-    float4 xj_n = xp[kClusterSize * nxt.cj + jj];
-    for (; e < e_end; e += kPruneWaves) {
-        const NbEntry ent = nxt;
-        const float4 xj = xj_n;
-        if (e + kPruneWaves < e_end) {       // prefetch this wave's next entry
-            nxt = entries[e + kPruneWaves];
-            xj_n = xp[kClusterSize * nxt.cj + jj];
+    // two entries ahead: (ent1, xj1) is the next one, (ent2, xj2) the one after
+    NbEntry ent1 = entries[it.e0];
+    float4 xj1 = xp[kClusterSize * ent1.cj + jj];
+    NbEntry ent2 = ent1;
+    float4 xj2 = xj1;
+    if (it.e0 + 1 < e_end) {
+        ent2 = entries[it.e0 + 1];
+        xj2 = xp[kClusterSize * ent2.cj + jj];
+    }
+    for (int e = it.e0; e < e_end; ++e) {
+        const NbEntry ent = ent1;
+        float4 xj = xj1;
+        ent1 = ent2;
+        xj1 = xj2;
+        if (e + 2 < e_end) {
+            ent2 = entries[e + 2];
+            xj2 = xp[kClusterSize * ent2.cj + jj];
         }
         const int code = ent.meta & 31u;
         const int sx = shift_x(code), sy = shift_y(code), sz = shift_z(code);
-        const int nj = (int)(ent.meta >> 24);
         const uint32_t omask = (ent.meta >> 8) & 0xffu;
-        const uint64_t jv = (nj >= 8) ? ~0ull : ((1ull << (8 * nj)) - 1ull);
         const int dc = (code == kShiftZero) ? ent.cj - ci0 : -1;
+        // the same separation as the list build: x_i - L for s > 0, x_j - L for s < 0
+        xj.x -= (sx < 0) ? S.L[0] : 0.f;
+        xj.y -= (sy < 0) ? S.L[1] : 0.f;
+        xj.z -= (sz < 0) ? S.L[2] : 0.f;
+        const float ox = (sx > 0) ? S.L[0] : 0.f, oy = (sy > 0) ? S.L[1] : 0.f,
+                    oz = (sz > 0) ? S.L[2] : 0.f;
         uint32_t imask = 0;
 #define NB_PB(c)                                                                       \
         if ((omask >> c) & 1u) {                                                       \
-            const float r2 = list_r2(xi##c, xj, sx, sy, sz, S);                        \
-            const uint64_t m = iv##c & jv & (dc == c ? 0x7f3f1f0f07030100ull : ~0ull); \
+            const float dx = (xi##c.x - ox) - xj.x;                                    \
+            const float dy = (xi##c.y - oy) - xj.y;                                    \
+            const float dz = (xi##c.z - oz) - xj.z;                                    \
+            const float r2 = (dx * dx + dy * dy) + dz * dz;                            \
+            const uint64_t m = (dc == c) ? 0x7f3f1f0f07030100ull : ~0ull;              \
             if (__builtin_amdgcn_ballot_w64(r2 < r2_inner) & m) imask |= 1u << c;      \
         }
         NB_FOR8(NB_PB)
@@ -468,9 +482,11 @@ hipError_t launch_list_finish(const NbDev& d, int n_sc, int64_t n_entries, int n
     return hipGetLastError();
 }
 
-hipError_t launch_prune(const NbDev& d, int item0, int n_items, float r2_inner, hipStream_t s) {
+hipError_t launch_prune(const NbDev& d, const float4* coords, int item0, int n_items,
+                        float r2_inner, hipStream_t s) {
     if (n_items > 0)
-        hipLaunchKernelGGL(k_prune, dim3(n_items), dim3(kPruneWaves * kWave), 0, s, d.items,
-                           d.entries, d.xp, d.cl_bb, d.sc_info, d.sys, item0, r2_inner);
+        hipLaunchKernelGGL(k_prune, dim3(blocks(n_items, kPruneWaves)), dim3(kPruneWaves * kWave),
+                           0, s, d.items, d.entries, coords, d.sc_info, d.sys, item0, n_items,
+                           r2_inner);
     return hipGetLastError();
 }

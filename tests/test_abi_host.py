@@ -129,14 +129,15 @@ def test_exec_shape_validation_without_device():
     st, h = create(good_params(), offsets=(0, 4))
     assert st == _lib.NB_OK
     try:
-        assert ctypes.sizeof(_lib.NbExecConfig) == 16
-        assert lib.nb_set_exec(h, -1, _lib.NB_EXEC_STATIC) == _lib.NB_ERR_ARG
-        assert lib.nb_set_exec(h, 65, _lib.NB_EXEC_STATIC) == _lib.NB_ERR_ARG
-        assert lib.nb_set_exec(h, 16, 3) == _lib.NB_ERR_ARG
-        assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_QUEUE) == _lib.NB_OK
+        assert ctypes.sizeof(_lib.NbExecConfig) == 24
+        assert lib.nb_set_exec(h, -1, _lib.NB_EXEC_STATIC, 1) == _lib.NB_ERR_ARG
+        assert lib.nb_set_exec(h, 65, _lib.NB_EXEC_STATIC, 1) == _lib.NB_ERR_ARG
+        assert lib.nb_set_exec(h, 16, 3, 1) == _lib.NB_ERR_ARG
+        assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_STATIC, 2) == _lib.NB_ERR_ARG
+        assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_QUEUE, 0) == _lib.NB_OK
         cfg = _lib.NbExecConfig()
         assert lib.nb_get_exec(h, ctypes.byref(cfg)) == _lib.NB_OK
-        assert (cfg.item_width, cfg.exec_mode) == (16, _lib.NB_EXEC_QUEUE)
+        assert (cfg.item_width, cfg.exec_mode, cfg.prune_fused) == (16, _lib.NB_EXEC_QUEUE, 0)
         n = ctypes.c_int32(0)
         best = _lib.NbExecConfig()
         assert lib.nb_autotune(h, None, None, None, 1, 3, None, 0, ctypes.byref(n),

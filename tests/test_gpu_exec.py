@@ -44,7 +44,7 @@ def test_modes_bitwise_equal_and_queue_relaunches(sys3k, width):
     ref = None
     for mode in ("static", "xcd", "queue", "queue", "queue", "static"):
         ctx.set_exec(width, mode)
-        assert ctx.get_exec() == {"item_width": width, "mode": mode}
+        assert ctx.get_exec() == {"item_width": width, "mode": mode, "prune_fused": True}
         out = ctx.forces(x, q, lj, energy=True, virial=True)
         torch.cuda.synchronize()
         if ref is None:
@@ -75,6 +75,29 @@ def test_fused_step_in_queue_mode_matches_static(sys3k):
     assert np.array_equal(ctx_a.get_pairs("inner"), ctx_b.get_pairs("inner"))
 
 
+@pytest.mark.parametrize("mode", ["xcd", "queue"])
+def test_separate_prune_step_equals_fused(sys3k, mode):
+    """nb_step with the prune as separate kernels: the same inner lists and bitwise the
+    same outputs as with the prune fused into the pair kernel."""
+    c = concat(sys3k)
+    kw = dict(nstlist=20, nstprune=4, **EWALD)
+    ctx_a, _ = built(c, **kw)
+    ctx_b, _ = built(c, **kw)
+    ctx_a.set_exec(16, mode, prune_fused=True)
+    ctx_b.set_exec(16, mode, prune_fused=False)
+    q, lj = dev(c["q"]), dev(c["lj"])
+    rng = np.random.default_rng(4)
+    x = c["x"].copy()
+    for t in range(1, 9):
+        x = (x + rng.normal(0, 0.01, x.shape)).astype(np.float32)
+        xt = dev(x)
+        fa, ea, va = ctx_a.step(xt, q, lj, t, energy=True, virial=True)
+        fb, eb, vb = ctx_b.step(xt, q, lj, t, energy=True, virial=True, graph=(t % 2 == 0))
+        torch.cuda.synchronize()
+        assert torch.equal(fa, fb) and torch.equal(ea, eb) and torch.equal(va, vb), t
+    assert np.array_equal(ctx_a.get_pairs("inner"), ctx_b.get_pairs("inner"))
+
+
 def test_item_width_changes_only_rounding(sys3k):
     """Another item width re-splits the lists: outputs agree with the default to FP32
     summation-order rounding and stay within the oracle bars."""
@@ -99,10 +122,14 @@ def test_autotune_keeps_fastest_and_stays_exact(sys3k):
     ctx, x = built(c, nstlist=10, nstprune=2, **EWALD)
     q, lj = dev(c["q"]), dev(c["lj"])
     best, trials = ctx.autotune(x, q, lj, energy=True, repeats=3)
-    assert len(trials) == 18
+    assert len(trials) == 20
     assert all(t["us_per_call"] > 0 for t in trials)
-    assert best["us_per_call"] == min(t["us_per_call"] for t in trials)
-    assert ctx.get_exec() == {"item_width": best["item_width"], "mode": best["mode"]}
+    shape = min(trials[:18], key=lambda t: t["us_per_call"])
+    assert (best["item_width"], best["mode"]) == (shape["item_width"], shape["mode"])
+    step = min(trials[18:], key=lambda t: t["us_per_call"])
+    assert best["prune_fused"] == step["prune_fused"]
+    assert ctx.get_exec() == {"item_width": best["item_width"], "mode": best["mode"],
+                              "prune_fused": best["prune_fused"]}
     f, e, _ = ctx.forces(x, q, lj)
     torch.cuda.synchronize()
     check_oracle(c, c["x"], f, e, "ewald", 1.0, 3.12)
