@@ -65,7 +65,7 @@ __device__ inline float erfcx_poly(float t) {
 // One 8x8 block of pairs (i-cluster c of the item, the current j-cluster): m is the
 // scalar 64-bit mask of non-excluded lanes (lane = ii + 8 jj).
 template <int COUL, bool ENERGY, bool VIRIAL, bool SHIFTED>
-__device__ __forceinline__ void pair_block(float xi, float yi, float zi, const float2* s_qt,
+__device__ __forceinline__ void pair_block(const float4* s_x, const int* s_t,
                                            uint64_t m, float& fx, float& fy,
                                            float& fz, const float4& xj, int tj,
                                            const float4* __restrict__ s_lj, const NbKParams& kp,
@@ -75,23 +75,23 @@ __device__ __forceinline__ void pair_block(float xi, float yi, float zi, const f
                                            int& nblock) {
     // The same separation as the list build: x_i - L for s > 0 on the i side, the j side
     // already shifted by -L for s < 0.
+    const float4 xv = *s_x;                            // (x_i, y_i, z_i, K q_i) of this lane
     float dx, dy, dz;
     if (SHIFTED) {
-        dx = (xi - sxi) - xj.x;
-        dy = (yi - syi) - xj.y;
-        dz = (zi - szi) - xj.z;
+        dx = (xv.x - sxi) - xj.x;
+        dy = (xv.y - syi) - xj.y;
+        dz = (xv.z - szi) - xj.z;
     } else {
-        dx = xi - xj.x;
-        dy = yi - xj.y;
-        dz = zi - xj.z;
+        dx = xv.x - xj.x;
+        dy = xv.y - xj.y;
+        dz = xv.z - xj.z;
     }
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     const uint64_t act = __builtin_amdgcn_ballot_w64(r2 < kp.rc2) & m;
     if (!act) return;
     const bool on = __builtin_amdgcn_inverse_ballot_w64(act);
-    const float2 qt = *s_qt;                           // (K q_i, type_i * T) of this lane's i-atom
-    const float qi = qt.x;
-    const int ti = __builtin_bit_cast(int, qt.y);
+    const float qi = xv.w;
+    const int ti = *s_t;                               // type_i * T
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float rinv2 = rinv * rinv;
     const float4 p = s_lj[ti + tj];                    // (6 c6, 12 c12, shift, c6)
@@ -143,14 +143,15 @@ __device__ __forceinline__ void pair_block(float xi, float yi, float zi, const f
     }
 }
 
-// Per-cluster scalars of the item's eight i-clusters (kept in registers).
+// Per-cluster code of the item's eight i-clusters (unrolled; force sums in registers).
 #define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
-// The work of one item (one wavefront): s_qt is the wavefront's 64-entry LDS table of
-// i-charges and types, s_lj the block's LJ table.
+// The work of one item (one wavefront): s_x and s_t are the wavefront's 64-entry LDS
+// tables of the super-cluster's atoms ((x, y, z, K q) and type * T, by slot), s_lj the
+// block's LJ table.
 template <int COUL, bool ENERGY, bool VIRIAL, bool PRUNE>
 __device__ __forceinline__ void fwd_item(
-    const int item, const int lane, float2* s_qt, const float4* __restrict__ s_lj,
+    const int item, const int lane, float4* s_x, int* s_t, const float4* __restrict__ s_lj,
     const NbItem* __restrict__ items, NbEntry* __restrict__ entries,
     const uint64_t* __restrict__ excl_rows, const float4* __restrict__ xq,
     const int32_t* __restrict__ type_slot, const NbScInfo* __restrict__ sc_info,
@@ -162,26 +163,17 @@ __device__ __forceinline__ void fwd_item(
     const int ii = lane & 7, jj = lane >> 3;
     const int sc = it.sc, ci0 = kClustersPerSc * sc;
     const NbSys S = sys[sc_info[sc].sys];
-    const int ibase = kScAtoms * sc + ii;
     {
         // lane l holds slot l of the super-cluster: (8 c + ii) for c = l >> 3
         const float4 v = xq[kScAtoms * sc + lane];
-        s_qt[lane] = make_float2(v.w * kp.epsfac_r,
-                                 __builtin_bit_cast(float, type_slot[kScAtoms * sc + lane] * T));
+        s_x[lane] = make_float4(v.x, v.y, v.z, v.w * kp.epsfac_r);
+        s_t[lane] = type_slot[kScAtoms * sc + lane] * T;
     }
     __builtin_amdgcn_wave_barrier();
 
-#define NB_ILOAD(c)                                                                    \
-    float xi##c, yi##c, zi##c;                                                         \
-    float fx##c = 0.f, fy##c = 0.f, fz##c = 0.f;                                       \
-    {                                                                                  \
-        const float4 v = xq[ibase + kClusterSize * c];                                 \
-        xi##c = v.x;                                                                   \
-        yi##c = v.y;                                                                   \
-        zi##c = v.z;                                                                   \
-    }
-    NB_FOR8(NB_ILOAD)
-#undef NB_ILOAD
+#define NB_IZERO(c) float fx##c = 0.f, fy##c = 0.f, fz##c = 0.f;
+    NB_FOR8(NB_IZERO)
+#undef NB_IZERO
 
     double elj_acc = 0.0, ec_acc = 0.0;
     double vir_acc[6] = {0, 0, 0, 0, 0, 0};
@@ -218,9 +210,10 @@ __device__ __forceinline__ void fwd_item(
             uint32_t imask = 0;
 #define NB_PB(c)                                                                       \
             if ((omask >> c) & 1u) {                                                   \
-                const float dx = (xi##c - ox) - xj.x;                                  \
-                const float dy = (yi##c - oy) - xj.y;                                  \
-                const float dz = (zi##c - oz) - xj.z;                                  \
+                const float4 xv = s_x[kClusterSize * c + ii];                          \
+                const float dx = (xv.x - ox) - xj.x;                                   \
+                const float dy = (xv.y - oy) - xj.y;                                   \
+                const float dz = (xv.z - oz) - xj.z;                                   \
                 const float r2 = (dx * dx + dy * dy) + dz * dz;                        \
                 const uint64_t m = (selfp && dcp == c) ? 0x7f3f1f0f07030100ull : ~0ull;  \
                 if (__builtin_amdgcn_ballot_w64(r2 < r2_inner) & m) imask |= 1u << c;  \
@@ -271,7 +264,7 @@ __device__ __forceinline__ void fwd_item(
 #define NB_BLOCK(c)                                                                    \
     if ((mask >> c) & 1u)                                                              \
         pair_block<COUL, ENERGY, VIRIAL, true>(                                        \
-            xi##c, yi##c, zi##c, s_qt + kClusterSize * c + ii, NB_MASK(c), fx##c, fy##c,  \
+            s_x + kClusterSize * c + ii, s_t + kClusterSize * c + ii, NB_MASK(c), fx##c, fy##c, \
             fz##c, xj, tj, s_lj, kp, sxi, syi, szi, fjx, fjy, fjz, elj, ec, eclo, vir,    \
             npair, nblock);
             NB_FOR8(NB_BLOCK)
@@ -348,7 +341,8 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
     int n_items, int prune_i0, int prune_i1, float r2_inner, int mode,
     const int32_t* __restrict__ order, int32_t* __restrict__ queue) {
     extern __shared__ float4 s_lj[];
-    __shared__ float2 s_qt_all[kFwdWaves][kScAtoms];   // per wave: (K q_i, type_i * T)
+    __shared__ float4 s_x_all[kFwdWaves][kScAtoms];    // per wave: (x, y, z, K q) by slot
+    __shared__ int s_t_all[kFwdWaves][kScAtoms];       // per wave: type * T by slot
     const int T = kp.n_types;
     for (int i = threadIdx.x; i < T * T; i += blockDim.x) {
         const float c6 = lj[2 * i], c12 = lj[2 * i + 1];
@@ -357,9 +351,10 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x & (kWave - 1);
-    float2* s_qt = s_qt_all[wave];
+    float4* s_x = s_x_all[wave];
+    int* s_t = s_t_all[wave];
 #define NB_ITEM_ARGS                                                                    \
-    lane, s_qt, s_lj, items, entries, excl_rows, xq, type_slot, sc_info, sys, jpart, ipart, \
+    lane, s_x, s_t, s_lj, items, entries, excl_rows, xq, type_slot, sc_info, sys, jpart, ipart, \
         epart, epart_stride, kp, prune_i0, prune_i1, r2_inner
     if (mode == kExecQueue) {
         // Tickets are taken in converged code: every lane issues the atomic, lane 0 adding
@@ -427,13 +422,11 @@ __device__ inline void neumaier(float& s, float& c, float v) {
 // step), the eight k0-lanes are combined in a fixed butterfly order, and lanes 0..7 add
 // the super-cluster's i-partials and write the atom's force in the caller's order.
 constexpr int kRedWaves = 4;
-__global__ __launch_bounds__(kRedWaves * kWave) void k_reduce_f(
-    const int32_t* __restrict__ slot_atom, const int32_t* __restrict__ jseg_start,
+__device__ __forceinline__ void reduce_cluster(
+    const int cj, const int32_t* __restrict__ slot_atom, const int32_t* __restrict__ jseg_start,
     const float4* __restrict__ jpart, const int32_t* __restrict__ sc_istart,
     const int32_t* __restrict__ sc_icount, const float4* __restrict__ ipart,
-    float* __restrict__ f, int accumulate, int n_cl) {
-    const int cj = blockIdx.x * kRedWaves + (int)(threadIdx.x / kWave);
-    if (cj >= n_cl) return;
+    float* __restrict__ f, int accumulate) {
     const int lane = threadIdx.x & (kWave - 1);
     const int jj = lane & 7, k0 = lane >> 3;
     float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
@@ -523,10 +516,24 @@ __device__ void chunk_sums(const T* __restrict__ vals, int stride, int K, int p0
     }
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_energy_chunks(NbDev d) {
-    const int4 ch = d.chunks[blockIdx.x];
-    chunk_sums(d.epart, d.epart_stride, kEpartStride, ch.y, ch.z,
-               d.cpart + (size_t)blockIdx.x * kChunkVals);
+// Force reduction and the first stage of the energy reduction in one launch: blocks
+// [0, n_fblk) reduce the forces of four clusters each (one wavefront per cluster), blocks
+// [n_fblk, n_fblk + n_chunks) sum one energy chunk each.
+__global__ __launch_bounds__(kRedThreads) void k_reduce_step(NbDev d, float* __restrict__ f,
+                                                             int accumulate, int n_cl,
+                                                             int n_fblk) {
+    static_assert(kRedThreads == kRedWaves * kWave, "one block shape for both parts");
+    if ((int)blockIdx.x >= n_fblk) {
+        const int c = blockIdx.x - n_fblk;
+        const int4 ch = d.chunks[c];
+        chunk_sums(d.epart, d.epart_stride, kEpartStride, ch.y, ch.z,
+                   d.cpart + (size_t)c * kChunkVals);
+        return;
+    }
+    const int cj = blockIdx.x * kRedWaves + (int)(threadIdx.x / kWave);
+    if (cj >= n_cl) return;
+    reduce_cluster(cj, d.slot_atom, d.jseg_start, d.jpart, d.sc_istart, d.sc_icount, d.ipart, f,
+                   accumulate);
 }
 
 // One block per system: chunk partials in order, then energies, virial and pair counts.
@@ -649,21 +656,16 @@ hipError_t launch_forces(const NbDev& d, const NbKParams& kp, int coulomb, uint3
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_forces(const NbDev& d, float* f, bool accumulate, int n_slots,
-                                hipStream_t s) {
+hipError_t launch_reduce(const NbDev& d, float* f, bool accumulate, int n_slots,
+                        double* energy, double* virial, uint32_t flags, int n_sys,
+                        hipStream_t s) {
     const int n_cl = n_slots / kClusterSize;
-    if (n_cl > 0)
-        hipLaunchKernelGGL(k_reduce_f, dim3(blocks(n_cl, kRedWaves)), dim3(kRedWaves * kWave), 0,
-                           s, d.slot_atom, d.jseg_start, d.jpart, d.sc_istart, d.sc_icount,
-                           d.ipart, f, accumulate ? 1 : 0, n_cl);
-    return hipGetLastError();
-}
-
-hipError_t launch_reduce_energies(const NbDev& d, double* energy, double* virial,
-                                  uint32_t flags, int n_sys, hipStream_t s) {
-    if (d.n_chunks > 0)
-        hipLaunchKernelGGL(k_energy_chunks, dim3(d.n_chunks), dim3(kRedThreads), 0, s, d);
-    if (n_sys > 0)
+    const int n_fblk = blocks(n_cl, kRedWaves);
+    const int n_eblk = (flags & (NB_F_ENERGY | NB_F_VIRIAL)) ? d.n_chunks : 0;
+    if (n_fblk + n_eblk > 0)
+        hipLaunchKernelGGL(k_reduce_step, dim3(n_fblk + n_eblk), dim3(kRedThreads), 0, s, d, f,
+                           accumulate ? 1 : 0, n_cl, n_fblk);
+    if ((flags & (NB_F_ENERGY | NB_F_VIRIAL)) && n_sys > 0)
         hipLaunchKernelGGL(k_energy_final, dim3(n_sys), dim3(kWave), 0, s, d, energy, virial,
                            flags);
     return hipGetLastError();

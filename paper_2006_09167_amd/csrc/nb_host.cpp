@@ -635,9 +635,8 @@ nb_status forces_impl(nb_ctx* c, const float* x, const float* q, const float* lj
                                 radius_sq(c->p.rinner), c->exec_mode, c->stream));
     }
     TimedSection ts(c, NB_T_FORCE_REDUCE);
-    NB_HIP(c, launch_reduce_forces(d, f, (flags & NB_F_ACCUMULATE) != 0, c->n_slots, c->stream));
-    if (flags & (NB_F_ENERGY | NB_F_VIRIAL))
-        NB_HIP(c, launch_reduce_energies(d, energy, virial, flags, c->n_sys, c->stream));
+    NB_HIP(c, launch_reduce(d, f, (flags & NB_F_ACCUMULATE) != 0, c->n_slots, energy, virial,
+                            flags, c->n_sys, c->stream));
     return NB_OK;
 }
 }  // namespace

@@ -121,10 +121,11 @@ hipError_t launch_forces(const NbDev& d, const NbKParams& kp, int coulomb, uint3
 // Resolve once, outside any stream capture, the launch shape of the pair kernel flavor
 // for these flags (its occupancy, used by the persistent mode).
 hipError_t prepare_forces(int coulomb, uint32_t flags, bool prune, int n_types);
-hipError_t launch_reduce_forces(const NbDev& d, float* f, bool accumulate, int n_slots,
-                                hipStream_t s);
-hipError_t launch_reduce_energies(const NbDev& d, double* energy, double* virial,
-                                  uint32_t flags, int n_sys, hipStream_t s);
+// Per-atom forces (compensated sums of the partials, written in the caller's order) and,
+// with NB_F_ENERGY / NB_F_VIRIAL, the energy chunks in the same launch, then per system.
+hipError_t launch_reduce(const NbDev& d, float* f, bool accumulate, int n_slots,
+                        double* energy, double* virial, uint32_t flags, int n_sys,
+                        hipStream_t s);
 hipError_t launch_backward(const NbDev& d, const NbKParams& kp, int coulomb, const float* lj,
                            const float* grad_f, const double* grad_energy, bool ljgrad,
                            int n_slots, int n_items, hipStream_t s);
