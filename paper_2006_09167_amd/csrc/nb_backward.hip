@@ -64,20 +64,21 @@ struct BScal {
 // One 8x8 block of pairs: i-atom data and accumulators as scalars (lane = ii + 8 jj).
 template <int COUL, bool LJGRAD, bool PRIV, bool SHIFTED>
 __device__ __forceinline__ void bwd_block(
-    float xi, float yi, float zi, const float4* s_gq, const int* s_ti, uint64_t m,
+    const float4* s_x, const float4* s_gq, const int* s_ti, uint64_t m,
     float& ax, float& ay, float& az, float& aq, const float4& xj, const float4& gj, int tj,
     const float4* __restrict__ s_lj, float* __restrict__ s_hist, int lane, const NbKParams& kp,
     const BScal& bs, float sxi, float syi, float szi, float& ajx, float& ajy, float& ajz,
     float& ajq) {
+    const float4 xv = *s_x;                            // (x_i, y_i, z_i, -) of this lane
     float dx, dy, dz;
     if (SHIFTED) {
-        dx = (xi - sxi) - xj.x;
-        dy = (yi - syi) - xj.y;
-        dz = (zi - szi) - xj.z;
+        dx = (xv.x - sxi) - xj.x;
+        dy = (xv.y - syi) - xj.y;
+        dz = (xv.z - szi) - xj.z;
     } else {
-        dx = xi - xj.x;
-        dy = yi - xj.y;
-        dz = zi - xj.z;
+        dx = xv.x - xj.x;
+        dy = xv.y - xj.y;
+        dz = xv.z - xj.z;
     }
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     const uint64_t act = __builtin_amdgcn_ballot_w64(r2 < kp.rc2) & m;
@@ -163,6 +164,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
     const double* __restrict__ grad_e, float4* __restrict__ jpart, float4* __restrict__ ipart,
     float* __restrict__ glj_part, int glj_stride, NbKParams kp, int n_items) {
     extern __shared__ float4 s_dyn[];
+    __shared__ float4 s_x_all[kBwdWaves][kScAtoms];    // per wave: (x_i, y_i, z_i, q_i)
     __shared__ float4 s_gq_all[kBwdWaves][kScAtoms];   // per wave: (G_i, K q_i)
     __shared__ int s_ti_all[kBwdWaves][kScAtoms];      // per wave: type_i * T
     const int T = kp.n_types;
@@ -192,29 +194,22 @@ __global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
     bs.gec = grad_e ? (float)grad_e[2 * sysi + 1] : 0.f;
     bs.rc_m6 = kp.rc_m6;
     bs.rc_m12 = kp.rc_m12;
-    const int ibase = kScAtoms * sc + ii;
+    float4* s_x = s_x_all[wave];
     float4* s_gq = s_gq_all[wave];
     int* s_ti = s_ti_all[wave];
     {
         // lane l holds slot l of the super-cluster: (8 c + ii) for c = l >> 3
         const float4 v = xq[kScAtoms * sc + lane];
         const float4 g = gslot[kScAtoms * sc + lane];
+        s_x[lane] = v;
         s_gq[lane] = make_float4(g.x, g.y, g.z, v.w * kp.epsfac_r);
         s_ti[lane] = type_slot[kScAtoms * sc + lane] * T;
     }
     __builtin_amdgcn_wave_barrier();
 
-#define NB_ILOAD(c)                                                                    \
-    float xi##c, yi##c, zi##c;                                                         \
-    float ax##c = 0.f, ay##c = 0.f, az##c = 0.f, aq##c = 0.f;                          \
-    {                                                                                  \
-        const float4 v = xq[ibase + kClusterSize * c];                                 \
-        xi##c = v.x;                                                                   \
-        yi##c = v.y;                                                                   \
-        zi##c = v.z;                                                                   \
-    }
-    NB_FOR8(NB_ILOAD)
-#undef NB_ILOAD
+#define NB_IZERO(c) float ax##c = 0.f, ay##c = 0.f, az##c = 0.f, aq##c = 0.f;
+    NB_FOR8(NB_IZERO)
+#undef NB_IZERO
 
     const int e_end = it.e0 + it.ne;
     NbEntry nxt = entries[it.e0];
@@ -258,7 +253,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
 #define NB_BLOCK(c)                                                                    \
     if ((mask >> c) & 1u)                                                              \
         bwd_block<COUL, LJGRAD, PRIV, true>(                                           \
-            xi##c, yi##c, zi##c, s_gq + kClusterSize * c + ii, s_ti + kClusterSize * c + ii, \
+            s_x + kClusterSize * c + ii, s_gq + kClusterSize * c + ii,                  \
+            s_ti + kClusterSize * c + ii,                                                \
             NB_MASK(c), ax##c, ay##c, az##c, aq##c, xj, gj, tj, s_lj, s_hist, lane, kp, bs, \
             sxi, syi, szi, ajx, ajy, ajz, ajq);
             NB_FOR8(NB_BLOCK)
