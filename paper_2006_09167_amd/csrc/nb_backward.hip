@@ -14,10 +14,10 @@
 // i-lanes with DPP and stored once per entry, table gradients in per-lane LDS
 // histograms reduced per item.  A second pass sums the partials per atom (compensated)
 // and the table partials per type pair in double precision.
+#include "nb_chunk_sums.h"
 #include "nb_erfc_coeffs.h"
 #include "nb_internal.h"
 
-hipError_t launch_glj_chunks(const NbDev& d, int n_keys, int n_items, hipStream_t s);
 
 namespace {
 
@@ -315,13 +315,11 @@ __device__ inline void neumaier(float& s, float& c, float v) {
 // k0, k0 + 8, ... with compensation, a fixed butterfly combines the k0-lanes, and lanes
 // 0..7 add the i-partials and write dL/dx and dL/dq in the caller's atom order.
 constexpr int kRedWaves = 4;
-__global__ __launch_bounds__(kRedWaves * kWave) void k_reduce_bwd(
-    const int32_t* __restrict__ slot_atom, const int32_t* __restrict__ jseg_start,
+__device__ inline void reduce_bwd_cluster(
+    int cj, const int32_t* __restrict__ slot_atom, const int32_t* __restrict__ jseg_start,
     const float4* __restrict__ jpart, const int32_t* __restrict__ sc_istart,
     const int32_t* __restrict__ sc_icount, const float4* __restrict__ ipart,
-    float* __restrict__ gx, float* __restrict__ gq, int accumulate, int n_cl) {
-    const int cj = blockIdx.x * kRedWaves + (int)(threadIdx.x / kWave);
-    if (cj >= n_cl) return;
+    float* __restrict__ gx, float* __restrict__ gq, int accumulate) {
     const int lane = threadIdx.x & (kWave - 1);
     const int jj = lane & 7, k0 = lane >> 3;
     float s[4] = {0, 0, 0, 0}, cmp[4] = {0, 0, 0, 0};
@@ -365,6 +363,27 @@ __global__ __launch_bounds__(kRedWaves * kWave) void k_reduce_bwd(
         const float r = s[3] + cmp[3];
         gq[a] = accumulate ? gq[a] + r : r;
     }
+}
+
+// Input-gradient reduction and the first stage of the table-gradient reduction in one
+// launch: blocks [0, n_gblk) reduce four clusters each (one wavefront per cluster), blocks
+// [n_gblk, n_gblk + n_chunks) sum kChunkItems item ranks of the table-gradient partials.
+__global__ __launch_bounds__(kRedThreads) void k_reduce_bwd_step(NbDev d, float* __restrict__ gx,
+                                                                 float* __restrict__ gq,
+                                                                 int accumulate, int n_cl,
+                                                                 int n_gblk, int n_keys,
+                                                                 int n_items) {
+    static_assert(kRedThreads == kRedWaves * kWave, "one block shape for both parts");
+    if ((int)blockIdx.x >= n_gblk) {
+        const int c = blockIdx.x - n_gblk;
+        const int p0 = c * kChunkItems, p1 = min(n_items, p0 + kChunkItems);
+        chunk_sums(d.glj_part, d.epart_stride, n_keys, p0, p1, d.cpart + (size_t)c * kChunkVals);
+        return;
+    }
+    const int cj = blockIdx.x * kRedWaves + (int)(threadIdx.x / kWave);
+    if (cj >= n_cl) return;
+    reduce_bwd_cluster(cj, d.slot_atom, d.jseg_start, d.jpart, d.sc_istart, d.sc_icount,
+                       d.ipart, gx, gq, accumulate);
 }
 
 // Table gradient, stage 2: one thread per (type pair, c6/c12) adds the chunk partials in
@@ -428,16 +447,14 @@ hipError_t launch_reduce_backward(const NbDev& d, float* grad_x, float* grad_q, 
                                   bool accumulate, int n_slots, int n_types, int n_items,
                                   hipStream_t s) {
     const int n_cl = n_slots / kClusterSize;
-    if (n_cl > 0 && (grad_x || grad_q))
-        hipLaunchKernelGGL(k_reduce_bwd, dim3(blocks(n_cl, kRedWaves)), dim3(kRedWaves * kWave),
-                           0, s, d.slot_atom, d.jseg_start, d.jpart, d.sc_istart, d.sc_icount,
-                           d.ipart, grad_x, grad_q, accumulate ? 1 : 0, n_cl);
-    if (grad_lj) {
-        const int nk = 2 * n_types * n_types;
-        hipError_t e = launch_glj_chunks(d, nk, n_items, s);
-        if (e != hipSuccess) return e;
+    const int n_gblk = (grad_x || grad_q) ? blocks(n_cl, kRedWaves) : 0;
+    const int nk = 2 * n_types * n_types;
+    const int n_chunks = grad_lj ? blocks(n_items, kChunkItems) : 0;
+    if (n_gblk + n_chunks > 0)
+        hipLaunchKernelGGL(k_reduce_bwd_step, dim3(n_gblk + n_chunks), dim3(kRedThreads), 0, s,
+                           d, grad_x, grad_q, accumulate ? 1 : 0, n_cl, n_gblk, nk, n_items);
+    if (grad_lj)
         hipLaunchKernelGGL(k_glj_final, dim3(blocks(nk, 64)), dim3(64), 0, s, d, grad_lj,
-                           n_types, blocks(n_items, kChunkItems), accumulate ? 1 : 0);
-    }
+                           n_types, n_chunks, accumulate ? 1 : 0);
     return hipGetLastError();
 }

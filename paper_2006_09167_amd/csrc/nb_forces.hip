@@ -16,6 +16,7 @@
 // single-precision sums, and writes the force in the caller's atom order.
 #include <algorithm>
 
+#include "nb_chunk_sums.h"
 #include "nb_erfc_coeffs.h"
 #include "nb_internal.h"
 
@@ -474,47 +475,6 @@ __device__ __forceinline__ void reduce_cluster(
 // Zero forces of atoms that no slot covers (only possible for an empty grid) is not
 // needed: every atom has a slot after a grid build.
 
-constexpr int kRedThreads = 256;
-
-// Deterministic two-stage reductions of per-item partial sums (structure of arrays, K
-// values, one column per item rank).  Stage 1: one block per chunk of up to kChunkItems
-// consecutive ranks of one segment sums each value (fixed butterfly and wave order) into
-// the chunk partial.  Stage 2: one block per segment adds its chunks in order.
-template <typename T>
-__device__ void chunk_sums(const T* __restrict__ vals, int stride, int K, int p0, int p1,
-                           double* __restrict__ out) {
-    constexpr int kG = 16;                 // values summed per pass (loads issued together)
-    __shared__ double s_w[kRedThreads / kWave][kG];
-    const int wv = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-    for (int k0 = 0; k0 < K; k0 += kG) {
-        const int g = min(kG, K - k0);
-        double acc[kG];
-#pragma unroll
-        for (int q = 0; q < kG; ++q) acc[q] = 0.0;
-        // Rows past the last value re-read row g-1 (in bounds, never written out), so
-        // every load of a pass is unconditional and all of them are in flight together.
-#pragma unroll 2
-        for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
-            T v[kG];
-#pragma unroll
-            for (int q = 0; q < kG; ++q) v[q] = vals[(size_t)(k0 + min(q, g - 1)) * stride + i];
-#pragma unroll
-            for (int q = 0; q < kG; ++q) acc[q] += (double)v[q];
-        }
-#pragma unroll
-        for (int q = 0; q < kG; ++q) {
-            for (int off = 1; off < kWave; off <<= 1) acc[q] += __shfl_xor(acc[q], off);
-            if (lane == 0) s_w[wv][q] = acc[q];
-        }
-        __syncthreads();
-        if (threadIdx.x < g) {
-            double t = 0.0;
-            for (int w = 0; w < kRedThreads / kWave; ++w) t += s_w[w][threadIdx.x];
-            out[k0 + threadIdx.x] = t;
-        }
-        __syncthreads();
-    }
-}
 
 // Force reduction and the first stage of the energy reduction in one launch: blocks
 // [0, n_fblk) reduce the forces of four clusters each (one wavefront per cluster), blocks
@@ -671,19 +631,3 @@ hipError_t launch_reduce(const NbDev& d, float* f, bool accumulate, int n_slots,
     return hipGetLastError();
 }
 
-template <typename T>
-__global__ __launch_bounds__(kRedThreads) void k_value_chunks(const T* __restrict__ vals,
-                                                              int stride, int K, int n,
-                                                              double* __restrict__ cpart) {
-    const int p0 = blockIdx.x * kChunkItems, p1 = min(n, p0 + kChunkItems);
-    chunk_sums(vals, stride, K, p0, p1, cpart + (size_t)blockIdx.x * kChunkVals);
-}
-
-// Stage 1 for the table gradient partials (float, one segment of n item ranks).
-hipError_t launch_glj_chunks(const NbDev& d, int n_keys, int n_items, hipStream_t s) {
-    const int nc = blocks(n_items, kChunkItems);
-    if (nc > 0)
-        hipLaunchKernelGGL((k_value_chunks<float>), dim3(nc), dim3(kRedThreads), 0, s,
-                           d.glj_part, d.epart_stride, n_keys, n_items, d.cpart);
-    return hipGetLastError();
-}

@@ -326,11 +326,12 @@ __global__ __launch_bounds__(kWave) void k_jseg_rank(NbDev d) {
 }
 
 constexpr int kPruneWaves = 4;
+constexpr int kPruneSplit = 2;          // wavefronts per item (alternate entries)
 #define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
-// Rolling prune (Sec. V.E) of a range of work items: one wavefront per item, the item's
-// eight i-clusters loaded once, entries processed in order with the next two entries'
-// j-clusters in flight.  For every i-cluster of the outer mask the inner bit is set iff
+// Rolling prune (Sec. V.E) of a range of work items: two wavefronts per item taking
+// alternate entries, the item's eight i-clusters loaded once per wavefront, entries
+// processed in order with the next two entries' j-clusters in flight.  For every i-cluster of the outer mask the inner bit is set iff
 // some atom pair is closer than r_inner in the list arithmetic (shift split between the
 // two sides, no contraction).  Empty slots sit far outside the box, so no valid-atom masks
 // are needed; a cluster with itself keeps ii < jj.
@@ -341,7 +342,8 @@ __global__ __launch_bounds__(kPruneWaves * kWave) void k_prune(
 #pragma clang fp contract(off)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x & (kWave - 1);
-    const int k = blockIdx.x * kPruneWaves + wave;
+    const int kw = blockIdx.x * kPruneWaves + wave;
+    const int k = kw / kPruneSplit, part = kw % kPruneSplit;
     if (k >= n_items) return;
     const NbItem it = items[item0 + k];
     const int ii = lane & 7, jj = lane >> 3;
@@ -351,22 +353,25 @@ __global__ __launch_bounds__(kPruneWaves * kWave) void k_prune(
     NB_FOR8(NB_PI)
 #undef NB_PI
     const int e_end = it.e0 + it.ne;
+    const int e_first = it.e0 + part;
+    if (e_first >= e_end) return;
+    constexpr int kStep = kPruneSplit;
     // two entries ahead: (ent1, xj1) is the next one, (ent2, xj2) the one after
-    NbEntry ent1 = entries[it.e0];
+    NbEntry ent1 = entries[e_first];
     float4 xj1 = xp[kClusterSize * ent1.cj + jj];
     NbEntry ent2 = ent1;
     float4 xj2 = xj1;
-    if (it.e0 + 1 < e_end) {
-        ent2 = entries[it.e0 + 1];
+    if (e_first + kStep < e_end) {
+        ent2 = entries[e_first + kStep];
         xj2 = xp[kClusterSize * ent2.cj + jj];
     }
-    for (int e = it.e0; e < e_end; ++e) {
+    for (int e = e_first; e < e_end; e += kStep) {
         const NbEntry ent = ent1;
         float4 xj = xj1;
         ent1 = ent2;
         xj1 = xj2;
-        if (e + 2 < e_end) {
-            ent2 = entries[e + 2];
+        if (e + 2 * kStep < e_end) {
+            ent2 = entries[e + 2 * kStep];
             xj2 = xp[kClusterSize * ent2.cj + jj];
         }
         const int code = ent.meta & 31u;
@@ -485,7 +490,8 @@ hipError_t launch_list_finish(const NbDev& d, int n_sc, int64_t n_entries, int n
 hipError_t launch_prune(const NbDev& d, const float4* coords, int item0, int n_items,
                         float r2_inner, hipStream_t s) {
     if (n_items > 0)
-        hipLaunchKernelGGL(k_prune, dim3(blocks(n_items, kPruneWaves)), dim3(kPruneWaves * kWave),
+        hipLaunchKernelGGL(k_prune, dim3(blocks((int64_t)n_items * kPruneSplit, kPruneWaves)),
+                           dim3(kPruneWaves * kWave),
                            0, s, d.items, d.entries, coords, d.sc_info, d.sys, item0, n_items,
                            r2_inner);
     return hipGetLastError();
