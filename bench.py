@@ -171,7 +171,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: workload's)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="water96k_ewald", choices=sorted(WORKLOADS))
-    ap.add_argument("--exec", default="auto", choices=["auto", "static", "xcd", "queue"],
+    ap.add_argument("--exec", default="auto", choices=["auto", "static", "xcd", "queue", "persist"],
                     help="pair kernel execution shape (auto = autotuner at the first build)")
     ap.add_argument("--item-width", type=int, default=0,
                     help="entries per work item with a fixed --exec mode (0 = built-in rule)")

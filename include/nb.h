@@ -210,11 +210,15 @@ nb_status nb_step_graph(nb_ctx* ctx, const float* x, const float* q, const float
  *   NB_EXEC_XCD     the same, blocks renumbered so that each of the 8 XCDs (each with its
  *                   own L2) processes one contiguous range of neighbouring items;
  *   NB_EXEC_QUEUE   persistent: one resident grid takes items from an atomic queue,
- *                   most pair work first (long lists not scheduled late, Sec. V.F).
+ *                   most pair work first (long lists not scheduled late, Sec. V.F);
+ *   NB_EXEC_PERSIST persistent: one resident grid, items taken in rounds in the same
+ *                   most-work-first order, wavefront g taking position g of even rounds
+ *                   and position G-1-g of odd rounds (G wavefronts), so the per-wavefront
+ *                   totals even out without any atomic.
  * Results do not depend on exec_mode (each item writes its own partial sums); they
  * depend on item_width only through the order of the final per-atom sums (a few ulp).
  */
-enum { NB_EXEC_STATIC = 0, NB_EXEC_XCD = 1, NB_EXEC_QUEUE = 2 };
+enum { NB_EXEC_STATIC = 0, NB_EXEC_XCD = 1, NB_EXEC_QUEUE = 2, NB_EXEC_PERSIST = 3 };
 typedef struct {
     int32_t item_width;   /* entries per work item, 1..64 */
     int32_t exec_mode;    /* NB_EXEC_* */
@@ -233,10 +237,10 @@ nb_status nb_get_exec(nb_ctx* ctx, nb_exec_config* out);
 /*
  * [sync] Autotuner (the paper calls for dynamic auto-tuning of code flavors, Sec. VII):
  * times nb_forces(x, q, lj, flags) on the current list for item widths 8, 16, 24, 32,
- * 48, 64 and the three execution modes (repeats timed calls after one warm-up each,
+ * 48, 64 and the four execution modes (repeats timed calls after one warm-up each,
  * HIP events, median), then, in the fastest shape, a rolling step (nb_step of part 1,
  * which re-prunes that part with x) with the prune fused and separate; writes up to cap
- * trials to host trials[] and their number (20) to *n_trials, and keeps the fastest
+ * trials to host trials[] and their number (26) to *n_trials, and keeps the fastest
  * choices (also returned in *best) for this and later builds.
  * flags: NB_F_ENERGY and/or NB_F_VIRIAL.  Allocates and frees its own output buffers.
  * Errors: NB_ERR_STATE without a list, NB_ERR_ARG.

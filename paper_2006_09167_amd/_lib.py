@@ -17,8 +17,9 @@ EXPORTS = ["nb_create", "nb_destroy", "nb_set_topology", "nb_grid_build", "nb_pa
            "nb_get_grid_dims", "nb_get_pairs", "nb_get_stats", "nb_set_timing", "nb_get_timing",
            "nb_strerror", "nb_last_error", "nb_step_graph", "nb_set_exec", "nb_get_exec",
            "nb_autotune"]
-NB_EXEC_STATIC, NB_EXEC_XCD, NB_EXEC_QUEUE = 0, 1, 2
-EXEC_MODES = {"static": NB_EXEC_STATIC, "xcd": NB_EXEC_XCD, "queue": NB_EXEC_QUEUE}
+NB_EXEC_STATIC, NB_EXEC_XCD, NB_EXEC_QUEUE, NB_EXEC_PERSIST = 0, 1, 2, 3
+EXEC_MODES = {"static": NB_EXEC_STATIC, "xcd": NB_EXEC_XCD, "queue": NB_EXEC_QUEUE,
+              "persist": NB_EXEC_PERSIST}
 NB_T_FORCES, NB_T_FORCE_REDUCE, NB_T_PRUNE, NB_T_BACKWARD, NB_T_BACKWARD_REDUCE, NB_T_COUNT = range(6)
 TIMING_KINDS = ["forces", "force_reduce", "prune", "backward", "backward_reduce"]
 

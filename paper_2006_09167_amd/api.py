@@ -174,7 +174,7 @@ class Context:
         return f, (e if energy else None), (vir if virial else None)
 
     def set_exec(self, item_width: int = 0, mode: str = "static", prune_fused: bool = True):
-        """Item width (0 = built-in rule), execution mode ('static', 'xcd', 'queue') and
+        """Item width (0 = built-in rule), execution mode ('static', 'xcd', 'queue', 'persist') and
         whether step() prunes inside the pair kernel or with separate kernels."""
         self._check(self.lib.nb_set_exec(self.h, int(item_width), EXEC_MODES[mode],
                                          1 if prune_fused else 0), "nb_set_exec")

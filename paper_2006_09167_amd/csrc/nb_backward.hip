@@ -14,9 +14,11 @@
 // i-lanes with DPP and stored once per entry, table gradients in per-lane LDS
 // histograms reduced per item.  A second pass sums the partials per atom (compensated)
 // and the table partials per type pair in double precision.
+#include <algorithm>
+
 #include "nb_chunk_sums.h"
-#include "nb_erfc_coeffs.h"
 #include "nb_internal.h"
+#include "nb_pair_common.h"
 
 
 namespace {
@@ -25,76 +27,41 @@ constexpr int kBwdWaves = 2;
 constexpr int kBwdThreads = kBwdWaves * kWave;
 constexpr int kPrivateHistTypes = 4;   // per-lane histograms up to this many types
 
-// Sum over the 8 consecutive lanes ii = 0..7 of a j-atom (row half), complete in every
-// lane of it: swap neighbours, swap pairs, then add the mirrored half row.
-constexpr int kJSumLane = 0;
-__device__ inline float dpp_sum8(float v) {
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                               0xB1, 0xF, 0xF, false));
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                               0x4E, 0xF, 0xF, false));
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                               0x141, 0xF, 0xF, false));
-    return v;
-}
-
-__device__ inline int shift_x(int code) { return code / 9 - 1; }
-__device__ inline int shift_y(int code) { return (code / 3) % 3 - 1; }
-__device__ inline int shift_z(int code) { return code % 3 - 1; }
-
-__device__ inline float erfcx_poly(float t) {
-    const float u = __builtin_amdgcn_rcpf(fmaf(NB_ERFC_P, t, 1.0f));
-    float p = NB_ERFC_C8;
-    p = fmaf(p, u, NB_ERFC_C7);
-    p = fmaf(p, u, NB_ERFC_C6);
-    p = fmaf(p, u, NB_ERFC_C5);
-    p = fmaf(p, u, NB_ERFC_C4);
-    p = fmaf(p, u, NB_ERFC_C3);
-    p = fmaf(p, u, NB_ERFC_C2);
-    p = fmaf(p, u, NB_ERFC_C1);
-    p = fmaf(p, u, NB_ERFC_C0);
-    return u * p;
-}
-
 struct BScal {
     float gel, gec;                // dL/dE_LJ, dL/dE_C of the item's system
     float rc_m6, rc_m12;
 };
 
 // One 8x8 block of pairs: i-atom data and accumulators as scalars (lane = ii + 8 jj).
-template <int COUL, bool LJGRAD, bool PRIV, bool SHIFTED>
+// xj is the lane's j-atom with the entry's periodic shift already added, lj_j the LDS
+// address of row 0 of the LJ table plus 16 bytes times the j-atom's type, tj16 that
+// offset alone (s_ti holds 16 T type_i per slot).
+template <int COUL, bool LJGRAD, bool PRIV>
 __device__ __forceinline__ void bwd_block(
     const float4* s_x, const float4* s_gq, const int* s_ti, uint64_t m,
-    float& ax, float& ay, float& az, float& aq, const float4& xj, const float4& gj, int tj,
-    const float4* __restrict__ s_lj, float* __restrict__ s_hist, int lane, const NbKParams& kp,
-    const BScal& bs, float sxi, float syi, float szi, float& ajx, float& ajy, float& ajz,
-    float& ajq) {
+    float& ax, float& ay, float& az, float& aq, const float4& xj, const float4& gj, int tj16,
+    const char* lj_j, float* __restrict__ s_hist, int lane, const NbKParams& kp,
+    const BScal& bs, float& ajx, float& ajy, float& ajz, float& ajq) {
     const float4 xv = *s_x;                            // (x_i, y_i, z_i, -) of this lane
-    float dx, dy, dz;
-    if (SHIFTED) {
-        dx = (xv.x - sxi) - xj.x;
-        dy = (xv.y - syi) - xj.y;
-        dz = (xv.z - szi) - xj.z;
-    } else {
-        dx = xv.x - xj.x;
-        dy = xv.y - xj.y;
-        dz = xv.z - xj.z;
-    }
+    const float dx = xv.x - xj.x, dy = xv.y - xj.y, dz = xv.z - xj.z;
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     const uint64_t act = __builtin_amdgcn_ballot_w64(r2 < kp.rc2) & m;
     if (!act) return;
     const bool on = __builtin_amdgcn_inverse_ballot_w64(act);
     const float4 gq = *s_gq;                           // (G_i, K q_i) of this lane's i-atom
     const float gxi = gq.x, gyi = gq.y, gzi = gq.z, qi = gq.w;
-    const int ti = *s_ti;                              // type_i * T
-    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const int ti16 = *s_ti;
+    const float4 p = *reinterpret_cast<const float4*>(lj_j + ti16);   // (6 c6, 12 c12, shift, c6)
+    // Pairs outside the cut-off or excluded get 1/r = 0 and q_i q_j = 0: the force terms
+    // and their derivatives below vanish (r2 stays finite); the energy-derivative terms
+    // w, g6, g12 are masked explicitly.
+    const float rinv = on ? __builtin_amdgcn_rsqf(r2) : 0.f;
     const float rinv2 = rinv * rinv;
-    const float4 p = s_lj[ti + tj];                    // (6 c6, 12 c12, shift, c6)
     const float rinv6 = rinv2 * rinv2 * rinv2;
     const float a = p.y * rinv6;                       // 12 c12 r^-6
     const float phi_lj = rinv6 * (a - p.x) * rinv2;
     const float dphi_lj = rinv6 * rinv2 * rinv2 * fmaf(-14.0f, a, 8.0f * p.x);
-    const float qq = qi * xj.w;
+    const float qq = on ? qi * xj.w : 0.f;
     float psi, dpsi, v;
     if (COUL == NB_COUL_RF) {
         psi = rinv * rinv2 - 2.0f * kp.krf;
@@ -103,7 +70,7 @@ __device__ __forceinline__ void bwd_block(
     } else {
         const float r = r2 * rinv;
         const float e = __builtin_amdgcn_exp2f(r2 * kp.beta2_log2e);
-        const float erfcv = e * erfcx_poly(kp.beta * r);
+        const float erfcv = e * erfcx_poly(r, kp.p_beta);
         const float te = kp.two_beta_sqrtpi * e;
         const float g = fmaf(erfcv, rinv, te);
         psi = g * rinv2;
@@ -115,14 +82,10 @@ __device__ __forceinline__ void bwd_block(
     const float u = fmaf(gdx, dx, fmaf(gdy, dy, gdz * dz));
     const float phi = phi_lj + phi_c;
     const float coef = fmaf(dphi_lj + qq * dpsi, u, -fmaf(bs.gel, phi_lj, bs.gec * phi_c));
-    float hx = fmaf(coef, dx, phi * gdx);
-    float hy = fmaf(coef, dy, phi * gdy);
-    float hz = fmaf(coef, dz, phi * gdz);
-    float w = fmaf(psi, u, bs.gec * v);
-    hx = on ? hx : 0.f;
-    hy = on ? hy : 0.f;
-    hz = on ? hz : 0.f;
-    w = on ? w : 0.f;
+    const float hx = fmaf(coef, dx, phi * gdx);
+    const float hy = fmaf(coef, dy, phi * gdy);
+    const float hz = fmaf(coef, dz, phi * gdz);
+    const float w = on ? fmaf(psi, u, bs.gec * v) : 0.f;
     ax += hx;
     ay += hy;
     az += hz;
@@ -137,53 +100,40 @@ __device__ __forceinline__ void bwd_block(
         float g6 = fmaf(u * -6.0f * rinv2, rinv6, bs.gel * (bs.rc_m6 - rinv6));
         g12 = on ? g12 : 0.f;
         g6 = on ? g6 : 0.f;
-        const int key = ti + tj;
+        const int key16 = ti16 + tj16;                // 16 (type_i T + type_j)
         if (PRIV) {
             // lane-private slots: plain read-modify-write (no LDS atomics needed)
-            float2* h = reinterpret_cast<float2*>(s_hist) + key * kWave + lane;
+            float2* h = reinterpret_cast<float2*>(reinterpret_cast<char*>(s_hist) +
+                                                  key16 * (int)(kWave * sizeof(float2) / 16)) +
+                        lane;
             float2 hv = *h;
             hv.x += g6;
             hv.y += g12;
             *h = hv;
         } else {
-            atomicAdd(&s_hist[2 * key], g6);
-            atomicAdd(&s_hist[2 * key + 1], g12);
+            atomicAdd(&s_hist[key16 >> 3], g6);
+            atomicAdd(&s_hist[(key16 >> 3) + 1], g12);
         }
     }
 }
 
 #define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
+// The work of one item (one wavefront): s_x, s_gq, s_ti the wavefront's LDS tables of the
+// super-cluster's atoms, s_hist its table-gradient histogram (zero on entry, zero again
+// on return).
 template <int COUL, bool LJGRAD, bool PRIV>
-__global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
+__device__ __forceinline__ void bwd_item(
+    const int item, const int lane, float4* s_x, float4* s_gq, int* s_ti,
+    const float4* __restrict__ s_lj, float* __restrict__ s_hist,
     const NbItem* __restrict__ items, const NbEntry* __restrict__ entries,
     const uint64_t* __restrict__ excl_rows, const float4* __restrict__ xq,
     const float4* __restrict__ gslot, const int32_t* __restrict__ type_slot,
-    const NbScInfo* __restrict__ sc_info,
-    const NbSys* __restrict__ sys, const float* __restrict__ lj,
+    const NbScInfo* __restrict__ sc_info, const NbSys* __restrict__ sys,
     const double* __restrict__ grad_e, float4* __restrict__ jpart, float4* __restrict__ ipart,
-    float* __restrict__ glj_part, int glj_stride, NbKParams kp, int n_items) {
-    extern __shared__ float4 s_dyn[];
-    __shared__ float4 s_x_all[kBwdWaves][kScAtoms];    // per wave: (x_i, y_i, z_i, q_i)
-    __shared__ float4 s_gq_all[kBwdWaves][kScAtoms];   // per wave: (G_i, K q_i)
-    __shared__ int s_ti_all[kBwdWaves][kScAtoms];      // per wave: type_i * T
+    float* __restrict__ glj_part, int glj_stride, const NbKParams& kp) {
     const int T = kp.n_types;
     const int TT = T * T;
-    float4* s_lj = s_dyn;
-    float* s_hist_all = reinterpret_cast<float*>(s_dyn + TT);
-    const int hist_per_wave = PRIV ? 2 * TT * kWave : 2 * TT;
-    for (int i = threadIdx.x; i < TT; i += blockDim.x) {
-        const float c6 = lj[2 * i], c12 = lj[2 * i + 1];
-        s_lj[i] = make_float4(6.0f * c6, 12.0f * c12, c12 * kp.rc_m12 - c6 * kp.rc_m6, c6);
-    }
-    if (LJGRAD)
-        for (int i = threadIdx.x; i < hist_per_wave * kBwdWaves; i += blockDim.x) s_hist_all[i] = 0.f;
-    __syncthreads();
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int lane = threadIdx.x & (kWave - 1);
-    const int item = blockIdx.x * kBwdWaves + wave;
-    if (item >= n_items) return;
-    float* s_hist = s_hist_all + wave * hist_per_wave;
     const NbItem it = items[item];
     const int ii = lane & 7, jj = lane >> 3;
     const int sc = it.sc, ci0 = kClustersPerSc * sc;
@@ -194,16 +144,13 @@ __global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
     bs.gec = grad_e ? (float)grad_e[2 * sysi + 1] : 0.f;
     bs.rc_m6 = kp.rc_m6;
     bs.rc_m12 = kp.rc_m12;
-    float4* s_x = s_x_all[wave];
-    float4* s_gq = s_gq_all[wave];
-    int* s_ti = s_ti_all[wave];
     {
         // lane l holds slot l of the super-cluster: (8 c + ii) for c = l >> 3
         const float4 v = xq[kScAtoms * sc + lane];
         const float4 g = gslot[kScAtoms * sc + lane];
         s_x[lane] = v;
         s_gq[lane] = make_float4(g.x, g.y, g.z, v.w * kp.epsfac_r);
-        s_ti[lane] = type_slot[kScAtoms * sc + lane] * T;
+        s_ti[lane] = type_slot[kScAtoms * sc + lane] * T * (int)sizeof(float4);
     }
     __builtin_amdgcn_wave_barrier();
 
@@ -242,21 +189,21 @@ __global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
         // and, for a cluster with itself, ii < jj are masked
 #define NB_MASK(c)                                                                     \
     ((xrow ? xrow[c] : ~0ull) & ((self && dc == c) ? 0x7f3f1f0f07030100ull : ~0ull))
-        // Exact periodic shift, one code path for every entry (x - 0 is exact).
+        // Periodic image of the j-cluster: x_j + s L, added once per entry.
         {
             const int sx = shift_x(code), sy = shift_y(code), sz = shift_z(code);
-            xj.x -= (sx < 0) ? S.L[0] : 0.f;
-            xj.y -= (sy < 0) ? S.L[1] : 0.f;
-            xj.z -= (sz < 0) ? S.L[2] : 0.f;
-            const float sxi = sx > 0 ? S.L[0] : 0.f, syi = sy > 0 ? S.L[1] : 0.f,
-                        szi = sz > 0 ? S.L[2] : 0.f;
+            xj.x += shift_value(sx, S.L[0]);
+            xj.y += shift_value(sy, S.L[1]);
+            xj.z += shift_value(sz, S.L[2]);
+            const int tj16 = tj * (int)sizeof(float4);
+            const char* lj_j = reinterpret_cast<const char*>(s_lj) + tj16;
 #define NB_BLOCK(c)                                                                    \
     if ((mask >> c) & 1u)                                                              \
-        bwd_block<COUL, LJGRAD, PRIV, true>(                                           \
+        bwd_block<COUL, LJGRAD, PRIV>(                                                 \
             s_x + kClusterSize * c + ii, s_gq + kClusterSize * c + ii,                  \
             s_ti + kClusterSize * c + ii,                                                \
-            NB_MASK(c), ax##c, ay##c, az##c, aq##c, xj, gj, tj, s_lj, s_hist, lane, kp, bs, \
-            sxi, syi, szi, ajx, ajy, ajz, ajq);
+            NB_MASK(c), ax##c, ay##c, az##c, aq##c, xj, gj, tj16, lj_j, s_hist, lane, kp, bs, \
+            ajx, ajy, ajz, ajq);
             NB_FOR8(NB_BLOCK)
 #undef NB_BLOCK
         }
@@ -293,7 +240,61 @@ __global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
             }
             glj_part[(size_t)k * glj_stride + it.pos] = v;
         }
+        // Cleared for the wavefront's next item.  The LDS operations of one wavefront
+        // complete in order, so these writes follow every read above.
+        const int hist_per_wave = PRIV ? 2 * TT * kWave : 2 * TT;
+        for (int k = lane; k < hist_per_wave; k += kWave) s_hist[k] = 0.f;
+        __builtin_amdgcn_wave_barrier();
     }
+}
+
+// Execution: one wavefront per item in item order, or (kExecPersist) a grid resident on
+// the device once, taking items in rounds of the most-work-first order as the forward
+// kernel's persistent mode does.
+template <int COUL, bool LJGRAD, bool PRIV>
+__global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
+    const NbItem* __restrict__ items, const NbEntry* __restrict__ entries,
+    const uint64_t* __restrict__ excl_rows, const float4* __restrict__ xq,
+    const float4* __restrict__ gslot, const int32_t* __restrict__ type_slot,
+    const NbScInfo* __restrict__ sc_info,
+    const NbSys* __restrict__ sys, const float* __restrict__ lj,
+    const double* __restrict__ grad_e, float4* __restrict__ jpart, float4* __restrict__ ipart,
+    float* __restrict__ glj_part, int glj_stride, NbKParams kp, int n_items, int mode,
+    const int32_t* __restrict__ order) {
+    extern __shared__ float4 s_dyn[];
+    __shared__ float4 s_x_all[kBwdWaves][kScAtoms];    // per wave: (x_i, y_i, z_i, q_i)
+    __shared__ float4 s_gq_all[kBwdWaves][kScAtoms];   // per wave: (G_i, K q_i)
+    __shared__ int s_ti_all[kBwdWaves][kScAtoms];      // per wave: 16 T type_i
+    const int T = kp.n_types;
+    const int TT = T * T;
+    float4* s_lj = s_dyn;
+    float* s_hist_all = reinterpret_cast<float*>(s_dyn + TT);
+    const int hist_per_wave = PRIV ? 2 * TT * kWave : 2 * TT;
+    for (int i = threadIdx.x; i < TT; i += blockDim.x) {
+        const float c6 = lj[2 * i], c12 = lj[2 * i + 1];
+        s_lj[i] = make_float4(6.0f * c6, 12.0f * c12, c12 * kp.rc_m12 - c6 * kp.rc_m6, c6);
+    }
+    if (LJGRAD)
+        for (int i = threadIdx.x; i < hist_per_wave * kBwdWaves; i += blockDim.x) s_hist_all[i] = 0.f;
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x & (kWave - 1);
+#define NB_ITEM_ARGS                                                                    \
+    lane, s_x_all[wave], s_gq_all[wave], s_ti_all[wave], s_lj,                           \
+        s_hist_all + wave * hist_per_wave, items, entries, excl_rows, xq, gslot, type_slot, \
+        sc_info, sys, grad_e, jpart, ipart, glj_part, glj_stride, kp
+    if (mode == kExecPersist) {
+        const int G = (int)gridDim.x * kBwdWaves;
+        const int g = (int)blockIdx.x * kBwdWaves + wave;
+        for (int base = 0, odd = 0; base < n_items; base += G, odd ^= 1) {
+            const int slot = base + (odd ? G - 1 - g : g);
+            if (slot < n_items) bwd_item<COUL, LJGRAD, PRIV>(order[slot], NB_ITEM_ARGS);
+        }
+        return;
+    }
+    const int item = blockIdx.x * kBwdWaves + wave;
+    if (item < n_items) bwd_item<COUL, LJGRAD, PRIV>(item, NB_ITEM_ARGS);
+#undef NB_ITEM_ARGS
 }
 
 // Slot-order adjoint G from the caller's per-atom dL/dF.
@@ -408,37 +409,61 @@ __global__ void k_glj_final(NbDev d, double* __restrict__ out, int n_types, int 
 
 inline int blocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
+template <int COUL, bool LJGRAD, bool PRIV>
+int bwd_blocks_per_cu(size_t lds) {
+    // resident blocks per CU of this kernel flavour for the last LDS size asked
+    static int per_cu = 0;
+    static size_t per_cu_lds = 0;
+    if (per_cu == 0 || per_cu_lds != lds) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_nb_bwd<COUL, LJGRAD, PRIV>,
+                                                         kBwdThreads, lds) != hipSuccess)
+            nb = 0;
+        per_cu = nb > 0 ? nb : 1;
+        per_cu_lds = lds;
+    }
+    return per_cu;
+}
+
 template <int COUL, bool LJG, bool PRIV>
 void launch_bwd_t(const NbDev& d, const NbKParams& kp, const float* lj, const double* ge,
-                  int n_items, hipStream_t s) {
+                  int n_items, int mode, hipStream_t s) {
     const int TT = kp.n_types * kp.n_types;
     const size_t hist = LJG ? (size_t)(PRIV ? 2 * TT * kWave : 2 * TT) * kBwdWaves : 0;
     const size_t lds = sizeof(float4) * TT + sizeof(float) * hist;
-    hipLaunchKernelGGL((k_nb_bwd<COUL, LJG, PRIV>), dim3(blocks(n_items, kBwdWaves)),
-                       dim3(kBwdThreads), lds, s, d.items, d.entries, d.excl_rows, d.xq, d.gslot,
-                       d.type_slot, d.sc_info, d.sys, lj, ge, d.jpart, d.ipart,
-                       d.glj_part, d.epart_stride, kp, n_items);
+    // the persistent schedule when the context runs the forward pass that way, else
+    // one wavefront per item
+    const int bmode = (mode == kExecPersist) ? kExecPersist : kExecStatic;
+    int grid = blocks(n_items, kBwdWaves);
+    if (bmode == kExecPersist)
+        grid = std::min(grid, bwd_blocks_per_cu<COUL, LJG, PRIV>(lds) * std::max(d.n_cu, 1));
+    hipLaunchKernelGGL((k_nb_bwd<COUL, LJG, PRIV>), dim3(grid), dim3(kBwdThreads), lds, s,
+                       d.items, d.entries, d.excl_rows, d.xq, d.gslot, d.type_slot, d.sc_info,
+                       d.sys, lj, ge, d.jpart, d.ipart, d.glj_part, d.epart_stride, kp, n_items,
+                       bmode, d.item_order);
 }
 
 template <int COUL>
 void launch_bwd_c(const NbDev& d, const NbKParams& kp, const float* lj, const double* ge,
-                  bool ljgrad, int n_items, hipStream_t s) {
-    if (!ljgrad) launch_bwd_t<COUL, false, false>(d, kp, lj, ge, n_items, s);
-    else if (kp.n_types <= kPrivateHistTypes) launch_bwd_t<COUL, true, true>(d, kp, lj, ge, n_items, s);
-    else launch_bwd_t<COUL, true, false>(d, kp, lj, ge, n_items, s);
+                  bool ljgrad, int n_items, int mode, hipStream_t s) {
+    if (!ljgrad) launch_bwd_t<COUL, false, false>(d, kp, lj, ge, n_items, mode, s);
+    else if (kp.n_types <= kPrivateHistTypes) launch_bwd_t<COUL, true, true>(d, kp, lj, ge, n_items, mode, s);
+    else launch_bwd_t<COUL, true, false>(d, kp, lj, ge, n_items, mode, s);
 }
 
 }  // namespace
 
 hipError_t launch_backward(const NbDev& d, const NbKParams& kp, int coulomb, const float* lj,
                            const float* grad_f, const double* grad_energy, bool ljgrad,
-                           int n_slots, int n_items, hipStream_t s) {
+                           int n_slots, int n_items, int mode, hipStream_t s) {
     if (n_slots > 0)
         hipLaunchKernelGGL(k_gather_g, dim3(blocks(n_slots, 256)), dim3(256), 0, s, d, grad_f,
                            n_slots);
     if (n_items > 0) {
-        if (coulomb == NB_COUL_RF) launch_bwd_c<NB_COUL_RF>(d, kp, lj, grad_energy, ljgrad, n_items, s);
-        else launch_bwd_c<NB_COUL_EWALD>(d, kp, lj, grad_energy, ljgrad, n_items, s);
+        if (coulomb == NB_COUL_RF)
+            launch_bwd_c<NB_COUL_RF>(d, kp, lj, grad_energy, ljgrad, n_items, mode, s);
+        else
+            launch_bwd_c<NB_COUL_EWALD>(d, kp, lj, grad_energy, ljgrad, n_items, mode, s);
     }
     return hipGetLastError();
 }

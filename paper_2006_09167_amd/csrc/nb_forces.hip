@@ -17,108 +17,61 @@
 #include <algorithm>
 
 #include "nb_chunk_sums.h"
-#include "nb_erfc_coeffs.h"
 #include "nb_internal.h"
+#include "nb_pair_common.h"
 
 namespace {
 
 constexpr int kFwdWaves = 4;
 constexpr int kFwdThreads = kFwdWaves * kWave;
 
-// Sum over the 8 consecutive lanes ii = 0..7 of a j-atom (row half), complete in every
-// lane of it: swap neighbours, swap pairs, then add the mirrored half row.
-constexpr int kJSumLane = 0;
-__device__ inline float dpp_sum8(float v) {
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                               0xB1, 0xF, 0xF, false));
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                               0x4E, 0xF, 0xF, false));
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                               0x141, 0xF, 0xF, false));
-    return v;
-}
-
-__device__ inline int shift_x(int code) { return code / 9 - 1; }
-__device__ inline int shift_y(int code) { return (code / 3) % 3 - 1; }
-__device__ inline int shift_z(int code) { return code % 3 - 1; }
-
-__device__ inline uint64_t valid_mask(int ni, int nj, bool diag) {
-    const uint64_t ibyte = (ni >= 8) ? 0xffull : ((1ull << ni) - 1ull);
-    const uint64_t jmask = (nj >= 8) ? ~0ull : ((1ull << (8 * nj)) - 1ull);
-    return ibyte * 0x0101010101010101ull & jmask & (diag ? 0x7f3f1f0f07030100ull : ~0ull);
-}
-
-// erfc(t) exp(t^2) = u P(u), u = 1/(1 + p t) (coefficients fitted by fit_erfc.py).
-__device__ inline float erfcx_poly(float t) {
-    const float u = __builtin_amdgcn_rcpf(fmaf(NB_ERFC_P, t, 1.0f));
-    float p = NB_ERFC_C8;
-    p = fmaf(p, u, NB_ERFC_C7);
-    p = fmaf(p, u, NB_ERFC_C6);
-    p = fmaf(p, u, NB_ERFC_C5);
-    p = fmaf(p, u, NB_ERFC_C4);
-    p = fmaf(p, u, NB_ERFC_C3);
-    p = fmaf(p, u, NB_ERFC_C2);
-    p = fmaf(p, u, NB_ERFC_C1);
-    p = fmaf(p, u, NB_ERFC_C0);
-    return u * p;
-}
-
 // One 8x8 block of pairs (i-cluster c of the item, the current j-cluster): m is the
-// scalar 64-bit mask of non-excluded lanes (lane = ii + 8 jj).
-template <int COUL, bool ENERGY, bool VIRIAL, bool SHIFTED>
+// scalar 64-bit mask of non-excluded lanes (lane = ii + 8 jj), xj the lane's j-atom with
+// the entry's periodic shift already added, lj_j the LDS address of row 0 of the LJ
+// table plus 16 bytes times the j-atom's type (s_t holds 16 T type_i per slot).
+template <int COUL, bool ENERGY, bool VIRIAL>
 __device__ __forceinline__ void pair_block(const float4* s_x, const int* s_t,
                                            uint64_t m, float& fx, float& fy,
-                                           float& fz, const float4& xj, int tj,
-                                           const float4* __restrict__ s_lj, const NbKParams& kp,
-                                           float sxi, float syi, float szi, float& fjx,
+                                           float& fz, const float4& xj, const char* lj_j,
+                                           const NbKParams& kp, float& fjx,
                                            float& fjy, float& fjz, float& elj, float& ec,
                                            float& eclo, float (&vir)[6], int& npair,
                                            int& nblock) {
-    // The same separation as the list build: x_i - L for s > 0 on the i side, the j side
-    // already shifted by -L for s < 0.
     const float4 xv = *s_x;                            // (x_i, y_i, z_i, K q_i) of this lane
-    float dx, dy, dz;
-    if (SHIFTED) {
-        dx = (xv.x - sxi) - xj.x;
-        dy = (xv.y - syi) - xj.y;
-        dz = (xv.z - szi) - xj.z;
-    } else {
-        dx = xv.x - xj.x;
-        dy = xv.y - xj.y;
-        dz = xv.z - xj.z;
-    }
+    const float dx = xv.x - xj.x, dy = xv.y - xj.y, dz = xv.z - xj.z;
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     const uint64_t act = __builtin_amdgcn_ballot_w64(r2 < kp.rc2) & m;
     if (!act) return;
     const bool on = __builtin_amdgcn_inverse_ballot_w64(act);
-    const float qi = xv.w;
-    const int ti = *s_t;                               // type_i * T
-    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float4 p = *reinterpret_cast<const float4*>(lj_j + *s_t);   // (6 c6, 12 c12, shift, c6)
+    // With energies, pairs outside the cut-off or excluded get 1/r = 0 and q_i q_j = 0
+    // (every force and energy term below then vanishes; r2 itself stays finite); without,
+    // the scalar force alone is masked at the end.
+    const float rinv = (ENERGY && !on) ? 0.f : __builtin_amdgcn_rsqf(r2);
+    const float qq = (ENERGY && !on) ? 0.f : xv.w * xj.w;   // epsfac/eps_r folded into q_i
     const float rinv2 = rinv * rinv;
-    const float4 p = s_lj[ti + tj];                    // (6 c6, 12 c12, shift, c6)
     const float rinv6 = rinv2 * rinv2 * rinv2;
     const float a = p.y * rinv6;
     const float flj = rinv6 * (a - p.x);               // F_LJ * r
-    const float qq = qi * xj.w;                        // epsfac/eps_r folded into q_i
-    float fscal, vc = 0.f, vlo = 0.f;
+    float fscal;
     if (COUL == NB_COUL_RF) {
         fscal = fmaf(flj, rinv2, qq * (rinv * rinv2 - 2.0f * kp.krf));
         if (ENERGY) {
-            vc = qq * (fmaf(kp.krf, r2, rinv) - kp.crf);
+            ec = fmaf(qq, fmaf(kp.krf, r2, rinv) - kp.crf, ec);
             // The residuals of the single-precision k_rf, c_rf are far below half an ulp of
-            // vc near the cut-off, where most pairs are; summed with vc they would vanish
-            // and leave a systematic 1e-6 bias in E_C.  They get their own accumulator.
-            vlo = qq * fmaf(kp.krf_lo, r2, -kp.crf_lo);
+            // the pair energy near the cut-off, where most pairs are; added to it they would
+            // vanish and leave a systematic 1e-6 bias in E_C.  They get their own sum.
+            eclo = fmaf(qq, fmaf(kp.krf_lo, r2, -kp.crf_lo), eclo);
         }
     } else {
         const float r = r2 * rinv;
         const float e = __builtin_amdgcn_exp2f(r2 * kp.beta2_log2e);   // exp(-beta^2 r^2)
-        const float erfcv = e * erfcx_poly(kp.beta * r);
+        const float erfcv = e * erfcx_poly(r, kp.p_beta);
         const float g = fmaf(erfcv, rinv, kp.two_beta_sqrtpi * e);
         fscal = fmaf(qq, g, flj) * rinv2;
-        if (ENERGY) vc = qq * fmaf(erfcv, rinv, -kp.ewald_shift);
+        if (ENERGY) ec = fmaf(qq, fmaf(erfcv, rinv, -kp.ewald_shift), ec);
     }
-    fscal = on ? fscal : 0.f;
+    if (!ENERGY) fscal = on ? fscal : 0.f;
     const float tx = fscal * dx, ty = fscal * dy, tz = fscal * dz;
     fx += tx;
     fy += ty;
@@ -127,10 +80,7 @@ __device__ __forceinline__ void pair_block(const float4* s_x, const int* s_t,
     fjy -= ty;
     fjz -= tz;
     if (ENERGY) {
-        const float vlj = fmaf(rinv6, fmaf(a, 1.0f / 12.0f, -p.w), -p.z);
-        elj += on ? vlj : 0.f;
-        ec += on ? vc : 0.f;
-        if (COUL == NB_COUL_RF) eclo += on ? vlo : 0.f;
+        elj += fmaf(rinv6, fmaf(a, 1.0f / 12.0f, -p.w), on ? -p.z : 0.f);
         npair += __builtin_popcountll(act);
         nblock += 1;
     }
@@ -148,7 +98,7 @@ __device__ __forceinline__ void pair_block(const float4* s_x, const int* s_t,
 #define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
 // The work of one item (one wavefront): s_x and s_t are the wavefront's 64-entry LDS
-// tables of the super-cluster's atoms ((x, y, z, K q) and type * T, by slot), s_lj the
+// tables of the super-cluster's atoms ((x, y, z, K q) and 16 T type, by slot), s_lj the
 // block's LJ table.
 template <int COUL, bool ENERGY, bool VIRIAL, bool PRUNE>
 __device__ __forceinline__ void fwd_item(
@@ -168,7 +118,7 @@ __device__ __forceinline__ void fwd_item(
         // lane l holds slot l of the super-cluster: (8 c + ii) for c = l >> 3
         const float4 v = xq[kScAtoms * sc + lane];
         s_x[lane] = make_float4(v.x, v.y, v.z, v.w * kp.epsfac_r);
-        s_t[lane] = type_slot[kScAtoms * sc + lane] * T;
+        s_t[lane] = type_slot[kScAtoms * sc + lane] * T * (int)sizeof(float4);
     }
     __builtin_amdgcn_wave_barrier();
 
@@ -252,22 +202,19 @@ __device__ __forceinline__ void fwd_item(
 
         // self cluster pairs keep ii < jj only (empty slots fail every distance test)
 #define NB_MASK(c) (((self && dc == c) ? 0x7f3f1f0f07030100ull : ~0ull) & (xrow ? xrow[c] : ~0ull))
-        // Exact periodic shift, one code path for every entry: subtract L on the side whose
-        // coordinate is near L (nothing for s = 0, and x - 0 is exact, so unshifted pairs
-        // see the same arithmetic as without any shift).
+        // Periodic image of the j-cluster: x_j + s L, added once per entry.  The shift is
+        // built from the bits of L with scalar integer operations (s in {-1, 0, 1}).
         {
             const int sx = shift_x(code), sy = shift_y(code), sz = shift_z(code);
-            xj.x -= (sx < 0) ? S.L[0] : 0.f;
-            xj.y -= (sy < 0) ? S.L[1] : 0.f;
-            xj.z -= (sz < 0) ? S.L[2] : 0.f;
-            const float sxi = sx > 0 ? S.L[0] : 0.f, syi = sy > 0 ? S.L[1] : 0.f,
-                        szi = sz > 0 ? S.L[2] : 0.f;
+            xj.x += shift_value(sx, S.L[0]);
+            xj.y += shift_value(sy, S.L[1]);
+            xj.z += shift_value(sz, S.L[2]);
+            const char* lj_j = reinterpret_cast<const char*>(s_lj) + tj * (int)sizeof(float4);
 #define NB_BLOCK(c)                                                                    \
     if ((mask >> c) & 1u)                                                              \
-        pair_block<COUL, ENERGY, VIRIAL, true>(                                        \
+        pair_block<COUL, ENERGY, VIRIAL>(                                              \
             s_x + kClusterSize * c + ii, s_t + kClusterSize * c + ii, NB_MASK(c), fx##c, fy##c, \
-            fz##c, xj, tj, s_lj, kp, sxi, syi, szi, fjx, fjy, fjz, elj, ec, eclo, vir,    \
-            npair, nblock);
+            fz##c, xj, lj_j, kp, fjx, fjy, fjz, elj, ec, eclo, vir, npair, nblock);
             NB_FOR8(NB_BLOCK)
 #undef NB_BLOCK
         }
@@ -278,7 +225,7 @@ __device__ __forceinline__ void fwd_item(
         if (ii == kJSumLane) jp[jj] = make_float4(fjx, fjy, fjz, 0.f);
         if (ENERGY) {
             elj_acc += (double)elj;
-            ec_acc += (double)ec + (double)eclo;
+            ec_acc += (COUL == NB_COUL_RF) ? (double)ec + (double)eclo : (double)ec;
         }
         if (VIRIAL) {
 #pragma unroll
@@ -331,7 +278,11 @@ __device__ inline int xcd_block(int b, int g) {
 //                from an atomic counter in the order given by `order` (most pair work
 //                first), until the counter passes n_items.  queue[0] is the counter,
 //                queue[1] counts finished wavefronts; the last one resets both to zero,
-//                so the next launch needs no clearing pass (and a captured graph none).
+//                so the next launch needs no clearing pass (and a captured graph none);
+//   kExecPersist persistent: the same grid and order, without atomics: rounds of G
+//                items (G wavefronts), wavefront g taking position g of even rounds and
+//                G - 1 - g of odd ones, so the most expensive item of one round goes
+//                with the cheapest of the next.
 template <int COUL, bool ENERGY, bool VIRIAL, bool PRUNE>
 __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIRIAL ? 3 : 4))) void k_nb_fwd(
     const NbItem* __restrict__ items, NbEntry* __restrict__ entries,
@@ -373,6 +324,15 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
         if (done == waves - 1 && lane == 0) {
             atomicExch(queue, 0);
             atomicExch(queue + 1, 0);
+        }
+        return;
+    }
+    if (mode == kExecPersist) {
+        const int G = (int)gridDim.x * kFwdWaves;
+        const int g = (int)blockIdx.x * kFwdWaves + wave;
+        for (int base = 0, odd = 0; base < n_items; base += G, odd ^= 1) {
+            const int slot = base + (odd ? G - 1 - g : g);
+            if (slot < n_items) fwd_item<COUL, ENERGY, VIRIAL, PRUNE>(order[slot], NB_ITEM_ARGS);
         }
         return;
     }
@@ -534,13 +494,16 @@ inline int blocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 // to the per-wave tables, so the first query holds for every table size).
 template <int COUL, bool E, bool V, bool P>
 int fwd_blocks_per_cu(size_t lds) {
+    // resident blocks per CU of this kernel flavour for the last LJ-table size asked
     static int per_cu = 0;
-    if (per_cu == 0) {
+    static size_t per_cu_lds = 0;
+    if (per_cu == 0 || per_cu_lds != lds) {
         int nb = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_nb_fwd<COUL, E, V, P>,
                                                          kFwdThreads, lds) != hipSuccess)
             nb = 0;
         per_cu = nb > 0 ? nb : 1;
+        per_cu_lds = lds;
     }
     return per_cu;
 }
@@ -559,7 +522,7 @@ void launch_fwd_t(const NbDev& d, const NbKParams& kp, const float* lj, int n_it
                   int pi0, int pi1, float r2_inner, int mode, hipStream_t s) {
     const size_t lds = sizeof(float4) * (size_t)kp.n_types * kp.n_types;
     int grid = blocks(n_items, kFwdWaves);
-    if (mode == kExecQueue)    // one resident wave of blocks over the whole device
+    if (mode == kExecQueue || mode == kExecPersist)   // one resident grid over the device
         grid = std::min(grid, fwd_blocks_per_cu<COUL, E, V, P>(lds) * std::max(d.n_cu, 1));
     hipLaunchKernelGGL((k_nb_fwd<COUL, E, V, P>), dim3(grid), dim3(kFwdThreads), lds, s,
                        d.items, d.entries, d.excl_rows, d.xq, d.type_slot, d.sc_info, d.sys,

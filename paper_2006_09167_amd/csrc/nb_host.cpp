@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "nb_erfc_coeffs.h"
 #include "nb_internal.h"
 
 struct nb_ctx {
@@ -97,6 +98,7 @@ NbKParams kernel_params(const nb_params& p) {
     k.crf_lo = (float)(crf - (double)k.crf);
     const double b = p.ewald_beta;
     k.beta = (float)b;
+    k.p_beta = (float)((double)NB_ERFC_P * b);
     k.beta2_log2e = (float)(-b * b / log(2.0));
     k.two_beta_sqrtpi = (float)(2.0 * b / sqrt(M_PI));
     const bool shift = p.modifier == NB_MOD_POTSHIFT;
@@ -600,7 +602,8 @@ nb_status nb_prune_rolling(nb_ctx* c, const float* x, int64_t steps_since_build)
     const int i0 = c->part_start[part], i1 = c->part_start[part + 1];
     TimedSection ts(c, NB_T_PRUNE);
     NB_HIP(c, launch_gather(c->d, x, nullptr, c->d.xp, c->n_slots, c->stream));
-    NB_HIP(c, launch_prune(c->d, c->d.xp, i0, i1 - i0, radius_sq(c->p.rinner), c->stream));
+    NB_HIP(c, launch_prune(c->d, c->d.xp, i0, i1 - i0, radius_sq(c->p.rinner), c->item_w,
+                           c->stream));
     return NB_OK;
 }
 
@@ -627,7 +630,8 @@ nb_status forces_impl(nb_ctx* c, const float* x, const float* q, const float* lj
         // then the plain pair kernel
         const int i0 = c->part_start[prune_part], i1 = c->part_start[prune_part + 1];
         TimedSection ts(c, NB_T_PRUNE);
-        NB_HIP(c, launch_prune(d, d.xq, i0, i1 - i0, radius_sq(c->p.rinner), c->stream));
+        NB_HIP(c, launch_prune(d, d.xq, i0, i1 - i0, radius_sq(c->p.rinner), c->item_w,
+                               c->stream));
     }
     {
         TimedSection ts(c, NB_T_FORCES);
@@ -730,7 +734,8 @@ nb_status nb_step_graph(nb_ctx* c, const float* x, const float* q, const float* 
 nb_status nb_set_exec(nb_ctx* c, int32_t width, int32_t exec_mode, int32_t prune_fused) {
     if (!c) return NB_ERR_ARG;
     if (width < 0 || width > 64) return fail(c, NB_ERR_ARG, "item width must be 0 (rule) or 1..64");
-    if (exec_mode != kExecStatic && exec_mode != kExecXcd && exec_mode != kExecQueue)
+    if (exec_mode != kExecStatic && exec_mode != kExecXcd && exec_mode != kExecQueue &&
+        exec_mode != kExecPersist)
         return fail(c, NB_ERR_ARG, "unknown execution mode");
     if (prune_fused != 0 && prune_fused != 1) return fail(c, NB_ERR_ARG, "prune_fused is 0 or 1");
     c->fixed_w = width;
@@ -785,7 +790,7 @@ nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj
     const bool timing = c->timing;
     c->timing = false;
     const int widths[] = {8, 16, 24, 32, 48, 64};
-    const int modes[] = {kExecStatic, kExecXcd, kExecQueue};
+    const int modes[] = {kExecStatic, kExecXcd, kExecQueue, kExecPersist};
     nb_exec_config win{0, 0, 1, 0, 1e300};
     int n = 0;
     nb_status st = NB_OK;
@@ -879,7 +884,7 @@ nb_status nb_forces_backward(nb_ctx* c, const float* x, const float* q, const fl
     {
         TimedSection ts(c, NB_T_BACKWARD);
         NB_HIP(c, launch_backward(d, kp, c->p.coulomb, lj, grad_f, grad_energy, grad_lj != nullptr,
-                                  c->n_slots, c->n_items, c->stream));
+                                  c->n_slots, c->n_items, c->exec_mode, c->stream));
     }
     TimedSection ts(c, NB_T_BACKWARD_REDUCE);
     NB_HIP(c, launch_reduce_backward(d, grad_x, grad_q, grad_lj, acc, c->n_slots, c->p.n_types,

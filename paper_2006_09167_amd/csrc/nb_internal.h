@@ -25,6 +25,7 @@ constexpr int kXcds = 8;                        // accelerator complex dies of a
 constexpr int kExecStatic = 0;                  // one wavefront per item, in item order
 constexpr int kExecXcd = 1;                     // blocks renumbered XCD-contiguously
 constexpr int kExecQueue = 2;                   // persistent grid, atomic item queue
+constexpr int kExecPersist = 3;                 // persistent grid, fixed balanced schedule
 constexpr int kMaxItemCost = 64 * 8;            // set outer-mask bits of one item, at most
 
 // One j-entry of a super-cluster's joint list (16 bytes, loaded with one scalar load).
@@ -78,6 +79,7 @@ struct NbKParams {
                          // sums q_i q_j (krf_lo r^2 - crf_lo) apart, else c_rf's rounding
                          // times the sum of q_i q_j leaves a 1e-6 relative bias in E_C
     float beta;          // Ewald splitting parameter
+    float p_beta;        // p beta, p the slope of the erfc substitution u = 1/(1 + p beta r)
     float beta2_log2e;   // -beta^2 / ln 2 (exp(-beta^2 r^2) = exp2(r^2 * this))
     float two_beta_sqrtpi;  // 2 beta / sqrt(pi)
     float ewald_shift;   // erfc(beta rc)/rc under the potential-shift modifier, else 0
@@ -114,7 +116,7 @@ hipError_t launch_fill_d(double* p, int n, double v, hipStream_t s);
 hipError_t launch_gather(const NbDev& d, const float* x, const float* q, float4* out,
                          int n_slots, hipStream_t s);
 hipError_t launch_prune(const NbDev& d, const float4* coords, int item0, int n_items,
-                        float r2_inner, hipStream_t s);
+                        float r2_inner, int item_width, hipStream_t s);
 hipError_t launch_forces(const NbDev& d, const NbKParams& kp, int coulomb, uint32_t flags,
                          const float* lj, int n_items, int prune_i0, int prune_i1,
                          float r2_inner, int mode, hipStream_t s);
@@ -128,7 +130,7 @@ hipError_t launch_reduce(const NbDev& d, float* f, bool accumulate, int n_slots,
                         hipStream_t s);
 hipError_t launch_backward(const NbDev& d, const NbKParams& kp, int coulomb, const float* lj,
                            const float* grad_f, const double* grad_energy, bool ljgrad,
-                           int n_slots, int n_items, hipStream_t s);
+                           int n_slots, int n_items, int mode, hipStream_t s);
 hipError_t launch_reduce_backward(const NbDev& d, float* grad_x, float* grad_q,
                                   double* grad_lj, bool accumulate, int n_slots,
                                   int n_types, int n_items, hipStream_t s);

@@ -16,15 +16,14 @@
 // Atom distances for list decisions use a fixed single-precision sequence without fused
 // operations: per axis a = (s > 0) ? x_i - L : x_i, b = (s < 0) ? x_j - L : x_j,
 // d = a - b; r2 = (dx*dx + dy*dy) + dz*dz; inside iff r2 < R2.
+#include <algorithm>
+
 #include "nb_internal.h"
+#include "nb_pair_common.h"
 
 namespace {
 
 constexpr int kScanThreads = 1024;
-
-__device__ inline int shift_x(int code) { return code / 9 - 1; }
-__device__ inline int shift_y(int code) { return (code / 3) % 3 - 1; }
-__device__ inline int shift_z(int code) { return code % 3 - 1; }
 
 __device__ inline int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
 
@@ -326,7 +325,7 @@ __global__ __launch_bounds__(kWave) void k_jseg_rank(NbDev d) {
 }
 
 constexpr int kPruneWaves = 4;
-constexpr int kPruneSplit = 2;          // wavefronts per item (alternate entries)
+constexpr int kPruneEntriesPerWave = 8;  // wavefronts per item: item width / 8, rounded up
 #define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
 // Rolling prune (Sec. V.E) of a range of work items: two wavefronts per item taking
@@ -338,12 +337,12 @@ constexpr int kPruneSplit = 2;          // wavefronts per item (alternate entrie
 __global__ __launch_bounds__(kPruneWaves * kWave) void k_prune(
     const NbItem* __restrict__ items, NbEntry* __restrict__ entries,
     const float4* __restrict__ xp, const NbScInfo* __restrict__ sc_info,
-    const NbSys* __restrict__ sys, int item0, int n_items, float r2_inner) {
+    const NbSys* __restrict__ sys, int item0, int n_items, float r2_inner, int split) {
 #pragma clang fp contract(off)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x & (kWave - 1);
     const int kw = blockIdx.x * kPruneWaves + wave;
-    const int k = kw / kPruneSplit, part = kw % kPruneSplit;
+    const int k = kw / split, part = kw % split;   // wavefront `part` takes every split-th entry
     if (k >= n_items) return;
     const NbItem it = items[item0 + k];
     const int ii = lane & 7, jj = lane >> 3;
@@ -355,7 +354,7 @@ __global__ __launch_bounds__(kPruneWaves * kWave) void k_prune(
     const int e_end = it.e0 + it.ne;
     const int e_first = it.e0 + part;
     if (e_first >= e_end) return;
-    constexpr int kStep = kPruneSplit;
+    const int kStep = split;
     // two entries ahead: (ent1, xj1) is the next one, (ent2, xj2) the one after
     NbEntry ent1 = entries[e_first];
     float4 xj1 = xp[kClusterSize * ent1.cj + jj];
@@ -488,11 +487,12 @@ hipError_t launch_list_finish(const NbDev& d, int n_sc, int64_t n_entries, int n
 }
 
 hipError_t launch_prune(const NbDev& d, const float4* coords, int item0, int n_items,
-                        float r2_inner, hipStream_t s) {
+                        float r2_inner, int item_width, hipStream_t s) {
+    const int split = std::max(1, (item_width + kPruneEntriesPerWave - 1) / kPruneEntriesPerWave);
     if (n_items > 0)
-        hipLaunchKernelGGL(k_prune, dim3(blocks((int64_t)n_items * kPruneSplit, kPruneWaves)),
+        hipLaunchKernelGGL(k_prune, dim3(blocks((int64_t)n_items * split, kPruneWaves)),
                            dim3(kPruneWaves * kWave),
                            0, s, d.items, d.entries, coords, d.sc_info, d.sys, item0, n_items,
-                           r2_inner);
+                           r2_inner, split);
     return hipGetLastError();
 }

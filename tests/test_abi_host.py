@@ -132,7 +132,9 @@ def test_exec_shape_validation_without_device():
         assert ctypes.sizeof(_lib.NbExecConfig) == 24
         assert lib.nb_set_exec(h, -1, _lib.NB_EXEC_STATIC, 1) == _lib.NB_ERR_ARG
         assert lib.nb_set_exec(h, 65, _lib.NB_EXEC_STATIC, 1) == _lib.NB_ERR_ARG
-        assert lib.nb_set_exec(h, 16, 3, 1) == _lib.NB_ERR_ARG
+        assert lib.nb_set_exec(h, 16, 4, 1) == _lib.NB_ERR_ARG
+        assert lib.nb_set_exec(h, 16, -1, 1) == _lib.NB_ERR_ARG
+        assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_PERSIST, 1) == _lib.NB_OK
         assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_STATIC, 2) == _lib.NB_ERR_ARG
         assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_QUEUE, 0) == _lib.NB_OK
         cfg = _lib.NbExecConfig()

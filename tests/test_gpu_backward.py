@@ -110,3 +110,35 @@ def test_autograd_force_matching_chain():
     assert rel_rms(q.grad.cpu().numpy(), oq) <= 1e-3
     assert rel_rms(sig.grad.cpu().numpy(), sig_c.grad.numpy()) <= 1e-3
     assert rel_rms(eps.grad.cpu().numpy(), eps_c.grad.numpy()) <= 1e-3
+
+
+@pytest.mark.parametrize("n_types", [4, 6])
+def test_backward_persistent_schedule_matches_static(sys24k, n_types):
+    """The persistent schedule (a resident grid, several items per wavefront, the table
+    histogram cleared between items) gives bitwise the backward pass of one wavefront per
+    item.  Four types use the lane-private histograms, six the shared ones with LDS
+    atomics; one entry per item makes many more items than resident wavefronts."""
+    import dataclasses
+    from paper_2006_09167_amd.systems import lj_table_lorentz_berthelot
+    rng = np.random.default_rng(7)
+    s = sys24k
+    if n_types != s.n_types:
+        sig = rng.uniform(0.25, 0.40, n_types)
+        eps = rng.uniform(0.1, 1.0, n_types)
+        s = dataclasses.replace(s, type=rng.integers(0, n_types, s.n).astype(np.int32),
+                                sigma=sig, eps=eps, lj=lj_table_lorentz_berthelot(sig, eps))
+    c = concat(s)
+    ctx = make_ctx(c, coulomb="rf", rc=1.0, rinner=1.0, rlist=1.0)
+    x = dev(c["x"])
+    ctx.grid_build(x, c["boxes"])
+    ctx.pairlist_build()
+    G = dev(rng.normal(size=(s.n, 3)).astype(np.float32))
+    ge = dev(np.array([[0.3, -0.7]], np.float64), torch.float64)
+    out = {}
+    for mode in ("static", "persist"):
+        ctx.set_exec(1, mode)
+        out[mode] = ctx.backward(x, dev(c["q"]), dev(c["lj"]), G, ge)
+        torch.cuda.synchronize()
+    assert ctx.stats()["n_work_items"] > 12000
+    for a, b in zip(out["static"], out["persist"]):
+        assert torch.equal(a, b)

@@ -1,4 +1,5 @@
-"""Execution shapes of the pair kernel (static, XCD-contiguous, persistent queue), item
+"""Execution shapes of the pair kernel (static, XCD-contiguous, persistent queue,
+persistent balanced schedule), item
 widths, the autotuner, the graph-replayed step and an ensemble of uneven replicas in one
 context, through the C ABI on an MI355X, against the FP64 oracle."""
 import numpy as np
@@ -42,7 +43,7 @@ def test_modes_bitwise_equal_and_queue_relaunches(sys3k, width):
     ctx, x = built(c, nstlist=10, nstprune=4, **EWALD)
     q, lj = dev(c["q"]), dev(c["lj"])
     ref = None
-    for mode in ("static", "xcd", "queue", "queue", "queue", "static"):
+    for mode in ("static", "xcd", "queue", "queue", "queue", "persist", "persist", "static"):
         ctx.set_exec(width, mode)
         assert ctx.get_exec() == {"item_width": width, "mode": mode, "prune_fused": True}
         out = ctx.forces(x, q, lj, energy=True, virial=True)
@@ -55,14 +56,15 @@ def test_modes_bitwise_equal_and_queue_relaunches(sys3k, width):
                 assert torch.equal(a, b), mode
 
 
-def test_fused_step_in_queue_mode_matches_static(sys3k):
-    """nb_step (prune fused into the pair kernel) under the persistent queue: same inner
+@pytest.mark.parametrize("mode", ["queue", "persist"])
+def test_fused_step_in_persistent_modes_matches_static(sys3k, mode):
+    """nb_step (prune fused into the pair kernel) under the persistent modes: same inner
     lists and bitwise the same outputs as the static mode over a rolling cycle."""
     c = concat(sys3k)
     kw = dict(nstlist=20, nstprune=4, **EWALD)
     ctx_a, _ = built(c, **kw)
     ctx_b, _ = built(c, **kw)
-    ctx_b.set_exec(0, "queue")
+    ctx_b.set_exec(0, mode)
     q, lj = dev(c["q"]), dev(c["lj"])
     rng = np.random.default_rng(3)
     x = c["x"].copy()
@@ -75,7 +77,7 @@ def test_fused_step_in_queue_mode_matches_static(sys3k):
     assert np.array_equal(ctx_a.get_pairs("inner"), ctx_b.get_pairs("inner"))
 
 
-@pytest.mark.parametrize("mode", ["xcd", "queue"])
+@pytest.mark.parametrize("mode", ["xcd", "queue", "persist"])
 def test_separate_prune_step_equals_fused(sys3k, mode):
     """nb_step with the prune as separate kernels: the same inner lists and bitwise the
     same outputs as with the prune fused into the pair kernel."""
@@ -122,11 +124,11 @@ def test_autotune_keeps_fastest_and_stays_exact(sys3k):
     ctx, x = built(c, nstlist=10, nstprune=2, **EWALD)
     q, lj = dev(c["q"]), dev(c["lj"])
     best, trials = ctx.autotune(x, q, lj, energy=True, repeats=3)
-    assert len(trials) == 20
+    assert len(trials) == 26
     assert all(t["us_per_call"] > 0 for t in trials)
-    shape = min(trials[:18], key=lambda t: t["us_per_call"])
+    shape = min(trials[:24], key=lambda t: t["us_per_call"])
     assert (best["item_width"], best["mode"]) == (shape["item_width"], shape["mode"])
-    step = min(trials[18:], key=lambda t: t["us_per_call"])
+    step = min(trials[24:], key=lambda t: t["us_per_call"])
     assert best["prune_fused"] == step["prune_fused"]
     assert ctx.get_exec() == {"item_width": best["item_width"], "mode": best["mode"],
                               "prune_fused": best["prune_fused"]}
@@ -139,7 +141,7 @@ def test_autotune_keeps_fastest_and_stays_exact(sys3k):
     assert ctx.get_exec()["item_width"] == best["item_width"]
 
 
-@pytest.mark.parametrize("mode", ["static", "queue"])
+@pytest.mark.parametrize("mode", ["static", "queue", "persist"])
 def test_graph_step_replays_match_eager(sys3k, mode):
     """nb_step_graph over two list lifetimes with positions updated in place: every replay
     (with eager work and synchronisation in between) equals the eager nb_step bitwise."""
@@ -188,7 +190,7 @@ def test_ensemble_uneven_replicas_all_modes():
     E, F, _, A = oracle_forces_multi(c, c["x"], oracle_params("rf", e_cfg["rc"]))
     tol = energy_tolerance(E, A, True)
     ref = None
-    for mode in ("static", "xcd", "queue"):
+    for mode in ("static", "xcd", "queue", "persist"):
         ctx.set_exec(0, mode)
         f, e, _ = ctx.forces(x, q, lj)
         torch.cuda.synchronize()
