@@ -35,19 +35,19 @@ PEAK_FP32_NONPACKED = 78.6e12 # without packed FP32 (one FMA per lane per cycle)
 # add/mul = 1, rsqrt/rcp/exp2 = 1, compare/select = 0):
 #   common: separation 3, r^2 5, rsqrt 1, r^-2 1, LJ force 5, q_i q_j 1,
 #           force accumulation 9                                            (= 25)
-#   Ewald:  r 1, beta r 1, u = 1/(1 + p t) 3, P(u) 16, u P 1, exp argument 1, exp2 1,
-#           erfc 1, g 3 (= 28), F/r 3, energies 9 (V_C 3, V_LJ 4, 2 sums)   => 66
+#   Ewald:  r 1, u = 1/(1 + (p beta) r) 3, P(u) of degree 7 14, u P 1, exp argument 1,
+#           exp2 1, erfc 1, g 3 (= 25), F/r 3, energies 9 (V_C 3, V_LJ 4, 2 sums) => 62
 #   RF:     force 5, energies 14 (V_C 4, its constants' residual term 3, V_LJ 4,
 #           3 sums)                                                         => 44
-FLOP_PER_PAIR = {"ewald": 66, "rf": 44}
+FLOP_PER_PAIR = {"ewald": 62, "rf": 44}
 # Backward pass per evaluated pair slot (same counting, with the table gradient):
 #   separation 3, r^2 5, rsqrt 1, r^-2 1, r^-6 and 12 c12 r^-6 3, phi_LJ 3, phi'_LJ/r 6,
 #   q_i q_j 1, phi_C 1, G_i - G_j 3, u 5, phi 1, coefficient of d 7, h 9, w 3,
 #   i- and j-accumulation 10, table gradient 15                                (= 77)
-#   Ewald psi, psi', v: beta r 2, u = 1/(1 + p t) 3, P(u) 16, u P 1, exp 2, erfc 1,
-#           2 beta/sqrt(pi) e 1, g 2, psi 1, psi' 6, v 2                      (= 37) => 114
+#   Ewald psi, psi', v: r 1, u = 1/(1 + (p beta) r) 3, P(u) 14, u P 1, exp 2, erfc 1,
+#           2 beta/sqrt(pi) e 1, g 2, psi 1, psi' 6, v 2                      (= 34) => 111
 #   RF psi, psi', v 8                                                                => 85
-FLOP_PER_PAIR_BWD = {"ewald": 114, "rf": 85}
+FLOP_PER_PAIR_BWD = {"ewald": 111, "rf": 85}
 
 WORKLOADS = {
     "water96k_ewald": "96,000-atom water-like box (32,000 molecules, 9.86 nm cube), Ewald "
@@ -78,12 +78,14 @@ def measured_traffic(workload, exec_cfg):
         return None
     text = open(path).read()
     src = b"".join(open(os.path.join(ROOT, "paper_2006_09167_amd", "csrc", f), "rb").read()
-                   for f in ("nb_forces.hip", "nb_internal.h", "nb_erfc_coeffs.h"))
+                   for f in ("nb_forces.hip", "nb_internal.h", "nb_erfc_coeffs.h",
+                             "nb_pair_common.h"))
     if hashlib.sha256(src).hexdigest()[:16] not in text:
         return None
     shape = "%d entries per item, %s" % (exec_cfg["item_width"],
                                           {"xcd": "XCD-contiguous", "static": "static",
-                                           "queue": "persistent queue"}[exec_cfg["mode"]])
+                                           "queue": "persistent queue",
+                                           "persist": "persistent balanced"}[exec_cfg["mode"]])
     if shape not in text.replace("\n", " "):
         return None
     for line in text.splitlines():

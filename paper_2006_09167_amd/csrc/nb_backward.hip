@@ -212,7 +212,7 @@ __device__ __forceinline__ void bwd_item(
         ajy = dpp_sum8(ajy);
         ajz = dpp_sum8(ajz);
         ajq = dpp_sum8(ajq);
-        if (ii == kJSumLane) jp[jj] = make_float4(ajx, ajy, ajz, ajq);
+        jp[jj] = make_float4(ajx, ajy, ajz, ajq);   // the same sums in all eight lanes
     }
     float4* ip = ipart + (size_t)item * kScAtoms;
 #define NB_IRED(c)                                                                     \

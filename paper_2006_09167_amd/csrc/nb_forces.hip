@@ -43,7 +43,7 @@ __device__ __forceinline__ void pair_block(const float4* s_x, const int* s_t,
     const uint64_t act = __builtin_amdgcn_ballot_w64(r2 < kp.rc2) & m;
     if (!act) return;
     const bool on = __builtin_amdgcn_inverse_ballot_w64(act);
-    const float4 p = *reinterpret_cast<const float4*>(lj_j + *s_t);   // (6 c6, 12 c12, shift, c6)
+    const float4 p = *reinterpret_cast<const float4*>(lj_j + *s_t);   // (6 c6, 12 c12, shift, c6/2)
     // With energies, pairs outside the cut-off or excluded get 1/r = 0 and q_i q_j = 0
     // (every force and energy term below then vanishes; r2 itself stays finite); without,
     // the scalar force alone is masked at the end.
@@ -51,8 +51,8 @@ __device__ __forceinline__ void pair_block(const float4* s_x, const int* s_t,
     const float qq = (ENERGY && !on) ? 0.f : xv.w * xj.w;   // epsfac/eps_r folded into q_i
     const float rinv2 = rinv * rinv;
     const float rinv6 = rinv2 * rinv2 * rinv2;
-    const float a = p.y * rinv6;
-    const float flj = rinv6 * (a - p.x);               // F_LJ * r
+    const float t = fmaf(p.y, rinv6, -p.x);            // 12 c12 r^-6 - 6 c6
+    const float flj = rinv6 * t;                       // F_LJ * r
     float fscal;
     if (COUL == NB_COUL_RF) {
         fscal = fmaf(flj, rinv2, qq * (rinv * rinv2 - 2.0f * kp.krf));
@@ -80,7 +80,8 @@ __device__ __forceinline__ void pair_block(const float4* s_x, const int* s_t,
     fjy -= ty;
     fjz -= tz;
     if (ENERGY) {
-        elj += fmaf(rinv6, fmaf(a, 1.0f / 12.0f, -p.w), on ? -p.z : 0.f);
+        // V_LJ = r^-6 (c12 r^-6 - c6) - shift = r^-6 (t / 12 - c6 / 2) - shift
+        elj += fmaf(rinv6, fmaf(t, 1.0f / 12.0f, -p.w), on ? -p.z : 0.f);
         npair += __builtin_popcountll(act);
         nblock += 1;
     }
@@ -222,7 +223,9 @@ __device__ __forceinline__ void fwd_item(
         fjx = dpp_sum8(fjx);
         fjy = dpp_sum8(fjy);
         fjz = dpp_sum8(fjz);
-        if (ii == kJSumLane) jp[jj] = make_float4(fjx, fjy, fjz, 0.f);
+        // every lane of a row holds the same sums: all eight store them (one 128-byte line
+        // per entry), which keeps the last DPP step fused with its add
+        jp[jj] = make_float4(fjx, fjy, fjz, 0.f);
         if (ENERGY) {
             elj_acc += (double)elj;
             ec_acc += (COUL == NB_COUL_RF) ? (double)ec + (double)eclo : (double)ec;
@@ -298,7 +301,7 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
     const int T = kp.n_types;
     for (int i = threadIdx.x; i < T * T; i += blockDim.x) {
         const float c6 = lj[2 * i], c12 = lj[2 * i + 1];
-        s_lj[i] = make_float4(6.0f * c6, 12.0f * c12, c12 * kp.rc_m12 - c6 * kp.rc_m6, c6);
+        s_lj[i] = make_float4(6.0f * c6, 12.0f * c12, c12 * kp.rc_m12 - c6 * kp.rc_m6, 0.5f * c6);
     }
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -509,12 +512,12 @@ int fwd_blocks_per_cu(size_t lds) {
 }
 
 template <int COUL, bool P>
-void prepare_fwd_c(uint32_t flags, size_t lds) {
+int prepare_fwd_c(uint32_t flags, size_t lds) {
     const bool E = (flags & NB_F_ENERGY) != 0, V = (flags & NB_F_VIRIAL) != 0;
-    if (E && V) fwd_blocks_per_cu<COUL, true, true, P>(lds);
-    else if (E) fwd_blocks_per_cu<COUL, true, false, P>(lds);
-    else if (V) fwd_blocks_per_cu<COUL, false, true, P>(lds);
-    else fwd_blocks_per_cu<COUL, false, false, P>(lds);
+    if (E && V) return fwd_blocks_per_cu<COUL, true, true, P>(lds);
+    if (E) return fwd_blocks_per_cu<COUL, true, false, P>(lds);
+    if (V) return fwd_blocks_per_cu<COUL, false, true, P>(lds);
+    return fwd_blocks_per_cu<COUL, false, false, P>(lds);
 }
 
 template <int COUL, bool E, bool V, bool P>
@@ -542,15 +545,17 @@ void launch_fwd_c(const NbDev& d, const NbKParams& kp, uint32_t flags, const flo
 
 }  // namespace
 
-hipError_t prepare_forces(int coulomb, uint32_t flags, bool prune, int n_types) {
+hipError_t prepare_forces(int coulomb, uint32_t flags, bool prune, int n_types,
+                          int* waves_per_cu) {
     const size_t lds = sizeof(float4) * (size_t)n_types * n_types;
-    if (coulomb == NB_COUL_RF) {
-        if (prune) prepare_fwd_c<NB_COUL_RF, true>(flags, lds);
-        else prepare_fwd_c<NB_COUL_RF, false>(flags, lds);
-    } else {
-        if (prune) prepare_fwd_c<NB_COUL_EWALD, true>(flags, lds);
-        else prepare_fwd_c<NB_COUL_EWALD, false>(flags, lds);
-    }
+    int nb;
+    if (coulomb == NB_COUL_RF)
+        nb = prune ? prepare_fwd_c<NB_COUL_RF, true>(flags, lds)
+                   : prepare_fwd_c<NB_COUL_RF, false>(flags, lds);
+    else
+        nb = prune ? prepare_fwd_c<NB_COUL_EWALD, true>(flags, lds)
+                   : prepare_fwd_c<NB_COUL_EWALD, false>(flags, lds);
+    if (waves_per_cu) *waves_per_cu = nb * kFwdWaves;
     return hipGetLastError();
 }
 

@@ -789,7 +789,7 @@ nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj
     hipEventCreate(&e1);
     const bool timing = c->timing;
     c->timing = false;
-    const int widths[] = {8, 16, 24, 32, 48, 64};
+    const int widths[] = {8, 16, 24, 32, 40, 48, 56, 64};
     const int modes[] = {kExecStatic, kExecXcd, kExecQueue, kExecPersist};
     nb_exec_config win{0, 0, 1, 0, 1e300};
     int n = 0;

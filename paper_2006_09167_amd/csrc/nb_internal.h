@@ -121,8 +121,10 @@ hipError_t launch_forces(const NbDev& d, const NbKParams& kp, int coulomb, uint3
                          const float* lj, int n_items, int prune_i0, int prune_i1,
                          float r2_inner, int mode, hipStream_t s);
 // Resolve once, outside any stream capture, the launch shape of the pair kernel flavor
-// for these flags (its occupancy, used by the persistent mode).
-hipError_t prepare_forces(int coulomb, uint32_t flags, bool prune, int n_types);
+// for these flags (its occupancy, used by the persistent modes); optionally returns the
+// wavefronts of that flavor resident per CU.
+hipError_t prepare_forces(int coulomb, uint32_t flags, bool prune, int n_types,
+                          int* waves_per_cu = nullptr);
 // Per-atom forces (compensated sums of the partials, written in the caller's order) and,
 // with NB_F_ENERGY / NB_F_VIRIAL, the energy chunks in the same launch, then per system.
 hipError_t launch_reduce(const NbDev& d, float* f, bool accumulate, int n_slots,

@@ -6,8 +6,8 @@
 //   a 64-lane ballot ("warp collectives"); the outer mask keeps pairs with an atom pair
 //   closer than rlist, the inner mask those closer than rinner.
 // * k_compact / items: entries are copied to one array in super-cluster order and cut
-//   into work items of at most W entries (list splitting, Sec. V.F), grouped by
-//   rolling-prune part.
+//   into work items of at most W entries, of near-equal length within a super-cluster
+//   (list splitting, Sec. V.F), grouped by rolling-prune part.
 // * exclusion rows: 64-bit masks per (entry, i-cluster) for force-field exclusions.
 // * j-partial slots: entries referencing the same j-cluster get consecutive slots of the
 //   partial-force buffer, ordered by entry index (deterministic force sums).
@@ -255,11 +255,13 @@ __global__ __launch_bounds__(kWave) void k_compact(NbDev d, int cap, int w, int 
         }
     const int i0 = d.sc_istart[sc], ni = d.sc_icount[sc];
     const int p0 = d.sc_ipos[sc];
+    // ni = ceil(n / w) items of near-equal length (floor or ceil of n / ni, never above w)
     for (int k = threadIdx.x; k < ni; k += blockDim.x) {
         NbItem it;
         it.sc = sc;
-        it.e0 = e0 + k * w;
-        it.ne = min(w, n - k * w);
+        const int a = (int)((int64_t)k * n / ni), b = (int)((int64_t)(k + 1) * n / ni);
+        it.e0 = e0 + a;
+        it.ne = b - a;
         it.pos = p0 + k;
         d.items[i0 + k] = it;
     }
@@ -325,7 +327,7 @@ __global__ __launch_bounds__(kWave) void k_jseg_rank(NbDev d) {
 }
 
 constexpr int kPruneWaves = 4;
-constexpr int kPruneEntriesPerWave = 8;  // wavefronts per item: item width / 8, rounded up
+constexpr int kPruneEntriesPerWave = 4;  // wavefronts per item: item width / 4, rounded up
 #define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
 // Rolling prune (Sec. V.E) of a range of work items: two wavefronts per item taking

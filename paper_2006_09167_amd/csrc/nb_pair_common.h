@@ -4,9 +4,9 @@
 #include "nb_erfc_coeffs.h"
 #include "nb_internal.h"
 
-// Sum over the 8 consecutive lanes ii = 0..7 of a j-atom (row half), complete in every
-// lane of it: swap neighbours, swap pairs, then add the mirrored half row.
-constexpr int kJSumLane = 0;
+// Sum over the 8 consecutive lanes ii = 0..7 of a j-atom (row half): swap neighbours,
+// swap pairs, then add the mirrored half row.  Each step adds two values in either order
+// in the two lanes involved, so all eight lanes end with bitwise the same sum.
 __device__ inline float dpp_sum8(float v) {
     v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
                                                                0xB1, 0xF, 0xF, true));
