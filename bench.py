@@ -86,10 +86,8 @@ def measured_traffic(workload, exec_cfg):
                                           {"xcd": "XCD-contiguous", "static": "static",
                                            "queue": "persistent queue",
                                            "persist": "persistent balanced"}[exec_cfg["mode"]])
-    if shape not in text.replace("\n", " "):
-        return None
     for line in text.splitlines():
-        if line.strip().startswith("HBM traffic"):
+        if line.strip().startswith("HBM traffic") and shape in line:
             return float(line.split()[-2]) * 1e6
     return None
 

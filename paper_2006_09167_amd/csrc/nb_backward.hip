@@ -366,19 +366,51 @@ __device__ inline void reduce_bwd_cluster(
     }
 }
 
-// Input-gradient reduction and the first stage of the table-gradient reduction in one
-// launch: blocks [0, n_gblk) reduce four clusters each (one wavefront per cluster), blocks
-// [n_gblk, n_gblk + n_chunks) sum kChunkItems item ranks of the table-gradient partials.
-__global__ __launch_bounds__(kRedThreads) void k_reduce_bwd_step(NbDev d, float* __restrict__ gx,
-                                                                 float* __restrict__ gq,
-                                                                 int accumulate, int n_cl,
-                                                                 int n_gblk, int n_keys,
-                                                                 int n_items) {
+// Table gradient totals: thread t of the block takes the (type pair, c6/c12) keys t,
+// t + blockDim.x, ... and adds the chunk partials in order.  The table is symmetric, so
+// the derivative with respect to the shared value of [t1][t2] and [t2][t1] is split
+// evenly between the two entries (independent of which atom of a pair the kernel treats
+// as i).
+__device__ inline void glj_totals(const NbDev& d, double* __restrict__ out, int n_types,
+                                  int n_chunks, int accumulate) {
+    const int n_keys = 2 * n_types * n_types;
+    for (int k = threadIdx.x; k < n_keys; k += blockDim.x) {
+        const int c = k & 1, t1 = (k >> 1) / n_types, t2 = (k >> 1) % n_types;
+        const int kt = 2 * (t2 * n_types + t1) + c;
+        double sk = 0.0, st = 0.0;
+        for (int q = 0; q < n_chunks; ++q) {
+            sk += d.cpart[(size_t)q * kChunkVals + k];
+            st += d.cpart[(size_t)q * kChunkVals + kt];
+        }
+        const double r = (kt != k) ? 0.5 * (sk + st) : sk;
+        out[k] = accumulate ? out[k] + r : r;
+    }
+}
+
+// Input-gradient reduction and the table-gradient reduction in one launch: blocks
+// [0, n_gblk) reduce four clusters each (one wavefront per cluster), blocks [n_gblk,
+// n_gblk + n_chunks) sum kChunkItems item ranks of the table-gradient partials each; the
+// last of those to finish (a ticket in queue[3], taken after a device-scope fence) forms
+// the totals and resets the ticket for the next launch.
+__global__ __launch_bounds__(kRedThreads) void k_reduce_bwd_step(
+    NbDev d, float* __restrict__ gx, float* __restrict__ gq, double* __restrict__ glj,
+    int accumulate, int n_cl, int n_gblk, int n_types, int n_items, int n_chunks) {
     static_assert(kRedThreads == kRedWaves * kWave, "one block shape for both parts");
     if ((int)blockIdx.x >= n_gblk) {
         const int c = blockIdx.x - n_gblk;
         const int p0 = c * kChunkItems, p1 = min(n_items, p0 + kChunkItems);
-        chunk_sums(d.glj_part, d.epart_stride, n_keys, p0, p1, d.cpart + (size_t)c * kChunkVals);
+        chunk_sums(d.glj_part, d.epart_stride, 2 * n_types * n_types, p0, p1,
+                   d.cpart + (size_t)c * kChunkVals);
+        __shared__ int s_last;
+        __threadfence();       // this block's chunk partials before its ticket
+        __syncthreads();
+        if (threadIdx.x == 0) s_last = (atomicAdd(d.queue + 3, 1) == n_chunks - 1);
+        __syncthreads();
+        if (s_last) {
+            __threadfence();   // every other block's partials after their tickets
+            glj_totals(d, glj, n_types, n_chunks, accumulate);
+            if (threadIdx.x == 0) atomicExch(d.queue + 3, 0);
+        }
         return;
     }
     const int cj = blockIdx.x * kRedWaves + (int)(threadIdx.x / kWave);
@@ -387,24 +419,9 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_bwd_step(NbDev d, float*
                        d.ipart, gx, gq, accumulate);
 }
 
-// Table gradient, stage 2: one thread per (type pair, c6/c12) adds the chunk partials in
-// order.  The table is symmetric, so the derivative with respect to the shared value of
-// [t1][t2] and [t2][t1] is split evenly between the two entries (independent of which
-// atom of a pair the kernel treats as i).
-__global__ void k_glj_final(NbDev d, double* __restrict__ out, int n_types, int n_chunks,
-                            int accumulate) {
-    const int n_keys = 2 * n_types * n_types;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_keys) return;
-    const int c = k & 1, t1 = (k >> 1) / n_types, t2 = (k >> 1) % n_types;
-    const int kt = 2 * (t2 * n_types + t1) + c;
-    double sk = 0.0, st = 0.0;
-    for (int q = 0; q < n_chunks; ++q) {
-        sk += d.cpart[(size_t)q * kChunkVals + k];
-        st += d.cpart[(size_t)q * kChunkVals + kt];
-    }
-    const double r = (kt != k) ? 0.5 * (sk + st) : sk;
-    out[k] = accumulate ? out[k] + r : r;
+// Table gradient totals when there is no item (all zero, or the outputs kept).
+__global__ void k_glj_final(NbDev d, double* __restrict__ out, int n_types, int accumulate) {
+    glj_totals(d, out, n_types, 0, accumulate);
 }
 
 inline int blocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
@@ -473,13 +490,13 @@ hipError_t launch_reduce_backward(const NbDev& d, float* grad_x, float* grad_q, 
                                   hipStream_t s) {
     const int n_cl = n_slots / kClusterSize;
     const int n_gblk = (grad_x || grad_q) ? blocks(n_cl, kRedWaves) : 0;
-    const int nk = 2 * n_types * n_types;
     const int n_chunks = grad_lj ? blocks(n_items, kChunkItems) : 0;
     if (n_gblk + n_chunks > 0)
         hipLaunchKernelGGL(k_reduce_bwd_step, dim3(n_gblk + n_chunks), dim3(kRedThreads), 0, s,
-                           d, grad_x, grad_q, accumulate ? 1 : 0, n_cl, n_gblk, nk, n_items);
-    if (grad_lj)
-        hipLaunchKernelGGL(k_glj_final, dim3(blocks(nk, 64)), dim3(64), 0, s, d, grad_lj,
-                           n_types, n_chunks, accumulate ? 1 : 0);
+                           d, grad_x, grad_q, grad_lj, accumulate ? 1 : 0, n_cl, n_gblk,
+                           n_types, n_items, n_chunks);
+    if (grad_lj && n_chunks == 0)
+        hipLaunchKernelGGL(k_glj_final, dim3(1), dim3(kRedThreads), 0, s, d, grad_lj, n_types,
+                           accumulate ? 1 : 0);
     return hipGetLastError();
 }

@@ -439,18 +439,60 @@ __device__ __forceinline__ void reduce_cluster(
 // needed: every atom has a slot after a grid build.
 
 
-// Force reduction and the first stage of the energy reduction in one launch: blocks
-// [0, n_fblk) reduce the forces of four clusters each (one wavefront per cluster), blocks
-// [n_fblk, n_fblk + n_chunks) sum one energy chunk each.
+// Per-system totals from the chunk partials, in chunk order: thread t of the block takes
+// the (system, value) pairs t, t + blockDim.x, ...  Values: E_LJ, E_C, the six virial
+// sums xx yy zz xy xz yz, pair count, raw pair count.
+__device__ inline void energy_totals(const NbDev& d, double* __restrict__ energy,
+                                     double* __restrict__ virial, uint32_t flags, int n_sys) {
+    const bool accum = flags & NB_F_ACCUMULATE;
+    for (int idx = threadIdx.x; idx < n_sys * kEpartStride; idx += blockDim.x) {
+        const int sys = idx / kEpartStride, k = idx % kEpartStride;
+        const int c0 = d.sys_chunk_start[sys], c1 = d.sys_chunk_start[sys + 1];
+        double t = 0.0;
+        for (int c = c0; c < c1; ++c) t += d.cpart[(size_t)c * kChunkVals + k];
+        if (k < 2) {
+            if ((flags & NB_F_ENERGY) && energy)
+                energy[2 * sys + k] = (accum ? energy[2 * sys + k] : 0.0) + t;
+        } else if (k < 8) {
+            // Xi = -1/2 sum d (x) f, symmetric; value k lands at these row-major positions
+            if ((flags & NB_F_VIRIAL) && virial) {
+                constexpr int q1[6] = {0, 4, 8, 1, 2, 5}, q2[6] = {-1, -1, -1, 3, 6, 7};
+                double* v = virial + 9 * sys;
+                v[q1[k - 2]] = (accum ? v[q1[k - 2]] : 0.0) - 0.5 * t;
+                if (q2[k - 2] >= 0) v[q2[k - 2]] = (accum ? v[q2[k - 2]] : 0.0) - 0.5 * t;
+            }
+        } else {
+            d.dstat[2 * sys + (k - 8)] = t;
+        }
+    }
+}
+
+// Force reduction and the energy reduction in one launch: blocks [0, n_fblk) reduce the
+// forces of four clusters each (one wavefront per cluster), blocks [n_fblk, n_fblk +
+// n_chunks) sum one energy chunk each; the last energy block to finish (a ticket in
+// queue[2], taken after a device-scope fence) adds the chunk partials per system and
+// resets the ticket for the next launch.
 __global__ __launch_bounds__(kRedThreads) void k_reduce_step(NbDev d, float* __restrict__ f,
                                                              int accumulate, int n_cl,
-                                                             int n_fblk) {
+                                                             int n_fblk, double* energy,
+                                                             double* virial, uint32_t flags,
+                                                             int n_sys) {
     static_assert(kRedThreads == kRedWaves * kWave, "one block shape for both parts");
     if ((int)blockIdx.x >= n_fblk) {
         const int c = blockIdx.x - n_fblk;
         const int4 ch = d.chunks[c];
         chunk_sums(d.epart, d.epart_stride, kEpartStride, ch.y, ch.z,
                    d.cpart + (size_t)c * kChunkVals);
+        __shared__ int s_last;
+        __threadfence();       // this block's chunk partials before its ticket
+        __syncthreads();
+        if (threadIdx.x == 0) s_last = (atomicAdd(d.queue + 2, 1) == d.n_chunks - 1);
+        __syncthreads();
+        if (s_last) {
+            __threadfence();   // every other block's partials after their tickets
+            energy_totals(d, energy, virial, flags, n_sys);
+            if (threadIdx.x == 0) atomicExch(d.queue + 2, 0);
+        }
         return;
     }
     const int cj = blockIdx.x * kRedWaves + (int)(threadIdx.x / kWave);
@@ -459,42 +501,15 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_step(NbDev d, float* __r
                    accumulate);
 }
 
-// One block per system: chunk partials in order, then energies, virial and pair counts.
+// Per-system totals when there is no chunk to reduce (no work items).
 __global__ void k_energy_final(NbDev d, double* __restrict__ energy, double* __restrict__ virial,
-                               uint32_t flags) {
-    const int sys = blockIdx.x;
-    const int c0 = d.sys_chunk_start[sys], c1 = d.sys_chunk_start[sys + 1];
-    __shared__ double s_out[kEpartStride];
-    const int k = threadIdx.x;
-    if (k < kEpartStride) {
-        double t = 0.0;
-        for (int c = c0; c < c1; ++c) t += d.cpart[(size_t)c * kChunkVals + k];
-        s_out[k] = t;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const double* out = s_out;
-        const bool accum = flags & NB_F_ACCUMULATE;
-        if ((flags & NB_F_ENERGY) && energy) {
-            energy[2 * sys] = (accum ? energy[2 * sys] : 0.0) + out[0];
-            energy[2 * sys + 1] = (accum ? energy[2 * sys + 1] : 0.0) + out[1];
-        }
-        if ((flags & NB_F_VIRIAL) && virial) {
-            // Xi = -1/2 sum d (x) f, symmetric: xx yy zz xy xz yz
-            const double v[9] = {out[2], out[5], out[6], out[5], out[3], out[7],
-                                 out[6], out[7], out[4]};
-            for (int q = 0; q < 9; ++q)
-                virial[9 * sys + q] = (accum ? virial[9 * sys + q] : 0.0) - 0.5 * v[q];
-        }
-        d.dstat[2 * sys] = out[8];
-        d.dstat[2 * sys + 1] = out[9];
-    }
+                               uint32_t flags, int n_sys) {
+    energy_totals(d, energy, virial, flags, n_sys);
 }
 
 inline int blocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
-// Resident blocks per CU of one flavor (queried once; the LJ table's LDS is small next
-// to the per-wave tables, so the first query holds for every table size).
+// Resident blocks per CU of one flavor.
 template <int COUL, bool E, bool V, bool P>
 int fwd_blocks_per_cu(size_t lds) {
     // resident blocks per CU of this kernel flavour for the last LJ-table size asked
@@ -589,13 +604,14 @@ hipError_t launch_reduce(const NbDev& d, float* f, bool accumulate, int n_slots,
                         hipStream_t s) {
     const int n_cl = n_slots / kClusterSize;
     const int n_fblk = blocks(n_cl, kRedWaves);
-    const int n_eblk = (flags & (NB_F_ENERGY | NB_F_VIRIAL)) ? d.n_chunks : 0;
+    const bool ev = (flags & (NB_F_ENERGY | NB_F_VIRIAL)) && n_sys > 0;
+    const int n_eblk = ev ? d.n_chunks : 0;
     if (n_fblk + n_eblk > 0)
         hipLaunchKernelGGL(k_reduce_step, dim3(n_fblk + n_eblk), dim3(kRedThreads), 0, s, d, f,
-                           accumulate ? 1 : 0, n_cl, n_fblk);
-    if ((flags & (NB_F_ENERGY | NB_F_VIRIAL)) && n_sys > 0)
-        hipLaunchKernelGGL(k_energy_final, dim3(n_sys), dim3(kWave), 0, s, d, energy, virial,
-                           flags);
+                           accumulate ? 1 : 0, n_cl, n_fblk, energy, virial, flags, n_sys);
+    if (ev && n_eblk == 0)
+        hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kRedThreads), 0, s, d, energy, virial,
+                           flags, n_sys);
     return hipGetLastError();
 }
 

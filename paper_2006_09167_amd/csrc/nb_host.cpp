@@ -137,8 +137,8 @@ nb_status ensure_device(nb_ctx* c) {
     NB_HIP(c, dev_alloc(d.sys, c->n_sys));
     NB_HIP(c, dev_alloc(d.sys_sc_start, c->n_sys + 1));
     NB_HIP(c, dev_alloc(d.part_start, c->p.nstprune + 1));
-    NB_HIP(c, dev_alloc(d.queue, 2));
-    NB_HIP(c, launch_fill(d.queue, 2, 0, c->stream));
+    NB_HIP(c, dev_alloc(d.queue, 4));
+    NB_HIP(c, launch_fill(d.queue, 4, 0, c->stream));
     int n_cu = 0;
     NB_HIP(c, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
     d.n_cu = n_cu;

@@ -183,8 +183,9 @@ struct NbDev {
     NbItem* items = nullptr;           // [item_cap]
     int32_t* item_cost = nullptr;      // [item_cap] set outer-mask bits per item
     int32_t* item_order = nullptr;     // [item_cap] items by decreasing cost (queue order)
-    int32_t* queue = nullptr;          // [2] item counter, finished wavefronts (kept zero
-                                       //     between launches by the kernel itself)
+    int32_t* queue = nullptr;          // [4] item counter, finished wavefronts, finished
+                                       //     energy-chunk blocks, unused (kept zero between
+                                       //     launches by the kernels themselves)
     int32_t* part_start = nullptr;     // [nstprune+1] item ranges per rolling part
     uint64_t* excl_rows = nullptr;     // [entry_cap][8]
     int32_t* jseg_count = nullptr;     // [8 n_sc_max]
