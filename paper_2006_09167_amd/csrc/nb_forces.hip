@@ -1,22 +1,17 @@
-// Cluster-pair force / energy kernel (Sec. V.A) and the reductions around it.
+// Cluster-pair force / energy kernel (Sec. V.A).
 //
 // One wavefront processes one work item: a chunk of one super-cluster's joint j-list.
 // Lane l holds the pair (i-atom ii = l & 7, j-atom jj = l >> 3) of the current 8x8
-// cluster pair.  The eight i-clusters' coordinates, charges, types and force
-// accumulators stay in registers for the whole item; per j-entry the loop over the
-// set bits of the interaction mask is uniform (scalar branches, no divergence), the
-// interaction, exclusion and cut-off masks are 64-bit scalar masks applied with one
-// select, and the j-forces are reduced over the eight i-lanes with DPP adds and stored
-// once per entry into the entry's own partial slot (Newton's third law: each pair once).
-// Energies are summed per entry in single precision and accumulated in double.
-//
-// No atomics: every partial has one writer.  A second pass adds, per atom, the
-// j-partials of the entries that reference its cluster (consecutive by construction)
-// and the i-partials of its super-cluster's items with compensated (Neumaier)
-// single-precision sums, and writes the force in the caller's atom order.
+// cluster pair.  The super-cluster's 64 i-atoms sit in a per-wavefront LDS table and the
+// eight i-clusters' force accumulators in registers for the whole item; per j-entry the
+// loop over the set bits of the interaction mask is uniform (scalar branches, no
+// divergence), the interaction, exclusion and cut-off masks are 64-bit scalar masks, and
+// the j-forces are reduced over the eight i-lanes with DPP adds and stored once per entry
+// into the entry's own partial slot (Newton's third law: each pair once).  Energies are
+// summed per entry in single precision and accumulated in double.  No atomics: every
+// partial has one writer; nb_reduce.hip adds them up.
 #include <algorithm>
 
-#include "nb_chunk_sums.h"
 #include "nb_internal.h"
 #include "nb_pair_common.h"
 
@@ -345,168 +340,6 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
 #undef NB_ITEM_ARGS
 }
 
-// Per-slot gather of user-order coordinates (and charges) into slot order, wrapped with
-// the image offsets of the last grid build in the same sequence as the build.
-__global__ void k_gather(NbDev d, const float* __restrict__ x, const float* __restrict__ q,
-                         float4* __restrict__ out, int n_slots) {
-#pragma clang fp contract(off)
-    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= n_slots) return;
-    const int a = d.slot_atom[slot];
-    // Empty slots (charge 0) sit on the lattice -D (1 + i, 1 + j, 1 + k) with spacing
-    // D = max box edge + 2 rlist + 1 nm and (i, j, k) the slot's base-1024 digits.  Any
-    // pair with an empty slot is then at least 2 rlist + 1 nm apart on some axis under
-    // every periodic shift s L (|s| <= 1), and an empty slot and its own image |s L| apart:
-    // with box edges up to 1000 nm the coordinates stay below 1025 D < 1.1e6 nm, where one
-    // ulp is at most 0.125 nm.  No distance test with an empty slot passes, so the pair
-    // kernels need no valid-atom masks.
-    const float D = d.filler_d;
-    float4 v = make_float4(-D * (float)(1 + (slot & 1023)), -D * (float)(1 + ((slot >> 10) & 1023)),
-                           -D * (float)(1 + (slot >> 20)), 0.f);
-    if (a >= 0) {
-        const int4 k = d.img[a];
-        const NbSys S = d.sys[d.atom_sys[a]];
-        const float kx = (float)k.x * S.L[0], ky = (float)k.y * S.L[1], kz = (float)k.z * S.L[2];
-        v.x = x[3 * a] - kx;
-        v.y = x[3 * a + 1] - ky;
-        v.z = x[3 * a + 2] - kz;
-        v.w = q ? q[a] : 0.f;
-    }
-    out[slot] = v;
-}
-
-__device__ inline void neumaier(float& s, float& c, float v) {
-    const float t = s + v;
-    c += (fabsf(s) >= fabsf(v)) ? ((s - t) + v) : ((v - t) + s);
-    s = t;
-}
-
-// One wavefront per cluster: lane (k0 = l >> 3, jj = l & 7) sums, with compensation, the
-// j-partials k0, k0 + 8, ... of the entries referencing the cluster (contiguous, 1 KB per
-// step), the eight k0-lanes are combined in a fixed butterfly order, and lanes 0..7 add
-// the super-cluster's i-partials and write the atom's force in the caller's order.
-constexpr int kRedWaves = 4;
-__device__ __forceinline__ void reduce_cluster(
-    const int cj, const int32_t* __restrict__ slot_atom, const int32_t* __restrict__ jseg_start,
-    const float4* __restrict__ jpart, const int32_t* __restrict__ sc_istart,
-    const int32_t* __restrict__ sc_icount, const float4* __restrict__ ipart,
-    float* __restrict__ f, int accumulate) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int jj = lane & 7, k0 = lane >> 3;
-    float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
-    const int s0 = jseg_start[cj], s1 = jseg_start[cj + 1];
-#pragma unroll 8
-    for (int k = s0 + k0; k < s1; k += 8) {
-        const float4 v = jpart[(size_t)k * kClusterSize + jj];
-        neumaier(sx, cx, v.x);
-        neumaier(sy, cy, v.y);
-        neumaier(sz, cz, v.z);
-    }
-    for (int off = 8; off < kWave; off <<= 1) {   // combine (sum, compensation) pairs
-        const float px = __shfl_xor(sx, off), py = __shfl_xor(sy, off), pz = __shfl_xor(sz, off);
-        const float qx = __shfl_xor(cx, off), qy = __shfl_xor(cy, off), qz = __shfl_xor(cz, off);
-        neumaier(sx, cx, px);
-        neumaier(sy, cy, py);
-        neumaier(sz, cz, pz);
-        cx += qx;
-        cy += qy;
-        cz += qz;
-    }
-    if (k0 != 0) return;
-    const int slot = cj * kClusterSize + jj;
-    const int a = slot_atom[slot];
-    const int sc = cj >> 3, loc = slot & (kScAtoms - 1);
-    const int i0 = sc_istart[sc], i1 = i0 + sc_icount[sc];
-    for (int i = i0; i < i1; ++i) {
-        const float4 v = ipart[(size_t)i * kScAtoms + loc];
-        neumaier(sx, cx, v.x);
-        neumaier(sy, cy, v.y);
-        neumaier(sz, cz, v.z);
-    }
-    if (a < 0) return;
-    float rx = sx + cx, ry = sy + cy, rz = sz + cz;
-    if (accumulate) {
-        rx += f[3 * a];
-        ry += f[3 * a + 1];
-        rz += f[3 * a + 2];
-    }
-    f[3 * a] = rx;
-    f[3 * a + 1] = ry;
-    f[3 * a + 2] = rz;
-}
-
-// Zero forces of atoms that no slot covers (only possible for an empty grid) is not
-// needed: every atom has a slot after a grid build.
-
-
-// Per-system totals from the chunk partials, in chunk order: thread t of the block takes
-// the (system, value) pairs t, t + blockDim.x, ...  Values: E_LJ, E_C, the six virial
-// sums xx yy zz xy xz yz, pair count, raw pair count.
-__device__ inline void energy_totals(const NbDev& d, double* __restrict__ energy,
-                                     double* __restrict__ virial, uint32_t flags, int n_sys) {
-    const bool accum = flags & NB_F_ACCUMULATE;
-    for (int idx = threadIdx.x; idx < n_sys * kEpartStride; idx += blockDim.x) {
-        const int sys = idx / kEpartStride, k = idx % kEpartStride;
-        const int c0 = d.sys_chunk_start[sys], c1 = d.sys_chunk_start[sys + 1];
-        double t = 0.0;
-        for (int c = c0; c < c1; ++c) t += d.cpart[(size_t)c * kChunkVals + k];
-        if (k < 2) {
-            if ((flags & NB_F_ENERGY) && energy)
-                energy[2 * sys + k] = (accum ? energy[2 * sys + k] : 0.0) + t;
-        } else if (k < 8) {
-            // Xi = -1/2 sum d (x) f, symmetric; value k lands at these row-major positions
-            if ((flags & NB_F_VIRIAL) && virial) {
-                constexpr int q1[6] = {0, 4, 8, 1, 2, 5}, q2[6] = {-1, -1, -1, 3, 6, 7};
-                double* v = virial + 9 * sys;
-                v[q1[k - 2]] = (accum ? v[q1[k - 2]] : 0.0) - 0.5 * t;
-                if (q2[k - 2] >= 0) v[q2[k - 2]] = (accum ? v[q2[k - 2]] : 0.0) - 0.5 * t;
-            }
-        } else {
-            d.dstat[2 * sys + (k - 8)] = t;
-        }
-    }
-}
-
-// Force reduction and the energy reduction in one launch: blocks [0, n_fblk) reduce the
-// forces of four clusters each (one wavefront per cluster), blocks [n_fblk, n_fblk +
-// n_chunks) sum one energy chunk each; the last energy block to finish (a ticket in
-// queue[2], taken after a device-scope fence) adds the chunk partials per system and
-// resets the ticket for the next launch.
-__global__ __launch_bounds__(kRedThreads) void k_reduce_step(NbDev d, float* __restrict__ f,
-                                                             int accumulate, int n_cl,
-                                                             int n_fblk, double* energy,
-                                                             double* virial, uint32_t flags,
-                                                             int n_sys) {
-    static_assert(kRedThreads == kRedWaves * kWave, "one block shape for both parts");
-    if ((int)blockIdx.x >= n_fblk) {
-        const int c = blockIdx.x - n_fblk;
-        const int4 ch = d.chunks[c];
-        chunk_sums(d.epart, d.epart_stride, kEpartStride, ch.y, ch.z,
-                   d.cpart + (size_t)c * kChunkVals);
-        __shared__ int s_last;
-        __threadfence();       // this block's chunk partials before its ticket
-        __syncthreads();
-        if (threadIdx.x == 0) s_last = (atomicAdd(d.queue + 2, 1) == d.n_chunks - 1);
-        __syncthreads();
-        if (s_last) {
-            __threadfence();   // every other block's partials after their tickets
-            energy_totals(d, energy, virial, flags, n_sys);
-            if (threadIdx.x == 0) atomicExch(d.queue + 2, 0);
-        }
-        return;
-    }
-    const int cj = blockIdx.x * kRedWaves + (int)(threadIdx.x / kWave);
-    if (cj >= n_cl) return;
-    reduce_cluster(cj, d.slot_atom, d.jseg_start, d.jpart, d.sc_istart, d.sc_icount, d.ipart, f,
-                   accumulate);
-}
-
-// Per-system totals when there is no chunk to reduce (no work items).
-__global__ void k_energy_final(NbDev d, double* __restrict__ energy, double* __restrict__ virial,
-                               uint32_t flags, int n_sys) {
-    energy_totals(d, energy, virial, flags, n_sys);
-}
-
 inline int blocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 // Resident blocks per CU of one flavor.
@@ -574,14 +407,6 @@ hipError_t prepare_forces(int coulomb, uint32_t flags, bool prune, int n_types,
     return hipGetLastError();
 }
 
-hipError_t launch_gather(const NbDev& d, const float* x, const float* q, float4* out,
-                         int n_slots, hipStream_t s) {
-    if (n_slots > 0)
-        hipLaunchKernelGGL(k_gather, dim3(blocks(n_slots, 256)), dim3(256), 0, s, d, x, q, out,
-                           n_slots);
-    return hipGetLastError();
-}
-
 hipError_t launch_forces(const NbDev& d, const NbKParams& kp, int coulomb, uint32_t flags,
                          const float* lj, int n_items, int prune_i0, int prune_i1,
                          float r2_inner, int mode, hipStream_t s) {
@@ -599,19 +424,4 @@ hipError_t launch_forces(const NbDev& d, const NbKParams& kp, int coulomb, uint3
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const NbDev& d, float* f, bool accumulate, int n_slots,
-                        double* energy, double* virial, uint32_t flags, int n_sys,
-                        hipStream_t s) {
-    const int n_cl = n_slots / kClusterSize;
-    const int n_fblk = blocks(n_cl, kRedWaves);
-    const bool ev = (flags & (NB_F_ENERGY | NB_F_VIRIAL)) && n_sys > 0;
-    const int n_eblk = ev ? d.n_chunks : 0;
-    if (n_fblk + n_eblk > 0)
-        hipLaunchKernelGGL(k_reduce_step, dim3(n_fblk + n_eblk), dim3(kRedThreads), 0, s, d, f,
-                           accumulate ? 1 : 0, n_cl, n_fblk, energy, virial, flags, n_sys);
-    if (ev && n_eblk == 0)
-        hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kRedThreads), 0, s, d, energy, virial,
-                           flags, n_sys);
-    return hipGetLastError();
-}
 
