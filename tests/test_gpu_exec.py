@@ -142,16 +142,19 @@ def test_autotune_keeps_fastest_and_stays_exact(sys3k):
     assert ctx.get_exec()["item_width"] == best["item_width"]
 
 
-@pytest.mark.parametrize("mode", ["static", "queue", "persist"])
-def test_graph_step_replays_match_eager(sys3k, mode):
+@pytest.mark.parametrize("mode,fused", [("static", True), ("queue", True), ("persist", True),
+                                        ("static", False), ("queue", False),
+                                        ("persist", False)])
+def test_graph_step_replays_match_eager(sys3k, mode, fused):
     """nb_step_graph over two list lifetimes with positions updated in place: every replay
-    (with eager work and synchronisation in between) equals the eager nb_step bitwise."""
+    (with eager work and synchronisation in between) equals the eager nb_step bitwise,
+    with the rolling prune fused into the pair kernel or as its own kernel."""
     c = concat(sys3k)
     kw = dict(nstlist=8, nstprune=4, **EWALD)
     ctx_g, _ = built(c, **kw)
     ctx_e, _ = built(c, **kw)
-    ctx_g.set_exec(0, mode)
-    ctx_e.set_exec(0, mode)
+    ctx_g.set_exec(0, mode, prune_fused=fused)
+    ctx_e.set_exec(0, mode, prune_fused=fused)
     q, lj = dev(c["q"]), dev(c["lj"])
     xg = dev(c["x"])                                   # fixed addresses for the graph
     fg = torch.empty_like(xg)
