@@ -212,7 +212,7 @@ __device__ __forceinline__ void bwd_item(
         ajy = dpp_sum8(ajy);
         ajz = dpp_sum8(ajz);
         ajq = dpp_sum8(ajq);
-        jp[jj] = make_float4(ajx, ajy, ajz, ajq);   // the same sums in all eight lanes
+        store_stream(&jp[jj], ajx, ajy, ajz, ajq);   // the same sums in all eight lanes
     }
     float4* ip = ipart + (size_t)item * kScAtoms;
 #define NB_IRED(c)                                                                     \
@@ -223,7 +223,7 @@ __device__ __forceinline__ void bwd_item(
         aq##c += __shfl_xor(aq##c, off);                                               \
     }                                                                                  \
     if (jj == 0)                                                                       \
-        ip[kClusterSize * c + ii] = make_float4(ax##c, ay##c, az##c, aq##c * kp.epsfac_r);
+        store_stream(&ip[kClusterSize * c + ii], ax##c, ay##c, az##c, aq##c * kp.epsfac_r);
     NB_FOR8(NB_IRED)
 #undef NB_IRED
     if (LJGRAD) {

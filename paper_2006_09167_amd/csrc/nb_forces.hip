@@ -220,7 +220,7 @@ __device__ __forceinline__ void fwd_item(
         fjz = dpp_sum8(fjz);
         // every lane of a row holds the same sums: all eight store them (one 128-byte line
         // per entry), which keeps the last DPP step fused with its add
-        jp[jj] = make_float4(fjx, fjy, fjz, 0.f);
+        store_stream(&jp[jj], fjx, fjy, fjz, 0.f);
         if (ENERGY) {
             elj_acc += (double)elj;
             ec_acc += (COUL == NB_COUL_RF) ? (double)ec + (double)eclo : (double)ec;
@@ -238,7 +238,7 @@ __device__ __forceinline__ void fwd_item(
         fy##c += __shfl_xor(fy##c, off);                                               \
         fz##c += __shfl_xor(fz##c, off);                                               \
     }                                                                                  \
-    if (jj == 0) ip[kClusterSize * c + ii] = make_float4(fx##c, fy##c, fz##c, 0.f);
+    if (jj == 0) store_stream(&ip[kClusterSize * c + ii], fx##c, fy##c, fz##c, 0.f);
     NB_FOR8(NB_IRED)
 #undef NB_IRED
     if (ENERGY || VIRIAL) {
