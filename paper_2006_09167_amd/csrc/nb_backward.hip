@@ -313,8 +313,9 @@ __device__ inline void neumaier(float& s, float& c, float v) {
 }
 
 // One wavefront per cluster, as the force reduction: lanes (k0, jj) sum the j-partials
-// k0, k0 + 8, ... with compensation, a fixed butterfly combines the k0-lanes, and lanes
-// 0..7 add the i-partials and write dL/dx and dL/dq in the caller's atom order.
+// k0, k0 + 8, ... and the i-partials of items k0, k0 + 8, ... with compensation, a fixed
+// butterfly combines the k0-lanes, and lanes 0..7 write dL/dx and dL/dq in the caller's
+// atom order.
 constexpr int kRedWaves = 4;
 __device__ inline void reduce_bwd_cluster(
     int cj, const int32_t* __restrict__ slot_atom, const int32_t* __restrict__ jseg_start,
@@ -323,11 +324,22 @@ __device__ inline void reduce_bwd_cluster(
     float* __restrict__ gx, float* __restrict__ gq, int accumulate) {
     const int lane = threadIdx.x & (kWave - 1);
     const int jj = lane & 7, k0 = lane >> 3;
-    float s[4] = {0, 0, 0, 0}, cmp[4] = {0, 0, 0, 0};
+    const int slot = cj * kClusterSize + jj;
+    const int sc = cj >> 3, loc = slot & (kScAtoms - 1);
     const int s0 = jseg_start[cj], s1 = jseg_start[cj + 1];
+    const int i0 = sc_istart[sc], i1 = i0 + sc_icount[sc];
+    float s[4] = {0, 0, 0, 0}, cmp[4] = {0, 0, 0, 0};
 #pragma unroll 4
     for (int k = s0 + k0; k < s1; k += 8) {
         const float4 v = jpart[(size_t)k * kClusterSize + jj];
+        neumaier(s[0], cmp[0], v.x);
+        neumaier(s[1], cmp[1], v.y);
+        neumaier(s[2], cmp[2], v.z);
+        neumaier(s[3], cmp[3], v.w);
+    }
+#pragma unroll 2
+    for (int i = i0 + k0; i < i1; i += 8) {
+        const float4 v = ipart[(size_t)i * kScAtoms + loc];
         neumaier(s[0], cmp[0], v.x);
         neumaier(s[1], cmp[1], v.y);
         neumaier(s[2], cmp[2], v.z);
@@ -342,17 +354,7 @@ __device__ inline void reduce_bwd_cluster(
         }
     }
     if (k0 != 0) return;
-    const int slot = cj * kClusterSize + jj;
     const int a = slot_atom[slot];
-    const int sc = cj >> 3, loc = slot & (kScAtoms - 1);
-    const int i0 = sc_istart[sc], i1 = i0 + sc_icount[sc];
-    for (int i = i0; i < i1; ++i) {
-        const float4 v = ipart[(size_t)i * kScAtoms + loc];
-        neumaier(s[0], cmp[0], v.x);
-        neumaier(s[1], cmp[1], v.y);
-        neumaier(s[2], cmp[2], v.z);
-        neumaier(s[3], cmp[3], v.w);
-    }
     if (a < 0) return;
     if (gx) {
         for (int k = 0; k < 3; ++k) {

@@ -46,8 +46,9 @@ __device__ inline void neumaier(float& s, float& c, float v) {
 
 // One wavefront per cluster: lane (k0 = l >> 3, jj = l & 7) sums, with compensation, the
 // j-partials k0, k0 + 8, ... of the entries referencing the cluster (contiguous, 1 KB per
-// step), the eight k0-lanes are combined in a fixed butterfly order, and lanes 0..7 add
-// the super-cluster's i-partials and write the atom's force in the caller's order.
+// step) and the i-partials of the super-cluster's items k0, k0 + 8, ...; the eight
+// k0-lanes are combined in a fixed butterfly order and lanes 0..7 write the atom's force
+// in the caller's order.
 constexpr int kRedWaves = 4;
 __device__ __forceinline__ void reduce_cluster(
     const int cj, const int32_t* __restrict__ slot_atom, const int32_t* __restrict__ jseg_start,
@@ -56,11 +57,23 @@ __device__ __forceinline__ void reduce_cluster(
     float* __restrict__ f, int accumulate) {
     const int lane = threadIdx.x & (kWave - 1);
     const int jj = lane & 7, k0 = lane >> 3;
-    float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+    const int slot = cj * kClusterSize + jj;
+    const int sc = cj >> 3, loc = slot & (kScAtoms - 1);
     const int s0 = jseg_start[cj], s1 = jseg_start[cj + 1];
+    const int i0 = sc_istart[sc], i1 = i0 + sc_icount[sc];
+    float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+    // lane (k0, jj): j-partials k0, k0 + 8, ... of the segment, then i-partials of the
+    // super-cluster's items i0 + k0, i0 + k0 + 8, ... (all loads independent)
 #pragma unroll 8
     for (int k = s0 + k0; k < s1; k += 8) {
         const float4 v = jpart[(size_t)k * kClusterSize + jj];
+        neumaier(sx, cx, v.x);
+        neumaier(sy, cy, v.y);
+        neumaier(sz, cz, v.z);
+    }
+#pragma unroll 2
+    for (int i = i0 + k0; i < i1; i += 8) {
+        const float4 v = ipart[(size_t)i * kScAtoms + loc];
         neumaier(sx, cx, v.x);
         neumaier(sy, cy, v.y);
         neumaier(sz, cz, v.z);
@@ -76,16 +89,7 @@ __device__ __forceinline__ void reduce_cluster(
         cz += qz;
     }
     if (k0 != 0) return;
-    const int slot = cj * kClusterSize + jj;
     const int a = slot_atom[slot];
-    const int sc = cj >> 3, loc = slot & (kScAtoms - 1);
-    const int i0 = sc_istart[sc], i1 = i0 + sc_icount[sc];
-    for (int i = i0; i < i1; ++i) {
-        const float4 v = ipart[(size_t)i * kScAtoms + loc];
-        neumaier(sx, cx, v.x);
-        neumaier(sy, cy, v.y);
-        neumaier(sz, cz, v.z);
-    }
     if (a < 0) return;
     float rx = sx + cx, ry = sy + cy, rz = sz + cz;
     if (accumulate) {
@@ -97,10 +101,6 @@ __device__ __forceinline__ void reduce_cluster(
     f[3 * a + 1] = ry;
     f[3 * a + 2] = rz;
 }
-
-// Zero forces of atoms that no slot covers (only possible for an empty grid) is not
-// needed: every atom has a slot after a grid build.
-
 
 // Per-system totals from the chunk partials, in chunk order: thread t of the block takes
 // the (system, value) pairs t, t + blockDim.x, ...  Values: E_LJ, E_C, the six virial
