@@ -376,27 +376,40 @@ __global__ __launch_bounds__(kPruneWaves * kWave) void k_prune(
             xj2 = xp[kClusterSize * ent2.cj + jj];
         }
         const int code = ent.meta & 31u;
-        const int sx = shift_x(code), sy = shift_y(code), sz = shift_z(code);
         const uint32_t omask = (ent.meta >> 8) & 0xffu;
-        const int dc = (code == kShiftZero) ? ent.cj - ci0 : -1;
-        // the same separation as the list build: x_i - L for s > 0, x_j - L for s < 0
-        xj.x -= (sx < 0) ? S.L[0] : 0.f;
-        xj.y -= (sy < 0) ? S.L[1] : 0.f;
-        xj.z -= (sz < 0) ? S.L[2] : 0.f;
-        const float ox = (sx > 0) ? S.L[0] : 0.f, oy = (sy > 0) ? S.L[1] : 0.f,
-                    oz = (sz > 0) ? S.L[2] : 0.f;
         uint32_t imask = 0;
+        if (code == kShiftZero) {
+            // no shift: x_i - x_j, the same bits as the general sequence with zero shifts
+            const int dc = ent.cj - ci0;
 #define NB_PB(c)                                                                       \
-        if ((omask >> c) & 1u) {                                                       \
-            const float dx = (xi##c.x - ox) - xj.x;                                    \
-            const float dy = (xi##c.y - oy) - xj.y;                                    \
-            const float dz = (xi##c.z - oz) - xj.z;                                    \
-            const float r2 = (dx * dx + dy * dy) + dz * dz;                            \
-            const uint64_t m = (dc == c) ? 0x7f3f1f0f07030100ull : ~0ull;              \
-            if (__builtin_amdgcn_ballot_w64(r2 < r2_inner) & m) imask |= 1u << c;      \
-        }
-        NB_FOR8(NB_PB)
+            if ((omask >> c) & 1u) {                                                   \
+                const float dx = xi##c.x - xj.x, dy = xi##c.y - xj.y, dz = xi##c.z - xj.z; \
+                const float r2 = (dx * dx + dy * dy) + dz * dz;                        \
+                const uint64_t m = (dc == c) ? 0x7f3f1f0f07030100ull : ~0ull;          \
+                if (__builtin_amdgcn_ballot_w64(r2 < r2_inner) & m) imask |= 1u << c;  \
+            }
+            NB_FOR8(NB_PB)
 #undef NB_PB
+        } else {
+            // the same separation as the list build: x_i - L for s > 0, x_j - L for s < 0
+            // (a shifted entry keeps all 64 pairs, an atom and its own image included)
+            const int sx = shift_x(code), sy = shift_y(code), sz = shift_z(code);
+            xj.x -= (sx < 0) ? S.L[0] : 0.f;
+            xj.y -= (sy < 0) ? S.L[1] : 0.f;
+            xj.z -= (sz < 0) ? S.L[2] : 0.f;
+            const float ox = (sx > 0) ? S.L[0] : 0.f, oy = (sy > 0) ? S.L[1] : 0.f,
+                        oz = (sz > 0) ? S.L[2] : 0.f;
+#define NB_PB(c)                                                                       \
+            if ((omask >> c) & 1u) {                                                   \
+                const float dx = (xi##c.x - ox) - xj.x;                                \
+                const float dy = (xi##c.y - oy) - xj.y;                                \
+                const float dz = (xi##c.z - oz) - xj.z;                                \
+                const float r2 = (dx * dx + dy * dy) + dz * dz;                        \
+                if (__builtin_amdgcn_ballot_w64(r2 < r2_inner)) imask |= 1u << c;      \
+            }
+            NB_FOR8(NB_PB)
+#undef NB_PB
+        }
         if (lane == 0) entries[e].meta = (ent.meta & ~(0xffu << 16)) | (imask << 16);
     }
 }
