@@ -252,7 +252,7 @@ __device__ __forceinline__ void bwd_item(
 // the device once, taking items in rounds of the most-work-first order as the forward
 // kernel's persistent mode does.
 template <int COUL, bool LJGRAD, bool PRIV>
-__global__ __launch_bounds__(kBwdThreads) void k_nb_bwd(
+__global__ __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_nb_bwd(
     const NbItem* __restrict__ items, const NbEntry* __restrict__ entries,
     const uint64_t* __restrict__ excl_rows, const float4* __restrict__ xq,
     const float4* __restrict__ gslot, const int32_t* __restrict__ type_slot,
