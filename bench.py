@@ -40,6 +40,8 @@ PEAK_FP32_NONPACKED = 78.6e12 # without packed FP32 (one FMA per lane per cycle)
 #   RF:     force 5, energies 14 (V_C 4, its constants' residual term 3, V_LJ 4,
 #           3 sums)                                                         => 44
 FLOP_PER_PAIR = {"ewald": 62, "rf": 44}
+# Lennard-Jones alone, forces only (the argon sweep): common 25 (no q_i q_j), F/r 1 => 25
+FLOP_PER_PAIR_LJ_FORCE = 25
 # Backward pass per evaluated pair slot (same counting, with the table gradient):
 #   separation 3, r^2 5, rsqrt 1, r^-2 1, r^-6 and 12 c12 r^-6 3, phi_LJ 3, phi'_LJ/r 6,
 #   q_i q_j 1, phi_C 1, G_i - G_j 3, u 5, phi 1, coefficient of d 7, h 9, w 3,
@@ -57,6 +59,9 @@ WORKLOADS = {
                         "Ewald real space beta=2.60/nm rc=1.2 nm, rlist=1.3 nm every 80 "
                         "steps, rinner=1.24 nm rolling prune in 4 parts, Gaussian steps "
                         "0.002 nm",
+    "argon157k_sweep": "157,464-atom Lennard-Jones argon box (rho = 26/nm^3, sigma = 0.3345 nm, "
+                       "18.2 nm cube), cut-off swept so that 50 ... 3000 particles fall in the "
+                       "half cut-off sphere, outer list rc + 0.1 nm, force-only evaluations",
     "ensemble256_rf": "256 independent water-like replicas of 3k-24k atoms (log-uniform, "
                       "2.63M atoms in all, density 100/nm^3) in one context, reaction field "
                       "rc=0.9 nm, rlist=1.0 nm every 100 steps, rinner=0.94 nm rolling prune "
@@ -165,6 +170,112 @@ def cpu_baseline(c, cfg, x_np, budget_s=8.0):
                                     "box (all partners of each)"), [(sel, None, F)]
 
 
+def argon_sweep(args):
+    """The paper's kernel-throughput experiment (Fig. 6): LJ argon, force-only evaluations
+    of a frozen list for each cut-off of the sweep; raw (computed pair slots) and effective
+    (pairs inside the cut-off) pair interactions per second."""
+    import numpy as np
+    import torch
+    from paper_2006_09167_amd import systems
+    from paper_2006_09167_amd.api import Context
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    s = systems.argon_box()
+    N = s.n
+    x = torch.from_numpy(s.x).to(dev)
+    q = torch.zeros(N, dtype=torch.float32, device=dev)
+    lj = torch.from_numpy(s.lj).to(dev)
+    f = torch.empty((N, 3), dtype=torch.float32, device=dev)
+    K = args.steps if args.steps is not None else 50
+    W = min(args.warmup, 10)
+    points, best = [], None
+    for n_half in systems.ARGON["n_half"]:
+        rc = systems.argon_cutoff(n_half)
+        rlist = rc + systems.ARGON["buffer"]
+        ctx = Context(n_types=1, coulomb="none", rc=rc, rinner=rlist, rlist=rlist,
+                      atom_offsets=[0, N], device=dev)
+        ctx.set_topology(s.type, s.excl_ptr, s.excl_idx)
+        ctx.grid_build(x, s.box[None])
+        ctx.pairlist_build()
+        if args.exec == "auto":
+            tuned, _ = ctx.autotune(x, q, lj, energy=False, repeats=3)
+        else:
+            ctx.set_exec(args.item_width, args.exec)
+        ctx.forces(x, q, lj, energy=True, f=f)          # pair counts of this list
+        st = ctx.stats()
+        for _ in range(W):
+            ctx.forces(x, q, lj, energy=False, f=f)
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(K):
+            ctx.forces(x, q, lj, energy=False, f=f)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / K
+        tm = ctx.get_timing()
+        ctx.set_timing(False)
+        kern = tm["forces"][0] * 1e-3 / max(tm["forces"][1], 1)
+        eff, raw = float(st["effective_pairs"]), float(st["computed_pairs"])
+        pt = {"n_half": n_half, "rc": round(rc, 4), "rlist": round(rlist, 4),
+              "list_entries": int(st["n_entries"]), "exec": ctx.get_exec(),
+              "effective_pairs": eff, "raw_pairs": raw, "ms_per_eval": 1e3 * wall,
+              "kernel_us": 1e6 * kern, "effective_pairs_per_s": eff / wall,
+              "raw_pairs_per_s": raw / wall, "kernel_raw_pairs_per_s": raw / kern,
+              "kernel_frac_of_peak": raw * FLOP_PER_PAIR_LJ_FORCE / kern / PEAK_FP32}
+        log("n_half %4d rc %.3f: %.3f ms/eval, effective %.3g /s, raw %.3g /s (kernel %.1f us)"
+            % (n_half, rc, 1e3 * wall, eff / wall, raw / wall, 1e6 * kern))
+        points.append(pt)
+        if best is None or pt["effective_pairs_per_s"] > best["effective_pairs_per_s"]:
+            best = pt
+        del ctx
+    result = {
+        "metric": "pair interactions/s (effective, LJ argon 157k, best point of the cut-off "
+                  "sweep)",
+        "value": best["effective_pairs_per_s"],
+        "unit": "pair interactions/s",
+        "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": best["ms_per_eval"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]),
+                   "atoms": N, "best_n_half": best["n_half"]},
+        "sweep": points,
+        "roofline": {"bound": "alu", "kernel": "k_nb_fwd<LJ only, forces>",
+                     "flop_per_pair": FLOP_PER_PAIR_LJ_FORCE,
+                     "achieved": best["kernel_raw_pairs_per_s"] * FLOP_PER_PAIR_LJ_FORCE / 1e12,
+                     "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                     "frac": best["kernel_frac_of_peak"], "traffic": None,
+                     "avg_launch_us": best["kernel_us"]},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        pt = next(p for p in points if p["n_half"] == 200)
+        p = oracle.params("rf", rc=pt["rc"])                       # all charges zero
+        rng = np.random.default_rng(7)
+        sel = np.sort(rng.choice(N, size=8192, replace=False))
+        t0 = time.perf_counter()
+        F = oracle.forces_on(sel, s.x, s.q, s.type, s.lj, s.excl_ptr, s.excl_idx, s.box, p)
+        dt = time.perf_counter() - t0
+        # the sampled atoms' pairs: 2 * 8192 / N of the effective pairs of that cut-off
+        result["cpu_baseline"] = {"value": pt["effective_pairs"] * 2.0 * sel.size / N / dt,
+                                  "unit": "pair interactions/s", "cores": oracle.num_threads(),
+                                  "kind": "oracle",
+                                  "sample": "FP64 brute-force forces on 8192 seeded atoms "
+                                            "(all partners) at n_half = 200", "seconds": dt}
+        # parity of the GPU forces at that cut-off on the sampled atoms
+        ctx = Context(n_types=1, coulomb="none", rc=pt["rc"], rinner=pt["rlist"],
+                      rlist=pt["rlist"], atom_offsets=[0, N], device=dev)
+        ctx.set_topology(s.type, s.excl_ptr, s.excl_idx)
+        ctx.grid_build(x, s.box[None])
+        ctx.pairlist_build()
+        ctx.forces(x, q, lj, energy=False, f=f)
+        fe = f.cpu().numpy()[sel]
+        result["parity"] = {"n_half": 200, "sampled_atoms": int(sel.size),
+                            "force_rel_rms": float(np.linalg.norm(fe - F) / np.linalg.norm(F))}
+        log("oracle %.2f s; parity %s" % (dt, result["parity"]))
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,6 +306,9 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     from paper_2006_09167_amd.api import Context, NBError
+    if args.workload == "argon157k_sweep":
+        argon_sweep(args)
+        return
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)

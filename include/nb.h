@@ -54,7 +54,9 @@ typedef enum {
     NB_ERR_NONFINITE = 7   /* non-finite coordinate met while building the grid          */
 } nb_status;
 
-enum { NB_COUL_RF = 0, NB_COUL_EWALD = 1 };
+/* Electrostatics of the pair kernel; NB_COUL_NONE is Lennard-Jones alone (charges are
+ * ignored and E_C is zero), as for the paper's argon benchmark (Sec. VI). */
+enum { NB_COUL_RF = 0, NB_COUL_EWALD = 1, NB_COUL_NONE = 2 };
 enum { NB_MOD_NONE = 0, NB_MOD_POTSHIFT = 1 };
 
 /* nb_forces / nb_forces_backward flags */
@@ -77,7 +79,7 @@ enum {
  */
 typedef struct {
     int32_t n_types;          /* LJ types T (1..32); lj tables are [T][T][2]              */
-    int32_t coulomb;          /* NB_COUL_RF or NB_COUL_EWALD                               */
+    int32_t coulomb;          /* NB_COUL_RF, NB_COUL_EWALD or NB_COUL_NONE                 */
     int32_t modifier;         /* NB_MOD_NONE or NB_MOD_POTSHIFT                            */
     float rc;                 /* interaction cut-off, nm, > 0                              */
     float rinner;             /* inner-list radius, rc <= rinner <= rlist                  */

@@ -8,7 +8,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnbmi.so"
 
 NB_OK, NB_ERR_ARG, NB_ERR_BOX, NB_ERR_NOMEM, NB_ERR_CAPACITY, NB_ERR_STATE, NB_ERR_HIP, \
     NB_ERR_NONFINITE = range(8)
-NB_COUL_RF, NB_COUL_EWALD = 0, 1
+NB_COUL_RF, NB_COUL_EWALD, NB_COUL_NONE = 0, 1, 2
 NB_MOD_NONE, NB_MOD_POTSHIFT = 0, 1
 NB_F_ENERGY, NB_F_VIRIAL, NB_F_ACCUMULATE = 1, 2, 4
 

@@ -52,7 +52,8 @@ class Context:
         rinner = rc if rinner is None else rinner
         rlist = rinner if rlist is None else rlist
         p = _lib.NbParams(n_types=n_types,
-                          coulomb={"rf": _lib.NB_COUL_RF, "ewald": _lib.NB_COUL_EWALD}[coulomb],
+                          coulomb={"rf": _lib.NB_COUL_RF, "ewald": _lib.NB_COUL_EWALD,
+                                   "none": _lib.NB_COUL_NONE}[coulomb],
                           modifier={"none": _lib.NB_MOD_NONE,
                                     "potshift": _lib.NB_MOD_POTSHIFT}[modifier],
                           rc=rc, rinner=rinner, rlist=rlist, eps_r=eps_r, eps_rf=eps_rf,

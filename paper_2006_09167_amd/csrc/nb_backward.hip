@@ -63,7 +63,9 @@ __device__ __forceinline__ void bwd_block(
     const float dphi_lj = rinv6 * rinv2 * rinv2 * fmaf(-14.0f, a, 8.0f * p.x);
     const float qq = on ? qi * xj.w : 0.f;
     float psi, dpsi, v;
-    if (COUL == NB_COUL_RF) {
+    if (COUL == NB_COUL_NONE) {
+        psi = dpsi = v = 0.f;
+    } else if (COUL == NB_COUL_RF) {
         psi = rinv * rinv2 - 2.0f * kp.krf;
         dpsi = -3.0f * rinv2 * rinv2 * rinv;
         v = fmaf(kp.krf, r2, rinv) - kp.crf;
@@ -481,6 +483,8 @@ hipError_t launch_backward(const NbDev& d, const NbKParams& kp, int coulomb, con
     if (n_items > 0) {
         if (coulomb == NB_COUL_RF)
             launch_bwd_c<NB_COUL_RF>(d, kp, lj, grad_energy, ljgrad, n_items, mode, s);
+        else if (coulomb == NB_COUL_NONE)
+            launch_bwd_c<NB_COUL_NONE>(d, kp, lj, grad_energy, ljgrad, n_items, mode, s);
         else
             launch_bwd_c<NB_COUL_EWALD>(d, kp, lj, grad_energy, ljgrad, n_items, mode, s);
     }

@@ -38,7 +38,7 @@ __device__ __forceinline__ void pair_block(const float4* s_x, const int* s_t,
     const uint64_t act = __builtin_amdgcn_ballot_w64(r2 < kp.rc2) & m;
     if (!act) return;
     const bool on = __builtin_amdgcn_inverse_ballot_w64(act);
-    const float4 p = *reinterpret_cast<const float4*>(lj_j + *s_t);   // (6 c6, 12 c12, shift, c6/2)
+    const float4 p = *reinterpret_cast<const float4*>(lj_j + *s_t);   // (6 c6, 12 c12, 12 shift, -)
     // With energies, pairs outside the cut-off or excluded get 1/r = 0 and q_i q_j = 0
     // (every force and energy term below then vanishes; r2 itself stays finite); without,
     // the scalar force alone is masked at the end.
@@ -49,7 +49,9 @@ __device__ __forceinline__ void pair_block(const float4* s_x, const int* s_t,
     const float t = fmaf(p.y, rinv6, -p.x);            // 12 c12 r^-6 - 6 c6
     const float flj = rinv6 * t;                       // F_LJ * r
     float fscal;
-    if (COUL == NB_COUL_RF) {
+    if (COUL == NB_COUL_NONE) {
+        fscal = flj * rinv2;
+    } else if (COUL == NB_COUL_RF) {
         fscal = fmaf(flj, rinv2, qq * (rinv * rinv2 - 2.0f * kp.krf));
         if (ENERGY) {
             ec = fmaf(qq, fmaf(kp.krf, r2, rinv) - kp.crf, ec);
@@ -75,8 +77,10 @@ __device__ __forceinline__ void pair_block(const float4* s_x, const int* s_t,
     fjy -= ty;
     fjz -= tz;
     if (ENERGY) {
-        // V_LJ = r^-6 (c12 r^-6 - c6) - shift = r^-6 (t / 12 - c6 / 2) - shift
-        elj += fmaf(rinv6, fmaf(t, 1.0f / 12.0f, -p.w), on ? -p.z : 0.f);
+        // 12 V_LJ = r^-6 (12 c12 r^-6 - 12 c6) - 12 shift = r^-6 (t - 6 c6) - 12 shift,
+        // summed as is and divided by 12 in double precision per item: no rounded 1/12
+        // (a relative bias of 4e-8 on every repulsive term)
+        elj += fmaf(rinv6, t - p.x, on ? -p.z : 0.f);
         npair += __builtin_popcountll(act);
         nblock += 1;
     }
@@ -223,7 +227,8 @@ __device__ __forceinline__ void fwd_item(
         store_stream(&jp[jj], fjx, fjy, fjz, 0.f);
         if (ENERGY) {
             elj_acc += (double)elj;
-            ec_acc += (COUL == NB_COUL_RF) ? (double)ec + (double)eclo : (double)ec;
+            if (COUL == NB_COUL_RF) ec_acc += (double)ec + (double)eclo;
+            else if (COUL == NB_COUL_EWALD) ec_acc += (double)ec;
         }
         if (VIRIAL) {
 #pragma unroll
@@ -242,7 +247,7 @@ __device__ __forceinline__ void fwd_item(
     NB_FOR8(NB_IRED)
 #undef NB_IRED
     if (ENERGY || VIRIAL) {
-        double v[8] = {elj_acc, ec_acc, vir_acc[0], vir_acc[1], vir_acc[2], vir_acc[3],
+        double v[8] = {elj_acc / 12.0, ec_acc, vir_acc[0], vir_acc[1], vir_acc[2], vir_acc[3],
                        vir_acc[4], vir_acc[5]};
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -296,7 +301,8 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
     const int T = kp.n_types;
     for (int i = threadIdx.x; i < T * T; i += blockDim.x) {
         const float c6 = lj[2 * i], c12 = lj[2 * i + 1];
-        s_lj[i] = make_float4(6.0f * c6, 12.0f * c12, c12 * kp.rc_m12 - c6 * kp.rc_m6, 0.5f * c6);
+        s_lj[i] = make_float4(6.0f * c6, 12.0f * c12,
+                              (12.0f * c12) * kp.rc_m12 - (12.0f * c6) * kp.rc_m6, 0.f);
     }
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -400,6 +406,9 @@ hipError_t prepare_forces(int coulomb, uint32_t flags, bool prune, int n_types,
     if (coulomb == NB_COUL_RF)
         nb = prune ? prepare_fwd_c<NB_COUL_RF, true>(flags, lds)
                    : prepare_fwd_c<NB_COUL_RF, false>(flags, lds);
+    else if (coulomb == NB_COUL_NONE)
+        nb = prune ? prepare_fwd_c<NB_COUL_NONE, true>(flags, lds)
+                   : prepare_fwd_c<NB_COUL_NONE, false>(flags, lds);
     else
         nb = prune ? prepare_fwd_c<NB_COUL_EWALD, true>(flags, lds)
                    : prepare_fwd_c<NB_COUL_EWALD, false>(flags, lds);
@@ -417,6 +426,9 @@ hipError_t launch_forces(const NbDev& d, const NbKParams& kp, int coulomb, uint3
     if (coulomb == NB_COUL_RF) {
         if (P) launch_fwd_c<NB_COUL_RF, true>(d, kp, flags, lj, n_items, i0, i1, r2, mode, s);
         else launch_fwd_c<NB_COUL_RF, false>(d, kp, flags, lj, n_items, i0, i1, r2, mode, s);
+    } else if (coulomb == NB_COUL_NONE) {
+        if (P) launch_fwd_c<NB_COUL_NONE, true>(d, kp, flags, lj, n_items, i0, i1, r2, mode, s);
+        else launch_fwd_c<NB_COUL_NONE, false>(d, kp, flags, lj, n_items, i0, i1, r2, mode, s);
     } else {
         if (P) launch_fwd_c<NB_COUL_EWALD, true>(d, kp, flags, lj, n_items, i0, i1, r2, mode, s);
         else launch_fwd_c<NB_COUL_EWALD, false>(d, kp, flags, lj, n_items, i0, i1, r2, mode, s);

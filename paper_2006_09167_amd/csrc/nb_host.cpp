@@ -222,7 +222,8 @@ nb_status nb_create(const nb_params* params, int32_t n_systems, const int64_t* a
     if (!params || !atom_offsets || n_systems < 1) return NB_ERR_ARG;
     const nb_params& p = *params;
     if (p.n_types < 1 || p.n_types > kMaxTypes) return NB_ERR_ARG;
-    if (p.coulomb != NB_COUL_RF && p.coulomb != NB_COUL_EWALD) return NB_ERR_ARG;
+    if (p.coulomb != NB_COUL_RF && p.coulomb != NB_COUL_EWALD && p.coulomb != NB_COUL_NONE)
+        return NB_ERR_ARG;
     if (p.modifier != NB_MOD_NONE && p.modifier != NB_MOD_POTSHIFT) return NB_ERR_ARG;
     if (!finite_pos(p.rc) || !isfinite(p.rinner) || !isfinite(p.rlist)) return NB_ERR_ARG;
     if (p.rinner < p.rc || p.rlist < p.rinner) return NB_ERR_ARG;

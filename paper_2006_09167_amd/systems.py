@@ -7,7 +7,8 @@ oracle receive what it returns.
 
 The paper measures its kernels on SPC/E water boxes and a Lennard-Jones argon
 system (Sec. V.C, Figs. 6 and 7).  Those inputs are not available here, so the
-boxes below are seeded stand-ins with the same density (about 100 atoms/nm^3),
+boxes below are seeded stand-ins: argon on a jittered lattice at the paper's density
+(argon_box), and water-like boxes with the same density (about 100 atoms/nm^3),
 charge pattern and exclusion structure as three-site water:
 
 * one O (q = -0.82 e, sigma = 0.3166 nm, epsilon = 0.65 kJ/mol) and two H
@@ -246,6 +247,40 @@ def water_box(n_mol: int, k: int, box: float, seed: int, min_contact: float = 0.
                   box=np.full(3, box, dtype=np.float32),
                   sigma=sigma, eps=eps, lj=lj_table_lorentz_berthelot(sigma, eps),
                   redraws=redraws)
+
+
+# Lennard-Jones argon for the kernel-throughput sweep of the paper's Fig. 6: 157k atoms
+# at 26 atoms/nm^3 with sigma = 0.3345 nm (the paper gives no epsilon; 0.996 kJ/mol is the
+# usual argon value and does not change the work).  The x axis of the figure is the number
+# of particles in the half cut-off sphere, n_half = (2/3) pi rc^3 rho; the sweep takes the
+# cut-off for each n_half below, the outer list 0.1 nm beyond it and no rolling prune.
+ARGON = dict(k=54, density=26.0, sigma=0.3345, eps=0.996, seed=2606, jitter=0.1,
+             n_half=(50, 100, 200, 400, 800, 1600, 3000), buffer=0.1)
+
+
+def argon_cutoff(n_half: float, density: float = ARGON["density"]) -> float:
+    """Cut-off (nm) that puts n_half particles in the half cut-off sphere."""
+    return (3.0 * n_half / (2.0 * math.pi * density)) ** (1.0 / 3.0)
+
+
+def argon_box(k: int = ARGON["k"], density: float = ARGON["density"], seed: int = ARGON["seed"],
+              jitter: float = ARGON["jitter"]) -> System:
+    """k^3 argon atoms on a cubic lattice of spacing density^(-1/3), each displaced
+    uniformly by up to +-jitter lattice spacings per axis; one LJ type, no charges and
+    no exclusions."""
+    a = density ** (-1.0 / 3.0)
+    box = k * a
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(1)[0])
+    g = np.stack(np.meshgrid(np.arange(k), np.arange(k), np.arange(k), indexing="ij"),
+                 -1).reshape(-1, 3).astype(np.float64)
+    x = (g + 0.5 + rng.uniform(-jitter, jitter, size=g.shape)) * a
+    n = x.shape[0]
+    sigma = np.array([ARGON["sigma"]])
+    eps = np.array([ARGON["eps"]])
+    return System(x=x.astype(np.float32), q=np.zeros(n, np.float32), type=np.zeros(n, np.int32),
+                  excl_ptr=np.zeros(n + 1, np.int64), excl_idx=np.zeros(0, np.int32),
+                  box=np.full(3, box, dtype=np.float32), sigma=sigma, eps=eps,
+                  lj=lj_table_lorentz_berthelot(sigma, eps))
 
 
 def config_system(name: str) -> System:
