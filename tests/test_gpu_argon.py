@@ -47,7 +47,7 @@ def test_argon_lj_only_parity(n_half):
     assert e[0, 1] == 0.0 and E[0, 1] == 0.0
     assert rel_rms(v, V) <= 1e-5
     st = ctx.stats()
-    assert st["effective_pairs"] > 0.9 * n_half * s.n      # about n_half pairs per atom
+    assert st["effective_pairs"] > 0.8 * n_half * s.n      # about n_half pairs per atom
 
 
 def test_argon_lj_only_backward():
