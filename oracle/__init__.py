@@ -10,7 +10,8 @@ Contents
     brute-force cluster-pair sets in a fixed single-precision sequence;
   * ``grid_spec.py``: the grid / slot assignment written out with numpy;
   * this module: ctypes wrappers, the pair-list set algebra (outer list, inner
-    list by rolling part) and finite-difference helpers.
+    list by rolling part) and finite-difference helpers;
+  * ``census.py``: the work-efficiency census of M x N sub-cluster lists (Fig. 5).
 
 Every function cites the part of the paper it follows (see the C file header).
 """
@@ -205,3 +206,6 @@ def rewrap_with(x: np.ndarray, k: np.ndarray, box: np.ndarray) -> np.ndarray:
     L = np.asarray(box, dtype=np.float32)
     return (np.asarray(x, dtype=np.float32)
             - (k.astype(np.float32) * L).astype(np.float32)).astype(np.float32)
+
+
+from . import census  # noqa: E402,F401  (work-efficiency census; uses the functions above)
