@@ -62,6 +62,10 @@ WORKLOADS = {
     "argon157k_sweep": "157,464-atom Lennard-Jones argon box (rho = 26/nm^3, sigma = 0.3345 nm, "
                        "18.2 nm cube), cut-off swept so that 50 ... 3000 particles fall in the "
                        "half cut-off sphere, outer list rc + 0.1 nm, force-only evaluations",
+    "water96k_work_efficiency": "96,000-atom water-like box (the water96k_ewald system), "
+                                "outer list at 1.45 nm, census of M x N sub-cluster lists "
+                                "(M, N in 1, 2, 4, 8) for cut-offs 0.9, 1.0, 1.2 nm and "
+                                "buffers 0 ... 0.25 nm",
     "ensemble256_rf": "256 independent water-like replicas of 3k-24k atoms (log-uniform, "
                       "2.63M atoms in all, density 100/nm^3) in one context, reaction field "
                       "rc=0.9 nm, rlist=1.0 nm every 100 steps, rinner=0.94 nm rolling prune "
@@ -276,6 +280,106 @@ def argon_sweep(args):
     print(json.dumps(result), flush=True)
 
 
+EFF_CUTOFFS = (0.9, 1.0, 1.2)
+EFF_BUFFERS = tuple(round(0.025 * k, 3) for k in range(11))
+EFF_SETUPS = ((1, 1), (4, 2), (4, 4), (8, 4), (8, 8))
+# list arithmetic of one atom pair slot: 3 coordinate differences, 3 squares, 2 additions
+FLOP_PER_SLOT_CENSUS = 8
+
+
+def work_efficiency_curves(args):
+    """The paper's work-efficiency figure (Fig. 5): for three cut-offs and a range of
+    buffers, the fraction of the pair evaluations of an M x N list that lie inside the
+    cut-off, from one census of an outer list at the largest radius.  The timed quantity is
+    the census kernel (8 x 8 pair slots examined per second)."""
+    import numpy as np
+    import torch
+    from paper_2006_09167_amd import _lib, systems
+    from paper_2006_09167_amd.api import Context
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    s = systems.config_system("water96k_ewald")
+    N = s.n
+    x = torch.from_numpy(s.x).to(dev)
+    radii = sorted({round(rc + b, 4) for rc in EFF_CUTOFFS for b in EFF_BUFFERS})
+    rlist = max(radii)
+    ctx = Context(n_types=s.lj.shape[0], coulomb="rf", rc=1.0, rinner=rlist, rlist=rlist,
+                  atom_offsets=[0, N], device=dev)
+    ctx.set_topology(s.type, s.excl_ptr, s.excl_idx)
+    ctx.grid_build(x, s.box[None])
+    ctx.pairlist_build()
+    st = ctx.stats()
+    K = args.steps if args.steps is not None else 50
+    W = min(args.warmup, 10)
+    for _ in range(W):
+        counts = ctx.list_census(radii)
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(K):
+        counts = ctx.list_census(radii)
+    wall = (time.perf_counter() - t0) / K
+    tm = ctx.get_timing()
+    ctx.set_timing(False)
+    kern = tm["census"][0] * 1e-3 / max(tm["census"][1], 1)
+    slots = 64.0 * st["outer_pairs"]
+    k_of = {r: i for i, r in enumerate(radii)}
+    curves = {}
+    for rc in EFF_CUTOFFS:
+        kc = k_of[round(rc, 4)]
+        cur = {"buffer_nm": list(EFF_BUFFERS)}
+        for M, N_ in EFF_SETUPS:
+            a, b = _lib.CENSUS_SIZES.index(M), _lib.CENSUS_SIZES.index(N_)
+            cur["%dx%d" % (M, N_)] = [
+                round(float(counts[0, 0, kc]) / (M * N_ * float(counts[a, b, k_of[round(rc + bb, 4)]])), 4)
+                for bb in EFF_BUFFERS]
+        curves["rc=%.1f" % rc] = cur
+        log("rc %.1f: 1x1 %s | 8x4 %s | 8x8 %s" % (rc, cur["1x1"][::2], cur["8x4"][::2],
+                                                   cur["8x8"][::2]))
+    # properties that hold at any size: the 8 x 8 count at the list radius is the outer list,
+    # counts grow with the radius and shrink with the sub-cluster size
+    parity = {"outer_list_equals_8x8": bool(counts[3, 3, -1] == st["outer_pairs"]),
+              "monotone_in_radius": bool(np.all(np.diff(counts, axis=2) >= 0)),
+              "nested_sizes": bool(np.all(counts[1:] <= counts[:-1]) and
+                                   np.all(counts[:, 1:] <= counts[:, :-1]))}
+    achieved = slots * FLOP_PER_SLOT_CENSUS / kern
+    result = {
+        "metric": "census pair slots/s (8x8 cluster-pair slots of the outer list examined "
+                  "for the work-efficiency curves)",
+        "value": slots / wall, "unit": "pair slots/s",
+        "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": 1e3 * wall,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]),
+                   "atoms": N, "rlist": rlist, "radii": len(radii),
+                   "outer_cluster_pairs": int(st["outer_pairs"])},
+        "curves": curves,
+        "parity": parity,
+        "roofline": {"bound": "alu", "kernel": "k_census", "flop_per_slot": FLOP_PER_SLOT_CENSUS,
+                     "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32, "traffic": None,
+                     "avg_launch_us": 1e6 * kern},
+    }
+    log("census: %.3f ms per call, kernel %.1f us, %.3g slots/s" % (1e3 * wall, 1e6 * kern,
+                                                                    slots / kern))
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        g = oracle.grid_spec.build_grid(s.x, s.box[None], np.array([0, N]))
+        n_cl = g["slot_atom"].size // 8
+        hi = n_cl // 32                                  # the first 1/32 of the i-clusters
+        t0 = time.perf_counter()
+        c_or = oracle.census.census(g["slot_atom"], g["w"], s.box, radii, ci_lo=0, ci_hi=hi)
+        dt = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": 64.0 * float(c_or[3, 3, -1]) / dt,
+                                  "unit": "pair slots/s", "cores": oracle.num_threads(),
+                                  "kind": "oracle",
+                                  "sample": "numpy census of the i-clusters 0..%d of %d, all "
+                                            "%d radii" % (hi, n_cl, len(radii)),
+                                  "seconds": dt}
+        log("oracle census sample %.2f s" % dt)
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,6 +412,9 @@ def main():
     from paper_2006_09167_amd.api import Context, NBError
     if args.workload == "argon157k_sweep":
         argon_sweep(args)
+        return
+    if args.workload == "water96k_work_efficiency":
+        work_efficiency_curves(args)
         return
 
     dev = torch.device("cuda", 0)

@@ -285,6 +285,26 @@ nb_status nb_get_pairs(nb_ctx* ctx, int32_t which, int32_t* triples, int64_t cap
 
 nb_status nb_get_stats(nb_ctx* ctx, nb_stats* out);
 
+/*
+ * [sync] Work-efficiency census of the current outer list (Sec. V.B, Fig. 5; the cluster
+ * setups of Sec. V.A and V.D).  For each radius radii[k] (host float[n_radii], nm, any
+ * order, repeats allowed, each in (0, rlist]) and each setup M x N with M, N in
+ * {1, 2, 4, 8}, counts the pairs of sub-clusters holding an atom pair closer than
+ * radii[k], where an i-sub-cluster is a run of M consecutive slots of an 8-atom cluster of
+ * the grid and a j-sub-cluster a run of N.  Pairs are taken as in the list: each unordered
+ * atom pair (atom and periodic image) once, distances at the build positions in the list
+ * arithmetic (r2 < float(radii[k])^2 in single precision), excluded pairs included.
+ * counts (host int64[16][n_radii]) receives at [(log2 M) * 4 + log2 N][k] the number of
+ * held M x N sub-cluster pairs: [0][k] the atom pairs closer than radii[k], [15][k] the
+ * 8 x 8 cluster pairs.  An M x N list at radius r_l costs M N pair evaluations per held
+ * pair, so its work efficiency at cut-off r_c is counts[0][k_c] / (M N counts[s][k_l]).
+ * Errors: NB_ERR_STATE without a list; NB_ERR_ARG for a null pointer, n_radii outside
+ * [1, NB_CENSUS_MAX_RADII] or a radius outside (0, rlist].  Allocates a per-context
+ * histogram buffer on first use.
+ */
+#define NB_CENSUS_MAX_RADII 64
+nb_status nb_list_census(nb_ctx* ctx, int32_t n_radii, const float* radii, int64_t* counts);
+
 /* Kernel timing with HIP events recorded on the context's stream around each kernel
  * group (opt-in; for benchmarks and profiling).  Kinds: */
 enum {
@@ -293,7 +313,8 @@ enum {
     NB_T_PRUNE = 2,           /* gather + rolling-prune kernel of nb_prune_rolling         */
     NB_T_BACKWARD = 3,        /* the pair kernel of nb_forces_backward                     */
     NB_T_BACKWARD_REDUCE = 4, /* gathers and reductions of nb_forces_backward              */
-    NB_T_COUNT = 5
+    NB_T_CENSUS = 5,          /* the census kernel of nb_list_census                       */
+    NB_T_COUNT = 6
 };
 
 /* Enable (1) or disable (0) event recording; enabling clears the accumulated totals. */

@@ -67,10 +67,12 @@ def pair_r2(slot_atom, w, box, ci, cj, code):
     return np.where(valid, r2, np.float32(np.inf)).astype(np.float32)
 
 
-def census(slot_atom, w, box, radii, chunk: int = 1 << 16) -> np.ndarray:
-    """Counts [4, 4, K] of held M x N sub-cluster pairs per radius (module docstring).
-    Candidates are the cluster triples within the largest radius (a sub-cluster pair with
-    an atom pair inside a radius lies in such a triple)."""
+def census(slot_atom, w, box, radii, chunk: int = 1 << 16, ci_lo: int = 0,
+           ci_hi=None) -> np.ndarray:
+    """Counts [4, 4, K] of held M x N sub-cluster pairs per radius (module docstring), over
+    the triples whose i-cluster ci lies in [ci_lo, ci_hi) (all by default).  Candidates are
+    the cluster triples within the largest radius (a sub-cluster pair with an atom pair
+    inside a radius lies in such a triple)."""
     radii = np.asarray(radii, dtype=np.float64).reshape(-1)
     slot_atom = np.asarray(slot_atom)
     n_cl = slot_atom.size // 8
@@ -78,7 +80,7 @@ def census(slot_atom, w, box, radii, chunk: int = 1 << 16) -> np.ndarray:
     out = np.zeros((4, 4, radii.size), dtype=np.int64)
     if radii.size == 0 or n_cl == 0:
         return out
-    keys = cluster_pairs(slot_atom, w, box, float(radii.max()))
+    keys = cluster_pairs(slot_atom, w, box, float(radii.max()), ci_lo, ci_hi)
     ci, cj, code = split_key(keys, n_cl)
     for p0 in range(0, keys.size, chunk):
         r2 = pair_r2(slot_atom, w, box, ci[p0:p0 + chunk], cj[p0:p0 + chunk],

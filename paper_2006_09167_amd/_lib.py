@@ -16,12 +16,15 @@ EXPORTS = ["nb_create", "nb_destroy", "nb_set_topology", "nb_grid_build", "nb_pa
            "nb_prune_rolling", "nb_forces", "nb_step", "nb_forces_backward", "nb_get_grid",
            "nb_get_grid_dims", "nb_get_pairs", "nb_get_stats", "nb_set_timing", "nb_get_timing",
            "nb_strerror", "nb_last_error", "nb_step_graph", "nb_set_exec", "nb_get_exec",
-           "nb_autotune"]
+           "nb_autotune", "nb_list_census"]
 NB_EXEC_STATIC, NB_EXEC_XCD, NB_EXEC_QUEUE, NB_EXEC_PERSIST = 0, 1, 2, 3
 EXEC_MODES = {"static": NB_EXEC_STATIC, "xcd": NB_EXEC_XCD, "queue": NB_EXEC_QUEUE,
               "persist": NB_EXEC_PERSIST}
-NB_T_FORCES, NB_T_FORCE_REDUCE, NB_T_PRUNE, NB_T_BACKWARD, NB_T_BACKWARD_REDUCE, NB_T_COUNT = range(6)
-TIMING_KINDS = ["forces", "force_reduce", "prune", "backward", "backward_reduce"]
+(NB_T_FORCES, NB_T_FORCE_REDUCE, NB_T_PRUNE, NB_T_BACKWARD, NB_T_BACKWARD_REDUCE, NB_T_CENSUS,
+ NB_T_COUNT) = range(7)
+TIMING_KINDS = ["forces", "force_reduce", "prune", "backward", "backward_reduce", "census"]
+NB_CENSUS_MAX_RADII = 64
+CENSUS_SIZES = (1, 2, 4, 8)
 
 
 class NbParams(ctypes.Structure):
@@ -82,6 +85,7 @@ def load():
         "nb_get_stats": ([P, ctypes.POINTER(NbStats)], st),
         "nb_set_timing": ([P, i32], st),
         "nb_get_timing": ([P, P, P], st),
+        "nb_list_census": ([P, i32, P, P], st),
         "nb_strerror": ([st], ctypes.c_char_p),
         "nb_last_error": ([P], ctypes.c_char_p),
     }

@@ -258,6 +258,17 @@ class Context:
         self._check(self.lib.nb_get_timing(self.h, _np_ptr(ms), _np_ptr(calls)), "nb_get_timing")
         return {k: (float(ms[i]), int(calls[i])) for i, k in enumerate(_lib.TIMING_KINDS)}
 
+    def list_census(self, radii) -> np.ndarray:
+        """Work-efficiency census of the current outer list (nb_list_census): int64 array
+        [4, 4, K], [a, b, k] = held pairs of sub-clusters of CENSUS_SIZES[a] i-slots and
+        CENSUS_SIZES[b] j-slots with an atom pair closer than radii[k] (nm, each in
+        (0, rlist]); [0, 0, k] counts atom pairs, [3, 3, k] cluster pairs (syncs)."""
+        r = np.ascontiguousarray(np.asarray(radii, dtype=np.float32).reshape(-1))
+        out = np.zeros((16, max(1, r.size)), dtype=np.int64)
+        self._check(self.lib.nb_list_census(self.h, int(r.size), _np_ptr(r), _np_ptr(out)),
+                    "nb_list_census")
+        return out.reshape(4, 4, -1)
+
     def stats(self) -> dict:
         s = _lib.NbStats()
         self._check(self.lib.nb_get_stats(self.h, ctypes.byref(s)), "nb_get_stats")

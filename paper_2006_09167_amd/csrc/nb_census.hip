@@ -1,0 +1,238 @@
+// Work-efficiency census of the outer list (Sec. V.B, Fig. 5; cluster setups of Sec. V.A
+// and V.D).
+//
+// For each radius R_k (at most the list radius) and each sub-cluster setup M x N with M, N
+// in {1, 2, 4, 8} (i-sub-clusters of M consecutive slots of an 8-atom cluster, j-sub-
+// clusters of N), count the pairs of sub-clusters holding an atom pair closer than R_k.
+// 1 x 1 counts the atom pairs themselves, 8 x 8 the cluster pairs.  Every sub-cluster pair
+// within the list radius lies in an outer-list cluster pair, so walking the outer list at
+// its build positions counts them all, with the list arithmetic (shift split between the
+// two sides, no contraction) and therefore exactly.
+//
+// * k_census: one wavefront per work item (the item's eight i-clusters loaded once).  Per
+//   cluster pair every lane takes the bin of its squared distance, the number of sorted
+//   thresholds R_k^2 at or below it (compares against wave-uniform thresholds); a sub-cluster
+//   pair holds a pair closer than R_k iff the smallest bin of its lanes is <= k, so folding
+//   the lane bins with min over lane-xor partners (1, 2, 4 on the i side, 8, 16, 32 on the j
+//   side; DPP where the partner is in the same row of 16 lanes) gives each sub-cluster
+//   pair's bin, which its first lane adds to an LDS histogram per setup.
+//   Each block then writes its histogram.
+// * k_census_sum / k_census_total: the block histograms summed in 64-bit (chunks of blocks,
+//   then the chunks); the host turns bins into counts by a prefix sum.
+#include <algorithm>
+#include <cfloat>
+
+#include "nb_internal.h"
+#include "nb_pair_common.h"
+
+namespace {
+
+constexpr int kCensusWaves = 8;
+constexpr int kCensusMaxBlocks = 16384;        // beyond, blocks stride over the items
+constexpr int kCensusSetups = 16;               // (log2 M) * 4 + log2 N
+constexpr int kCensusBins = NB_CENSUS_MAX_RADII;
+
+#define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
+
+// Number of thresholds at or below v (v finite).  The thresholds are wave-uniform, padded
+// with +inf to NCH chunks of 8: with NCH > 0 they are loaded once per wavefront into scalar
+// registers (t), otherwise read per use from memory (tp, n_pad entries).  For finite floats
+// v - t is +0 when v == t and keeps the sign of the exact difference, so t <= v iff the sign
+// bit of v - t is clear (an +inf pad gives -inf): each threshold costs a subtraction, a
+// shift and an add per lane, with no compare-to-carry hazard and no LDS traffic.
+__device__ inline int below(float v, float t) { return (int)(__float_as_uint(v - t) >> 31); }
+
+template <int NCH>
+__device__ inline int bin_of(const float* t, const float* __restrict__ tp, int n_pad,
+                             float v) {
+    int neg = 0;
+    if constexpr (NCH > 0) {
+#pragma unroll
+        for (int k = 0; k < 8 * NCH; ++k) neg += below(v, t[k]);
+        return 8 * NCH - neg;
+    } else {
+        for (int k0 = 0; k0 < n_pad; k0 += 8) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) neg += below(v, tp[k0 + k]);
+        }
+        return n_pad - neg;
+    }
+}
+
+// min(v, v of the lane whose index differs in the given bit): DPP inside a row of 16 lanes
+// (xor 1, 2 as quad permutations; xor 4 as the half-row mirror, which pairs each lane with
+// one in the other quad: equal to xor 4 once quads hold equal values; xor 8 as a rotation
+// by 8), a swizzle for xor 16 and a permute across the halves for xor 32.
+template <int BIT>
+__device__ inline int fold_min(int v, int lane) {
+    int p;
+    if constexpr (BIT == 1) p = __builtin_amdgcn_update_dpp(0, v, 0xb1, 0xf, 0xf, false);
+    else if constexpr (BIT == 2) p = __builtin_amdgcn_update_dpp(0, v, 0x4e, 0xf, 0xf, false);
+    else if constexpr (BIT == 4) p = __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);
+    else if constexpr (BIT == 8) p = __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, false);
+    else if constexpr (BIT == 16) p = __builtin_amdgcn_ds_swizzle(v, 0x401f);
+    else p = __builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, v);
+    return min(v, p);
+}
+
+// Histogram one 8x8 cluster pair given each lane's bin (n_radii: not inside any radius).
+template <int A>
+__device__ inline void census_jfold(uint32_t (*hist)[kCensusBins], int bi, int lane,
+                                    int n_radii) {
+    const int ii = lane & 7, jj = lane >> 3;
+    const bool ilead = (ii & ((1 << A) - 1)) == 0;
+    int b2 = bi;
+    if (ilead && b2 < n_radii) atomicAdd(&hist[4 * A + 0][b2], 1u);
+    b2 = fold_min<8>(b2, lane);
+    if (ilead && (jj & 1) == 0 && b2 < n_radii) atomicAdd(&hist[4 * A + 1][b2], 1u);
+    b2 = fold_min<16>(b2, lane);
+    if (ilead && (jj & 3) == 0 && b2 < n_radii) atomicAdd(&hist[4 * A + 2][b2], 1u);
+    b2 = fold_min<32>(b2, lane);
+    if (ilead && jj == 0 && b2 < n_radii) atomicAdd(&hist[4 * A + 3][b2], 1u);
+}
+
+__device__ inline void census_block(uint32_t (*hist)[kCensusBins], int bin, int lane,
+                                    int n_radii) {
+    if (!__builtin_amdgcn_ballot_w64(bin < n_radii)) return;
+    census_jfold<0>(hist, bin, lane, n_radii);
+    int bi = fold_min<1>(bin, lane);
+    census_jfold<1>(hist, bi, lane, n_radii);
+    bi = fold_min<2>(bi, lane);
+    census_jfold<2>(hist, bi, lane, n_radii);
+    bi = fold_min<4>(bi, lane);
+    census_jfold<3>(hist, bi, lane, n_radii);
+}
+
+template <int NCH>
+__global__ __launch_bounds__(kCensusWaves * kWave) void k_census(
+    const NbItem* __restrict__ items, const NbEntry* __restrict__ entries,
+    const float4* __restrict__ xw, const float4* __restrict__ cl_bb,
+    const NbScInfo* __restrict__ sc_info, const NbSys* __restrict__ sys, int n_items,
+    const float* __restrict__ r2_sorted, int n_radii, int n_pad,
+    uint32_t* __restrict__ block_hist) {
+#pragma clang fp contract(off)
+    __shared__ uint32_t hist[kCensusSetups][kCensusBins];
+    for (int t = threadIdx.x; t < kCensusSetups * kCensusBins; t += blockDim.x)
+        hist[t / kCensusBins][t % kCensusBins] = 0u;
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int ii = lane & 7, jj = lane >> 3;
+    const float big = FLT_MAX;                     // a pair not counted: above every radius
+    float t[NCH > 0 ? 8 * NCH : 1];
+#pragma unroll
+    for (int k = 0; k < (NCH > 0 ? 8 * NCH : 1); ++k) t[k] = r2_sorted[k];
+    for (int k = blockIdx.x * kCensusWaves + wave; k < n_items;
+         k += gridDim.x * kCensusWaves) {
+        const NbItem it = items[k];
+        const NbSys S = sys[sc_info[it.sc].sys];
+        const int ci0 = kClustersPerSc * it.sc;
+        // build positions and atom counts of the item's i-clusters (empty slots hold zeros
+        // in the build coordinates: lanes past a cluster's count are not counted)
+#define NB_CI(c)                                                                          \
+        const float4 xi##c = xw[kScAtoms * it.sc + kClusterSize * c + ii];                \
+        const bool iv##c = ii < (int)cl_bb[2 * (ci0 + c)].w;
+        NB_FOR8(NB_CI)
+#undef NB_CI
+        for (int e = it.e0; e < it.e0 + it.ne; ++e) {
+            const NbEntry ent = entries[e];
+            float4 xj = xw[kClusterSize * ent.cj + jj];
+            const int code = ent.meta & 31u;
+            const uint32_t omask = (ent.meta >> 8) & 0xffu;
+            const bool jv = jj < (int)((ent.meta >> 24) & 15u);
+            const int sx = shift_x(code), sy = shift_y(code), sz = shift_z(code);
+            // a = x_i - L for s > 0, b = x_j - L for s < 0, d = a - b (exact shifts)
+            xj.x -= (sx < 0) ? S.L[0] : 0.f;
+            xj.y -= (sy < 0) ? S.L[1] : 0.f;
+            xj.z -= (sz < 0) ? S.L[2] : 0.f;
+            const float ox = (sx > 0) ? S.L[0] : 0.f, oy = (sy > 0) ? S.L[1] : 0.f,
+                        oz = (sz > 0) ? S.L[2] : 0.f;
+            const int dc = (code == kShiftZero) ? ent.cj - ci0 : -1;
+#define NB_CB(c)                                                                          \
+            if ((omask >> c) & 1u) {                                                      \
+                const float dx = (xi##c.x - ox) - xj.x;                                   \
+                const float dy = (xi##c.y - oy) - xj.y;                                   \
+                const float dz = (xi##c.z - oz) - xj.z;                                   \
+                float r2 = (dx * dx + dy * dy) + dz * dz;                                 \
+                if (!(iv##c && jv) || (dc == c && ii >= jj)) r2 = big;                    \
+                census_block(hist, bin_of<NCH>(t, r2_sorted, n_pad, r2), lane, n_radii);         \
+            }
+            NB_FOR8(NB_CB)
+#undef NB_CB
+        }
+    }
+    __syncthreads();
+    uint32_t* out = block_hist + (size_t)blockIdx.x * kCensusSetups * kCensusBins;
+    for (int t = threadIdx.x; t < kCensusSetups * kCensusBins; t += blockDim.x)
+        out[t] = hist[t / kCensusBins][t % kCensusBins];
+}
+
+// Two-stage sum of the block histograms (integer, so the order does not matter): stage 1
+// gives each thread kSumRows block rows of one histogram word, stage 2 adds the chunks.
+constexpr int kSumRows = 64;
+constexpr int kHistWords = kCensusSetups * kCensusBins;
+
+__global__ __launch_bounds__(256) void k_census_sum(const uint32_t* __restrict__ block_hist,
+                                                    int n_blocks,
+                                                    unsigned long long* __restrict__ part) {
+    const int t = blockIdx.x * 256 + threadIdx.x;          // histogram word
+    const int b0 = blockIdx.y * kSumRows;
+    const int b1 = min(n_blocks, b0 + kSumRows);
+    unsigned long long s = 0;
+    for (int b = b0; b < b1; ++b) s += block_hist[(size_t)b * kHistWords + t];
+    part[(size_t)blockIdx.y * kHistWords + t] = s;
+}
+
+__global__ __launch_bounds__(256) void k_census_total(const unsigned long long* __restrict__ part,
+                                                      int n_chunks,
+                                                      unsigned long long* __restrict__ total) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    unsigned long long s = 0;
+    for (int c = 0; c < n_chunks; ++c) s += part[(size_t)c * kHistWords + t];
+    total[t] = s;
+}
+
+}  // namespace
+
+int census_blocks(int n_items, int n_cu) {
+    (void)n_cu;
+    const int need = (n_items + kCensusWaves - 1) / kCensusWaves;   // one item per wavefront
+    return std::max(1, std::min(need, kCensusMaxBlocks));
+}
+
+size_t census_hist_words(int n_blocks) {
+    return (size_t)n_blocks * kHistWords;
+}
+
+size_t census_part_words(int n_blocks) {
+    return (size_t)((n_blocks + kSumRows - 1) / kSumRows) * kHistWords;
+}
+
+hipError_t launch_census(const NbDev& d, int n_items, const float* r2_sorted, int n_radii,
+                         uint32_t* block_hist, int n_blocks, hipStream_t s) {
+    const int n_pad = (n_radii + 7) / 8 * 8;     // r2_sorted holds +inf up to n_pad
+#define NB_CENSUS_LAUNCH(NCH)                                                                \
+    hipLaunchKernelGGL(k_census<NCH>, dim3(n_blocks), dim3(kCensusWaves * kWave), 0, s,     \
+                       d.items, d.entries, d.xw, d.cl_bb, d.sc_info, d.sys, n_items,        \
+                       r2_sorted, n_radii, n_pad, block_hist)
+    switch (n_pad / 8) {
+        case 1: NB_CENSUS_LAUNCH(1); break;
+        case 2: NB_CENSUS_LAUNCH(2); break;
+        case 3: NB_CENSUS_LAUNCH(3); break;
+        case 4: NB_CENSUS_LAUNCH(4); break;
+        default: NB_CENSUS_LAUNCH(0); break;
+    }
+#undef NB_CENSUS_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_census_sum(const uint32_t* block_hist, int n_blocks,
+                             unsigned long long* part, unsigned long long* total,
+                             hipStream_t s) {
+    const int n_chunks = (n_blocks + kSumRows - 1) / kSumRows;
+    hipLaunchKernelGGL(k_census_sum, dim3(kHistWords / 256, n_chunks), dim3(256), 0, s,
+                       block_hist, n_blocks, part);
+    hipLaunchKernelGGL(k_census_total, dim3(kHistWords / 256), dim3(256), 0, s, part, n_chunks,
+                       total);
+    return hipGetLastError();
+}

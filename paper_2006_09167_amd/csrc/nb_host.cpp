@@ -50,8 +50,14 @@ struct nb_ctx {
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[NB_T_COUNT];
     std::vector<hipEvent_t> ev_free;
-    double t_ms[NB_T_COUNT] = {0, 0, 0, 0, 0};
-    int64_t t_calls[NB_T_COUNT] = {0, 0, 0, 0, 0};
+    double t_ms[NB_T_COUNT] = {};
+    int64_t t_calls[NB_T_COUNT] = {};
+    // census buffers (allocated on the first nb_list_census call)
+    uint32_t* census_hist = nullptr;          // [census_hist_words(census_nb)]
+    unsigned long long* census_part = nullptr;   // [census_part_words(census_nb)]
+    unsigned long long* census_total = nullptr;  // [16 * NB_CENSUS_MAX_RADII]
+    float* census_thr = nullptr;              // [NB_CENSUS_MAX_RADII]
+    int census_nb = 0;
 };
 
 namespace {
@@ -271,6 +277,9 @@ void nb_destroy(nb_ctx* c) {
     drop_graphs(c);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     for (void* q : ptrs)
+        if (q) hipFree(q);
+    for (void* q : {(void*)c->census_hist, (void*)c->census_part, (void*)c->census_total,
+                    (void*)c->census_thr})
         if (q) hipFree(q);
     for (int k = 0; k < NB_T_COUNT; ++k)
         for (auto& pr : c->ev[k]) {
@@ -971,6 +980,56 @@ nb_status nb_get_timing(nb_ctx* c, double* ms, int64_t* calls) {
         calls[k] = c->t_calls[k];
         c->t_ms[k] = 0;
         c->t_calls[k] = 0;
+    }
+    return NB_OK;
+}
+
+nb_status nb_list_census(nb_ctx* c, int32_t n_radii, const float* radii, int64_t* counts) {
+    if (!c) return NB_ERR_ARG;
+    if (!radii || !counts) return fail(c, NB_ERR_ARG, "null radii or counts");
+    if (n_radii < 1 || n_radii > NB_CENSUS_MAX_RADII)
+        return fail(c, NB_ERR_ARG, "n_radii outside [1, NB_CENSUS_MAX_RADII]");
+    if (!c->has_list) return fail(c, NB_ERR_STATE, "no pair list");
+    for (int k = 0; k < n_radii; ++k)
+        if (!(radii[k] > 0.f) || !(radii[k] <= c->p.rlist))
+            return fail(c, NB_ERR_ARG, "census radius outside (0, rlist]");
+    NB_HIP(c, hipSetDevice(c->device));
+    // thresholds in ascending order; counts are scattered back to the caller's order
+    std::vector<int> ord(n_radii);
+    for (int k = 0; k < n_radii; ++k) ord[k] = k;
+    std::vector<float> r2(n_radii);
+    for (int k = 0; k < n_radii; ++k) r2[k] = radius_sq(radii[k]);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return r2[a] < r2[b]; });
+    std::vector<float> r2s(NB_CENSUS_MAX_RADII, __builtin_inff());   // +inf padding
+    for (int k = 0; k < n_radii; ++k) r2s[k] = r2[ord[k]];
+    const int n_items = c->n_items;
+    const int nb = census_blocks(n_items, c->d.n_cu);
+    if (nb > c->census_nb) {
+        NB_HIP(c, dev_alloc(c->census_hist, census_hist_words(nb)));
+        NB_HIP(c, dev_alloc(c->census_part, census_part_words(nb)));
+        c->census_nb = nb;
+    }
+    if (!c->census_total) NB_HIP(c, dev_alloc(c->census_total, 16 * NB_CENSUS_MAX_RADII));
+    if (!c->census_thr) NB_HIP(c, dev_alloc(c->census_thr, NB_CENSUS_MAX_RADII));
+    NB_HIP(c, hipMemcpyAsync(c->census_thr, r2s.data(), sizeof(float) * r2s.size(),
+                             hipMemcpyHostToDevice, c->stream));
+    {
+        TimedSection ts(c, NB_T_CENSUS);
+        NB_HIP(c, launch_census(c->d, n_items, c->census_thr, n_radii, c->census_hist, nb,
+                                c->stream));
+    }
+    NB_HIP(c, launch_census_sum(c->census_hist, nb, c->census_part, c->census_total,
+                                c->stream));
+    std::vector<unsigned long long> tot(16 * NB_CENSUS_MAX_RADII);
+    nb_status st = to_host(c, tot.data(), c->census_total, tot.size());
+    if (st != NB_OK) return st;
+    // bin b holds the sub-cluster pairs first inside the b-th smallest radius
+    for (int s = 0; s < 16; ++s) {
+        int64_t acc = 0;
+        for (int k = 0; k < n_radii; ++k) {
+            acc += (int64_t)tot[(size_t)s * NB_CENSUS_MAX_RADII + k];
+            counts[(size_t)s * n_radii + ord[k]] = acc;
+        }
     }
     return NB_OK;
 }

@@ -83,6 +83,16 @@ def test_state_and_topology_errors_without_device():
         assert lib.nb_forces_backward(h, None, None, None, None, None, None, None, None, 0) \
             == _lib.NB_ERR_STATE
         assert b"no pair list" in lib.nb_last_error(h)
+        # census: arguments checked first, then the list
+        r = np.array([0.5], np.float32)
+        cnt = np.zeros(16, np.int64)
+        vpp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        assert lib.nb_list_census(h, 1, vpp(r), vpp(cnt)) == _lib.NB_ERR_STATE
+        assert lib.nb_list_census(h, 0, vpp(r), vpp(cnt)) == _lib.NB_ERR_ARG
+        assert lib.nb_list_census(h, _lib.NB_CENSUS_MAX_RADII + 1, vpp(r), vpp(cnt)) \
+            == _lib.NB_ERR_ARG
+        assert lib.nb_list_census(h, 1, None, vpp(cnt)) == _lib.NB_ERR_ARG
+        assert lib.nb_list_census(None, 1, vpp(r), vpp(cnt)) == _lib.NB_ERR_ARG
         # topology validation happens before any device call
         t = np.array([0, 1, 2, 0], np.int32)                     # type 2 >= n_types
         ptr = np.zeros(5, np.int64)
