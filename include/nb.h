@@ -305,6 +305,64 @@ nb_status nb_get_stats(nb_ctx* ctx, nb_stats* out);
 #define NB_CENSUS_MAX_RADII 64
 nb_status nb_list_census(nb_ctx* ctx, int32_t n_radii, const float* radii, int64_t* counts);
 
+/*
+ * [sync] Coverage of the current outer list by an M x N list (M = 2^log2_m, N = 2^log2_n,
+ * each 1 ... 8; sub-clusters as in nb_list_census): the implicit buffer of cluster lists
+ * that the Verlet buffer estimate takes into account (Sec. V.B).  covered (host
+ * int64[n_radii][n_radii]) receives at [l][k] the number of atom pairs closer than radii[k]
+ * that lie in an M x N sub-cluster pair holding an atom pair closer than radii[l], i.e. the
+ * pairs within radii[k] that an M x N list at radius radii[l] contains.  [k][k] (and any
+ * [l][k] with radii[l] >= radii[k]) is the number of atom pairs closer than radii[k].  Pairs,
+ * distances, radii and errors as in nb_list_census; NB_ERR_ARG also for log2 sizes outside
+ * [0, 3].
+ */
+nb_status nb_list_coverage(nb_ctx* ctx, int32_t log2_m, int32_t log2_n, int32_t n_radii,
+                           const float* radii, int64_t* covered);
+
+/*
+ * Verlet buffer estimate (Sec. V.B): the drift of the energy caused by pairs that move
+ * from outside a list radius to inside the cut-off during the list's lifetime, and the
+ * smallest list radius that keeps it within a tolerance.  Host-only (no context, no device).
+ *
+ * Atoms are grouped in classes of equal mass, charge and LJ type.  Over a list age t each
+ * atom moves by a Gaussian displacement of variance k_B T t^2 / m per axis; beyond the list
+ * radius partners are spread uniformly; a pair not in the list that ends inside r_c misses
+ * |V(r)|, V the pair potential selected by the nb_params (LJ with the electrostatics and the
+ * modifier of the kernels).  The missed energy per atom at age (steps - 1) dt, divided by
+ * steps * dt, is the drift (kJ mol^-1 ps^-1 per atom).  A cluster list holds a fraction of
+ * the pairs beyond its radius (its implicit buffer): with n_cov > 0 that fraction is taken
+ * from a coverage table of nb_list_coverage (cov_radii ascending, covered[n_cov][n_cov]),
+ * and the list radius must be one of cov_radii; with n_cov = 0 the list is a particle list.
+ */
+typedef struct {
+    int32_t n_classes;
+    const int64_t* count;     /* atoms per class                                              */
+    const double* mass;       /* mass that carries the atom over the list lifetime, amu       */
+    const float* charge;      /* e                                                            */
+    const int32_t* type;      /* LJ type, < nb_params.n_types                                 */
+    const float* lj;          /* (c6, c12) per type pair, float[n_types][n_types][2]          */
+    double volume;            /* nm^3                                                         */
+    double temperature;       /* K                                                            */
+    double dt;                /* time step, ps                                                */
+    int32_t n_cov;            /* coverage radii (0: particle list, no implicit buffer)        */
+    const float* cov_radii;   /* [n_cov], ascending                                           */
+    const int64_t* covered;   /* [n_cov][n_cov] as returned by nb_list_coverage               */
+} nb_buffer_input;
+
+/* Drift for a list of radius r_list (>= rc) used for `steps` steps after its build.
+ * NB_ERR_ARG for invalid input or, with a coverage table, an r_list not in it. */
+nb_status nb_buffer_drift(const nb_params* params, const nb_buffer_input* in, int32_t steps,
+                          double r_list, double* drift);
+
+/* Smallest list radius in [rc, rc + max_buffer] with drift <= tolerance: by bisection to
+ * 1e-6 nm for a particle list, the smallest such table radius for a cluster list.  Writes
+ * the radius and its drift (drift may be null); NB_ERR_CAPACITY when no radius in range
+ * reaches the tolerance.  For the dual list of Sec. V.E: steps = nstlist gives the outer
+ * radius, steps = nstprune the inner one. */
+nb_status nb_buffer_estimate(const nb_params* params, const nb_buffer_input* in, int32_t steps,
+                             double tolerance, double max_buffer, double* r_list,
+                             double* drift);
+
 /* Kernel timing with HIP events recorded on the context's stream around each kernel
  * group (opt-in; for benchmarks and profiling).  Kinds: */
 enum {

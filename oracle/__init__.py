@@ -11,7 +11,8 @@ Contents
   * ``grid_spec.py``: the grid / slot assignment written out with numpy;
   * this module: ctypes wrappers, the pair-list set algebra (outer list, inner
     list by rolling part) and finite-difference helpers;
-  * ``census.py``: the work-efficiency census of M x N sub-cluster lists (Fig. 5).
+  * ``census.py``: the work-efficiency census of M x N sub-cluster lists (Fig. 5);
+  * ``buffer.py``: list coverage by sub-cluster pairs and the Verlet buffer estimate.
 
 Every function cites the part of the paper it follows (see the C file header).
 """
@@ -209,3 +210,4 @@ def rewrap_with(x: np.ndarray, k: np.ndarray, box: np.ndarray) -> np.ndarray:
 
 
 from . import census  # noqa: E402,F401  (work-efficiency census; uses the functions above)
+from . import buffer  # noqa: E402,F401  (Verlet buffer estimate and list coverage)

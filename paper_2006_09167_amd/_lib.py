@@ -16,7 +16,8 @@ EXPORTS = ["nb_create", "nb_destroy", "nb_set_topology", "nb_grid_build", "nb_pa
            "nb_prune_rolling", "nb_forces", "nb_step", "nb_forces_backward", "nb_get_grid",
            "nb_get_grid_dims", "nb_get_pairs", "nb_get_stats", "nb_set_timing", "nb_get_timing",
            "nb_strerror", "nb_last_error", "nb_step_graph", "nb_set_exec", "nb_get_exec",
-           "nb_autotune", "nb_list_census"]
+           "nb_autotune", "nb_list_census", "nb_list_coverage", "nb_buffer_drift",
+           "nb_buffer_estimate"]
 NB_EXEC_STATIC, NB_EXEC_XCD, NB_EXEC_QUEUE, NB_EXEC_PERSIST = 0, 1, 2, 3
 EXEC_MODES = {"static": NB_EXEC_STATIC, "xcd": NB_EXEC_XCD, "queue": NB_EXEC_QUEUE,
               "persist": NB_EXEC_PERSIST}
@@ -35,6 +36,15 @@ class NbParams(ctypes.Structure):
                 ("ewald_beta", ctypes.c_float), ("epsfac", ctypes.c_float),
                 ("nstlist", ctypes.c_int32), ("nstprune", ctypes.c_int32),
                 ("list_capacity_hint", ctypes.c_int64)]
+
+
+class NbBufferInput(ctypes.Structure):
+    _fields_ = [("n_classes", ctypes.c_int32), ("count", ctypes.c_void_p),
+                ("mass", ctypes.c_void_p), ("charge", ctypes.c_void_p),
+                ("type", ctypes.c_void_p), ("lj", ctypes.c_void_p),
+                ("volume", ctypes.c_double), ("temperature", ctypes.c_double),
+                ("dt", ctypes.c_double), ("n_cov", ctypes.c_int32),
+                ("cov_radii", ctypes.c_void_p), ("covered", ctypes.c_void_p)]
 
 
 class NbStats(ctypes.Structure):
@@ -86,6 +96,13 @@ def load():
         "nb_set_timing": ([P, i32], st),
         "nb_get_timing": ([P, P, P], st),
         "nb_list_census": ([P, i32, P, P], st),
+        "nb_list_coverage": ([P, i32, i32, i32, P, P], st),
+        "nb_buffer_drift": ([ctypes.POINTER(NbParams), ctypes.POINTER(NbBufferInput), i32,
+                             ctypes.c_double, ctypes.POINTER(ctypes.c_double)], st),
+        "nb_buffer_estimate": ([ctypes.POINTER(NbParams), ctypes.POINTER(NbBufferInput), i32,
+                                ctypes.c_double, ctypes.c_double,
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+                               st),
         "nb_strerror": ([st], ctypes.c_char_p),
         "nb_last_error": ([P], ctypes.c_char_p),
     }

@@ -37,6 +37,77 @@ def _np_ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+def make_params(n_types: int, coulomb: str = "rf", rc: float = 1.0,
+                rinner: Optional[float] = None, rlist: Optional[float] = None,
+                eps_r: float = 1.0, eps_rf: float = math.inf, beta: float = 0.0,
+                epsfac: float = 138.935458, modifier: str = "potshift", nstlist: int = 1,
+                nstprune: int = 1, capacity_hint: int = 0) -> _lib.NbParams:
+    rinner = rc if rinner is None else rinner
+    rlist = rinner if rlist is None else rlist
+    return _lib.NbParams(n_types=n_types,
+                         coulomb={"rf": _lib.NB_COUL_RF, "ewald": _lib.NB_COUL_EWALD,
+                                  "none": _lib.NB_COUL_NONE}[coulomb],
+                         modifier={"none": _lib.NB_MOD_NONE,
+                                   "potshift": _lib.NB_MOD_POTSHIFT}[modifier],
+                         rc=rc, rinner=rinner, rlist=rlist, eps_r=eps_r, eps_rf=eps_rf,
+                         ewald_beta=beta, epsfac=epsfac, nstlist=nstlist, nstprune=nstprune,
+                         list_capacity_hint=capacity_hint)
+
+
+class _BufferArgs:
+    """Marshalled nb_buffer_input (keeps the arrays alive)."""
+
+    def __init__(self, classes: dict, lj, volume, temperature, dt, coverage=None):
+        self.count = np.ascontiguousarray(classes["count"], dtype=np.int64)
+        self.mass = np.ascontiguousarray(classes["mass"], dtype=np.float64)
+        self.charge = np.ascontiguousarray(classes["charge"], dtype=np.float32)
+        self.type = np.ascontiguousarray(classes["type"], dtype=np.int32)
+        self.lj = np.ascontiguousarray(np.asarray(lj, dtype=np.float32))
+        n_cov, R, C = 0, None, None
+        if coverage is not None:
+            R = np.ascontiguousarray(coverage[0], dtype=np.float32)
+            C = np.ascontiguousarray(coverage[1], dtype=np.int64)
+            n_cov = int(R.size)
+        self.R, self.C = R, C
+        self.s = _lib.NbBufferInput(
+            n_classes=int(self.count.size), count=_np_ptr(self.count), mass=_np_ptr(self.mass),
+            charge=_np_ptr(self.charge), type=_np_ptr(self.type), lj=_np_ptr(self.lj),
+            volume=float(volume), temperature=float(temperature), dt=float(dt), n_cov=n_cov,
+            cov_radii=_np_ptr(R) if R is not None else None,
+            covered=_np_ptr(C) if C is not None else None)
+
+
+def buffer_drift(params, classes: dict, lj, volume: float, temperature: float, dt: float,
+                 steps: int, r_list: float, coverage=None) -> float:
+    """Drift (kJ/mol/ps per atom) of a list at r_list used for `steps` steps
+    (nb_buffer_drift).  classes: arrays count, mass, charge, type; coverage: (radii,
+    covered) from Context.list_coverage, or None for a particle list."""
+    lib = _lib.load()
+    a = _BufferArgs(classes, lj, volume, temperature, dt, coverage)
+    out = ctypes.c_double()
+    st = lib.nb_buffer_drift(ctypes.byref(params), ctypes.byref(a.s), int(steps),
+                             float(r_list), ctypes.byref(out))
+    if st != 0:
+        raise NBError(st, "nb_buffer_drift")
+    return out.value
+
+
+def buffer_estimate(params, classes: dict, lj, volume: float, temperature: float, dt: float,
+                    steps: int, tolerance: float = 0.005, max_buffer: float = 1.0,
+                    coverage=None):
+    """(list radius, its drift): the smallest radius within the drift tolerance
+    (nb_buffer_estimate)."""
+    lib = _lib.load()
+    a = _BufferArgs(classes, lj, volume, temperature, dt, coverage)
+    r, d = ctypes.c_double(), ctypes.c_double()
+    st = lib.nb_buffer_estimate(ctypes.byref(params), ctypes.byref(a.s), int(steps),
+                                float(tolerance), float(max_buffer), ctypes.byref(r),
+                                ctypes.byref(d))
+    if st != 0:
+        raise NBError(st, "nb_buffer_estimate")
+    return r.value, d.value
+
+
 class Context:
     """One library context (one or several boxes) on one device and stream."""
 
@@ -49,16 +120,8 @@ class Context:
         self.lib = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
             else torch.device(device)
-        rinner = rc if rinner is None else rinner
-        rlist = rinner if rlist is None else rlist
-        p = _lib.NbParams(n_types=n_types,
-                          coulomb={"rf": _lib.NB_COUL_RF, "ewald": _lib.NB_COUL_EWALD,
-                                   "none": _lib.NB_COUL_NONE}[coulomb],
-                          modifier={"none": _lib.NB_MOD_NONE,
-                                    "potshift": _lib.NB_MOD_POTSHIFT}[modifier],
-                          rc=rc, rinner=rinner, rlist=rlist, eps_r=eps_r, eps_rf=eps_rf,
-                          ewald_beta=beta, epsfac=epsfac, nstlist=nstlist, nstprune=nstprune,
-                          list_capacity_hint=capacity_hint)
+        p = make_params(n_types, coulomb, rc, rinner, rlist, eps_r, eps_rf, beta, epsfac,
+                        modifier, nstlist, nstprune, capacity_hint)
         self.params = p
         self.offsets = np.ascontiguousarray(atom_offsets, dtype=np.int64)
         self.n_sys = self.offsets.size - 1
@@ -268,6 +331,19 @@ class Context:
         self._check(self.lib.nb_list_census(self.h, int(r.size), _np_ptr(r), _np_ptr(out)),
                     "nb_list_census")
         return out.reshape(4, 4, -1)
+
+    def list_coverage(self, radii, m: int = 8, n: int = 8) -> np.ndarray:
+        """Coverage of the current outer list by an m x n list (nb_list_coverage): int64
+        [K, K], [l, k] = atom pairs closer than radii[k] in an m x n sub-cluster pair that
+        holds an atom pair closer than radii[l] (syncs)."""
+        sizes = _lib.CENSUS_SIZES
+        if m not in sizes or n not in sizes:
+            raise ValueError("sub-cluster sizes must be 1, 2, 4 or 8")
+        r = np.ascontiguousarray(np.asarray(radii, dtype=np.float32).reshape(-1))
+        out = np.zeros((max(1, r.size), max(1, r.size)), dtype=np.int64)
+        self._check(self.lib.nb_list_coverage(self.h, sizes.index(m), sizes.index(n), int(r.size),
+                                              _np_ptr(r), _np_ptr(out)), "nb_list_coverage")
+        return out
 
     def stats(self) -> dict:
         s = _lib.NbStats()

@@ -17,8 +17,12 @@
 //   side; DPP where the partner is in the same row of 16 lanes) gives each sub-cluster
 //   pair's bin, which its first lane adds to an LDS histogram per setup.
 //   Each block then writes its histogram.
+// * the same walk with COVER: per lane, the bin k of its own distance and the bin l of its
+//   sub-cluster pair of one chosen setup; a K x K histogram over (l, k) gives, after prefix
+//   sums, the atom pairs closer than R_k that lie in a sub-cluster pair held at R_l (the
+//   implicit buffer of a list at R_l, used by the Verlet buffer estimate).
 // * k_census_sum / k_census_total: the block histograms summed in 64-bit (chunks of blocks,
-//   then the chunks); the host turns bins into counts by a prefix sum.
+//   then the chunks); the host turns bins into counts by prefix sums.
 #include <algorithm>
 #include <cfloat>
 
@@ -29,8 +33,11 @@ namespace {
 
 constexpr int kCensusWaves = 8;
 constexpr int kCensusMaxBlocks = 16384;        // beyond, blocks stride over the items
+constexpr int kCoverMaxBlocks = 2048;          // coverage histograms are 16 KB per block
 constexpr int kCensusSetups = 16;               // (log2 M) * 4 + log2 N
 constexpr int kCensusBins = NB_CENSUS_MAX_RADII;
+constexpr int kHistWords = kCensusSetups * kCensusBins;     // census histogram words
+constexpr int kCoverWords = kCensusBins * kCensusBins;      // coverage histogram words
 
 #define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
@@ -77,22 +84,22 @@ __device__ inline int fold_min(int v, int lane) {
 
 // Histogram one 8x8 cluster pair given each lane's bin (n_radii: not inside any radius).
 template <int A>
-__device__ inline void census_jfold(uint32_t (*hist)[kCensusBins], int bi, int lane,
-                                    int n_radii) {
+__device__ inline void census_jfold(uint32_t* hist, int bi, int lane, int n_radii) {
     const int ii = lane & 7, jj = lane >> 3;
     const bool ilead = (ii & ((1 << A) - 1)) == 0;
     int b2 = bi;
-    if (ilead && b2 < n_radii) atomicAdd(&hist[4 * A + 0][b2], 1u);
+    if (ilead && b2 < n_radii) atomicAdd(&hist[(4 * A + 0) * kCensusBins + b2], 1u);
     b2 = fold_min<8>(b2, lane);
-    if (ilead && (jj & 1) == 0 && b2 < n_radii) atomicAdd(&hist[4 * A + 1][b2], 1u);
+    if (ilead && (jj & 1) == 0 && b2 < n_radii)
+        atomicAdd(&hist[(4 * A + 1) * kCensusBins + b2], 1u);
     b2 = fold_min<16>(b2, lane);
-    if (ilead && (jj & 3) == 0 && b2 < n_radii) atomicAdd(&hist[4 * A + 2][b2], 1u);
+    if (ilead && (jj & 3) == 0 && b2 < n_radii)
+        atomicAdd(&hist[(4 * A + 2) * kCensusBins + b2], 1u);
     b2 = fold_min<32>(b2, lane);
-    if (ilead && jj == 0 && b2 < n_radii) atomicAdd(&hist[4 * A + 3][b2], 1u);
+    if (ilead && jj == 0 && b2 < n_radii) atomicAdd(&hist[(4 * A + 3) * kCensusBins + b2], 1u);
 }
 
-__device__ inline void census_block(uint32_t (*hist)[kCensusBins], int bin, int lane,
-                                    int n_radii) {
+__device__ inline void census_block(uint32_t* hist, int bin, int lane, int n_radii) {
     if (!__builtin_amdgcn_ballot_w64(bin < n_radii)) return;
     census_jfold<0>(hist, bin, lane, n_radii);
     int bi = fold_min<1>(bin, lane);
@@ -103,17 +110,33 @@ __device__ inline void census_block(uint32_t (*hist)[kCensusBins], int bin, int 
     census_jfold<3>(hist, bi, lane, n_radii);
 }
 
-template <int NCH>
+// Coverage of one 8x8 cluster pair for the setup of 2^ca x 2^cb sub-clusters: each lane
+// with bin k < n_radii adds one to [l][k], l the bin of its sub-cluster pair (the smallest
+// lane bin in it, so l <= k): the pair lies in a sub-cluster pair held at radius l.
+__device__ inline void coverage_block(uint32_t* hist, int bin, int lane, int n_radii, int ca,
+                                      int cb) {
+    if (!__builtin_amdgcn_ballot_w64(bin < n_radii)) return;
+    int b = bin;
+    if (ca >= 1) b = fold_min<1>(b, lane);
+    if (ca >= 2) b = fold_min<2>(b, lane);
+    if (ca >= 3) b = fold_min<4>(b, lane);
+    if (cb >= 1) b = fold_min<8>(b, lane);
+    if (cb >= 2) b = fold_min<16>(b, lane);
+    if (cb >= 3) b = fold_min<32>(b, lane);
+    if (bin < n_radii) atomicAdd(&hist[b * kCensusBins + bin], 1u);
+}
+
+template <int NCH, bool COVER>
 __global__ __launch_bounds__(kCensusWaves * kWave) void k_census(
     const NbItem* __restrict__ items, const NbEntry* __restrict__ entries,
     const float4* __restrict__ xw, const float4* __restrict__ cl_bb,
     const NbScInfo* __restrict__ sc_info, const NbSys* __restrict__ sys, int n_items,
-    const float* __restrict__ r2_sorted, int n_radii, int n_pad,
+    const float* __restrict__ r2_sorted, int n_radii, int n_pad, int ca, int cb,
     uint32_t* __restrict__ block_hist) {
 #pragma clang fp contract(off)
-    __shared__ uint32_t hist[kCensusSetups][kCensusBins];
-    for (int t = threadIdx.x; t < kCensusSetups * kCensusBins; t += blockDim.x)
-        hist[t / kCensusBins][t % kCensusBins] = 0u;
+    constexpr int kWords = COVER ? kCoverWords : kHistWords;
+    __shared__ uint32_t hist[kWords];
+    for (int t = threadIdx.x; t < kWords; t += blockDim.x) hist[t] = 0u;
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x & (kWave - 1);
@@ -155,84 +178,86 @@ __global__ __launch_bounds__(kCensusWaves * kWave) void k_census(
                 const float dz = (xi##c.z - oz) - xj.z;                                   \
                 float r2 = (dx * dx + dy * dy) + dz * dz;                                 \
                 if (!(iv##c && jv) || (dc == c && ii >= jj)) r2 = big;                    \
-                census_block(hist, bin_of<NCH>(t, r2_sorted, n_pad, r2), lane, n_radii);         \
+                const int bin = bin_of<NCH>(t, r2_sorted, n_pad, r2);                     \
+                if constexpr (COVER) coverage_block(hist, bin, lane, n_radii, ca, cb);    \
+                else census_block(hist, bin, lane, n_radii);                              \
             }
             NB_FOR8(NB_CB)
 #undef NB_CB
         }
     }
     __syncthreads();
-    uint32_t* out = block_hist + (size_t)blockIdx.x * kCensusSetups * kCensusBins;
-    for (int t = threadIdx.x; t < kCensusSetups * kCensusBins; t += blockDim.x)
-        out[t] = hist[t / kCensusBins][t % kCensusBins];
+    uint32_t* out = block_hist + (size_t)blockIdx.x * kWords;
+    for (int t = threadIdx.x; t < kWords; t += blockDim.x) out[t] = hist[t];
 }
 
 // Two-stage sum of the block histograms (integer, so the order does not matter): stage 1
 // gives each thread kSumRows block rows of one histogram word, stage 2 adds the chunks.
 constexpr int kSumRows = 64;
-constexpr int kHistWords = kCensusSetups * kCensusBins;
 
 __global__ __launch_bounds__(256) void k_census_sum(const uint32_t* __restrict__ block_hist,
-                                                    int n_blocks,
+                                                    int n_blocks, int words,
                                                     unsigned long long* __restrict__ part) {
     const int t = blockIdx.x * 256 + threadIdx.x;          // histogram word
     const int b0 = blockIdx.y * kSumRows;
     const int b1 = min(n_blocks, b0 + kSumRows);
     unsigned long long s = 0;
-    for (int b = b0; b < b1; ++b) s += block_hist[(size_t)b * kHistWords + t];
-    part[(size_t)blockIdx.y * kHistWords + t] = s;
+    for (int b = b0; b < b1; ++b) s += block_hist[(size_t)b * words + t];
+    part[(size_t)blockIdx.y * words + t] = s;
 }
 
 __global__ __launch_bounds__(256) void k_census_total(const unsigned long long* __restrict__ part,
-                                                      int n_chunks,
+                                                      int n_chunks, int words,
                                                       unsigned long long* __restrict__ total) {
     const int t = blockIdx.x * 256 + threadIdx.x;
     unsigned long long s = 0;
-    for (int c = 0; c < n_chunks; ++c) s += part[(size_t)c * kHistWords + t];
+    for (int c = 0; c < n_chunks; ++c) s += part[(size_t)c * words + t];
     total[t] = s;
 }
 
 }  // namespace
 
-int census_blocks(int n_items, int n_cu) {
-    (void)n_cu;
+int census_blocks(int n_items, bool cover) {
     const int need = (n_items + kCensusWaves - 1) / kCensusWaves;   // one item per wavefront
-    return std::max(1, std::min(need, kCensusMaxBlocks));
+    return std::max(1, std::min(need, cover ? kCoverMaxBlocks : kCensusMaxBlocks));
 }
 
-size_t census_hist_words(int n_blocks) {
-    return (size_t)n_blocks * kHistWords;
-}
-
-size_t census_part_words(int n_blocks) {
-    return (size_t)((n_blocks + kSumRows - 1) / kSumRows) * kHistWords;
-}
+size_t census_words(bool cover) { return cover ? kCoverWords : kHistWords; }
 
 hipError_t launch_census(const NbDev& d, int n_items, const float* r2_sorted, int n_radii,
-                         uint32_t* block_hist, int n_blocks, hipStream_t s) {
+                         bool cover, int ca, int cb, uint32_t* block_hist, int n_blocks,
+                         hipStream_t s) {
     const int n_pad = (n_radii + 7) / 8 * 8;     // r2_sorted holds +inf up to n_pad
-#define NB_CENSUS_LAUNCH(NCH)                                                                \
-    hipLaunchKernelGGL(k_census<NCH>, dim3(n_blocks), dim3(kCensusWaves * kWave), 0, s,     \
-                       d.items, d.entries, d.xw, d.cl_bb, d.sc_info, d.sys, n_items,        \
-                       r2_sorted, n_radii, n_pad, block_hist)
-    switch (n_pad / 8) {
-        case 1: NB_CENSUS_LAUNCH(1); break;
-        case 2: NB_CENSUS_LAUNCH(2); break;
-        case 3: NB_CENSUS_LAUNCH(3); break;
-        case 4: NB_CENSUS_LAUNCH(4); break;
-        default: NB_CENSUS_LAUNCH(0); break;
+#define NB_CENSUS_LAUNCH(NCH, COV)                                                           \
+    hipLaunchKernelGGL((k_census<NCH, COV>), dim3(n_blocks), dim3(kCensusWaves * kWave), 0, \
+                       s, d.items, d.entries, d.xw, d.cl_bb, d.sc_info, d.sys, n_items,     \
+                       r2_sorted, n_radii, n_pad, ca, cb, block_hist)
+#define NB_CENSUS_CASES(COV)                                                                 \
+    switch (n_pad / 8) {                                                                     \
+        case 1: NB_CENSUS_LAUNCH(1, COV); break;                                             \
+        case 2: NB_CENSUS_LAUNCH(2, COV); break;                                             \
+        case 3: NB_CENSUS_LAUNCH(3, COV); break;                                             \
+        case 4: NB_CENSUS_LAUNCH(4, COV); break;                                             \
+        default: NB_CENSUS_LAUNCH(0, COV); break;                                            \
     }
+    if (cover) {
+        NB_CENSUS_CASES(true)
+    } else {
+        NB_CENSUS_CASES(false)
+    }
+#undef NB_CENSUS_CASES
 #undef NB_CENSUS_LAUNCH
     return hipGetLastError();
 }
 
-hipError_t launch_census_sum(const uint32_t* block_hist, int n_blocks,
+hipError_t launch_census_sum(const uint32_t* block_hist, int n_blocks, bool cover,
                              unsigned long long* part, unsigned long long* total,
                              hipStream_t s) {
+    const int words = cover ? kCoverWords : kHistWords;
     const int n_chunks = (n_blocks + kSumRows - 1) / kSumRows;
-    hipLaunchKernelGGL(k_census_sum, dim3(kHistWords / 256, n_chunks), dim3(256), 0, s,
-                       block_hist, n_blocks, part);
-    hipLaunchKernelGGL(k_census_total, dim3(kHistWords / 256), dim3(256), 0, s, part, n_chunks,
+    hipLaunchKernelGGL(k_census_sum, dim3(words / 256, n_chunks), dim3(256), 0, s, block_hist,
+                       n_blocks, words, part);
+    hipLaunchKernelGGL(k_census_total, dim3(words / 256), dim3(256), 0, s, part, n_chunks, words,
                        total);
     return hipGetLastError();
 }

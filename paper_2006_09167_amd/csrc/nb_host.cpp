@@ -53,11 +53,11 @@ struct nb_ctx {
     double t_ms[NB_T_COUNT] = {};
     int64_t t_calls[NB_T_COUNT] = {};
     // census buffers (allocated on the first nb_list_census call)
-    uint32_t* census_hist = nullptr;          // [census_hist_words(census_nb)]
-    unsigned long long* census_part = nullptr;   // [census_part_words(census_nb)]
-    unsigned long long* census_total = nullptr;  // [16 * NB_CENSUS_MAX_RADII]
+    uint32_t* census_hist = nullptr;          // [census_hist_n] block histograms
+    unsigned long long* census_part = nullptr;   // [census_part_n] chunk sums
+    unsigned long long* census_total = nullptr;  // [NB_CENSUS_MAX_RADII^2] totals
     float* census_thr = nullptr;              // [NB_CENSUS_MAX_RADII]
-    int census_nb = 0;
+    size_t census_hist_n = 0, census_part_n = 0;
 };
 
 namespace {
@@ -984,9 +984,12 @@ nb_status nb_get_timing(nb_ctx* c, double* ms, int64_t* calls) {
     return NB_OK;
 }
 
-nb_status nb_list_census(nb_ctx* c, int32_t n_radii, const float* radii, int64_t* counts) {
-    if (!c) return NB_ERR_ARG;
-    if (!radii || !counts) return fail(c, NB_ERR_ARG, "null radii or counts");
+namespace {
+
+// One census or coverage walk of the outer list: validates the radii, sorts them (ord maps a
+// sorted position to the caller's index) and returns the summed histogram words.
+nb_status census_run(nb_ctx* c, int32_t n_radii, const float* radii, bool cover, int ca,
+                     int cb, std::vector<int>& ord, std::vector<unsigned long long>& tot) {
     if (n_radii < 1 || n_radii > NB_CENSUS_MAX_RADII)
         return fail(c, NB_ERR_ARG, "n_radii outside [1, NB_CENSUS_MAX_RADII]");
     if (!c->has_list) return fail(c, NB_ERR_STATE, "no pair list");
@@ -994,8 +997,7 @@ nb_status nb_list_census(nb_ctx* c, int32_t n_radii, const float* radii, int64_t
         if (!(radii[k] > 0.f) || !(radii[k] <= c->p.rlist))
             return fail(c, NB_ERR_ARG, "census radius outside (0, rlist]");
     NB_HIP(c, hipSetDevice(c->device));
-    // thresholds in ascending order; counts are scattered back to the caller's order
-    std::vector<int> ord(n_radii);
+    ord.resize(n_radii);
     for (int k = 0; k < n_radii; ++k) ord[k] = k;
     std::vector<float> r2(n_radii);
     for (int k = 0; k < n_radii; ++k) r2[k] = radius_sq(radii[k]);
@@ -1003,25 +1005,41 @@ nb_status nb_list_census(nb_ctx* c, int32_t n_radii, const float* radii, int64_t
     std::vector<float> r2s(NB_CENSUS_MAX_RADII, __builtin_inff());   // +inf padding
     for (int k = 0; k < n_radii; ++k) r2s[k] = r2[ord[k]];
     const int n_items = c->n_items;
-    const int nb = census_blocks(n_items, c->d.n_cu);
-    if (nb > c->census_nb) {
-        NB_HIP(c, dev_alloc(c->census_hist, census_hist_words(nb)));
-        NB_HIP(c, dev_alloc(c->census_part, census_part_words(nb)));
-        c->census_nb = nb;
+    const int nb = census_blocks(n_items, cover);
+    const size_t words = census_words(cover);
+    const size_t need_hist = (size_t)nb * words, need_part = (size_t)((nb + 63) / 64) * words;
+    if (need_hist > c->census_hist_n) {
+        NB_HIP(c, dev_alloc(c->census_hist, need_hist));
+        c->census_hist_n = need_hist;
     }
-    if (!c->census_total) NB_HIP(c, dev_alloc(c->census_total, 16 * NB_CENSUS_MAX_RADII));
+    if (need_part > c->census_part_n) {
+        NB_HIP(c, dev_alloc(c->census_part, need_part));
+        c->census_part_n = need_part;
+    }
+    if (!c->census_total)
+        NB_HIP(c, dev_alloc(c->census_total, (size_t)NB_CENSUS_MAX_RADII * NB_CENSUS_MAX_RADII));
     if (!c->census_thr) NB_HIP(c, dev_alloc(c->census_thr, NB_CENSUS_MAX_RADII));
     NB_HIP(c, hipMemcpyAsync(c->census_thr, r2s.data(), sizeof(float) * r2s.size(),
                              hipMemcpyHostToDevice, c->stream));
     {
         TimedSection ts(c, NB_T_CENSUS);
-        NB_HIP(c, launch_census(c->d, n_items, c->census_thr, n_radii, c->census_hist, nb,
-                                c->stream));
+        NB_HIP(c, launch_census(c->d, n_items, c->census_thr, n_radii, cover, ca, cb,
+                                c->census_hist, nb, c->stream));
     }
-    NB_HIP(c, launch_census_sum(c->census_hist, nb, c->census_part, c->census_total,
+    NB_HIP(c, launch_census_sum(c->census_hist, nb, cover, c->census_part, c->census_total,
                                 c->stream));
-    std::vector<unsigned long long> tot(16 * NB_CENSUS_MAX_RADII);
-    nb_status st = to_host(c, tot.data(), c->census_total, tot.size());
+    tot.assign(words, 0ull);
+    return to_host(c, tot.data(), c->census_total, tot.size());
+}
+
+}  // namespace
+
+nb_status nb_list_census(nb_ctx* c, int32_t n_radii, const float* radii, int64_t* counts) {
+    if (!c) return NB_ERR_ARG;
+    if (!radii || !counts) return fail(c, NB_ERR_ARG, "null radii or counts");
+    std::vector<int> ord;
+    std::vector<unsigned long long> tot;
+    nb_status st = census_run(c, n_radii, radii, false, 0, 0, ord, tot);
     if (st != NB_OK) return st;
     // bin b holds the sub-cluster pairs first inside the b-th smallest radius
     for (int s = 0; s < 16; ++s) {
@@ -1031,6 +1049,33 @@ nb_status nb_list_census(nb_ctx* c, int32_t n_radii, const float* radii, int64_t
             counts[(size_t)s * n_radii + ord[k]] = acc;
         }
     }
+    return NB_OK;
+}
+
+nb_status nb_list_coverage(nb_ctx* c, int32_t log2_m, int32_t log2_n, int32_t n_radii,
+                           const float* radii, int64_t* covered) {
+    if (!c) return NB_ERR_ARG;
+    if (!radii || !covered) return fail(c, NB_ERR_ARG, "null radii or covered");
+    if (log2_m < 0 || log2_m > 3 || log2_n < 0 || log2_n > 3)
+        return fail(c, NB_ERR_ARG, "sub-cluster sizes must be 1, 2, 4 or 8");
+    std::vector<int> ord;
+    std::vector<unsigned long long> tot;
+    nb_status st = census_run(c, n_radii, radii, true, log2_m, log2_n, ord, tot);
+    if (st != NB_OK) return st;
+    // [l][k] (sorted bins): pairs first inside radius k whose sub-cluster pair is first held
+    // at radius l; two prefix sums give pairs inside R_k in sub-cluster pairs held at R_l
+    std::vector<int64_t> cum((size_t)n_radii * n_radii, 0);
+    for (int l = 0; l < n_radii; ++l)
+        for (int k = 0; k < n_radii; ++k) {
+            int64_t v = (int64_t)tot[(size_t)l * NB_CENSUS_MAX_RADII + k];
+            if (l > 0) v += cum[(size_t)(l - 1) * n_radii + k];
+            if (k > 0) v += cum[(size_t)l * n_radii + k - 1];
+            if (l > 0 && k > 0) v -= cum[(size_t)(l - 1) * n_radii + k - 1];
+            cum[(size_t)l * n_radii + k] = v;
+        }
+    for (int l = 0; l < n_radii; ++l)
+        for (int k = 0; k < n_radii; ++k)
+            covered[(size_t)ord[l] * n_radii + ord[k]] = cum[(size_t)l * n_radii + k];
     return NB_OK;
 }
 

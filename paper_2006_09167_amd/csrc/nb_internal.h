@@ -137,16 +137,16 @@ hipError_t launch_reduce_backward(const NbDev& d, float* grad_x, float* grad_q,
                                   double* grad_lj, bool accumulate, int n_slots,
                                   int n_types, int n_items, hipStream_t s);
 
-// Work-efficiency census of the outer list at its build positions (nb_census.hip):
-// r2_sorted holds the ascending squared radii followed by +inf up to a multiple of 8,
-// block_hist census_hist_words(n_blocks) words, part census_part_words(n_blocks), total
-// 16 * NB_CENSUS_MAX_RADII.
-int census_blocks(int n_items, int n_cu);
-size_t census_hist_words(int n_blocks);
-size_t census_part_words(int n_blocks);
+// Work-efficiency census and coverage of the outer list at its build positions
+// (nb_census.hip): r2_sorted holds the ascending squared radii followed by +inf up to a
+// multiple of 8; a call uses census_blocks(n_items, cover) blocks of census_words(cover)
+// histogram words each, then part (one row of words per 64 blocks) and total (words).
+int census_blocks(int n_items, bool cover);
+size_t census_words(bool cover);
 hipError_t launch_census(const NbDev& d, int n_items, const float* r2_sorted, int n_radii,
-                         uint32_t* block_hist, int n_blocks, hipStream_t s);
-hipError_t launch_census_sum(const uint32_t* block_hist, int n_blocks,
+                         bool cover, int ca, int cb, uint32_t* block_hist, int n_blocks,
+                         hipStream_t s);
+hipError_t launch_census_sum(const uint32_t* block_hist, int n_blocks, bool cover,
                              unsigned long long* part, unsigned long long* total,
                              hipStream_t s);
 
