@@ -66,6 +66,12 @@ WORKLOADS = {
                                 "outer list at 1.45 nm, census of M x N sub-cluster lists "
                                 "(M, N in 1, 2, 4, 8) for cut-offs 0.9, 1.0, 1.2 nm and "
                                 "buffers 0 ... 0.25 nm",
+    "water96k_verlet_buffer": "96,000-atom water-like box (the water96k_ewald system), list "
+                              "coverage by 8x8 and 8x4 cluster pairs at 64 radii (r_c + "
+                              "0.01 k nm; timed at r_c = 0.9 nm) and the tolerance-based "
+                              "Verlet buffer estimate "
+                              "(0.005 kJ/mol/ps per atom, 300 K, 2 fs) for the particle and "
+                              "cluster lists",
     "ensemble256_rf": "256 independent water-like replicas of 3k-24k atoms (log-uniform, "
                       "2.63M atoms in all, density 100/nm^3) in one context, reaction field "
                       "rc=0.9 nm, rlist=1.0 nm every 100 steps, rinner=0.94 nm rolling prune "
@@ -380,6 +386,126 @@ def work_efficiency_curves(args):
     print(json.dumps(result), flush=True)
 
 
+BUF_TOL = 0.005          # kJ/mol/ps per atom: the paper's default drift tolerance
+BUF_T, BUF_DT = 300.0, 0.002
+BUF_RIGID_MASS = 18.015  # a rigid water molecule carries each of its atoms
+BUF_FREE_MASS = (15.9994, 1.008)
+
+
+def verlet_buffer(args):
+    """The Verlet buffer estimate (Sec. V.B) with the cluster implicit buffer measured by
+    the coverage kernel: the list radius a particle list and the 8x8 / 8x4 cluster lists
+    need for the same drift tolerance, at the paper's buffer-comparison setting (r_c 0.9 nm,
+    list every 40 steps) and at the dual-list setting of the 96k workload (outer list every
+    100 steps, rolling prune in 4 parts).  Timed: the coverage kernel."""
+    import numpy as np
+    import torch
+    from paper_2006_09167_amd import api, systems
+    from paper_2006_09167_amd.api import Context
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    s = systems.config_system("water96k_ewald")
+    N = s.n
+    x = torch.from_numpy(s.x).to(dev)
+    V = float(np.prod(s.box.astype(np.float64)))
+    n_o = int(np.sum(s.type == 0))
+    rigid = dict(count=[n_o, N - n_o], mass=[BUF_RIGID_MASS] * 2, charge=[-0.82, 0.41],
+                 type=[0, 1])
+    free = dict(rigid, mass=list(BUF_FREE_MASS))
+    K = args.steps if args.steps is not None else 20
+    W = min(args.warmup, 5)
+    # (name, r_c, Ewald beta, table step, mass readings, [(list, steps)])
+    settings = [("paper_buffer_comparison", 0.9, 3.47, 0.01, ("rigid", "free"), [("list", 40)]),
+                ("dual_list_96k", 1.0, 3.12, 0.005, ("rigid",), [("outer", 100), ("inner", 4)])]
+    out, timing = {}, None
+    for name, rc, beta, step, readings, lists in settings:
+        radii = (np.float32(rc) + np.float32(step) * np.arange(64, dtype=np.float32)).astype(np.float32)
+        ctx = Context(n_types=s.lj.shape[0], coulomb="ewald", rc=rc, beta=beta,
+                      rinner=float(radii[-1]), rlist=float(radii[-1]), atom_offsets=[0, N],
+                      device=dev)
+        ctx.set_topology(s.type, s.excl_ptr, s.excl_idx)
+        ctx.grid_build(x, s.box[None])
+        ctx.pairlist_build()
+        st = ctx.stats()
+        if timing is None:
+            for _ in range(W):
+                ctx.list_coverage(radii, 8, 8)
+            ctx.set_timing(True)
+            t0 = time.perf_counter()
+            for _ in range(K):
+                ctx.list_coverage(radii, 8, 8)
+            wall = (time.perf_counter() - t0) / K
+            tm = ctx.get_timing()
+            ctx.set_timing(False)
+            kern = tm["census"][0] * 1e-3 / max(tm["census"][1], 1)
+            timing = dict(wall=wall, kern=kern, slots=64.0 * st["outer_pairs"],
+                          rlist=float(radii[-1]), setting=name)
+        cov = {"8x8": ctx.list_coverage(radii, 8, 8), "8x4": ctx.list_coverage(radii, 8, 4)}
+        p = api.make_params(int(s.lj.shape[0]), "ewald", rc=rc, beta=beta)
+        rc32 = float(np.float32(rc))
+        res = {"rc": rc, "ewald_beta": beta, "table": "%d radii, r_c + %.3f k nm" % (64, step)}
+        for lname, steps in lists:
+            for reading in readings:
+                classes = rigid if reading == "rigid" else free
+                r = {}
+                for setup, table in [("1x1", None)] + list(cov.items()):
+                    kw = {} if table is None else {"coverage": (radii, table)}
+                    try:
+                        rl, d = api.buffer_estimate(p, classes, s.lj, V, BUF_T, BUF_DT, steps,
+                                                    BUF_TOL, max_buffer=float(radii[-1]) - rc32,
+                                                    **kw)
+                        r[setup] = {"r_list": round(rl, 4), "buffer_nm": round(rl - rc32, 4),
+                                    "drift": d}
+                    except RuntimeError:                 # not reached inside the table
+                        r[setup] = None
+                res["%s_steps_%d_%s_masses" % (lname, steps, reading)] = r
+                log("%s %s (%d steps, %s masses): %s" % (
+                    name, lname, steps, reading,
+                    {k: (v["buffer_nm"] if v else None) for k, v in r.items()}))
+        out[name] = res
+        del ctx
+    kern = timing["kern"]
+    achieved = timing["slots"] * FLOP_PER_SLOT_CENSUS / kern
+    result = {
+        "metric": "coverage pair slots/s (8x8 cluster-pair slots of the outer list classified "
+                  "for the Verlet buffer estimate)",
+        "value": timing["slots"] / timing["wall"], "unit": "pair slots/s",
+        "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": 1e3 * timing["wall"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]),
+                   "atoms": N, "radii": 64, "tolerance": BUF_TOL, "temperature": BUF_T,
+                   "dt_ps": BUF_DT, "timed_list_radius": timing["rlist"],
+                   "timed_setting": timing["setting"],
+                   "mass_readings": {"rigid": "18.015 for every atom (molecule translates)",
+                                     "free": "O 15.9994, H 1.008 (free flight)"}},
+        "buffers": out,
+        "roofline": {"bound": "alu", "kernel": "k_census<0, cover>",
+                     "flop_per_slot": FLOP_PER_SLOT_CENSUS, "achieved": achieved / 1e12,
+                     "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
+                     "traffic": None, "avg_launch_us": 1e6 * kern},
+    }
+    log("coverage: %.3f ms per call, kernel %.1f us" % (1e3 * timing["wall"], 1e6 * kern))
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        g = oracle.grid_spec.build_grid(s.x, s.box[None], np.array([0, N]))
+        n_cl = g["slot_atom"].size // 8
+        hi = n_cl // 2                                   # half of the i-clusters
+        radii = (np.float32(0.9) + np.float32(0.01) * np.arange(64, dtype=np.float32)).astype(np.float32)
+        t0 = time.perf_counter()
+        c_or = oracle.buffer.coverage(g["slot_atom"], g["w"], s.box, radii, 8, 8, ci_lo=0,
+                                      ci_hi=hi)
+        dt = time.perf_counter() - t0
+        n_trip = oracle.cluster_pairs(g["slot_atom"], g["w"], s.box, float(radii[-1]), 0, hi).size
+        result["cpu_baseline"] = {"value": 64.0 * n_trip / dt, "unit": "pair slots/s",
+                                  "cores": oracle.num_threads(), "kind": "oracle",
+                                  "sample": "numpy coverage (8x8, 64 radii) of the i-clusters "
+                                            "0..%d of %d" % (hi, n_cl), "seconds": dt}
+        log("oracle coverage sample %.2f s" % dt)
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -415,6 +541,9 @@ def main():
         return
     if args.workload == "water96k_work_efficiency":
         work_efficiency_curves(args)
+        return
+    if args.workload == "water96k_verlet_buffer":
+        verlet_buffer(args)
         return
 
     dev = torch.device("cuda", 0)

@@ -40,8 +40,10 @@ WINDOW = 10.0                  # Gaussian widths integrated on each side
 # ---------------------------------------------------------------------------------------
 # Coverage of a list by M x N sub-cluster pairs.
 # ---------------------------------------------------------------------------------------
-def coverage(slot_atom, w, box, radii, M: int, N: int, chunk: int = 1 << 15) -> np.ndarray:
-    """[K, K] counts (module docstring).  Per cluster triple within the largest radius: the
+def coverage(slot_atom, w, box, radii, M: int, N: int, chunk: int = 1 << 15, ci_lo: int = 0,
+             ci_hi=None) -> np.ndarray:
+    """[K, K] counts (module docstring), over the triples whose i-cluster lies in
+    [ci_lo, ci_hi) (all by default).  Per cluster triple within the largest radius: the
     smallest r2 of each M x N sub-cluster pair decides the radii at which it is held, each
     atom pair's own r2 the radii it lies within; a 2-d count over (first held radius, first
     radius the pair is within), summed cumulatively over both indices."""
@@ -53,7 +55,7 @@ def coverage(slot_atom, w, box, radii, M: int, N: int, chunk: int = 1 << 15) -> 
     slot_atom = np.asarray(slot_atom)
     n_cl = slot_atom.size // 8
     hist = np.zeros((K + 1, K + 1), dtype=np.int64)
-    keys = cluster_pairs(slot_atom, w, box, float(radii.max()))
+    keys = cluster_pairs(slot_atom, w, box, float(radii.max()), ci_lo, ci_hi)
     ci, cj, code = split_key(keys, n_cl)
     for p0 in range(0, keys.size, chunk):
         r2 = pair_r2(slot_atom, w, box, ci[p0:p0 + chunk], cj[p0:p0 + chunk],
