@@ -44,51 +44,39 @@ __device__ inline void neumaier(float& s, float& c, float v) {
     s = t;
 }
 
-// One wavefront per cluster: lane (k0 = l >> 3, jj = l & 7) sums, with compensation, the
-// j-partials k0, k0 + 8, ... of the entries referencing the cluster (contiguous, 1 KB per
-// step) and the i-partials of the super-cluster's items k0, k0 + 8, ...; the eight
-// k0-lanes are combined in a fixed butterfly order and lanes 0..7 write the atom's force
-// in the caller's order.
+// One wavefront per super-cluster, lane = slot within it (cluster c = l >> 3, atom jj = l &
+// 7): each lane sums, with compensation, the j-partials of the entries referencing its
+// cluster (a contiguous segment, in entry order) and then the i-partials of the
+// super-cluster's items (in item order; one 1 KB row per item, read by the whole wavefront),
+// and writes its atom's force in the caller's order.  No lanes are combined, so there is no
+// cross-lane traffic, and the order of every sum is fixed.
 constexpr int kRedWaves = 4;
-__device__ __forceinline__ void reduce_cluster(
-    const int cj, const int32_t* __restrict__ slot_atom, const int32_t* __restrict__ jseg_start,
+__device__ __forceinline__ void reduce_sc(
+    const int sc, const int32_t* __restrict__ slot_atom, const int32_t* __restrict__ jseg_start,
     const float4* __restrict__ jpart, const int32_t* __restrict__ sc_istart,
     const int32_t* __restrict__ sc_icount, const float4* __restrict__ ipart,
     float* __restrict__ f, int accumulate) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int jj = lane & 7, k0 = lane >> 3;
-    const int slot = cj * kClusterSize + jj;
-    const int sc = cj >> 3, loc = slot & (kScAtoms - 1);
+    const int jj = lane & 7;
+    const int cj = sc * kClustersPerSc + (lane >> 3);
+    const int slot = sc * kScAtoms + lane;
     const int s0 = jseg_start[cj], s1 = jseg_start[cj + 1];
     const int i0 = sc_istart[sc], i1 = i0 + sc_icount[sc];
     float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
-    // lane (k0, jj): j-partials k0, k0 + 8, ... of the segment, then i-partials of the
-    // super-cluster's items i0 + k0, i0 + k0 + 8, ... (all loads independent)
-#pragma unroll 8
-    for (int k = s0 + k0; k < s1; k += 8) {
+#pragma unroll 4
+    for (int k = s0; k < s1; ++k) {
         const float4 v = jpart[(size_t)k * kClusterSize + jj];
         neumaier(sx, cx, v.x);
         neumaier(sy, cy, v.y);
         neumaier(sz, cz, v.z);
     }
 #pragma unroll 2
-    for (int i = i0 + k0; i < i1; i += 8) {
-        const float4 v = ipart[(size_t)i * kScAtoms + loc];
+    for (int i = i0; i < i1; ++i) {
+        const float4 v = ipart[(size_t)i * kScAtoms + lane];
         neumaier(sx, cx, v.x);
         neumaier(sy, cy, v.y);
         neumaier(sz, cz, v.z);
     }
-    for (int off = 8; off < kWave; off <<= 1) {   // combine (sum, compensation) pairs
-        const float px = __shfl_xor(sx, off), py = __shfl_xor(sy, off), pz = __shfl_xor(sz, off);
-        const float qx = __shfl_xor(cx, off), qy = __shfl_xor(cy, off), qz = __shfl_xor(cz, off);
-        neumaier(sx, cx, px);
-        neumaier(sy, cy, py);
-        neumaier(sz, cz, pz);
-        cx += qx;
-        cy += qy;
-        cz += qz;
-    }
-    if (k0 != 0) return;
     const int a = slot_atom[slot];
     if (a < 0) return;
     float rx = sx + cx, ry = sy + cy, rz = sz + cz;
@@ -131,12 +119,12 @@ __device__ inline void energy_totals(const NbDev& d, double* __restrict__ energy
 }
 
 // Force reduction and the energy reduction in one launch: blocks [0, n_fblk) reduce the
-// forces of four clusters each (one wavefront per cluster), blocks [n_fblk, n_fblk +
+// forces of four super-clusters each (one wavefront per super-cluster), blocks [n_fblk, n_fblk +
 // n_chunks) sum one energy chunk each; the last energy block to finish (a ticket in
 // queue[2], taken after a device-scope fence) adds the chunk partials per system and
 // resets the ticket for the next launch.
 __global__ __launch_bounds__(kRedThreads) void k_reduce_step(NbDev d, float* __restrict__ f,
-                                                             int accumulate, int n_cl,
+                                                             int accumulate, int n_sc,
                                                              int n_fblk, double* energy,
                                                              double* virial, uint32_t flags,
                                                              int n_sys) {
@@ -158,10 +146,10 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_step(NbDev d, float* __r
         }
         return;
     }
-    const int cj = blockIdx.x * kRedWaves + (int)(threadIdx.x / kWave);
-    if (cj >= n_cl) return;
-    reduce_cluster(cj, d.slot_atom, d.jseg_start, d.jpart, d.sc_istart, d.sc_icount, d.ipart, f,
-                   accumulate);
+    const int sc = blockIdx.x * kRedWaves + (int)(threadIdx.x / kWave);
+    if (sc >= n_sc) return;
+    reduce_sc(sc, d.slot_atom, d.jseg_start, d.jpart, d.sc_istart, d.sc_icount, d.ipart, f,
+              accumulate);
 }
 
 // Per-system totals when there is no chunk to reduce (no work items).
@@ -185,13 +173,13 @@ hipError_t launch_gather(const NbDev& d, const float* x, const float* q, float4*
 hipError_t launch_reduce(const NbDev& d, float* f, bool accumulate, int n_slots,
                         double* energy, double* virial, uint32_t flags, int n_sys,
                         hipStream_t s) {
-    const int n_cl = n_slots / kClusterSize;
-    const int n_fblk = blocks(n_cl, kRedWaves);
+    const int n_sc = n_slots / kScAtoms;
+    const int n_fblk = blocks(n_sc, kRedWaves);
     const bool ev = (flags & (NB_F_ENERGY | NB_F_VIRIAL)) && n_sys > 0;
     const int n_eblk = ev ? d.n_chunks : 0;
     if (n_fblk + n_eblk > 0)
         hipLaunchKernelGGL(k_reduce_step, dim3(n_fblk + n_eblk), dim3(kRedThreads), 0, s, d, f,
-                           accumulate ? 1 : 0, n_cl, n_fblk, energy, virial, flags, n_sys);
+                           accumulate ? 1 : 0, n_sc, n_fblk, energy, virial, flags, n_sys);
     if (ev && n_eblk == 0)
         hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kRedThreads), 0, s, d, energy, virial,
                            flags, n_sys);
