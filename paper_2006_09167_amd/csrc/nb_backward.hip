@@ -314,25 +314,24 @@ __device__ inline void neumaier(float& s, float& c, float v) {
     s = t;
 }
 
-// One wavefront per cluster, as the force reduction: lanes (k0, jj) sum the j-partials
-// k0, k0 + 8, ... and the i-partials of items k0, k0 + 8, ... with compensation, a fixed
-// butterfly combines the k0-lanes, and lanes 0..7 write dL/dx and dL/dq in the caller's
-// atom order.
+// One wavefront per super-cluster, as the force reduction: each lane (slot) sums with
+// compensation the j-partials of its cluster's segment and then the super-cluster's item
+// rows, in a fixed order, and writes dL/dx and dL/dq in the caller's atom order.
 constexpr int kRedWaves = 4;
-__device__ inline void reduce_bwd_cluster(
-    int cj, const int32_t* __restrict__ slot_atom, const int32_t* __restrict__ jseg_start,
+__device__ inline void reduce_bwd_sc(
+    int sc, const int32_t* __restrict__ slot_atom, const int32_t* __restrict__ jseg_start,
     const float4* __restrict__ jpart, const int32_t* __restrict__ sc_istart,
     const int32_t* __restrict__ sc_icount, const float4* __restrict__ ipart,
     float* __restrict__ gx, float* __restrict__ gq, int accumulate) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int jj = lane & 7, k0 = lane >> 3;
-    const int slot = cj * kClusterSize + jj;
-    const int sc = cj >> 3, loc = slot & (kScAtoms - 1);
+    const int jj = lane & 7;
+    const int cj = sc * kClustersPerSc + (lane >> 3);
+    const int slot = sc * kScAtoms + lane;
     const int s0 = jseg_start[cj], s1 = jseg_start[cj + 1];
     const int i0 = sc_istart[sc], i1 = i0 + sc_icount[sc];
     float s[4] = {0, 0, 0, 0}, cmp[4] = {0, 0, 0, 0};
 #pragma unroll 4
-    for (int k = s0 + k0; k < s1; k += 8) {
+    for (int k = s0; k < s1; ++k) {
         const float4 v = jpart[(size_t)k * kClusterSize + jj];
         neumaier(s[0], cmp[0], v.x);
         neumaier(s[1], cmp[1], v.y);
@@ -340,22 +339,13 @@ __device__ inline void reduce_bwd_cluster(
         neumaier(s[3], cmp[3], v.w);
     }
 #pragma unroll 2
-    for (int i = i0 + k0; i < i1; i += 8) {
-        const float4 v = ipart[(size_t)i * kScAtoms + loc];
+    for (int i = i0; i < i1; ++i) {
+        const float4 v = ipart[(size_t)i * kScAtoms + lane];
         neumaier(s[0], cmp[0], v.x);
         neumaier(s[1], cmp[1], v.y);
         neumaier(s[2], cmp[2], v.z);
         neumaier(s[3], cmp[3], v.w);
     }
-    for (int off = 8; off < kWave; off <<= 1) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float ps = __shfl_xor(s[q], off), pc = __shfl_xor(cmp[q], off);
-            neumaier(s[q], cmp[q], ps);
-            cmp[q] += pc;
-        }
-    }
-    if (k0 != 0) return;
     const int a = slot_atom[slot];
     if (a < 0) return;
     if (gx) {
@@ -392,13 +382,13 @@ __device__ inline void glj_totals(const NbDev& d, double* __restrict__ out, int 
 }
 
 // Input-gradient reduction and the table-gradient reduction in one launch: blocks
-// [0, n_gblk) reduce four clusters each (one wavefront per cluster), blocks [n_gblk,
+// [0, n_gblk) reduce four super-clusters each (one wavefront per super-cluster), blocks [n_gblk,
 // n_gblk + n_chunks) sum kChunkItems item ranks of the table-gradient partials each; the
 // last of those to finish (a ticket in queue[3], taken after a device-scope fence) forms
 // the totals and resets the ticket for the next launch.
 __global__ __launch_bounds__(kRedThreads) void k_reduce_bwd_step(
     NbDev d, float* __restrict__ gx, float* __restrict__ gq, double* __restrict__ glj,
-    int accumulate, int n_cl, int n_gblk, int n_types, int n_items, int n_chunks) {
+    int accumulate, int n_sc, int n_gblk, int n_types, int n_items, int n_chunks) {
     static_assert(kRedThreads == kRedWaves * kWave, "one block shape for both parts");
     if ((int)blockIdx.x >= n_gblk) {
         const int c = blockIdx.x - n_gblk;
@@ -417,10 +407,10 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_bwd_step(
         }
         return;
     }
-    const int cj = blockIdx.x * kRedWaves + (int)(threadIdx.x / kWave);
-    if (cj >= n_cl) return;
-    reduce_bwd_cluster(cj, d.slot_atom, d.jseg_start, d.jpart, d.sc_istart, d.sc_icount,
-                       d.ipart, gx, gq, accumulate);
+    const int sc = blockIdx.x * kRedWaves + (int)(threadIdx.x / kWave);
+    if (sc >= n_sc) return;
+    reduce_bwd_sc(sc, d.slot_atom, d.jseg_start, d.jpart, d.sc_istart, d.sc_icount, d.ipart, gx,
+                  gq, accumulate);
 }
 
 // Table gradient totals when there is no item (all zero, or the outputs kept).
@@ -494,12 +484,12 @@ hipError_t launch_backward(const NbDev& d, const NbKParams& kp, int coulomb, con
 hipError_t launch_reduce_backward(const NbDev& d, float* grad_x, float* grad_q, double* grad_lj,
                                   bool accumulate, int n_slots, int n_types, int n_items,
                                   hipStream_t s) {
-    const int n_cl = n_slots / kClusterSize;
-    const int n_gblk = (grad_x || grad_q) ? blocks(n_cl, kRedWaves) : 0;
+    const int n_sc = n_slots / kScAtoms;
+    const int n_gblk = (grad_x || grad_q) ? blocks(n_sc, kRedWaves) : 0;
     const int n_chunks = grad_lj ? blocks(n_items, kChunkItems) : 0;
     if (n_gblk + n_chunks > 0)
         hipLaunchKernelGGL(k_reduce_bwd_step, dim3(n_gblk + n_chunks), dim3(kRedThreads), 0, s,
-                           d, grad_x, grad_q, grad_lj, accumulate ? 1 : 0, n_cl, n_gblk,
+                           d, grad_x, grad_q, grad_lj, accumulate ? 1 : 0, n_sc, n_gblk,
                            n_types, n_items, n_chunks);
     if (grad_lj && n_chunks == 0)
         hipLaunchKernelGGL(k_glj_final, dim3(1), dim3(kRedThreads), 0, s, d, grad_lj, n_types,
