@@ -326,54 +326,58 @@ __global__ __launch_bounds__(kWave) void k_jseg_rank(NbDev d) {
     }
 }
 
-constexpr int kPruneWaves = 4;
-constexpr int kPruneEntriesPerWave = 4;  // wavefronts per item: item width / 4, rounded up
+constexpr int kPruneWaves = 4;                  // wavefronts per item (one block per item)
 #define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
-// Rolling prune (Sec. V.E) of a range of work items: two wavefronts per item taking
-// alternate entries, the item's eight i-clusters loaded once per wavefront, entries
-// processed in order with the next two entries' j-clusters in flight.  For every i-cluster of the outer mask the inner bit is set iff
+// Rolling prune (Sec. V.E) of a range of work items: one block per item, whose 64 i-atoms
+// are staged once in LDS (one load per lane) and whose entries are dealt to the block's
+// wavefronts in turn, each processing its entries in order with the next four entries'
+// j-clusters in flight.  For every i-cluster of the outer mask the inner bit is set iff
 // some atom pair is closer than r_inner in the list arithmetic (shift split between the
 // two sides, no contraction).  Empty slots sit far outside the box, so no valid-atom masks
 // are needed; a cluster with itself keeps ii < jj.
 __global__ __launch_bounds__(kPruneWaves * kWave) void k_prune(
     const NbItem* __restrict__ items, NbEntry* __restrict__ entries,
     const float4* __restrict__ xp, const NbScInfo* __restrict__ sc_info,
-    const NbSys* __restrict__ sys, int item0, int n_items, float r2_inner, int split) {
+    const NbSys* __restrict__ sys, int item0, float r2_inner) {
 #pragma clang fp contract(off)
+    __shared__ float4 s_xi[kScAtoms];
+    const NbItem it = items[item0 + blockIdx.x];
+    if (threadIdx.x < kScAtoms) s_xi[threadIdx.x] = xp[kScAtoms * it.sc + threadIdx.x];
+    __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x & (kWave - 1);
-    const int kw = blockIdx.x * kPruneWaves + wave;
-    const int k = kw / split, part = kw % split;   // wavefront `part` takes every split-th entry
-    if (k >= n_items) return;
-    const NbItem it = items[item0 + k];
     const int ii = lane & 7, jj = lane >> 3;
+    const int e_end = it.e0 + it.ne;
+    const int e_first = it.e0 + wave;
+    if (e_first >= e_end) return;
     const NbSys S = sys[sc_info[it.sc].sys];
     const int ci0 = kClustersPerSc * it.sc;
-#define NB_PI(c) const float4 xi##c = xp[kScAtoms * it.sc + kClusterSize * c + ii];
+#define NB_PI(c) const float4 xi##c = s_xi[kClusterSize * c + ii];
     NB_FOR8(NB_PI)
 #undef NB_PI
-    const int e_end = it.e0 + it.ne;
-    const int e_first = it.e0 + part;
-    if (e_first >= e_end) return;
-    const int kStep = split;
-    // two entries ahead: (ent1, xj1) is the next one, (ent2, xj2) the one after
-    NbEntry ent1 = entries[e_first];
-    float4 xj1 = xp[kClusterSize * ent1.cj + jj];
-    NbEntry ent2 = ent1;
-    float4 xj2 = xj1;
-    if (e_first + kStep < e_end) {
-        ent2 = entries[e_first + kStep];
-        xj2 = xp[kClusterSize * ent2.cj + jj];
+    const int kStep = kPruneWaves;
+    // a ring of the next kAhead entries and their j-clusters, loaded in flight
+    constexpr int kAhead = 4;
+    NbEntry en[kAhead];
+    float4 xq[kAhead];
+#pragma unroll
+    for (int a = 0; a < kAhead; ++a) {
+        const int ea = e_first + a * kStep;
+        en[a] = entries[ea < e_end ? ea : e_first];
+        xq[a] = xp[kClusterSize * en[a].cj + jj];
     }
     for (int e = e_first; e < e_end; e += kStep) {
-        const NbEntry ent = ent1;
-        float4 xj = xj1;
-        ent1 = ent2;
-        xj1 = xj2;
-        if (e + 2 * kStep < e_end) {
-            ent2 = entries[e + 2 * kStep];
-            xj2 = xp[kClusterSize * ent2.cj + jj];
+        const NbEntry ent = en[0];
+        float4 xj = xq[0];
+#pragma unroll
+        for (int a = 0; a + 1 < kAhead; ++a) {
+            en[a] = en[a + 1];
+            xq[a] = xq[a + 1];
+        }
+        if (e + kAhead * kStep < e_end) {
+            en[kAhead - 1] = entries[e + kAhead * kStep];
+            xq[kAhead - 1] = xp[kClusterSize * en[kAhead - 1].cj + jj];
         }
         const int code = ent.meta & 31u;
         const uint32_t omask = (ent.meta >> 8) & 0xffu;
@@ -503,11 +507,9 @@ hipError_t launch_list_finish(const NbDev& d, int n_sc, int64_t n_entries, int n
 
 hipError_t launch_prune(const NbDev& d, const float4* coords, int item0, int n_items,
                         float r2_inner, int item_width, hipStream_t s) {
-    const int split = std::max(1, (item_width + kPruneEntriesPerWave - 1) / kPruneEntriesPerWave);
+    (void)item_width;
     if (n_items > 0)
-        hipLaunchKernelGGL(k_prune, dim3(blocks((int64_t)n_items * split, kPruneWaves)),
-                           dim3(kPruneWaves * kWave),
-                           0, s, d.items, d.entries, coords, d.sc_info, d.sys, item0, n_items,
-                           r2_inner, split);
+        hipLaunchKernelGGL(k_prune, dim3(n_items), dim3(kPruneWaves * kWave), 0, s, d.items,
+                           d.entries, coords, d.sc_info, d.sys, item0, r2_inner);
     return hipGetLastError();
 }
