@@ -11,8 +11,9 @@
 //
 // * k_census: one wavefront per work item (the item's eight i-clusters loaded once).  Per
 //   cluster pair every lane takes the bin of its squared distance, the number of sorted
-//   thresholds R_k^2 at or below it (compares against wave-uniform thresholds); a sub-cluster
-//   pair holds a pair closer than R_k iff the smallest bin of its lanes is <= k, so folding
+//   thresholds R_k^2 at or below it (a two-level count: chunk pivots, then one chunk); a
+//   sub-cluster pair holds a pair closer than R_k iff the smallest bin of its lanes is <= k,
+//   so folding
 //   the lane bins with min over lane-xor partners (1, 2, 4 on the i side, 8, 16, 32 on the j
 //   side; DPP where the partner is in the same row of 16 lanes) gives each sub-cluster
 //   pair's bin, which its first lane adds to an LDS histogram per setup.
@@ -41,29 +42,27 @@ constexpr int kCoverWords = kCensusBins * kCensusBins;      // coverage histogra
 
 #define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
-// Number of thresholds at or below v (v finite).  The thresholds are wave-uniform, padded
-// with +inf to NCH chunks of 8: with NCH > 0 they are loaded once per wavefront into scalar
-// registers (t), otherwise read per use from memory (tp, n_pad entries).  For finite floats
+// Number of thresholds at or below v (v finite), for NCH chunks of 8 ascending thresholds
+// padded with +inf.  Two levels: the last threshold of each chunk (pivots, wave-uniform, in
+// scalar registers) gives the chunk g holding v's place, since every threshold of the
+// chunks before g is at or below its pivot <= v and every one after is at or above a pivot
+// > v; then the first seven thresholds of chunk g, read from LDS (two 16-byte reads; the
+// table carries one more chunk of +inf for g = NCH), finish the count.  For finite floats
 // v - t is +0 when v == t and keeps the sign of the exact difference, so t <= v iff the sign
-// bit of v - t is clear (an +inf pad gives -inf): each threshold costs a subtraction, a
-// shift and an add per lane, with no compare-to-carry hazard and no LDS traffic.
+// bit of v - t is clear: each comparison costs a subtraction, a shift and an add.
 __device__ inline int below(float v, float t) { return (int)(__float_as_uint(v - t) >> 31); }
 
 template <int NCH>
-__device__ inline int bin_of(const float* t, const float* __restrict__ tp, int n_pad,
-                             float v) {
+__device__ inline int bin_of(const float* piv, const float* s_thr, float v) {
     int neg = 0;
-    if constexpr (NCH > 0) {
 #pragma unroll
-        for (int k = 0; k < 8 * NCH; ++k) neg += below(v, t[k]);
-        return 8 * NCH - neg;
-    } else {
-        for (int k0 = 0; k0 < n_pad; k0 += 8) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) neg += below(v, tp[k0 + k]);
-        }
-        return n_pad - neg;
-    }
+    for (int c = 0; c < NCH; ++c) neg += below(v, piv[c]);
+    const int g = NCH - neg;
+    const float4 a = *reinterpret_cast<const float4*>(s_thr + 8 * g);
+    const float4 b = *reinterpret_cast<const float4*>(s_thr + 8 * g + 4);
+    const int m = below(v, a.x) + below(v, a.y) + below(v, a.z) + below(v, a.w) +
+                  below(v, b.x) + below(v, b.y) + below(v, b.z);
+    return 8 * g + 7 - m;
 }
 
 // min(v, v of the lane whose index differs in the given bit): DPP inside a row of 16 lanes
@@ -136,15 +135,18 @@ __global__ __launch_bounds__(kCensusWaves * kWave) void k_census(
 #pragma clang fp contract(off)
     constexpr int kWords = COVER ? kCoverWords : kHistWords;
     __shared__ uint32_t hist[kWords];
+    __shared__ __attribute__((aligned(16))) float s_thr[8 * (NCH + 1)];
     for (int t = threadIdx.x; t < kWords; t += blockDim.x) hist[t] = 0u;
+    for (int t = threadIdx.x; t < 8 * (NCH + 1); t += blockDim.x)
+        s_thr[t] = (t < n_pad) ? r2_sorted[t] : __builtin_inff();
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x & (kWave - 1);
     const int ii = lane & 7, jj = lane >> 3;
     const float big = FLT_MAX;                     // a pair not counted: above every radius
-    float t[NCH > 0 ? 8 * NCH : 1];
+    float piv[NCH];                                // last threshold of each chunk of 8
 #pragma unroll
-    for (int k = 0; k < (NCH > 0 ? 8 * NCH : 1); ++k) t[k] = r2_sorted[k];
+    for (int c = 0; c < NCH; ++c) piv[c] = r2_sorted[8 * c + 7];
     for (int k = blockIdx.x * kCensusWaves + wave; k < n_items;
          k += gridDim.x * kCensusWaves) {
         const NbItem it = items[k];
@@ -178,7 +180,7 @@ __global__ __launch_bounds__(kCensusWaves * kWave) void k_census(
                 const float dz = (xi##c.z - oz) - xj.z;                                   \
                 float r2 = (dx * dx + dy * dy) + dz * dz;                                 \
                 if (!(iv##c && jv) || (dc == c && ii >= jj)) r2 = big;                    \
-                const int bin = bin_of<NCH>(t, r2_sorted, n_pad, r2);                     \
+                const int bin = bin_of<NCH>(piv, s_thr, r2);                              \
                 if constexpr (COVER) coverage_block(hist, bin, lane, n_radii, ca, cb);    \
                 else census_block(hist, bin, lane, n_radii);                              \
             }
@@ -238,7 +240,10 @@ hipError_t launch_census(const NbDev& d, int n_items, const float* r2_sorted, in
         case 2: NB_CENSUS_LAUNCH(2, COV); break;                                             \
         case 3: NB_CENSUS_LAUNCH(3, COV); break;                                             \
         case 4: NB_CENSUS_LAUNCH(4, COV); break;                                             \
-        default: NB_CENSUS_LAUNCH(0, COV); break;                                            \
+        case 5: NB_CENSUS_LAUNCH(5, COV); break;                                             \
+        case 6: NB_CENSUS_LAUNCH(6, COV); break;                                             \
+        case 7: NB_CENSUS_LAUNCH(7, COV); break;                                             \
+        default: NB_CENSUS_LAUNCH(8, COV); break;                                            \
     }
     if (cover) {
         NB_CENSUS_CASES(true)
