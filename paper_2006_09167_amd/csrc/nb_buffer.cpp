@@ -111,7 +111,9 @@ struct Uncovered {
     double at_shell(int k) const {   // shell (R[k-1], R[k]), k > l
         const int64_t all = cov[(size_t)k * n + k] - cov[(size_t)(k - 1) * n + k - 1];
         const int64_t held = cov[(size_t)l * n + k] - cov[(size_t)l * n + k - 1];
-        return all > 0 ? 1.0 - (double)held / (double)all : 1.0;
+        if (all <= 0) return 1.0;
+        // a table from nb_list_coverage has 0 <= held <= all; clamp any other input
+        return std::min(1.0, std::max(0.0, 1.0 - (double)held / (double)all));
     }
 };
 
@@ -131,6 +133,7 @@ double missed_energy(const nb_params& p, const nb_buffer_input& in, int steps, d
             if (in.count[a] == 0 || in.count[b] == 0) continue;
             const double s2 = kBoltzmann * in.temperature * t * t * (1.0 / in.mass[a] + 1.0 / in.mass[b]);
             const double sig = sqrt(s2);
+            if (!(sig > 0.0)) continue;                     // nothing moves (T = 0)
             const int ta = in.type[a], tb = in.type[b];
             const float* lj = in.lj + 2 * ((size_t)ta * p.n_types + tb);
             const Potential V = make_potential(p, lj[0], lj[1], (double)in.charge[a] * in.charge[b]);

@@ -258,6 +258,20 @@ def test_library_cluster_drift_and_estimate_match_oracle(oracle_mod, sys3k):
     assert oracle_mod.buffer.drift(po, WATER_CLASSES, s.lj, V, 300.0, 0.002, 40, r - 2e-6) > 0.005
 
 
+def test_library_buffer_degenerate_inputs(sys3k):
+    """Zero temperature or a list used once: nothing moves, no drift, the radius is r_c."""
+    from paper_2006_09167_amd import api
+    pl = lib_params("ewald", 0.9, 3.47)
+    V = float(np.prod(sys3k.box))
+    assert api.buffer_drift(pl, WATER_CLASSES, sys3k.lj, V, 0.0, 0.002, 40, 0.9) == 0.0
+    assert api.buffer_drift(pl, WATER_CLASSES, sys3k.lj, V, 300.0, 0.002, 1, 0.9) == 0.0
+    assert api.buffer_drift(pl, WATER_CLASSES, sys3k.lj, V, 300.0, 0.0, 40, 0.9) == 0.0
+    r, d = api.buffer_estimate(pl, WATER_CLASSES, sys3k.lj, V, 0.0, 0.002, 40)
+    assert r == float(np.float32(0.9)) and d == 0.0
+    empty = dict(count=[0, 0], mass=[18.0, 18.0], charge=[0.0, 0.0], type=[0, 1])
+    assert api.buffer_drift(pl, empty, sys3k.lj, V, 300.0, 0.002, 40, 0.9) == 0.0
+
+
 def test_library_buffer_argument_errors(sys3k):
     from paper_2006_09167_amd import api
     pl = lib_params("ewald", 0.9, 3.47)
