@@ -268,37 +268,49 @@ __global__ __launch_bounds__(kWave) void k_compact(NbDev d, int cap, int w, int 
 }
 
 // One thread per entry: exclusion masks (bit ii + 8 jj cleared for excluded atom pairs),
-// a row only for entries with an exclusion; j-segment counts; list statistics.
+// a row only for entries with an exclusion; j-segment counts; list statistics (summed over
+// the wavefront first: one atomic per wavefront on each total).
 __global__ void k_entry_finish(NbDev d, int n_entries) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n_entries) return;
-    const NbEntry ent = d.entries[e];
-    const int sc = d.entry_sc[e];
-    const uint32_t omask = (ent.meta >> 8) & 0xffu;
-    uint64_t m[kClustersPerSc];
-    bool any = false;
-    for (int c = 0; c < kClustersPerSc; ++c) {
-        m[c] = ~0ull;
-        if (!((omask >> c) & 1u)) continue;
-        const int ci = kClustersPerSc * sc + c;
-        for (int ii = 0; ii < kClusterSize; ++ii) {
-            const int slot = kClusterSize * ci + ii;
-            for (int k = 0; k < d.max_excl; ++k) {
-                const int ps = d.excl_slot[(size_t)slot * d.max_excl + k];
-                if (ps >= 0 && ps / kClusterSize == ent.cj)
-                    m[c] &= ~(1ull << (ii + 8 * (ps % kClusterSize)));
+    int n_outer = 0, n_inner = 0;
+    if (e < n_entries) {
+        const NbEntry ent = d.entries[e];
+        const int sc = d.entry_sc[e];
+        const uint32_t omask = (ent.meta >> 8) & 0xffu;
+        uint64_t m[kClustersPerSc];
+        bool any = false;
+        for (int c = 0; c < kClustersPerSc; ++c) {
+            m[c] = ~0ull;
+            if (!((omask >> c) & 1u)) continue;
+            const int ci = kClustersPerSc * sc + c;
+            for (int ii = 0; ii < kClusterSize; ++ii) {
+                const int slot = kClusterSize * ci + ii;
+                for (int k = 0; k < d.max_excl; ++k) {
+                    const int ps = d.excl_slot[(size_t)slot * d.max_excl + k];
+                    if (ps >= 0 && ps / kClusterSize == ent.cj)
+                        m[c] &= ~(1ull << (ii + 8 * (ps % kClusterSize)));
+                }
             }
+            any |= (m[c] != ~0ull);
         }
-        any |= (m[c] != ~0ull);
+        if (any) {
+            const int row = atomicAdd(&d.flags[kFlagNumRows], 1);
+            for (int c = 0; c < kClustersPerSc; ++c)
+                d.excl_rows[(size_t)row * kClustersPerSc + c] = m[c];
+            d.entries[e].excl = row;
+        }
+        atomicAdd(&d.jseg_count[ent.cj], 1);
+        n_outer = __builtin_popcount(omask);
+        n_inner = __builtin_popcount((ent.meta >> 16) & 0xffu);
     }
-    if (any) {
-        const int row = atomicAdd(&d.flags[kFlagNumRows], 1);
-        for (int c = 0; c < kClustersPerSc; ++c) d.excl_rows[(size_t)row * kClustersPerSc + c] = m[c];
-        d.entries[e].excl = row;
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        n_outer += __shfl_xor(n_outer, off);
+        n_inner += __shfl_xor(n_inner, off);
     }
-    atomicAdd(&d.jseg_count[ent.cj], 1);
-    atomicAdd(&d.totals[2], __builtin_popcount(omask));
-    atomicAdd(&d.totals[3], __builtin_popcount((ent.meta >> 16) & 0xffu));
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        atomicAdd(&d.totals[2], n_outer);
+        atomicAdd(&d.totals[3], n_inner);
+    }
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_jseg(NbDev d, int n_cl) {
