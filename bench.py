@@ -30,6 +30,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "pair interactions/s & % FP32 VALU peak, fwd vs fwd+bwd, 96k-atom box"
 PEAK_FP32 = 157.3e12          # MI355X FP32 vector peak (FLOP/s), counting packed FP32
+CPU_SAMPLE_ATOMS = 16384      # oracle sample of a box too large to evaluate whole (~7 s)
+ARGON_SAMPLE_ATOMS = 131072   # oracle sample of the argon box at n_half = 200 (~6 s)
 PEAK_FP32_NONPACKED = 78.6e12 # without packed FP32 (one FMA per lane per cycle)
 # Algorithmic FLOP per evaluated pair slot of the force+energy kernels (FMA = 2,
 # add/mul = 1, rsqrt/rcp/exp2 = 1, compare/select = 0):
@@ -171,13 +173,13 @@ def cpu_baseline(c, cfg, x_np, budget_s=8.0):
                          "N(N-1)/2 minimum-image pairs)" % n), [(0, first[0], first[1])]
     # large box: forces on a seeded sample of atoms (all partners of each)
     rng = np.random.default_rng(7)
-    sel = np.sort(rng.choice(N, size=1024, replace=False))
+    sel = np.sort(rng.choice(N, size=CPU_SAMPLE_ATOMS, replace=False))
     t0 = time.perf_counter()
     F = oracle.forces_on(sel, x_np, s.q, s.type, s.lj, s.excl_ptr, s.excl_idx, s.box, p)
     dt = time.perf_counter() - t0
-    # the pairs of 1024 sampled atoms: 2 * 1024 / N of all pair interactions
-    return dt, 2.0 * sel.size / N, ("FP64 brute-force forces on 1024 seeded atoms of the "
-                                    "box (all partners of each)"), [(sel, None, F)]
+    # the pairs of the sampled atoms: 2 * n_sample / N of all pair interactions
+    return dt, 2.0 * sel.size / N, ("FP64 brute-force forces on %d seeded atoms of the "
+                                    "box (all partners of each)" % sel.size), [(sel, None, F)]
 
 
 def argon_sweep(args):
@@ -262,15 +264,15 @@ def argon_sweep(args):
         pt = next(p for p in points if p["n_half"] == 200)
         p = oracle.params("rf", rc=pt["rc"])                       # all charges zero
         rng = np.random.default_rng(7)
-        sel = np.sort(rng.choice(N, size=8192, replace=False))
+        sel = np.sort(rng.choice(N, size=ARGON_SAMPLE_ATOMS, replace=False))
         t0 = time.perf_counter()
         F = oracle.forces_on(sel, s.x, s.q, s.type, s.lj, s.excl_ptr, s.excl_idx, s.box, p)
         dt = time.perf_counter() - t0
-        # the sampled atoms' pairs: 2 * 8192 / N of the effective pairs of that cut-off
+        # the sampled atoms' pairs: 2 * n_sample / N of the effective pairs of that cut-off
         result["cpu_baseline"] = {"value": pt["effective_pairs"] * 2.0 * sel.size / N / dt,
                                   "unit": "pair interactions/s", "cores": oracle.num_threads(),
                                   "kind": "oracle",
-                                  "sample": "FP64 brute-force forces on 8192 seeded atoms "
+                                  "sample": "FP64 brute-force forces on %d seeded atoms " % sel.size +
                                             "(all partners) at n_half = 200", "seconds": dt}
         # parity of the GPU forces at that cut-off on the sampled atoms
         ctx = Context(n_types=1, coulomb="none", rc=pt["rc"], rinner=pt["rlist"],
