@@ -45,7 +45,10 @@ struct nb_ctx {
     std::string err;
     // allocated element counts
     size_t a_atoms = 0, a_cols = 0, a_sc = 0, a_scratch = 0, a_entries = 0, a_items = 0;
-    size_t a_excl_nnz = 0;
+    size_t a_excl_nnz = 0, a_chunks = 0, a_cpart = 0;
+    // host copies of the item tables of the current list (see finish_items)
+    std::vector<int32_t> h_sss, h_ipos, h_chunk_start;
+    std::vector<int4> h_chunks;
     // opt-in kernel timing: event pairs per kind, recorded on the stream
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[NB_T_COUNT];
@@ -478,36 +481,55 @@ nb_status make_items(nb_ctx* c, int W, bool copy_entries) {
 // per-system reductions and the queue order of the items.
 nb_status finish_items(nb_ctx* c) {
     NbDev& d = c->d;
-    nb_status st = to_host(c, c->h_totals, d.totals, 8);
+    // item totals, rolling-part ranges and per-system item ranks: one round trip
+    c->part_start.resize(c->p.nstprune + 1);
+    c->h_sss.resize(c->n_sys + 1);
+    c->h_ipos.resize((size_t)c->n_sc + 1);
+    NB_HIP(c, hipMemcpyAsync(c->h_totals, d.totals, sizeof(c->h_totals), hipMemcpyDeviceToHost,
+                             c->stream));
+    NB_HIP(c, hipMemcpyAsync(c->part_start.data(), d.part_start,
+                             sizeof(int32_t) * c->part_start.size(), hipMemcpyDeviceToHost,
+                             c->stream));
+    NB_HIP(c, hipMemcpyAsync(c->h_sss.data(), d.sys_sc_start, sizeof(int32_t) * c->h_sss.size(),
+                             hipMemcpyDeviceToHost, c->stream));
+    NB_HIP(c, hipMemcpyAsync(c->h_ipos.data(), d.sc_ipos, sizeof(int32_t) * c->h_ipos.size(),
+                             hipMemcpyDeviceToHost, c->stream));
+    nb_status st = sync(c);
     if (st != NB_OK) return st;
     c->n_items = c->h_totals[1];
-    c->part_start.resize(c->p.nstprune + 1);
-    st = to_host(c, c->part_start.data(), d.part_start, c->p.nstprune + 1);
-    if (st != NB_OK) return st;
     // item ranks of system s are [sc_ipos[sys_sc_start[s]], sc_ipos[sys_sc_start[s+1]])
-    std::vector<int32_t> sss(c->n_sys + 1), ipos((size_t)c->n_sc + 1);
-    st = to_host(c, sss.data(), d.sys_sc_start, sss.size());
-    if (st != NB_OK) return st;
-    st = to_host(c, ipos.data(), d.sc_ipos, ipos.size());
-    if (st != NB_OK) return st;
-    std::vector<int4> ch;
-    std::vector<int32_t> start(c->n_sys + 1, 0);
+    std::vector<int4>& ch = c->h_chunks;
+    std::vector<int32_t>& start = c->h_chunk_start;
+    ch.clear();
+    start.assign(c->n_sys + 1, 0);
     for (int s = 0; s < c->n_sys; ++s) {
         start[s] = (int32_t)ch.size();
-        const int p0 = ipos[sss[s]], p1 = ipos[sss[s + 1]];
+        const int p0 = c->h_ipos[c->h_sss[s]], p1 = c->h_ipos[c->h_sss[s + 1]];
         for (int p = p0; p < p1; p += kChunkItems)
             ch.push_back(make_int4(s, p, std::min(p1, p + kChunkItems), 0));
     }
     start[c->n_sys] = (int32_t)ch.size();
     const size_t nglj = (size_t)(c->n_items + kChunkItems - 1) / kChunkItems;
     const size_t ncap = std::max(ch.size(), nglj) + 1;
-    NB_HIP(c, dev_alloc(d.chunks, ch.size() + 1));
-    NB_HIP(c, dev_alloc(d.sys_chunk_start, c->n_sys + 1));
-    NB_HIP(c, dev_alloc(d.cpart, ncap * kChunkVals));
+    // the tables only grow: no free/allocate (and no implied device synchronisation) at a
+    // rebuild of the same size
+    if (ch.size() + 1 > c->a_chunks || !d.chunks) {
+        const size_t n = ch.size() + ch.size() / 8 + 16;
+        NB_HIP(c, dev_alloc(d.chunks, n));
+        c->a_chunks = n;
+    }
+    if (!d.sys_chunk_start) NB_HIP(c, dev_alloc(d.sys_chunk_start, c->n_sys + 1));
+    if (ncap > c->a_cpart || !d.cpart) {
+        const size_t n = ncap + ncap / 8 + 16;
+        NB_HIP(c, dev_alloc(d.cpart, n * kChunkVals));
+        c->a_cpart = n;
+    }
+    // host tables live in the context until the next rebuild, after a synchronisation
     if (!ch.empty())
-        NB_HIP(c, hipMemcpy(d.chunks, ch.data(), ch.size() * sizeof(int4), hipMemcpyHostToDevice));
-    NB_HIP(c, hipMemcpy(d.sys_chunk_start, start.data(), start.size() * sizeof(int32_t),
-                        hipMemcpyHostToDevice));
+        NB_HIP(c, hipMemcpyAsync(d.chunks, ch.data(), ch.size() * sizeof(int4),
+                                 hipMemcpyHostToDevice, c->stream));
+    NB_HIP(c, hipMemcpyAsync(d.sys_chunk_start, start.data(), start.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, c->stream));
     d.n_chunks = (int32_t)ch.size();
     NB_HIP(c, launch_item_order(d, c->n_items, c->stream));
     c->stats.n_work_items = c->n_items;
@@ -583,8 +605,8 @@ nb_status nb_pairlist_build(nb_ctx* c) {
     NB_HIP(c, launch_fill(d.totals + 2, 2, 0, c->stream));
     NB_HIP(c, launch_fill(d.flags + kFlagNumRows, 1, 0, c->stream));
     NB_HIP(c, launch_list_finish(d, n_sc, E, c->n_cl, c->stream));
-    st = to_host(c, flags, d.flags, kFlagCount);
-    if (st != NB_OK) return st;
+    // read back with finish_items' round trip (it synchronises the stream)
+    NB_HIP(c, hipMemcpyAsync(flags, d.flags, sizeof(flags), hipMemcpyDeviceToHost, c->stream));
     st = finish_items(c);
     if (st != NB_OK) return st;
     c->stats.outer_pairs = c->h_totals[2];
