@@ -88,3 +88,30 @@ def test_census_argument_errors(sys3k):
         with pytest.raises(RuntimeError):
             ctx.list_census(bad)
     assert ctx.list_census([1.0])[0, 0, 0] > 0
+
+
+def test_census_and_coverage_with_empty_and_one_atom_systems():
+    """Systems without atoms or with a single atom hold no pairs; the census and coverage
+    of the ensemble equal those of its other members, and a list with no pair inside any
+    radius counts nothing."""
+    from test_gpu_buffer import oracle_coverage_multi
+    one = small_random_system(52, 1, 2.4)
+    empty = systems.System(**{**one.__dict__, "x": np.zeros((0, 3), np.float32),
+                              "q": np.zeros(0, np.float32), "type": np.zeros(0, np.int32),
+                              "excl_ptr": np.zeros(1, np.int64),
+                              "excl_idx": np.zeros(0, np.int32)})
+    parts = [small_random_system(51, 120, 2.3), empty, one, small_random_system(53, 60, 2.2)]
+    c = concat(parts)
+    radii = [0.3, 0.6, 0.9]
+    ctx, got = census_of(c, 0.9, radii)
+    assert np.array_equal(got, oracle_census_multi(c, radii))
+    assert got[0, 0, -1] > 0
+    assert np.array_equal(ctx.list_coverage(radii, 8, 4), oracle_coverage_multi(c, radii, 8, 4))
+    # two atoms 1.5 nm apart: nothing within 0.5 nm
+    far = systems.System(**{**one.__dict__, "x": np.array([[0.2, 0.2, 0.2], [1.7, 0.2, 0.2]],
+                                                         np.float32),
+                            "q": np.zeros(2, np.float32), "type": np.zeros(2, np.int32),
+                            "excl_ptr": np.zeros(3, np.int64), "excl_idx": np.zeros(0, np.int32),
+                            "box": np.full(3, 4.0, np.float32)})
+    _, none = census_of(concat(far), 0.5, [0.2, 0.5])
+    assert not np.any(none)
