@@ -326,9 +326,9 @@ nb_status nb_list_coverage(nb_ctx* ctx, int32_t log2_m, int32_t log2_n, int32_t 
  *
  * Atoms are grouped in classes of equal mass, charge and LJ type.  Over a list age t each
  * atom moves by a Gaussian displacement of variance k_B T t^2 / m per axis; beyond the list
- * radius partners are spread uniformly; a pair not in the list that ends inside r_c misses
- * |V(r)|, V the pair potential selected by the nb_params (LJ with the electrostatics and the
- * modifier of the kernels).  The missed energy per atom at age (steps - 1) dt, divided by
+ * radius partners are spread uniformly; a pair not in the list that ends inside r_c, at a
+ * distance of at least r_c / 2, misses |V(r)|, V the pair potential selected by the
+ * nb_params (LJ with the electrostatics and the modifier of the kernels).  The missed energy per atom at age (steps - 1) dt, divided by
  * steps * dt, is the drift (kJ mol^-1 ps^-1 per atom).  A cluster list holds a fraction of
  * the pairs beyond its radius (its implicit buffer): with n_cov > 0 that fraction is taken
  * from a coverage table of nb_list_coverage (cov_radii ascending, covered[n_cov][n_cov]),

@@ -20,7 +20,10 @@ setup with its implicit buffer; the model below is this build's reading of it):
   * E = (1/N) (1/2) sum_a sum_b N_a (N_b / V) int_{r_l} 4 pi r0^2 U(r0)
                                              int^{r_c} |V_ab(r)| g_sigma(r - r0) dr dr0,
     at the oldest use of the list t = (steps - 1) dt, and drift = E / (steps dt).
-The integrals are evaluated by scipy's adaptive quadrature over 10 sigma windows.
+The integrals are evaluated by scipy's adaptive quadrature over 10 sigma windows; the
+inner one starts no lower than r_c / 2 (missed pairs end near the cut-off; below that the
+free-flight expectation of |V| would be dominated by atomic overlaps, and with the r^-12
+core it has no finite value at all).
 """
 from __future__ import annotations
 
@@ -119,7 +122,7 @@ def missed_energy_pair(V, sigma: float, rc: float, r_list: float, U=None) -> flo
     """int_{r_l} 4 pi r0^2 U(r0) int^{r_c} |V(r)| g_sigma(r - r0) dr dr0 for one class pair."""
     if sigma <= 0.0:
         return 0.0
-    lo = max(rc - WINDOW * sigma, 1e-3 * rc)
+    lo = max(rc - WINDOW * sigma, 0.5 * rc)        # missed pairs end near the cut-off
     hi = r_list + WINDOW * sigma
 
     def inner(r0):

@@ -13,8 +13,10 @@
 //   * missed energy per atom  E = (1/N) (1/2) sum_a sum_b N_a (N_b / V)
 //                                 int_{r_l} dr0 4 pi r0^2 U(r0) int^{r_c} dr |V_ab(r)| g(r - r0)
 //     at the oldest use of the list, t = (steps - 1) dt, and drift = E / (steps dt).
-// The integrals run over 10 sigma on either Gaussian side (the rest is below e^-50), on
-// Gauss-Legendre panels: the outer ones split at the coverage radii (U is constant between
+// The integrals run over 10 sigma on either Gaussian side (the rest is below e^-50), the
+// inner one from no lower than r_c / 2 (missed pairs end near the cut-off; below, the
+// free-flight expectation of |V| would be dominated by atomic overlaps), on Gauss-Legendre
+// panels: the outer ones split at the coverage radii (U is constant between
 // them) and at most sigma / 2 wide, the inner ones at most sigma / 8 wide and split at the
 // zeros of V_ab, where |V_ab| has a kink.
 #include <math.h>
@@ -137,8 +139,9 @@ double missed_energy(const nb_params& p, const nb_buffer_input& in, int steps, d
             const int ta = in.type[a], tb = in.type[b];
             const float* lj = in.lj + 2 * ((size_t)ta * p.n_types + tb);
             const Potential V = make_potential(p, lj[0], lj[1], (double)in.charge[a] * in.charge[b]);
-            // inner nodes: r in [rc - W sigma, rc], panels <= sigma / 8, split at zeros of V
-            const double lo = std::max(rc - kWindow * sig, 1e-3 * rc);
+            // inner nodes: r in [max(rc - W sigma, rc / 2), rc], panels <= sigma / 8, split at
+            // zeros of V
+            const double lo = std::max(rc - kWindow * sig, 0.5 * rc);
             const int n_in = std::max(1, (int)ceil((rc - lo) / (sig / 8.0)));
             std::vector<double> edges;
             for (int i = 0; i <= n_in; ++i) {
