@@ -13,11 +13,10 @@
 //   cluster pair every lane takes the bin of its squared distance, the number of sorted
 //   thresholds R_k^2 at or below it (a two-level count: chunk pivots, then one chunk); a
 //   sub-cluster pair holds a pair closer than R_k iff the smallest bin of its lanes is <= k,
-//   so folding
-//   the lane bins with min over lane-xor partners (1, 2, 4 on the i side, 8, 16, 32 on the j
-//   side; DPP where the partner is in the same row of 16 lanes) gives each sub-cluster
-//   pair's bin, which its first lane adds to an LDS histogram per setup.
-//   Each block then writes its histogram.
+//   so folding the lane bins with min over lane-xor partners (1, 2, 4 on the i side, 8, 16,
+//   32 on the j side; DPP where the partner is in the same row of 16 lanes) gives each
+//   sub-cluster pair's bin, which its first lane adds to an LDS histogram per setup.  Each
+//   block then writes its histogram.
 // * the same walk with COVER: per lane, the bin k of its own distance and the bin l of its
 //   sub-cluster pair of one chosen setup; a K x K histogram over (l, k) gives, after prefix
 //   sums, the atom pairs closer than R_k that lie in a sub-cluster pair held at R_l (the
