@@ -338,7 +338,10 @@ __global__ __launch_bounds__(kWave) void k_jseg_rank(NbDev d) {
     }
 }
 
-constexpr int kPruneWaves = 4;                  // wavefronts per item (one block per item)
+// wavefronts per item (one block per item): eight when a part has few items (fewer than
+// kPruneFewItemsPerCu per CU: each wavefront's entry walk is then the critical path), else
+// four (fewer wavefronts to start per entry)
+constexpr int kPruneFewItemsPerCu = 8;
 #define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
 // Rolling prune (Sec. V.E) of a range of work items: one block per item, whose 64 i-atoms
@@ -348,6 +351,7 @@ constexpr int kPruneWaves = 4;                  // wavefronts per item (one bloc
 // some atom pair is closer than r_inner in the list arithmetic (shift split between the
 // two sides, no contraction).  Empty slots sit far outside the box, so no valid-atom masks
 // are needed; a cluster with itself keeps ii < jj.
+template <int kPruneWaves>
 __global__ __launch_bounds__(kPruneWaves * kWave) void k_prune(
     const NbItem* __restrict__ items, NbEntry* __restrict__ entries,
     const float4* __restrict__ xp, const NbScInfo* __restrict__ sc_info,
@@ -520,8 +524,12 @@ hipError_t launch_list_finish(const NbDev& d, int n_sc, int64_t n_entries, int n
 hipError_t launch_prune(const NbDev& d, const float4* coords, int item0, int n_items,
                         float r2_inner, int item_width, hipStream_t s) {
     (void)item_width;
-    if (n_items > 0)
-        hipLaunchKernelGGL(k_prune, dim3(n_items), dim3(kPruneWaves * kWave), 0, s, d.items,
-                           d.entries, coords, d.sc_info, d.sys, item0, r2_inner);
+    if (n_items <= 0) return hipSuccess;
+    if (n_items < kPruneFewItemsPerCu * std::max(d.n_cu, 1))
+        hipLaunchKernelGGL(k_prune<8>, dim3(n_items), dim3(8 * kWave), 0, s, d.items, d.entries,
+                           coords, d.sc_info, d.sys, item0, r2_inner);
+    else
+        hipLaunchKernelGGL(k_prune<4>, dim3(n_items), dim3(4 * kWave), 0, s, d.items, d.entries,
+                           coords, d.sc_info, d.sys, item0, r2_inner);
     return hipGetLastError();
 }
