@@ -55,18 +55,27 @@ def make_params(n_types: int, coulomb: str = "rf", rc: float = 1.0,
 
 
 class _BufferArgs:
-    """Marshalled nb_buffer_input (keeps the arrays alive)."""
+    """Marshalled nb_buffer_input (keeps the arrays alive; checks the sizes the library
+    reads: one entry per class in every class array, an n_types x n_types x 2 table, a
+    square coverage table)."""
 
-    def __init__(self, classes: dict, lj, volume, temperature, dt, coverage=None):
-        self.count = np.ascontiguousarray(classes["count"], dtype=np.int64)
-        self.mass = np.ascontiguousarray(classes["mass"], dtype=np.float64)
-        self.charge = np.ascontiguousarray(classes["charge"], dtype=np.float32)
-        self.type = np.ascontiguousarray(classes["type"], dtype=np.int32)
+    def __init__(self, params, classes: dict, lj, volume, temperature, dt, coverage=None):
+        self.count = np.ascontiguousarray(classes["count"], dtype=np.int64).reshape(-1)
+        self.mass = np.ascontiguousarray(classes["mass"], dtype=np.float64).reshape(-1)
+        self.charge = np.ascontiguousarray(classes["charge"], dtype=np.float32).reshape(-1)
+        self.type = np.ascontiguousarray(classes["type"], dtype=np.int32).reshape(-1)
+        n = self.count.size
+        if not (self.mass.size == self.charge.size == self.type.size == n):
+            raise ValueError("class arrays count, mass, charge, type differ in length")
         self.lj = np.ascontiguousarray(np.asarray(lj, dtype=np.float32))
+        if self.lj.size != 2 * params.n_types * params.n_types:
+            raise ValueError("lj must hold (c6, c12) for n_types x n_types type pairs")
         n_cov, R, C = 0, None, None
         if coverage is not None:
-            R = np.ascontiguousarray(coverage[0], dtype=np.float32)
+            R = np.ascontiguousarray(coverage[0], dtype=np.float32).reshape(-1)
             C = np.ascontiguousarray(coverage[1], dtype=np.int64)
+            if C.shape != (R.size, R.size):
+                raise ValueError("coverage table must be [len(radii), len(radii)]")
             n_cov = int(R.size)
         self.R, self.C = R, C
         self.s = _lib.NbBufferInput(
@@ -83,7 +92,7 @@ def buffer_drift(params, classes: dict, lj, volume: float, temperature: float, d
     (nb_buffer_drift).  classes: arrays count, mass, charge, type; coverage: (radii,
     covered) from Context.list_coverage, or None for a particle list."""
     lib = _lib.load()
-    a = _BufferArgs(classes, lj, volume, temperature, dt, coverage)
+    a = _BufferArgs(params, classes, lj, volume, temperature, dt, coverage)
     out = ctypes.c_double()
     st = lib.nb_buffer_drift(ctypes.byref(params), ctypes.byref(a.s), int(steps),
                              float(r_list), ctypes.byref(out))
@@ -98,7 +107,7 @@ def buffer_estimate(params, classes: dict, lj, volume: float, temperature: float
     """(list radius, its drift): the smallest radius within the drift tolerance
     (nb_buffer_estimate)."""
     lib = _lib.load()
-    a = _BufferArgs(classes, lj, volume, temperature, dt, coverage)
+    a = _BufferArgs(params, classes, lj, volume, temperature, dt, coverage)
     r, d = ctypes.c_double(), ctypes.c_double()
     st = lib.nb_buffer_estimate(ctypes.byref(params), ctypes.byref(a.s), int(steps),
                                 float(tolerance), float(max_buffer), ctypes.byref(r),

@@ -285,6 +285,13 @@ def test_library_buffer_argument_errors(sys3k):
     with pytest.raises(RuntimeError):            # radius not in the coverage table
         api.buffer_drift(pl, WATER_CLASSES, sys3k.lj, V, 300.0, 0.002, 40, 0.93,
                          coverage=(radii, np.ones((2, 2), np.int64)))
+    with pytest.raises(ValueError):              # class arrays of different lengths
+        api.buffer_drift(pl, dict(WATER_CLASSES, mass=[18.0]), sys3k.lj, V, 300.0, 0.002, 40, 1.0)
+    with pytest.raises(ValueError):              # table for the wrong number of types
+        api.buffer_drift(pl, WATER_CLASSES, sys3k.lj[:1, :1], V, 300.0, 0.002, 40, 1.0)
+    with pytest.raises(ValueError):              # coverage table not square in the radii
+        api.buffer_drift(pl, WATER_CLASSES, sys3k.lj, V, 300.0, 0.002, 40, 0.9,
+                         coverage=(radii, np.ones((2, 3), np.int64)))
     with pytest.raises(RuntimeError):            # tolerance not reached within the range
         api.buffer_estimate(pl, WATER_CLASSES, sys3k.lj, V, 300.0, 0.002, 40, 1e-30,
                             max_buffer=0.01)
