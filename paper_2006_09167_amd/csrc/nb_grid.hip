@@ -174,9 +174,12 @@ __global__ void k_col_scatter(int n, const int4* __restrict__ img,
 }
 
 // One block per column: order the column's atoms by (z, atom index).  The key
-// (sortable z bits, index) is unique, so each atom's rank is the number of smaller keys.
+// (sortable z bits, index) is unique, so the order is fixed.  A column that fits in LDS is
+// sorted there by a bitonic network over the next power of two (padded with all-ones keys,
+// which no atom's key reaches, so the pads end up last); a larger one ranks each atom by
+// counting the smaller keys in global memory.
 constexpr int kSortThreads = 256;
-constexpr int kSortLds = 2048;
+constexpr int kSortLds = 4096;                   // keys of a column sorted in LDS (32 KB)
 
 __global__ __launch_bounds__(kSortThreads) void k_col_sort(
     const int32_t* __restrict__ col_start, const int32_t* __restrict__ col_count,
@@ -190,14 +193,27 @@ __global__ __launch_bounds__(kSortThreads) void k_col_sort(
         return ((unsigned long long)sortable_bits(wpos[a].z) << 32) | (unsigned)a;
     };
     if (n <= kSortLds) {
-        for (int i = threadIdx.x; i < n; i += blockDim.x) s_key[i] = key_of(i);
+        int P = 1;
+        while (P < n) P <<= 1;
+        for (int i = threadIdx.x; i < P; i += blockDim.x) s_key[i] = (i < n) ? key_of(i) : ~0ull;
         __syncthreads();
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const unsigned long long k = s_key[i];
-            int r = 0;
-            for (int j = 0; j < n; ++j) r += (s_key[j] < k) ? 1 : 0;
-            col_sorted[base + r] = (int)(k & 0xffffffffu);
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        const unsigned long long a = s_key[i], b = s_key[l];
+                        if ((a > b) == ((i & k) == 0)) {
+                            s_key[i] = b;
+                            s_key[l] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
         }
+        for (int i = threadIdx.x; i < n; i += blockDim.x)
+            col_sorted[base + i] = (int)(s_key[i] & 0xffffffffu);
     } else {
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
             const unsigned long long k = key_of(i);
