@@ -306,6 +306,20 @@ nb_status nb_get_stats(nb_ctx* ctx, nb_stats* out);
 nb_status nb_list_census(nb_ctx* ctx, int32_t n_radii, const float* radii, int64_t* counts);
 
 /*
+ * [sync] nb_list_census without any device or host allocation, for callers that cannot
+ * allocate (tight loops that re-estimate list buffers, harnesses that forbid hipMalloc).
+ * Same arguments, results (bit for bit) and errors as nb_list_census; the census kernels
+ * use a fixed per-device scratch array of the library (about 4.2 MB: the histograms of at
+ * most 1024 blocks, which stride over the work items, so every list fits) instead of the
+ * context's census buffers; the only size limit is n_radii <= NB_CENSUS_MAX_RADII
+ * (NB_ERR_ARG beyond).  The scratch is shared by every context on a device and keeps the
+ * last call's contents: calls that overlap on one device (contexts on different streams or
+ * threads) race and must be serialised by the caller.  No timing events are recorded.
+ */
+nb_status nb_list_census_noalloc(nb_ctx* ctx, int32_t n_radii, const float* radii,
+                                 int64_t* counts);
+
+/*
  * [sync] Coverage of the current outer list by an M x N list (M = 2^log2_m, N = 2^log2_n,
  * each 1 ... 8; sub-clusters as in nb_list_census): the implicit buffer of cluster lists
  * that the Verlet buffer estimate takes into account (Sec. V.B).  covered (host

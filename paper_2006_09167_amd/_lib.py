@@ -17,7 +17,7 @@ EXPORTS = ["nb_create", "nb_destroy", "nb_set_topology", "nb_grid_build", "nb_pa
            "nb_get_grid_dims", "nb_get_pairs", "nb_get_stats", "nb_set_timing", "nb_get_timing",
            "nb_strerror", "nb_last_error", "nb_step_graph", "nb_set_exec", "nb_get_exec",
            "nb_autotune", "nb_list_census", "nb_list_coverage", "nb_buffer_drift",
-           "nb_buffer_estimate"]
+           "nb_buffer_estimate", "nb_list_census_noalloc"]
 NB_EXEC_STATIC, NB_EXEC_XCD, NB_EXEC_QUEUE, NB_EXEC_PERSIST = 0, 1, 2, 3
 EXEC_MODES = {"static": NB_EXEC_STATIC, "xcd": NB_EXEC_XCD, "queue": NB_EXEC_QUEUE,
               "persist": NB_EXEC_PERSIST}
@@ -96,6 +96,7 @@ def load():
         "nb_set_timing": ([P, i32], st),
         "nb_get_timing": ([P, P, P], st),
         "nb_list_census": ([P, i32, P, P], st),
+        "nb_list_census_noalloc": ([P, i32, P, P], st),
         "nb_list_coverage": ([P, i32, i32, i32, P, P], st),
         "nb_buffer_drift": ([ctypes.POINTER(NbParams), ctypes.POINTER(NbBufferInput), i32,
                              ctypes.c_double, ctypes.POINTER(ctypes.c_double)], st),

@@ -341,6 +341,15 @@ class Context:
                     "nb_list_census")
         return out.reshape(4, 4, -1)
 
+    def list_census_noalloc(self, radii) -> np.ndarray:
+        """nb_list_census_noalloc: the census of list_census computed in the library's fixed
+        per-device scratch (no allocation); same layout and values (syncs)."""
+        r = np.ascontiguousarray(np.asarray(radii, dtype=np.float32).reshape(-1))
+        out = np.zeros((16, max(1, r.size)), dtype=np.int64)
+        self._check(self.lib.nb_list_census_noalloc(self.h, int(r.size), _np_ptr(r),
+                                                    _np_ptr(out)), "nb_list_census_noalloc")
+        return out.reshape(4, 4, -1)
+
     def list_coverage(self, radii, m: int = 8, n: int = 8) -> np.ndarray:
         """Coverage of the current outer list by an m x n list (nb_list_coverage): int64
         [K, K], [l, k] = atom pairs closer than radii[k] in an m x n sub-cluster pair that

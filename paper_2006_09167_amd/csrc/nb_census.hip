@@ -25,6 +25,7 @@
 //   then the chunks); the host turns bins into counts by prefix sums.
 #include <algorithm>
 #include <cfloat>
+#include <mutex>
 
 #include "nb_internal.h"
 #include "nb_pair_common.h"
@@ -216,7 +217,73 @@ __global__ __launch_bounds__(256) void k_census_total(const unsigned long long* 
     total[t] = s;
 }
 
+// Thresholds of one census call passed by value (the allocation-free variant writes them
+// into its scratch with this kernel instead of a host-to-device copy).
+struct NbThrTable {
+    float v[NB_CENSUS_MAX_RADII];
+};
+
+__global__ void k_set_thr(NbThrTable t, float* __restrict__ out) {
+    out[threadIdx.x] = t.v[threadIdx.x];
+}
+
+// Scratch of nb_list_census_noalloc: the block histograms of at most kNoAllocBlocks blocks
+// (the census kernel's blocks stride over the items, so any list fits), their chunk sums,
+// the totals and the thresholds.  Every word used by a call is written by that call
+// before it is read, so nothing has to be cleared between calls.
+constexpr int kNoAllocBlocks = 1024;
+constexpr size_t kNaHistOff = 0;
+constexpr size_t kNaPartOff = kNaHistOff + (size_t)kNoAllocBlocks * kHistWords * 4;
+constexpr size_t kNaTotalOff = kNaPartOff + (size_t)(kNoAllocBlocks / kSumRows) * kHistWords * 8;
+constexpr size_t kNaThrOff = kNaTotalOff + (size_t)kHistWords * 8;
+constexpr size_t kNaBytes = kNaThrOff + (size_t)NB_CENSUS_MAX_RADII * 4;
+static_assert(kNoAllocBlocks % kSumRows == 0, "whole chunks of block rows");
+static_assert(kNaPartOff % 256 == 0 && kNaTotalOff % 256 == 0 && kNaThrOff % 256 == 0,
+              "aligned sub-buffers");
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
 }  // namespace
+
+// Device address of this device's copy of `scratch`, looked up once per device with that
+// device current (each device holds its own copy at its own address; host code must use
+// this address, never the symbol itself).
+hipError_t census_noalloc_scratch(int device, NbCensusScratch* out) {
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = p;
+    }
+    unsigned char* base = static_cast<unsigned char*>(addr[device]);
+    out->hist = reinterpret_cast<uint32_t*>(base + kNaHistOff);
+    out->part = reinterpret_cast<unsigned long long*>(base + kNaPartOff);
+    out->total = reinterpret_cast<unsigned long long*>(base + kNaTotalOff);
+    out->thr = reinterpret_cast<float*>(base + kNaThrOff);
+    out->max_blocks = kNoAllocBlocks;
+    out->bytes = kNaBytes;
+    return hipSuccess;
+}
+
+hipError_t launch_set_thresholds(const float* r2_sorted_host, float* thr, hipStream_t s) {
+    NbThrTable t;
+    for (int k = 0; k < NB_CENSUS_MAX_RADII; ++k) t.v[k] = r2_sorted_host[k];
+    hipLaunchKernelGGL(k_set_thr, dim3(1), dim3(NB_CENSUS_MAX_RADII), 0, s, t, thr);
+    return hipGetLastError();
+}
 
 int census_blocks(int n_items, bool cover) {
     const int need = (n_items + kCensusWaves - 1) / kCensusWaves;   // one item per wavefront

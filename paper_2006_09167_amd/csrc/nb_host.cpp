@@ -1008,10 +1008,56 @@ nb_status nb_get_timing(nb_ctx* c, double* ms, int64_t* calls) {
 
 namespace {
 
+// Device buffers of one census walk: block histograms of up to max_blocks blocks, their
+// chunk sums, the summed words and the thresholds.
+struct CensusBufs {
+    uint32_t* hist;
+    unsigned long long* part;
+    unsigned long long* total;
+    float* thr;
+    int max_blocks;
+    bool thr_by_kernel;   // write the thresholds with a kernel argument (no copy) and
+                          // record no timing events
+};
+
 // One census or coverage walk of the outer list: validates the radii, sorts them (ord maps a
-// sorted position to the caller's index) and returns the summed histogram words.
-nb_status census_run(nb_ctx* c, int32_t n_radii, const float* radii, bool cover, int ca,
-                     int cb, std::vector<int>& ord, std::vector<unsigned long long>& tot) {
+// sorted position to the caller's index) and returns the summed histogram words in tot
+// (census_words(cover) words).  Uses no heap memory of its own.
+nb_status census_walk(nb_ctx* c, int32_t n_radii, const float* radii, bool cover, int ca,
+                      int cb, const CensusBufs& b, int* ord, unsigned long long* tot) {
+    float r2[NB_CENSUS_MAX_RADII];
+    for (int k = 0; k < n_radii; ++k) r2[k] = radius_sq(radii[k]);
+    // stable insertion sort of at most NB_CENSUS_MAX_RADII radii
+    for (int k = 0; k < n_radii; ++k) {
+        int p = k;
+        while (p > 0 && r2[ord[p - 1]] > r2[k]) {
+            ord[p] = ord[p - 1];
+            --p;
+        }
+        ord[p] = k;
+    }
+    float r2s[NB_CENSUS_MAX_RADII];
+    for (int k = 0; k < NB_CENSUS_MAX_RADII; ++k)
+        r2s[k] = k < n_radii ? r2[ord[k]] : __builtin_inff();   // +inf padding
+    const int n_items = c->n_items;
+    const int nb = std::min(census_blocks(n_items, cover), b.max_blocks);
+    if (b.thr_by_kernel)
+        NB_HIP(c, launch_set_thresholds(r2s, b.thr, c->stream));
+    else
+        NB_HIP(c, hipMemcpyAsync(b.thr, r2s, sizeof(r2s), hipMemcpyHostToDevice, c->stream));
+    if (b.thr_by_kernel) {
+        NB_HIP(c, launch_census(c->d, n_items, b.thr, n_radii, cover, ca, cb, b.hist, nb,
+                                c->stream));
+    } else {
+        TimedSection ts(c, NB_T_CENSUS);
+        NB_HIP(c, launch_census(c->d, n_items, b.thr, n_radii, cover, ca, cb, b.hist, nb,
+                                c->stream));
+    }
+    NB_HIP(c, launch_census_sum(b.hist, nb, cover, b.part, b.total, c->stream));
+    return to_host(c, tot, b.total, census_words(cover));
+}
+
+nb_status census_check(nb_ctx* c, int32_t n_radii, const float* radii) {
     if (n_radii < 1 || n_radii > NB_CENSUS_MAX_RADII)
         return fail(c, NB_ERR_ARG, "n_radii outside [1, NB_CENSUS_MAX_RADII]");
     if (!c->has_list) return fail(c, NB_ERR_STATE, "no pair list");
@@ -1019,15 +1065,12 @@ nb_status census_run(nb_ctx* c, int32_t n_radii, const float* radii, bool cover,
         if (!(radii[k] > 0.f) || !(radii[k] <= c->p.rlist))
             return fail(c, NB_ERR_ARG, "census radius outside (0, rlist]");
     NB_HIP(c, hipSetDevice(c->device));
-    ord.resize(n_radii);
-    for (int k = 0; k < n_radii; ++k) ord[k] = k;
-    std::vector<float> r2(n_radii);
-    for (int k = 0; k < n_radii; ++k) r2[k] = radius_sq(radii[k]);
-    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return r2[a] < r2[b]; });
-    std::vector<float> r2s(NB_CENSUS_MAX_RADII, __builtin_inff());   // +inf padding
-    for (int k = 0; k < n_radii; ++k) r2s[k] = r2[ord[k]];
-    const int n_items = c->n_items;
-    const int nb = census_blocks(n_items, cover);
+    return NB_OK;
+}
+
+// The context's census buffers, allocated on first use and grown to the list.
+nb_status census_ctx_bufs(nb_ctx* c, bool cover, CensusBufs* b) {
+    const int nb = census_blocks(c->n_items, cover);
     const size_t words = census_words(cover);
     const size_t need_hist = (size_t)nb * words, need_part = (size_t)((nb + 63) / 64) * words;
     if (need_hist > c->census_hist_n) {
@@ -1041,29 +1084,14 @@ nb_status census_run(nb_ctx* c, int32_t n_radii, const float* radii, bool cover,
     if (!c->census_total)
         NB_HIP(c, dev_alloc(c->census_total, (size_t)NB_CENSUS_MAX_RADII * NB_CENSUS_MAX_RADII));
     if (!c->census_thr) NB_HIP(c, dev_alloc(c->census_thr, NB_CENSUS_MAX_RADII));
-    NB_HIP(c, hipMemcpyAsync(c->census_thr, r2s.data(), sizeof(float) * r2s.size(),
-                             hipMemcpyHostToDevice, c->stream));
-    {
-        TimedSection ts(c, NB_T_CENSUS);
-        NB_HIP(c, launch_census(c->d, n_items, c->census_thr, n_radii, cover, ca, cb,
-                                c->census_hist, nb, c->stream));
-    }
-    NB_HIP(c, launch_census_sum(c->census_hist, nb, cover, c->census_part, c->census_total,
-                                c->stream));
-    tot.assign(words, 0ull);
-    return to_host(c, tot.data(), c->census_total, tot.size());
+    *b = CensusBufs{c->census_hist, c->census_part, c->census_total, c->census_thr, nb, false};
+    return NB_OK;
 }
 
-}  // namespace
-
-nb_status nb_list_census(nb_ctx* c, int32_t n_radii, const float* radii, int64_t* counts) {
-    if (!c) return NB_ERR_ARG;
-    if (!radii || !counts) return fail(c, NB_ERR_ARG, "null radii or counts");
-    std::vector<int> ord;
-    std::vector<unsigned long long> tot;
-    nb_status st = census_run(c, n_radii, radii, false, 0, 0, ord, tot);
-    if (st != NB_OK) return st;
-    // bin b holds the sub-cluster pairs first inside the b-th smallest radius
+// Census counts from the summed bins: bin b holds the sub-cluster pairs first inside the
+// b-th smallest radius.
+void census_counts(int32_t n_radii, const int* ord, const unsigned long long* tot,
+                   int64_t* counts) {
     for (int s = 0; s < 16; ++s) {
         int64_t acc = 0;
         for (int k = 0; k < n_radii; ++k) {
@@ -1071,6 +1099,41 @@ nb_status nb_list_census(nb_ctx* c, int32_t n_radii, const float* radii, int64_t
             counts[(size_t)s * n_radii + ord[k]] = acc;
         }
     }
+}
+
+}  // namespace
+
+nb_status nb_list_census(nb_ctx* c, int32_t n_radii, const float* radii, int64_t* counts) {
+    if (!c) return NB_ERR_ARG;
+    if (!radii || !counts) return fail(c, NB_ERR_ARG, "null radii or counts");
+    nb_status st = census_check(c, n_radii, radii);
+    if (st != NB_OK) return st;
+    CensusBufs b;
+    st = census_ctx_bufs(c, false, &b);
+    if (st != NB_OK) return st;
+    int ord[NB_CENSUS_MAX_RADII];
+    std::vector<unsigned long long> tot(census_words(false));
+    st = census_walk(c, n_radii, radii, false, 0, 0, b, ord, tot.data());
+    if (st != NB_OK) return st;
+    census_counts(n_radii, ord, tot.data(), counts);
+    return NB_OK;
+}
+
+nb_status nb_list_census_noalloc(nb_ctx* c, int32_t n_radii, const float* radii,
+                                 int64_t* counts) {
+    if (!c) return NB_ERR_ARG;
+    if (!radii || !counts) return fail(c, NB_ERR_ARG, "null radii or counts");
+    nb_status st = census_check(c, n_radii, radii);
+    if (st != NB_OK) return st;
+    NbCensusScratch sc{};
+    NB_HIP(c, census_noalloc_scratch(c->device, &sc));
+    const CensusBufs b{sc.hist, sc.part, sc.total, sc.thr, sc.max_blocks, true};
+    int ord[NB_CENSUS_MAX_RADII];
+    unsigned long long tot[NB_CENSUS_MAX_RADII * 16];
+    static_assert(sizeof(tot) / sizeof(tot[0]) >= 16 * NB_CENSUS_MAX_RADII, "census words");
+    st = census_walk(c, n_radii, radii, false, 0, 0, b, ord, tot);
+    if (st != NB_OK) return st;
+    census_counts(n_radii, ord, tot, counts);
     return NB_OK;
 }
 
@@ -1080,9 +1143,14 @@ nb_status nb_list_coverage(nb_ctx* c, int32_t log2_m, int32_t log2_n, int32_t n_
     if (!radii || !covered) return fail(c, NB_ERR_ARG, "null radii or covered");
     if (log2_m < 0 || log2_m > 3 || log2_n < 0 || log2_n > 3)
         return fail(c, NB_ERR_ARG, "sub-cluster sizes must be 1, 2, 4 or 8");
-    std::vector<int> ord;
-    std::vector<unsigned long long> tot;
-    nb_status st = census_run(c, n_radii, radii, true, log2_m, log2_n, ord, tot);
+    nb_status st = census_check(c, n_radii, radii);
+    if (st != NB_OK) return st;
+    CensusBufs b;
+    st = census_ctx_bufs(c, true, &b);
+    if (st != NB_OK) return st;
+    int ord[NB_CENSUS_MAX_RADII];
+    std::vector<unsigned long long> tot(census_words(true));
+    st = census_walk(c, n_radii, radii, true, log2_m, log2_n, b, ord, tot.data());
     if (st != NB_OK) return st;
     // [l][k] (sorted bins): pairs first inside radius k whose sub-cluster pair is first held
     // at radius l; two prefix sums give pairs inside R_k in sub-cluster pairs held at R_l

@@ -150,6 +150,24 @@ hipError_t launch_census_sum(const uint32_t* block_hist, int n_blocks, bool cove
                              unsigned long long* part, unsigned long long* total,
                              hipStream_t s);
 
+// Allocation-free census (nb_list_census_noalloc): sub-buffers of a file-scope device
+// array in nb_census.hip, resolved per device.  hist holds max_blocks block histograms of
+// census_words(false) words, part their chunk sums, total the summed words, thr the
+// NB_CENSUS_MAX_RADII thresholds.
+constexpr int kMaxDevices = 64;
+struct NbCensusScratch {
+    uint32_t* hist;
+    unsigned long long* part;
+    unsigned long long* total;
+    float* thr;
+    int max_blocks;
+    size_t bytes;
+};
+hipError_t census_noalloc_scratch(int device, NbCensusScratch* out);
+// Writes the NB_CENSUS_MAX_RADII thresholds of a host array into device memory by a kernel
+// argument (no host-to-device copy).
+hipError_t launch_set_thresholds(const float* r2_sorted_host, float* thr, hipStream_t s);
+
 // All device arrays of a context (plain pointers; sizes in the comments).
 struct NbDev {
     int32_t n_atoms = 0, n_sys = 0, n_cols = 0, n_types = 0, max_excl = 0;
