@@ -6,7 +6,8 @@ share no code (only the seeded input generators feed both).
 
 Contents
   * ``nb_oracle.c`` (built here with gcc into ``_nb_oracle.so``): brute-force
-    minimum-image energies, forces, virial and backward pass in FP64, and the
+    minimum-image energies, forces, virial and backward pass in FP64 (and the same
+    energies, forces and virial through a cell grid for large boxes), and the
     brute-force cluster-pair sets in a fixed single-precision sequence;
   * ``grid_spec.py``: the grid / slot assignment written out with numpy;
   * this module: ctypes wrappers, the pair-list set algebra (outer list, inner
@@ -49,17 +50,20 @@ class Params(ctypes.Structure):
     _fields_ = [("coulomb", ctypes.c_int32), ("modifier", ctypes.c_int32),
                 ("rc", ctypes.c_double), ("eps_r", ctypes.c_double),
                 ("eps_rf", ctypes.c_double), ("beta", ctypes.c_double),
-                ("epsfac", ctypes.c_double)]
+                ("epsfac", ctypes.c_double), ("excl_corr", ctypes.c_int32)]
 
 
 def params(coulomb: str = "rf", rc: float = 1.0, eps_r: float = 1.0, eps_rf: float = math.inf,
-           beta: float = 0.0, epsfac: float = 138.935458, modifier: str = "potshift") -> Params:
-    """Oracle parameters.  Cut-offs are taken as the float32 values the GPU receives."""
+           beta: float = 0.0, epsfac: float = 138.935458, modifier: str = "potshift",
+           excl_corr: bool = False) -> Params:
+    """Oracle parameters.  Cut-offs are taken as the float32 values the GPU receives.
+    excl_corr: excluded pairs inside rc and each atom with itself carry the electrostatic
+    corrections of a run with a long-range part (Sec. V.A)."""
     return Params(coulomb={"rf": 0, "ewald": 1}[coulomb],
                   modifier={"none": 0, "potshift": 1}[modifier],
                   rc=float(np.float32(rc)), eps_r=float(np.float32(eps_r)),
                   eps_rf=float(np.float32(eps_rf)), beta=float(np.float32(beta)),
-                  epsfac=float(np.float32(epsfac)))
+                  epsfac=float(np.float32(epsfac)), excl_corr=1 if excl_corr else 0)
 
 
 def _load():
@@ -72,6 +76,8 @@ def _load():
         i64 = ctypes.c_int64
         lib.oracle_forces.argtypes = [i64, P, P, P, ctypes.c_int32, P, P, P, P,
                                       ctypes.POINTER(Params), P, P, P, P]
+        lib.oracle_forces_cells.argtypes = [i64, P, P, P, ctypes.c_int32, P, P, P, P,
+                                            ctypes.POINTER(Params), P, P, P, P]
         lib.oracle_forces_on.argtypes = [i64, P, P, P, ctypes.c_int32, P, P, P, P,
                                          ctypes.POINTER(Params), i64, P, P]
         lib.oracle_backward.argtypes = [i64, P, P, P, ctypes.c_int32, P, P, P, P,
@@ -79,12 +85,18 @@ def _load():
         lib.oracle_cluster_pairs.argtypes = [i64, P, P, P, ctypes.c_float, i64, i64, P, i64]
         lib.oracle_cluster_pairs.restype = i64
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
         _lib = lib
     return _lib
 
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (for single-thread timings)."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def _c(a, dtype):
@@ -111,6 +123,28 @@ def forces(x, q, type_, lj, excl_ptr, excl_idx, box, p: Params, energy_abs: bool
                                _ptr(ea))
     if rc != 0:
         raise MemoryError("oracle_forces failed")
+    if energy_abs:
+        return e, f, v.reshape(3, 3), ea
+    return e, f, v.reshape(3, 3)
+
+
+def forces_cells(x, q, type_, lj, excl_ptr, excl_idx, box, p: Params, energy_abs: bool = False):
+    """The results of ``forces`` summed through a cell grid (each atom against the atoms
+    of its 27 neighbouring cells, cells at least rc wide): linear in N, for the boxes whose
+    all-pairs sum is too slow.  Falls back to ``forces`` below three cells per axis."""
+    x, q, t = _c(x, np.float32), _c(q, np.float32), _c(type_, np.int32)
+    lj = _c(lj, np.float32)
+    ep, ei, box = _c(excl_ptr, np.int64), _c(excl_idx, np.int32), _c(box, np.float32)
+    n = x.shape[0]
+    f = np.zeros((n, 3), dtype=np.float64)
+    e = np.zeros(2, dtype=np.float64)
+    v = np.zeros(9, dtype=np.float64)
+    ea = np.zeros(2, dtype=np.float64)
+    rc = _load().oracle_forces_cells(n, _ptr(x), _ptr(q), _ptr(t), lj.shape[0], _ptr(lj),
+                                     _ptr(ep), _ptr(ei), _ptr(box), ctypes.byref(p), _ptr(f),
+                                     _ptr(e), _ptr(v), _ptr(ea))
+    if rc != 0:
+        raise MemoryError("oracle_forces_cells failed")
     if energy_abs:
         return e, f, v.reshape(3, 3), ea
     return e, f, v.reshape(3, 3)

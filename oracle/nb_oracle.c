@@ -18,6 +18,14 @@
  *    the textbook 12-6 Lennard-Jones on (c6, c12), reaction field, and the Ewald
  *    real-space erfc term, with a potential-shift modifier for LJ and Ewald.
  *
+ *    With excl_corr set, excluded pairs inside the cut-off and each atom with
+ *    itself add the electrostatic corrections a long-range part needs (Sec. V.A:
+ *    the real-space Ewald correction of PME runs; the reaction-field analogue).
+ *
+ *  - oracle_forces_cells: the same sums found through a cell grid (each atom against
+ *    the atoms of its 27 neighbouring cells), for boxes too large for the all-pairs
+ *    loop; checked against oracle_forces.
+ *
  *  - oracle_backward: gradients of a scalar loss L(F, E) with respect to the
  *    positions, the charges and the (c6, c12) table, given dL/dF and dL/dE, over
  *    the frozen set of pairs inside the cut-off (the pair list is piecewise
@@ -51,6 +59,8 @@ typedef struct {
     double eps_rf;       /* reaction-field dielectric; +inf allowed          */
     double beta;         /* Ewald splitting parameter, 1/nm                  */
     double epsfac;       /* Coulomb constant, kJ mol^-1 nm e^-2              */
+    int32_t excl_corr;   /* 1: excluded pairs inside rc and each atom with
+                            itself carry their electrostatic corrections     */
 } oracle_params;
 
 int oracle_num_threads(void) {
@@ -58,6 +68,15 @@ int oracle_num_threads(void) {
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Threads of the following parallel loops (n >= 1), for single-thread timings. */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }
 
@@ -134,6 +153,45 @@ static void pair_eval(const oracle_params* p, double r2, double c6, double c12, 
 }
 
 /*
+ * Electrostatics of an excluded pair inside the cut-off, when the run has a long-range
+ * part that counts every pair of charges (Sec. V.A: for PME runs the kernel computes the
+ * real-space Ewald correction; force-field exclusions are enforced together with the
+ * cut-off).  Excluded pairs have no Lennard-Jones and no 1/r term, but keep what the
+ * long-range treatment assigns to every pair:
+ *   Ewald:  V = -kq erf(beta r)/r                (the reciprocal-space pair energy removed)
+ *           phi = -V'(r)/r = kq (2 beta/sqrt(pi) exp(-beta^2 r^2) - erf(beta r)/r) / r^2
+ *   RF:     V = kq (k_rf r^2 - c_rf),  phi = -2 kq k_rf   (the reaction field of the pair)
+ * At r = 0 (never reached by distinct atoms) the limits -kq 2 beta/sqrt(pi) and
+ * -kq 4 beta^3/(3 sqrt(pi)) are used.  Each atom with itself adds the energy
+ * self_term(kq_aa) (kq_aa = epsfac q_a^2 / eps_r) and no force:
+ *   Ewald: -kq_aa beta/sqrt(pi);   RF: -kq_aa c_rf / 2.
+ */
+static void excl_eval(const oracle_params* p, double r2, double kq, double krf, double crf,
+                      double* v, double* phi) {
+    if (p->coulomb == 0) {
+        *v = kq * (krf * r2 - crf);
+        *phi = -2.0 * kq * krf;
+        return;
+    }
+    const double b = p->beta;
+    if (r2 == 0.0) {
+        *v = -kq * 2.0 * b / sqrt(M_PI);
+        *phi = -kq * 4.0 * b * b * b / (3.0 * sqrt(M_PI));
+        return;
+    }
+    const double r = sqrt(r2);
+    const double ef = erf(b * r);
+    *v = -kq * ef / r;
+    *phi = kq * (2.0 * b / sqrt(M_PI) * exp(-b * b * r2) - ef / r) / r2;
+}
+
+static double self_term(const oracle_params* p, double kq_aa, double crf) {
+    if (!p->excl_corr) return 0.0;
+    if (p->coulomb == 0) return -0.5 * kq_aa * crf;
+    return -kq_aa * p->beta / sqrt(M_PI);
+}
+
+/*
  * Energies [LJ, Coulomb], forces f[n][3] and virial Xi = -1/2 sum_pairs d (x) (phi d),
  * all in FP64, over every pair a < b with (a, b) not excluded and |d_ab| < rc.
  * energy_abs (may be NULL) receives the sums of |pair energy| [LJ, Coulomb], the scale
@@ -171,22 +229,32 @@ int oracle_forces(int64_t n, const float* x, const float* q, const int32_t* type
                     d[k] = min_image((double)x[3 * a + k] - (double)x[3 * b + k], L[k]);
                 double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
                 if (!(r2 < rc2)) continue;
-                if (excluded(excl_ptr, excl_idx, a, b)) continue;
-                const float* c = lj + 2 * ((int64_t)type[a] * ntypes + type[b]);
-                pair_terms t;
-                pair_eval(p, r2, c[0], c[1], kq0 * q[a] * q[b], krf, crf, &t);
-                double phi = t.flj + t.fc;
+                double phi, vlj = 0.0, vc;
+                if (excluded(excl_ptr, excl_idx, a, b)) {
+                    if (!p->excl_corr) continue;
+                    excl_eval(p, r2, kq0 * q[a] * q[b], krf, crf, &vc, &phi);
+                } else {
+                    const float* c = lj + 2 * ((int64_t)type[a] * ntypes + type[b]);
+                    pair_terms t;
+                    pair_eval(p, r2, c[0], c[1], kq0 * q[a] * q[b], krf, crf, &t);
+                    phi = t.flj + t.fc;
+                    vlj = t.vlj;
+                    vc = t.vc;
+                }
                 for (int k = 0; k < 3; ++k) {
                     fl[3 * a + k] += phi * d[k];
                     fl[3 * b + k] -= phi * d[k];
                 }
-                el[0] += t.vlj;
-                el[1] += t.vc;
+                el[0] += vlj;
+                el[1] += vc;
                 for (int i = 0; i < 3; ++i)
                     for (int j = 0; j < 3; ++j) el[2 + 3 * i + j] += -0.5 * d[i] * phi * d[j];
-                el[11] += fabs(t.vlj);
-                el[12] += fabs(t.vc);
+                el[11] += fabs(vlj);
+                el[12] += fabs(vc);
             }
+            const double vs = self_term(p, kq0 * q[a] * q[a], crf);
+            el[1] += vs;
+            el[12] += fabs(vs);
         }
     }
     /* Fixed-order reduction over threads. */
@@ -231,15 +299,141 @@ int oracle_forces_on(int64_t n, const float* x, const float* q, const int32_t* t
                 d[k] = min_image((double)x[3 * a + k] - (double)x[3 * b + k], L[k]);
             double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
             if (!(r2 < rc2)) continue;
-            if (excluded(excl_ptr, excl_idx, a, b)) continue;
-            const float* c = lj + 2 * ((int64_t)type[a] * ntypes + type[b]);
-            pair_terms t;
-            pair_eval(p, r2, c[0], c[1], kq0 * q[a] * q[b], krf, crf, &t);
-            double phi = t.flj + t.fc;
+            double phi;
+            if (excluded(excl_ptr, excl_idx, a, b)) {
+                if (!p->excl_corr) continue;
+                double vc;
+                excl_eval(p, r2, kq0 * q[a] * q[b], krf, crf, &vc, &phi);
+            } else {
+                const float* c = lj + 2 * ((int64_t)type[a] * ntypes + type[b]);
+                pair_terms t;
+                pair_eval(p, r2, c[0], c[1], kq0 * q[a] * q[b], krf, crf, &t);
+                phi = t.flj + t.fc;
+            }
             for (int k = 0; k < 3; ++k) fa[k] += phi * d[k];
         }
         for (int k = 0; k < 3; ++k) f_sel[3 * s + k] = fa[k];
     }
+    return 0;
+}
+
+/*
+ * The energies, forces and virial of oracle_forces, summed per atom over the atoms of
+ * its 27 neighbouring cells instead of over all pairs: for boxes whose all-pairs sum is
+ * too slow to repeat (1.5 million atoms).  The box is cut into nc[k] = floor(L_k / rc')
+ * cells per axis (rc' = rc (1 + 1e-9), so a cell is wider than the cut-off and two atoms
+ * closer than rc lie in the same or adjacent cells); atoms are binned by their FP64
+ * wrapped position.  With fewer than three cells on an axis the 27 neighbours would
+ * repeat, and the call returns oracle_forces.  Every pair inside rc is found from both of
+ * its atoms: each atom sums its own force, and half of each pair's energies, |energies|
+ * and virial.  Blocks of 256 consecutive atoms keep their partial sums, added in block
+ * order afterwards, so the result does not depend on the thread count.  Tested against
+ * oracle_forces (rounding-level agreement).
+ */
+int oracle_forces_cells(int64_t n, const float* x, const float* q, const int32_t* type,
+                        int32_t ntypes, const float* lj, const int64_t* excl_ptr,
+                        const int32_t* excl_idx, const float* box, const oracle_params* p,
+                        double* f, double* energy, double* virial, double* energy_abs) {
+    const double L[3] = {box[0], box[1], box[2]};
+    int nc[3];
+    for (int k = 0; k < 3; ++k) {
+        nc[k] = (int)floor(L[k] / (p->rc * (1.0 + 1e-9)));
+        if (nc[k] < 3)
+            return oracle_forces(n, x, q, type, ntypes, lj, excl_ptr, excl_idx, box, p, f,
+                                 energy, virial, energy_abs);
+    }
+    const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+    int64_t* cell_of = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t* start = (int64_t*)calloc((size_t)ncell + 1, sizeof(int64_t));
+    int64_t* fill = (int64_t*)calloc((size_t)ncell, sizeof(int64_t));
+    int64_t* members = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    const int64_t n_blk = (n + 255) / 256;
+    double* bsum = (double*)calloc((size_t)(n_blk > 0 ? n_blk : 1) * 13, sizeof(double));
+    if (!cell_of || !start || !fill || !members || !bsum) {
+        free(cell_of); free(start); free(fill); free(members); free(bsum);
+        return -1;
+    }
+    /* bin: counting sort by cell, atoms in index order inside a cell */
+    for (int64_t a = 0; a < n; ++a) {
+        int64_t c = 0;
+        for (int k = 0; k < 3; ++k) {
+            const double v = (double)x[3 * a + k];
+            const double w = v - L[k] * floor(v / L[k]);
+            int ck = (int)floor(w / L[k] * nc[k]);
+            if (ck < 0) ck = 0;
+            if (ck > nc[k] - 1) ck = nc[k] - 1;
+            c = c * nc[k] + ck;
+        }
+        cell_of[a] = c;
+        start[c + 1]++;
+    }
+    for (int64_t c = 0; c < ncell; ++c) start[c + 1] += start[c];
+    for (int64_t a = 0; a < n; ++a) members[start[cell_of[a]] + fill[cell_of[a]]++] = a;
+
+    double krf = 0, crf = 0;
+    rf_constants(p, &krf, &crf);
+    const double rc2 = p->rc * p->rc;
+    const double kq0 = p->epsfac / p->eps_r;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t blk = 0; blk < n_blk; ++blk) {
+        double* s = bsum + 13 * blk;
+        const int64_t a1 = (blk + 1) * 256 < n ? (blk + 1) * 256 : n;
+        for (int64_t a = blk * 256; a < a1; ++a) {
+            const int64_t c = cell_of[a];
+            const int cz = (int)(c % nc[2]), cy = (int)((c / nc[2]) % nc[1]),
+                      cx = (int)(c / ((int64_t)nc[1] * nc[2]));
+            double fa[3] = {0, 0, 0};
+            for (int dx = -1; dx <= 1; ++dx)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dz = -1; dz <= 1; ++dz) {
+                        const int64_t nb = (((int64_t)((cx + dx + nc[0]) % nc[0]) * nc[1] +
+                                             (cy + dy + nc[1]) % nc[1]) * nc[2]) +
+                                           (cz + dz + nc[2]) % nc[2];
+                        for (int64_t m = start[nb]; m < start[nb + 1]; ++m) {
+                            const int64_t b = members[m];
+                            if (b == a) continue;
+                            double d[3];
+                            for (int k = 0; k < 3; ++k)
+                                d[k] = min_image((double)x[3 * a + k] - (double)x[3 * b + k],
+                                                 L[k]);
+                            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                            if (!(r2 < rc2)) continue;
+                            double phi, vlj = 0.0, vc;
+                            if (excluded(excl_ptr, excl_idx, a, b)) {
+                                if (!p->excl_corr) continue;
+                                excl_eval(p, r2, kq0 * q[a] * q[b], krf, crf, &vc, &phi);
+                            } else {
+                                const float* cc = lj + 2 * ((int64_t)type[a] * ntypes + type[b]);
+                                pair_terms t;
+                                pair_eval(p, r2, cc[0], cc[1], kq0 * q[a] * q[b], krf, crf, &t);
+                                phi = t.flj + t.fc;
+                                vlj = t.vlj;
+                                vc = t.vc;
+                            }
+                            for (int k = 0; k < 3; ++k) fa[k] += phi * d[k];
+                            s[0] += 0.5 * vlj;
+                            s[1] += 0.5 * vc;
+                            for (int i = 0; i < 3; ++i)
+                                for (int j = 0; j < 3; ++j)
+                                    s[2 + 3 * i + j] += -0.25 * d[i] * phi * d[j];
+                            s[11] += 0.5 * fabs(vlj);
+                            s[12] += 0.5 * fabs(vc);
+                        }
+                    }
+            const double vs = self_term(p, kq0 * q[a] * q[a], crf);
+            s[1] += vs;
+            s[12] += fabs(vs);
+            for (int k = 0; k < 3; ++k) f[3 * a + k] = fa[k];
+        }
+    }
+    for (int k = 0; k < 13; ++k) {
+        double t = 0;
+        for (int64_t blk = 0; blk < n_blk; ++blk) t += bsum[13 * blk + k];
+        if (k < 2) energy[k] = t;
+        else if (k < 11) virial[k - 2] = t;
+        else if (energy_abs) energy_abs[k - 11] = t;
+    }
+    free(cell_of); free(start); free(fill); free(members); free(bsum);
     return 0;
 }
 

@@ -227,3 +227,45 @@ def test_forces_on_matches_full(oracle_mod, sys3k):
     sel = np.array([0, 1, 2, 77, 1500, 2999])
     fs = oracle_mod.forces_on(sel, s.x, s.q, s.type, s.lj, s.excl_ptr, s.excl_idx, s.box, p)
     assert np.allclose(fs, f[sel], rtol=1e-10, atol=1e-9)
+
+
+# ---- cell-grid evaluation against the all-pairs sum -----------------------------------
+def _cells_vs_pairs(o, s, **kw):
+    p = o.params(**kw)
+    args = (s.x, s.q, s.type, s.lj, s.excl_ptr, s.excl_idx, s.box, p)
+    e0, f0, v0, a0 = o.forces(*args, energy_abs=True)
+    e1, f1, v1, a1 = o.forces_cells(*args, energy_abs=True)
+    scale = np.abs(f0).max()
+    assert np.abs(f1 - f0).max() <= 1e-12 * scale
+    assert np.allclose(e1, e0, rtol=1e-12, atol=1e-12 * a0.max())
+    assert np.allclose(v1, v0, rtol=1e-11, atol=1e-12 * np.abs(v0).max())
+    assert np.allclose(a1, a0, rtol=1e-12)
+    return e0
+
+
+def test_cells_equal_all_pairs_water3k(oracle_mod, sys3k):
+    # 3.104 nm box, rc 1.0: three cells per axis, every cell a neighbour of every other
+    _cells_vs_pairs(oracle_mod, sys3k, coulomb="rf", rc=1.0)
+    _cells_vs_pairs(oracle_mod, sys3k, coulomb="ewald", rc=1.0, beta=3.12)
+
+
+def test_cells_equal_all_pairs_diff24k(oracle_mod, sys24k):
+    _cells_vs_pairs(oracle_mod, sys24k, coulomb="rf", rc=1.0)      # six cells per axis
+
+
+def test_cells_equal_all_pairs_water96k(oracle_mod):
+    from paper_2006_09167_amd import systems
+    s = systems.config_system("water96k_ewald")
+    _cells_vs_pairs(oracle_mod, s, coulomb="ewald", rc=1.0, beta=3.12)
+
+
+def test_cells_unwrapped_coordinates_and_small_boxes(oracle_mod):
+    s = small_random_system(61, 400, [3.5, 4.1, 3.2], n_types=3)
+    # move atoms by whole and partial box multiples: minimum images are unchanged
+    rng = np.random.default_rng(2)
+    x = s.x + (rng.integers(-3, 4, s.x.shape) * s.box).astype(np.float32)
+    s2 = System(**{**s.__dict__, "x": x.astype(np.float32)})
+    _cells_vs_pairs(oracle_mod, s2, coulomb="ewald", rc=1.1, beta=3.0, modifier="none")
+    # below three cells per axis the all-pairs sum is used
+    t = small_random_system(62, 120, 2.5)
+    _cells_vs_pairs(oracle_mod, t, coulomb="rf", rc=1.0)

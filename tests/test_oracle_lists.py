@@ -257,3 +257,26 @@ def test_inner_subset_of_outer_and_monotone(oracle_mod, sys3k):
              for p in range(n_parts)]
     assert sum(p.size for p in parts) == inner.size
     assert np.array_equal(np.sort(np.concatenate(parts)), inner)
+
+
+def test_rolling_part_owner_is_the_lower_cluster(oracle_mod):
+    """Rolling parts follow the owner of a cluster pair, the super-cluster of its lower
+    cluster index (Sec. V.E: the list is pruned in parts, one per step; Sec. V.A: each
+    pair is listed once, with the super-cluster of the lower cluster).  Three atoms in
+    clusters 0, 8 and 17 (super-clusters 0, 1 and 2) form the pairs (0, 8) and (8, 17);
+    the second pair belongs to super-cluster 1, so with two parts it is in part 1 and with
+    three parts in part 1 (owning by the higher cluster would give parts 0 and 2)."""
+    slot_atom = np.full(3 * 64, -1, np.int32)
+    slot_atom[0], slot_atom[64], slot_atom[8 * 17] = 0, 1, 2
+    w = np.array([[1.0, 1.0, 1.0], [1.5, 1.0, 1.0], [2.0, 1.0, 1.0]], np.float32)
+    box = np.full(3, 10.0, np.float32)
+    n_cl = 24
+    outer = oracle_mod.cluster_pairs(slot_atom, w, box, 0.7)
+    k08 = (0 * n_cl + 8) * 27 + 13
+    k817 = (8 * n_cl + 17) * 27 + 13
+    assert outer.tolist() == [k08, k817]
+    expect = {2: {0: [k08], 1: [k817]}, 3: {0: [k08], 1: [k817], 2: []}}
+    for n_parts, parts in expect.items():
+        for part, keys in parts.items():
+            got = oracle_mod.inner_pairs(outer, slot_atom, w, box, 0.7, n_parts, part)
+            assert got.tolist() == keys, (n_parts, part)
