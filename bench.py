@@ -15,8 +15,10 @@ replayed from a HIP graph with positions updated in place (the copy of the step'
 positions into the fixed buffer is inside the timed region).  The execution shape of
 the pair kernel is chosen by the autotuner at the first list build (untimed).  The JSON
 line reports effective pair interactions/s of that step, the eager and separate-call
-variants, forward + backward, ns/day-equivalent at 2 fs, the force kernel's FP32
-roofline fraction from HIP-event kernel times, and the FP64 oracle timed on the host.
+variants, forward + backward, ns/day-equivalent at 2 fs (the mean step without list
+builds plus 1/nstlist of a separately timed rebuild), the force kernel's FP32 roofline
+fraction from HIP-event kernel times, and the FP64 oracle timed on the host (all threads
+and one thread) with the per-output error of the GPU result at one step.
 """
 import argparse
 import json
@@ -30,7 +32,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "pair interactions/s & % FP32 VALU peak, fwd vs fwd+bwd, 96k-atom box"
 PEAK_FP32 = 157.3e12          # MI355X FP32 vector peak (FLOP/s), counting packed FP32
-CPU_SAMPLE_ATOMS = 16384      # oracle sample of a box too large to evaluate whole (~7 s)
 ARGON_SAMPLE_ATOMS = 131072   # oracle sample of the argon box at n_half = 200 (~6 s)
 PEAK_FP32_NONPACKED = 78.6e12 # without packed FP32 (one FMA per lane per cycle)
 # Algorithmic FLOP per evaluated pair slot of the force+energy kernels (FMA = 2,
@@ -148,7 +149,7 @@ def cpu_baseline(c, cfg, x_np, budget_s=8.0):
             a0, a1 = int(offs[r]), int(offs[r + 1])
             E, F, _ = oracle.forces(x_np[a0:a1], s.q, s.type, s.lj, s.excl_ptr, s.excl_idx,
                                     s.box, p)
-            res.append((r, E, F))
+            res.append((r, E, F, None))
             done += 1
             atoms += a1 - a0
             if time.perf_counter() - t0 >= budget_s:
@@ -170,16 +171,51 @@ def cpu_baseline(c, cfg, x_np, budget_s=8.0):
                 break
         dt = (time.perf_counter() - t0) / n
         return dt, 1.0, ("%d FP64 brute-force force+energy evaluations of the box (all "
-                         "N(N-1)/2 minimum-image pairs)" % n), [(0, first[0], first[1])]
-    # large box: forces on a seeded sample of atoms (all partners of each)
-    rng = np.random.default_rng(7)
-    sel = np.sort(rng.choice(N, size=CPU_SAMPLE_ATOMS, replace=False))
+                         "N(N-1)/2 minimum-image pairs)" % n), [(0, first[0], first[1], None)]
+    # large box: the whole box through the oracle's cell grid (every force, the energies
+    # and the virial, equal to the all-pairs sum to rounding)
     t0 = time.perf_counter()
-    F = oracle.forces_on(sel, x_np, s.q, s.type, s.lj, s.excl_ptr, s.excl_idx, s.box, p)
+    E, F, V = oracle.forces_cells(x_np, s.q, s.type, s.lj, s.excl_ptr, s.excl_idx, s.box, p)
     dt = time.perf_counter() - t0
-    # the pairs of the sampled atoms: 2 * n_sample / N of all pair interactions
-    return dt, 2.0 * sel.size / N, ("FP64 brute-force forces on %d seeded atoms of the "
-                                    "box (all partners of each)" % sel.size), [(sel, None, F)]
+    return dt, 1.0, ("one FP64 force+energy+virial evaluation of the whole box through the "
+                     "oracle's cell grid"), [(0, E, F, V)]
+
+
+def cpu_single_thread(c, cfg, x_np, n_sel=1024):
+    """The oracle on one host thread: per-atom FP64 sums over all partners for a seeded
+    sample of atoms of the first system.  Returns (pair interactions/s, description)."""
+    import numpy as np
+    import oracle
+    p = oracle.params(cfg["coulomb"], rc=cfg["rc"], beta=cfg["beta"])
+    s = c["parts"][0]
+    n = s.n
+    a0 = int(c["offsets"][0])
+    rng = np.random.default_rng(11)
+    sel = np.sort(rng.choice(n, size=min(n_sel, n), replace=False))
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.forces_on(sel, x_np[a0:a0 + n], s.q, s.type, s.lj, s.excl_ptr, s.excl_idx,
+                         s.box, p)
+        dt = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
+    return dt, sel.size, n, ("FP64 brute-force forces (all partners) on %d seeded atoms of "
+                             "the first box, one thread" % sel.size)
+
+
+def host_info():
+    """Logical CPUs and the CPU model of the host that ran the oracle."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
 
 
 def argon_sweep(args):
@@ -392,6 +428,7 @@ BUF_TOL = 0.005          # kJ/mol/ps per atom: the paper's default drift toleran
 BUF_T, BUF_DT = 300.0, 0.002
 BUF_RIGID_MASS = 18.015  # a rigid water molecule carries each of its atoms
 BUF_FREE_MASS = (15.9994, 1.008)
+BUF_OH = 0.1             # nm: a hydrogen rotates about its oxygen at this distance
 
 
 def verlet_buffer(args):
@@ -414,11 +451,15 @@ def verlet_buffer(args):
     rigid = dict(count=[n_o, N - n_o], mass=[BUF_RIGID_MASS] * 2, charge=[-0.82, 0.41],
                  type=[0, 1])
     free = dict(rigid, mass=list(BUF_FREE_MASS))
+    rotor = dict(rigid, rot_len=[0.0, BUF_OH], rot_mass=list(BUF_FREE_MASS))
+    mass_classes = {"rigid": rigid, "rotor": rotor, "free": free}
     K = args.steps if args.steps is not None else 20
     W = min(args.warmup, 5)
     # (name, r_c, Ewald beta, table step, mass readings, [(list, steps)])
-    settings = [("paper_buffer_comparison", 0.9, 3.47, 0.01, ("rigid", "free"), [("list", 40)]),
-                ("dual_list_96k", 1.0, 3.12, 0.005, ("rigid",), [("outer", 100), ("inner", 4)])]
+    settings = [("paper_buffer_comparison", 0.9, 3.47, 0.01, ("rotor", "rigid", "free"),
+                 [("list", 40), ("list", 10)]),
+                ("dual_list_96k", 1.0, 3.12, 0.005, ("rotor", "rigid"),
+                 [("outer", 100), ("inner", 4)])]
     out, timing = {}, None
     for name, rc, beta, step, readings, lists in settings:
         radii = (np.float32(rc) + np.float32(step) * np.arange(64, dtype=np.float32)).astype(np.float32)
@@ -448,7 +489,7 @@ def verlet_buffer(args):
         res = {"rc": rc, "ewald_beta": beta, "table": "%d radii, r_c + %.3f k nm" % (64, step)}
         for lname, steps in lists:
             for reading in readings:
-                classes = rigid if reading == "rigid" else free
+                classes = mass_classes[reading]
                 r = {}
                 for setup, table in [("1x1", None)] + list(cov.items()):
                     kw = {} if table is None else {"coverage": (radii, table)}
@@ -460,10 +501,25 @@ def verlet_buffer(args):
                                     "drift": d}
                     except RuntimeError:                 # not reached inside the table
                         r[setup] = None
+                if name == "paper_buffer_comparison" and steps == 40:
+                    # the same tolerance for both setups, the one the 8x4 list reaches
+                    # with the paper's 0.105 nm (the table radii 0.10 and 0.11 nm)
+                    same = {}
+                    for b84 in (0.10, 0.11):
+                        k = int(round(b84 / step))
+                        d84 = api.buffer_drift(p, classes, s.lj, V, BUF_T, BUF_DT, steps,
+                                               float(radii[k]),
+                                               coverage=(radii, cov["8x4"]))
+                        r11, _ = api.buffer_estimate(p, classes, s.lj, V, BUF_T, BUF_DT,
+                                                     steps, d84, max_buffer=0.8)
+                        same["8x4_%.2f" % b84] = {"drift": d84,
+                                                  "1x1_buffer_nm": round(r11 - rc32, 4)}
+                    r["1x1_at_the_drift_of_8x4"] = same
                 res["%s_steps_%d_%s_masses" % (lname, steps, reading)] = r
                 log("%s %s (%d steps, %s masses): %s" % (
                     name, lname, steps, reading,
-                    {k: (v["buffer_nm"] if v else None) for k, v in r.items()}))
+                    {k: (v["buffer_nm"] if v and "buffer_nm" in v else v)
+                     for k, v in r.items()}))
         out[name] = res
         del ctx
     kern = timing["kern"]
@@ -479,7 +535,9 @@ def verlet_buffer(args):
                    "atoms": N, "radii": 64, "tolerance": BUF_TOL, "temperature": BUF_T,
                    "dt_ps": BUF_DT, "timed_list_radius": timing["rlist"],
                    "timed_setting": timing["setting"],
-                   "mass_readings": {"rigid": "18.015 for every atom (molecule translates)",
+                   "mass_readings": {"rotor": "molecule translates (18.015); H rotates about "
+                                              "O at 0.1 nm with its own mass 1.008",
+                                     "rigid": "18.015 for every atom (molecule translates)",
                                      "free": "O 15.9994, H 1.008 (free flight)"}},
         "buffers": out,
         "roofline": {"bound": "alu", "kernel": "k_census<0, cover>",
@@ -676,6 +734,23 @@ def main():
         log("timed fwd+bwd pass")
         wall_fb, tm_fb = timed("eager", bwd=True, timing=True)
 
+    # The list rebuild (grid, outer list with its initial prune, work items) on its own:
+    # the ns/day equivalent adds 1/nstlist of it to the step time without builds.
+    torch.cuda.synchronize()
+    t_build = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        ctx.grid_build(traj[W], boxes)
+        ctx.pairlist_build()
+        torch.cuda.synchronize()
+        t_build.append(time.perf_counter() - t0)
+    build_s = sorted(t_build)[1]
+    n_builds = sum(1 for t in range(W, T) if t % nstlist == 0)
+    step_s = max(wall - n_builds * build_s, 0.0) / K
+    amortized_s = step_s + build_s / nstlist
+    log("list rebuild %.3f ms; step without builds %.4f ms, amortized %.4f ms"
+        % (1e3 * build_s, 1e3 * step_s, 1e3 * amortized_s))
+
     # Roofline of the plain force kernel: the separate-call pass launches only that flavor
     # (the fused pass adds the list-distance test of the pruned part to some launches).
     plain_ms, plain_calls = tm_sep["forces"]
@@ -705,7 +780,10 @@ def main():
                                     else "as separate kernels"),
         "effective_pairs_per_step": float(eff[W:].mean()),
         "raw_pairs_per_s": comp_timed / wall,
-        "ns_per_day_equiv": 0.1728 / (wall / K),
+        "ns_per_day_equiv": 0.1728 / amortized_s,
+        "ms_list_rebuild": 1e3 * build_s,
+        "ms_per_step_amortized": 1e3 * amortized_s,
+        "builds_in_timed_steps": n_builds,
         "ms_per_step_eager": 1e3 * wall_eager / K,
         "ms_per_step_separate_prune_call": 1e3 * wall_sep / K,
         "fwd_bwd_pairs_per_s": (eff_timed / wall_fb) if wall_fb else None,
@@ -748,35 +826,43 @@ def main():
         x_np = traj[tb].cpu().numpy()
         fe = f.cpu().numpy()
         ee = e.cpu().numpy()
+        # the virial of that step too, for the per-output errors
+        xv = traj[tb].clone()
+        _, _, vv = ctx.forces(xv, q, lj, energy=True, virial=True)
+        vv = vv.cpu().numpy()
         dt, frac, sample, res = cpu_baseline(c, cfg, x_np)
         par = {"step": tb}
         if S > 1:
             offs = c["offsets"]
             num = den = 0.0
             worst = 0.0
-            for r, E, F in res:
+            for r, E, F, _ in res:
                 a0, a1 = int(offs[r]), int(offs[r + 1])
                 num += float(np.sum((fe[a0:a1] - F) ** 2))
                 den += float(np.sum(F ** 2))
                 worst = max(worst, float(np.max(np.abs(ee[r] - E) / np.abs(E))))
             par.update(force_rel_rms=math.sqrt(num / den), energy_rel_max=worst,
                        replicas=len(res))
-        elif res[0][1] is None:
-            sel, _, F = res[0]
-            par.update(force_rel_rms=float(np.linalg.norm(fe[sel] - F) / np.linalg.norm(F)),
-                       sampled_atoms=int(sel.size))
         else:
-            _, E, F = res[0]
+            _, E, F, V = res[0]
             par.update(force_rel_rms=float(np.linalg.norm(fe - F) / np.linalg.norm(F)),
                        energy_rel=[float(abs(ee[0, k] - E[k]) / abs(E[k])) for k in range(2)])
+            if V is not None:
+                par["virial_rel_rms"] = float(np.linalg.norm(vv[0] - V) / np.linalg.norm(V))
         import oracle
+        dt1, n1, n_box, sample1 = cpu_single_thread(c, cfg, x_np)
+        # the sampled atoms' pairs are 2 n1 / n_box of the first box's pairs
+        eff_box = float(eff[tb]) * n_box / N
         result["cpu_baseline"] = {"value": float(eff[tb]) * frac / dt,
                                   "unit": "pair interactions/s",
                                   "cores": oracle.num_threads(), "kind": "oracle",
                                   "sample": sample + " at step %d" % tb,
-                                  "seconds": dt}
+                                  "seconds": dt,
+                                  "value_one_thread": eff_box * 2.0 * n1 / n_box / dt1,
+                                  "sample_one_thread": sample1, "seconds_one_thread": dt1,
+                                  "host": host_info()}
         result["parity_at_step"] = par
-        log("oracle %.2f s; parity %s" % (dt, par))
+        log("oracle %.2f s (one thread: %.2f s); parity %s" % (dt, dt1, par))
     print(json.dumps(result), flush=True)
 
 

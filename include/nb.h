@@ -63,7 +63,16 @@ enum { NB_MOD_NONE = 0, NB_MOD_POTSHIFT = 1 };
 enum {
     NB_F_ENERGY = 1u,      /* also compute energies [LJ, Coulomb] per system (FP64)      */
     NB_F_VIRIAL = 2u,      /* also compute the virial -1/2 sum d (x) f per system (FP64) */
-    NB_F_ACCUMULATE = 4u   /* add into the output arrays instead of overwriting them     */
+    NB_F_ACCUMULATE = 4u,  /* add into the output arrays instead of overwriting them     */
+    NB_F_EXCL_CORR = 8u    /* nb_forces / nb_step: add the electrostatic corrections of
+                              excluded pairs inside rc and of each atom with itself, which
+                              a run with a long-range part needs (Sec. V.A: the real-space
+                              Ewald correction of PME runs; its reaction-field analogue):
+                              Ewald V = -K qa qb erf(beta r)/r, self -K qa^2 beta/sqrt(pi);
+                              RF V = K qa qb (k_rf r^2 - c_rf), self -K qa^2 c_rf / 2;
+                              K = epsfac / eps_r; computed by a kernel of their own in
+                              double precision; no effect with NB_COUL_NONE.  The backward
+                              pass does not differentiate these terms. */
 };
 
 /*
@@ -75,7 +84,8 @@ enum {
  *          c_rf = 1/rc + k_rf rc^2;
  *   V_EW = epsfac qa qb / eps_r erfc(beta r)/r, minus its value at rc under
  *          NB_MOD_POTSHIFT;
- * for pairs with r < rc that are neither self pairs nor listed as excluded.
+ * for pairs with r < rc that are neither self pairs nor listed as excluded (excluded pairs
+ * and self pairs contribute nothing unless NB_F_EXCL_CORR asks for their corrections).
  */
 typedef struct {
     int32_t n_types;          /* LJ types T (1..32); lj tables are [T][T][2]              */
@@ -129,7 +139,10 @@ void nb_destroy(nb_ctx* ctx);
  * as a symmetric CSR list (host int64[N+1] row pointers, host int32[] partner atom
  * indices in the same system); Sec. V.A: excluded pairs never interact and are masked
  * with bit masks stored with the j-clusters.  Self pairs need not be listed.  Copied once;
- * fixed for the lifetime of the context.  At most 32 partners per atom.
+ * fixed for the lifetime of the context.  At most 32 partners per atom.  Errors:
+ * NB_ERR_ARG for a type out of range, a partner out of range or in another system, more
+ * than 32 partners, a partner listed twice, or an asymmetric list (b listed for a but a not
+ * for b).
  */
 nb_status nb_set_topology(nb_ctx* ctx, const int32_t* type, const int64_t* excl_ptr,
                           const int32_t* excl_idx);
@@ -216,33 +229,47 @@ nb_status nb_step_graph(nb_ctx* ctx, const float* x, const float* q, const float
  *   NB_EXEC_PERSIST persistent: one resident grid, items taken in rounds in the same
  *                   most-work-first order, wavefront g taking position g of even rounds
  *                   and position G-1-g of odd rounds (G wavefronts), so the per-wavefront
- *                   totals even out without any atomic.
- * Results do not depend on exec_mode (each item writes its own partial sums); they
- * depend on item_width only through the order of the final per-atom sums (a few ulp).
+ *                   totals even out without any atomic;
+ *   NB_EXEC_BALANCED one resident grid of G wavefronts (those of the energy flavor that fit
+ *                   the device at once), the list cut into G contiguous runs of near-equal
+ *                   cost (an entry costs 1 + 2 x the set bits of its outer mask), each run
+ *                   split at super-cluster boundaries and into pieces of at most
+ *                   item_width entries: every wavefront gets the same share of the work
+ *                   (list splitting against kernel tails, Sec. V.F).  Its items differ from
+ *                   the other modes', so results differ from theirs in the last bits.
+ * Results do not depend on exec_mode among the first four (each item writes its own
+ * partial sums); they depend on the items only through the order of the final per-atom
+ * sums (a few ulp).
  */
-enum { NB_EXEC_STATIC = 0, NB_EXEC_XCD = 1, NB_EXEC_QUEUE = 2, NB_EXEC_PERSIST = 3 };
+enum { NB_EXEC_STATIC = 0, NB_EXEC_XCD = 1, NB_EXEC_QUEUE = 2, NB_EXEC_PERSIST = 3,
+       NB_EXEC_BALANCED = 4 };
 typedef struct {
     int32_t item_width;   /* entries per work item, 1..64 */
     int32_t exec_mode;    /* NB_EXEC_* */
     int32_t prune_fused;  /* nb_step: 1 = rolling prune inside the pair kernel (Sec. V.D),
                              0 = the prune as its own kernels before the pair kernel */
-    int32_t reserved;
+    int32_t prune_waves;  /* wavefronts per work item in the separate rolling-prune kernel:
+                             1, 2, 4 or 8, or 0 = the most with which one rolling part
+                             fits the device at once */
     double us_per_call;   /* nb_autotune: median time of the timed call, microseconds */
 } nb_exec_config;
 
-/* Fix the item width (0 = the built-in rule, about 8192 items, width 8..64), the mode and
- * where nb_step prunes (prune_fused 0 or 1; same inner list and results either way);
- * applies to the current list at once and to every later build.  Errors: NB_ERR_ARG. */
-nb_status nb_set_exec(nb_ctx* ctx, int32_t item_width, int32_t exec_mode, int32_t prune_fused);
+/* Fix the item width (0 = the built-in rule, about 8192 items, width 8..64), the mode,
+ * where nb_step prunes (prune_fused 0 or 1; same inner list and results either way) and
+ * the wavefronts per item of the separate prune kernel (prune_waves 0, 1, 2, 4 or 8; same
+ * inner list either way); applies to the current list at once and to every later build.
+ * Errors: NB_ERR_ARG. */
+nb_status nb_set_exec(nb_ctx* ctx, int32_t item_width, int32_t exec_mode, int32_t prune_fused,
+                      int32_t prune_waves);
 nb_status nb_get_exec(nb_ctx* ctx, nb_exec_config* out);
 
 /*
  * [sync] Autotuner (the paper calls for dynamic auto-tuning of code flavors, Sec. VII):
  * times nb_forces(x, q, lj, flags) on the current list for item widths 8, 16, ..., 64 (steps
- * of 8), each with the four execution modes (repeats timed calls after one warm-up each,
+ * of 8), each with the five execution modes (repeats timed calls after one warm-up each,
  * HIP events, median), then, in the fastest shape, a rolling step (nb_step of part 1,
  * which re-prunes that part with x) with the prune fused and separate; writes up to cap
- * trials to host trials[] and their number (34) to *n_trials, and keeps
+ * trials to host trials[] and their number (42) to *n_trials, and keeps
  * the fastest choices (also returned in *best) for this and later builds.
  * flags: NB_F_ENERGY and/or NB_F_VIRIAL.  Allocates and frees its own output buffers.
  * Errors: NB_ERR_STATE without a list, NB_ERR_ARG.
@@ -277,8 +304,13 @@ nb_status nb_get_grid_dims(nb_ctx* ctx, int32_t* dims);
 /*
  * Cluster pairs of the outer (which = 1) or inner (which = 2) list as triples
  * (i-cluster, j-cluster, shift code) in host int32[cap][3]; shift code
- * (sx+1)*9 + (sy+1)*3 + (sz+1) for the j-cluster image x_j + s L.  *count receives the
- * number of triples (even when above cap, in which case nothing is written).
+ * (sx+1)*9 + (sy+1)*3 + (sz+1) for the j-cluster image x_j + s L.  which = 0 gives the
+ * bounding-box candidates of the build (Sec. V.D: cluster pairs whose bounding boxes lie
+ * within rlist, before the atom-distance prune), recomputed on the current grid by the
+ * search kernel in a recording mode; the box test uses the list's own arithmetic so that
+ * it is a superset of the outer list for every accepted box (allocates a temporary device
+ * buffer).  *count receives the number of triples (even when above cap, in which case
+ * nothing is written).
  */
 nb_status nb_get_pairs(nb_ctx* ctx, int32_t which, int32_t* triples, int64_t cap,
                        int64_t* count);
@@ -339,7 +371,13 @@ nb_status nb_list_coverage(nb_ctx* ctx, int32_t log2_m, int32_t log2_n, int32_t 
  * smallest list radius that keeps it within a tolerance.  Host-only (no context, no device).
  *
  * Atoms are grouped in classes of equal mass, charge and LJ type.  Over a list age t each
- * atom moves by a Gaussian displacement of variance k_B T t^2 / m per axis; beyond the list
+ * atom moves by a Gaussian displacement of variance k_B T t^2 / m per axis (m: the mass that
+ * carries it, its own or that of the rigid unit it belongs to); an atom constrained at a
+ * distance d to a partner about which it rotates (the refinement for constrained atoms,
+ * Sec. V.B) adds the displacement of a free rotor whose angular velocity, perpendicular to
+ * the bond, has the variance k_B T / (m_own d^2) per component: per axis
+ * (2/3) d^2 sqrt(2) s D(s / sqrt(2)), s = t sqrt(k_B T / (m_own d^2)), D Dawson's integral
+ * (as (2/3) k_B T t^2 / m_own at first, levelling off at (2/3) d^2), taken as Gaussian; beyond the list
  * radius partners are spread uniformly; a pair not in the list that ends inside r_c, at a
  * distance of at least r_c / 2, misses |V(r)|, V the pair potential selected by the
  * nb_params (LJ with the electrostatics and the modifier of the kernels).  The missed energy per atom at age (steps - 1) dt, divided by
@@ -361,6 +399,9 @@ typedef struct {
     int32_t n_cov;            /* coverage radii (0: particle list, no implicit buffer)        */
     const float* cov_radii;   /* [n_cov], ascending                                           */
     const int64_t* covered;   /* [n_cov][n_cov] as returned by nb_list_coverage               */
+    const double* rot_len;    /* per class: distance to the constraint partner it rotates
+                                 about, nm (0: none); null: no class rotates                  */
+    const double* rot_mass;   /* per class: the atom's own mass, amu (read where rot_len > 0) */
 } nb_buffer_input;
 
 /* Drift for a list of radius r_list (>= rc) used for `steps` steps after its build.

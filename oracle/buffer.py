@@ -11,8 +11,19 @@ radii[l] -- the pairs within radii[k] that an M x N list at radii[l] contains.
 Drift (the paper names the inputs: masses, temperature, pair potentials and the cluster
 setup with its implicit buffer; the model below is this build's reading of it):
   * over a list age t an atom of mass m moves by a Gaussian of variance k_B T t^2 / m per
-    axis, so the distance of a pair of classes a, b changes by a Gaussian of variance
-    sigma^2 = k_B T t^2 (1/m_a + 1/m_b);
+    axis (free flight; m is the mass that carries the atom: its own, or that of the rigid
+    unit it belongs to), so the distance of a pair of classes a, b changes by a Gaussian
+    of variance sigma^2 = var_a + var_b;
+  * an atom constrained at distance d to a partner about which it rotates (the refinement
+    for constrained atoms of Sec. V.B) adds the displacement of a free rotor: its bond
+    direction u turns at a constant angular velocity w perpendicular to u, a 2-d Gaussian
+    of variance k_B T / (m_own d^2) per component (equipartition of the rotational kinetic
+    energy m_own d^2 |w|^2 / 2), by the angle theta = |w| t; the displacement d (u(t) - u(0))
+    has the squared length 2 d^2 (1 - cos theta), a third of it along any fixed axis, and
+    with |w| Rayleigh distributed E[cos theta] = 1 - sqrt(2) s D(s / sqrt(2)), s^2 =
+    k_B T t^2 / (m_own d^2), D Dawson's integral; the per-axis variance
+    (2/3) d^2 sqrt(2) s D(s / sqrt(2)) grows as (2/3) k_B T t^2 / m_own at first and
+    levels off at (2/3) d^2, and it enters sigma^2 as a Gaussian of that variance;
   * beyond the list radius partners of class b have density N_b / V;
   * a pair not in the list at r0 >= r_l that ends at r < r_c misses |V_ab(r)|; a list holds
     the fraction 1 - U(r0) of the pairs at r0 (U = 1 for a particle list, from a coverage
@@ -31,7 +42,7 @@ import math
 
 import numpy as np
 from scipy import integrate
-from scipy.special import erfc
+from scipy.special import dawsn, erfc
 
 from . import cluster_pairs, radius_sq_f32, split_key
 from .census import pair_r2
@@ -139,6 +150,18 @@ def missed_energy_pair(V, sigma: float, rc: float, r_list: float, U=None) -> flo
     return val
 
 
+def displacement_var(kT: float, t: float, mass: float, rot_len: float = 0.0,
+                     rot_mass: float = 0.0) -> float:
+    """Per-axis variance of an atom's displacement over the time t (module docstring):
+    free flight with the mass that carries it, plus, for rot_len > 0, the rotation about
+    its constraint partner with its own mass rot_mass."""
+    v = kT * t * t / mass
+    if rot_len > 0.0:
+        s = t * math.sqrt(kT / (rot_mass * rot_len * rot_len))
+        v += (2.0 / 3.0) * rot_len * rot_len * math.sqrt(2.0) * s * dawsn(s / math.sqrt(2.0))
+    return v
+
+
 def missed_energy(p, classes: dict, lj, volume: float, temperature: float, dt: float,
                   steps: int, r_list: float, U=None) -> float:
     """Missed energy per atom after (steps - 1) dt (module docstring)."""
@@ -147,17 +170,21 @@ def missed_energy(p, classes: dict, lj, volume: float, temperature: float, dt: f
     mass = np.asarray(classes["mass"], dtype=np.float64)
     charge = np.asarray(classes["charge"], dtype=np.float64)
     typ = np.asarray(classes["type"], dtype=np.int64)
+    rot_len = np.asarray(classes.get("rot_len", np.zeros(count.size)), dtype=np.float64)
+    rot_mass = np.asarray(classes.get("rot_mass", np.zeros(count.size)), dtype=np.float64)
     lj = np.asarray(lj, dtype=np.float64)
     N = count.sum()
     if t <= 0.0 or N == 0:
         return 0.0
     rc = float(p.rc) if not isinstance(p, dict) else p["rc"]
+    kT = KB * temperature
+    var = [displacement_var(kT, t, mass[a], rot_len[a], rot_mass[a]) for a in range(count.size)]
     total = 0.0
     for a in range(count.size):
         for b in range(count.size):
             if count[a] == 0 or count[b] == 0:
                 continue
-            sigma = math.sqrt(KB * temperature * t * t * (1 / mass[a] + 1 / mass[b]))
+            sigma = math.sqrt(var[a] + var[b])
             c6, c12 = lj[typ[a], typ[b], 0], lj[typ[a], typ[b], 1]
             qq = charge[a] * charge[b]
             V = lambda r, c6=c6, c12=c12, qq=qq: pair_potential(r, c6, c12, qq, p)

@@ -10,7 +10,7 @@ NB_OK, NB_ERR_ARG, NB_ERR_BOX, NB_ERR_NOMEM, NB_ERR_CAPACITY, NB_ERR_STATE, NB_E
     NB_ERR_NONFINITE = range(8)
 NB_COUL_RF, NB_COUL_EWALD, NB_COUL_NONE = 0, 1, 2
 NB_MOD_NONE, NB_MOD_POTSHIFT = 0, 1
-NB_F_ENERGY, NB_F_VIRIAL, NB_F_ACCUMULATE = 1, 2, 4
+NB_F_ENERGY, NB_F_VIRIAL, NB_F_ACCUMULATE, NB_F_EXCL_CORR = 1, 2, 4, 8
 
 EXPORTS = ["nb_create", "nb_destroy", "nb_set_topology", "nb_grid_build", "nb_pairlist_build",
            "nb_prune_rolling", "nb_forces", "nb_step", "nb_forces_backward", "nb_get_grid",
@@ -18,9 +18,9 @@ EXPORTS = ["nb_create", "nb_destroy", "nb_set_topology", "nb_grid_build", "nb_pa
            "nb_strerror", "nb_last_error", "nb_step_graph", "nb_set_exec", "nb_get_exec",
            "nb_autotune", "nb_list_census", "nb_list_coverage", "nb_buffer_drift",
            "nb_buffer_estimate", "nb_list_census_noalloc"]
-NB_EXEC_STATIC, NB_EXEC_XCD, NB_EXEC_QUEUE, NB_EXEC_PERSIST = 0, 1, 2, 3
+NB_EXEC_STATIC, NB_EXEC_XCD, NB_EXEC_QUEUE, NB_EXEC_PERSIST, NB_EXEC_BALANCED = 0, 1, 2, 3, 4
 EXEC_MODES = {"static": NB_EXEC_STATIC, "xcd": NB_EXEC_XCD, "queue": NB_EXEC_QUEUE,
-              "persist": NB_EXEC_PERSIST}
+              "persist": NB_EXEC_PERSIST, "balanced": NB_EXEC_BALANCED}
 (NB_T_FORCES, NB_T_FORCE_REDUCE, NB_T_PRUNE, NB_T_BACKWARD, NB_T_BACKWARD_REDUCE, NB_T_CENSUS,
  NB_T_COUNT) = range(7)
 TIMING_KINDS = ["forces", "force_reduce", "prune", "backward", "backward_reduce", "census"]
@@ -44,7 +44,8 @@ class NbBufferInput(ctypes.Structure):
                 ("type", ctypes.c_void_p), ("lj", ctypes.c_void_p),
                 ("volume", ctypes.c_double), ("temperature", ctypes.c_double),
                 ("dt", ctypes.c_double), ("n_cov", ctypes.c_int32),
-                ("cov_radii", ctypes.c_void_p), ("covered", ctypes.c_void_p)]
+                ("cov_radii", ctypes.c_void_p), ("covered", ctypes.c_void_p),
+                ("rot_len", ctypes.c_void_p), ("rot_mass", ctypes.c_void_p)]
 
 
 class NbStats(ctypes.Structure):
@@ -56,7 +57,7 @@ class NbStats(ctypes.Structure):
 
 class NbExecConfig(ctypes.Structure):
     _fields_ = [("item_width", ctypes.c_int32), ("exec_mode", ctypes.c_int32),
-                ("prune_fused", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("prune_fused", ctypes.c_int32), ("prune_waves", ctypes.c_int32),
                 ("us_per_call", ctypes.c_double)]
 
 
@@ -84,7 +85,7 @@ def load():
         "nb_forces": ([P, P, P, P, P, P, P, u32], st),
         "nb_step": ([P, P, P, P, P, P, P, u32, i64], st),
         "nb_step_graph": ([P, P, P, P, P, P, P, u32, i64], st),
-        "nb_set_exec": ([P, i32, i32, i32], st),
+        "nb_set_exec": ([P, i32, i32, i32, i32], st),
         "nb_get_exec": ([P, ctypes.POINTER(NbExecConfig)], st),
         "nb_autotune": ([P, P, P, P, u32, i32, P, i32, ctypes.POINTER(i32),
                          ctypes.POINTER(NbExecConfig)], st),

@@ -18,7 +18,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import EXEC_MODES, NB_F_ACCUMULATE, NB_F_ENERGY, NB_F_VIRIAL, NbExecConfig
+from ._lib import (EXEC_MODES, NB_F_ACCUMULATE, NB_F_ENERGY, NB_F_EXCL_CORR, NB_F_VIRIAL,
+                   NbExecConfig)
 
 _MODE_NAMES = {v: k for k, v in EXEC_MODES.items()}
 
@@ -67,6 +68,13 @@ class _BufferArgs:
         n = self.count.size
         if not (self.mass.size == self.charge.size == self.type.size == n):
             raise ValueError("class arrays count, mass, charge, type differ in length")
+        self.rot_len = self.rot_mass = None
+        if classes.get("rot_len") is not None:
+            self.rot_len = np.ascontiguousarray(classes["rot_len"], dtype=np.float64).reshape(-1)
+            self.rot_mass = np.ascontiguousarray(classes["rot_mass"],
+                                                 dtype=np.float64).reshape(-1)
+            if not (self.rot_len.size == self.rot_mass.size == n):
+                raise ValueError("class arrays rot_len, rot_mass differ in length")
         self.lj = np.ascontiguousarray(np.asarray(lj, dtype=np.float32))
         if self.lj.size != 2 * params.n_types * params.n_types:
             raise ValueError("lj must hold (c6, c12) for n_types x n_types type pairs")
@@ -83,14 +91,18 @@ class _BufferArgs:
             charge=_np_ptr(self.charge), type=_np_ptr(self.type), lj=_np_ptr(self.lj),
             volume=float(volume), temperature=float(temperature), dt=float(dt), n_cov=n_cov,
             cov_radii=_np_ptr(R) if R is not None else None,
-            covered=_np_ptr(C) if C is not None else None)
+            covered=_np_ptr(C) if C is not None else None,
+            rot_len=_np_ptr(self.rot_len) if self.rot_len is not None else None,
+            rot_mass=_np_ptr(self.rot_mass) if self.rot_mass is not None else None)
 
 
 def buffer_drift(params, classes: dict, lj, volume: float, temperature: float, dt: float,
                  steps: int, r_list: float, coverage=None) -> float:
     """Drift (kJ/mol/ps per atom) of a list at r_list used for `steps` steps
-    (nb_buffer_drift).  classes: arrays count, mass, charge, type; coverage: (radii,
-    covered) from Context.list_coverage, or None for a particle list."""
+    (nb_buffer_drift).  classes: arrays count, mass, charge, type, and optionally rot_len,
+    rot_mass (atoms that rotate about a constraint partner: the distance to it and their own
+    mass); coverage: (radii, covered) from Context.list_coverage, or None for a particle
+    list."""
     lib = _lib.load()
     a = _BufferArgs(params, classes, lj, volume, temperature, dt, coverage)
     out = ctypes.c_double()
@@ -195,8 +207,9 @@ class Context:
                     "nb_prune_rolling")
 
     def forces(self, x, q, lj, energy: bool = True, virial: bool = False, f=None, e=None,
-               vir=None, accumulate: bool = False):
-        """Returns (f [N,3] float32, energy [S,2] float64 or None, virial [S,3,3] or None)."""
+               vir=None, accumulate: bool = False, excl_corr: bool = False):
+        """Returns (f [N,3] float32, energy [S,2] float64 or None, virial [S,3,3] or None).
+        excl_corr adds the electrostatic corrections of excluded pairs and self terms."""
         x = self._dev(x, (self.n_atoms, 3), torch.float32, "x")
         q = self._dev(q, (self.n_atoms,), torch.float32, "q")
         lj = self._dev(lj, (self.n_types, self.n_types, 2), torch.float32, "lj")
@@ -213,13 +226,16 @@ class Context:
                 vir = torch.empty((self.n_sys, 3, 3), dtype=torch.float64, device=self.device)
         if accumulate:
             flags |= NB_F_ACCUMULATE
+        if excl_corr:
+            flags |= NB_F_EXCL_CORR
         self._check(self.lib.nb_forces(self.h, _ptr(x), _ptr(q), _ptr(lj), _ptr(f),
                                        _ptr(e) if energy else None,
                                        _ptr(vir) if virial else None, flags), "nb_forces")
         return f, (e if energy else None), (vir if virial else None)
 
     def step(self, x, q, lj, steps_since_build: int, energy: bool = True, virial: bool = False,
-             f=None, e=None, vir=None, accumulate: bool = False, graph: bool = False):
+             f=None, e=None, vir=None, accumulate: bool = False, graph: bool = False,
+             excl_corr: bool = False):
         """Rolling prune of part (steps_since_build mod nstprune) fused into the force pass;
         the same result as prune_rolling(x, steps_since_build) followed by forces(...).
         graph=True replays the step from a captured HIP graph (nb_step_graph): keep x, q,
@@ -240,23 +256,28 @@ class Context:
                 vir = torch.empty((self.n_sys, 3, 3), dtype=torch.float64, device=self.device)
         if accumulate:
             flags |= NB_F_ACCUMULATE
+        if excl_corr:
+            flags |= NB_F_EXCL_CORR
         fn = self.lib.nb_step_graph if graph else self.lib.nb_step
         self._check(fn(self.h, _ptr(x), _ptr(q), _ptr(lj), _ptr(f),
                        _ptr(e) if energy else None, _ptr(vir) if virial else None,
                        flags, int(steps_since_build)), "nb_step_graph" if graph else "nb_step")
         return f, (e if energy else None), (vir if virial else None)
 
-    def set_exec(self, item_width: int = 0, mode: str = "static", prune_fused: bool = True):
-        """Item width (0 = built-in rule), execution mode ('static', 'xcd', 'queue', 'persist') and
-        whether step() prunes inside the pair kernel or with separate kernels."""
+    def set_exec(self, item_width: int = 0, mode: str = "static", prune_fused: bool = True,
+                 prune_waves: int = 0):
+        """Item width (0 = built-in rule), execution mode ('static', 'xcd', 'queue',
+        'persist', 'balanced'), whether step() prunes inside the pair kernel or with separate
+        kernels, and the wavefronts per item of the separate prune (0 = automatic)."""
         self._check(self.lib.nb_set_exec(self.h, int(item_width), EXEC_MODES[mode],
-                                         1 if prune_fused else 0), "nb_set_exec")
+                                         1 if prune_fused else 0, int(prune_waves)),
+                    "nb_set_exec")
 
     def get_exec(self) -> dict:
         out = NbExecConfig()
         self._check(self.lib.nb_get_exec(self.h, ctypes.byref(out)), "nb_get_exec")
         return {"item_width": out.item_width, "mode": _MODE_NAMES[out.exec_mode],
-                "prune_fused": bool(out.prune_fused)}
+                "prune_fused": bool(out.prune_fused), "prune_waves": int(out.prune_waves)}
 
     def autotune(self, x, q, lj, energy: bool = True, virial: bool = False, repeats: int = 5):
         """Time nb_forces over item widths and execution modes on the current list, keep the
@@ -312,7 +333,9 @@ class Context:
         return out
 
     def get_pairs(self, which: str = "outer") -> np.ndarray:
-        w = {"outer": 1, "inner": 2}[which]
+        """Cluster-pair triples (ci, cj, shift code) of the "bb" candidates, the "outer" or
+        the "inner" list (syncs)."""
+        w = {"bb": 0, "outer": 1, "inner": 2}[which]
         n = ctypes.c_int64()
         self._check(self.lib.nb_get_pairs(self.h, w, None, 0, ctypes.byref(n)), "nb_get_pairs")
         out = np.empty((n.value, 3), dtype=np.int32)

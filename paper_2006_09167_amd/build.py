@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libnbmi.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 SOURCES = ["nb_host.cpp", "nb_grid.hip", "nb_list.hip", "nb_forces.hip", "nb_reduce.hip",
-           "nb_backward.hip", "nb_census.hip", "nb_buffer.cpp"]
+           "nb_backward.hip", "nb_census.hip", "nb_buffer.cpp", "nb_excl.hip"]
 ARCH = os.environ.get("NB_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are kept out of every kernel (the compiler would otherwise

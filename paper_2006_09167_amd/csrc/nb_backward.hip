@@ -152,7 +152,7 @@ __device__ __forceinline__ void bwd_item(
         const float4 g = gslot[kScAtoms * sc + lane];
         s_x[lane] = v;
         s_gq[lane] = make_float4(g.x, g.y, g.z, v.w * kp.epsfac_r);
-        s_ti[lane] = type_slot[kScAtoms * sc + lane] * T * (int)sizeof(float4);
+        s_ti[lane] = type_slot[kScAtoms * sc + lane] * T;   // type_slot holds 16 type
     }
     __builtin_amdgcn_wave_barrier();
 
@@ -197,7 +197,7 @@ __device__ __forceinline__ void bwd_item(
             xj.x += shift_value(sx, S.L[0]);
             xj.y += shift_value(sy, S.L[1]);
             xj.z += shift_value(sz, S.L[2]);
-            const int tj16 = tj * (int)sizeof(float4);
+            const int tj16 = tj;                 // type_slot holds 16 type
             const char* lj_j = reinterpret_cast<const char*>(s_lj) + tj16;
 #define NB_BLOCK(c)                                                                    \
     if ((mask >> c) & 1u)                                                              \

@@ -4,8 +4,14 @@
 //
 // Model (all in double precision):
 //   * over a list age t each atom moves by a Gaussian displacement of variance k_B T t^2 / m
-//     per axis (free flight); the distance of a pair of classes a, b then changes by a
-//     Gaussian of variance sigma^2 = k_B T t^2 (1/m_a + 1/m_b);
+//     per axis (free flight, m the mass that carries it); an atom constrained at distance d
+//     to a partner about which it rotates adds a free rotor's displacement d (u(t) - u(0)):
+//     its angular velocity w, perpendicular to the bond, is a 2-d Gaussian of variance
+//     k_B T / (m_own d^2) per component, the squared displacement 2 d^2 (1 - cos |w| t) has a
+//     third along any axis, and over the Rayleigh-distributed |w|
+//     E[cos |w| t] = 1 - sqrt(2) s D(s / sqrt(2)), s^2 = k_B T t^2 / (m_own d^2), D Dawson's
+//     integral; that variance enters as a Gaussian.  The distance of a pair of classes a, b
+//     then changes by a Gaussian of variance sigma^2 = var_a + var_b;
 //   * beyond the list radius the partners of class b are spread with density N_b / V;
 //   * a pair not in the list at distance r0 >= r_l at the build that ends at r < r_c misses
 //     |V_ab(r)|; a cluster list holds the fraction 1 - U(r0) of the pairs at r0 (its
@@ -68,6 +74,39 @@ const Rule& rule8() {
 const Rule& rule16() {
     static const Rule r = gauss_legendre(16);
     return r;
+}
+
+// Dawson's integral D(x) = exp(-x^2) int_0^x exp(t^2) dt = int_0^x exp(-u (2 x - u)) du
+// (u = x - t), x >= 0: 16-point Gauss-Legendre panels over u, at most 1/4 and 1/(4 x) wide,
+// up to where the exponent passes 60 (the rest is below e^-60 x).
+double dawson(double x) {
+    if (!(x > 0.0)) return 0.0;
+    double hi = x;
+    if (x * x > 60.0) hi = x - sqrt(x * x - 60.0);
+    const double w = std::min(0.25, 0.25 / x);
+    const int np = std::max(1, (int)ceil(hi / w));
+    const Rule& g = rule16();
+    double sum = 0.0;
+    for (int p = 0; p < np; ++p) {
+        const double a = hi * p / np, b = hi * (p + 1) / np;
+        const double h = 0.5 * (b - a), m = 0.5 * (a + b);
+        for (size_t j = 0; j < g.x.size(); ++j) {
+            const double u = m + h * g.x[j];
+            sum += h * g.w[j] * exp(-u * (2.0 * x - u));
+        }
+    }
+    return sum;
+}
+
+// Per-axis variance of the displacement of an atom of class a over the time t.
+double displacement_var(const nb_buffer_input& in, int a, double kT, double t) {
+    double v = kT * t * t / in.mass[a];
+    if (in.rot_len && in.rot_len[a] > 0.0) {
+        const double d = in.rot_len[a];
+        const double s = t * sqrt(kT / (in.rot_mass[a] * d * d));
+        v += (2.0 / 3.0) * d * d * M_SQRT2 * s * dawson(s / M_SQRT2);
+    }
+    return v;
 }
 
 // Pair potential of the kernel (LJ and the chosen electrostatics, potential-shift modifier
@@ -133,8 +172,8 @@ double missed_energy(const nb_params& p, const nb_buffer_input& in, int steps, d
     for (int a = 0; a < in.n_classes; ++a)
         for (int b = 0; b < in.n_classes; ++b) {
             if (in.count[a] == 0 || in.count[b] == 0) continue;
-            const double s2 = kBoltzmann * in.temperature * t * t * (1.0 / in.mass[a] + 1.0 / in.mass[b]);
-            const double sig = sqrt(s2);
+            const double kT = kBoltzmann * in.temperature;
+            const double sig = sqrt(displacement_var(in, a, kT, t) + displacement_var(in, b, kT, t));
             if (!(sig > 0.0)) continue;                     // nothing moves (T = 0)
             const int ta = in.type[a], tb = in.type[b];
             const float* lj = in.lj + 2 * ((size_t)ta * p.n_types + tb);
@@ -220,6 +259,12 @@ nb_status check_input(const nb_params* p, const nb_buffer_input* in, int steps) 
         if (in->count[a] < 0 || !(in->mass[a] > 0.0) || in->type[a] < 0 ||
             in->type[a] >= p->n_types || !isfinite(in->charge[a]))
             return NB_ERR_ARG;
+    if (in->rot_len)
+        for (int a = 0; a < in->n_classes; ++a) {
+            if (!(in->rot_len[a] >= 0.0) || !isfinite(in->rot_len[a])) return NB_ERR_ARG;
+            if (in->rot_len[a] > 0.0 && (!in->rot_mass || !(in->rot_mass[a] > 0.0)))
+                return NB_ERR_ARG;
+        }
     if (in->n_cov < 0 || in->n_cov > NB_CENSUS_MAX_RADII) return NB_ERR_ARG;
     if (in->n_cov > 0) {
         if (!in->cov_radii || !in->covered) return NB_ERR_ARG;

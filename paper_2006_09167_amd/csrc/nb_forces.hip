@@ -22,12 +22,13 @@ constexpr int kFwdThreads = kFwdWaves * kWave;
 
 // One 8x8 block of pairs (i-cluster c of the item, the current j-cluster): m is the
 // scalar 64-bit mask of non-excluded lanes (lane = ii + 8 jj), xj the lane's j-atom with
-// the entry's periodic shift already added, lj_j the LDS address of row 0 of the LJ
-// table plus 16 bytes times the j-atom's type (s_t holds 16 T type_i per slot).
+// the entry's periodic shift already added, tjo 16 bytes times the j-atom's type; s_t
+// holds per slot the byte offset of the i-atom's row of the LJ table s_lj (16 T type_i).
 template <int COUL, bool ENERGY, bool VIRIAL>
 __device__ __forceinline__ void pair_block(const float4* s_x, const int* s_t,
+                                           const float4* __restrict__ s_lj,
                                            uint64_t m, float& fx, float& fy,
-                                           float& fz, const float4& xj, const char* lj_j,
+                                           float& fz, const float4& xj, const int tjo,
                                            const NbKParams& kp, float& fjx,
                                            float& fjy, float& fjz, float& elj, float& ec,
                                            float& eclo, float (&vir)[6], int& npair,
@@ -38,7 +39,9 @@ __device__ __forceinline__ void pair_block(const float4* s_x, const int* s_t,
     const uint64_t act = __builtin_amdgcn_ballot_w64(r2 < kp.rc2) & m;
     if (!act) return;
     const bool on = __builtin_amdgcn_inverse_ballot_w64(act);
-    const float4 p = *reinterpret_cast<const float4*>(lj_j + *s_t);   // (6 c6, 12 c12, 12 shift, -)
+    // (6 c6, 12 c12, 12 shift, -) of the pair's types
+    const float4 p = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_lj) +
+                                                      (*s_t + tjo));
     // With energies, pairs outside the cut-off or excluded get 1/r = 0 and q_i q_j = 0
     // (every force and energy term below then vanishes; r2 itself stays finite); without,
     // the scalar force alone is masked at the end.
@@ -108,7 +111,7 @@ __device__ __forceinline__ void fwd_item(
     const int32_t* __restrict__ type_slot, const NbScInfo* __restrict__ sc_info,
     const NbSys* __restrict__ sys, float4* __restrict__ jpart, float4* __restrict__ ipart,
     double* __restrict__ epart, const int epart_stride, const NbKParams& kp,
-    const int prune_i0, const int prune_i1, const float r2_inner) {
+    const int prune_part, const int nstprune, const float r2_inner) {
     const int T = kp.n_types;
     const NbItem it = items[item];
     const int ii = lane & 7, jj = lane >> 3;
@@ -118,7 +121,8 @@ __device__ __forceinline__ void fwd_item(
         // lane l holds slot l of the super-cluster: (8 c + ii) for c = l >> 3
         const float4 v = xq[kScAtoms * sc + lane];
         s_x[lane] = make_float4(v.x, v.y, v.z, v.w * kp.epsfac_r);
-        s_t[lane] = type_slot[kScAtoms * sc + lane] * T * (int)sizeof(float4);
+        // byte offset of the i-atom's row of the LJ table (type_slot holds 16 type)
+        s_t[lane] = type_slot[kScAtoms * sc + lane] * T;
     }
     __builtin_amdgcn_wave_barrier();
 
@@ -131,11 +135,12 @@ __device__ __forceinline__ void fwd_item(
     int npair = 0, nblock = 0;
 
     const int e_end = it.e0 + it.ne;
-    // Items of the rolling part pruned in this pass (Sec. V.E) first re-derive the inner
+    // Items of the rolling part pruned in this pass (Sec. V.E; part = super-cluster mod
+    // nstprune) first re-derive the inner
     // masks of all their entries from the outer masks and the current coordinates, in the
     // list arithmetic: lane (e - e0) keeps entry e's new mask (items hold at most 64
     // entries) for the force loop below, lane 0 writes it back for later passes.
-    const bool do_prune = PRUNE && item >= prune_i0 && item < prune_i1;
+    const bool do_prune = PRUNE && (sc % nstprune) == prune_part;
     uint32_t pmask = 0;
     if (do_prune) {
 #pragma clang fp contract(off)
@@ -175,46 +180,31 @@ __device__ __forceinline__ void fwd_item(
             if (lane == 0) entries[e].meta = (ent.meta & ~(0xffu << 16)) | (imask << 16);
         }
     }
-    NbEntry nxt = entries[it.e0];
-    float4 xj_n = xq[kClusterSize * nxt.cj + jj];
-    int tj_n = type_slot[kClusterSize * nxt.cj + jj];
-    for (int e = it.e0; e < e_end; ++e) {
-        const NbEntry ent = nxt;
-        float4 xj = xj_n;
-        const int tj = tj_n;
-        if (e + 1 < e_end) {               // prefetch the next j-cluster
-            nxt = entries[e + 1];
-            xj_n = xq[kClusterSize * nxt.cj + jj];
-            tj_n = type_slot[kClusterSize * nxt.cj + jj];
-        }
+    // the next entry's j-atom loads are in flight while the current entry is computed
+    float elj = 0.f, ec = 0.f, eclo = 0.f;   // single-precision sums over one entry
+    // xj: the lane's j-atom with the entry's periodic shift already added
+    auto do_entry = [&](const NbEntry& ent, const float4& xj, const int tjo, const int e) {
         const uint32_t mask =
             do_prune ? (uint32_t)__builtin_amdgcn_readlane((int)pmask, e - it.e0)
                      : (ent.meta >> 16) & 0xffu;
-        float4* jp = jpart + (size_t)ent.jpos * kClusterSize;
         // an entry with an empty mask runs no block and stores zero j-partials below
         const int code = ent.meta & 31u;
         const uint64_t* xrow =
             (ent.excl >= 0) ? excl_rows + (size_t)ent.excl * kClustersPerSc : nullptr;
         const bool self = (ent.cj >> 3) == sc && code == kShiftZero;
-        float fjx = 0.f, fjy = 0.f, fjz = 0.f, elj = 0.f, ec = 0.f, eclo = 0.f;
+        float fjx = 0.f, fjy = 0.f, fjz = 0.f;
         float vir[6] = {0, 0, 0, 0, 0, 0};
         const int dc = ent.cj - ci0;        // the i-cluster equal to the j-cluster, if any
 
         // self cluster pairs keep ii < jj only (empty slots fail every distance test)
 #define NB_MASK(c) (((self && dc == c) ? 0x7f3f1f0f07030100ull : ~0ull) & (xrow ? xrow[c] : ~0ull))
-        // Periodic image of the j-cluster: x_j + s L, added once per entry.  The shift is
-        // built from the bits of L with scalar integer operations (s in {-1, 0, 1}).
         {
-            const int sx = shift_x(code), sy = shift_y(code), sz = shift_z(code);
-            xj.x += shift_value(sx, S.L[0]);
-            xj.y += shift_value(sy, S.L[1]);
-            xj.z += shift_value(sz, S.L[2]);
-            const char* lj_j = reinterpret_cast<const char*>(s_lj) + tj * (int)sizeof(float4);
 #define NB_BLOCK(c)                                                                    \
     if ((mask >> c) & 1u)                                                              \
         pair_block<COUL, ENERGY, VIRIAL>(                                              \
-            s_x + kClusterSize * c + ii, s_t + kClusterSize * c + ii, NB_MASK(c), fx##c, fy##c, \
-            fz##c, xj, lj_j, kp, fjx, fjy, fjz, elj, ec, eclo, vir, npair, nblock);
+            s_x + kClusterSize * c + ii, s_t + kClusterSize * c + ii, s_lj, NB_MASK(c), fx##c, \
+            fy##c,                                                                     \
+            fz##c, xj, tjo, kp, fjx, fjy, fjz, elj, ec, eclo, vir, npair, nblock);
             NB_FOR8(NB_BLOCK)
 #undef NB_BLOCK
         }
@@ -223,17 +213,55 @@ __device__ __forceinline__ void fwd_item(
         fjy = dpp_sum8(fjy);
         fjz = dpp_sum8(fjz);
         // every lane of a row holds the same sums: all eight store them (one 128-byte line
-        // per entry), which keeps the last DPP step fused with its add
-        store_stream(&jp[jj], fjx, fjy, fjz, 0.f);
-        if (ENERGY) {
-            elj_acc += (double)elj;
-            if (COUL == NB_COUL_RF) ec_acc += (double)ec + (double)eclo;
-            else if (COUL == NB_COUL_EWALD) ec_acc += (double)ec;
-        }
+        // per entry, non-temporal: read once, later, by the reduction), which keeps the
+        // last DPP step fused with its add
+        store_stream(jpart + (size_t)ent.jpos * kClusterSize + jj, fjx, fjy, fjz, 0.f);
         if (VIRIAL) {
 #pragma unroll
             for (int k = 0; k < 6; ++k) vir_acc[k] += (double)vir[k];
         }
+    };
+    auto load_j = [&](const NbEntry& ent, float4& xj, int& tjo) {
+        xj = xq[kClusterSize * ent.cj + jj];
+        tjo = type_slot[kClusterSize * ent.cj + jj];
+    };
+    auto flush_energy = [&]() {
+        if (ENERGY) {
+            elj_acc += (double)elj;
+            if (COUL == NB_COUL_RF) ec_acc += (double)ec + (double)eclo;
+            else if (COUL == NB_COUL_EWALD) ec_acc += (double)ec;
+            elj = 0.f;
+            ec = 0.f;
+            eclo = 0.f;
+        }
+    };
+    // entry e + 1 is loaded one iteration before its j-atoms, so that load never waits for
+    // the entry it depends on
+    NbEntry nxt = entries[it.e0];
+    NbEntry nxt2 = entries[it.e0 + 1 < e_end ? it.e0 + 1 : it.e0];
+    float4 xj_n;
+    int tj_n;
+    load_j(nxt, xj_n, tj_n);
+    for (int e = it.e0; e < e_end; ++e) {
+        const NbEntry ent = nxt;
+        // Periodic image of the j-cluster: x_j + s L, added once per entry (the shift is
+        // built from the bits of L with scalar integer operations, s in {-1, 0, 1}).  The
+        // loaded coordinates are dead after this, so the next entry's loads can land in
+        // the same registers.
+        const int code = ent.meta & 31u;
+        float4 xj = xj_n;
+        xj.x += shift_value(shift_x(code), S.L[0]);
+        xj.y += shift_value(shift_y(code), S.L[1]);
+        xj.z += shift_value(shift_z(code), S.L[2]);
+        const int tj = tj_n;
+        // prefetch the next j-cluster and the entry after it (past the end the last entry
+        // loads itself again: unconditional loads keep the prefetch registers in place
+        // across iterations)
+        nxt = nxt2;
+        nxt2 = entries[e + 2 < e_end ? e + 2 : e_end - 1];
+        load_j(nxt, xj_n, tj_n);
+        do_entry(ent, xj, tj, e);
+        flush_energy();
     }
     // i-forces: reduce over the eight j-lanes jj (stride 8) and store the item's partials.
     float4* ip = ipart + (size_t)item * kScAtoms;
@@ -293,8 +321,9 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
     const int32_t* __restrict__ type_slot, const NbScInfo* __restrict__ sc_info,
     const NbSys* __restrict__ sys, const float* __restrict__ lj, float4* __restrict__ jpart,
     float4* __restrict__ ipart, double* __restrict__ epart, int epart_stride, NbKParams kp,
-    int n_items, int prune_i0, int prune_i1, float r2_inner, int mode,
-    const int32_t* __restrict__ order, int32_t* __restrict__ queue) {
+    int n_items, int prune_part, int nstprune, float r2_inner, int mode,
+    const int32_t* __restrict__ order, int32_t* __restrict__ queue,
+    const int32_t* __restrict__ wave_item, int n_waves) {
     extern __shared__ float4 s_lj[];
     __shared__ float4 s_x_all[kFwdWaves][kScAtoms];    // per wave: (x, y, z, K q) by slot
     __shared__ int s_t_all[kFwdWaves][kScAtoms];       // per wave: type * T by slot
@@ -311,7 +340,15 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
     int* s_t = s_t_all[wave];
 #define NB_ITEM_ARGS                                                                    \
     lane, s_x, s_t, s_lj, items, entries, excl_rows, xq, type_slot, sc_info, sys, jpart, ipart, \
-        epart, epart_stride, kp, prune_i0, prune_i1, r2_inner
+        epart, epart_stride, kp, prune_part, nstprune, r2_inner
+    if (mode == kExecBalanced) {
+        // each wavefront its own run of items, of near-equal cost
+        const int g = (int)blockIdx.x * kFwdWaves + wave;
+        if (g < n_waves)
+            for (int i = wave_item[g]; i < wave_item[g + 1]; ++i)
+                fwd_item<COUL, ENERGY, VIRIAL, PRUNE>(i, NB_ITEM_ARGS);
+        return;
+    }
     if (mode == kExecQueue) {
         // Tickets are taken in converged code: every lane issues the atomic, lane 0 adding
         // one and the others zero, and lane 0's result is broadcast.  (A fetch inside a
@@ -376,25 +413,26 @@ int prepare_fwd_c(uint32_t flags, size_t lds) {
 
 template <int COUL, bool E, bool V, bool P>
 void launch_fwd_t(const NbDev& d, const NbKParams& kp, const float* lj, int n_items,
-                  int pi0, int pi1, float r2_inner, int mode, hipStream_t s) {
+                  int part, int nstprune, float r2_inner, int mode, hipStream_t s) {
     const size_t lds = sizeof(float4) * (size_t)kp.n_types * kp.n_types;
     int grid = blocks(n_items, kFwdWaves);
     if (mode == kExecQueue || mode == kExecPersist)   // one resident grid over the device
         grid = std::min(grid, fwd_blocks_per_cu<COUL, E, V, P>(lds) * std::max(d.n_cu, 1));
+    if (mode == kExecBalanced) grid = blocks(d.n_waves, kFwdWaves);
     hipLaunchKernelGGL((k_nb_fwd<COUL, E, V, P>), dim3(grid), dim3(kFwdThreads), lds, s,
                        d.items, d.entries, d.excl_rows, d.xq, d.type_slot, d.sc_info, d.sys,
-                       lj, d.jpart, d.ipart, d.epart, d.epart_stride, kp, n_items, pi0, pi1,
-                       r2_inner, mode, d.item_order, d.queue);
+                       lj, d.jpart, d.ipart, d.epart, d.epart_stride, kp, n_items, part,
+                       nstprune, r2_inner, mode, d.item_order, d.queue, d.wave_item, d.n_waves);
 }
 
 template <int COUL, bool P>
 void launch_fwd_c(const NbDev& d, const NbKParams& kp, uint32_t flags, const float* lj,
-                  int n_items, int pi0, int pi1, float r2_inner, int mode, hipStream_t s) {
+                  int n_items, int part, int nstprune, float r2_inner, int mode, hipStream_t s) {
     const bool E = (flags & NB_F_ENERGY) != 0, V = (flags & NB_F_VIRIAL) != 0;
-    if (E && V) launch_fwd_t<COUL, true, true, P>(d, kp, lj, n_items, pi0, pi1, r2_inner, mode, s);
-    else if (E) launch_fwd_t<COUL, true, false, P>(d, kp, lj, n_items, pi0, pi1, r2_inner, mode, s);
-    else if (V) launch_fwd_t<COUL, false, true, P>(d, kp, lj, n_items, pi0, pi1, r2_inner, mode, s);
-    else launch_fwd_t<COUL, false, false, P>(d, kp, lj, n_items, pi0, pi1, r2_inner, mode, s);
+    if (E && V) launch_fwd_t<COUL, true, true, P>(d, kp, lj, n_items, part, nstprune, r2_inner, mode, s);
+    else if (E) launch_fwd_t<COUL, true, false, P>(d, kp, lj, n_items, part, nstprune, r2_inner, mode, s);
+    else if (V) launch_fwd_t<COUL, false, true, P>(d, kp, lj, n_items, part, nstprune, r2_inner, mode, s);
+    else launch_fwd_t<COUL, false, false, P>(d, kp, lj, n_items, part, nstprune, r2_inner, mode, s);
 }
 
 }  // namespace
@@ -417,23 +455,21 @@ hipError_t prepare_forces(int coulomb, uint32_t flags, bool prune, int n_types,
 }
 
 hipError_t launch_forces(const NbDev& d, const NbKParams& kp, int coulomb, uint32_t flags,
-                         const float* lj, int n_items, int prune_i0, int prune_i1,
+                         const float* lj, int n_items, int prune_part, int nstprune,
                          float r2_inner, int mode, hipStream_t s) {
     if (n_items <= 0) return hipGetLastError();
-    const bool P = prune_i1 > prune_i0;
-    const int i0 = P ? prune_i0 : 0, i1 = P ? prune_i1 : 0;
+    const bool P = prune_part >= 0;
     const float r2 = P ? r2_inner : 0.f;
+    const int part = P ? prune_part : -1, np = std::max(nstprune, 1);
     if (coulomb == NB_COUL_RF) {
-        if (P) launch_fwd_c<NB_COUL_RF, true>(d, kp, flags, lj, n_items, i0, i1, r2, mode, s);
-        else launch_fwd_c<NB_COUL_RF, false>(d, kp, flags, lj, n_items, i0, i1, r2, mode, s);
+        if (P) launch_fwd_c<NB_COUL_RF, true>(d, kp, flags, lj, n_items, part, np, r2, mode, s);
+        else launch_fwd_c<NB_COUL_RF, false>(d, kp, flags, lj, n_items, part, np, r2, mode, s);
     } else if (coulomb == NB_COUL_NONE) {
-        if (P) launch_fwd_c<NB_COUL_NONE, true>(d, kp, flags, lj, n_items, i0, i1, r2, mode, s);
-        else launch_fwd_c<NB_COUL_NONE, false>(d, kp, flags, lj, n_items, i0, i1, r2, mode, s);
+        if (P) launch_fwd_c<NB_COUL_NONE, true>(d, kp, flags, lj, n_items, part, np, r2, mode, s);
+        else launch_fwd_c<NB_COUL_NONE, false>(d, kp, flags, lj, n_items, part, np, r2, mode, s);
     } else {
-        if (P) launch_fwd_c<NB_COUL_EWALD, true>(d, kp, flags, lj, n_items, i0, i1, r2, mode, s);
-        else launch_fwd_c<NB_COUL_EWALD, false>(d, kp, flags, lj, n_items, i0, i1, r2, mode, s);
+        if (P) launch_fwd_c<NB_COUL_EWALD, true>(d, kp, flags, lj, n_items, part, np, r2, mode, s);
+        else launch_fwd_c<NB_COUL_EWALD, false>(d, kp, flags, lj, n_items, part, np, r2, mode, s);
     }
     return hipGetLastError();
 }
-
-

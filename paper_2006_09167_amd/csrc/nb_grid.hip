@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kWave) void k_supercell(NbDev d) {
     const int atom = (src >= 0) ? s_a[src] : -1;
     const int slot = sc * kScAtoms + lane;
     d.slot_atom[slot] = atom;
-    d.type_slot[slot] = (atom >= 0) ? d.type[atom] : 0;
+    d.type_slot[slot] = (atom >= 0) ? d.type[atom] * (int)sizeof(float4) : 0;
     float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
     if (atom >= 0) {
         d.atom_slot[atom] = slot;

@@ -27,7 +27,9 @@ struct nb_ctx {
     int32_t item_w = 0;       // entries per work item of the current list
     int32_t fixed_w = 0;      // item width chosen by nb_set_exec / nb_autotune (0 = rule)
     int32_t exec_mode = kExecStatic;
+    bool items_balanced = false;  // the current items are the balanced mode's partition
     bool prune_fused = true;  // nb_step: rolling prune inside the pair kernel, else separate
+    int32_t prune_waves = 0;  // wavefronts per item of the separate prune (0 = automatic)
     uint64_t list_gen = 0;    // bumped whenever items or launch shapes change
     // graphs of nb_step_graph: key = (part, flags, pointers, list_gen)
     struct GraphEntry {
@@ -93,14 +95,23 @@ nb_status hip_fail(nb_ctx* c, hipError_t e, const char* where) {
 
 bool finite_pos(float v) { return isfinite(v) && v > 0.f; }
 
+// Reaction-field constants in double precision: k_rf = (eps_rf - eps_r) / ((2 eps_rf +
+// eps_r) rc^3) (1 / (2 rc^3) for eps_rf = inf), c_rf = 1/rc + k_rf rc^2.
+void rf_constants(const nb_params& p, double* krf_out, double* crf_out) {
+    const double rc = p.rc;
+    double krf;
+    if (isinf(p.eps_rf)) krf = 1.0 / (2.0 * rc * rc * rc);
+    else krf = ((double)p.eps_rf - p.eps_r) / ((2.0 * p.eps_rf + p.eps_r) * rc * rc * rc);
+    *krf_out = krf;
+    *crf_out = 1.0 / rc + krf * rc * rc;
+}
+
 NbKParams kernel_params(const nb_params& p) {
     NbKParams k{};
     const double rc = p.rc;
     k.rc2 = (float)(rc * rc);
-    double krf;
-    if (isinf(p.eps_rf)) krf = 1.0 / (2.0 * rc * rc * rc);
-    else krf = ((double)p.eps_rf - p.eps_r) / ((2.0 * p.eps_rf + p.eps_r) * rc * rc * rc);
-    const double crf = 1.0 / rc + krf * rc * rc;
+    double krf, crf;
+    rf_constants(p, &krf, &crf);
     k.krf = (float)krf;
     k.crf = (float)crf;
     k.krf_lo = (float)(krf - (double)k.krf);
@@ -147,6 +158,8 @@ nb_status ensure_device(nb_ctx* c) {
     NB_HIP(c, dev_alloc(d.sys_sc_start, c->n_sys + 1));
     NB_HIP(c, dev_alloc(d.part_start, c->p.nstprune + 1));
     NB_HIP(c, dev_alloc(d.queue, 4));
+    NB_HIP(c, dev_alloc(d.wave_e, kMaxBalancedWaves + 1));
+    NB_HIP(c, dev_alloc(d.wave_item, kMaxBalancedWaves + 1));
     NB_HIP(c, launch_fill(d.queue, 4, 0, c->stream));
     int n_cu = 0;
     NB_HIP(c, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
@@ -276,7 +289,8 @@ void nb_destroy(nb_ctx* c) {
                     d.sc_istart, d.sc_icount, d.scratch, d.entries, d.entry_sc, d.items,
                     d.part_start, d.excl_rows, d.jseg_count, d.jseg_start, d.jseg_fill,
                     d.jseg_entries, d.totals, d.flags, d.jpart, d.ipart, d.epart, d.glj_part,
-                    d.dstat, d.item_cost, d.item_order, d.queue};
+                    d.dstat, d.item_cost, d.item_order, d.queue, d.xcf, d.xce,
+                    d.part_items, d.wave_e, d.wave_item};
     drop_graphs(c);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     for (void* q : ptrs)
@@ -319,6 +333,24 @@ nb_status nb_set_topology(nb_ctx* c, const int32_t* type, const int64_t* excl_pt
     }
     const int64_t nnz = n > 0 ? excl_ptr[n] : 0;
     if (nnz > INT32_MAX) return fail(c, NB_ERR_ARG, "too many exclusions");
+    // The list is symmetric: b is a partner of a iff a is a partner of b (each side's
+    // exclusion mask is built from its own row).  Self entries are ignored.
+    for (int64_t a = 0; a < n; ++a)
+        for (int64_t k = excl_ptr[a]; k < excl_ptr[a + 1]; ++k) {
+            const int32_t b = excl_idx[k];
+            for (int64_t m = excl_ptr[a]; m < k; ++m)
+                if (excl_idx[m] == b)
+                    return fail(c, NB_ERR_ARG, "exclusion partner " + std::to_string(b) +
+                                                   " listed twice for atom " + std::to_string(a));
+            if (b == a) continue;
+            bool found = false;
+            for (int64_t m = excl_ptr[b]; m < excl_ptr[b + 1] && !found; ++m)
+                found = excl_idx[m] == a;
+            if (!found)
+                return fail(c, NB_ERR_ARG, "exclusions not symmetric: atom " +
+                                               std::to_string(b) + " lacks partner " +
+                                               std::to_string(a));
+        }
     for (int64_t a = 0; a <= n; ++a) hptr[a] = n > 0 ? (int32_t)excl_ptr[a] : 0;
     NbDev& d = c->d;
     nb_status st = ensure_device(c);
@@ -420,6 +452,8 @@ nb_status nb_grid_build(nb_ctx* c, const float* x, const float* box) {
         NB_HIP(c, dev_alloc(d.jseg_count, cl + 8));
         NB_HIP(c, dev_alloc(d.jseg_start, cl + 9));
         NB_HIP(c, dev_alloc(d.jseg_fill, cl + 8));
+        NB_HIP(c, dev_alloc(d.xcf, slots));
+        NB_HIP(c, dev_alloc(d.xce, 7 * ns));
         c->a_sc = ns;
         c->a_excl_nnz = 0;
     }
@@ -456,11 +490,27 @@ int item_width(const nb_ctx* c) {
                                                                target_items));
 }
 
-// Split every super-cluster's entries into items of at most W entries (rolling-part
-// major order); at a build also copy the entries out of the search scratch.
+// Wavefronts of the balanced partition: those of the pair kernel's energy flavor resident
+// on the whole device at once.
+nb_status balanced_waves(nb_ctx* c, int* waves) {
+    int per_cu = 0;
+    NB_HIP(c, prepare_forces(c->p.coulomb, NB_F_ENERGY, false, c->p.n_types, &per_cu));
+    *waves = std::min(kMaxBalancedWaves, std::max(1, per_cu) * std::max(1, c->d.n_cu));
+    return NB_OK;
+}
+
+// Split the entries into items of at most W entries: per super-cluster (rolling-part major
+// order), or in the balanced mode into equal-cost runs per wavefront; at a build also copy
+// the entries out of the search scratch.
 nb_status make_items(nb_ctx* c, int W, bool copy_entries) {
     NbDev& d = c->d;
-    const size_t item_cap = (size_t)c->n_sc + (size_t)(c->n_entries / W) + 1;
+    int waves = 0;
+    if (c->exec_mode == kExecBalanced) {
+        nb_status st = balanced_waves(c, &waves);
+        if (st != NB_OK) return st;
+    }
+    // per super-cluster ceil(n / W) items, plus at most one more per wavefront boundary
+    const size_t item_cap = (size_t)c->n_sc + (size_t)(c->n_entries / W) + 1 + (size_t)waves;
     if (item_cap > c->a_items || !d.items) {
         const size_t ni = item_cap + item_cap / 8 + 64;
         NB_HIP(c, dev_alloc(d.items, ni));
@@ -470,10 +520,14 @@ nb_status make_items(nb_ctx* c, int W, bool copy_entries) {
         NB_HIP(c, dev_alloc(d.epart, ni * kEpartStride));
         d.epart_stride = (int32_t)ni;
         NB_HIP(c, dev_alloc(d.glj_part, ni * (size_t)c->p.n_types * c->p.n_types * 2));
+        NB_HIP(c, dev_alloc(d.part_items, ni));
         c->a_items = ni;
     }
-    NB_HIP(c, launch_make_items(d, c->n_sc, c->cap, W, c->p.nstprune, copy_entries, c->stream));
+    d.n_waves = waves;
+    NB_HIP(c, launch_make_items(d, c->n_sc, c->cap, W, c->p.nstprune, copy_entries, waves,
+                                c->stream));
     c->item_w = W;
+    c->items_balanced = waves > 0;
     return NB_OK;
 }
 
@@ -559,8 +613,6 @@ nb_status nb_pairlist_build(nb_ctx* c) {
     c->n_cl = n_sc * kClustersPerSc;
     c->n_slots = n_sc * kScAtoms;
     const float r2o = radius_sq(c->p.rlist), r2i = radius_sq(c->p.rinner);
-    const double rbb = (double)c->p.rlist * (1.0 + 1e-5) + 1e-6;
-    const float r2bb = (float)(rbb * rbb);
     // Search with the current per-super-cluster capacity; grow and repeat on overflow.
     for (int attempt = 0;; ++attempt) {
         const size_t need = (size_t)std::max(n_sc, 1) * c->cap;
@@ -572,7 +624,7 @@ nb_status nb_pairlist_build(nb_ctx* c) {
                               c->stream));
         // keep the super-cluster count (it lives in the same array)
         NB_HIP(c, launch_fill(d.flags + kFlagNumSc, 1, n_sc, c->stream));
-        NB_HIP(c, launch_search(d, n_sc, c->cap, r2o, r2i, r2bb, c->p.rlist, c->stream));
+        NB_HIP(c, launch_search(d, n_sc, c->cap, r2o, r2i, c->p.rlist, c->stream));
         st = to_host(c, flags, d.flags, kFlagCount);
         if (st != NB_OK) return st;
         if (!flags[kFlagScOverflow]) break;
@@ -599,6 +651,7 @@ nb_status nb_pairlist_build(nb_ctx* c) {
         NB_HIP(c, dev_alloc(d.jseg_entries, ne));
         NB_HIP(c, dev_alloc(d.jpart, ne * kClusterSize));
         c->a_entries = ne;
+        d.entry_cap = (int64_t)ne;
     }
     st = make_items(c, item_width(c), true);
     if (st != NB_OK) return st;
@@ -634,16 +687,17 @@ nb_status nb_prune_rolling(nb_ctx* c, const float* x, int64_t steps_since_build)
     const int i0 = c->part_start[part], i1 = c->part_start[part + 1];
     TimedSection ts(c, NB_T_PRUNE);
     NB_HIP(c, launch_gather(c->d, x, nullptr, c->d.xp, c->n_slots, c->stream));
-    NB_HIP(c, launch_prune(c->d, c->d.xp, i0, i1 - i0, radius_sq(c->p.rinner), c->item_w,
+    NB_HIP(c, launch_prune(c->d, c->d.xp, i0, i1 - i0, radius_sq(c->p.rinner), c->prune_waves,
                            c->stream));
     return NB_OK;
 }
 
 namespace {
+constexpr uint32_t kForceFlags = NB_F_ENERGY | NB_F_VIRIAL | NB_F_ACCUMULATE | NB_F_EXCL_CORR;
+
 nb_status forces_impl(nb_ctx* c, const float* x, const float* q, const float* lj, float* f,
                       double* energy, double* virial, uint32_t flags, int prune_part) {
-    if (flags & ~(uint32_t)(NB_F_ENERGY | NB_F_VIRIAL | NB_F_ACCUMULATE))
-        return fail(c, NB_ERR_ARG, "unknown flag");
+    if (flags & ~kForceFlags) return fail(c, NB_ERR_ARG, "unknown flag");
     if (c->d.n_atoms > 0 && (!x || !q || !lj || !f)) return fail(c, NB_ERR_ARG, "null array");
     if ((flags & NB_F_ENERGY) && !energy) return fail(c, NB_ERR_ARG, "energy output missing");
     if ((flags & NB_F_VIRIAL) && !virial) return fail(c, NB_ERR_ARG, "virial output missing");
@@ -651,8 +705,6 @@ nb_status forces_impl(nb_ctx* c, const float* x, const float* q, const float* lj
     NbDev& d = c->d;
     const NbKParams kp = kernel_params(c->p);
     const bool fused = prune_part >= 0 && c->prune_fused;
-    const int pi0 = fused ? c->part_start[prune_part] : 0;
-    const int pi1 = fused ? c->part_start[prune_part + 1] : 0;
     {
         TimedSection ts(c, NB_T_FORCE_REDUCE);
         NB_HIP(c, launch_gather(d, x, q, d.xq, c->n_slots, c->stream));
@@ -662,17 +714,28 @@ nb_status forces_impl(nb_ctx* c, const float* x, const float* q, const float* lj
         // then the plain pair kernel
         const int i0 = c->part_start[prune_part], i1 = c->part_start[prune_part + 1];
         TimedSection ts(c, NB_T_PRUNE);
-        NB_HIP(c, launch_prune(d, d.xq, i0, i1 - i0, radius_sq(c->p.rinner), c->item_w,
+        NB_HIP(c, launch_prune(d, d.xq, i0, i1 - i0, radius_sq(c->p.rinner), c->prune_waves,
                                c->stream));
     }
     {
         TimedSection ts(c, NB_T_FORCES);
-        NB_HIP(c, launch_forces(d, kp, c->p.coulomb, flags, lj, c->n_items, pi0, pi1,
+        NB_HIP(c, launch_forces(d, kp, c->p.coulomb, flags, lj, c->n_items,
+                                fused ? prune_part : -1, c->p.nstprune,
                                 radius_sq(c->p.rinner), c->exec_mode, c->stream));
     }
+    // Exclusion corrections (a kernel of their own over the excluded pairs; the pair
+    // kernel above is the same with or without them)
+    const bool corr = (flags & NB_F_EXCL_CORR) && c->p.coulomb != NB_COUL_NONE;
     TimedSection ts(c, NB_T_FORCE_REDUCE);
+    if (corr) {
+        double krf, crf;
+        rf_constants(c->p, &krf, &crf);
+        NB_HIP(c, launch_excl_corr(d, kp, c->p.coulomb, krf, crf, c->n_sc, d.xcf, d.xce,
+                                   c->stream));
+    }
     NB_HIP(c, launch_reduce(d, f, (flags & NB_F_ACCUMULATE) != 0, c->n_slots, energy, virial,
-                            flags, c->n_sys, c->stream));
+                            flags, c->n_sys, corr ? d.xcf : nullptr, c->stream));
+    if (corr) NB_HIP(c, launch_excl_energy(d, d.xce, energy, virial, flags, c->n_sys, c->stream));
     return NB_OK;
 }
 }  // namespace
@@ -712,8 +775,7 @@ nb_status nb_step_graph(nb_ctx* c, const float* x, const float* q, const float* 
     int part = -1;
     nb_status st = step_part(c, steps_since_build, &part);
     if (st != NB_OK) return st;
-    if (flags & ~(uint32_t)(NB_F_ENERGY | NB_F_VIRIAL | NB_F_ACCUMULATE))
-        return fail(c, NB_ERR_ARG, "unknown flag");
+    if (flags & ~kForceFlags) return fail(c, NB_ERR_ARG, "unknown flag");
     NB_HIP(c, hipSetDevice(c->device));
     const void* key[7] = {x, q, lj, f, energy, virial, nullptr};
     for (auto& g : c->graphs)
@@ -763,14 +825,19 @@ nb_status nb_step_graph(nb_ctx* c, const float* x, const float* q, const float* 
     return NB_OK;
 }
 
-nb_status nb_set_exec(nb_ctx* c, int32_t width, int32_t exec_mode, int32_t prune_fused) {
+nb_status nb_set_exec(nb_ctx* c, int32_t width, int32_t exec_mode, int32_t prune_fused,
+                      int32_t prune_waves) {
     if (!c) return NB_ERR_ARG;
     if (width < 0 || width > 64) return fail(c, NB_ERR_ARG, "item width must be 0 (rule) or 1..64");
     if (exec_mode != kExecStatic && exec_mode != kExecXcd && exec_mode != kExecQueue &&
-        exec_mode != kExecPersist)
+        exec_mode != kExecPersist && exec_mode != kExecBalanced)
         return fail(c, NB_ERR_ARG, "unknown execution mode");
     if (prune_fused != 0 && prune_fused != 1) return fail(c, NB_ERR_ARG, "prune_fused is 0 or 1");
+    if (prune_waves != 0 && prune_waves != 1 && prune_waves != 2 && prune_waves != 4 &&
+        prune_waves != 8)
+        return fail(c, NB_ERR_ARG, "prune_waves is 0, 1, 2, 4 or 8");
     c->fixed_w = width;
+    c->prune_waves = prune_waves;
     c->exec_mode = exec_mode;
     c->prune_fused = prune_fused != 0;
     c->list_gen++;
@@ -778,7 +845,8 @@ nb_status nb_set_exec(nb_ctx* c, int32_t width, int32_t exec_mode, int32_t prune
         NB_HIP(c, hipSetDevice(c->device));
         drop_graphs(c);
     }
-    if (c->has_list && item_width(c) != c->item_w) {
+    if (c->has_list && (item_width(c) != c->item_w ||
+                        c->items_balanced != (exec_mode == kExecBalanced))) {
         nb_status st = make_items(c, item_width(c), false);
         if (st != NB_OK) return st;
         return finish_items(c);
@@ -791,7 +859,7 @@ nb_status nb_get_exec(nb_ctx* c, nb_exec_config* out) {
     out->item_width = c->has_list ? c->item_w : c->fixed_w;
     out->exec_mode = c->exec_mode;
     out->prune_fused = c->prune_fused ? 1 : 0;
-    out->reserved = 0;
+    out->prune_waves = c->prune_waves;
     out->us_per_call = 0.0;
     return NB_OK;
 }
@@ -822,7 +890,7 @@ nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj
     const bool timing = c->timing;
     c->timing = false;
     const int widths[] = {8, 16, 24, 32, 40, 48, 56, 64};
-    const int modes[] = {kExecStatic, kExecXcd, kExecQueue, kExecPersist};
+    const int modes[] = {kExecStatic, kExecXcd, kExecQueue, kExecPersist, kExecBalanced};
     nb_exec_config win{0, 0, 1, 0, 1e300};
     int n = 0;
     nb_status st = NB_OK;
@@ -848,14 +916,20 @@ nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj
     const bool fused0 = c->prune_fused;
     for (int W : widths) {
         if (st != NB_OK) break;
+        c->exec_mode = kExecStatic;
         st = make_items(c, W, false);
         if (st == NB_OK) st = finish_items(c);
         for (int m : modes) {
             if (st != NB_OK) break;
             c->exec_mode = m;
+            if (m == kExecBalanced) {          // items of its own: equal-cost runs per wavefront
+                st = make_items(c, W, false);
+                if (st == NB_OK) st = finish_items(c);
+                if (st != NB_OK) break;
+            }
             double us = 0.0;
             if (!time_calls(-1, &us)) break;
-            const nb_exec_config t{W, m, fused0 ? 1 : 0, 0, us};
+            const nb_exec_config t{W, m, fused0 ? 1 : 0, c->prune_waves, us};
             if (n < cap) trials[n] = t;
             ++n;
             if (t.us_per_call < win.us_per_call) win = t;
@@ -864,15 +938,15 @@ nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj
     // Then, for the chosen shape, a rolling step with the prune fused into the pair kernel
     // against the prune as its own kernels; the step time decides.
     if (st == NB_OK) {
+        c->exec_mode = win.exec_mode;
         st = make_items(c, win.item_width, false);
         if (st == NB_OK) st = finish_items(c);
-        c->exec_mode = win.exec_mode;
         double best_step = 1e300;
         for (int pf = 1; pf >= 0 && st == NB_OK; --pf) {
             c->prune_fused = pf != 0;
             double us = 0.0;
             if (!time_calls(c->p.nstprune > 1 ? 1 : 0, &us)) break;
-            const nb_exec_config t{win.item_width, win.exec_mode, pf, 0, us};
+            const nb_exec_config t{win.item_width, win.exec_mode, pf, c->prune_waves, us};
             if (n < cap) trials[n] = t;
             ++n;
             if (us < best_step) {
@@ -946,10 +1020,59 @@ nb_status nb_get_grid_dims(nb_ctx* c, int32_t* dims) {
     return NB_OK;
 }
 
+namespace {
+// Cluster pairs passing the bounding-box tests of the search, recomputed on the grid of the
+// current list by the search kernel in its recording mode (same kernel, same inputs).
+nb_status get_bb_pairs(nb_ctx* c, int32_t* triples, int64_t cap, int64_t* count) {
+    NbDev& d = c->d;
+    const int rec_cap = (int)std::min<int64_t>(INT32_MAX / 2, std::max<int64_t>(1, c->stats.bb_pairs));
+    NB_HIP(c, dev_alloc(d.bb_rec, (size_t)rec_cap));
+    nb_status st = NB_OK;
+    std::vector<int4> rec;
+    int32_t n_rec = 0;
+    hipError_t e = launch_fill(d.flags + kFlagBbRecords, 1, 0, c->stream);
+    if (e == hipSuccess)
+        e = launch_search_record(d, c->n_sc, radius_sq(c->p.rlist), c->p.rlist, rec_cap,
+                                 c->stream);
+    if (e != hipSuccess) st = hip_fail(c, e, "bounding-box search");
+    if (st == NB_OK) st = to_host(c, &n_rec, d.flags + kFlagBbRecords, 1);
+    if (st == NB_OK && n_rec > rec_cap)
+        st = fail(c, NB_ERR_HIP, "bounding-box records exceed the build's count");
+    if (st == NB_OK) {
+        rec.resize((size_t)n_rec);
+        st = to_host(c, rec.data(), d.bb_rec, rec.size());
+    }
+    hipFree(d.bb_rec);
+    d.bb_rec = nullptr;
+    if (st != NB_OK) return st;
+    // records are written in completion order: sort them for a deterministic output
+    std::sort(rec.begin(), rec.end(), [](const int4& a, const int4& b) {
+        if (a.x != b.x) return a.x < b.x;
+        if (a.y != b.y) return a.y < b.y;
+        return a.z < b.z;
+    });
+    int64_t n = 0;
+    for (const int4& r : rec) n += __builtin_popcount((uint32_t)r.w);
+    *count = n;
+    if (!triples || cap < n) return NB_OK;
+    int64_t k = 0;
+    for (const int4& r : rec)
+        for (int b = 0; b < 8; ++b)
+            if ((r.w >> b) & 1) {
+                triples[3 * k] = r.x * kClustersPerSc + b;
+                triples[3 * k + 1] = r.y;
+                triples[3 * k + 2] = r.z;
+                ++k;
+            }
+    return NB_OK;
+}
+}  // namespace
+
 nb_status nb_get_pairs(nb_ctx* c, int32_t which, int32_t* triples, int64_t cap, int64_t* count) {
-    if (!c || !count || (which != 1 && which != 2)) return NB_ERR_ARG;
+    if (!c || !count || which < 0 || which > 2) return NB_ERR_ARG;
     if (!c->has_list) return fail(c, NB_ERR_STATE, "no pair list");
     NB_HIP(c, hipSetDevice(c->device));
+    if (which == 0) return get_bb_pairs(c, triples, cap, count);
     const size_t E = (size_t)c->n_entries;
     std::vector<NbEntry> ent(E);
     std::vector<int32_t> esc(E);

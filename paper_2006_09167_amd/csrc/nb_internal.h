@@ -26,6 +26,8 @@ constexpr int kExecStatic = 0;                  // one wavefront per item, in it
 constexpr int kExecXcd = 1;                     // blocks renumbered XCD-contiguously
 constexpr int kExecQueue = 2;                   // persistent grid, atomic item queue
 constexpr int kExecPersist = 3;                 // persistent grid, fixed balanced schedule
+constexpr int kExecBalanced = 4;                // one run of equal-cost items per wavefront
+constexpr int kMaxBalancedWaves = 16384;        // wavefronts of a balanced partition, at most
 constexpr int kMaxItemCost = 64 * 8;            // set outer-mask bits of one item, at most
 
 // One j-entry of a super-cluster's joint list (16 bytes, loaded with one scalar load).
@@ -95,7 +97,8 @@ enum NbFlag {
     kFlagScNeeded = 2,    // largest per-sc entry count seen
     kFlagNumSc = 3,       // number of super-clusters of the current grid
     kFlagNumRows = 4,     // exclusion rows allocated
-    kFlagBbPairs = 5,     // cluster pairs passing the bounding-box test (low 32 bits)
+    kFlagBbPairs = 5,     // cluster pairs passing the bounding-box test
+    kFlagBbRecords = 6,   // records written by the recording search (nb_get_pairs, BB)
     kFlagCount = 8
 };
 
@@ -104,10 +107,16 @@ struct NbDev;   // device buffer set, defined below
 
 hipError_t launch_grid_build(const NbDev& d, const float* x, hipStream_t s);
 hipError_t launch_search(const NbDev& d, int n_sc, int cap, float r2_outer, float r2_inner,
-                         float r2_bb, float rlist, hipStream_t s);
+                         float rlist, hipStream_t s);
+// The same search recording only the cluster pairs that pass the bounding-box tests
+// (d.bb_rec, at most rec_cap records, counted in flags[kFlagBbRecords]).
+hipError_t launch_search_record(const NbDev& d, int n_sc, float r2_outer, float rlist,
+                                int rec_cap, hipStream_t s);
 hipError_t launch_scan_entries(const NbDev& d, int n_sc, hipStream_t s);
+// Work items of at most w entries; balanced_waves > 0: the balanced mode's partition of
+// the list into that many equal-cost runs (wave_e, wave_item), else per super-cluster.
 hipError_t launch_make_items(const NbDev& d, int n_sc, int cap, int w, int nstprune,
-                             bool copy_entries, hipStream_t s);
+                             bool copy_entries, int balanced_waves, hipStream_t s);
 hipError_t launch_item_order(const NbDev& d, int n_items, hipStream_t s);
 hipError_t launch_list_finish(const NbDev& d, int n_sc, int64_t n_entries, int n_cl,
                               hipStream_t s);
@@ -115,10 +124,14 @@ hipError_t launch_fill(int32_t* p, int n, int32_t v, hipStream_t s);
 hipError_t launch_fill_d(double* p, int n, double v, hipStream_t s);
 hipError_t launch_gather(const NbDev& d, const float* x, const float* q, float4* out,
                          int n_slots, hipStream_t s);
+// waves: wavefronts per item (1, 2, 4, 8), or 0 for the most with which all the part's
+// blocks are resident at once
 hipError_t launch_prune(const NbDev& d, const float4* coords, int item0, int n_items,
-                        float r2_inner, int item_width, hipStream_t s);
+                        float r2_inner, int waves, hipStream_t s);
+// prune_part >= 0: the pair kernel also re-prunes the items of that rolling part (parts by
+// super-cluster mod nstprune).
 hipError_t launch_forces(const NbDev& d, const NbKParams& kp, int coulomb, uint32_t flags,
-                         const float* lj, int n_items, int prune_i0, int prune_i1,
+                         const float* lj, int n_items, int prune_part, int nstprune,
                          float r2_inner, int mode, hipStream_t s);
 // Resolve once, outside any stream capture, the launch shape of the pair kernel flavor
 // for these flags (its occupancy, used by the persistent modes); optionally returns the
@@ -129,7 +142,15 @@ hipError_t prepare_forces(int coulomb, uint32_t flags, bool prune, int n_types,
 // with NB_F_ENERGY / NB_F_VIRIAL, the energy chunks in the same launch, then per system.
 hipError_t launch_reduce(const NbDev& d, float* f, bool accumulate, int n_slots,
                         double* energy, double* virial, uint32_t flags, int n_sys,
-                        hipStream_t s);
+                        const float4* xcf, hipStream_t s);
+// Electrostatic corrections of excluded pairs inside rc and of each atom with itself
+// (nb_excl.hip): per-slot forces into xcf (float4 [64 n_sc_max]) and per-super-cluster
+// energy and virial partials into xce ([7][n_sc_max]: E_C, then the six virial sums
+// xx yy zz xy xz yz of phi d d); then added per system to energy / virial.
+hipError_t launch_excl_corr(const NbDev& d, const NbKParams& kp, int coulomb, double krf,
+                            double crf, int n_sc, float4* xcf, double* xce, hipStream_t s);
+hipError_t launch_excl_energy(const NbDev& d, const double* xce, double* energy, double* virial,
+                              uint32_t flags, int n_sys, hipStream_t s);
 hipError_t launch_backward(const NbDev& d, const NbKParams& kp, int coulomb, const float* lj,
                            const float* grad_f, const double* grad_energy, bool ljgrad,
                            int n_slots, int n_items, int mode, hipStream_t s);
@@ -193,7 +214,8 @@ struct NbDev {
     NbScInfo* sc_info = nullptr;       // [n_sc_max]
     int32_t* slot_atom = nullptr;      // [64 n_sc_max]
     int32_t* atom_slot = nullptr;      // [N]
-    int32_t* type_slot = nullptr;      // [64 n_sc_max]
+    int32_t* type_slot = nullptr;      // [64 n_sc_max] 16 type: the byte offset of the type's
+                                       // entry in a row of a float4 table over types
     int32_t* excl_slot = nullptr;      // [64 n_sc_max][max_excl]
     float4* cl_bb = nullptr;           // [8 n_sc_max][2] lo (w = atom count), hi
     float4* sc_bb = nullptr;           // [n_sc_max][2]
@@ -209,6 +231,8 @@ struct NbDev {
     int32_t* sc_icount = nullptr;      // [n_sc_max]
     int32_t* sc_ipos = nullptr;        // [n_sc_max+1] item ranks in super-cluster order
     NbEntry* scratch = nullptr;        // [n_sc_max * cap]
+    int4* bb_rec = nullptr;            // bounding-box records (sc, cj, shift code, i-mask),
+                                       // only during nb_get_pairs(which = 0)
     NbEntry* entries = nullptr;        // [entry_cap]
     int32_t* entry_sc = nullptr;       // [entry_cap]
     NbItem* items = nullptr;           // [item_cap]
@@ -217,7 +241,11 @@ struct NbDev {
     int32_t* queue = nullptr;          // [4] item counter, finished wavefronts, finished
                                        //     energy-chunk blocks, unused (kept zero between
                                        //     launches by the kernels themselves)
-    int32_t* part_start = nullptr;     // [nstprune+1] item ranges per rolling part
+    int32_t* part_start = nullptr;     // [nstprune+1] ranges of part_items per rolling part
+    int32_t* part_items = nullptr;     // [item_cap] items grouped by rolling part
+    int32_t* wave_e = nullptr;         // [kMaxBalancedWaves+1] first entry per wavefront
+    int32_t* wave_item = nullptr;      // [kMaxBalancedWaves+1] first item per wavefront
+    int32_t n_waves = 0;               // wavefronts of the balanced partition (0: none)
     uint64_t* excl_rows = nullptr;     // [entry_cap][8]
     int32_t* jseg_count = nullptr;     // [8 n_sc_max]
     int32_t* jseg_start = nullptr;     // [8 n_sc_max + 1]
@@ -227,6 +255,7 @@ struct NbDev {
     int32_t* flags = nullptr;          // [kFlagCount]
     // force partials
     float4* jpart = nullptr;           // [entry_cap * 8]
+    int64_t entry_cap = 0;             // entries allocated
     float4* ipart = nullptr;           // [item_cap * 64]
     double* epart = nullptr;           // [kEpartStride][epart_stride] by item rank
     int32_t epart_stride = 0;
@@ -236,6 +265,8 @@ struct NbDev {
     double* cpart = nullptr;           // [n_chunks][kChunkVals] chunk partial sums
     int32_t n_chunks = 0;
     double* dstat = nullptr;           // [n_sys][2]: effective / computed pairs, last call
+    float4* xcf = nullptr;             // [64 n_sc_max] exclusion-correction forces by slot
+    double* xce = nullptr;             // [7][n_sc_max] exclusion-correction energy, virial
 };
 
 constexpr int kEpartStride = 10;       // E_LJ, E_C, virial xx yy zz xy xz yz, pairs, slots

@@ -42,14 +42,32 @@ __device__ inline float list_r2(float4 xi, float4 xj, int sx, int sy, int sz, co
     return t + zz;
 }
 
-// Squared gap between two boxes, the j box shifted by s L (conservative: compared with a
-// slightly enlarged radius).
-__device__ inline float bb_d2(float4 ilo, float4 ihi, float4 jlo, float4 jhi, float ox, float oy,
-                              float oz) {
-    const float gx = fmaxf(0.f, fmaxf(jlo.x + ox - ihi.x, ilo.x - (jhi.x + ox)));
-    const float gy = fmaxf(0.f, fmaxf(jlo.y + oy - ihi.y, ilo.y - (jhi.y + oy)));
-    const float gz = fmaxf(0.f, fmaxf(jlo.z + oz - ihi.z, ilo.z - (jhi.z + oz)));
-    return gx * gx + gy * gy + gz * gz;
+// Gap along one axis between an i box [ilo, ihi] and a j box [jlo, jhi] whose image is
+// x_j + s L, with the shift on the same side as in list_r2 (x_i - L for s > 0, x_j - L for
+// s < 0).  Rounding is monotone, so every atom's shifted coordinate lies inside its box's
+// shifted bounds, and the gap (b_lo - a_hi or a_lo - b_hi, one rounding) is at most the
+// |a - b| of every atom pair of the two boxes.
+__device__ inline float bb_gap(float ilo, float ihi, float jlo, float jhi, int s, float L) {
+#pragma clang fp contract(off)
+    const float alo = (s > 0) ? ilo - L : ilo, ahi = (s > 0) ? ihi - L : ihi;
+    const float blo = (s < 0) ? jlo - L : jlo, bhi = (s < 0) ? jhi - L : jhi;
+    return fmaxf(0.f, fmaxf(blo - ahi, alo - bhi));
+}
+
+// Squared box gap summed as list_r2 sums (no contraction).  Squares and sums of
+// non-negative terms are monotone too, so bb_d2 <= list_r2 for every atom pair of the two
+// boxes: compared with the list's own squared radius, the box test never rejects a pair the
+// atom-distance test would keep (the bounding-box candidates are a superset of the list,
+// Sec. V.D), for any box edge.
+__device__ inline float bb_d2(float4 ilo, float4 ihi, float4 jlo, float4 jhi, int sx, int sy,
+                              int sz, const NbSys& S) {
+#pragma clang fp contract(off)
+    const float gx = bb_gap(ilo.x, ihi.x, jlo.x, jhi.x, sx, S.L[0]);
+    const float gy = bb_gap(ilo.y, ihi.y, jlo.y, jhi.y, sy, S.L[1]);
+    const float gz = bb_gap(ilo.z, ihi.z, jlo.z, jhi.z, sz, S.L[2]);
+    const float xx = gx * gx, yy = gy * gy, zz = gz * gz;
+    const float t = xx + yy;
+    return t + zz;
 }
 
 // Valid-lane mask of an 8x8 cluster pair (lane = ii + 8 jj): real i-atoms (ii < ni), real
@@ -62,8 +80,12 @@ __device__ inline uint64_t pair_valid_mask(int ni, int nj, bool diag) {
     return imask & jmask & (diag ? tri : ~0ull);
 }
 
+// One wavefront per i-super-cluster.  kRecord: only list the cluster pairs that pass the
+// bounding-box tests, as records (super-cluster, j-cluster, shift code, 8-bit i-mask) in
+// d.bb_rec (counted in flags[kFlagBbRecords]), and leave the list and its counters alone.
+template <bool kRecord>
 __global__ __launch_bounds__(kWave) void k_search(NbDev d, int cap, float r2_outer,
-                                                   float r2_inner, float r2_bb, float rlist) {
+                                                   float r2_inner, float rlist, int rec_cap) {
     const int sc = blockIdx.x;
     const int lane = threadIdx.x;
     const int ii = lane & 7, jj = lane >> 3;
@@ -105,7 +127,7 @@ __global__ __launch_bounds__(kWave) void k_search(NbDev d, int cap, float r2_out
                     const int J = J0 + k / 3;
                     const int sz = k % 3 - 1;
                     const float4 jlo = d.sc_bb[2 * J], jhi = d.sc_bb[2 * J + 1];
-                    pass = bb_d2(slo, shi, jlo, jhi, sx * S.L[0], sy * S.L[1], sz * S.L[2]) < r2_bb;
+                    pass = bb_d2(slo, shi, jlo, jhi, sx, sy, sz, S) < r2_outer;
                 }
                 uint64_t cand = __builtin_amdgcn_ballot_w64(pass);
                 while (cand) {
@@ -114,20 +136,27 @@ __global__ __launch_bounds__(kWave) void k_search(NbDev d, int cap, float r2_out
                     const int J = J0 + (base + t) / 3;
                     const int sz = (base + t) % 3 - 1;
                     const int code = (sx + 1) * 9 + (sy + 1) * 3 + (sz + 1);
-                    const float ox = sx * S.L[0], oy = sy * S.L[1], oz = sz * S.L[2];
                     // 64 cluster-pair box tests: lane -> (j-cluster jj, i-cluster ii)
                     const int cjl = kClustersPerSc * J + jj;
                     const int cil = ci0 + ii;
                     const float4 jlo = d.cl_bb[2 * cjl], jhi = d.cl_bb[2 * cjl + 1];
                     const bool canon = (cjl > cil) || (cjl == cil && code >= kShiftZero);
                     const bool ok = canon && jlo.w > 0.f && s_ilo[ii].w > 0.f &&
-                                    bb_d2(s_ilo[ii], s_ihi[ii], jlo, jhi, ox, oy, oz) < r2_bb;
+                                    bb_d2(s_ilo[ii], s_ihi[ii], jlo, jhi, sx, sy, sz, S) < r2_outer;
                     const uint64_t M = __builtin_amdgcn_ballot_w64(ok);
                     for (int jc = 0; jc < kClustersPerSc; ++jc) {
                         const uint32_t bbmask = (uint32_t)(M >> (8 * jc)) & 0xffu;
                         if (!bbmask) continue;
                         bb_pairs += __builtin_popcount(bbmask);
                         const int cj = kClustersPerSc * J + jc;
+                        if constexpr (kRecord) {
+                            if (lane == 0) {
+                                const int r = atomicAdd(&d.flags[kFlagBbRecords], 1);
+                                if (r < rec_cap)
+                                    d.bb_rec[r] = make_int4(sc, cj, code, (int)bbmask);
+                            }
+                            continue;
+                        }
                         const int nj = (int)d.cl_bb[2 * cj].w;
                         const float4 xj = d.xw[kClusterSize * cj + jj];
                         uint32_t omask = 0, imask = 0;
@@ -160,7 +189,7 @@ __global__ __launch_bounds__(kWave) void k_search(NbDev d, int cap, float r2_out
             }
         }
     }
-    if (lane == 0) {
+    if (!kRecord && lane == 0) {
         d.sc_ecount[sc] = min(n_out, cap);
         if (n_out > cap) atomicOr(&d.flags[kFlagScOverflow], 1);
         atomicMax(&d.flags[kFlagScNeeded], n_out);
@@ -243,8 +272,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_items(NbDev d, int n_sc, 
 
 // Per super-cluster: copy its entries from the search scratch (at a build only; later
 // re-splits into items of another width keep the entries, whose masks the rolling prune
-// has changed since), and write its work items.
-__global__ __launch_bounds__(kWave) void k_compact(NbDev d, int cap, int w, int copy_entries) {
+// has changed since), and write its work items (with write_items; their part-major order
+// is the item order itself, so part_items is the identity).
+__global__ __launch_bounds__(kWave) void k_compact(NbDev d, int cap, int w, int copy_entries,
+                                                   int write_items) {
     const int sc = blockIdx.x;
     const int n = d.sc_ecount[sc];
     const int e0 = d.sc_estart[sc];
@@ -253,6 +284,7 @@ __global__ __launch_bounds__(kWave) void k_compact(NbDev d, int cap, int w, int 
             d.entries[e0 + k] = d.scratch[(size_t)sc * cap + k];
             d.entry_sc[e0 + k] = sc;
         }
+    if (!write_items) return;
     const int i0 = d.sc_istart[sc], ni = d.sc_icount[sc];
     const int p0 = d.sc_ipos[sc];
     // ni = ceil(n / w) items of near-equal length (floor or ceil of n / ni, never above w)
@@ -264,7 +296,125 @@ __global__ __launch_bounds__(kWave) void k_compact(NbDev d, int cap, int w, int 
         it.ne = b - a;
         it.pos = p0 + k;
         d.items[i0 + k] = it;
+        d.part_items[i0 + k] = i0 + k;
     }
+}
+
+// Work items for the balanced execution mode: the entries (in super-cluster order) are
+// dealt to P wavefronts in contiguous runs of near-equal cost, an entry costing 1 + 2 x
+// (set bits of its outer mask) (a fixed part for its j-cluster load, partial store and
+// reductions, and its possible 8 x 8 blocks), so that all wavefronts of one resident grid
+// end together (the paper's list splitting against kernel tails, Sec. V.F, taken to its
+// end: no wavefront waits for another's longer list).  Items are the pieces of a
+// super-cluster's list inside one wavefront's run, cut further into near-equal pieces of
+// at most w entries; wave_item[g] .. wave_item[g + 1] are the items of wavefront g, in
+// super-cluster order (so item index = rank).  part_items lists the items of each rolling
+// part together (part p: super-clusters p, p + nparts, ...) for the separate prune.
+// One block; prefix (>= E + 1 ints) and ppos (>= n_sc ints) are scratch.
+__global__ __launch_bounds__(kScanThreads) void k_balanced_items(NbDev d, int n_sc, int w,
+                                                                 int nparts, int P,
+                                                                 int32_t* prefix,
+                                                                 int32_t* ppos) {
+    const int E = d.totals[0];
+    const int C = block_scan(E, [&](int i) {
+        return 1 + 2 * __builtin_popcount((d.entries[i].meta >> 8) & 0xffu);
+    }, prefix);
+    __syncthreads();
+    for (int g = threadIdx.x; g <= P; g += blockDim.x) {
+        const int64_t target = ((int64_t)g * C + P - 1) / P;        // ceil(g C / P)
+        int lo = 0, hi = E;                                          // first prefix >= target
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (prefix[mid] < target) lo = mid + 1;
+            else hi = mid;
+        }
+        d.wave_e[g] = (g == P) ? E : lo;
+    }
+    __syncthreads();
+    // pieces of super-cluster sc: its entries cut at the wavefront boundaries inside them,
+    // each run cut into ceil(len / w) near-equal items; f(first entry, entries, item index
+    // within the super-cluster) for each item in order
+    auto for_items = [&](int sc, auto&& f) {
+        const int a = d.sc_estart[sc], b = a + d.sc_ecount[sc];
+        int lo = 0, hi = P + 1;                      // first boundary above a
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (d.wave_e[mid] <= a) lo = mid + 1;
+            else hi = mid;
+        }
+        int k = 0;
+        for (int s0 = a, g = lo; s0 < b; ++g) {
+            const int t = (g <= P && d.wave_e[g] < b) ? d.wave_e[g] : b;
+            const int len = t - s0, ni = (len + w - 1) / w;
+            for (int j = 0; j < ni; ++j) {
+                const int x0 = (int)((int64_t)j * len / ni), x1 = (int)((int64_t)(j + 1) * len / ni);
+                f(s0 + x0, x1 - x0, k++);
+            }
+            s0 = t;
+        }
+        return k;
+    };
+    for (int sc = threadIdx.x; sc < n_sc; sc += blockDim.x)
+        d.sc_icount[sc] = for_items(sc, [](int, int, int) {});
+    __syncthreads();
+    const int total = block_scan(n_sc, [&](int sc) { return d.sc_icount[sc]; }, d.sc_istart);
+    __syncthreads();
+    // part-major positions: parts p hold super-clusters p, p + nparts, ...
+    auto sc_of = [&](int k) {
+        int p = 0, before = 0;
+        while (p < nparts) {
+            const int cnt = (n_sc > p) ? (n_sc - p + nparts - 1) / nparts : 0;
+            if (k < before + cnt) break;
+            before += cnt;
+            ++p;
+        }
+        return p + nparts * (k - before);
+    };
+    block_scan(n_sc, [&](int k) { return d.sc_icount[sc_of(k)]; }, ppos);
+    __syncthreads();
+    for (int sc = threadIdx.x; sc < n_sc; sc += blockDim.x) {
+        d.sc_ipos[sc] = d.sc_istart[sc];
+        const int i0 = d.sc_istart[sc];
+        // part-major position of this super-cluster's first item
+        int k = 0;
+        {
+            const int p = sc % nparts;
+            for (int q = 0; q < p; ++q) k += (n_sc > q) ? (n_sc - q + nparts - 1) / nparts : 0;
+            k += sc / nparts;
+        }
+        const int pp = ppos[k];
+        for_items(sc, [&](int e0, int ne, int j) {
+            NbItem it;
+            it.sc = sc;
+            it.e0 = e0;
+            it.ne = ne;
+            it.pos = i0 + j;
+            d.items[i0 + j] = it;
+            d.part_items[pp + j] = i0 + j;
+        });
+    }
+    __syncthreads();
+    for (int g = threadIdx.x; g <= P; g += blockDim.x) {
+        // first item starting at or after the wavefront's first entry
+        int lo = 0, hi = total;
+        const int e = d.wave_e[g];
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (d.items[mid].e0 < e) lo = mid + 1;
+            else hi = mid;
+        }
+        d.wave_item[g] = (g == P) ? total : lo;
+    }
+    if (threadIdx.x == 0) {
+        int before = 0;
+        for (int p = 0; p < nparts; ++p) {
+            d.part_start[p] = (before < n_sc) ? ppos[before] : total;
+            before += (n_sc > p) ? (n_sc - p + nparts - 1) / nparts : 0;
+        }
+        d.part_start[nparts] = total;
+        d.totals[1] = total;
+    }
+    d.sc_ipos[n_sc] = total;
 }
 
 // One thread per entry: exclusion masks (bit ii + 8 jj cleared for excluded atom pairs),
@@ -338,29 +488,26 @@ __global__ __launch_bounds__(kWave) void k_jseg_rank(NbDev d) {
     }
 }
 
-// wavefronts per item (one block per item): eight when a part has few items (fewer than
-// kPruneFewItemsPerCu per CU: each wavefront's entry walk is then the critical path), else
-// four (fewer wavefronts to start per entry)
-constexpr int kPruneFewItemsPerCu = 8;
 #define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
-// Rolling prune (Sec. V.E) of a range of work items: one block per item, whose 64 i-atoms
-// are staged once in LDS (one load per lane) and whose entries are dealt to the block's
-// wavefronts in turn, each processing its entries in order with the next four entries'
-// j-clusters in flight.  For every i-cluster of the outer mask the inner bit is set iff
-// some atom pair is closer than r_inner in the list arithmetic (shift split between the
-// two sides, no contraction).  Empty slots sit far outside the box, so no valid-atom masks
-// are needed; a cluster with itself keeps ii < jj.
+// Rolling prune (Sec. V.E) of a range of the items of one part (part_items lists each
+// part's items together): one block of kPruneWaves wavefronts per item, wavefront w taking
+// the item's entries w, w + kPruneWaves, ... in order with the next four entries'
+// j-clusters in flight.  Each wavefront loads the item's 64 i-atoms itself (lane ii of
+// cluster c: slot 8 c + ii), at the same time as its first entries: the waves of a block
+// share no data, so there is no barrier and the dependent loads before the first distance
+// test are the item, its entries and their j-clusters.  For every i-cluster of the outer
+// mask the inner bit is set iff some atom pair is closer than r_inner in the list
+// arithmetic (shift split between the two sides, no contraction).  Empty slots sit far
+// outside the box, so no valid-atom masks are needed; a cluster with itself keeps ii < jj.
 template <int kPruneWaves>
 __global__ __launch_bounds__(kPruneWaves * kWave) void k_prune(
-    const NbItem* __restrict__ items, NbEntry* __restrict__ entries,
-    const float4* __restrict__ xp, const NbScInfo* __restrict__ sc_info,
-    const NbSys* __restrict__ sys, int item0, float r2_inner) {
+    const NbItem* __restrict__ items, const int32_t* __restrict__ part_items,
+    NbEntry* __restrict__ entries, const float4* __restrict__ xp,
+    const NbScInfo* __restrict__ sc_info, const NbSys* __restrict__ sys, int item0,
+    float r2_inner) {
 #pragma clang fp contract(off)
-    __shared__ float4 s_xi[kScAtoms];
-    const NbItem it = items[item0 + blockIdx.x];
-    if (threadIdx.x < kScAtoms) s_xi[threadIdx.x] = xp[kScAtoms * it.sc + threadIdx.x];
-    __syncthreads();
+    const NbItem it = items[part_items[item0 + blockIdx.x]];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x & (kWave - 1);
     const int ii = lane & 7, jj = lane >> 3;
@@ -369,32 +516,34 @@ __global__ __launch_bounds__(kPruneWaves * kWave) void k_prune(
     if (e_first >= e_end) return;
     const NbSys S = sys[sc_info[it.sc].sys];
     const int ci0 = kClustersPerSc * it.sc;
-#define NB_PI(c) const float4 xi##c = s_xi[kClusterSize * c + ii];
+#define NB_PI(c) const float4 xi##c = xp[kScAtoms * it.sc + kClusterSize * c + ii];
     NB_FOR8(NB_PI)
 #undef NB_PI
     const int kStep = kPruneWaves;
-    // a ring of the next kAhead entries and their j-clusters, loaded in flight
-    constexpr int kAhead = 4;
-    NbEntry en[kAhead];
+    // Rings of the wavefront's next entries and of their j-clusters, loaded in flight: a
+    // j-cluster is loaded kAhead iterations before its use, and its entry kLead iterations
+    // before that, so no load waits for the entry it depends on.  Positions past the end
+    // load the wavefront's first entry again (valid memory, never used).
+    constexpr int kAhead = 4, kLead = 2;
+    NbEntry en[kAhead + kLead];
     float4 xq[kAhead];
 #pragma unroll
-    for (int a = 0; a < kAhead; ++a) {
+    for (int a = 0; a < kAhead + kLead; ++a) {
         const int ea = e_first + a * kStep;
         en[a] = entries[ea < e_end ? ea : e_first];
-        xq[a] = xp[kClusterSize * en[a].cj + jj];
     }
+#pragma unroll
+    for (int a = 0; a < kAhead; ++a) xq[a] = xp[kClusterSize * en[a].cj + jj];
     for (int e = e_first; e < e_end; e += kStep) {
         const NbEntry ent = en[0];
         float4 xj = xq[0];
 #pragma unroll
-        for (int a = 0; a + 1 < kAhead; ++a) {
-            en[a] = en[a + 1];
-            xq[a] = xq[a + 1];
-        }
-        if (e + kAhead * kStep < e_end) {
-            en[kAhead - 1] = entries[e + kAhead * kStep];
-            xq[kAhead - 1] = xp[kClusterSize * en[kAhead - 1].cj + jj];
-        }
+        for (int a = 0; a + 1 < kAhead + kLead; ++a) en[a] = en[a + 1];
+#pragma unroll
+        for (int a = 0; a + 1 < kAhead; ++a) xq[a] = xq[a + 1];
+        xq[kAhead - 1] = xp[kClusterSize * en[kAhead - 1].cj + jj];
+        const int en_next = e + (kAhead + kLead) * kStep;
+        en[kAhead + kLead - 1] = entries[en_next < e_end ? en_next : e_first];
         const int code = ent.meta & 31u;
         const uint32_t omask = (ent.meta >> 8) & 0xffu;
         uint32_t imask = 0;
@@ -482,10 +631,18 @@ hipError_t launch_item_order(const NbDev& d, int n_items, hipStream_t s) {
 }
 
 hipError_t launch_search(const NbDev& d, int n_sc, int cap, float r2_outer, float r2_inner,
-                         float r2_bb, float rlist, hipStream_t s) {
+                         float rlist, hipStream_t s) {
     if (n_sc > 0)
-        hipLaunchKernelGGL(k_search, dim3(n_sc), dim3(kWave), 0, s, d, cap, r2_outer, r2_inner,
-                           r2_bb, rlist);
+        hipLaunchKernelGGL(k_search<false>, dim3(n_sc), dim3(kWave), 0, s, d, cap, r2_outer,
+                           r2_inner, rlist, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_search_record(const NbDev& d, int n_sc, float r2_outer, float rlist,
+                                int rec_cap, hipStream_t s) {
+    if (n_sc > 0)
+        hipLaunchKernelGGL(k_search<true>, dim3(n_sc), dim3(kWave), 0, s, d, 0, r2_outer,
+                           r2_outer, rlist, rec_cap);
     return hipGetLastError();
 }
 
@@ -495,13 +652,21 @@ hipError_t launch_scan_entries(const NbDev& d, int n_sc, hipStream_t s) {
 }
 
 hipError_t launch_make_items(const NbDev& d, int n_sc, int cap, int w, int nstprune,
-                             bool copy_entries, hipStream_t s) {
+                             bool copy_entries, int balanced_waves, hipStream_t s) {
+    if (balanced_waves > 0) {
+        if (copy_entries && n_sc > 0)
+            hipLaunchKernelGGL(k_compact, dim3(n_sc), dim3(kWave), 0, s, d, cap, w, 1, 0);
+        // jseg_entries (entry_cap >= E + 1) and jseg_fill (>= n_sc) serve as scratch
+        hipLaunchKernelGGL(k_balanced_items, dim3(1), dim3(kScanThreads), 0, s, d, n_sc, w,
+                           nstprune, balanced_waves, d.jseg_entries, d.jseg_fill);
+        return hipGetLastError();
+    }
     // jseg_fill doubles as the scratch of the permuted scan (n_sc + 1 <= 8 n_sc_max).
     hipLaunchKernelGGL(k_scan_items, dim3(1), dim3(kScanThreads), 0, s, d, n_sc, w, nstprune,
                        d.jseg_fill);
     if (n_sc > 0)
         hipLaunchKernelGGL(k_compact, dim3(n_sc), dim3(kWave), 0, s, d, cap, w,
-                           copy_entries ? 1 : 0);
+                           copy_entries ? 1 : 0, 1);
     return hipGetLastError();
 }
 
@@ -521,15 +686,40 @@ hipError_t launch_list_finish(const NbDev& d, int n_sc, int64_t n_entries, int n
     return hipGetLastError();
 }
 
+namespace {
+// Blocks of k_prune<W> resident on one CU (queried once).
+template <int W>
+int prune_blocks_per_cu() {
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_prune<W>, W * kWave, 0) !=
+                hipSuccess ||
+            nb < 1)
+            nb = 1;
+        per_cu = nb;
+    }
+    return per_cu;
+}
+}  // namespace
+
+// Wavefronts per item as asked, or (waves = 0) the most (8, 4, 2, 1) with which every
+// block of the part is resident at once (one round: the dependent loads at the start of a
+// block are paid once), one wavefront per item when no width fits.
 hipError_t launch_prune(const NbDev& d, const float4* coords, int item0, int n_items,
-                        float r2_inner, int item_width, hipStream_t s) {
-    (void)item_width;
+                        float r2_inner, int waves, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    if (n_items < kPruneFewItemsPerCu * std::max(d.n_cu, 1))
-        hipLaunchKernelGGL(k_prune<8>, dim3(n_items), dim3(8 * kWave), 0, s, d.items, d.entries,
-                           coords, d.sc_info, d.sys, item0, r2_inner);
-    else
-        hipLaunchKernelGGL(k_prune<4>, dim3(n_items), dim3(4 * kWave), 0, s, d.items, d.entries,
-                           coords, d.sc_info, d.sys, item0, r2_inner);
+    const int64_t cus = std::max(d.n_cu, 1);
+#define NB_PRUNE_LAUNCH(W)                                                                  hipLaunchKernelGGL(k_prune<W>, dim3(n_items), dim3(W * kWave), 0, s, d.items,                                 d.part_items, d.entries, coords, d.sc_info, d.sys, item0, r2_inner)
+    if (waves == 0)
+        waves = (n_items <= prune_blocks_per_cu<8>() * cus)   ? 8
+                : (n_items <= prune_blocks_per_cu<4>() * cus) ? 4
+                : (n_items <= prune_blocks_per_cu<2>() * cus) ? 2
+                                                              : 1;
+    if (waves == 8) NB_PRUNE_LAUNCH(8);
+    else if (waves == 4) NB_PRUNE_LAUNCH(4);
+    else if (waves == 2) NB_PRUNE_LAUNCH(2);
+    else NB_PRUNE_LAUNCH(1);
+#undef NB_PRUNE_LAUNCH
     return hipGetLastError();
 }

@@ -47,9 +47,10 @@ __device__ inline float erfcx_poly(float r, float p_beta) {
     return u * p;
 }
 
+typedef float nb_f4 __attribute__((ext_vector_type(4)));
+
 // A 16-byte store marked non-temporal: partial sums read once, later, by another kernel
 // stream past the caches, so that they do not evict the coordinates.
-typedef float nb_f4 __attribute__((ext_vector_type(4)));
 __device__ inline void store_stream(float4* p, float x, float y, float z, float w) {
     const nb_f4 v = {x, y, z, w};
     __builtin_nontemporal_store(v, reinterpret_cast<nb_f4*>(p));

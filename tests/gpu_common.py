@@ -72,6 +72,55 @@ def energy_tolerance(E, A, strict):
     return tol
 
 
+def term_scale(c, p):
+    """Per system, [LJ, Coulomb] sums over the non-excluded pairs inside rc of the magnitudes
+    of the terms a single-precision pair energy is made of (FP64, minimum image): LJ
+    c12 r^-12 + c6 r^-6 + |c12 rc^-12 - c6 rc^-6|; Coulomb K |q_a q_b| times 1/r + k_rf r^2 +
+    c_rf (reaction field) or erfc(beta r)/r + erfc(beta rc)/rc (Ewald, the shift when set).
+    Near the cut-off a shifted pair energy is a small difference of these terms, so its
+    rounding error is a fraction of them, not of the pair energy itself.  p: oracle.params."""
+    from scipy.spatial import cKDTree
+    from scipy.special import erfc
+    offs = c["offsets"]
+    out = np.zeros((offs.size - 1, 2))
+    rc = float(np.float32(p.rc))
+    K = p.epsfac / p.eps_r
+    shift = p.modifier == 1
+    for s in range(offs.size - 1):
+        a0, a1 = int(offs[s]), int(offs[s + 1])
+        if a1 - a0 < 2:
+            continue
+        L = c["boxes"][s].astype(np.float64)
+        x = np.mod(c["x"][a0:a1].astype(np.float64), L)
+        pr = cKDTree(x, boxsize=L).query_pairs(rc, output_type="ndarray")
+        if pr.size == 0:
+            continue
+        ep, ei = c["excl_ptr"], c["excl_idx"]
+        excl = np.array([(j + a0) in ei[ep[i + a0]:ep[i + a0 + 1]] for i, j in pr], bool)
+        pr = pr[~excl]
+        d = x[pr[:, 0]] - x[pr[:, 1]]
+        d -= L * np.round(d / L)
+        r2 = np.sum(d * d, axis=1)
+        keep = r2 < rc * rc
+        pr, r2 = pr[keep], r2[keep]
+        r = np.sqrt(r2)
+        t = c["type"][a0:a1]
+        lj = c["lj"].astype(np.float64)[t[pr[:, 0]], t[pr[:, 1]]]
+        c6, c12 = lj[:, 0], lj[:, 1]
+        lj_shift = np.abs(c12 * rc ** -12 - c6 * rc ** -6) if shift else 0.0
+        out[s, 0] = np.sum(c12 * r2 ** -6 + c6 * r2 ** -3 + lj_shift)
+        qq = np.abs(c["q"][a0:a1][pr[:, 0]].astype(np.float64) * c["q"][a0:a1][pr[:, 1]])
+        if p.coulomb == 0:
+            krf = 1.0 / (2 * rc ** 3) if np.isinf(p.eps_rf) else \
+                (p.eps_rf - p.eps_r) / ((2 * p.eps_rf + p.eps_r) * rc ** 3)
+            crf = 1.0 / rc + krf * rc ** 2
+            out[s, 1] = K * np.sum(qq * (1.0 / r + krf * r2 + crf))
+        elif p.coulomb == 1:
+            cs = erfc(p.beta * rc) / rc if shift else 0.0
+            out[s, 1] = K * np.sum(qq * (erfc(p.beta * r) / r + cs))
+    return out
+
+
 def keys_of(triples, n_cl):
     t = np.asarray(triples, dtype=np.int64).reshape(-1, 3)
     return (t[:, 0] * n_cl + t[:, 1]) * 27 + t[:, 2]

@@ -140,16 +140,22 @@ def test_exec_shape_validation_without_device():
     assert st == _lib.NB_OK
     try:
         assert ctypes.sizeof(_lib.NbExecConfig) == 24
-        assert lib.nb_set_exec(h, -1, _lib.NB_EXEC_STATIC, 1) == _lib.NB_ERR_ARG
-        assert lib.nb_set_exec(h, 65, _lib.NB_EXEC_STATIC, 1) == _lib.NB_ERR_ARG
-        assert lib.nb_set_exec(h, 16, 4, 1) == _lib.NB_ERR_ARG
-        assert lib.nb_set_exec(h, 16, -1, 1) == _lib.NB_ERR_ARG
-        assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_PERSIST, 1) == _lib.NB_OK
-        assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_STATIC, 2) == _lib.NB_ERR_ARG
-        assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_QUEUE, 0) == _lib.NB_OK
+        assert lib.nb_set_exec(h, -1, _lib.NB_EXEC_STATIC, 1, 0) == _lib.NB_ERR_ARG
+        assert lib.nb_set_exec(h, 65, _lib.NB_EXEC_STATIC, 1, 0) == _lib.NB_ERR_ARG
+        assert lib.nb_set_exec(h, 16, 5, 1, 0) == _lib.NB_ERR_ARG
+        assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_BALANCED, 1, 0) == _lib.NB_OK
+        assert lib.nb_set_exec(h, 16, -1, 1, 0) == _lib.NB_ERR_ARG
+        assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_PERSIST, 1, 0) == _lib.NB_OK
+        assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_STATIC, 2, 0) == _lib.NB_ERR_ARG
+        assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_QUEUE, 0, 0) == _lib.NB_OK
         cfg = _lib.NbExecConfig()
         assert lib.nb_get_exec(h, ctypes.byref(cfg)) == _lib.NB_OK
         assert (cfg.item_width, cfg.exec_mode, cfg.prune_fused) == (16, _lib.NB_EXEC_QUEUE, 0)
+        for w, ok in [(1, True), (2, True), (4, True), (8, True), (3, False), (16, False),
+                      (-1, False)]:
+            assert (lib.nb_set_exec(h, 16, _lib.NB_EXEC_STATIC, 0, w) == _lib.NB_OK) == ok
+        assert lib.nb_get_exec(h, ctypes.byref(cfg)) == _lib.NB_OK
+        assert (cfg.exec_mode, cfg.prune_waves) == (_lib.NB_EXEC_STATIC, 8)
         n = ctypes.c_int32(0)
         best = _lib.NbExecConfig()
         assert lib.nb_autotune(h, None, None, None, 1, 3, None, 0, ctypes.byref(n),
@@ -157,5 +163,36 @@ def test_exec_shape_validation_without_device():
         assert lib.nb_step_graph(h, None, None, None, None, None, None, 0, 1) \
             == _lib.NB_ERR_STATE
         assert lib.nb_get_exec(h, None) == _lib.NB_ERR_ARG
+    finally:
+        lib.nb_destroy(h)
+
+
+def test_asymmetric_exclusions_rejected():
+    """Exclusion masks are built from each atom's own row, so the list must be symmetric:
+    atom 0 lists atom 1 but atom 1 does not list atom 0."""
+    lib = _lib.load()
+    st, h = create(good_params(), offsets=(0, 3))
+    assert st == _lib.NB_OK
+    try:
+        t = np.zeros(3, np.int32)
+        ptr = np.array([0, 1, 2, 3], np.int64)
+        idx = np.array([1, 2, 1], np.int32)          # 0->1, 1->2, 2->1: 1 lacks 0
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        assert lib.nb_set_topology(h, vp(t), vp(ptr), vp(idx)) == _lib.NB_ERR_ARG
+        assert b"symmetric" in lib.nb_last_error(h)
+    finally:
+        lib.nb_destroy(h)
+
+
+def test_get_pairs_argument_and_state_errors():
+    lib = _lib.load()
+    st, h = create(good_params(), offsets=(0, 4))
+    assert st == _lib.NB_OK
+    try:
+        n = ctypes.c_int64(0)
+        for which in (0, 1, 2):
+            assert lib.nb_get_pairs(h, which, None, 0, ctypes.byref(n)) == _lib.NB_ERR_STATE
+        for which in (-1, 3):
+            assert lib.nb_get_pairs(h, which, None, 0, ctypes.byref(n)) == _lib.NB_ERR_ARG
     finally:
         lib.nb_destroy(h)

@@ -14,6 +14,52 @@ from paper_2006_09167_amd import systems
 pytestmark = pytest.mark.gpu
 
 
+# Mean relative error of the hardware reciprocal square root (v_rsq_f32, at most 1 ulp) on
+# gfx950 against the correctly rounded value, measured over uniform r^2 in 0.05-4 nm^2:
+# -7.3e-9 to -9.2e-9 depending on the range (-0.08 to -0.11 ulp); the bound below allows
+# +-2e-9 around the middle value.
+RSQ_MEAN_REL = -7.5e-9
+RSQ_MEAN_REL_SPREAD = 2e-9
+
+
+def lj_sums(s, rc):
+    """Repulsive and dispersive sums R = sum c12 r^-12, D = sum c6 r^-6 over the pairs
+    inside rc (FP64)."""
+    from scipy.spatial import cKDTree
+    L = s.box.astype(np.float64)
+    x = np.mod(s.x.astype(np.float64), L)
+    rc = float(np.float32(rc))
+    pairs = cKDTree(x, boxsize=L).query_pairs(rc, output_type="ndarray")
+    d = x[pairs[:, 0]] - x[pairs[:, 1]]
+    d -= L * np.round(d / L)
+    r2 = np.sum(d * d, axis=1)
+    r2 = r2[r2 < rc * rc]
+    c6, c12 = s.lj[0, 0].astype(np.float64)
+    return float(np.sum(c12 * r2 ** -6)), float(np.sum(c6 * r2 ** -3))
+
+
+def table_rounding_shift(s, rc):
+    """The change of E_LJ caused by the kernel's single-precision constants 6 c6 and 12 c12
+    (relative roundings d6, d12 shared by every pair): V = c12 (r^-12 - rc^-12) - c6 (r^-6 -
+    rc^-6) is linear in c6 and c12, so the energy of the rounded table is E + d12 R - d6 D
+    with R, D the repulsive and dispersive sums over the pairs inside rc (FP64)."""
+    from scipy.spatial import cKDTree
+    L = s.box.astype(np.float64)
+    x = np.mod(s.x.astype(np.float64), L)
+    rc = float(np.float32(rc))
+    pairs = cKDTree(x, boxsize=L).query_pairs(rc, output_type="ndarray")
+    d = x[pairs[:, 0]] - x[pairs[:, 1]]
+    d -= L * np.round(d / L)
+    r2 = np.sum(d * d, axis=1)
+    r2 = r2[r2 < rc * rc]
+    c6, c12 = s.lj[0, 0].astype(np.float64)
+    d12 = float(np.float32(12.0 * np.float32(c12))) / (12.0 * c12) - 1.0
+    d6 = float(np.float32(6.0 * np.float32(c6))) / (6.0 * c6) - 1.0
+    R = float(np.sum(c12 * (r2 ** -6 - rc ** -12)))
+    D = float(np.sum(c6 * (r2 ** -3 - rc ** -6)))
+    return d12 * R - d6 * D
+
+
 @pytest.mark.parametrize("n_half", [50, 400])
 def test_argon_lj_only_parity(n_half):
     s = systems.argon_box(k=14, seed=11)          # 2744 atoms, 4.7 nm box
@@ -38,16 +84,28 @@ def test_argon_lj_only_parity(n_half):
     f, e, v = f.cpu().numpy(), e.cpu().numpy(), v.cpu().numpy()
     assert rel_rms(f, F) <= 1e-5, rel_rms(f, F)
     # At this density the lattice sits near the LJ zero crossing: E_LJ is a near-cancellation
-    # of much larger pair energies (sum |e_pair| / |E_LJ| is 23 at the shorter cut-off and
-    # 84 at the longer).  Each FP32 pair energy carries the error of r^-12 from the
-    # hardware reciprocal square root (up to 1 ulp, times 12: a few 1e-7 relative), so the
-    # bound here is max(1e-6 |E|, 1e-7 sum |e_pair|).
-    tol = max(1e-6 * abs(E[0, 0]), 1e-7 * A[0, 0])
-    assert abs(e[0, 0] - E[0, 0]) <= tol, (e[0, 0], E[0, 0], A[0, 0])
+    # of much larger terms (sum |e_pair| / |E_LJ| is 23 at the shorter cut-off and 84 at the
+    # longer).  Two errors are shared by every pair and so do not average out:
+    # * the kernel takes 6 c6 and 12 c12 rounded to single precision, one relative error
+    #   (here 5.6e-8 and 3.9e-8) that shifts the repulsive and the dispersive sums by that
+    #   fraction (about -8e-4 here, 2.3e-6 of E_LJ at the longer cut-off);
+    # * the hardware 1/sqrt is biased low on average (RSQ_MEAN_REL): a relative error eps of
+    #   1/r moves r^-12 by 12 eps and r^-6 by 6 eps, so E_LJ by eps (12 R - 6 D), about
+    #   -2e-3 here.
+    # The rest of each pair's rounding is unbiased and small: a CPU emulation of the kernel's
+    # single-precision sequence with a correctly rounded 1/sqrt(r^2) leaves 3e-5 and 6e-5
+    # beyond the first shift.  The bar: the oracle's E_LJ plus both shifts, within 1e-6
+    # relative plus the spread of the mean bias.
+    R, D = lj_sums(s, rc)
+    expect = E[0, 0] + table_rounding_shift(s, rc) + RSQ_MEAN_REL * (12 * R - 6 * D)
+    tol = 1e-6 * abs(E[0, 0]) + RSQ_MEAN_REL_SPREAD * (12 * R + 6 * D)
+    assert abs(e[0, 0] - expect) <= tol, (e[0, 0], expect, tol, E[0, 0], A[0, 0])
     assert e[0, 1] == 0.0 and E[0, 1] == 0.0
     assert rel_rms(v, V) <= 1e-5
     st = ctx.stats()
-    assert st["effective_pairs"] > 0.8 * n_half * s.n      # about n_half pairs per atom
+    # about n_half pairs per atom: on this jittered cubic lattice the count is 0.907 n_half N
+    # at rc = 2.9 lattice spacings (discrete neighbour shells) and 0.98 n_half N at 5.8
+    assert st["effective_pairs"] > 0.9 * n_half * s.n
 
 
 def test_argon_lj_only_backward():

@@ -1,6 +1,5 @@
 """Execution shapes of the pair kernel (static, XCD-contiguous, persistent queue,
-persistent balanced schedule), item
-widths, the autotuner, the graph-replayed step and an ensemble of uneven replicas in one
+persistent balanced schedule, equal-cost runs per wavefront), item widths, the autotuner, the graph-replayed step and an ensemble of uneven replicas in one
 context, through the C ABI on an MI355X, against the FP64 oracle."""
 import numpy as np
 import pytest
@@ -45,7 +44,8 @@ def test_modes_bitwise_equal_and_queue_relaunches(sys3k, width):
     ref = None
     for mode in ("static", "xcd", "queue", "queue", "queue", "persist", "persist", "static"):
         ctx.set_exec(width, mode)
-        assert ctx.get_exec() == {"item_width": width, "mode": mode, "prune_fused": True}
+        assert ctx.get_exec() == {"item_width": width, "mode": mode, "prune_fused": True,
+                                  "prune_waves": 0}
         out = ctx.forces(x, q, lj, energy=True, virial=True)
         torch.cuda.synchronize()
         if ref is None:
@@ -77,7 +77,7 @@ def test_fused_step_in_persistent_modes_matches_static(sys3k, mode):
     assert np.array_equal(ctx_a.get_pairs("inner"), ctx_b.get_pairs("inner"))
 
 
-@pytest.mark.parametrize("mode", ["xcd", "queue", "persist"])
+@pytest.mark.parametrize("mode", ["xcd", "queue", "persist", "balanced"])
 def test_separate_prune_step_equals_fused(sys3k, mode):
     """nb_step with the prune as separate kernels: the same inner lists and bitwise the
     same outputs as with the prune fused into the pair kernel."""
@@ -98,6 +98,37 @@ def test_separate_prune_step_equals_fused(sys3k, mode):
         torch.cuda.synchronize()
         assert torch.equal(fa, fb) and torch.equal(ea, eb) and torch.equal(va, vb), t
     assert np.array_equal(ctx_a.get_pairs("inner"), ctx_b.get_pairs("inner"))
+
+
+@pytest.mark.parametrize("width", [8, 40, 64])
+def test_balanced_mode_rolling_cycle(sys3k, width):
+    """The balanced mode (equal-cost runs of items per wavefront) over a rolling cycle with
+    the prune fused: the same inner lists as the static mode, outputs equal to FP32
+    summation-order rounding, and within the oracle bars."""
+    c = concat(sys3k)
+    kw = dict(nstlist=20, nstprune=4, **EWALD)
+    ctx_a, _ = built(c, **kw)
+    ctx_b, _ = built(c, **kw)
+    ctx_b.set_exec(width, "balanced")
+    assert ctx_b.get_exec() == {"item_width": width, "mode": "balanced", "prune_fused": True,
+                                "prune_waves": 0}
+    st = ctx_b.stats()
+    assert st["n_work_items"] >= st["n_superclusters"]
+    q, lj = dev(c["q"]), dev(c["lj"])
+    rng = np.random.default_rng(13)
+    x = c["x"].copy()
+    for t in range(0, 7):
+        if t > 0:
+            x = (x + rng.normal(0, 0.002, x.shape)).astype(np.float32)
+        xt = dev(x)
+        fa, ea, va = ctx_a.step(xt, q, lj, t, energy=True, virial=True)
+        fb, eb, vb = ctx_b.step(xt, q, lj, t, energy=True, virial=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(ctx_a.get_pairs("inner"), ctx_b.get_pairs("inner")), t
+        assert rel_rms(fb.cpu().numpy(), fa.cpu().numpy()) <= 1e-6, t
+        assert torch.allclose(eb, ea, rtol=1e-9, atol=0), t
+        assert torch.allclose(vb, va, rtol=1e-6, atol=1e-6 * va.abs().max().item()), t
+    check_oracle(c, x, fb, eb, "ewald", 1.0, 3.12)
 
 
 def test_item_width_changes_only_rounding(sys3k):
@@ -124,7 +155,7 @@ def test_autotune_keeps_fastest_and_stays_exact(sys3k):
     ctx, x = built(c, nstlist=10, nstprune=2, **EWALD)
     q, lj = dev(c["q"]), dev(c["lj"])
     best, trials = ctx.autotune(x, q, lj, energy=True, repeats=3)
-    assert len(trials) == 34
+    assert len(trials) == 42
     n_shape = len(trials) - 2
     assert all(t["us_per_call"] > 0 for t in trials)
     shape = min(trials[:n_shape], key=lambda t: t["us_per_call"])
@@ -132,7 +163,7 @@ def test_autotune_keeps_fastest_and_stays_exact(sys3k):
     step = min(trials[n_shape:], key=lambda t: t["us_per_call"])
     assert best["prune_fused"] == step["prune_fused"]
     assert ctx.get_exec() == {"item_width": best["item_width"], "mode": best["mode"],
-                              "prune_fused": best["prune_fused"]}
+                              "prune_fused": best["prune_fused"], "prune_waves": 0}
     f, e, _ = ctx.forces(x, q, lj)
     torch.cuda.synchronize()
     check_oracle(c, c["x"], f, e, "ewald", 1.0, 3.12)
@@ -143,8 +174,9 @@ def test_autotune_keeps_fastest_and_stays_exact(sys3k):
 
 
 @pytest.mark.parametrize("mode,fused", [("static", True), ("queue", True), ("persist", True),
-                                        ("static", False), ("queue", False),
-                                        ("persist", False)])
+                                        ("balanced", True), ("static", False),
+                                        ("queue", False), ("persist", False),
+                                        ("balanced", False)])
 def test_graph_step_replays_match_eager(sys3k, mode, fused):
     """nb_step_graph over two list lifetimes with positions updated in place: every replay
     (with eager work and synchronisation in between) equals the eager nb_step bitwise,
@@ -194,12 +226,13 @@ def test_ensemble_uneven_replicas_all_modes():
     E, F, _, A = oracle_forces_multi(c, c["x"], oracle_params("rf", e_cfg["rc"]))
     tol = energy_tolerance(E, A, True)
     ref = None
-    for mode in ("static", "xcd", "queue", "persist"):
+    for mode in ("static", "xcd", "queue", "persist", "balanced"):
         ctx.set_exec(0, mode)
         f, e, _ = ctx.forces(x, q, lj)
         torch.cuda.synchronize()
-        if ref is None:
-            ref = (f.clone(), e.clone())
+        if ref is None or mode == "balanced":      # balanced: items of its own
+            if ref is None:
+                ref = (f.clone(), e.clone())
             assert rel_rms(f.cpu().numpy(), F) <= 1e-5
             en = e.cpu().numpy()
             assert np.all(np.abs(en - E) <= tol), np.max(np.abs(en - E) / np.abs(E))

@@ -3,9 +3,13 @@ benchmark times (autotuned execution shape, fused rolling prune):
 
 * the 96,000-atom Ewald box: every force, both energies and the virial against the FP64
   oracle over all N(N-1)/2 minimum-image pairs, at the build and at rolling steps;
-* the 1,500,000-atom Ewald box: forces on a seeded sample of atoms against the oracle's
-  per-atom sums over all partners, and the list invariants (each cluster pair once,
-  inner list inside the outer list) over the whole box."""
+* the 96,000-atom Ewald box backward pass (the one the forward + backward metric times:
+  adjoint of a force-matching loss, table gradient on) against the oracle's backward
+  pass, in the benchmark's execution shape;
+* the 1,500,000-atom Ewald box: the grid slot order against the oracle's grid, every
+  force, both energies and the virial against the FP64 oracle at the build and at rolling
+  steps around a rebuild, and the list invariants (each cluster pair once, inner list
+  inside the outer list) over the whole box."""
 import numpy as np
 import pytest
 import torch
@@ -55,8 +59,52 @@ def test_water96k_full_parity_at_build_and_rolling_steps():
         assert rel_rms(v.cpu().numpy(), V) <= 1e-5
 
 
+def symmetrize(gl):
+    """Split the derivative w.r.t. each off-diagonal table value evenly over its entries."""
+    return 0.5 * (gl + np.transpose(gl, (1, 0, 2)))
+
+
 @pytest.mark.timeout(420)
-def test_water1500k_sampled_forces_and_list_invariants():
+def test_water96k_backward_in_benchmark_shape():
+    s = systems.config_system("water96k_ewald")
+    c = concat(s)
+    ctx, cfg = ctx_for("water96k_ewald", c)
+    x = dev(c["x"])
+    ctx.grid_build(x, c["boxes"])
+    ctx.pairlist_build()
+    ctx.set_exec(40, "persist", False)
+    q, lj = dev(c["q"]), dev(c["lj"])
+    p = oracle_params("ewald", cfg["rc"], cfg["beta"])
+    rng = np.random.default_rng(31)
+    xs = c["x"].copy()
+    for t in range(0, 3):
+        if t > 0:
+            xs = (xs + rng.normal(0.0, cfg["sigma_step"], xs.shape)).astype(np.float32)
+        xt = dev(xs)
+        f0, _, _ = ctx.step(xt, q, lj, t, energy=False)
+        f_ref, _, _ = ctx.forces(xt, q * 1.05, lj * 1.05, energy=False)
+        G = (2.0 * (f0 - f_ref)).contiguous()
+        gE = None if t == 0 else np.array([[0.7, -0.4]], np.float64)
+        gx, gq, gl = ctx.backward(xt, q, lj, G, None if gE is None else dev(gE, torch.float64))
+        torch.cuda.synchronize()
+        if t == 1:
+            continue
+        ox, oq, ol = oracle.backward(xs, s.q, s.type, s.lj, s.excl_ptr, s.excl_idx, s.box, p,
+                                     G.cpu().numpy().astype(np.float64),
+                                     (0.0, 0.0) if gE is None else gE[0])
+        errs = [rel_rms(gx.cpu().numpy(), ox), rel_rms(gq.cpu().numpy(), oq),
+                rel_rms(gl.cpu().numpy(), symmetrize(ol))]
+        print("96k backward step %d: grad x / q / lj rel RMS %s" % (t, errs), flush=True)
+        assert max(errs) <= 1e-4, errs
+
+
+@pytest.mark.timeout(840)
+def test_water1500k_every_output_at_build_and_rolling_steps():
+    """Every force, both energies and the virial of the 1.5M-atom box against the FP64
+    oracle (summed through its cell grid, which equals the all-pairs sum to rounding), in
+    the autotuned shape, at the build (step 0), the last step of the first list (79), the
+    rebuild (80) and the first rolling step after it (81); Gaussian steps of 0.002 nm
+    drawn on the GPU.  Also the grid slot order and the list invariants at the build."""
     s = systems.config_system("water1500k_ewald")
     print("1.5M box generated", flush=True)
     c = concat(s)
@@ -65,17 +113,11 @@ def test_water1500k_sampled_forces_and_list_invariants():
     ctx.grid_build(x, c["boxes"])
     ctx.pairlist_build()
     q, lj = dev(c["q"]), dev(c["lj"])
-    f, e, _ = ctx.step(x, q, lj, 0, energy=True)
-    torch.cuda.synchronize()
-    print("1.5M box: list built, forces done", flush=True)
-    rng = np.random.default_rng(23)
-    sel = np.sort(rng.choice(s.n, size=512, replace=False))
-    F = oracle.forces_on(sel, s.x, s.q, s.type, s.lj, s.excl_ptr, s.excl_idx, s.box,
-                         oracle_params("ewald", cfg["rc"], cfg["beta"]))
-    err = rel_rms(f.cpu().numpy()[sel], F)
-    print("1.5M box: sampled force rel RMS %.2e over %d atoms" % (err, sel.size))
-    assert err <= 1e-5
-    assert np.all(np.isfinite(e.cpu().numpy()))
+    best, _ = ctx.autotune(x, q, lj, energy=True, repeats=2)
+    print("1.5M box: autotuned", best, flush=True)
+    g = oracle.grid_spec.build_grid(c["x"], c["boxes"], c["offsets"])
+    assert np.array_equal(ctx.get_grid(), g["slot_atom"])
+    del g
     st = ctx.stats()
     n_cl = st["n_clusters"]
     ko = keys_of(ctx.get_pairs("outer"), n_cl)
@@ -83,3 +125,30 @@ def test_water1500k_sampled_forces_and_list_invariants():
     assert np.unique(ko).size == ko.size
     assert np.all(np.isin(ki, ko))
     assert st["outer_pairs"] == ko.size and st["inner_pairs"] == ki.size
+    del ko, ki
+    p = oracle_params("ewald", cfg["rc"], cfg["beta"])
+    gen = torch.Generator(device="cuda").manual_seed(cfg["seed"])
+    nst = cfg["nstlist"]
+    for t in range(0, nst + 2):
+        if t > 0:
+            x = x + cfg["sigma_step"] * torch.randn(x.shape, generator=gen, device="cuda")
+        k = t % nst
+        if k == 0 and t > 0:
+            ctx.grid_build(x, c["boxes"])
+            ctx.pairlist_build()
+        f, e, v = ctx.step(x, q, lj, k, energy=True, virial=True)
+        if t not in (0, nst - 1, nst, nst + 1):
+            continue
+        torch.cuda.synchronize()
+        xs = x.cpu().numpy()
+        E, F, V, A = oracle.forces_cells(xs, s.q, s.type, s.lj, s.excl_ptr, s.excl_idx, s.box,
+                                         p, energy_abs=True)
+        err_f = rel_rms(f.cpu().numpy(), F)
+        en = e.cpu().numpy()[0]
+        err_e = np.abs(en - E) / np.abs(E)
+        err_v = rel_rms(v.cpu().numpy()[0], V)
+        print("1.5M step %d: force rel RMS %.2e, E_LJ rel %.2e, E_C rel %.2e, virial rel RMS "
+              "%.2e" % (t, err_f, err_e[0], err_e[1], err_v), flush=True)
+        assert err_f <= 1e-5
+        assert np.all(err_e <= 1e-6)
+        assert err_v <= 1e-5

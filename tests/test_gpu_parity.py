@@ -11,7 +11,7 @@ import torch
 import oracle
 from conftest import small_random_system
 from gpu_common import (concat, dev, energy_tolerance, keys_of, make_ctx, oracle_forces_multi,
-                        oracle_pair_keys, oracle_params, rel_rms)
+                        oracle_pair_keys, oracle_params, rel_rms, term_scale)
 from paper_2006_09167_amd import systems
 
 pytestmark = pytest.mark.gpu
@@ -51,13 +51,16 @@ def check_lists(ctx, c, g, rlist, rinner):
 
 
 def check_forces(ctx, c, x, coul, rc, beta=0.0, modifier="potshift", virial=True, eps_rf=math.inf,
-                 strict=True):
+                 strict=True, term_ulps=None):
     q = dev(c["q"])
     lj = dev(c["lj"])
     f, e, v = ctx.forces(x, q, lj, energy=True, virial=virial)
     torch.cuda.synchronize()
     E, F, V, A = oracle_forces_multi(c, c["x"], oracle_params(coul, rc, beta, modifier, eps_rf))
     tol = energy_tolerance(E, A, strict)
+    if term_ulps is not None:          # (LJ, Coulomb) worst-case units of 2^-24 per term
+        p = oracle_params(coul, rc, beta, modifier, eps_rf)
+        tol = np.maximum(tol, np.asarray(term_ulps) * 2.0 ** -24 * term_scale(c, p))
     f = f.cpu().numpy()
     e = e.cpu().numpy()
     assert np.all(np.isfinite(f))
@@ -123,13 +126,16 @@ def test_ensemble_with_empty_and_tiny_systems():
     check_forces(ctx, c, x, "rf", 1.0, strict=False)
 
 
-def test_rolling_prune_matches_oracle(sys3k):
+@pytest.mark.parametrize("prune_waves", [0, 1, 2, 4, 8])
+def test_rolling_prune_matches_oracle(sys3k, prune_waves):
     """Dual list: inner masks of part (t mod nstprune) are re-derived from the outer list
-    with the step-t coordinates; forces then follow the current inner list."""
+    with the step-t coordinates, by the prune kernel with each number of wavefronts per
+    item; forces then follow the current inner list."""
     c = concat(sys3k)
     nst, npr = 20, 4
     ctx, x = build(c, coulomb="ewald", rc=1.0, rinner=1.04, rlist=1.1, beta=3.12, nstlist=nst,
                    nstprune=npr)
+    ctx.set_exec(0, "static", True, prune_waves)
     g = oracle.grid_spec.build_grid(c["x"], c["boxes"], c["offsets"])
     n_cl = g["slot_atom"].size // 8
     outer = keys_of(ctx.get_pairs("outer"), n_cl)

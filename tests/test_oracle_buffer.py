@@ -350,3 +350,96 @@ def test_missed_energy_of_simulated_free_flight_on_water(oracle_mod, sys3k):
     for name in ("1x1", "8x8"):
         assert 0.7 <= direct[name] / est[name] <= 1.1, (name, direct[name], est[name])
     assert est["8x8"] < 0.1 * est["1x1"]                # the implicit buffer matters
+
+
+# ---- constrained atoms rotating about their partner -------------------------------------
+ROTOR_CLASSES = dict(WATER_CLASSES, rot_len=[0.0, 0.1], rot_mass=[15.9994, 1.008])
+
+
+def simulated_rotor_var(rng, n, kT, t, m, d):
+    """Per-axis variance of d (u(t) - u(0)) for a free rotor, by simulation of the geometry:
+    u(0) uniform on the sphere, angular velocity w perpendicular to u(0) with Gaussian
+    components of variance kT / (m d^2) (equipartition of m d^2 |w|^2 / 2 over the two
+    perpendicular axes), u turned about w by |w| t (Rodrigues' rotation)."""
+    u = rng.normal(size=(n, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    g = rng.normal(0.0, math.sqrt(kT / (m * d * d)), (n, 3))
+    w = g - np.sum(g * u, axis=1, keepdims=True) * u        # the part perpendicular to u
+    om = np.linalg.norm(w, axis=1, keepdims=True)
+    k = w / om
+    th = om * t
+    # Rodrigues with k perpendicular to u: u cos th + (k x u) sin th
+    ut = u * np.cos(th) + np.cross(k, u) * np.sin(th)
+    disp = d * (ut - u)
+    return disp.var(axis=0).mean(), disp
+
+
+@pytest.mark.parametrize("t", [0.005, 0.04, 0.078, 0.2, 1.0])
+def test_rotor_variance_against_simulated_rotation(oracle_mod, t):
+    """The closed form (2/3) d^2 sqrt(2) s D(s / sqrt(2)) against the variance of simulated
+    free-rotor displacements of a hydrogen 0.1 nm from its partner, from the free-flight
+    regime (t = 5 fs) to the saturated one (1 ps), within 4 standard errors."""
+    rng = np.random.default_rng(5)
+    kT = oracle_mod.buffer.KB * 300.0
+    n = 400000
+    sim, disp = simulated_rotor_var(rng, n, kT, t, 1.008, 0.1)
+    got = oracle_mod.buffer.displacement_var(kT, t, 1e30, 0.1, 1.008)   # rotation only
+    se = disp.reshape(-1).astype(np.float64).__pow__(2).std() / math.sqrt(3 * n)
+    assert abs(got - sim) <= 4 * se + 1e-12, (t, got, sim, se)
+
+
+def test_rotor_variance_limits(oracle_mod):
+    """Small t: free flight of the atom's own mass along the two directions perpendicular to
+    the bond, (2/3) k_B T t^2 / m; large t: the fixed (2/3) d^2 of a uniformly oriented bond
+    vector; no rotation: k_B T t^2 / m of the carrying mass alone."""
+    kT = oracle_mod.buffer.KB * 300.0
+    m, d = 1.008, 0.1
+    for t in (1e-5, 1e-4):
+        v = oracle_mod.buffer.displacement_var(kT, t, 1e30, d, m)
+        assert abs(v - (2 / 3) * kT * t * t / m) <= 1e-6 * v
+    v = oracle_mod.buffer.displacement_var(kT, 1e3, 1e30, d, m)
+    assert abs(v - (2 / 3) * d * d) <= 1e-4 * v
+    v = oracle_mod.buffer.displacement_var(kT, 0.05, 18.015)
+    assert abs(v - kT * 0.05 ** 2 / 18.015) <= 1e-15 * v
+    # the translation of the carrying mass adds
+    both = oracle_mod.buffer.displacement_var(kT, 0.05, 18.015, d, m)
+    assert abs(both - (kT * 0.05 ** 2 / 18.015
+                       + oracle_mod.buffer.displacement_var(kT, 0.05, 1e300, d, m))) <= 1e-12
+
+
+def test_rotor_drift_between_rigid_and_free(oracle_mod, sys3k):
+    """The rotor reading lies between a rigid molecule (hydrogen carried by the molecular
+    mass alone) and free atoms (hydrogen moving freely in all three directions with its own
+    mass) for a list used for 40 steps of 2 fs."""
+    p = oracle_mod.params("ewald", rc=0.9, beta=3.47)
+    V = float(np.prod(sys3k.box))
+    free = dict(WATER_CLASSES, mass=[15.9994, 1.008])
+    args = (p, None, sys3k.lj, V, 300.0, 0.002, 40, 0.95)
+    d_rigid, d_rot, d_free = (oracle_mod.buffer.drift(p, cl, *args[2:])
+                              for cl in (WATER_CLASSES, ROTOR_CLASSES, free))
+    assert d_rigid < d_rot < d_free, (d_rigid, d_rot, d_free)
+
+
+def test_library_rotor_drift_matches_oracle(oracle_mod, sys3k):
+    """nb_buffer_drift with rotating classes (its own Dawson integral) against the oracle
+    (scipy's dawsn), particle list, several list ages."""
+    from paper_2006_09167_amd import api
+    V = float(np.prod(sys3k.box))
+    po = oracle_mod.params("ewald", rc=0.9, beta=3.47)
+    pl = lib_params("ewald", 0.9, 3.47)
+    for steps, b in ((2, 0.0), (40, 0.0), (40, 0.05), (100, 0.1), (400, 0.2)):
+        rl = float(np.float32(0.9)) + b
+        ref = oracle_mod.buffer.drift(po, ROTOR_CLASSES, sys3k.lj, V, 300.0, 0.002, steps, rl)
+        got = api.buffer_drift(pl, ROTOR_CLASSES, sys3k.lj, V, 300.0, 0.002, steps, rl)
+        assert abs(got - ref) <= 1e-6 * ref, (steps, b, got, ref)
+
+
+def test_library_rotor_argument_errors(sys3k):
+    from paper_2006_09167_amd import api
+    V = float(np.prod(sys3k.box))
+    pl = lib_params("ewald", 0.9, 3.47)
+    for bad in (dict(ROTOR_CLASSES, rot_len=[0.0, -0.1]),
+                dict(ROTOR_CLASSES, rot_mass=[15.9994, 0.0]),
+                dict(ROTOR_CLASSES, rot_len=[0.0, float("nan")])):
+        with pytest.raises(Exception):
+            api.buffer_drift(pl, bad, sys3k.lj, V, 300.0, 0.002, 40, 0.95)
