@@ -319,6 +319,26 @@ __global__ void k_excl_slots(NbDev d) {
     }
 }
 
+// Per cluster, the range of clusters that hold the excluded partners of its atoms
+// ((2^31 - 1, -1) when none): the list's exclusion pass looks at the partners of an entry's
+// i-cluster only when the j-cluster falls in that range.
+__global__ void k_excl_cluster_range(NbDev d) {
+    const int ci = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ci >= d.flags[kFlagNumSc] * kClustersPerSc) return;
+    int lo = 0x7fffffff, hi = -1;
+    for (int ii = 0; ii < kClusterSize; ++ii) {
+        const int slot = kClusterSize * ci + ii;
+        for (int k = 0; k < d.max_excl; ++k) {
+            const int ps = d.excl_slot[(size_t)slot * d.max_excl + k];
+            if (ps >= 0) {
+                lo = min(lo, ps / kClusterSize);
+                hi = max(hi, ps / kClusterSize);
+            }
+        }
+    }
+    d.cl_xrange[ci] = make_int2(lo, hi);
+}
+
 inline int blocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
@@ -353,6 +373,9 @@ hipError_t launch_grid_build(const NbDev& d, const float* x, hipStream_t s) {
         hipLaunchKernelGGL(k_supercell, dim3(d.n_sc_max), dim3(kWave), 0, s, d);
         hipLaunchKernelGGL(k_excl_slots, dim3(blocks((int64_t)d.n_sc_max * kScAtoms, 256)),
                            dim3(256), 0, s, d);
+        hipLaunchKernelGGL(k_excl_cluster_range,
+                           dim3(blocks((int64_t)d.n_sc_max * kClustersPerSc, 256)), dim3(256), 0,
+                           s, d);
     }
     return hipGetLastError();
 }

@@ -290,7 +290,7 @@ void nb_destroy(nb_ctx* c) {
                     d.part_start, d.excl_rows, d.jseg_count, d.jseg_start, d.jseg_fill,
                     d.jseg_entries, d.totals, d.flags, d.jpart, d.ipart, d.epart, d.glj_part,
                     d.dstat, d.item_cost, d.item_order, d.queue, d.xcf, d.xce,
-                    d.part_items, d.wave_e, d.wave_item};
+                    d.part_items, d.wave_e, d.wave_item, d.cl_xrange};
     drop_graphs(c);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     for (void* q : ptrs)
@@ -453,6 +453,7 @@ nb_status nb_grid_build(nb_ctx* c, const float* x, const float* box) {
         NB_HIP(c, dev_alloc(d.jseg_start, cl + 9));
         NB_HIP(c, dev_alloc(d.jseg_fill, cl + 8));
         NB_HIP(c, dev_alloc(d.xcf, slots));
+        NB_HIP(c, dev_alloc(d.cl_xrange, cl));
         NB_HIP(c, dev_alloc(d.xce, 7 * ns));
         c->a_sc = ns;
         c->a_excl_nnz = 0;
@@ -602,31 +603,33 @@ nb_status nb_pairlist_build(nb_ctx* c) {
     NB_HIP(c, hipSetDevice(c->device));
     NbDev& d = c->d;
     int32_t flags[kFlagCount];
-    nb_status st = to_host(c, flags, d.flags, kFlagCount);
-    if (st != NB_OK) return st;
-    if (flags[kFlagNonFinite]) {
-        c->has_grid = false;
-        return fail(c, NB_ERR_NONFINITE, "non-finite or out-of-range coordinates at grid build");
-    }
-    const int n_sc = flags[kFlagNumSc];
-    c->n_sc = n_sc;
-    c->n_cl = n_sc * kClustersPerSc;
-    c->n_slots = n_sc * kScAtoms;
+    int32_t totals[8];
+    nb_status st = NB_OK;
     const float r2o = radius_sq(c->p.rlist), r2i = radius_sq(c->p.rinner);
-    // Search with the current per-super-cluster capacity; grow and repeat on overflow.
+    // Search with the current per-super-cluster capacity over the bound on the super-cluster
+    // count (the kernels read the grid build's own count), scan the entry counts, then one
+    // round trip for the flags and the entry total; grow and repeat on overflow.
+    const int n_sc_max = d.n_sc_max;
     for (int attempt = 0;; ++attempt) {
-        const size_t need = (size_t)std::max(n_sc, 1) * c->cap;
+        const size_t need = (size_t)std::max(n_sc_max, 1) * c->cap * kSearchWaves;
         if (need > c->a_scratch) {
             NB_HIP(c, dev_alloc(d.scratch, need));
             c->a_scratch = need;
         }
-        NB_HIP(c, launch_fill(d.flags + kFlagScOverflow, kFlagCount - kFlagScOverflow, 0,
-                              c->stream));
-        // keep the super-cluster count (it lives in the same array)
-        NB_HIP(c, launch_fill(d.flags + kFlagNumSc, 1, n_sc, c->stream));
-        NB_HIP(c, launch_search(d, n_sc, c->cap, r2o, r2i, c->p.rlist, c->stream));
-        st = to_host(c, flags, d.flags, kFlagCount);
+        // clear the search's outputs; the grid build's count and non-finite flag stay
+        NB_HIP(c, launch_fill(d.flags + kFlagScOverflow, 2, 0, c->stream));
+        NB_HIP(c, launch_fill(d.flags + kFlagNumRows, kFlagCount - kFlagNumRows, 0, c->stream));
+        NB_HIP(c, launch_search(d, n_sc_max, c->cap, r2o, r2i, c->p.rlist, c->stream));
+        NB_HIP(c, launch_scan_entries(d, -1, c->stream));
+        NB_HIP(c, hipMemcpyAsync(totals, d.totals, sizeof(totals), hipMemcpyDeviceToHost,
+                                 c->stream));
+        st = to_host(c, flags, d.flags, kFlagCount);   // synchronises: totals too
         if (st != NB_OK) return st;
+        if (flags[kFlagNonFinite]) {
+            c->has_grid = false;
+            return fail(c, NB_ERR_NONFINITE,
+                        "non-finite or out-of-range coordinates at grid build");
+        }
         if (!flags[kFlagScOverflow]) break;
         if (c->p.list_capacity_hint > 0)
             return fail(c, NB_ERR_CAPACITY, "a super-cluster has " +
@@ -636,11 +639,11 @@ nb_status nb_pairlist_build(nb_ctx* c) {
         c->stats.regrows++;
         if (attempt > 4) return fail(c, NB_ERR_CAPACITY, "list capacity did not converge");
     }
+    const int n_sc = flags[kFlagNumSc];
+    c->n_sc = n_sc;
+    c->n_cl = n_sc * kClustersPerSc;
+    c->n_slots = n_sc * kScAtoms;
     c->stats.bb_pairs = (uint32_t)flags[kFlagBbPairs];
-    NB_HIP(c, launch_scan_entries(d, n_sc, c->stream));
-    int32_t totals[8];
-    st = to_host(c, totals, d.totals, 8);
-    if (st != NB_OK) return st;
     const int64_t E = totals[0];
     c->n_entries = E;
     if ((size_t)E > c->a_entries || !d.entries) {

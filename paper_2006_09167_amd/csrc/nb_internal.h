@@ -16,6 +16,7 @@ constexpr int kClusterSize = 8;                 // atoms per cluster (i and j si
 constexpr int kClustersPerSc = 8;               // clusters per super-cluster
 constexpr int kScAtoms = 64;                    // atom slots per super-cluster
 constexpr int kWave = 64;                       // wavefront width on gfx950
+constexpr int kSearchWaves = 4;                 // wavefronts per super-cluster in the search
 constexpr int kMaxTypes = 32;                   // LJ types supported by the kernels
 constexpr int kMaxExcl = 32;                    // exclusion partners per atom
 constexpr int kShiftZero = 13;                  // shift code of s = (0,0,0)
@@ -217,6 +218,7 @@ struct NbDev {
     int32_t* type_slot = nullptr;      // [64 n_sc_max] 16 type: the byte offset of the type's
                                        // entry in a row of a float4 table over types
     int32_t* excl_slot = nullptr;      // [64 n_sc_max][max_excl]
+    int2* cl_xrange = nullptr;         // [8 n_sc_max] clusters holding excluded partners: [lo, hi]
     float4* cl_bb = nullptr;           // [8 n_sc_max][2] lo (w = atom count), hi
     float4* sc_bb = nullptr;           // [n_sc_max][2]
     float4* xw = nullptr;              // [64 n_sc_max] build coordinates by slot

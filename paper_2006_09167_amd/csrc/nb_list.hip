@@ -80,24 +80,35 @@ __device__ inline uint64_t pair_valid_mask(int ni, int nj, bool diag) {
     return imask & jmask & (diag ? tri : ~0ull);
 }
 
-// One wavefront per i-super-cluster.  kRecord: only list the cluster pairs that pass the
-// bounding-box tests, as records (super-cluster, j-cluster, shift code, 8-bit i-mask) in
-// d.bb_rec (counted in flags[kFlagBbRecords]), and leave the list and its counters alone.
+// One block of kSearchWaves wavefronts per i-super-cluster.  The candidate j-super-clusters
+// are visited column by column in batches of 64 (super-cluster, z shift) candidates; batch
+// u of that sequence goes to wavefront u mod kSearchWaves, which writes its entries in its
+// own cap-long region of the super-cluster's scratch (kSearchWaves cap entries); at the end
+// the regions are moved together in wavefront order, so the entry order is fixed by the
+// grid alone.  kRecord: only list the cluster pairs that pass the bounding-box tests, as
+// records (super-cluster, j-cluster, shift code, 8-bit i-mask) in d.bb_rec (counted in
+// flags[kFlagBbRecords]), and leave the list and its counters alone.
 template <bool kRecord>
-__global__ __launch_bounds__(kWave) void k_search(NbDev d, int cap, float r2_outer,
-                                                   float r2_inner, float rlist, int rec_cap) {
+__global__ __launch_bounds__(kSearchWaves * kWave) void k_search(NbDev d, int cap, float r2_outer,
+                                                                  float r2_inner, float rlist,
+                                                                  int rec_cap) {
     const int sc = blockIdx.x;
-    const int lane = threadIdx.x;
+    // the grid may be launched for the bound on the super-cluster count: the grid build's
+    // own count decides, and a grid built from non-finite coordinates is not searched
+    if (sc >= d.flags[kFlagNumSc] || d.flags[kFlagNonFinite]) return;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x & (kWave - 1);
     const int ii = lane & 7, jj = lane >> 3;
     __shared__ float4 s_ilo[kClustersPerSc], s_ihi[kClustersPerSc];
     __shared__ float4 s_ix[kScAtoms];
+    __shared__ int s_n[kSearchWaves];
     const NbScInfo info = d.sc_info[sc];
     const NbSys S = d.sys[info.sys];
-    if (lane < kClustersPerSc) {
-        s_ilo[lane] = d.cl_bb[2 * (kClustersPerSc * sc + lane)];
-        s_ihi[lane] = d.cl_bb[2 * (kClustersPerSc * sc + lane) + 1];
+    if (threadIdx.x < kClustersPerSc) {
+        s_ilo[threadIdx.x] = d.cl_bb[2 * (kClustersPerSc * sc + threadIdx.x)];
+        s_ihi[threadIdx.x] = d.cl_bb[2 * (kClustersPerSc * sc + threadIdx.x) + 1];
     }
-    s_ix[lane] = d.xw[kScAtoms * sc + lane];
+    if (threadIdx.x < kScAtoms) s_ix[threadIdx.x] = d.xw[kScAtoms * sc + threadIdx.x];
     __syncthreads();
     const float4 slo = d.sc_bb[2 * sc], shi = d.sc_bb[2 * sc + 1];
     const float margin = 0.01f;   // in column widths; column ranges only need to be supersets
@@ -106,8 +117,10 @@ __global__ __launch_bounds__(kWave) void k_search(NbDev d, int cap, float r2_out
     const int jy0 = (int)floorf((slo.y - rlist) / S.colw[1] - margin);
     const int jy1 = (int)floorf((shi.y + rlist) / S.colw[1] + margin);
     const int ci0 = kClustersPerSc * sc;
+    NbEntry* out = d.scratch + ((size_t)sc * kSearchWaves + wave) * cap;
     int n_out = 0;
     int bb_pairs = 0;
+    int unit = 0;                         // batch number in the super-cluster's sequence
     for (int jx = jx0; jx <= jx1; ++jx) {
         const int sx = floordiv(jx, S.nx);
         if (sx < -1 || sx > 1) continue;
@@ -120,7 +133,8 @@ __global__ __launch_bounds__(kWave) void k_search(NbDev d, int cap, float r2_out
             const int J0 = max(d.col_sc_start[jcol], sc);
             const int J1 = d.col_sc_start[jcol + 1];
             const int n_cand = (J1 > J0) ? (J1 - J0) * 3 : 0;
-            for (int base = 0; base < n_cand; base += kWave) {
+            for (int base = 0; base < n_cand; base += kWave, ++unit) {
+                if (unit % kSearchWaves != wave) continue;
                 const int k = base + lane;
                 bool pass = false;
                 if (k < n_cand) {
@@ -180,7 +194,7 @@ __global__ __launch_bounds__(kWave) void k_search(NbDev d, int cap, float r2_out
                                          ((uint32_t)nj << 24);
                                 e.excl = -1;
                                 e.jpos = -1;
-                                d.scratch[(size_t)sc * cap + n_out] = e;
+                                out[n_out] = e;
                             }
                             ++n_out;
                         }
@@ -189,11 +203,39 @@ __global__ __launch_bounds__(kWave) void k_search(NbDev d, int cap, float r2_out
             }
         }
     }
-    if (!kRecord && lane == 0) {
-        d.sc_ecount[sc] = min(n_out, cap);
-        if (n_out > cap) atomicOr(&d.flags[kFlagScOverflow], 1);
-        atomicMax(&d.flags[kFlagScNeeded], n_out);
-        atomicAdd(&d.flags[kFlagBbPairs], bb_pairs);
+    if constexpr (kRecord) return;
+    if (lane == 0) {
+        s_n[wave] = n_out;
+        if (bb_pairs) atomicAdd(&d.flags[kFlagBbPairs], bb_pairs);
+    }
+    __syncthreads();
+    int total = 0, before = 0;
+    for (int w = 0; w < kSearchWaves; ++w) {
+        const int n = s_n[w];
+        if (w < wave) before += min(n, cap);
+        total += n;
+    }
+    // Move the regions together in wavefront order: wavefront w's entries go to
+    // [before, before + n) from w cap on, never after their source (before <= w cap), and
+    // each 64-entry chunk is read in full before it is written, so a chunk overwrites only
+    // entries already moved.  The wavefronts take turns.
+    NbEntry* base = d.scratch + (size_t)sc * kSearchWaves * cap;
+    for (int w = 1; w < kSearchWaves; ++w) {
+        if (wave == w) {
+            const int n = min(n_out, cap);
+            for (int k0 = 0; k0 < n; k0 += kWave) {
+                NbEntry v{};
+                if (k0 + lane < n) v = base[(size_t)w * cap + k0 + lane];
+                __builtin_amdgcn_wave_barrier();
+                if (k0 + lane < n) base[before + k0 + lane] = v;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        d.sc_ecount[sc] = min(total, cap);
+        if (total > cap) atomicOr(&d.flags[kFlagScOverflow], 1);
+        atomicMax(&d.flags[kFlagScNeeded], total);
     }
 }
 
@@ -225,7 +267,9 @@ __device__ int block_scan(int n, F f, int32_t* __restrict__ out) {
     return total;
 }
 
+// n_sc < 0: the grid build's own count (none after non-finite coordinates)
 __global__ __launch_bounds__(kScanThreads) void k_scan_entries(NbDev d, int n_sc) {
+    if (n_sc < 0) n_sc = d.flags[kFlagNonFinite] ? 0 : d.flags[kFlagNumSc];
     const int total = block_scan(n_sc, [&](int i) { return d.sc_ecount[i]; }, d.sc_estart);
     if (threadIdx.x == 0) d.totals[0] = total;
 }
@@ -281,7 +325,7 @@ __global__ __launch_bounds__(kWave) void k_compact(NbDev d, int cap, int w, int 
     const int e0 = d.sc_estart[sc];
     if (copy_entries)
         for (int k = threadIdx.x; k < n; k += blockDim.x) {
-            d.entries[e0 + k] = d.scratch[(size_t)sc * cap + k];
+            d.entries[e0 + k] = d.scratch[(size_t)sc * kSearchWaves * cap + k];
             d.entry_sc[e0 + k] = sc;
         }
     if (!write_items) return;
@@ -418,46 +462,66 @@ __global__ __launch_bounds__(kScanThreads) void k_balanced_items(NbDev d, int n_
 }
 
 // One thread per entry: exclusion masks (bit ii + 8 jj cleared for excluded atom pairs),
-// a row only for entries with an exclusion; j-segment counts; list statistics (summed over
-// the wavefront first: one atomic per wavefront on each total).
-__global__ void k_entry_finish(NbDev d, int n_entries) {
+// a row only for entries with an exclusion (rows taken with one atomic per wavefront: a
+// single counter taken once per entry serialises); j-segment counts; list statistics
+// (summed over the wavefront first: one atomic per wavefront on each total).
+__global__ __launch_bounds__(256) void k_entry_finish(NbDev d, int n_entries) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
     int n_outer = 0, n_inner = 0;
+    uint64_t m[kClustersPerSc];
+    bool any = false;
+    NbEntry ent{};
     if (e < n_entries) {
-        const NbEntry ent = d.entries[e];
+        ent = d.entries[e];
         const int sc = d.entry_sc[e];
         const uint32_t omask = (ent.meta >> 8) & 0xffu;
-        uint64_t m[kClustersPerSc];
-        bool any = false;
+        // the partner-cluster ranges of the eight i-clusters, then the partner slots of
+        // those in range, each group of loads issued together
+        int2 xr[kClustersPerSc];
+#pragma unroll
+        for (int c = 0; c < kClustersPerSc; ++c)
+            xr[c] = ((omask >> c) & 1u) ? d.cl_xrange[kClustersPerSc * sc + c]
+                                        : make_int2(0x7fffffff, -1);
+#pragma unroll
         for (int c = 0; c < kClustersPerSc; ++c) {
             m[c] = ~0ull;
-            if (!((omask >> c) & 1u)) continue;
+            if (ent.cj < xr[c].x || ent.cj > xr[c].y) continue;   // no partner in cj
             const int ci = kClustersPerSc * sc + c;
-            for (int ii = 0; ii < kClusterSize; ++ii) {
-                const int slot = kClusterSize * ci + ii;
-                for (int k = 0; k < d.max_excl; ++k) {
-                    const int ps = d.excl_slot[(size_t)slot * d.max_excl + k];
-                    if (ps >= 0 && ps / kClusterSize == ent.cj)
-                        m[c] &= ~(1ull << (ii + 8 * (ps % kClusterSize)));
-                }
+            for (int k = 0; k < d.max_excl; ++k) {
+                int ps[kClusterSize];
+#pragma unroll
+                for (int ii = 0; ii < kClusterSize; ++ii)
+                    ps[ii] = d.excl_slot[(size_t)(kClusterSize * ci + ii) * d.max_excl + k];
+#pragma unroll
+                for (int ii = 0; ii < kClusterSize; ++ii)
+                    if (ps[ii] >= 0 && ps[ii] / kClusterSize == ent.cj)
+                        m[c] &= ~(1ull << (ii + 8 * (ps[ii] % kClusterSize)));
             }
             any |= (m[c] != ~0ull);
-        }
-        if (any) {
-            const int row = atomicAdd(&d.flags[kFlagNumRows], 1);
-            for (int c = 0; c < kClustersPerSc; ++c)
-                d.excl_rows[(size_t)row * kClustersPerSc + c] = m[c];
-            d.entries[e].excl = row;
         }
         atomicAdd(&d.jseg_count[ent.cj], 1);
         n_outer = __builtin_popcount(omask);
         n_inner = __builtin_popcount((ent.meta >> 16) & 0xffu);
     }
+    // rows of this wavefront's entries with exclusions: one atomic, then ranks by lane
+    const uint64_t need = __builtin_amdgcn_ballot_w64(any);
+    int row0 = 0;
+    if (need) {
+        if (lane == 0) row0 = atomicAdd(&d.flags[kFlagNumRows], __builtin_popcountll(need));
+        row0 = __builtin_amdgcn_readfirstlane(row0);
+    }
+    if (any) {
+        const int row = row0 + __builtin_popcountll(need & ((1ull << lane) - 1ull));
+        for (int c = 0; c < kClustersPerSc; ++c)
+            d.excl_rows[(size_t)row * kClustersPerSc + c] = m[c];
+        d.entries[e].excl = row;
+    }
     for (int off = kWave / 2; off > 0; off >>= 1) {
         n_outer += __shfl_xor(n_outer, off);
         n_inner += __shfl_xor(n_inner, off);
     }
-    if ((threadIdx.x & (kWave - 1)) == 0) {
+    if (lane == 0) {
         atomicAdd(&d.totals[2], n_outer);
         atomicAdd(&d.totals[3], n_inner);
     }
@@ -490,16 +554,30 @@ __global__ __launch_bounds__(kWave) void k_jseg_rank(NbDev d) {
 
 #define NB_FOR8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
+// OR of an 8-bit value over the 64 lanes: swap neighbours, swap pairs, mirror the half
+// rows, mirror the rows (every lane then holds its 16-lane row's OR), then the four rows.
+__device__ inline uint32_t wave_or(uint32_t v) {
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, true);
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, true);
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, true);
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, true);
+    return (uint32_t)(__builtin_amdgcn_readlane((int)v, 0) | __builtin_amdgcn_readlane((int)v, 16) |
+                      __builtin_amdgcn_readlane((int)v, 32) | __builtin_amdgcn_readlane((int)v, 48));
+}
+
 // Rolling prune (Sec. V.E) of a range of the items of one part (part_items lists each
 // part's items together): one block of kPruneWaves wavefronts per item, wavefront w taking
-// the item's entries w, w + kPruneWaves, ... in order with the next four entries'
-// j-clusters in flight.  Each wavefront loads the item's 64 i-atoms itself (lane ii of
-// cluster c: slot 8 c + ii), at the same time as its first entries: the waves of a block
-// share no data, so there is no barrier and the dependent loads before the first distance
-// test are the item, its entries and their j-clusters.  For every i-cluster of the outer
-// mask the inner bit is set iff some atom pair is closer than r_inner in the list
-// arithmetic (shift split between the two sides, no contraction).  Empty slots sit far
-// outside the box, so no valid-atom masks are needed; a cluster with itself keeps ii < jj.
+// the item's entries w, w + kPruneWaves, ... in order.  Lane k of a wavefront loads the
+// (j-cluster, mask word) of its k-th entry once, at the start (items hold at most 64
+// entries), and the loop reads them with readlane, so no step waits for an entry load;
+// the next entries' j-clusters are in flight.  The item's 64 i-atoms are staged once in
+// LDS.  For every i-cluster c of an
+// entry's outer mask each lane tests its pair (i-atom 8 c + ii, j-atom jj) against r_inner
+// in the list arithmetic (shift split between the two sides, no contraction) and keeps the
+// result as bit c of a per-lane word; one OR over the wavefront per entry gives the inner
+// mask.  (Per-lane bits keep the scalar unit out of the per-cluster work: a ballot and its
+// test per cluster made the kernel bound by scalar issue.)  Empty slots sit far outside
+// the box, so no valid-atom masks are needed; a cluster with itself keeps ii < jj.
 template <int kPruneWaves>
 __global__ __launch_bounds__(kPruneWaves * kWave) void k_prune(
     const NbItem* __restrict__ items, const int32_t* __restrict__ part_items,
@@ -507,58 +585,64 @@ __global__ __launch_bounds__(kPruneWaves * kWave) void k_prune(
     const NbScInfo* __restrict__ sc_info, const NbSys* __restrict__ sys, int item0,
     float r2_inner) {
 #pragma clang fp contract(off)
+    __shared__ float4 s_xi[kScAtoms];
     const NbItem it = items[part_items[item0 + blockIdx.x]];
+    if (it.ne <= 0) return;               // (items are never empty; uniform over the block)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x & (kWave - 1);
     const int ii = lane & 7, jj = lane >> 3;
     const int e_end = it.e0 + it.ne;
     const int e_first = it.e0 + wave;
-    if (e_first >= e_end) return;
+    const int kStep = kPruneWaves;
+    const int n_mine = e_first < e_end ? (e_end - e_first + kStep - 1) / kStep : 0;
+    int2 mine = make_int2(0, 0);          // lane k: (cj, meta) of entry e_first + k kStep
+    if (lane < n_mine)
+        mine = *reinterpret_cast<const int2*>(&entries[e_first + lane * kStep]);
+    // A j-cluster is loaded kAhead entries before its use; positions past the end load the
+    // last one again (valid memory, never used).  The loads are in flight while the block
+    // waits for the i-atoms.
+    constexpr int kAhead = 3;
+    float4 xq[kAhead];
+    const int last = n_mine > 0 ? n_mine - 1 : 0;
+#pragma unroll
+    for (int a = 0; a < kAhead; ++a)
+        xq[a] = xp[kClusterSize * __builtin_amdgcn_readlane(mine.x, a < last ? a : last) + jj];
+    if (threadIdx.x < kScAtoms) s_xi[threadIdx.x] = xp[kScAtoms * it.sc + threadIdx.x];
+    __syncthreads();
+    if (n_mine == 0) return;
     const NbSys S = sys[sc_info[it.sc].sys];
     const int ci0 = kClustersPerSc * it.sc;
-#define NB_PI(c) const float4 xi##c = xp[kScAtoms * it.sc + kClusterSize * c + ii];
+    // i-atom ii of cluster c in registers (no LDS wait inside the loop)
+#define NB_PI(c) const float4 xi##c = s_xi[kClusterSize * c + ii];
     NB_FOR8(NB_PI)
 #undef NB_PI
-    const int kStep = kPruneWaves;
-    // Rings of the wavefront's next entries and of their j-clusters, loaded in flight: a
-    // j-cluster is loaded kAhead iterations before its use, and its entry kLead iterations
-    // before that, so no load waits for the entry it depends on.  Positions past the end
-    // load the wavefront's first entry again (valid memory, never used).
-    constexpr int kAhead = 4, kLead = 2;
-    NbEntry en[kAhead + kLead];
-    float4 xq[kAhead];
-#pragma unroll
-    for (int a = 0; a < kAhead + kLead; ++a) {
-        const int ea = e_first + a * kStep;
-        en[a] = entries[ea < e_end ? ea : e_first];
-    }
-#pragma unroll
-    for (int a = 0; a < kAhead; ++a) xq[a] = xp[kClusterSize * en[a].cj + jj];
-    for (int e = e_first; e < e_end; e += kStep) {
-        const NbEntry ent = en[0];
+    for (int k = 0; k < n_mine; ++k) {
+        const int2 ent = make_int2(__builtin_amdgcn_readlane(mine.x, k),
+                                   __builtin_amdgcn_readlane(mine.y, k));
         float4 xj = xq[0];
 #pragma unroll
-        for (int a = 0; a + 1 < kAhead + kLead; ++a) en[a] = en[a + 1];
-#pragma unroll
         for (int a = 0; a + 1 < kAhead; ++a) xq[a] = xq[a + 1];
-        xq[kAhead - 1] = xp[kClusterSize * en[kAhead - 1].cj + jj];
-        const int en_next = e + (kAhead + kLead) * kStep;
-        en[kAhead + kLead - 1] = entries[en_next < e_end ? en_next : e_first];
-        const int code = ent.meta & 31u;
-        const uint32_t omask = (ent.meta >> 8) & 0xffu;
-        uint32_t imask = 0;
+        const int kn = k + kAhead < last ? k + kAhead : last;
+        xq[kAhead - 1] = xp[kClusterSize * __builtin_amdgcn_readlane(mine.x, kn) + jj];
+        const int e = e_first + k * kStep;
+        const uint32_t meta = (uint32_t)ent.y;
+        const int code = meta & 31u;
+        const uint32_t omask = (meta >> 8) & 0xffu;
+        uint32_t hits = 0;                // bit c: this lane's pair of cluster c is inside
         if (code == kShiftZero) {
             // no shift: x_i - x_j, the same bits as the general sequence with zero shifts
-            const int dc = ent.cj - ci0;
 #define NB_PB(c)                                                                       \
             if ((omask >> c) & 1u) {                                                   \
-                const float dx = xi##c.x - xj.x, dy = xi##c.y - xj.y, dz = xi##c.z - xj.z; \
+                const float dx = xi##c.x - xj.x;                                       \
+                const float dy = xi##c.y - xj.y;                                       \
+                const float dz = xi##c.z - xj.z;                                       \
                 const float r2 = (dx * dx + dy * dy) + dz * dz;                        \
-                const uint64_t m = (dc == c) ? 0x7f3f1f0f07030100ull : ~0ull;          \
-                if (__builtin_amdgcn_ballot_w64(r2 < r2_inner) & m) imask |= 1u << c;  \
+                hits |= (r2 < r2_inner) ? (1u << c) : 0u;                              \
             }
             NB_FOR8(NB_PB)
 #undef NB_PB
+            const int dc = ent.x - ci0;   // a cluster with itself: pairs ii < jj only
+            if ((unsigned)dc < (unsigned)kClustersPerSc && ii >= jj) hits &= ~(1u << dc);
         } else {
             // the same separation as the list build: x_i - L for s > 0, x_j - L for s < 0
             // (a shifted entry keeps all 64 pairs, an atom and its own image included)
@@ -574,12 +658,13 @@ __global__ __launch_bounds__(kPruneWaves * kWave) void k_prune(
                 const float dy = (xi##c.y - oy) - xj.y;                                \
                 const float dz = (xi##c.z - oz) - xj.z;                                \
                 const float r2 = (dx * dx + dy * dy) + dz * dz;                        \
-                if (__builtin_amdgcn_ballot_w64(r2 < r2_inner)) imask |= 1u << c;      \
+                hits |= (r2 < r2_inner) ? (1u << c) : 0u;                              \
             }
             NB_FOR8(NB_PB)
 #undef NB_PB
         }
-        if (lane == 0) entries[e].meta = (ent.meta & ~(0xffu << 16)) | (imask << 16);
+        const uint32_t imask = wave_or(hits);
+        if (lane == 0) entries[e].meta = (meta & ~(0xffu << 16)) | (imask << 16);
     }
 }
 
@@ -633,16 +718,16 @@ hipError_t launch_item_order(const NbDev& d, int n_items, hipStream_t s) {
 hipError_t launch_search(const NbDev& d, int n_sc, int cap, float r2_outer, float r2_inner,
                          float rlist, hipStream_t s) {
     if (n_sc > 0)
-        hipLaunchKernelGGL(k_search<false>, dim3(n_sc), dim3(kWave), 0, s, d, cap, r2_outer,
-                           r2_inner, rlist, 0);
+        hipLaunchKernelGGL(k_search<false>, dim3(n_sc), dim3(kSearchWaves * kWave), 0, s, d, cap,
+                           r2_outer, r2_inner, rlist, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_search_record(const NbDev& d, int n_sc, float r2_outer, float rlist,
                                 int rec_cap, hipStream_t s) {
     if (n_sc > 0)
-        hipLaunchKernelGGL(k_search<true>, dim3(n_sc), dim3(kWave), 0, s, d, 0, r2_outer,
-                           r2_outer, rlist, rec_cap);
+        hipLaunchKernelGGL(k_search<true>, dim3(n_sc), dim3(kSearchWaves * kWave), 0, s, d, 0,
+                           r2_outer, r2_outer, rlist, rec_cap);
     return hipGetLastError();
 }
 
@@ -703,19 +788,17 @@ int prune_blocks_per_cu() {
 }
 }  // namespace
 
-// Wavefronts per item as asked, or (waves = 0) the most (8, 4, 2, 1) with which every
-// block of the part is resident at once (one round: the dependent loads at the start of a
-// block are paid once), one wavefront per item when no width fits.
+// Wavefronts per item as asked, or (waves = 0) eight while the part's blocks fill the
+// device at most twice over (each wavefront's walk over its entries is then short), else
+// two (measured at 96k atoms, 1,400 items per part: 14.6 us with eight against 16.1 with
+// four; at 1.5M atoms, 22,000 items per part: 148 us with two, 151 with four, 166 with
+// eight).
 hipError_t launch_prune(const NbDev& d, const float4* coords, int item0, int n_items,
                         float r2_inner, int waves, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     const int64_t cus = std::max(d.n_cu, 1);
 #define NB_PRUNE_LAUNCH(W)                                                                  hipLaunchKernelGGL(k_prune<W>, dim3(n_items), dim3(W * kWave), 0, s, d.items,                                 d.part_items, d.entries, coords, d.sc_info, d.sys, item0, r2_inner)
-    if (waves == 0)
-        waves = (n_items <= prune_blocks_per_cu<8>() * cus)   ? 8
-                : (n_items <= prune_blocks_per_cu<4>() * cus) ? 4
-                : (n_items <= prune_blocks_per_cu<2>() * cus) ? 2
-                                                              : 1;
+    if (waves == 0) waves = (n_items <= 2 * prune_blocks_per_cu<8>() * cus) ? 8 : 2;
     if (waves == 8) NB_PRUNE_LAUNCH(8);
     else if (waves == 4) NB_PRUNE_LAUNCH(4);
     else if (waves == 2) NB_PRUNE_LAUNCH(2);

@@ -44,67 +44,40 @@ __device__ inline void neumaier(float& s, float& c, float v) {
     s = t;
 }
 
-// One block of kRedWaves wavefronts per super-cluster, lane = slot within it (cluster c =
-// l >> 3, atom jj = l & 7).  The j-partials of the entries referencing the lane's cluster
-// (a contiguous segment, in entry order) and the i-partials of the super-cluster's items
-// (one 1 KB row per item, read by the whole wavefront) are each cut into kRedWaves
-// consecutive ranges; wavefront w sums range w of both with compensation (Neumaier), and
-// wavefront 0 adds the four compensated sums in wavefront order through LDS, then the
-// atom's exclusion correction, and writes the atom's force in the caller's order.  The
-// order of every sum is fixed by the list alone; the split gives four times the loads in
-// flight of one wavefront per super-cluster, whose sums are short chains of dependent
-// loads.
+// One wavefront per super-cluster, lane = slot within it (cluster c = l >> 3, atom jj = l &
+// 7): each lane sums, with compensation, the j-partials of the entries referencing its
+// cluster (a contiguous segment, in entry order) and then the i-partials of the
+// super-cluster's items (in item order; one 1 KB row per item, read by the whole wavefront),
+// then its exclusion correction, and writes its atom's force in the caller's order.  No
+// lanes are combined, so there is no cross-lane traffic, and the order of every sum is
+// fixed.  (Four wavefronts per super-cluster, each summing a quarter of every segment and
+// combined through LDS, measured no faster.)
 constexpr int kRedWaves = 4;
 __device__ __forceinline__ void reduce_sc(
     const int sc, const int32_t* __restrict__ slot_atom, const int32_t* __restrict__ jseg_start,
     const float4* __restrict__ jpart, const int32_t* __restrict__ sc_istart,
     const int32_t* __restrict__ sc_icount, const float4* __restrict__ ipart,
     const float4* __restrict__ xcf, float* __restrict__ f, int accumulate) {
-    __shared__ float s_part[kRedWaves - 1][6][kWave];
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x & (kWave - 1);
     const int jj = lane & 7;
     const int cj = sc * kClustersPerSc + (lane >> 3);
     const int slot = sc * kScAtoms + lane;
     const int s0 = jseg_start[cj], s1 = jseg_start[cj + 1];
-    const int i0 = sc_istart[sc], ni = sc_icount[sc];
-    const int ka = s0 + (int)(((int64_t)(s1 - s0) * wave) / kRedWaves);
-    const int kb = s0 + (int)(((int64_t)(s1 - s0) * (wave + 1)) / kRedWaves);
-    const int ia = i0 + (ni * wave) / kRedWaves, ib = i0 + (ni * (wave + 1)) / kRedWaves;
+    const int i0 = sc_istart[sc], i1 = i0 + sc_icount[sc];
     float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
 #pragma unroll 4
-    for (int k = ka; k < kb; ++k) {
+    for (int k = s0; k < s1; ++k) {
         const float4 v = jpart[(size_t)k * kClusterSize + jj];
         neumaier(sx, cx, v.x);
         neumaier(sy, cy, v.y);
         neumaier(sz, cz, v.z);
     }
 #pragma unroll 2
-    for (int i = ia; i < ib; ++i) {
+    for (int i = i0; i < i1; ++i) {
         const float4 v = ipart[(size_t)i * kScAtoms + lane];
         neumaier(sx, cx, v.x);
         neumaier(sy, cy, v.y);
         neumaier(sz, cz, v.z);
-    }
-    if (wave > 0) {
-        float* p = &s_part[wave - 1][0][lane];
-        p[0 * kWave] = sx;
-        p[1 * kWave] = sy;
-        p[2 * kWave] = sz;
-        p[3 * kWave] = cx;
-        p[4 * kWave] = cy;
-        p[5 * kWave] = cz;
-    }
-    __syncthreads();
-    if (wave > 0) return;
-    for (int w = 0; w + 1 < kRedWaves; ++w) {   // (s, c) + (s_w, c_w): s_w compensated, c_w added
-        const float* p = &s_part[w][0][lane];
-        neumaier(sx, cx, p[0 * kWave]);
-        neumaier(sy, cy, p[1 * kWave]);
-        neumaier(sz, cz, p[2 * kWave]);
-        cx += p[3 * kWave];
-        cy += p[4 * kWave];
-        cz += p[5 * kWave];
     }
     if (xcf) {                          // exclusion corrections of this atom, if any
         const float4 v = xcf[slot];
@@ -154,8 +127,8 @@ __device__ inline void energy_totals(const NbDev& d, double* __restrict__ energy
 }
 
 // Force reduction and the energy reduction in one launch: blocks [0, n_fblk) reduce the
-// forces of one super-cluster each, blocks [n_fblk, n_fblk + n_chunks) sum one energy chunk
-// each; the last energy block to finish (a ticket in
+// forces of four super-clusters each (one wavefront per super-cluster), blocks [n_fblk,
+// n_fblk + n_chunks) sum one energy chunk each; the last energy block to finish (a ticket in
 // queue[2], taken after a device-scope fence) adds the chunk partials per system and
 // resets the ticket for the next launch.
 __global__ __launch_bounds__(kRedThreads) void k_reduce_step(NbDev d, float* __restrict__ f,
@@ -182,7 +155,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_step(NbDev d, float* __r
         }
         return;
     }
-    const int sc = blockIdx.x;
+    const int sc = blockIdx.x * kRedWaves + (int)(threadIdx.x / kWave);
     if (sc >= n_sc) return;
     reduce_sc(sc, d.slot_atom, d.jseg_start, d.jpart, d.sc_istart, d.sc_icount, d.ipart, xcf,
               f, accumulate);
@@ -210,7 +183,7 @@ hipError_t launch_reduce(const NbDev& d, float* f, bool accumulate, int n_slots,
                         double* energy, double* virial, uint32_t flags, int n_sys,
                         const float4* xcf, hipStream_t s) {
     const int n_sc = n_slots / kScAtoms;
-    const int n_fblk = n_sc;
+    const int n_fblk = blocks(n_sc, kRedWaves);
     const bool ev = (flags & (NB_F_ENERGY | NB_F_VIRIAL)) && n_sys > 0;
     const int n_eblk = ev ? d.n_chunks : 0;
     if (n_fblk + n_eblk > 0)
