@@ -103,7 +103,8 @@ def measured_traffic(workload, exec_cfg):
     shape = "%d entries per item, %s" % (exec_cfg["item_width"],
                                           {"xcd": "XCD-contiguous", "static": "static",
                                            "queue": "persistent queue",
-                                           "persist": "persistent balanced"}[exec_cfg["mode"]])
+                                           "persist": "persistent balanced",
+                                           "balanced": "equal-cost runs"}[exec_cfg["mode"]])
     for line in text.splitlines():
         if line.strip().startswith("HBM traffic") and shape in line:
             return float(line.split()[-2]) * 1e6
@@ -572,7 +573,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: workload's)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="water96k_ewald", choices=sorted(WORKLOADS))
-    ap.add_argument("--exec", default="auto", choices=["auto", "static", "xcd", "queue", "persist"],
+    ap.add_argument("--exec", default="auto",
+                    choices=["auto", "static", "xcd", "queue", "persist", "balanced"],
                     help="pair kernel execution shape (auto = autotuner at the first build)")
     ap.add_argument("--item-width", type=int, default=0,
                     help="entries per work item with a fixed --exec mode (0 = built-in rule)")
