@@ -567,6 +567,13 @@ def verlet_buffer(args):
     print(json.dumps(result), flush=True)
 
 
+def prune_place(code):
+    """Where nb_step prunes, from get_exec()['prune_fused'] (True, False or 'ahead')."""
+    return {True: "inside the pair kernel", False: "as its own kernel before the pair kernel",
+            "ahead": "as its own kernel after the pair kernel, for the next step, beside the "
+                     "force reduction"}[code]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -578,7 +585,7 @@ def main():
                     help="pair kernel execution shape (auto = autotuner at the first build)")
     ap.add_argument("--item-width", type=int, default=0,
                     help="entries per work item with a fixed --exec mode (0 = built-in rule)")
-    ap.add_argument("--prune", default="fused", choices=["fused", "separate"],
+    ap.add_argument("--prune", default="fused", choices=["fused", "separate", "ahead"],
                     help="rolling prune placement with a fixed --exec mode")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
@@ -654,9 +661,11 @@ def main():
         best, trials = ctx.autotune(traj[0], q, lj, energy=True, repeats=5)
         tune = {"best": best, "trials": trials}
         log("autotune: item width %d, mode %s, prune %s"
-            % (best["item_width"], best["mode"], "fused" if best["prune_fused"] else "separate"))
+            % (best["item_width"], best["mode"], {True: "fused", False: "separate",
+                                                   "ahead": "ahead"}[best["prune_fused"]]))
     else:
-        ctx.set_exec(args.item_width, args.exec, prune_fused=(args.prune == "fused"))
+        ctx.set_exec(args.item_width, args.exec,
+                     prune_fused={"fused": True, "separate": False, "ahead": "ahead"}[args.prune])
 
     have_bwd = not args.no_backward
     G = None
@@ -725,8 +734,14 @@ def main():
         return wall, tm
 
     log("timed graph-replayed step: %d warmup + %d steps" % (W, K))
-    wall, _ = timed("graph")
-    log("graph: %.3f ms/step" % (1e3 * wall / K))
+    wall_graph, _ = timed("graph")
+    log("graph: %.3f ms/step" % (1e3 * wall_graph / K))
+    # The same steps launched one by one (positions read where they are: no copy into a
+    # fixed buffer, no events); the faster of the two is the step's time.
+    wall_plain, _ = timed("eager")
+    log("eager step without timing events: %.3f ms/step" % (1e3 * wall_plain / K))
+    graph_path = wall_graph <= wall_plain
+    wall = wall_graph if graph_path else wall_plain
     wall_eager, tm_eager = timed("eager", timing=True)
     log("eager step: %.3f ms/step" % (1e3 * wall_eager / K))
     wall_sep, tm_sep = timed("separate", timing=True)
@@ -777,16 +792,19 @@ def main():
                    "list_entries": int(first_stats["n_entries"]),
                    "work_items": int(first_stats["n_work_items"]),
                    "exec": ctx.get_exec()},
-        "step_path": "nb_step_graph (HIP graph replay, positions copied in place; rolling "
-                     "prune %s)" % ("inside the pair kernel" if ctx.get_exec()["prune_fused"]
-                                    else "as separate kernels"),
+        "step_path": ("nb_step_graph (HIP graph replay, positions copied in place" if graph_path
+                      else "nb_step launched kernel by kernel (positions read in place")
+        + "; rolling prune %s; the faster of graph replay and kernel-by-kernel launch)"
+        % prune_place(ctx.get_exec()["prune_fused"]),
+        "ms_per_step_graph": 1e3 * wall_graph / K,
+        "ms_per_step_launched": 1e3 * wall_plain / K,
         "effective_pairs_per_step": float(eff[W:].mean()),
         "raw_pairs_per_s": comp_timed / wall,
         "ns_per_day_equiv": 0.1728 / amortized_s,
         "ms_list_rebuild": 1e3 * build_s,
         "ms_per_step_amortized": 1e3 * amortized_s,
         "builds_in_timed_steps": n_builds,
-        "ms_per_step_eager": 1e3 * wall_eager / K,
+        "ms_per_step_eager_with_timing_events": 1e3 * wall_eager / K,
         "ms_per_step_separate_prune_call": 1e3 * wall_sep / K,
         "fwd_bwd_pairs_per_s": (eff_timed / wall_fb) if wall_fb else None,
         "fwd_bwd_ms_per_step": (1e3 * wall_fb / K) if wall_fb else None,

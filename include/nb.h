@@ -193,11 +193,18 @@ nb_status nb_forces(nb_ctx* ctx, const float* x, const float* q, const float* lj
                     double* energy, double* virial, uint32_t flags);
 
 /*
- * One MD step of the pair path in a single pass: exactly nb_prune_rolling(x,
- * steps_since_build) followed by nb_forces(x, q, lj, ...), with the rolling prune of the
- * part done inside the pair kernel (Sec. V.D: a special version of the force kernel
- * prunes the list it processes).  Same inner list, same forces, one gather and one
- * kernel fewer.  steps_since_build = 0 evaluates forces only.  Errors as both calls.
+ * One MD step of the pair path.  With the prune fused (nb_set_exec prune_fused = 1, the
+ * default): exactly nb_prune_rolling(x, steps_since_build) followed by nb_forces(x, q, lj,
+ * ...), with the rolling prune of the part done inside the pair kernel (Sec. V.D: a
+ * special version of the force kernel prunes the list it processes); same inner list, same
+ * forces, one gather and one kernel fewer.  With prune_fused = 0 the same two calls as
+ * separate kernels.  steps_since_build = 0 evaluates forces only.  With prune_fused = 2
+ * (ahead, the paper's rolling schedule between force computations, Sec. V.E): nb_forces
+ * with the current inner list, then the part (steps_since_build + 1) mod nstprune is
+ * pruned with this step's x for the next step, on a second stream beside the force
+ * reduction (none when steps_since_build + 1 = nstlist); a part is then used 1 to
+ * nstprune steps after its prune instead of 0 to nstprune - 1.  Work queued on the
+ * context's stream after the call waits for that prune.  Errors as both calls.
  */
 nb_status nb_step(nb_ctx* ctx, const float* x, const float* q, const float* lj, float* f,
                   double* energy, double* virial, uint32_t flags, int64_t steps_since_build);
@@ -247,7 +254,9 @@ typedef struct {
     int32_t item_width;   /* entries per work item, 1..64 */
     int32_t exec_mode;    /* NB_EXEC_* */
     int32_t prune_fused;  /* nb_step: 1 = rolling prune inside the pair kernel (Sec. V.D),
-                             0 = the prune as its own kernels before the pair kernel */
+                             0 = the prune as its own kernel before the pair kernel,
+                             2 = ahead: its own kernel after the pair kernel, for the
+                             next step's part (Sec. V.E) */
     int32_t prune_waves;  /* wavefronts per work item in the separate rolling-prune kernel:
                              1, 2, 4 or 8, or 0 = the most with which one rolling part
                              fits the device at once */
@@ -255,7 +264,8 @@ typedef struct {
 } nb_exec_config;
 
 /* Fix the item width (0 = the built-in rule, about 8192 items, width 8..64), the mode,
- * where nb_step prunes (prune_fused 0 or 1; same inner list and results either way) and
+ * where nb_step prunes (prune_fused 0, 1 or 2; 0 and 1 give the same inner list and
+ * results, 2 prunes each part one step earlier, see nb_step) and
  * the wavefronts per item of the separate prune kernel (prune_waves 0, 1, 2, 4 or 8; same
  * inner list either way); applies to the current list at once and to every later build.
  * Errors: NB_ERR_ARG. */
@@ -267,9 +277,9 @@ nb_status nb_get_exec(nb_ctx* ctx, nb_exec_config* out);
  * [sync] Autotuner (the paper calls for dynamic auto-tuning of code flavors, Sec. VII):
  * times nb_forces(x, q, lj, flags) on the current list for item widths 8, 16, ..., 64 (steps
  * of 8), each with the five execution modes (repeats timed calls after one warm-up each,
- * HIP events, median), then, in the fastest shape, a rolling step (nb_step of part 1,
- * which re-prunes that part with x) with the prune fused and separate; writes up to cap
- * trials to host trials[] and their number (42) to *n_trials, and keeps
+ * HIP events, median), then, in the fastest shape, a rolling step (nb_step re-pruning
+ * part 1 with x) with the prune fused, separate and ahead; writes up to cap
+ * trials to host trials[] and their number (43) to *n_trials, and keeps
  * the fastest choices (also returned in *best) for this and later builds.
  * flags: NB_F_ENERGY and/or NB_F_VIRIAL.  Allocates and frees its own output buffers.
  * Errors: NB_ERR_STATE without a list, NB_ERR_ARG.

@@ -19,6 +19,7 @@ EXPORTS = ["nb_create", "nb_destroy", "nb_set_topology", "nb_grid_build", "nb_pa
            "nb_autotune", "nb_list_census", "nb_list_coverage", "nb_buffer_drift",
            "nb_buffer_estimate", "nb_list_census_noalloc"]
 NB_EXEC_STATIC, NB_EXEC_XCD, NB_EXEC_QUEUE, NB_EXEC_PERSIST, NB_EXEC_BALANCED = 0, 1, 2, 3, 4
+NB_PRUNE_SEPARATE, NB_PRUNE_FUSED, NB_PRUNE_AHEAD = 0, 1, 2
 EXEC_MODES = {"static": NB_EXEC_STATIC, "xcd": NB_EXEC_XCD, "queue": NB_EXEC_QUEUE,
               "persist": NB_EXEC_PERSIST, "balanced": NB_EXEC_BALANCED}
 (NB_T_FORCES, NB_T_FORCE_REDUCE, NB_T_PRUNE, NB_T_BACKWARD, NB_T_BACKWARD_REDUCE, NB_T_CENSUS,

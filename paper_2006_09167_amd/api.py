@@ -55,6 +55,19 @@ def make_params(n_types: int, coulomb: str = "rf", rc: float = 1.0,
                          list_capacity_hint=capacity_hint)
 
 
+def _prune_code(prune_fused) -> int:
+    """nb_exec_config.prune_fused from True / False / "ahead"."""
+    if isinstance(prune_fused, str):
+        if prune_fused != "ahead":
+            raise ValueError("prune_fused is True, False or 'ahead'")
+        return _lib.NB_PRUNE_AHEAD
+    return 1 if prune_fused else 0
+
+
+def _prune_name(code: int):
+    return "ahead" if code == _lib.NB_PRUNE_AHEAD else bool(code)
+
+
 class _BufferArgs:
     """Marshalled nb_buffer_input (keeps the arrays alive; checks the sizes the library
     reads: one entry per class in every class array, an n_types x n_types x 2 table, a
@@ -264,20 +277,22 @@ class Context:
                        flags, int(steps_since_build)), "nb_step_graph" if graph else "nb_step")
         return f, (e if energy else None), (vir if virial else None)
 
-    def set_exec(self, item_width: int = 0, mode: str = "static", prune_fused: bool = True,
+    def set_exec(self, item_width: int = 0, mode: str = "static", prune_fused=True,
                  prune_waves: int = 0):
         """Item width (0 = built-in rule), execution mode ('static', 'xcd', 'queue',
-        'persist', 'balanced'), whether step() prunes inside the pair kernel or with separate
-        kernels, and the wavefronts per item of the separate prune (0 = automatic)."""
+        'persist', 'balanced'), where step() prunes (True: inside the pair kernel; False: its
+        own kernel before it; "ahead": its own kernel after it, beside the force reduction,
+        for the next step's part with this step's positions), and the wavefronts per item
+        of the prune kernel (0 = automatic)."""
         self._check(self.lib.nb_set_exec(self.h, int(item_width), EXEC_MODES[mode],
-                                         1 if prune_fused else 0, int(prune_waves)),
+                                         _prune_code(prune_fused), int(prune_waves)),
                     "nb_set_exec")
 
     def get_exec(self) -> dict:
         out = NbExecConfig()
         self._check(self.lib.nb_get_exec(self.h, ctypes.byref(out)), "nb_get_exec")
         return {"item_width": out.item_width, "mode": _MODE_NAMES[out.exec_mode],
-                "prune_fused": bool(out.prune_fused), "prune_waves": int(out.prune_waves)}
+                "prune_fused": _prune_name(out.prune_fused), "prune_waves": int(out.prune_waves)}
 
     def autotune(self, x, q, lj, energy: bool = True, virial: bool = False, repeats: int = 5):
         """Time nb_forces over item widths and execution modes on the current list, keep the
@@ -296,7 +311,7 @@ class Context:
 
         def d(t):
             return {"item_width": t.item_width, "mode": _MODE_NAMES[t.exec_mode],
-                    "prune_fused": bool(t.prune_fused), "us_per_call": t.us_per_call}
+                    "prune_fused": _prune_name(t.prune_fused), "us_per_call": t.us_per_call}
         return d(best), [d(trials[i]) for i in range(min(n.value, cap))]
 
     def backward(self, x, q, lj, grad_f, grad_energy=None, need_x=True, need_q=True,

@@ -28,12 +28,15 @@ struct nb_ctx {
     int32_t fixed_w = 0;      // item width chosen by nb_set_exec / nb_autotune (0 = rule)
     int32_t exec_mode = kExecStatic;
     bool items_balanced = false;  // the current items are the balanced mode's partition
-    bool prune_fused = true;  // nb_step: rolling prune inside the pair kernel, else separate
+    // nb_step's rolling prune: kPruneFused inside the pair kernel, kPruneSeparate as its own
+    // kernel before it, kPruneAhead as its own kernel after it on a second stream, for the
+    // next step's part with this step's positions
+    int prune_mode = kPruneFused;
     int32_t prune_waves = 0;  // wavefronts per item of the separate prune (0 = automatic)
     uint64_t list_gen = 0;    // bumped whenever items or launch shapes change
     // graphs of nb_step_graph: key = (part, flags, pointers, list_gen)
     struct GraphEntry {
-        int part;
+        int part, ahead;
         uint32_t flags;
         const void* ptr[7];
         uint64_t gen;
@@ -41,6 +44,8 @@ struct nb_ctx {
     };
     std::vector<GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;
+    hipStream_t side_stream = nullptr;      // the ahead prune, beside the force reduction
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<int32_t> part_start;
     int32_t h_totals[8] = {};  // host copy of the device totals after the last list change
     nb_stats stats{};
@@ -187,16 +192,18 @@ hipEvent_t take_event(nb_ctx* c) {
 struct TimedSection {
     nb_ctx* c;
     int kind;
+    hipStream_t s;
     hipEvent_t a = nullptr, b = nullptr;
-    TimedSection(nb_ctx* c_, int k) : c(c_), kind(k) {
+    TimedSection(nb_ctx* c_, int k, hipStream_t s_ = nullptr)
+        : c(c_), kind(k), s(s_ ? s_ : c_->stream) {
         if (!c->timing) return;
         a = take_event(c);
         b = take_event(c);
-        if (a) hipEventRecord(a, c->stream);
+        if (a) hipEventRecord(a, s);
     }
     ~TimedSection() {
         if (!c->timing || !a || !b) return;
-        hipEventRecord(b, c->stream);
+        hipEventRecord(b, s);
         c->ev[kind].emplace_back(a, b);
     }
 };
@@ -293,6 +300,9 @@ void nb_destroy(nb_ctx* c) {
                     d.part_items, d.wave_e, d.wave_item, d.cl_xrange};
     drop_graphs(c);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+    if (c->side_stream) hipStreamDestroy(c->side_stream);
+    if (c->ev_fork) hipEventDestroy(c->ev_fork);
+    if (c->ev_join) hipEventDestroy(c->ev_join);
     for (void* q : ptrs)
         if (q) hipFree(q);
     for (void* q : {(void*)c->census_hist, (void*)c->census_part, (void*)c->census_total,
@@ -698,8 +708,12 @@ nb_status nb_prune_rolling(nb_ctx* c, const float* x, int64_t steps_since_build)
 namespace {
 constexpr uint32_t kForceFlags = NB_F_ENERGY | NB_F_VIRIAL | NB_F_ACCUMULATE | NB_F_EXCL_CORR;
 
+// prune_part >= 0: re-prune that rolling part with x before the pair kernel (inside it when
+// the prune is fused); ahead_part >= 0: after the pair kernel, re-prune that part with x on
+// the side stream while the force reduction runs, joined before the call returns its work.
 nb_status forces_impl(nb_ctx* c, const float* x, const float* q, const float* lj, float* f,
-                      double* energy, double* virial, uint32_t flags, int prune_part) {
+                      double* energy, double* virial, uint32_t flags, int prune_part,
+                      int ahead_part = -1) {
     if (flags & ~kForceFlags) return fail(c, NB_ERR_ARG, "unknown flag");
     if (c->d.n_atoms > 0 && (!x || !q || !lj || !f)) return fail(c, NB_ERR_ARG, "null array");
     if ((flags & NB_F_ENERGY) && !energy) return fail(c, NB_ERR_ARG, "energy output missing");
@@ -707,7 +721,7 @@ nb_status forces_impl(nb_ctx* c, const float* x, const float* q, const float* lj
     NB_HIP(c, hipSetDevice(c->device));
     NbDev& d = c->d;
     const NbKParams kp = kernel_params(c->p);
-    const bool fused = prune_part >= 0 && c->prune_fused;
+    const bool fused = prune_part >= 0 && c->prune_mode == kPruneFused;
     {
         TimedSection ts(c, NB_T_FORCE_REDUCE);
         NB_HIP(c, launch_gather(d, x, q, d.xq, c->n_slots, c->stream));
@@ -726,6 +740,23 @@ nb_status forces_impl(nb_ctx* c, const float* x, const float* q, const float* lj
                                 fused ? prune_part : -1, c->p.nstprune,
                                 radius_sq(c->p.rinner), c->exec_mode, c->stream));
     }
+    if (ahead_part >= 0) {
+        // the paper's rolling schedule: the next step's part is pruned between force
+        // computations (Sec. V.E), here beside the force reduction
+        if (!c->side_stream)
+            NB_HIP(c, hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
+        if (!c->ev_fork) NB_HIP(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        if (!c->ev_join) NB_HIP(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+        NB_HIP(c, hipEventRecord(c->ev_fork, c->stream));
+        NB_HIP(c, hipStreamWaitEvent(c->side_stream, c->ev_fork, 0));
+        {
+            const int i0 = c->part_start[ahead_part], i1 = c->part_start[ahead_part + 1];
+            TimedSection ts(c, NB_T_PRUNE, c->side_stream);
+            NB_HIP(c, launch_prune(d, d.xq, i0, i1 - i0, radius_sq(c->p.rinner),
+                                   c->prune_waves, c->side_stream));
+        }
+        NB_HIP(c, hipEventRecord(c->ev_join, c->side_stream));
+    }
     // Exclusion corrections (a kernel of their own over the excluded pairs; the pair
     // kernel above is the same with or without them)
     const bool corr = (flags & NB_F_EXCL_CORR) && c->p.coulomb != NB_COUL_NONE;
@@ -739,6 +770,7 @@ nb_status forces_impl(nb_ctx* c, const float* x, const float* q, const float* lj
     NB_HIP(c, launch_reduce(d, f, (flags & NB_F_ACCUMULATE) != 0, c->n_slots, energy, virial,
                             flags, c->n_sys, corr ? d.xcf : nullptr, c->stream));
     if (corr) NB_HIP(c, launch_excl_energy(d, d.xce, energy, virial, flags, c->n_sys, c->stream));
+    if (ahead_part >= 0) NB_HIP(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
     return NB_OK;
 }
 }  // namespace
@@ -751,13 +783,23 @@ nb_status nb_forces(nb_ctx* c, const float* x, const float* q, const float* lj, 
 }
 
 namespace {
-// Rolling part pruned by nb_step at steps_since_build (-1: none), or a status < 0.
-nb_status step_part(nb_ctx* c, int64_t steps_since_build, int* part) {
+// Rolling parts of nb_step at steps_since_build s (-1: none): with the prune before or
+// inside the pair kernel, part s mod nstprune with this step's positions (none at s = 0,
+// the build's prune); with the ahead prune, after the pair kernel, part (s + 1) mod
+// nstprune for the next step (none when s + 1 = nstlist, a build step).
+nb_status step_part(nb_ctx* c, int64_t steps_since_build, int* part, int* ahead) {
     if (!c->has_list) return fail(c, NB_ERR_STATE, "no pair list");
     if (steps_since_build < 0) return fail(c, NB_ERR_ARG, "negative step");
     if (steps_since_build >= c->p.nstlist)
         return fail(c, NB_ERR_STATE, "the outer list has expired (steps_since_build >= nstlist)");
-    *part = steps_since_build == 0 ? -1 : (int)(steps_since_build % c->p.nstprune);
+    *part = -1;
+    *ahead = -1;
+    if (c->prune_mode == kPruneAhead) {
+        if (steps_since_build + 1 < c->p.nstlist)
+            *ahead = (int)((steps_since_build + 1) % c->p.nstprune);
+    } else if (steps_since_build > 0) {
+        *part = (int)(steps_since_build % c->p.nstprune);
+    }
     return NB_OK;
 }
 }  // namespace
@@ -765,24 +807,24 @@ nb_status step_part(nb_ctx* c, int64_t steps_since_build, int* part) {
 nb_status nb_step(nb_ctx* c, const float* x, const float* q, const float* lj, float* f,
                   double* energy, double* virial, uint32_t flags, int64_t steps_since_build) {
     if (!c) return NB_ERR_ARG;
-    int part = -1;
-    nb_status st = step_part(c, steps_since_build, &part);
+    int part = -1, ahead = -1;
+    nb_status st = step_part(c, steps_since_build, &part, &ahead);
     if (st != NB_OK) return st;
-    return forces_impl(c, x, q, lj, f, energy, virial, flags, part);
+    return forces_impl(c, x, q, lj, f, energy, virial, flags, part, ahead);
 }
 
 nb_status nb_step_graph(nb_ctx* c, const float* x, const float* q, const float* lj, float* f,
                         double* energy, double* virial, uint32_t flags,
                         int64_t steps_since_build) {
     if (!c) return NB_ERR_ARG;
-    int part = -1;
-    nb_status st = step_part(c, steps_since_build, &part);
+    int part = -1, ahead = -1;
+    nb_status st = step_part(c, steps_since_build, &part, &ahead);
     if (st != NB_OK) return st;
     if (flags & ~kForceFlags) return fail(c, NB_ERR_ARG, "unknown flag");
     NB_HIP(c, hipSetDevice(c->device));
     const void* key[7] = {x, q, lj, f, energy, virial, nullptr};
     for (auto& g : c->graphs)
-        if (g.part == part && g.flags == flags && g.gen == c->list_gen &&
+        if (g.part == part && g.ahead == ahead && g.flags == flags && g.gen == c->list_gen &&
             std::equal(key, key + 7, g.ptr)) {
             NB_HIP(c, hipGraphLaunch(g.exec, c->stream));
             return NB_OK;
@@ -796,7 +838,7 @@ nb_status nb_step_graph(nb_ctx* c, const float* x, const float* q, const float* 
     c->stream = c->cap_stream;
     c->timing = false;
     hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) st = forces_impl(c, x, q, lj, f, energy, virial, flags, part);
+    if (e == hipSuccess) st = forces_impl(c, x, q, lj, f, energy, virial, flags, part, ahead);
     hipGraph_t graph = nullptr;
     const hipError_t e_end = (e == hipSuccess) ? hipStreamEndCapture(c->cap_stream, &graph) : e;
     c->stream = user;
@@ -819,6 +861,7 @@ nb_status nb_step_graph(nb_ctx* c, const float* x, const float* q, const float* 
     }
     nb_ctx::GraphEntry g{};
     g.part = part;
+    g.ahead = ahead;
     g.flags = flags;
     std::copy(key, key + 7, g.ptr);
     g.gen = c->list_gen;
@@ -835,14 +878,15 @@ nb_status nb_set_exec(nb_ctx* c, int32_t width, int32_t exec_mode, int32_t prune
     if (exec_mode != kExecStatic && exec_mode != kExecXcd && exec_mode != kExecQueue &&
         exec_mode != kExecPersist && exec_mode != kExecBalanced)
         return fail(c, NB_ERR_ARG, "unknown execution mode");
-    if (prune_fused != 0 && prune_fused != 1) return fail(c, NB_ERR_ARG, "prune_fused is 0 or 1");
+    if (prune_fused != kPruneSeparate && prune_fused != kPruneFused && prune_fused != kPruneAhead)
+        return fail(c, NB_ERR_ARG, "prune_fused is 0, 1 or 2");
     if (prune_waves != 0 && prune_waves != 1 && prune_waves != 2 && prune_waves != 4 &&
         prune_waves != 8)
         return fail(c, NB_ERR_ARG, "prune_waves is 0, 1, 2, 4 or 8");
     c->fixed_w = width;
     c->prune_waves = prune_waves;
     c->exec_mode = exec_mode;
-    c->prune_fused = prune_fused != 0;
+    c->prune_mode = prune_fused;
     c->list_gen++;
     if (c->d.flags) {
         NB_HIP(c, hipSetDevice(c->device));
@@ -861,7 +905,7 @@ nb_status nb_get_exec(nb_ctx* c, nb_exec_config* out) {
     if (!c || !out) return NB_ERR_ARG;
     out->item_width = c->has_list ? c->item_w : c->fixed_w;
     out->exec_mode = c->exec_mode;
-    out->prune_fused = c->prune_fused ? 1 : 0;
+    out->prune_fused = c->prune_mode;
     out->prune_waves = c->prune_waves;
     out->us_per_call = 0.0;
     return NB_OK;
@@ -898,12 +942,15 @@ nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj
     int n = 0;
     nb_status st = NB_OK;
     // median time of `repeats` calls after a warm-up; part < 0: forces only, else a step
-    // that also re-prunes that rolling part (valid with any current positions)
+    // that also re-prunes that rolling part (valid with any current positions), before or
+    // inside the pair kernel, or after it beside the reduction with the ahead prune
     auto time_calls = [&](int part, double* us) {
         std::vector<float> ms;
+        const bool ahead = part >= 0 && c->prune_mode == kPruneAhead;
         for (int r = 0; r <= repeats && st == NB_OK; ++r) {
             hipEventRecord(e0, c->stream);
-            st = forces_impl(c, x, q, lj, f, ev, ev + 2 * c->n_sys, flags, part);
+            st = forces_impl(c, x, q, lj, f, ev, ev + 2 * c->n_sys, flags, ahead ? -1 : part,
+                             ahead ? part : -1);
             hipEventRecord(e1, c->stream);
             if (st == NB_OK && hipEventSynchronize(e1) != hipSuccess)
                 st = fail(c, NB_ERR_HIP, "autotune event");
@@ -916,7 +963,7 @@ nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj
         *us = 1e3 * ms[ms.size() / 2];
         return true;
     };
-    const bool fused0 = c->prune_fused;
+    const int prune0 = c->prune_mode;
     for (int W : widths) {
         if (st != NB_OK) break;
         c->exec_mode = kExecStatic;
@@ -932,21 +979,23 @@ nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj
             }
             double us = 0.0;
             if (!time_calls(-1, &us)) break;
-            const nb_exec_config t{W, m, fused0 ? 1 : 0, c->prune_waves, us};
+            const nb_exec_config t{W, m, prune0, c->prune_waves, us};
             if (n < cap) trials[n] = t;
             ++n;
             if (t.us_per_call < win.us_per_call) win = t;
         }
     }
-    // Then, for the chosen shape, a rolling step with the prune fused into the pair kernel
-    // against the prune as its own kernels; the step time decides.
+    // Then, for the chosen shape, a rolling step with the prune fused into the pair kernel,
+    // as its own kernel before it and as its own kernel after it beside the reduction; the
+    // step time decides.
     if (st == NB_OK) {
         c->exec_mode = win.exec_mode;
         st = make_items(c, win.item_width, false);
         if (st == NB_OK) st = finish_items(c);
         double best_step = 1e300;
-        for (int pf = 1; pf >= 0 && st == NB_OK; --pf) {
-            c->prune_fused = pf != 0;
+        for (int pf : {kPruneFused, kPruneSeparate, kPruneAhead}) {
+            if (st != NB_OK) break;
+            c->prune_mode = pf;
             double us = 0.0;
             if (!time_calls(c->p.nstprune > 1 ? 1 : 0, &us)) break;
             const nb_exec_config t{win.item_width, win.exec_mode, pf, c->prune_waves, us};
@@ -967,7 +1016,7 @@ nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj
     if (n_trials) *n_trials = n;
     c->fixed_w = win.item_width;
     c->exec_mode = win.exec_mode;
-    c->prune_fused = win.prune_fused != 0;
+    c->prune_mode = win.prune_fused;
     st = finish_items(c);          // fresh item order and no graphs of the timing calls
     if (st != NB_OK) return st;
     if (best) *best = win;

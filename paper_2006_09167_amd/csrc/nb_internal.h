@@ -28,6 +28,8 @@ constexpr int kExecXcd = 1;                     // blocks renumbered XCD-contigu
 constexpr int kExecQueue = 2;                   // persistent grid, atomic item queue
 constexpr int kExecPersist = 3;                 // persistent grid, fixed balanced schedule
 constexpr int kExecBalanced = 4;                // one run of equal-cost items per wavefront
+// where nb_step prunes (values of nb_exec_config.prune_fused)
+constexpr int kPruneSeparate = 0, kPruneFused = 1, kPruneAhead = 2;
 constexpr int kMaxBalancedWaves = 16384;        // wavefronts of a balanced partition, at most
 constexpr int kMaxItemCost = 64 * 8;            // set outer-mask bits of one item, at most
 

@@ -146,7 +146,8 @@ def test_exec_shape_validation_without_device():
         assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_BALANCED, 1, 0) == _lib.NB_OK
         assert lib.nb_set_exec(h, 16, -1, 1, 0) == _lib.NB_ERR_ARG
         assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_PERSIST, 1, 0) == _lib.NB_OK
-        assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_STATIC, 2, 0) == _lib.NB_ERR_ARG
+        assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_STATIC, 3, 0) == _lib.NB_ERR_ARG
+        assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_STATIC, _lib.NB_PRUNE_AHEAD, 0) == _lib.NB_OK
         assert lib.nb_set_exec(h, 16, _lib.NB_EXEC_QUEUE, 0, 0) == _lib.NB_OK
         cfg = _lib.NbExecConfig()
         assert lib.nb_get_exec(h, ctypes.byref(cfg)) == _lib.NB_OK

@@ -46,7 +46,12 @@ def required_keys(x, k_build, box, slot_of, n_cl, rc, mol):
 
 
 @pytest.mark.timeout(300)
-def test_dual_list_coverage_96k():
+@pytest.mark.parametrize("prune", [True, "ahead"])
+def test_dual_list_coverage_96k(prune):
+    """With the prune fused, step t prunes its part with its own positions, so the inner
+    list after the step is the one it used; with the ahead prune a part is pruned one step
+    before its first use, so the list checked against step t's positions is the one
+    before the step."""
     cfg = systems.CONFIGS["water96k_ewald"]
     s = systems.config_system("water96k_ewald")
     c = concat(s)
@@ -55,6 +60,7 @@ def test_dual_list_coverage_96k():
     g = oracle.grid_spec.build_grid(c["x"], c["boxes"], c["offsets"])
     ctx.grid_build(dev(c["x"]), c["boxes"])
     ctx.pairlist_build()
+    ctx.set_exec(0, "static", prune_fused=prune)
     assert np.array_equal(ctx.get_grid(), g["slot_atom"])
     n_cl = g["slot_atom"].size // 8
     slot_of = g["atom_slot"]
@@ -64,12 +70,17 @@ def test_dual_list_coverage_96k():
     x = c["x"].copy()
     check = {1, 2, 3, 4, 5, 50, 98, 99}
     report = []
+    if prune == "ahead":
+        ctx.step(dev(x), q, lj, 0, energy=False)         # prunes part 1 for step 1
     for t in range(1, cfg["nstlist"]):
         x = (x + rng.normal(0.0, cfg["sigma_step"], x.shape)).astype(np.float32)
+        if prune == "ahead" and t in check:
+            inner = np.unique(keys_of(ctx.get_pairs("inner"), n_cl))   # the list step t uses
         ctx.step(dev(x), q, lj, t, energy=False)
         if t not in check:
             continue
-        inner = np.unique(keys_of(ctx.get_pairs("inner"), n_cl))
+        if prune is True:
+            inner = np.unique(keys_of(ctx.get_pairs("inner"), n_cl))
         outer = np.unique(keys_of(ctx.get_pairs("outer"), n_cl))
         need, n_pairs = required_keys(x, g["k"], c["boxes"][0], slot_of, n_cl,
                                       float(cfg["rc"]), mol)

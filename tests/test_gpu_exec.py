@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_common import (concat, dev, energy_tolerance, make_ctx, oracle_forces_multi,
+from gpu_common import (concat, dev, energy_tolerance, keys_of, make_ctx, oracle_forces_multi,
                         oracle_params, rel_rms)
 from paper_2006_09167_amd import systems
 
@@ -155,8 +155,8 @@ def test_autotune_keeps_fastest_and_stays_exact(sys3k):
     ctx, x = built(c, nstlist=10, nstprune=2, **EWALD)
     q, lj = dev(c["q"]), dev(c["lj"])
     best, trials = ctx.autotune(x, q, lj, energy=True, repeats=3)
-    assert len(trials) == 42
-    n_shape = len(trials) - 2
+    assert len(trials) == 43
+    n_shape = len(trials) - 3
     assert all(t["us_per_call"] > 0 for t in trials)
     shape = min(trials[:n_shape], key=lambda t: t["us_per_call"])
     assert (best["item_width"], best["mode"]) == (shape["item_width"], shape["mode"])
@@ -176,11 +176,14 @@ def test_autotune_keeps_fastest_and_stays_exact(sys3k):
 @pytest.mark.parametrize("mode,fused", [("static", True), ("queue", True), ("persist", True),
                                         ("balanced", True), ("static", False),
                                         ("queue", False), ("persist", False),
-                                        ("balanced", False)])
+                                        ("balanced", False), ("persist", "ahead"),
+                                        ("static", "ahead")])
 def test_graph_step_replays_match_eager(sys3k, mode, fused):
     """nb_step_graph over two list lifetimes with positions updated in place: every replay
     (with eager work and synchronisation in between) equals the eager nb_step bitwise,
-    with the rolling prune fused into the pair kernel or as its own kernel."""
+    with the rolling prune fused into the pair kernel, as its own kernel before it, or as
+    its own kernel after it on a second stream (captured into the graph as a fork and a
+    join)."""
     c = concat(sys3k)
     kw = dict(nstlist=8, nstprune=4, **EWALD)
     ctx_g, _ = built(c, **kw)
@@ -238,3 +241,46 @@ def test_ensemble_uneven_replicas_all_modes():
             assert np.all(np.abs(en - E) <= tol), np.max(np.abs(en - E) / np.abs(E))
         else:
             assert torch.equal(f, ref[0]) and torch.equal(e, ref[1]), mode
+
+
+@pytest.mark.parametrize("mode", ["persist", "xcd"])
+def test_ahead_prune_step_equals_prune_then_forces(sys3k, mode):
+    """The ahead prune (the paper's rolling schedule, Sec. V.E: parts pruned between force
+    computations): step s computes forces with the current inner list, then prunes part
+    (s + 1) mod nstprune with the step-s positions beside the force reduction.  So step s
+    equals prune_rolling(x_{s-1}, s) followed by forces(x_s), bitwise, and the inner list
+    after step s equals the oracle's with part (s + 1) mod nstprune pruned at x_s."""
+    c = concat(sys3k)
+    nst, npr = 20, 4
+    kw = dict(nstlist=nst, nstprune=npr, **EWALD)
+    ctx_a, _ = built(c, **kw)
+    ctx_b, _ = built(c, **kw)
+    ctx_a.set_exec(16, mode, prune_fused="ahead")
+    ctx_b.set_exec(16, mode, prune_fused=False)
+    assert ctx_a.get_exec()["prune_fused"] == "ahead"
+    q, lj = dev(c["q"]), dev(c["lj"])
+    g = oracle.grid_spec.build_grid(c["x"], c["boxes"], c["offsets"])
+    n_cl = g["slot_atom"].size // 8
+    box = c["boxes"][0]
+    outer = keys_of(ctx_a.get_pairs("outer"), n_cl)
+    rng = np.random.default_rng(17)
+    xs = [c["x"].copy()]
+    last = {p: 0 for p in range(npr)}              # positions each part was pruned with
+    for s in range(0, 9):
+        if s > 0:
+            xs.append((xs[-1] + rng.normal(0, 0.004, xs[-1].shape)).astype(np.float32))
+            ctx_b.prune_rolling(dev(xs[s - 1]), s)
+        fa, ea, _ = ctx_a.step(dev(xs[s]), q, lj, s, energy=True)
+        fb, eb, _ = ctx_b.forces(dev(xs[s]), q, lj, energy=True)
+        torch.cuda.synchronize()
+        assert torch.equal(fa, fb) and torch.equal(ea, eb), s
+        last[(s + 1) % npr] = s
+        inner = np.sort(keys_of(ctx_a.get_pairs("inner"), n_cl))
+        ref = []
+        for p in range(npr):
+            w = oracle.rewrap_with(xs[last[p]], g["k"], box)
+            ref.append(oracle.inner_pairs(outer, g["slot_atom"], w, box, EWALD["rinner"], npr, p))
+        assert np.array_equal(inner, np.sort(np.concatenate(ref))), s
+    cc = dict(c)
+    cc["x"] = xs[-1]
+    check_oracle(cc, xs[-1], fa, ea, "ewald", 1.0, 3.12)
