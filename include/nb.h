@@ -201,10 +201,9 @@ nb_status nb_forces(nb_ctx* ctx, const float* x, const float* q, const float* lj
  * separate kernels.  steps_since_build = 0 evaluates forces only.  With prune_fused = 2
  * (ahead, the paper's rolling schedule between force computations, Sec. V.E): nb_forces
  * with the current inner list, then the part (steps_since_build + 1) mod nstprune is
- * pruned with this step's x for the next step, on a second stream beside the force
- * reduction (none when steps_since_build + 1 = nstlist); a part is then used 1 to
- * nstprune steps after its prune instead of 0 to nstprune - 1.  Work queued on the
- * context's stream after the call waits for that prune.  Errors as both calls.
+ * pruned with this step's x for the next step, by blocks of the force reduction's launch
+ * (none when steps_since_build + 1 = nstlist); a part is then used 1 to nstprune steps
+ * after its prune instead of 0 to nstprune - 1.  Errors as both calls.
  */
 nb_status nb_step(nb_ctx* ctx, const float* x, const float* q, const float* lj, float* f,
                   double* energy, double* virial, uint32_t flags, int64_t steps_since_build);

@@ -29,8 +29,8 @@ struct nb_ctx {
     int32_t exec_mode = kExecStatic;
     bool items_balanced = false;  // the current items are the balanced mode's partition
     // nb_step's rolling prune: kPruneFused inside the pair kernel, kPruneSeparate as its own
-    // kernel before it, kPruneAhead as its own kernel after it on a second stream, for the
-    // next step's part with this step's positions
+    // kernel before it, kPruneAhead after it in the force reduction's launch, for the next
+    // step's part with this step's positions
     int prune_mode = kPruneFused;
     int32_t prune_waves = 0;  // wavefronts per item of the separate prune (0 = automatic)
     uint64_t list_gen = 0;    // bumped whenever items or launch shapes change
@@ -44,8 +44,6 @@ struct nb_ctx {
     };
     std::vector<GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;
-    hipStream_t side_stream = nullptr;      // the ahead prune, beside the force reduction
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<int32_t> part_start;
     int32_t h_totals[8] = {};  // host copy of the device totals after the last list change
     nb_stats stats{};
@@ -300,9 +298,6 @@ void nb_destroy(nb_ctx* c) {
                     d.part_items, d.wave_e, d.wave_item, d.cl_xrange};
     drop_graphs(c);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
-    if (c->side_stream) hipStreamDestroy(c->side_stream);
-    if (c->ev_fork) hipEventDestroy(c->ev_fork);
-    if (c->ev_join) hipEventDestroy(c->ev_join);
     for (void* q : ptrs)
         if (q) hipFree(q);
     for (void* q : {(void*)c->census_hist, (void*)c->census_part, (void*)c->census_total,
@@ -709,8 +704,8 @@ namespace {
 constexpr uint32_t kForceFlags = NB_F_ENERGY | NB_F_VIRIAL | NB_F_ACCUMULATE | NB_F_EXCL_CORR;
 
 // prune_part >= 0: re-prune that rolling part with x before the pair kernel (inside it when
-// the prune is fused); ahead_part >= 0: after the pair kernel, re-prune that part with x on
-// the side stream while the force reduction runs, joined before the call returns its work.
+// the prune is fused); ahead_part >= 0: after the pair kernel, re-prune that part with x in
+// the force reduction's launch.
 nb_status forces_impl(nb_ctx* c, const float* x, const float* q, const float* lj, float* f,
                       double* energy, double* virial, uint32_t flags, int prune_part,
                       int ahead_part = -1) {
@@ -740,22 +735,12 @@ nb_status forces_impl(nb_ctx* c, const float* x, const float* q, const float* lj
                                 fused ? prune_part : -1, c->p.nstprune,
                                 radius_sq(c->p.rinner), c->exec_mode, c->stream));
     }
+    // The ahead prune (the paper's rolling schedule: the next step's part is pruned between
+    // force computations, Sec. V.E) runs in the force reduction's launch, beside its blocks.
+    int pi0 = 0, pn = 0;
     if (ahead_part >= 0) {
-        // the paper's rolling schedule: the next step's part is pruned between force
-        // computations (Sec. V.E), here beside the force reduction
-        if (!c->side_stream)
-            NB_HIP(c, hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
-        if (!c->ev_fork) NB_HIP(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-        if (!c->ev_join) NB_HIP(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-        NB_HIP(c, hipEventRecord(c->ev_fork, c->stream));
-        NB_HIP(c, hipStreamWaitEvent(c->side_stream, c->ev_fork, 0));
-        {
-            const int i0 = c->part_start[ahead_part], i1 = c->part_start[ahead_part + 1];
-            TimedSection ts(c, NB_T_PRUNE, c->side_stream);
-            NB_HIP(c, launch_prune(d, d.xq, i0, i1 - i0, radius_sq(c->p.rinner),
-                                   c->prune_waves, c->side_stream));
-        }
-        NB_HIP(c, hipEventRecord(c->ev_join, c->side_stream));
+        pi0 = c->part_start[ahead_part];
+        pn = c->part_start[ahead_part + 1] - pi0;
     }
     // Exclusion corrections (a kernel of their own over the excluded pairs; the pair
     // kernel above is the same with or without them)
@@ -768,9 +753,9 @@ nb_status forces_impl(nb_ctx* c, const float* x, const float* q, const float* lj
                                    c->stream));
     }
     NB_HIP(c, launch_reduce(d, f, (flags & NB_F_ACCUMULATE) != 0, c->n_slots, energy, virial,
-                            flags, c->n_sys, corr ? d.xcf : nullptr, c->stream));
+                            flags, c->n_sys, corr ? d.xcf : nullptr, pi0, pn,
+                            radius_sq(c->p.rinner), c->stream));
     if (corr) NB_HIP(c, launch_excl_energy(d, d.xce, energy, virial, flags, c->n_sys, c->stream));
-    if (ahead_part >= 0) NB_HIP(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
     return NB_OK;
 }
 }  // namespace

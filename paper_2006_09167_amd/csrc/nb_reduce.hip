@@ -5,6 +5,7 @@
 // order; energies, virial and pair counts per system in double precision.
 #include "nb_chunk_sums.h"
 #include "nb_internal.h"
+#include "nb_prune_item.h"
 
 namespace {
 
@@ -126,9 +127,11 @@ __device__ inline void energy_totals(const NbDev& d, double* __restrict__ energy
     }
 }
 
-// Force reduction and the energy reduction in one launch: blocks [0, n_fblk) reduce the
-// forces of four super-clusters each (one wavefront per super-cluster), blocks [n_fblk,
-// n_fblk + n_chunks) sum one energy chunk each; the last energy block to finish (a ticket in
+// The ahead rolling prune, the force reduction and the energy reduction in one launch:
+// blocks [0, n_pblk) prune one item each of the next step's rolling part (prune_item, four
+// wavefronts per item; the reductions read no list data, so the two run side by side),
+// blocks [n_pblk, n_pblk + n_fblk) reduce the forces of four super-clusters each (one
+// wavefront per super-cluster), the blocks after them sum one energy chunk each; the last energy block to finish (a ticket in
 // queue[2], taken after a device-scope fence) adds the chunk partials per system and
 // resets the ticket for the next launch.
 __global__ __launch_bounds__(kRedThreads) void k_reduce_step(NbDev d, float* __restrict__ f,
@@ -136,10 +139,19 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_step(NbDev d, float* __r
                                                              int n_fblk, double* energy,
                                                              double* virial, uint32_t flags,
                                                              int n_sys,
-                                                             const float4* __restrict__ xcf) {
-    static_assert(kRedThreads == kRedWaves * kWave, "one block shape for both parts");
-    if ((int)blockIdx.x >= n_fblk) {
-        const int c = blockIdx.x - n_fblk;
+                                                             const float4* __restrict__ xcf,
+                                                             int n_pblk, int prune_item0,
+                                                             float r2_inner) {
+    static_assert(kRedThreads == kRedWaves * kWave, "one block shape for all parts");
+    if ((int)blockIdx.x < n_pblk) {
+        __shared__ float4 s_xi[kScAtoms];
+        prune_item<kRedWaves>(d.items[d.part_items[prune_item0 + blockIdx.x]], d.entries, d.xq,
+                              d.sc_info, d.sys, r2_inner, s_xi);
+        return;
+    }
+    const int b = (int)blockIdx.x - n_pblk;
+    if (b >= n_fblk) {
+        const int c = b - n_fblk;
         const int4 ch = d.chunks[c];
         chunk_sums(d.epart, d.epart_stride, kEpartStride, ch.y, ch.z,
                    d.cpart + (size_t)c * kChunkVals);
@@ -155,7 +167,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_step(NbDev d, float* __r
         }
         return;
     }
-    const int sc = blockIdx.x * kRedWaves + (int)(threadIdx.x / kWave);
+    const int sc = b * kRedWaves + (int)(threadIdx.x / kWave);
     if (sc >= n_sc) return;
     reduce_sc(sc, d.slot_atom, d.jseg_start, d.jpart, d.sc_istart, d.sc_icount, d.ipart, xcf,
               f, accumulate);
@@ -181,14 +193,17 @@ hipError_t launch_gather(const NbDev& d, const float* x, const float* q, float4*
 
 hipError_t launch_reduce(const NbDev& d, float* f, bool accumulate, int n_slots,
                         double* energy, double* virial, uint32_t flags, int n_sys,
-                        const float4* xcf, hipStream_t s) {
+                        const float4* xcf, int prune_item0, int n_prune, float r2_inner,
+                        hipStream_t s) {
     const int n_sc = n_slots / kScAtoms;
     const int n_fblk = blocks(n_sc, kRedWaves);
     const bool ev = (flags & (NB_F_ENERGY | NB_F_VIRIAL)) && n_sys > 0;
     const int n_eblk = ev ? d.n_chunks : 0;
-    if (n_fblk + n_eblk > 0)
-        hipLaunchKernelGGL(k_reduce_step, dim3(n_fblk + n_eblk), dim3(kRedThreads), 0, s, d, f,
-                           accumulate ? 1 : 0, n_sc, n_fblk, energy, virial, flags, n_sys, xcf);
+    const int n_pblk = n_prune > 0 ? n_prune : 0;
+    if (n_pblk + n_fblk + n_eblk > 0)
+        hipLaunchKernelGGL(k_reduce_step, dim3(n_pblk + n_fblk + n_eblk), dim3(kRedThreads), 0,
+                           s, d, f, accumulate ? 1 : 0, n_sc, n_fblk, energy, virial, flags,
+                           n_sys, xcf, n_pblk, prune_item0, r2_inner);
     if (ev && n_eblk == 0)
         hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kRedThreads), 0, s, d, energy, virial,
                            flags, n_sys);

@@ -181,9 +181,8 @@ def test_autotune_keeps_fastest_and_stays_exact(sys3k):
 def test_graph_step_replays_match_eager(sys3k, mode, fused):
     """nb_step_graph over two list lifetimes with positions updated in place: every replay
     (with eager work and synchronisation in between) equals the eager nb_step bitwise,
-    with the rolling prune fused into the pair kernel, as its own kernel before it, or as
-    its own kernel after it on a second stream (captured into the graph as a fork and a
-    join)."""
+    with the rolling prune fused into the pair kernel, as its own kernel before it, or
+    after it for the next step inside the force reduction's launch."""
     c = concat(sys3k)
     kw = dict(nstlist=8, nstprune=4, **EWALD)
     ctx_g, _ = built(c, **kw)
@@ -247,7 +246,7 @@ def test_ensemble_uneven_replicas_all_modes():
 def test_ahead_prune_step_equals_prune_then_forces(sys3k, mode):
     """The ahead prune (the paper's rolling schedule, Sec. V.E: parts pruned between force
     computations): step s computes forces with the current inner list, then prunes part
-    (s + 1) mod nstprune with the step-s positions beside the force reduction.  So step s
+    (s + 1) mod nstprune with the step-s positions in the force reduction's launch.  So step s
     equals prune_rolling(x_{s-1}, s) followed by forces(x_s), bitwise, and the inner list
     after step s equals the oracle's with part (s + 1) mod nstprune pruned at x_s."""
     c = concat(sys3k)
