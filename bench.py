@@ -102,8 +102,8 @@ def measured_traffic(workload, exec_cfg):
         return None
     shape = "%d entries per item, %s" % (exec_cfg["item_width"],
                                           {"xcd": "XCD-contiguous", "static": "static",
-                                           "queue": "persistent queue",
-                                           "persist": "persistent balanced",
+                                           "queue": "balanced runs + dynamic tail",
+                                           "persist": "persistent rounds",
                                            "balanced": "equal-cost runs"}[exec_cfg["mode"]])
     for line in text.splitlines():
         if line.strip().startswith("HBM traffic") and shape in line:

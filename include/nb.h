@@ -230,22 +230,27 @@ nb_status nb_step_graph(nb_ctx* ctx, const float* x, const float* q, const float
  *   NB_EXEC_STATIC  one wavefront per item in item order;
  *   NB_EXEC_XCD     the same, blocks renumbered so that each of the 8 XCDs (each with its
  *                   own L2) processes one contiguous range of neighbouring items;
- *   NB_EXEC_QUEUE   persistent: one resident grid takes items from an atomic queue,
- *                   most pair work first (long lists not scheduled late, Sec. V.F);
- *   NB_EXEC_PERSIST persistent: one resident grid, items taken in rounds in the same
- *                   most-work-first order, wavefront g taking position g of even rounds
- *                   and position G-1-g of odd rounds (G wavefronts), so the per-wavefront
- *                   totals even out without any atomic;
+ *   NB_EXEC_QUEUE   one resident grid of G wavefronts, each first taking its own run of
+ *                   near-equal estimated cost (as NB_EXEC_BALANCED, over 85 % of the
+ *                   cost), then shorter runs (the rest of the list, G / 2 runs) from one
+ *                   of 64 ticket pools, each shared by wavefronts spread over the device:
+ *                   wavefronts on faster SIMDs take more of the tail, so all end
+ *                   together (list splitting against kernel tails, Sec. V.F, with a
+ *                   dynamic remainder).  Its items differ from the other modes';
+ *   NB_EXEC_PERSIST persistent: one resident grid, items taken in rounds in most-work-first
+ *                   order, wavefront g taking position g of even rounds and position G-1-g
+ *                   of odd rounds (G wavefronts), so the per-wavefront totals even out
+ *                   without any atomic;
  *   NB_EXEC_BALANCED one resident grid of G wavefronts (those of the energy flavor that fit
  *                   the device at once), the list cut into G contiguous runs of near-equal
- *                   cost (an entry costs 1 + 2 x the set bits of its outer mask), each run
- *                   split at super-cluster boundaries and into pieces of at most
- *                   item_width entries: every wavefront gets the same share of the work
- *                   (list splitting against kernel tails, Sec. V.F).  Its items differ from
- *                   the other modes', so results differ from theirs in the last bits.
- * Results do not depend on exec_mode among the first four (each item writes its own
- * partial sums); they depend on the items only through the order of the final per-atom
- * sums (a few ulp).
+ *                   cost (an entry costs 2 + the set bits of its inner mask as built), each
+ *                   run split at super-cluster boundaries and into pieces of at most
+ *                   item_width entries: every wavefront gets the same estimated share of
+ *                   the work (list splitting against kernel tails, Sec. V.F).  Its items
+ *                   differ from the other modes'.
+ * Results do not depend on exec_mode among static, XCD and persist (each item writes its
+ * own partial sums, whichever wavefront computes it), nor between launches of one mode;
+ * they depend on the items only through the order of the final per-atom sums (a few ulp).
  */
 enum { NB_EXEC_STATIC = 0, NB_EXEC_XCD = 1, NB_EXEC_QUEUE = 2, NB_EXEC_PERSIST = 3,
        NB_EXEC_BALANCED = 4 };

@@ -305,17 +305,32 @@ __device__ inline int xcd_block(int b, int g) {
 //   kExecStatic  one wavefront per item, item = 4 block + wave (rolling-part major: the
 //                items processed together are four super-clusters apart);
 //   kExecXcd     the same with the XCD-contiguous block numbering above;
-//   kExecQueue   persistent: a grid that fills the device once; wavefronts take items
-//                from an atomic counter in the order given by `order` (most pair work
-//                first), until the counter passes n_items.  queue[0] is the counter,
-//                queue[1] counts finished wavefronts; the last one resets both to zero,
-//                so the next launch needs no clearing pass (and a captured graph none);
-//   kExecPersist persistent: the same grid and order, without atomics: rounds of G
-//                items (G wavefronts), wavefront g taking position g of even rounds and
-//                G - 1 - g of odd ones, so the most expensive item of one round goes
-//                with the cheapest of the next.
+//   kExecQueue   one resident grid; wavefront g first takes its own run of items
+//                (wave_item[g] .. wave_item[g + 1], near-equal estimated cost, most of
+//                the work), then shorter runs (the n_dyn runs after the n_waves own ones)
+//                from ticket pool g mod kQueuePools, which holds runs p, p + kQueuePools,
+//                ... and is shared by wavefronts spread over the device: those that end
+//                their own run early take more.  A ticket is one atomic add by lane 0,
+//                after a read of the counter, so a finished pool takes no more atomics
+//                (same-address atomics serialise: waves of the whole grid taking turns
+//                on the last open pools cost more than the balance they buy, measured).
+//                The last block to finish (counted per group of blocks, then over the
+//                groups) sets every counter back to zero, so the next launch needs no
+//                clearing pass (and a captured graph none);
+//   kExecPersist persistent: a grid that fills the device once, rounds of G items (G
+//                wavefronts) in the order given by `order` (most pair work first),
+//                wavefront g taking position g of even rounds and G - 1 - g of odd ones,
+//                so the most expensive item of one round goes with the cheapest of the
+//                next;
+//   kExecBalanced wavefront g takes its own run of items only (no dynamic tail).
+// Scalar registers are capped at 96 per wavefront: at the compiler's own choice (106 in the
+// energy flavor) a SIMD holds six wavefronts of this kernel although its vector registers
+// leave room for seven (measured from the wavefronts' start times; the occupancy query
+// still reports seven); with the cap the seventh is resident and a dozen scalars live in
+// vector-register lanes instead.
 template <int COUL, bool ENERGY, bool VIRIAL, bool PRUNE>
-__global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIRIAL ? 3 : 4))) void k_nb_fwd(
+__global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIRIAL ? 3 : 4)))
+__attribute__((amdgpu_num_sgpr(96))) void k_nb_fwd(
     const NbItem* __restrict__ items, NbEntry* __restrict__ entries,
     const uint64_t* __restrict__ excl_rows, const float4* __restrict__ xq,
     const int32_t* __restrict__ type_slot, const NbScInfo* __restrict__ sc_info,
@@ -323,7 +338,7 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
     float4* __restrict__ ipart, double* __restrict__ epart, int epart_stride, NbKParams kp,
     int n_items, int prune_part, int nstprune, float r2_inner, int mode,
     const int32_t* __restrict__ order, int32_t* __restrict__ queue,
-    const int32_t* __restrict__ wave_item, int n_waves) {
+    const int32_t* __restrict__ wave_item, int n_waves, int n_dyn) {
     extern __shared__ float4 s_lj[];
     __shared__ float4 s_x_all[kFwdWaves][kScAtoms];    // per wave: (x, y, z, K q) by slot
     __shared__ int s_t_all[kFwdWaves][kScAtoms];       // per wave: type * T by slot
@@ -350,21 +365,57 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(VIR
         return;
     }
     if (mode == kExecQueue) {
-        // Tickets are taken in converged code: every lane issues the atomic, lane 0 adding
-        // one and the others zero, and lane 0's result is broadcast.  (A fetch inside a
-        // lane-0-only branch makes the loop exit divergent: the other lanes would never
-        // see the end of the queue.)  The exit test below is a uniform scalar branch.
-        const int one = (lane == 0) ? 1 : 0;
+        const int g = (int)blockIdx.x * kFwdWaves + wave;
+        const int32_t* dyn_item = wave_item + n_waves;   // dynamic run k: items k .. k + 1
+        int32_t* tickets = queue + kQueueTickets;
+        // the wavefront's pool: its runs are p, p + kQueuePools, ... below n_dyn
+        const int p = g % kQueuePools;
+        const int runs_p = (n_dyn > p) ? (n_dyn - p + kQueuePools - 1) / kQueuePools : 0;
+        int32_t* ticket = queue + kQueueTickets + p * kPoolStride;
+        int i = (g < n_waves) ? wave_item[g] : 0, i_end = (g < n_waves) ? wave_item[g + 1] : 0;
         for (;;) {
-            const int slot = __builtin_amdgcn_readfirstlane(atomicAdd(queue, one));
-            if (slot >= n_items) break;
-            fwd_item<COUL, ENERGY, VIRIAL, PRUNE>(order[slot], NB_ITEM_ARGS);
+            if (i < i_end) {            // one call site: the item's registers as in other modes
+                fwd_item<COUL, ENERGY, VIRIAL, PRUNE>(i, NB_ITEM_ARGS);
+                ++i;
+                continue;
+            }
+            // read the counter first: a pool that is done takes no more atomics
+            if (__builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                    ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >= runs_p)
+                break;
+            int t = 0;
+            if (lane == 0) t = atomicAdd(ticket, 1);
+            t = __builtin_amdgcn_readlane(t, 0);
+            if (t >= runs_p) break;
+            const int k = p + kQueuePools * t;
+            i = dyn_item[k];
+            i_end = dyn_item[k + 1];
         }
-        const int waves = (int)gridDim.x * kFwdWaves;
-        const int done = __builtin_amdgcn_readfirstlane(atomicAdd(queue + 1, one));
-        if (done == waves - 1 && lane == 0) {
-            atomicExch(queue, 0);
-            atomicExch(queue + 1, 0);
+        // every wavefront of the block has taken its last ticket: count the block done
+        __shared__ int s_last;
+        __syncthreads();
+        // (no fences: an agent-scope fence writes back and invalidates the XCD's whole L2,
+        // costing tens of microseconds over the grid; the counters are only ever touched
+        // by atomics, which take effect in order at one coherent point)
+        if (threadIdx.x == 0) {
+            const int grp = (int)blockIdx.x % kQueuePools;
+            const int grp_blocks = ((int)gridDim.x - grp + kQueuePools - 1) / kQueuePools;
+            const int groups = min((int)gridDim.x, kQueuePools);
+            s_last = atomicAdd(queue + kQueueDone + grp * kPoolStride, 1) == grp_blocks - 1 &&
+                     atomicAdd(queue + kQueueDoneAll, 1) == groups - 1;
+        }
+        __syncthreads();
+        if (s_last) {
+            // the last block: no other wavefront of this launch touches the counters now
+            for (int k = threadIdx.x; k < kQueuePools; k += blockDim.x) {
+                __hip_atomic_store(tickets + k * kPoolStride, 0, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(queue + kQueueDone + k * kPoolStride, 0, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (threadIdx.x == 0)
+                __hip_atomic_store(queue + kQueueDoneAll, 0, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
         return;
     }
@@ -416,13 +467,14 @@ void launch_fwd_t(const NbDev& d, const NbKParams& kp, const float* lj, int n_it
                   int part, int nstprune, float r2_inner, int mode, hipStream_t s) {
     const size_t lds = sizeof(float4) * (size_t)kp.n_types * kp.n_types;
     int grid = blocks(n_items, kFwdWaves);
-    if (mode == kExecQueue || mode == kExecPersist)   // one resident grid over the device
+    if (mode == kExecPersist)   // one resident grid over the device
         grid = std::min(grid, fwd_blocks_per_cu<COUL, E, V, P>(lds) * std::max(d.n_cu, 1));
-    if (mode == kExecBalanced) grid = blocks(d.n_waves, kFwdWaves);
+    if (mode == kExecBalanced || mode == kExecQueue) grid = blocks(d.n_waves, kFwdWaves);
     hipLaunchKernelGGL((k_nb_fwd<COUL, E, V, P>), dim3(grid), dim3(kFwdThreads), lds, s,
                        d.items, d.entries, d.excl_rows, d.xq, d.type_slot, d.sc_info, d.sys,
                        lj, d.jpart, d.ipart, d.epart, d.epart_stride, kp, n_items, part,
-                       nstprune, r2_inner, mode, d.item_order, d.queue, d.wave_item, d.n_waves);
+                       nstprune, r2_inner, mode, d.item_order, d.queue, d.wave_item, d.n_waves,
+                       d.n_dyn);
 }
 
 template <int COUL, bool P>

@@ -27,7 +27,7 @@ struct nb_ctx {
     int32_t item_w = 0;       // entries per work item of the current list
     int32_t fixed_w = 0;      // item width chosen by nb_set_exec / nb_autotune (0 = rule)
     int32_t exec_mode = kExecStatic;
-    bool items_balanced = false;  // the current items are the balanced mode's partition
+    int items_kind = 0;           // partition of the current items (items_kind_of)
     // nb_step's rolling prune: kPruneFused inside the pair kernel, kPruneSeparate as its own
     // kernel before it, kPruneAhead after it in the force reduction's launch, for the next
     // step's part with this step's positions
@@ -160,10 +160,10 @@ nb_status ensure_device(nb_ctx* c) {
     NB_HIP(c, dev_alloc(d.sys, c->n_sys));
     NB_HIP(c, dev_alloc(d.sys_sc_start, c->n_sys + 1));
     NB_HIP(c, dev_alloc(d.part_start, c->p.nstprune + 1));
-    NB_HIP(c, dev_alloc(d.queue, 4));
+    NB_HIP(c, dev_alloc(d.queue, kQueueWords));
     NB_HIP(c, dev_alloc(d.wave_e, kMaxBalancedWaves + 1));
     NB_HIP(c, dev_alloc(d.wave_item, kMaxBalancedWaves + 1));
-    NB_HIP(c, launch_fill(d.queue, 4, 0, c->stream));
+    NB_HIP(c, launch_fill(d.queue, kQueueWords, 0, c->stream));
     int n_cu = 0;
     NB_HIP(c, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
     d.n_cu = n_cu;
@@ -496,12 +496,23 @@ int item_width(const nb_ctx* c) {
                                                                target_items));
 }
 
+// Item partition an execution mode runs on: 0 per super-cluster, 1 the balanced runs,
+// 2 the queue mode's runs with their dynamic tail.
+int items_kind_of(int exec_mode) {
+    return exec_mode == kExecBalanced ? 1 : exec_mode == kExecQueue ? 2 : 0;
+}
+
 // Wavefronts of the balanced partition: those of the pair kernel's energy flavor resident
-// on the whole device at once.
-nb_status balanced_waves(nb_ctx* c, int* waves) {
+// on the whole device at once; in the queue mode also its dynamic runs (half as many,
+// kQueueDynPerTwoWaves per two wavefronts), the two together within kMaxBalancedWaves.
+nb_status balanced_waves(nb_ctx* c, int* waves, int* dyn) {
     int per_cu = 0;
     NB_HIP(c, prepare_forces(c->p.coulomb, NB_F_ENERGY, false, c->p.n_types, &per_cu));
-    *waves = std::min(kMaxBalancedWaves, std::max(1, per_cu) * std::max(1, c->d.n_cu));
+    const bool queue = c->exec_mode == kExecQueue;
+    const int limit = queue ? kMaxBalancedWaves * 2 / (2 + kQueueDynPerTwoWaves)
+                            : kMaxBalancedWaves;
+    *waves = std::min(limit, std::max(1, per_cu) * std::max(1, c->d.n_cu));
+    *dyn = queue ? *waves * kQueueDynPerTwoWaves / 2 : 0;
     return NB_OK;
 }
 
@@ -510,13 +521,14 @@ nb_status balanced_waves(nb_ctx* c, int* waves) {
 // the entries out of the search scratch.
 nb_status make_items(nb_ctx* c, int W, bool copy_entries) {
     NbDev& d = c->d;
-    int waves = 0;
-    if (c->exec_mode == kExecBalanced) {
-        nb_status st = balanced_waves(c, &waves);
+    int waves = 0, dyn = 0;
+    if (c->exec_mode == kExecBalanced || c->exec_mode == kExecQueue) {
+        nb_status st = balanced_waves(c, &waves, &dyn);
         if (st != NB_OK) return st;
     }
-    // per super-cluster ceil(n / W) items, plus at most one more per wavefront boundary
-    const size_t item_cap = (size_t)c->n_sc + (size_t)(c->n_entries / W) + 1 + (size_t)waves;
+    // per super-cluster ceil(n / W) items, plus at most one more per run boundary
+    const size_t item_cap =
+        (size_t)c->n_sc + (size_t)(c->n_entries / W) + 1 + (size_t)waves + (size_t)dyn;
     if (item_cap > c->a_items || !d.items) {
         const size_t ni = item_cap + item_cap / 8 + 64;
         NB_HIP(c, dev_alloc(d.items, ni));
@@ -530,10 +542,11 @@ nb_status make_items(nb_ctx* c, int W, bool copy_entries) {
         c->a_items = ni;
     }
     d.n_waves = waves;
+    d.n_dyn = dyn;
     NB_HIP(c, launch_make_items(d, c->n_sc, c->cap, W, c->p.nstprune, copy_entries, waves,
-                                c->stream));
+                                dyn, kQueueStaticPermille, c->stream));
     c->item_w = W;
-    c->items_balanced = waves > 0;
+    c->items_kind = items_kind_of(c->exec_mode);
     return NB_OK;
 }
 
@@ -878,7 +891,7 @@ nb_status nb_set_exec(nb_ctx* c, int32_t width, int32_t exec_mode, int32_t prune
         drop_graphs(c);
     }
     if (c->has_list && (item_width(c) != c->item_w ||
-                        c->items_balanced != (exec_mode == kExecBalanced))) {
+                        c->items_kind != items_kind_of(exec_mode))) {
         nb_status st = make_items(c, item_width(c), false);
         if (st != NB_OK) return st;
         return finish_items(c);
@@ -957,7 +970,7 @@ nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj
         for (int m : modes) {
             if (st != NB_OK) break;
             c->exec_mode = m;
-            if (m == kExecBalanced) {          // items of its own: equal-cost runs per wavefront
+            if (c->items_kind != items_kind_of(m)) {   // the balanced and queue runs
                 st = make_items(c, W, false);
                 if (st == NB_OK) st = finish_items(c);
                 if (st != NB_OK) break;

@@ -25,12 +25,24 @@ constexpr int kXcds = 8;                        // accelerator complex dies of a
 // Execution modes of the pair kernel (values of NB_EXEC_* in nb.h).
 constexpr int kExecStatic = 0;                  // one wavefront per item, in item order
 constexpr int kExecXcd = 1;                     // blocks renumbered XCD-contiguously
-constexpr int kExecQueue = 2;                   // persistent grid, atomic item queue
+constexpr int kExecQueue = 2;                   // balanced runs, then a dynamic tail
 constexpr int kExecPersist = 3;                 // persistent grid, fixed balanced schedule
 constexpr int kExecBalanced = 4;                // one run of equal-cost items per wavefront
 // where nb_step prunes (values of nb_exec_config.prune_fused)
 constexpr int kPruneSeparate = 0, kPruneFused = 1, kPruneAhead = 2;
-constexpr int kMaxBalancedWaves = 16384;        // wavefronts of a balanced partition, at most
+constexpr int kMaxBalancedWaves = 16384;        // runs of a balanced partition, at most
+// Queue mode: the wavefronts' own runs carry this share of the estimated cost (per mille),
+// the rest is cut into kQueueDynPerTwoWaves x (wavefronts) / 2 shorter runs taken from
+// kQueuePools ticket pools (pool p: runs p, p + kQueuePools, ...); each counter on its own
+// 128-byte line (same-address atomics serialise at about 12 ns each on this GPU).
+constexpr int kQueueStaticPermille = 650;
+constexpr int kQueueDynPerTwoWaves = 2;
+constexpr int kQueuePools = 64;                 // pool of wavefront g: g mod kQueuePools
+constexpr int kPoolStride = 32;                 // int32 words per counter
+constexpr int kQueueTickets = kPoolStride;      // queue[] offsets: ticket counters,
+constexpr int kQueueDone = kQueueTickets + kQueuePools * kPoolStride;   // finished blocks
+constexpr int kQueueDoneAll = kQueueDone + kQueuePools * kPoolStride;   // per group, groups
+constexpr int kQueueWords = kQueueDoneAll + kPoolStride;
 constexpr int kMaxItemCost = 64 * 8;            // set outer-mask bits of one item, at most
 
 // One j-entry of a super-cluster's joint list (16 bytes, loaded with one scalar load).
@@ -116,10 +128,13 @@ hipError_t launch_search(const NbDev& d, int n_sc, int cap, float r2_outer, floa
 hipError_t launch_search_record(const NbDev& d, int n_sc, float r2_outer, float rlist,
                                 int rec_cap, hipStream_t s);
 hipError_t launch_scan_entries(const NbDev& d, int n_sc, hipStream_t s);
-// Work items of at most w entries; balanced_waves > 0: the balanced mode's partition of
-// the list into that many equal-cost runs (wave_e, wave_item), else per super-cluster.
+// Work items of at most w entries; balanced_waves > 0: the balanced and queue modes'
+// partition of the list into that many equal-cost runs (wave_e, wave_item), the first
+// static_permille / 1000 of the cost when dynamic_runs > 0, whose runs hold the rest;
+// else per super-cluster.
 hipError_t launch_make_items(const NbDev& d, int n_sc, int cap, int w, int nstprune,
-                             bool copy_entries, int balanced_waves, hipStream_t s);
+                             bool copy_entries, int balanced_waves, int dynamic_runs,
+                             int static_permille, hipStream_t s);
 hipError_t launch_item_order(const NbDev& d, int n_items, hipStream_t s);
 hipError_t launch_list_finish(const NbDev& d, int n_sc, int64_t n_entries, int n_cl,
                               hipStream_t s);
@@ -245,14 +260,16 @@ struct NbDev {
     NbItem* items = nullptr;           // [item_cap]
     int32_t* item_cost = nullptr;      // [item_cap] set outer-mask bits per item
     int32_t* item_order = nullptr;     // [item_cap] items by decreasing cost (queue order)
-    int32_t* queue = nullptr;          // [4] item counter, finished wavefronts, finished
-                                       //     energy-chunk blocks, unused (kept zero between
-                                       //     launches by the kernels themselves)
+    int32_t* queue = nullptr;          // [kQueueWords] unused, unused, finished
+                                       //     energy-chunk blocks, finished backward chunks,
+                                       //     then the queue mode's pool counters (kept zero
+                                       //     between launches by the kernels themselves)
     int32_t* part_start = nullptr;     // [nstprune+1] ranges of part_items per rolling part
     int32_t* part_items = nullptr;     // [item_cap] items grouped by rolling part
-    int32_t* wave_e = nullptr;         // [kMaxBalancedWaves+1] first entry per wavefront
-    int32_t* wave_item = nullptr;      // [kMaxBalancedWaves+1] first item per wavefront
+    int32_t* wave_e = nullptr;         // [kMaxBalancedWaves+1] first entry per run
+    int32_t* wave_item = nullptr;      // [kMaxBalancedWaves+1] first item per run
     int32_t n_waves = 0;               // wavefronts of the balanced partition (0: none)
+    int32_t n_dyn = 0;                 // dynamic runs after them (queue mode)
     uint64_t* excl_rows = nullptr;     // [entry_cap][8]
     int32_t* jseg_count = nullptr;     // [8 n_sc_max]
     int32_t* jseg_start = nullptr;     // [8 n_sc_max + 1]

@@ -345,35 +345,42 @@ __global__ __launch_bounds__(kWave) void k_compact(NbDev d, int cap, int w, int 
     }
 }
 
-// Work items for the balanced execution mode: the entries (in super-cluster order) are
-// dealt to P wavefronts in contiguous runs of near-equal cost, an entry costing 1 + 2 x
-// (set bits of its outer mask) (a fixed part for its j-cluster load, partial store and
-// reductions, and its possible 8 x 8 blocks), so that all wavefronts of one resident grid
-// end together (the paper's list splitting against kernel tails, Sec. V.F, taken to its
-// end: no wavefront waits for another's longer list).  Items are the pieces of a
-// super-cluster's list inside one wavefront's run, cut further into near-equal pieces of
-// at most w entries; wave_item[g] .. wave_item[g + 1] are the items of wavefront g, in
-// super-cluster order (so item index = rank).  part_items lists the items of each rolling
-// part together (part p: super-clusters p, p + nparts, ...) for the separate prune.
-// One block; prefix (>= E + 1 ints) and ppos (>= n_sc ints) are scratch.
+// Work items for the balanced and queue execution modes: the entries (in super-cluster
+// order) are dealt in contiguous runs of near-equal cost, an entry costing 2 + (set bits of
+// its inner mask) (its j-cluster load, shift, partial store and reductions weigh about two
+// 8 x 8 blocks in measured wavefront times), to P wavefronts (the paper's list splitting
+// against kernel tails, Sec. V.F, taken to its end: no wavefront waits for another's longer
+// list).  With D > 0 (queue mode) the P runs cover the first fs_permille / 1000 of the
+// cost and the rest is cut into D shorter runs that wavefronts take from ticket pools once
+// their own run is done, which absorbs both the cost model's error and the speed
+// differences between SIMDs.  Items are the pieces of a super-cluster's list inside one
+// run, cut further into near-equal pieces of at most w entries; wave_item[g] ..
+// wave_item[g + 1] are the items of run g (g < P: wavefront g's own, P <= g < P + D:
+// dynamic run g - P), in super-cluster order (so item index = rank).  part_items lists the
+// items of each rolling part together (part p: super-clusters p, p + nparts, ...) for the
+// separate prune.  One block; prefix (>= E + 1 ints) and ppos (>= n_sc ints) are scratch.
 __global__ __launch_bounds__(kScanThreads) void k_balanced_items(NbDev d, int n_sc, int w,
-                                                                 int nparts, int P,
+                                                                 int nparts, int P, int D,
+                                                                 int fs_permille,
                                                                  int32_t* prefix,
                                                                  int32_t* ppos) {
     const int E = d.totals[0];
     const int C = block_scan(E, [&](int i) {
-        return 1 + 2 * __builtin_popcount((d.entries[i].meta >> 8) & 0xffu);
+        return 2 + __builtin_popcount((d.entries[i].meta >> 16) & 0xffu);
     }, prefix);
     __syncthreads();
-    for (int g = threadIdx.x; g <= P; g += blockDim.x) {
-        const int64_t target = ((int64_t)g * C + P - 1) / P;        // ceil(g C / P)
+    const int R = P + D;                                             // runs
+    const int64_t Cs = (D > 0) ? (int64_t)C * fs_permille / 1000 : C;   // cost of the P runs
+    for (int g = threadIdx.x; g <= R; g += blockDim.x) {
+        const int64_t target = (g <= P) ? ((int64_t)g * Cs + P - 1) / P      // ceil(g Cs / P)
+                                        : Cs + ((int64_t)(g - P) * (C - Cs) + D - 1) / D;
         int lo = 0, hi = E;                                          // first prefix >= target
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
             if (prefix[mid] < target) lo = mid + 1;
             else hi = mid;
         }
-        d.wave_e[g] = (g == P) ? E : lo;
+        d.wave_e[g] = (g == R) ? E : lo;
     }
     __syncthreads();
     // pieces of super-cluster sc: its entries cut at the wavefront boundaries inside them,
@@ -381,7 +388,7 @@ __global__ __launch_bounds__(kScanThreads) void k_balanced_items(NbDev d, int n_
     // within the super-cluster) for each item in order
     auto for_items = [&](int sc, auto&& f) {
         const int a = d.sc_estart[sc], b = a + d.sc_ecount[sc];
-        int lo = 0, hi = P + 1;                      // first boundary above a
+        int lo = 0, hi = R + 1;                      // first boundary above a
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
             if (d.wave_e[mid] <= a) lo = mid + 1;
@@ -389,7 +396,7 @@ __global__ __launch_bounds__(kScanThreads) void k_balanced_items(NbDev d, int n_
         }
         int k = 0;
         for (int s0 = a, g = lo; s0 < b; ++g) {
-            const int t = (g <= P && d.wave_e[g] < b) ? d.wave_e[g] : b;
+            const int t = (g <= R && d.wave_e[g] < b) ? d.wave_e[g] : b;
             const int len = t - s0, ni = (len + w - 1) / w;
             for (int j = 0; j < ni; ++j) {
                 const int x0 = (int)((int64_t)j * len / ni), x1 = (int)((int64_t)(j + 1) * len / ni);
@@ -439,8 +446,8 @@ __global__ __launch_bounds__(kScanThreads) void k_balanced_items(NbDev d, int n_
         });
     }
     __syncthreads();
-    for (int g = threadIdx.x; g <= P; g += blockDim.x) {
-        // first item starting at or after the wavefront's first entry
+    for (int g = threadIdx.x; g <= R; g += blockDim.x) {
+        // first item starting at or after the run's first entry
         int lo = 0, hi = total;
         const int e = d.wave_e[g];
         while (lo < hi) {
@@ -448,7 +455,7 @@ __global__ __launch_bounds__(kScanThreads) void k_balanced_items(NbDev d, int n_
             if (d.items[mid].e0 < e) lo = mid + 1;
             else hi = mid;
         }
-        d.wave_item[g] = (g == P) ? total : lo;
+        d.wave_item[g] = (g == R) ? total : lo;
     }
     if (threadIdx.x == 0) {
         int before = 0;
@@ -650,13 +657,15 @@ hipError_t launch_scan_entries(const NbDev& d, int n_sc, hipStream_t s) {
 }
 
 hipError_t launch_make_items(const NbDev& d, int n_sc, int cap, int w, int nstprune,
-                             bool copy_entries, int balanced_waves, hipStream_t s) {
+                             bool copy_entries, int balanced_waves, int dynamic_runs,
+                             int static_permille, hipStream_t s) {
     if (balanced_waves > 0) {
         if (copy_entries && n_sc > 0)
             hipLaunchKernelGGL(k_compact, dim3(n_sc), dim3(kWave), 0, s, d, cap, w, 1, 0);
         // jseg_entries (entry_cap >= E + 1) and jseg_fill (>= n_sc) serve as scratch
         hipLaunchKernelGGL(k_balanced_items, dim3(1), dim3(kScanThreads), 0, s, d, n_sc, w,
-                           nstprune, balanced_waves, d.jseg_entries, d.jseg_fill);
+                           nstprune, balanced_waves, dynamic_runs, static_permille,
+                           d.jseg_entries, d.jseg_fill);
         return hipGetLastError();
     }
     // jseg_fill doubles as the scratch of the permuted scan (n_sc + 1 <= 8 n_sc_max).

@@ -155,13 +155,19 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_step(NbDev d, float* __r
         const int4 ch = d.chunks[c];
         chunk_sums(d.epart, d.epart_stride, kEpartStride, ch.y, ch.z,
                    d.cpart + (size_t)c * kChunkVals);
+        // One release fence per block, by the thread that takes the ticket: the barrier
+        // orders the block's partial stores before it.  (A device-scope fence writes the
+        // XCD's L2 back; one per wavefront cost about 2 us per launch at 96k atoms.)
         __shared__ int s_last;
-        __threadfence();       // this block's chunk partials before its ticket
         __syncthreads();
-        if (threadIdx.x == 0) s_last = (atomicAdd(d.queue + 2, 1) == d.n_chunks - 1);
+        if (threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            s_last = (atomicAdd(d.queue + 2, 1) == d.n_chunks - 1);
+        }
         __syncthreads();
         if (s_last) {
-            __threadfence();   // every other block's partials after their tickets
+            // every other block's partials, released before their tickets
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             energy_totals(d, energy, virial, flags, n_sys);
             if (threadIdx.x == 0) atomicExch(d.queue + 2, 0);
         }

@@ -1,5 +1,5 @@
-"""Execution shapes of the pair kernel (static, XCD-contiguous, persistent queue,
-persistent balanced schedule, equal-cost runs per wavefront), item widths, the autotuner, the graph-replayed step and an ensemble of uneven replicas in one
+"""Execution shapes of the pair kernel (static, XCD-contiguous, balanced runs with a
+dynamic tail from ticket pools, persistent rounds, equal-cost runs per wavefront), item widths, the autotuner, the graph-replayed step and an ensemble of uneven replicas in one
 context, through the C ABI on an MI355X, against the FP64 oracle."""
 import numpy as np
 import pytest
@@ -35,31 +35,47 @@ def check_oracle(c, x_np, f, e, coul, rc, beta=0.0, strict=True):
 
 @pytest.mark.parametrize("width", [8, 32, 64])
 def test_modes_bitwise_equal_and_queue_relaunches(sys3k, width):
-    """For one item width every mode gives bitwise the same forces, energies and virial
-    (each item writes its own partials); the persistent queue resets itself between
-    launches, so consecutive launches repeat the result."""
+    """For one item width the modes on the per-super-cluster items give bitwise the same
+    forces, energies and virial (each item writes its own partials, whichever wavefront
+    computes it).  The queue mode runs on items of its own (balanced runs plus the dynamic
+    tail): its launches repeat one another bitwise, which also shows that its ticket pools
+    are back at zero after every launch (a pool left behind would skip runs), and it is
+    within the oracle bars."""
     c = concat(sys3k)
     ctx, x = built(c, nstlist=10, nstprune=4, **EWALD)
     q, lj = dev(c["q"]), dev(c["lj"])
     ref = None
-    for mode in ("static", "xcd", "queue", "queue", "queue", "persist", "persist", "static"):
+    qref = None
+    for mode in ("static", "xcd", "queue", "queue", "queue", "persist", "persist", "queue",
+                 "static"):
         ctx.set_exec(width, mode)
         assert ctx.get_exec() == {"item_width": width, "mode": mode, "prune_fused": True,
                                   "prune_waves": 0}
         out = ctx.forces(x, q, lj, energy=True, virial=True)
         torch.cuda.synchronize()
-        if ref is None:
+        if mode == "queue":
+            if qref is None:
+                qref = [t.clone() for t in out]
+                check_oracle(c, c["x"], out[0], out[1], "ewald", 1.0, 3.12)
+            else:
+                for a, b in zip(qref, out):
+                    assert torch.equal(a, b), mode
+        elif ref is None:
             ref = [t.clone() for t in out]
             check_oracle(c, c["x"], out[0], out[1], "ewald", 1.0, 3.12)
         else:
             for a, b in zip(ref, out):
                 assert torch.equal(a, b), mode
+    # rounding only between the two partitions
+    assert rel_rms(qref[0].cpu().numpy(), ref[0].cpu().numpy()) <= 1e-6
+    assert torch.allclose(qref[1], ref[1], rtol=1e-9, atol=0)
 
 
 @pytest.mark.parametrize("mode", ["queue", "persist"])
 def test_fused_step_in_persistent_modes_matches_static(sys3k, mode):
     """nb_step (prune fused into the pair kernel) under the persistent modes: same inner
-    lists and bitwise the same outputs as the static mode over a rolling cycle."""
+    lists as the static mode over a rolling cycle, and bitwise the same outputs (persist,
+    same items) or the same to FP32 summation-order rounding (queue, items of its own)."""
     c = concat(sys3k)
     kw = dict(nstlist=20, nstprune=4, **EWALD)
     ctx_a, _ = built(c, **kw)
@@ -73,8 +89,15 @@ def test_fused_step_in_persistent_modes_matches_static(sys3k, mode):
         xt = dev(x)
         fa, ea, va = ctx_a.step(xt, q, lj, t, energy=True, virial=True)
         fb, eb, vb = ctx_b.step(xt, q, lj, t, energy=True, virial=True)
-        assert torch.equal(fa, fb) and torch.equal(ea, eb) and torch.equal(va, vb), t
-    assert np.array_equal(ctx_a.get_pairs("inner"), ctx_b.get_pairs("inner"))
+        if mode == "persist":
+            assert torch.equal(fa, fb) and torch.equal(ea, eb) and torch.equal(va, vb), t
+        else:
+            torch.cuda.synchronize()
+            assert rel_rms(fb.cpu().numpy(), fa.cpu().numpy()) <= 1e-6, t
+            assert torch.allclose(eb, ea, rtol=1e-9, atol=0), t
+            assert torch.allclose(vb, va, rtol=1e-6, atol=1e-6 * va.abs().max().item()), t
+        assert np.array_equal(ctx_a.get_pairs("inner"), ctx_b.get_pairs("inner")), t
+    check_oracle(c, x, fb, eb, "ewald", 1.0, 3.12)
 
 
 @pytest.mark.parametrize("mode", ["xcd", "queue", "persist", "balanced"])
@@ -232,7 +255,7 @@ def test_ensemble_uneven_replicas_all_modes():
         ctx.set_exec(0, mode)
         f, e, _ = ctx.forces(x, q, lj)
         torch.cuda.synchronize()
-        if ref is None or mode == "balanced":      # balanced: items of its own
+        if ref is None or mode in ("balanced", "queue"):      # items of their own
             if ref is None:
                 ref = (f.clone(), e.clone())
             assert rel_rms(f.cpu().numpy(), F) <= 1e-5
