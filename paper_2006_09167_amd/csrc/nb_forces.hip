@@ -338,7 +338,7 @@ __attribute__((amdgpu_num_sgpr(96))) void k_nb_fwd(
     float4* __restrict__ ipart, double* __restrict__ epart, int epart_stride, NbKParams kp,
     int n_items, int prune_part, int nstprune, float r2_inner, int mode,
     const int32_t* __restrict__ order, int32_t* __restrict__ queue,
-    const int32_t* __restrict__ wave_item, int n_waves, int n_dyn) {
+    const int32_t* __restrict__ wave_item, int n_waves, int n_dyn, int n_cu) {
     extern __shared__ float4 s_lj[];
     __shared__ float4 s_x_all[kFwdWaves][kScAtoms];    // per wave: (x, y, z, K q) by slot
     __shared__ int s_t_all[kFwdWaves][kScAtoms];       // per wave: type * T by slot
@@ -421,7 +421,13 @@ __attribute__((amdgpu_num_sgpr(96))) void k_nb_fwd(
     }
     if (mode == kExecPersist) {
         const int G = (int)gridDim.x * kFwdWaves;
-        const int g = (int)blockIdx.x * kFwdWaves + wave;
+        // Blocks are dispatched round robin over the CUs (block b shares its CU with
+        // b +- n_cu, measured), so with positions in plain block order CU 0 would take the
+        // most expensive item of every CU round and the last CU the cheapest.  Positions
+        // snake instead: odd CU rounds of blocks take theirs in reverse.
+        const int b = (int)blockIdx.x, r = b / n_cu, at = b - r * n_cu;
+        const int m = min(n_cu, (int)gridDim.x - r * n_cu);          // blocks in round r
+        const int g = (r * n_cu + ((r & 1) ? m - 1 - at : at)) * kFwdWaves + wave;
         for (int base = 0, odd = 0; base < n_items; base += G, odd ^= 1) {
             const int slot = base + (odd ? G - 1 - g : g);
             if (slot < n_items) fwd_item<COUL, ENERGY, VIRIAL, PRUNE>(order[slot], NB_ITEM_ARGS);
@@ -474,7 +480,7 @@ void launch_fwd_t(const NbDev& d, const NbKParams& kp, const float* lj, int n_it
                        d.items, d.entries, d.excl_rows, d.xq, d.type_slot, d.sc_info, d.sys,
                        lj, d.jpart, d.ipart, d.epart, d.epart_stride, kp, n_items, part,
                        nstprune, r2_inner, mode, d.item_order, d.queue, d.wave_item, d.n_waves,
-                       d.n_dyn);
+                       d.n_dyn, std::max(d.n_cu, 1));
 }
 
 template <int COUL, bool P>

@@ -750,11 +750,6 @@ nb_status forces_impl(nb_ctx* c, const float* x, const float* q, const float* lj
     }
     // The ahead prune (the paper's rolling schedule: the next step's part is pruned between
     // force computations, Sec. V.E) runs in the force reduction's launch, beside its blocks.
-    int pi0 = 0, pn = 0;
-    if (ahead_part >= 0) {
-        pi0 = c->part_start[ahead_part];
-        pn = c->part_start[ahead_part + 1] - pi0;
-    }
     // Exclusion corrections (a kernel of their own over the excluded pairs; the pair
     // kernel above is the same with or without them)
     const bool corr = (flags & NB_F_EXCL_CORR) && c->p.coulomb != NB_COUL_NONE;
@@ -766,7 +761,11 @@ nb_status forces_impl(nb_ctx* c, const float* x, const float* q, const float* lj
                                    c->stream));
     }
     NB_HIP(c, launch_reduce(d, f, (flags & NB_F_ACCUMULATE) != 0, c->n_slots, energy, virial,
-                            flags, c->n_sys, corr ? d.xcf : nullptr, pi0, pn,
+                            flags, c->n_sys, corr ? d.xcf : nullptr, ahead_part,
+                            c->p.nstprune, ahead_part >= 0 ? c->part_start[ahead_part] : 0,
+                            ahead_part >= 0 ? c->part_start[ahead_part + 1] -
+                                                  c->part_start[ahead_part]
+                                            : 0,
                             radius_sq(c->p.rinner), c->stream));
     if (corr) NB_HIP(c, launch_excl_energy(d, d.xce, energy, virial, flags, c->n_sys, c->stream));
     return NB_OK;
@@ -981,6 +980,40 @@ nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj
             if (n < cap) trials[n] = t;
             ++n;
             if (t.us_per_call < win.us_per_call) win = t;
+        }
+    }
+    // One more shape: the persistent round-robin schedule at the smallest width whose
+    // items all fit the resident grid in one round (per super-cluster ceil(n / W) items):
+    // every wavefront then takes one item and the grid has no partial round of blocks.
+    // The widths above straddle that count (measured at 96k: 7094 items of at most 36
+    // entries on 7168 resident wavefronts, 82 us, against 84.6 at 40 entries).
+    if (st == NB_OK) {
+        int per_cu = 0;
+        hipError_t he = prepare_forces(c->p.coulomb, flags, false, c->p.n_types, &per_cu);
+        if (he != hipSuccess) st = hip_fail(c, he, "autotune occupancy");
+        std::vector<int32_t> cnt((size_t)c->n_sc);
+        if (st == NB_OK) st = to_host(c, cnt.data(), c->d.sc_ecount, cnt.size());
+        if (st == NB_OK) {
+            const int64_t G = (int64_t)std::max(1, per_cu) * std::max(1, c->d.n_cu);
+            int wfit = widths[sizeof(widths) / sizeof(widths[0]) - 1];
+            for (int w = widths[0]; w < wfit; ++w) {
+                int64_t items = 0;
+                for (int32_t k : cnt) items += (k + w - 1) / w;
+                if (items <= G) {
+                    wfit = w;
+                    break;
+                }
+            }
+            c->exec_mode = kExecPersist;
+            st = make_items(c, wfit, false);
+            if (st == NB_OK) st = finish_items(c);
+            double us = 0.0;
+            if (st == NB_OK && time_calls(-1, &us)) {
+                const nb_exec_config t{wfit, kExecPersist, prune0, c->prune_waves, us};
+                if (n < cap) trials[n] = t;
+                ++n;
+                if (t.us_per_call < win.us_per_call) win = t;
+            }
         }
     }
     // Then, for the chosen shape, a rolling step with the prune fused into the pair kernel,

@@ -158,12 +158,14 @@ hipError_t prepare_forces(int coulomb, uint32_t flags, bool prune, int n_types,
                           int* waves_per_cu = nullptr);
 // Per-atom forces (compensated sums of the partials, written in the caller's order) and,
 // with NB_F_ENERGY / NB_F_VIRIAL, the energy chunks in the same launch, then per system.
-// n_prune > 0: the same launch also prunes the items part_items[prune_item0 ...
-// prune_item0 + n_prune) against r2_inner with the gathered coordinates (the ahead prune)
+// prune_part >= 0: the same launch also prunes the lists of that rolling part's
+// super-clusters (prune_part, prune_part + nstprune, ...; their items are
+// part_items[item0 .. item0 + n_part_items)) against r2_inner with the gathered
+// coordinates (the ahead prune)
 hipError_t launch_reduce(const NbDev& d, float* f, bool accumulate, int n_slots,
                         double* energy, double* virial, uint32_t flags, int n_sys,
-                        const float4* xcf, int prune_item0, int n_prune, float r2_inner,
-                        hipStream_t s);
+                        const float4* xcf, int prune_part, int nstprune, int item0,
+                        int n_part_items, float r2_inner, hipStream_t s);
 // Electrostatic corrections of excluded pairs inside rc and of each atom with itself
 // (nb_excl.hip): per-slot forces into xcf (float4 [64 n_sc_max]) and per-super-cluster
 // energy and virial partials into xce ([7][n_sc_max]: E_C, then the six virial sums

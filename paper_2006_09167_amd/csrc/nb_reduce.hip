@@ -128,25 +128,50 @@ __device__ inline void energy_totals(const NbDev& d, double* __restrict__ energy
 }
 
 // The ahead rolling prune, the force reduction and the energy reduction in one launch:
-// blocks [0, n_pblk) prune one item each of the next step's rolling part (prune_item, four
-// wavefronts per item; the reductions read no list data, so the two run side by side),
-// blocks [n_pblk, n_pblk + n_fblk) reduce the forces of four super-clusters each (one
-// wavefront per super-cluster), the blocks after them sum one energy chunk each; the last energy block to finish (a ticket in
-// queue[2], taken after a device-scope fence) adds the chunk partials per system and
-// resets the ticket for the next launch.
+// blocks [0, n_pblk) prune the lists of the next step's rolling part (prune_item, four
+// wavefronts per unit; the reductions read no list data, so the two run side by side), blocks [n_pblk, n_pblk + n_fblk) reduce the forces of four super-clusters
+// each (one wavefront per super-cluster), the blocks after them sum one energy chunk each;
+// the last energy block to finish (a ticket in queue[2], taken after a device-scope
+// fence) adds the chunk partials per system and resets the ticket for the next launch.
 __global__ __launch_bounds__(kRedThreads) void k_reduce_step(NbDev d, float* __restrict__ f,
                                                              int accumulate, int n_sc,
                                                              int n_fblk, double* energy,
                                                              double* virial, uint32_t flags,
                                                              int n_sys,
                                                              const float4* __restrict__ xcf,
-                                                             int n_pblk, int prune_item0,
+                                                             int n_pblk, int prune_part,
+                                                             int nstprune, int item0,
+                                                             int n_units, int q,
                                                              float r2_inner) {
     static_assert(kRedThreads == kRedWaves * kWave, "one block shape for all parts");
     if ((int)blockIdx.x < n_pblk) {
+        // Units u = blockIdx.x, + n_pblk, ... of the part.  q == 0: unit u is the pair
+        // kernel's item part_items[item0 + u] (one or two per block).  q == 1: unit u is
+        // the whole list of super-cluster
+        // prune_part + u nstprune, in runs of at most 64 entries per wavefront (a device
+        // already full of reduction blocks: fewer, longer prune blocks stage fewer i-atoms).
         __shared__ float4 s_xi[kScAtoms];
-        prune_item<kRedWaves>(d.items[d.part_items[prune_item0 + blockIdx.x]], d.entries, d.xq,
-                              d.sc_info, d.sys, r2_inner, s_xi);
+        bool first = true;
+        for (int u = blockIdx.x; u < n_units; u += n_pblk) {
+            NbItem it;
+            if (q == 0) {
+                it = d.items[d.part_items[item0 + u]];
+            } else {
+                it.sc = prune_part + u * nstprune;
+                it.e0 = d.sc_estart[it.sc];
+                it.ne = d.sc_ecount[it.sc];
+                it.pos = 0;
+            }
+            const int e_end = it.e0 + it.ne;
+            for (int e0 = it.e0; e0 < e_end; e0 += kRedWaves * kWave) {   // one call site
+                if (!first) __syncthreads();               // s_xi of the previous run read
+                first = false;
+                NbItem run = it;
+                run.e0 = e0;
+                run.ne = min(kRedWaves * kWave, e_end - e0);
+                prune_item<kRedWaves>(run, d.entries, d.xq, d.sc_info, d.sys, r2_inner, s_xi);
+            }
+        }
         return;
     }
     const int b = (int)blockIdx.x - n_pblk;
@@ -197,19 +222,51 @@ hipError_t launch_gather(const NbDev& d, const float* x, const float* q, float4*
     return hipGetLastError();
 }
 
+// Resident blocks per CU of k_reduce_step (queried once).
+static int red_blocks_per_cu() {
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_reduce_step, kRedThreads, 0) !=
+            hipSuccess)
+            nb = 0;
+        per_cu = nb > 0 ? nb : 1;
+    }
+    return per_cu;
+}
+
 hipError_t launch_reduce(const NbDev& d, float* f, bool accumulate, int n_slots,
                         double* energy, double* virial, uint32_t flags, int n_sys,
-                        const float4* xcf, int prune_item0, int n_prune, float r2_inner,
-                        hipStream_t s) {
+                        const float4* xcf, int prune_part, int nstprune, int item0,
+                        int n_part_items, float r2_inner, hipStream_t s) {
     const int n_sc = n_slots / kScAtoms;
     const int n_fblk = blocks(n_sc, kRedWaves);
     const bool ev = (flags & (NB_F_ENERGY | NB_F_VIRIAL)) && n_sys > 0;
     const int n_eblk = ev ? d.n_chunks : 0;
-    const int n_pblk = n_prune > 0 ? n_prune : 0;
+    // Prune units: the pair kernel's items of the part, one per block while they fit the
+    // device beside the reduction's blocks (a second round of a few blocks cost 2.5 us at
+    // 96k atoms; up to twice as many items take two per block); on a device already full
+    // of reduction blocks whole super-cluster lists, several per block (1.5M atoms: 129 us
+    // for the launch against 164 with items four per block and 140 with lists in
+    // quarters; whole lists at 96k: 25 us, too few blocks for the latency of each).
+    int q = 0, n_units = 0, n_pblk = 0;
+    if (prune_part >= 0 && n_part_items > 0) {
+        const int resident = red_blocks_per_cu() * std::max(d.n_cu, 1);
+        const int avail = resident - n_fblk - n_eblk;
+        if (2 * avail >= n_part_items) {
+            n_units = n_part_items;
+            n_pblk = std::min(n_units, avail);
+        } else {
+            q = 1;
+            n_units = (n_sc > prune_part) ? (n_sc - prune_part + nstprune - 1) / nstprune : 0;
+            n_pblk = std::min(n_units, std::max(avail, (n_units + 3) / 4));
+        }
+    }
     if (n_pblk + n_fblk + n_eblk > 0)
         hipLaunchKernelGGL(k_reduce_step, dim3(n_pblk + n_fblk + n_eblk), dim3(kRedThreads), 0,
                            s, d, f, accumulate ? 1 : 0, n_sc, n_fblk, energy, virial, flags,
-                           n_sys, xcf, n_pblk, prune_item0, r2_inner);
+                           n_sys, xcf, n_pblk, prune_part, nstprune, item0, n_units, q,
+                           r2_inner);
     if (ev && n_eblk == 0)
         hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kRedThreads), 0, s, d, energy, virial,
                            flags, n_sys);

@@ -178,7 +178,8 @@ def test_autotune_keeps_fastest_and_stays_exact(sys3k):
     ctx, x = built(c, nstlist=10, nstprune=2, **EWALD)
     q, lj = dev(c["q"]), dev(c["lj"])
     best, trials = ctx.autotune(x, q, lj, energy=True, repeats=3)
-    assert len(trials) == 43
+    assert len(trials) == 44
+    assert trials[40]["mode"] == "persist"          # the one-round width
     n_shape = len(trials) - 3
     assert all(t["us_per_call"] > 0 for t in trials)
     shape = min(trials[:n_shape], key=lambda t: t["us_per_call"])
