@@ -339,6 +339,30 @@ __global__ void k_excl_cluster_range(NbDev d) {
     d.cl_xrange[ci] = make_int2(lo, hi);
 }
 
+// Per slot: the image offset of its atom, (kx Lx, ky Ly, kz Lz) in FP32 as the gather
+// subtracts it, or, for an empty slot, its filler position.  Empty slots (charge 0) sit on
+// the lattice -D (1 + i, 1 + j, 1 + k) with spacing D = max box edge + 2 rlist + 1 nm and
+// (i, j, k) the slot's base-1024 digits.  Any pair with an empty slot is then at least
+// 2 rlist + 1 nm apart on some axis under every periodic shift s L (|s| <= 1), and an empty
+// slot and its own image |s L| apart: with box edges up to 1000 nm the coordinates stay
+// below 1025 D < 1.1e6 nm, where one ulp is at most 0.125 nm.  No distance test with an
+// empty slot passes, so the pair kernels need no valid-atom masks.
+__global__ void k_slot_pre(NbDev d, int n_slots) {
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    // slots of super-clusters this build made (k_supercell writes no others)
+    if (slot >= n_slots || slot >= d.flags[kFlagNumSc] * kScAtoms) return;
+    const int a = d.slot_atom[slot];
+    const float D = d.filler_d;
+    float4 v = make_float4(-D * (float)(1 + (slot & 1023)), -D * (float)(1 + ((slot >> 10) & 1023)),
+                           -D * (float)(1 + (slot >> 20)), 0.f);
+    if (a >= 0) {
+        const int4 k = d.img[a];
+        const NbSys S = d.sys[d.atom_sys[a]];
+        v = make_float4((float)k.x * S.L[0], (float)k.y * S.L[1], (float)k.z * S.L[2], 0.f);
+    }
+    d.slot_pre[slot] = v;
+}
+
 inline int blocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
@@ -376,6 +400,8 @@ hipError_t launch_grid_build(const NbDev& d, const float* x, hipStream_t s) {
         hipLaunchKernelGGL(k_excl_cluster_range,
                            dim3(blocks((int64_t)d.n_sc_max * kClustersPerSc, 256)), dim3(256), 0,
                            s, d);
+        hipLaunchKernelGGL(k_slot_pre, dim3(blocks((int64_t)d.n_sc_max * kScAtoms, 256)),
+                           dim3(256), 0, s, d, (int)(d.n_sc_max * kScAtoms));
     }
     return hipGetLastError();
 }

@@ -295,7 +295,7 @@ void nb_destroy(nb_ctx* c) {
                     d.part_start, d.excl_rows, d.jseg_count, d.jseg_start, d.jseg_fill,
                     d.jseg_entries, d.totals, d.flags, d.jpart, d.ipart, d.epart, d.glj_part,
                     d.dstat, d.item_cost, d.item_order, d.queue, d.xcf, d.xce,
-                    d.part_items, d.wave_e, d.wave_item, d.cl_xrange};
+                    d.part_items, d.wave_e, d.wave_item, d.cl_xrange, d.slot_pre};
     drop_graphs(c);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     for (void* q : ptrs)
@@ -442,6 +442,7 @@ nb_status nb_grid_build(nb_ctx* c, const float* x, const float* box) {
         const size_t ns = (size_t)n_sc_max, slots = ns * kScAtoms, cl = ns * kClustersPerSc;
         NB_HIP(c, dev_alloc(d.sc_info, ns));
         NB_HIP(c, dev_alloc(d.slot_atom, slots));
+        NB_HIP(c, dev_alloc(d.slot_pre, slots));
         NB_HIP(c, dev_alloc(d.type_slot, slots));
         NB_HIP(c, dev_alloc(d.cl_bb, 2 * cl));
         NB_HIP(c, dev_alloc(d.sc_bb, 2 * ns));

@@ -236,6 +236,9 @@ struct NbDev {
     int32_t* col_sorted = nullptr;     // [N] sorted by (column, z, index)
     NbScInfo* sc_info = nullptr;       // [n_sc_max]
     int32_t* slot_atom = nullptr;      // [64 n_sc_max]
+    float4* slot_pre = nullptr;        // [64 n_sc_max] per slot of the last grid build: the
+                                       // image offset (kx Lx, ky Ly, kz Lz, 0) subtracted
+                                       // from its atom, or an empty slot's filler position
     int32_t* atom_slot = nullptr;      // [N]
     int32_t* type_slot = nullptr;      // [64 n_sc_max] 16 type: the byte offset of the type's
                                        // entry in a row of a float4 table over types

@@ -10,30 +10,22 @@
 namespace {
 
 // Per-slot gather of user-order coordinates (and charges) into slot order, wrapped with
-// the image offsets of the last grid build in the same sequence as the build.
+// the image offsets of the last grid build (kept per slot in slot_pre, the same FP32
+// products the build formed, so that the loads a slot waits for are two deep: its atom
+// index and offset, then the atom's coordinates).  An empty slot takes its filler
+// position from slot_pre and charge 0.
 __global__ void k_gather(NbDev d, const float* __restrict__ x, const float* __restrict__ q,
                          float4* __restrict__ out, int n_slots) {
 #pragma clang fp contract(off)
     const int slot = blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= n_slots) return;
     const int a = d.slot_atom[slot];
-    // Empty slots (charge 0) sit on the lattice -D (1 + i, 1 + j, 1 + k) with spacing
-    // D = max box edge + 2 rlist + 1 nm and (i, j, k) the slot's base-1024 digits.  Any
-    // pair with an empty slot is then at least 2 rlist + 1 nm apart on some axis under
-    // every periodic shift s L (|s| <= 1), and an empty slot and its own image |s L| apart:
-    // with box edges up to 1000 nm the coordinates stay below 1025 D < 1.1e6 nm, where one
-    // ulp is at most 0.125 nm.  No distance test with an empty slot passes, so the pair
-    // kernels need no valid-atom masks.
-    const float D = d.filler_d;
-    float4 v = make_float4(-D * (float)(1 + (slot & 1023)), -D * (float)(1 + ((slot >> 10) & 1023)),
-                           -D * (float)(1 + (slot >> 20)), 0.f);
+    const float4 p = d.slot_pre[slot];
+    float4 v = p;
     if (a >= 0) {
-        const int4 k = d.img[a];
-        const NbSys S = d.sys[d.atom_sys[a]];
-        const float kx = (float)k.x * S.L[0], ky = (float)k.y * S.L[1], kz = (float)k.z * S.L[2];
-        v.x = x[3 * a] - kx;
-        v.y = x[3 * a + 1] - ky;
-        v.z = x[3 * a + 2] - kz;
+        v.x = x[3 * a] - p.x;
+        v.y = x[3 * a + 1] - p.y;
+        v.z = x[3 * a + 2] - p.z;
         v.w = q ? q[a] : 0.f;
     }
     out[slot] = v;
