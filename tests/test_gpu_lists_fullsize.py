@@ -6,7 +6,11 @@ oracle's cluster-pair sets, as sets, each cluster pair once:
 * at rolling steps 1-4 (Sec. V.E: one part per step, pruned with that step's positions),
   in five execution shapes: the prune as its own kernel with one, two, four and eight
   wavefronts per item and with the automatic choice, and the prune fused into the pair
-  kernel."""
+  kernel;
+* with the ahead prune (part (t + 1) mod nstprune pruned with the positions of step t,
+  in the force reduction's launch) in its two unit layouts: the pair kernel's items,
+  several per block at 36 entries per item (more items than blocks that fit beside the
+  reduction), and whole super-cluster lists at 8 entries per item (many more items)."""
 import numpy as np
 import pytest
 import torch
@@ -19,7 +23,8 @@ pytestmark = pytest.mark.gpu
 
 # (entries per item, mode, prune fused, prune wavefronts per item)
 SHAPES = [(8, "static", False, 1), (40, "persist", False, 0), (40, "xcd", False, 2),
-          (16, "static", False, 4), (24, "persist", False, 8), (40, "persist", True, 0)]
+          (16, "static", False, 4), (24, "persist", False, 8), (40, "persist", True, 0),
+          (36, "persist", "ahead", 0), (8, "persist", "ahead", 0)]
 
 
 @pytest.mark.timeout(600)
@@ -59,6 +64,7 @@ def test_water96k_lists_at_build_and_rolling_steps():
     x = c["x"].copy()
     part_keys = {p: oracle.inner_pairs(ref_o, g["slot_atom"], g["w"], box, ri, npr, p)
                  for p in range(npr)}
+    ahead_keys = dict(part_keys)
     for t in range(1, 5):
         x = (x + rng.normal(0.0, cfg["sigma_step"], x.shape)).astype(np.float32)
         xt = dev(x)
@@ -68,8 +74,12 @@ def test_water96k_lists_at_build_and_rolling_steps():
         p = t % npr
         w_t = oracle.rewrap_with(x, g["k"], box)
         part_keys[p] = oracle.inner_pairs(ref_o, g["slot_atom"], w_t, box, ri, npr, p)
+        pa = (t + 1) % npr
+        ahead_keys[pa] = oracle.inner_pairs(ref_o, g["slot_atom"], w_t, box, ri, npr, pa)
         ref_i = np.sort(np.concatenate([part_keys[k] for k in range(npr)]))
+        ref_a = np.sort(np.concatenate([ahead_keys[k] for k in range(npr)]))
         for k, ctx in enumerate(ctxs):
             ki = np.sort(keys_of(ctx.get_pairs("inner"), n_cl))
-            assert np.array_equal(ki, ref_i), (t, SHAPES[k])
+            ref = ref_a if SHAPES[k][2] == "ahead" else ref_i
+            assert np.array_equal(ki, ref), (t, SHAPES[k])
         print("96k step %d: inner %d cluster pairs in all shapes" % (t, ref_i.size), flush=True)
