@@ -151,10 +151,14 @@ __global__ __launch_bounds__(kSearchWaves * kWave) void k_search(NbDev d, int ca
                     const int J = J0 + (base + t) / 3;
                     const int sz = (base + t) % 3 - 1;
                     const int code = (sx + 1) * 9 + (sy + 1) * 3 + (sz + 1);
-                    // 64 cluster-pair box tests: lane -> (j-cluster jj, i-cluster ii)
+                    // 64 cluster-pair box tests: lane -> (j-cluster jj, i-cluster ii); the
+                    // j-super-cluster's 64 atoms are loaded at the same time (lane l: atom l)
+                    // and handed to the distance tests below by shuffles, so those wait on
+                    // no load of their own
                     const int cjl = kClustersPerSc * J + jj;
                     const int cil = ci0 + ii;
                     const float4 jlo = d.cl_bb[2 * cjl], jhi = d.cl_bb[2 * cjl + 1];
+                    const float4 xall = d.xw[kScAtoms * J + lane];
                     const bool canon = (cjl > cil) || (cjl == cil && code >= kShiftZero);
                     const bool ok = canon && jlo.w > 0.f && s_ilo[ii].w > 0.f &&
                                     bb_d2(s_ilo[ii], s_ihi[ii], jlo, jhi, sx, sy, sz, S) < r2_outer;
@@ -172,8 +176,12 @@ __global__ __launch_bounds__(kSearchWaves * kWave) void k_search(NbDev d, int ca
                             }
                             continue;
                         }
-                        const int nj = (int)d.cl_bb[2 * cj].w;
-                        const float4 xj = d.xw[kClusterSize * cj + jj];
+                        // atoms in cluster jc: the box of lane 8 jc (ii = 0, jj = jc)
+                        const int nj = (int)__int_as_float(
+                            __builtin_amdgcn_readlane(__float_as_int(jlo.w), kClusterSize * jc));
+                        const int src = kClusterSize * jc + jj;
+                        const float4 xj = make_float4(__shfl(xall.x, src), __shfl(xall.y, src),
+                                                      __shfl(xall.z, src), 0.f);
                         uint32_t omask = 0, imask = 0;
                         for (uint32_t bits = bbmask; bits; bits &= bits - 1) {
                             const int c = __builtin_ctz(bits);
