@@ -262,7 +262,7 @@ __global__ __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(5))
     const NbSys* __restrict__ sys, const float* __restrict__ lj,
     const double* __restrict__ grad_e, float4* __restrict__ jpart, float4* __restrict__ ipart,
     float* __restrict__ glj_part, int glj_stride, NbKParams kp, int n_items, int mode,
-    const int32_t* __restrict__ order) {
+    const int32_t* __restrict__ order, int n_cu) {
     extern __shared__ float4 s_dyn[];
     __shared__ float4 s_x_all[kBwdWaves][kScAtoms];    // per wave: (x_i, y_i, z_i, q_i)
     __shared__ float4 s_gq_all[kBwdWaves][kScAtoms];   // per wave: (G_i, K q_i)
@@ -287,7 +287,11 @@ __global__ __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(5))
         sc_info, sys, grad_e, jpart, ipart, glj_part, glj_stride, kp
     if (mode == kExecPersist) {
         const int G = (int)gridDim.x * kBwdWaves;
-        const int g = (int)blockIdx.x * kBwdWaves + wave;
+        // positions snake over the CU rounds of blocks (odd rounds reversed), as in the
+        // forward kernel: blocks are dealt to the CUs round robin
+        const int b = (int)blockIdx.x, r = b / n_cu, at = b - r * n_cu;
+        const int m = min(n_cu, (int)gridDim.x - r * n_cu);
+        const int g = (r * n_cu + ((r & 1) ? m - 1 - at : at)) * kBwdWaves + wave;
         for (int base = 0, odd = 0; base < n_items; base += G, odd ^= 1) {
             const int slot = base + (odd ? G - 1 - g : g);
             if (slot < n_items) bwd_item<COUL, LJGRAD, PRIV>(order[slot], NB_ITEM_ARGS);
@@ -442,12 +446,26 @@ int bwd_blocks_per_cu(size_t lds) {
     return per_cu;
 }
 
+// Dynamic LDS of one flavor: the LJ table and the table-gradient histograms.
+template <bool LJG, bool PRIV>
+size_t bwd_lds(int n_types) {
+    const int TT = n_types * n_types;
+    const size_t hist = LJG ? (size_t)(PRIV ? 2 * TT * kWave : 2 * TT) * kBwdWaves : 0;
+    return sizeof(float4) * TT + sizeof(float) * hist;
+}
+
+template <int COUL>
+int bwd_waves_c(bool ljgrad, int n_types) {
+    if (!ljgrad) return bwd_blocks_per_cu<COUL, false, false>(bwd_lds<false, false>(n_types));
+    if (n_types <= kPrivateHistTypes)
+        return bwd_blocks_per_cu<COUL, true, true>(bwd_lds<true, true>(n_types));
+    return bwd_blocks_per_cu<COUL, true, false>(bwd_lds<true, false>(n_types));
+}
+
 template <int COUL, bool LJG, bool PRIV>
 void launch_bwd_t(const NbDev& d, const NbKParams& kp, const float* lj, const double* ge,
                   int n_items, int mode, hipStream_t s) {
-    const int TT = kp.n_types * kp.n_types;
-    const size_t hist = LJG ? (size_t)(PRIV ? 2 * TT * kWave : 2 * TT) * kBwdWaves : 0;
-    const size_t lds = sizeof(float4) * TT + sizeof(float) * hist;
+    const size_t lds = bwd_lds<LJG, PRIV>(kp.n_types);
     // the persistent schedule when the context runs the forward pass that way, else
     // one wavefront per item
     const int bmode = (mode == kExecPersist) ? kExecPersist : kExecStatic;
@@ -457,7 +475,7 @@ void launch_bwd_t(const NbDev& d, const NbKParams& kp, const float* lj, const do
     hipLaunchKernelGGL((k_nb_bwd<COUL, LJG, PRIV>), dim3(grid), dim3(kBwdThreads), lds, s,
                        d.items, d.entries, d.excl_rows, d.xq, d.gslot, d.type_slot, d.sc_info,
                        d.sys, lj, ge, d.jpart, d.ipart, d.glj_part, d.epart_stride, kp, n_items,
-                       bmode, d.item_order);
+                       bmode, d.item_order, std::max(d.n_cu, 1));
 }
 
 template <int COUL>
@@ -469,6 +487,13 @@ void launch_bwd_c(const NbDev& d, const NbKParams& kp, const float* lj, const do
 }
 
 }  // namespace
+
+int backward_waves_per_cu(int coulomb, bool ljgrad, int n_types) {
+    const int blocks_per_cu = (coulomb == NB_COUL_RF)     ? bwd_waves_c<NB_COUL_RF>(ljgrad, n_types)
+                              : (coulomb == NB_COUL_NONE) ? bwd_waves_c<NB_COUL_NONE>(ljgrad, n_types)
+                                                          : bwd_waves_c<NB_COUL_EWALD>(ljgrad, n_types);
+    return blocks_per_cu * kBwdWaves;
+}
 
 hipError_t launch_backward(const NbDev& d, const NbKParams& kp, int coulomb, const float* lj,
                            const float* grad_f, const double* grad_energy, bool ljgrad,

@@ -28,6 +28,13 @@ struct nb_ctx {
     int32_t fixed_w = 0;      // item width chosen by nb_set_exec / nb_autotune (0 = rule)
     int32_t exec_mode = kExecStatic;
     int items_kind = 0;           // partition of the current items (items_kind_of)
+    // the backward pass's items (see backward_items): for list generation bwd_gen and
+    // flavor bwd_flavor (with table gradient or not), bwd_n of width bwd_w, in the b_*
+    // arrays when bwd_own, else the forward items
+    uint64_t bwd_gen = ~0ull;
+    int bwd_flavor = -1, bwd_w = 0, bwd_n = 0;
+    bool bwd_own = false;
+    size_t a_bitems = 0, a_bsc = 0;
     // nb_step's rolling prune: kPruneFused inside the pair kernel, kPruneSeparate as its own
     // kernel before it, kPruneAhead after it in the force reduction's launch, for the next
     // step's part with this step's positions
@@ -295,7 +302,9 @@ void nb_destroy(nb_ctx* c) {
                     d.part_start, d.excl_rows, d.jseg_count, d.jseg_start, d.jseg_fill,
                     d.jseg_entries, d.totals, d.flags, d.jpart, d.ipart, d.epart, d.glj_part,
                     d.dstat, d.item_cost, d.item_order, d.queue, d.xcf, d.xce,
-                    d.part_items, d.wave_e, d.wave_item, d.cl_xrange, d.slot_pre};
+                    d.part_items, d.wave_e, d.wave_item, d.cl_xrange, d.slot_pre,
+                    d.b_items, d.b_item_order, d.b_item_cost, d.b_sc_istart, d.b_sc_icount,
+                    d.b_sc_ipos, d.b_part_items, d.b_part_start, d.b_totals};
     drop_graphs(c);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     for (void* q : ptrs)
@@ -1055,6 +1064,96 @@ nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj
     return NB_OK;
 }
 
+namespace {
+// Items of the backward pass.  Its kernel holds fewer wavefronts per SIMD than the forward
+// kernel (more registers per pair), so the forward items can take it two rounds, the
+// second partial; it takes per-super-cluster items of the smallest width, not below the
+// forward items', whose items all fit its resident grid in one round (at 96k atoms 52
+// entries against the forward's 36: 171 -> 144 us), or the forward items themselves when
+// that is their width.  Built once per list generation and flavor, on the device, into
+// arrays of their own; an item count never above the forward's, so the per-item partial
+// buffers fit.
+nb_status backward_items(nb_ctx* c, bool ljgrad, NbDev* db, int* n_items) {
+    NbDev& d = c->d;
+    const int flavor = ljgrad ? 1 : 0;
+    if (c->bwd_gen != c->list_gen || c->bwd_flavor != flavor) {
+        const int per_cu = backward_waves_per_cu(c->p.coulomb, ljgrad, c->p.n_types);
+        const int64_t G = (int64_t)std::max(1, per_cu) * std::max(1, d.n_cu);
+        std::vector<int32_t> cnt((size_t)c->n_sc);
+        nb_status st = to_host(c, cnt.data(), d.sc_ecount, cnt.size());
+        if (st != NB_OK) return st;
+        auto items_at = [&](int w) {
+            int64_t n = 0;
+            for (int32_t k : cnt) n += (k + w - 1) / w;
+            return n;
+        };
+        const int w0 = std::max(1, std::min(c->item_w, 64));
+        int wb = 64;
+        for (int w = w0; w < 64; ++w)
+            if (items_at(w) <= G) {
+                wb = w;
+                break;
+            }
+        const bool own = !(wb == c->item_w && c->items_kind == 0);
+        const int nb = (int)items_at(wb);
+        if (own) {
+            const size_t need = (size_t)nb + 64, nsc = (size_t)std::max(d.n_sc_max, 1) + 1;
+            if (need > c->a_bitems || !d.b_items) {
+                NB_HIP(c, dev_alloc(d.b_items, need));
+                NB_HIP(c, dev_alloc(d.b_item_order, need));
+                NB_HIP(c, dev_alloc(d.b_item_cost, need));
+                NB_HIP(c, dev_alloc(d.b_part_items, need));
+                c->a_bitems = need;
+            }
+            if (nsc > c->a_bsc || !d.b_sc_istart) {
+                NB_HIP(c, dev_alloc(d.b_sc_istart, nsc));
+                NB_HIP(c, dev_alloc(d.b_sc_icount, nsc));
+                NB_HIP(c, dev_alloc(d.b_sc_ipos, nsc));
+                c->a_bsc = nsc;
+            }
+            if (!d.b_part_start) NB_HIP(c, dev_alloc(d.b_part_start, c->p.nstprune + 1));
+            if (!d.b_totals) NB_HIP(c, dev_alloc(d.b_totals, 8));
+            NB_HIP(c, hipMemcpyAsync(d.b_totals, d.totals, 8 * sizeof(int32_t),
+                                     hipMemcpyDeviceToDevice, c->stream));
+        }
+        c->bwd_gen = c->list_gen;
+        c->bwd_flavor = flavor;
+        c->bwd_w = wb;
+        c->bwd_n = own ? nb : c->n_items;
+        c->bwd_own = own;
+        if (own) {
+            NbDev t = d;
+            t.items = d.b_items;
+            t.item_order = d.b_item_order;
+            t.item_cost = d.b_item_cost;
+            t.sc_istart = d.b_sc_istart;
+            t.sc_icount = d.b_sc_icount;
+            t.sc_ipos = d.b_sc_ipos;
+            t.part_items = d.b_part_items;
+            t.part_start = d.b_part_start;
+            t.totals = d.b_totals;
+            NB_HIP(c, launch_make_items(t, c->n_sc, c->cap, wb, c->p.nstprune, false, 0, 0,
+                                        kQueueStaticPermille, c->stream));
+            NB_HIP(c, launch_item_order(t, nb, c->stream));
+        }
+    }
+    *db = d;
+    if (c->bwd_own) {
+        db->items = d.b_items;
+        db->item_order = d.b_item_order;
+        db->item_cost = d.b_item_cost;
+        db->sc_istart = d.b_sc_istart;
+        db->sc_icount = d.b_sc_icount;
+        db->sc_ipos = d.b_sc_ipos;
+        db->part_items = d.b_part_items;
+        db->part_start = d.b_part_start;
+        db->totals = d.b_totals;
+    }
+    *n_items = c->bwd_n;
+    return NB_OK;
+}
+}  // namespace
+
 nb_status nb_forces_backward(nb_ctx* c, const float* x, const float* q, const float* lj,
                              const float* grad_f, const double* grad_energy, float* grad_x,
                              float* grad_q, double* grad_lj, uint32_t flags) {
@@ -1064,9 +1163,12 @@ nb_status nb_forces_backward(nb_ctx* c, const float* x, const float* q, const fl
     if (c->d.n_atoms > 0 && (!x || !q || !lj || !grad_f))
         return fail(c, NB_ERR_ARG, "null array");
     NB_HIP(c, hipSetDevice(c->device));
-    NbDev& d = c->d;
     const NbKParams kp = kernel_params(c->p);
     const bool acc = (flags & NB_F_ACCUMULATE) != 0;
+    NbDev d;
+    int n_items = 0;
+    nb_status st = backward_items(c, grad_lj != nullptr, &d, &n_items);
+    if (st != NB_OK) return st;
     {
         TimedSection ts(c, NB_T_BACKWARD_REDUCE);
         NB_HIP(c, launch_gather(d, x, q, d.xq, c->n_slots, c->stream));
@@ -1074,11 +1176,11 @@ nb_status nb_forces_backward(nb_ctx* c, const float* x, const float* q, const fl
     {
         TimedSection ts(c, NB_T_BACKWARD);
         NB_HIP(c, launch_backward(d, kp, c->p.coulomb, lj, grad_f, grad_energy, grad_lj != nullptr,
-                                  c->n_slots, c->n_items, c->exec_mode, c->stream));
+                                  c->n_slots, n_items, c->exec_mode, c->stream));
     }
     TimedSection ts(c, NB_T_BACKWARD_REDUCE);
     NB_HIP(c, launch_reduce_backward(d, grad_x, grad_q, grad_lj, acc, c->n_slots, c->p.n_types,
-                                     c->n_items, c->stream));
+                                     n_items, c->stream));
     return NB_OK;
 }
 

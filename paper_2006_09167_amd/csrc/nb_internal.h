@@ -174,6 +174,9 @@ hipError_t launch_excl_corr(const NbDev& d, const NbKParams& kp, int coulomb, do
                             double crf, int n_sc, float4* xcf, double* xce, hipStream_t s);
 hipError_t launch_excl_energy(const NbDev& d, const double* xce, double* energy, double* virial,
                               uint32_t flags, int n_sys, hipStream_t s);
+// Wavefronts of the backward kernel's flavor (with or without the table gradient)
+// resident per CU.
+int backward_waves_per_cu(int coulomb, bool ljgrad, int n_types);
 hipError_t launch_backward(const NbDev& d, const NbKParams& kp, int coulomb, const float* lj,
                            const float* grad_f, const double* grad_energy, bool ljgrad,
                            int n_slots, int n_items, int mode, hipStream_t s);
@@ -275,6 +278,19 @@ struct NbDev {
     int32_t* wave_item = nullptr;      // [kMaxBalancedWaves+1] first item per run
     int32_t n_waves = 0;               // wavefronts of the balanced partition (0: none)
     int32_t n_dyn = 0;                 // dynamic runs after them (queue mode)
+    // The backward pass's own items (per super-cluster, of the width whose items fit its
+    // resident grid in one round), when that width differs from the forward items':
+    // same layout as items, item_order, item_cost, sc_istart, sc_icount, sc_ipos,
+    // part_items, part_start, totals
+    NbItem* b_items = nullptr;
+    int32_t* b_item_order = nullptr;
+    int32_t* b_item_cost = nullptr;
+    int32_t* b_sc_istart = nullptr;
+    int32_t* b_sc_icount = nullptr;
+    int32_t* b_sc_ipos = nullptr;
+    int32_t* b_part_items = nullptr;
+    int32_t* b_part_start = nullptr;
+    int32_t* b_totals = nullptr;
     uint64_t* excl_rows = nullptr;     // [entry_cap][8]
     int32_t* jseg_count = nullptr;     // [8 n_sc_max]
     int32_t* jseg_start = nullptr;     // [8 n_sc_max + 1]
