@@ -31,6 +31,7 @@ struct nb_ctx {
     // the backward pass's items (see backward_items): for list generation bwd_gen and
     // flavor bwd_flavor (with table gradient or not), bwd_n of width bwd_w, in the b_*
     // arrays when bwd_own, else the forward items
+    std::vector<int32_t> h_ecount;   // entries per super-cluster of the current list
     uint64_t bwd_gen = ~0ull;
     int bwd_flavor = -1, bwd_w = 0, bwd_n = 0;
     bool bwd_own = false;
@@ -577,6 +578,11 @@ nb_status finish_items(nb_ctx* c) {
                              hipMemcpyDeviceToHost, c->stream));
     NB_HIP(c, hipMemcpyAsync(c->h_ipos.data(), d.sc_ipos, sizeof(int32_t) * c->h_ipos.size(),
                              hipMemcpyDeviceToHost, c->stream));
+    // entries per super-cluster, for the backward pass's item width (no round trip there)
+    c->h_ecount.resize((size_t)c->n_sc);
+    if (c->n_sc > 0)
+        NB_HIP(c, hipMemcpyAsync(c->h_ecount.data(), d.sc_ecount, sizeof(int32_t) * c->n_sc,
+                                 hipMemcpyDeviceToHost, c->stream));
     nb_status st = sync(c);
     if (st != NB_OK) return st;
     c->n_items = c->h_totals[1];
@@ -1001,8 +1007,7 @@ nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj
         int per_cu = 0;
         hipError_t he = prepare_forces(c->p.coulomb, flags, false, c->p.n_types, &per_cu);
         if (he != hipSuccess) st = hip_fail(c, he, "autotune occupancy");
-        std::vector<int32_t> cnt((size_t)c->n_sc);
-        if (st == NB_OK) st = to_host(c, cnt.data(), c->d.sc_ecount, cnt.size());
+        const std::vector<int32_t>& cnt = c->h_ecount;
         if (st == NB_OK) {
             const int64_t G = (int64_t)std::max(1, per_cu) * std::max(1, c->d.n_cu);
             int wfit = widths[sizeof(widths) / sizeof(widths[0]) - 1];
@@ -1070,18 +1075,17 @@ namespace {
 // second partial; it takes per-super-cluster items of the smallest width, not below the
 // forward items', whose items all fit its resident grid in one round (at 96k atoms 52
 // entries against the forward's 36: 171 -> 144 us), or the forward items themselves when
-// that is their width.  Built once per list generation and flavor, on the device, into
-// arrays of their own; an item count never above the forward's, so the per-item partial
-// buffers fit.
+// that is their width.  The width is chosen on the host from the entry counts the list
+// build brought back; the items are built once per list generation and flavor, on the
+// device (no wait), into arrays of their own; an item count never above the forward's,
+// so the per-item partial buffers fit.
 nb_status backward_items(nb_ctx* c, bool ljgrad, NbDev* db, int* n_items) {
     NbDev& d = c->d;
     const int flavor = ljgrad ? 1 : 0;
     if (c->bwd_gen != c->list_gen || c->bwd_flavor != flavor) {
         const int per_cu = backward_waves_per_cu(c->p.coulomb, ljgrad, c->p.n_types);
         const int64_t G = (int64_t)std::max(1, per_cu) * std::max(1, d.n_cu);
-        std::vector<int32_t> cnt((size_t)c->n_sc);
-        nb_status st = to_host(c, cnt.data(), d.sc_ecount, cnt.size());
-        if (st != NB_OK) return st;
+        const std::vector<int32_t>& cnt = c->h_ecount;
         auto items_at = [&](int w) {
             int64_t n = 0;
             for (int32_t k : cnt) n += (k + w - 1) / w;
