@@ -59,6 +59,43 @@ def test_water96k_full_parity_at_build_and_rolling_steps():
         assert rel_rms(v.cpu().numpy(), V) <= 1e-5
 
 
+def test_water96k_queue_and_balanced_modes_match_persistent():
+    """The queue mode (balanced runs plus the dynamic tail from ticket pools) and the
+    balanced mode at full size, with the ahead prune, over rolling steps: the same inner
+    lists as the persistent mode, outputs equal to FP32 summation-order rounding (their
+    items differ), the last step within the oracle bars."""
+    s = systems.config_system("water96k_ewald")
+    c = concat(s)
+    q, lj = dev(c["q"]), dev(c["lj"])
+    ctxs = {}
+    for mode in ("persist", "queue", "balanced"):
+        ctx, cfg = ctx_for("water96k_ewald", c)
+        ctx.grid_build(dev(c["x"]), c["boxes"])
+        ctx.pairlist_build()
+        ctx.set_exec(36, mode, "ahead")
+        ctxs[mode] = ctx
+    rng = np.random.default_rng(23)
+    xs = c["x"].copy()
+    for t in range(0, 4):
+        if t > 0:
+            xs = (xs + rng.normal(0.0, cfg["sigma_step"], xs.shape)).astype(np.float32)
+        xt = dev(xs)
+        out = {m: ctx.step(xt, q, lj, t, energy=True, virial=True) for m, ctx in ctxs.items()}
+        torch.cuda.synchronize()
+        fa, ea, va = out["persist"]
+        inner = ctxs["persist"].get_pairs("inner")
+        for m in ("queue", "balanced"):
+            fb, eb, vb = out[m]
+            assert rel_rms(fb.cpu().numpy(), fa.cpu().numpy()) <= 1e-6, (m, t)
+            assert torch.allclose(eb, ea, rtol=1e-9, atol=0), (m, t)
+            assert torch.allclose(vb, va, rtol=1e-6, atol=1e-6 * va.abs().max().item()), (m, t)
+            assert np.array_equal(ctxs[m].get_pairs("inner"), inner), (m, t)
+    E, F, V, A = oracle_forces_multi(c, xs, oracle_params("ewald", cfg["rc"], cfg["beta"]))
+    f, e, v = out["queue"]
+    assert rel_rms(f.cpu().numpy(), F) <= 1e-5
+    assert np.all(np.abs(e.cpu().numpy() - E) <= energy_tolerance(E, A, True))
+
+
 def symmetrize(gl):
     """Split the derivative w.r.t. each off-diagonal table value evenly over its entries."""
     return 0.5 * (gl + np.transpose(gl, (1, 0, 2)))
