@@ -807,6 +807,7 @@ def main():
         "ms_per_step_eager_with_timing_events": 1e3 * wall_eager / K,
         "ms_per_step_separate_prune_call": 1e3 * wall_sep / K,
         "fwd_bwd_pairs_per_s": (eff_timed / wall_fb) if wall_fb else None,
+        "fwd_bwd_raw_pairs_per_s": (comp_timed / wall_fb) if wall_fb else None,
         "fwd_bwd_ms_per_step": (1e3 * wall_fb / K) if wall_fb else None,
         "bwd_over_fwd_kernel": (tm_fb["backward"][0] / max(tm_fb["forces"][0], 1e-9))
         if tm_fb else None,
