@@ -43,7 +43,7 @@ constexpr int kQueueTickets = kPoolStride;      // queue[] offsets: ticket count
 constexpr int kQueueDone = kQueueTickets + kQueuePools * kPoolStride;   // finished blocks
 constexpr int kQueueDoneAll = kQueueDone + kQueuePools * kPoolStride;   // per group, groups
 constexpr int kQueueWords = kQueueDoneAll + kPoolStride;
-constexpr int kMaxItemCost = 64 * 8;            // set outer-mask bits of one item, at most
+constexpr int kMaxItemCost = 64 * 10;           // estimated cost of one item, at most
 
 // One j-entry of a super-cluster's joint list (16 bytes, loaded with one scalar load).
 //   meta bits  0..4   shift code (sx+1)*9 + (sy+1)*3 + (sz+1), image x_j + s L
@@ -266,7 +266,7 @@ struct NbDev {
     NbEntry* entries = nullptr;        // [entry_cap]
     int32_t* entry_sc = nullptr;       // [entry_cap]
     NbItem* items = nullptr;           // [item_cap]
-    int32_t* item_cost = nullptr;      // [item_cap] set outer-mask bits per item
+    int32_t* item_cost = nullptr;      // [item_cap] estimated cost per item (k_item_cost)
     int32_t* item_order = nullptr;     // [item_cap] items by decreasing cost (queue order)
     int32_t* queue = nullptr;          // [kQueueWords] unused, unused, finished
                                        //     energy-chunk blocks, finished backward chunks,

@@ -596,7 +596,9 @@ __global__ __launch_bounds__(kPruneWaves * kWave) void k_prune(
                             r2_inner, s_xi);
 }
 
-// Pair work of each item (one wavefront per item): set bits of its entries' outer masks.
+// Estimated cost of each item (one wavefront per item): per entry 2 + the set bits of its
+// inner mask as built (an entry's j-load, shift, partial store and reductions weigh about
+// two 8 x 8 blocks in measured wavefront times).
 __global__ __launch_bounds__(4 * kWave) void k_item_cost(NbDev d, int n_items) {
     const int item = blockIdx.x * 4 + (int)(threadIdx.x / kWave);
     const int lane = threadIdx.x & (kWave - 1);
@@ -604,7 +606,7 @@ __global__ __launch_bounds__(4 * kWave) void k_item_cost(NbDev d, int n_items) {
     const NbItem it = d.items[item];
     int c = 0;
     for (int k = lane; k < it.ne; k += kWave)
-        c += __builtin_popcount((d.entries[it.e0 + k].meta >> 8) & 0xffu);
+        c += 2 + __builtin_popcount((d.entries[it.e0 + k].meta >> 16) & 0xffu);
     for (int off = 1; off < kWave; off <<= 1) c += __shfl_xor(c, off);
     if (lane == 0) d.item_cost[item] = c;
 }
