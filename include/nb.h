@@ -282,9 +282,10 @@ nb_status nb_get_exec(nb_ctx* ctx, nb_exec_config* out);
  * times nb_forces(x, q, lj, flags) on the current list for item widths 8, 16, ..., 64 (steps
  * of 8), each with the five execution modes (repeats timed calls after one warm-up each,
  * HIP events, median), and NB_EXEC_PERSIST at the smallest width whose items fit the
- * resident grid in one round; then, in the fastest shape, a rolling step (nb_step
- * re-pruning part 1 with x) with the prune fused, separate and ahead; writes up to cap
- * trials to host trials[] and their number (44) to *n_trials, and keeps
+ * resident grid in one round; then, in the two fastest shapes, a rolling step (nb_step
+ * re-pruning part 1 with x) with the prune fused, separate and ahead, the step time
+ * choosing shape and placement; writes up to cap trials to host trials[] and their
+ * number (47) to *n_trials, and keeps
  * the fastest choices (also returned in *best) for this and later builds.
  * flags: NB_F_ENERGY and/or NB_F_VIRIAL.  Allocates and frees its own output buffers.
  * Errors: NB_ERR_STATE without a list, NB_ERR_ARG.

@@ -951,7 +951,17 @@ nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj
     c->timing = false;
     const int widths[] = {8, 16, 24, 32, 40, 48, 56, 64};
     const int modes[] = {kExecStatic, kExecXcd, kExecQueue, kExecPersist, kExecBalanced};
-    nb_exec_config win{0, 0, 1, 0, 1e300};
+    nb_exec_config win{0, 0, 1, 0, 1e300}, second{0, 0, 1, 0, 1e300};
+    // the two fastest shapes (item width and mode), distinct
+    auto keep_best = [&](const nb_exec_config& t) {
+        const bool same_win = t.item_width == win.item_width && t.exec_mode == win.exec_mode;
+        if (t.us_per_call < win.us_per_call) {
+            if (!same_win) second = win;
+            win = t;
+        } else if (!same_win && t.us_per_call < second.us_per_call) {
+            second = t;
+        }
+    };
     int n = 0;
     nb_status st = NB_OK;
     // median time of `repeats` calls after a warm-up; part < 0: forces only, else a step
@@ -995,7 +1005,7 @@ nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj
             const nb_exec_config t{W, m, prune0, c->prune_waves, us};
             if (n < cap) trials[n] = t;
             ++n;
-            if (t.us_per_call < win.us_per_call) win = t;
+            keep_best(t);
         }
     }
     // One more shape: the persistent round-robin schedule at the smallest width whose
@@ -1027,31 +1037,40 @@ nb_status nb_autotune(nb_ctx* c, const float* x, const float* q, const float* lj
                 const nb_exec_config t{wfit, kExecPersist, prune0, c->prune_waves, us};
                 if (n < cap) trials[n] = t;
                 ++n;
-                if (t.us_per_call < win.us_per_call) win = t;
+                keep_best(t);
             }
         }
     }
-    // Then, for the chosen shape, a rolling step with the prune fused into the pair kernel,
-    // as its own kernel before it and as its own kernel after it beside the reduction; the
-    // step time decides.
+    // Then, for the two fastest shapes, a rolling step with the prune fused into the pair
+    // kernel, as its own kernel before it and as its own kernel after it beside the
+    // reduction; the step time decides shape and placement together (at 96k two widths
+    // tie on the pair kernel, 36 and 40 entries, while the ahead prune's share of the
+    // reduction launch differs by 1.3 us between them).
     if (st == NB_OK) {
-        c->exec_mode = win.exec_mode;
-        st = make_items(c, win.item_width, false);
-        if (st == NB_OK) st = finish_items(c);
+        const nb_exec_config shapes[2] = {win, second.us_per_call < 1e299 ? second : win};
         double best_step = 1e300;
-        for (int pf : {kPruneFused, kPruneSeparate, kPruneAhead}) {
-            if (st != NB_OK) break;
-            c->prune_mode = pf;
-            double us = 0.0;
-            if (!time_calls(c->p.nstprune > 1 ? 1 : 0, &us)) break;
-            const nb_exec_config t{win.item_width, win.exec_mode, pf, c->prune_waves, us};
-            if (n < cap) trials[n] = t;
-            ++n;
-            if (us < best_step) {
-                best_step = us;
-                win.prune_fused = pf;
+        nb_exec_config chosen = win;
+        for (int k = 0; k < 2 && st == NB_OK; ++k) {
+            const nb_exec_config& sh = shapes[k];
+            c->exec_mode = sh.exec_mode;
+            st = make_items(c, sh.item_width, false);
+            if (st == NB_OK) st = finish_items(c);
+            for (int pf : {kPruneFused, kPruneSeparate, kPruneAhead}) {
+                if (st != NB_OK) break;
+                c->prune_mode = pf;
+                double us = 0.0;
+                if (!time_calls(c->p.nstprune > 1 ? 1 : 0, &us)) break;
+                const nb_exec_config t{sh.item_width, sh.exec_mode, pf, c->prune_waves, us};
+                if (n < cap) trials[n] = t;
+                ++n;
+                if (us < best_step) {
+                    best_step = us;
+                    chosen = sh;
+                    chosen.prune_fused = pf;
+                }
             }
         }
+        win = chosen;
     }
     c->timing = timing;
     hipEventDestroy(e0);
