@@ -279,11 +279,12 @@ class Context:
 
     def set_exec(self, item_width: int = 0, mode: str = "static", prune_fused=True,
                  prune_waves: int = 0):
-        """Item width (0 = built-in rule), execution mode ('static', 'xcd', 'queue',
-        'persist', 'balanced'), where step() prunes (True: inside the pair kernel; False: its
-        own kernel before it; "ahead": its own kernel after it, beside the force reduction,
-        for the next step's part with this step's positions), and the wavefronts per item
-        of the prune kernel (0 = automatic)."""
+        """Item width (0 = built-in rule), execution mode ('static', 'xcd', 'queue':
+        balanced runs plus a dynamic tail, 'persist': rounds in cost order, 'balanced'),
+        where step() prunes (True: inside the pair kernel; False: its own kernel before it;
+        "ahead": after the pair kernel, in the force reduction's launch, for the next
+        step's part with this step's positions), and the wavefronts per item of the prune
+        kernel (0 = automatic)."""
         self._check(self.lib.nb_set_exec(self.h, int(item_width), EXEC_MODES[mode],
                                          _prune_code(prune_fused), int(prune_waves)),
                     "nb_set_exec")
@@ -295,8 +296,10 @@ class Context:
                 "prune_fused": _prune_name(out.prune_fused), "prune_waves": int(out.prune_waves)}
 
     def autotune(self, x, q, lj, energy: bool = True, virial: bool = False, repeats: int = 5):
-        """Time nb_forces over item widths and execution modes on the current list, keep the
-        fastest; returns (best, trials) as dicts with item_width, mode, us_per_call."""
+        """Time nb_forces over item widths and execution modes on the current list, then a
+        rolling step with each prune placement in the two fastest shapes; keep the fastest
+        step's shape and placement.  Returns (best, trials) as dicts with item_width, mode,
+        prune_fused, prune_waves, us_per_call."""
         x = self._dev(x, (self.n_atoms, 3), torch.float32, "x")
         q = self._dev(q, (self.n_atoms,), torch.float32, "q")
         lj = self._dev(lj, (self.n_types, self.n_types, 2), torch.float32, "lj")
