@@ -593,7 +593,7 @@ def main():
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)",
+        print("bench.py measures one GPU: the library has no multi-GPU path (--gpus must be 1)",
               file=sys.stderr)
         sys.exit(2)
 

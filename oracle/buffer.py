@@ -9,7 +9,7 @@ M x N sub-cluster pair (sub-clusters as in census.py) holding an atom pair close
 radii[l] -- the pairs within radii[k] that an M x N list at radii[l] contains.
 
 Drift (the paper names the inputs: masses, temperature, pair potentials and the cluster
-setup with its implicit buffer; the model below is this build's reading of it):
+setup with its implicit buffer; the model below is the reading this oracle takes of it):
   * over a list age t an atom of mass m moves by a Gaussian of variance k_B T t^2 / m per
     axis (free flight; m is the mass that carries the atom: its own, or that of the rigid
     unit it belongs to), so the distance of a pair of classes a, b changes by a Gaussian

@@ -349,7 +349,7 @@ __global__ void k_excl_cluster_range(NbDev d) {
 // empty slot passes, so the pair kernels need no valid-atom masks.
 __global__ void k_slot_pre(NbDev d, int n_slots) {
     const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-    // slots of super-clusters this build made (k_supercell writes no others)
+    // slots of the super-clusters of this grid (k_supercell writes no others)
     if (slot >= n_slots || slot >= d.flags[kFlagNumSc] * kScAtoms) return;
     const int a = d.slot_atom[slot];
     const float D = d.filler_d;
