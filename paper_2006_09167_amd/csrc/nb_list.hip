@@ -256,6 +256,9 @@ __device__ int block_scan(int n, F f, int32_t* __restrict__ out) {
     const int seg = (n + kScanThreads - 1) / kScanThreads;
     const int b = min(n, t * seg), e = min(n, b + seg);
     int sum = 0;
+    // each thread walks its own segment: unrolled so that several of its loads are in
+    // flight at once (integer sums: the order changes nothing)
+#pragma unroll 8
     for (int i = b; i < e; ++i) sum += f(i);
     s_part[t] = sum;
     __syncthreads();
@@ -266,6 +269,7 @@ __device__ int block_scan(int n, F f, int32_t* __restrict__ out) {
         __syncthreads();
     }
     int run = s_part[t] - sum;
+#pragma unroll 8
     for (int i = b; i < e; ++i) {
         out[i] = run;
         run += f(i);
