@@ -152,3 +152,112 @@ def host_program(tmp_path_factory):
 def test_block_maps_as_written_in_the_kernels(host_program):
     r = subprocess.run([host_program], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and r.stdout.strip() == "ok", r.stdout + r.stderr
+
+
+def _queue_snippets():
+    fwd = _src("nb_forces.hip")
+    pool = re.search(r"(const int p = g % kQueuePools;\n\s*const int runs_p = [^\n]*;)", fwd)
+    done = re.search(r"(const int grp = \(int\)blockIdx\.x % kQueuePools;.*?groups - 1;)", fwd,
+                     re.S)
+    consts = re.search(r"(constexpr int kQueueStaticPermille.*?constexpr int kQueueWords[^\n]*)",
+                       _src("nb_internal.h"), re.S)
+    grid = re.search(r"if \(mode == kExecBalanced \|\| mode == kExecQueue\) grid = "
+                     r"blocks\(d\.n_waves, kFwdWaves\);", fwd)
+    dyn = re.search(r"\*dyn = queue \? \*waves \* kQueueDynPerTwoWaves / 2 : 0;",
+                    open(os.path.join(CSRC, "nb_host.cpp")).read())
+    assert pool and done and consts and grid and dyn, "queue-mode code not found"
+    return pool.group(1), done.group(1), consts.group(1)
+
+
+QUEUE_HOST = r"""
+#include <algorithm>
+#include <cstdio>
+#include <random>
+#include <vector>
+using std::min;
+constexpr int kFwdWaves = %(fwd)d;
+%(consts)s
+struct Dim3 { unsigned x; };
+static Dim3 blockIdx, gridDim;
+static int atomicAdd(int* p, int v) { const int o = *p; *p += v; return o; }
+
+static void pool_of(int g, int n_dyn, int* pool, int* runs) {
+%(pool)s
+    *pool = p;
+    *runs = runs_p;
+}
+
+static bool block_done(int* queue, int b) {
+    blockIdx.x = b;
+    bool s_last;
+%(done)s
+    return s_last;
+}
+
+static int fail(const char* what, int a, int b, int c) {
+    std::printf("FAIL %%s %%d %%d %%d\n", what, a, b, c);
+    return 1;
+}
+
+int main() {
+    std::mt19937 rng(7);
+    for (int n_waves = 1; n_waves <= 3000; n_waves += (n_waves < 300 ? 1 : 97)) {
+        // the launch: one wavefront per own run, blocks of kFwdWaves; the dynamic runs
+        const int grid = (n_waves + kFwdWaves - 1) / kFwdWaves, G = grid * kFwdWaves;
+        const int n_dyn = n_waves * kQueueDynPerTwoWaves / 2;
+        // every dynamic run is taken from exactly one pool that some wavefront draws from
+        std::vector<int> taken(std::max(n_dyn, 1), 0), pool_seen(kQueuePools, 0);
+        for (int g = 0; g < G; ++g) {
+            int p, runs;
+            pool_of(g, n_dyn, &p, &runs);
+            if (p < 0 || p >= kQueuePools) return fail("pool range", n_waves, g, p);
+            if (pool_seen[p]++) continue;                  // a pool's runs, counted once
+            for (int t = 0; t < runs; ++t) {
+                const int k = p + kQueuePools * t;
+                if (k >= n_dyn || taken[k]++) return fail("run", n_waves, g, k);
+            }
+        }
+        for (int k = 0; k < n_dyn; ++k)
+            if (taken[k] != 1) return fail("run not taken", n_waves, k, n_dyn);
+        // finishing blocks in any order: exactly the last one sees itself last, and the
+        // counters it then clears are the only ones touched
+        gridDim.x = grid;
+        std::vector<int> queue(kQueueWords, 0), order(grid);
+        for (int rep = 0; rep < 3; ++rep) {
+            for (int b = 0; b < grid; ++b) order[b] = b;
+            std::shuffle(order.begin(), order.end(), rng);
+            for (int i = 0; i < grid; ++i)
+                if (block_done(queue.data(), order[i]) != (i == grid - 1))
+                    return fail("last block", n_waves, rep, i);
+            for (int w = 0; w < kQueueWords; ++w) {
+                const bool counter = (w >= kQueueDone && w < kQueueDone + kQueuePools * kPoolStride &&
+                                      (w - kQueueDone) %% kPoolStride == 0) || w == kQueueDoneAll;
+                if (!counter && queue[w] != 0) return fail("stray word", n_waves, rep, w);
+            }
+            // the last block's reset, as the kernel does it
+            for (int k = 0; k < kQueuePools; ++k) queue[kQueueDone + k * kPoolStride] = 0;
+            queue[kQueueDoneAll] = 0;
+        }
+    }
+    std::printf("ok\n");
+    return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def queue_program(tmp_path_factory):
+    pool, done, consts = _queue_snippets()
+    text = QUEUE_HOST % dict(fwd=_const(_src("nb_forces.hip"), "kFwdWaves"), consts=consts,
+                             pool=_indent(pool, 4), done=_indent(done, 4))
+    d = tmp_path_factory.mktemp("queue")
+    src, exe = d / "queue.cpp", d / "queue"
+    src.write_text(text)
+    subprocess.run(["g++", "-O1", "-std=c++17", "-Wall", "-Werror", "-o", str(exe), str(src)],
+                   check=True, timeout=120)
+    return str(exe)
+
+
+def test_queue_runs_and_last_block_as_written_in_the_kernel(queue_program):
+    r = subprocess.run([queue_program], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", r.stdout + r.stderr
