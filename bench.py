@@ -94,7 +94,8 @@ def measured_traffic(workload, exec_cfg):
     path = os.path.join(ROOT, "profiles", "k_nb_fwd_%s_counters.txt" % workload)
     if not os.path.exists(path):
         return None
-    text = open(path).read()
+    with open(path) as fh:
+        text = fh.read()
     src = b"".join(open(os.path.join(ROOT, "paper_2006_09167_amd", "csrc", f), "rb").read()
                    for f in ("nb_forces.hip", "nb_internal.h", "nb_erfc_coeffs.h",
                              "nb_pair_common.h"))

@@ -38,7 +38,8 @@ def _fake_root(tmp_path, profile_text, tamper=False):
 
 def test_traffic_is_read_for_the_summarised_shapes_only(monkeypatch):
     path = os.path.join(ROOT, "profiles", "k_nb_fwd_water96k_ewald_counters.txt")
-    lines = [l for l in open(path).read().splitlines() if l.strip().startswith("HBM traffic")]
+    with open(path) as fh:
+        lines = [l for l in fh.read().splitlines() if l.strip().startswith("HBM traffic")]
     assert lines, "the committed summary has no traffic line"
     for line in lines:
         width = int(line.split("scaled, ")[1].split(" entries")[0])
